@@ -1,0 +1,412 @@
+"""Pins that tie the FP64 oracle to what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each checks a closed form, an
+invariant the paper states, a special case with a textbook answer, or an
+independent scalar-loop transcription.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dna_oracle as O
+from paper_1301_3389_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# --------------------------------------------------------------------------- eq. (1)
+
+def test_kl_closed_forms():
+    # d(v, z) for scalars: v log(v/z) - v + z; Gibbs: >= 0, = 0 iff V == Z.
+    assert oracle.kl_divergence([[2.0]], [[1.0]]) == pytest.approx(2 * math.log(2) - 1, rel=1e-15)
+    assert oracle.kl_divergence([[0.0]], [[3.0]]) == pytest.approx(3.0, rel=1e-15)  # zero v: only +z
+    rng = np.random.default_rng(0)
+    V = rng.gamma(1.0, 1.0, (7, 9))
+    assert oracle.kl_divergence(V, V) == pytest.approx(0.0, abs=1e-12)
+    Z = rng.gamma(1.0, 1.0, (7, 9))
+    assert oracle.kl_divergence(V, Z) > 0
+    assert oracle.kl_divergence([[1.0]], [[0.0]]) == np.inf
+
+
+# --------------------------------------------------------------------------- P1: R = 1
+
+def test_r1_worked_example_golden():
+    g = json.load(open(os.path.join(GOLD, "r1_closed_form.json")))
+    W = np.array(g["w"])[:, None]
+    V = np.array(g["v"])[:, None]
+    r = oracle.h_step(V, W, np.array([[g["h"]]]))
+    assert r.A[0, 0] == pytest.approx(g["a"], rel=1e-15)
+    assert r.B[0, 0] == pytest.approx(g["b"], rel=1e-15)
+    assert r.X_mu[0, 0] == pytest.approx(g["h_mu"], rel=1e-15)
+    pre = O.newton_candidate(np.array([[g["h"]]]), r.A, r.B)
+    assert pre[0, 0] == pytest.approx(g["h_newton_before_renorm"], rel=1e-15)
+    assert r.X_newton[0, 0] == pytest.approx(g["h_newton"], rel=1e-15)
+    assert r.d_mu[0] == pytest.approx(g["d"], rel=1e-14)
+    assert r.X[0, 0] == pytest.approx(6.0, rel=1e-15)
+    s = g["second_case"]
+    r2 = oracle.h_step(V, W, np.array([[s["h"]]]))
+    assert r2.A[0, 0] == pytest.approx(s["a"], rel=1e-15)
+    assert r2.B[0, 0] == pytest.approx(s["b"], rel=1e-15)
+    pre2 = O.newton_candidate(np.array([[s["h"]]]), r2.A, r2.B)
+    assert pre2[0, 0] == pytest.approx(s["h_newton_before_renorm"], rel=1e-15)
+
+
+def test_r1_closed_form_random():
+    """R = 1: a = S/(hc) - 1, b = S/(h^2 c); Newton before renorm is S/c or eps h
+    (a < 0) or 2h - h^2 c/S (a >= 0); both candidates renormalise to S/c."""
+    rng = np.random.default_rng(1)
+    N, T = 9, 40
+    w = rng.uniform(0.05, 1.0, (N, 1))
+    V = rng.poisson(3.0, (N, T)).astype(float)
+    V[0] += 1.0                                          # every column has S > 0
+    H = rng.uniform(0.01, 40.0, (1, T))
+    H[0, :3] = [1e-4, 1e4, 5e3]                          # floor and far-side cases
+    c, S, h = w.sum(), V.sum(axis=0), H[0]
+    r = oracle.h_step(V, w, H)
+    np.testing.assert_allclose(r.A[0], S / (h * c) - 1, rtol=1e-13)
+    np.testing.assert_allclose(r.B[0], S / (h * h * c), rtol=1e-13)
+    pre = O.newton_candidate(H, r.A, r.B)[0]
+    a = r.A[0]
+    expect = np.where(a < 0, np.where(S / (h * c) < oracle.EPS, oracle.EPS * h, S / c),
+                      2 * h - h * h * c / S)
+    np.testing.assert_allclose(pre, expect, rtol=1e-12)
+    np.testing.assert_allclose(r.X_mu[0], S / c, rtol=1e-12)
+    np.testing.assert_allclose(r.X_newton[0], S / c, rtol=1e-12)
+    np.testing.assert_allclose(r.X[0], S / c, rtol=1e-12)
+    # exact tie in exact arithmetic: margin at rounding level only
+    assert np.all(np.abs(r.margin) <= 1e-12 * np.abs(r.d_mu) + 1e-12)
+
+
+# --------------------------------------------------------------------------- P2, P3
+
+def _full_cost_cols(V, W, H):
+    Z = W @ H
+    return O.partial_cost(V, Z, 0) - V.sum(0) + Z.sum(0)
+
+
+def _full_cost_rows(V, W, H):
+    Z = W @ H
+    return O.partial_cost(V, Z, 1) - V.sum(1) + Z.sum(1)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mu_monotone_per_column_and_row(seed):
+    """MU never increases the cost (Sec. 2.1, ref. [1]); per column for H, per row for W."""
+    w = synth.random_problem(30, 25, 4, seed, zero_frac=0.2)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    for _ in range(15):
+        before = _full_cost_cols(V, W, H)
+        H, _ = oracle.mu_h_step(V, W, H)
+        after = _full_cost_cols(V, W, H)
+        assert np.all(after <= before + 1e-12 * np.abs(before))
+        before = _full_cost_rows(V, W, H)
+        W, _ = oracle.mu_w_step(V, W, H)
+        after = _full_cost_rows(V, W, H)
+        assert np.all(after <= before + 1e-12 * np.abs(before))
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_dna_not_worse_than_mu_and_monotone(seed):
+    """d_sel <= d_MU per column / row; full KL never increases (Sec. 2.4)."""
+    w = synth.random_problem(40, 30, 5, seed, zero_frac=0.1)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    W, H = oracle.normalize_w_columns(W, H)
+    kl = oracle.kl_cost(V, W, H)
+    saw_newton = False
+    for _ in range(12):
+        before_cols = _full_cost_cols(V, W, H)
+        r = oracle.h_step(V, W, H)
+        assert np.all(r.d_sel <= r.d_mu)
+        saw_newton |= bool(r.chose_newton.any())
+        H = r.X
+        after_cols = _full_cost_cols(V, W, H)
+        assert np.all(after_cols <= before_cols + 1e-12 * np.abs(before_cols))
+        W, H = oracle.normalize_h_rows(W, H)
+        r = oracle.w_step(V, W, H)
+        assert np.all(r.d_sel <= r.d_mu)
+        W = r.X
+        W, H = oracle.normalize_w_columns(W, H)
+        kl_new = oracle.kl_cost(V, W, H)
+        assert kl_new <= kl * (1 + 1e-12)
+        kl = kl_new
+    assert saw_newton
+
+
+# --------------------------------------------------------------------------- P4
+
+def test_planted_exact_factorisation_is_fixed_point():
+    rng = np.random.default_rng(4)
+    W0 = rng.uniform(0.2, 1.0, (12, 3))
+    H0 = rng.uniform(0.2, 1.0, (3, 10))
+    V = W0 @ H0
+    assert oracle.kl_cost(V, W0, H0) == pytest.approx(0.0, abs=1e-12)
+    r = oracle.h_step(V, W0, H0)
+    np.testing.assert_allclose(r.A, 0.0, atol=1e-13)
+    np.testing.assert_allclose(r.X_mu, H0, rtol=1e-13)
+    np.testing.assert_allclose(r.X_newton, H0, rtol=1e-13)
+    np.testing.assert_allclose(r.X, H0, rtol=1e-13)
+    rw = oracle.w_step(V, W0, H0)
+    np.testing.assert_allclose(rw.X, W0, rtol=1e-13)
+    m, _ = oracle.mu_h_step(V, W0, H0)
+    np.testing.assert_allclose(m, H0, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- P5
+
+def test_renormalisation_identity():
+    """Eq. (9): sum_r c_r h_r = 1^t v for MU (automatic) and Newton (after eq. 10),
+    hence sum_n z_nt = s_t for both candidates."""
+    w = synth.random_problem(50, 33, 6, 5, zero_frac=0.3)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    c, s = W.sum(0), V.sum(0)
+    r = oracle.h_step(V, W, H)
+    np.testing.assert_allclose(c @ r.X_mu, s, rtol=1e-12)
+    np.testing.assert_allclose(c @ r.X_newton, s, rtol=1e-12)
+    np.testing.assert_allclose((W @ r.X).sum(0), s, rtol=1e-12)
+    rw = oracle.w_step(V, W, H)
+    g, sr = H.sum(1), V.sum(1)
+    np.testing.assert_allclose(rw.X_mu @ g, sr, rtol=1e-12)
+    np.testing.assert_allclose(rw.X_newton @ g, sr, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- P6
+
+def test_w_step_is_h_step_on_transposes():
+    """d_KL(V, WH) = d_KL(V^t, H^t W^t) (Sec. 2): the W step is the H step of the
+    transposed problem."""
+    w = synth.random_problem(21, 17, 4, 6, zero_frac=0.2)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    a = oracle.w_step(V, W, H)
+    b = oracle.h_step(V.T, H.T, W.T)
+    np.testing.assert_allclose(a.X, b.X.T, rtol=1e-13)
+    np.testing.assert_array_equal(a.chose_newton, b.chose_newton)
+    np.testing.assert_allclose(a.d_sel, b.d_sel, rtol=1e-13)
+    np.testing.assert_allclose(a.A, b.A.T, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(a.B, b.B.T, rtol=1e-12)
+    m1, d1 = oracle.mu_w_step(V, W, H)
+    m2, d2 = oracle.mu_h_step(V.T, H.T, W.T)
+    np.testing.assert_allclose(m1, m2.T, rtol=1e-13)
+    np.testing.assert_allclose(d1, d2, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- P7
+
+def test_diagonal_hessian_by_finite_differences():
+    """With g_r(h) = a_r(h) h_r (eq. 8), d g_r / d h_r = a_r - h_r b_r is the
+    diagonal of eq. (13); the unfloored a < 0 Newton candidate is one scalar
+    Newton step on g_r with the other coordinates fixed (Sec. 2.2)."""
+    w = synth.random_problem(25, 6, 4, 7, positive=True)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    W = W * 3.0                                   # c != 1 on purpose
+    c = W.sum(0)
+
+    def a_of(h, t):
+        z = W @ h
+        return (W.T @ (V[:, t] / z)) / c - 1.0
+
+    r = oracle.h_step(V, W, H)
+    pre = O.newton_candidate(H, r.A, r.B, eps=0.0)
+    for t in range(H.shape[1]):
+        for k in range(H.shape[0]):
+            h = H[:, t].copy()
+            step = 1e-6 * h[k]
+            hp, hm = h.copy(), h.copy()
+            hp[k] += step
+            hm[k] -= step
+            fd = (a_of(hp, t)[k] * hp[k] - a_of(hm, t)[k] * hm[k]) / (2 * step)
+            assert fd == pytest.approx(r.A[k, t] - H[k, t] * r.B[k, t], rel=1e-6, abs=1e-9)
+            if r.A[k, t] < 0:
+                g = r.A[k, t] * H[k, t]
+                assert pre[k, t] == pytest.approx(H[k, t] - g / fd, rel=1e-6)
+
+
+# --------------------------------------------------------------------------- P8
+
+def test_scale_invariance():
+    """At lambda = 0 rescaling W columns by kappa and H rows by 1/kappa leaves the
+    selection, the costs and the new W H unchanged (W H-valued outputs)."""
+    w = synth.random_problem(30, 20, 5, 8, zero_frac=0.2)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    kappa = np.array([0.5, 2.0, 8.0, 0.125, 3.0])
+    r1 = oracle.h_step(V, W, H)
+    r2 = oracle.h_step(V, W * kappa[None, :], H / kappa[:, None])
+    np.testing.assert_array_equal(r1.chose_newton, r2.chose_newton)
+    np.testing.assert_allclose(r1.d_sel, r2.d_sel, rtol=1e-12)
+    np.testing.assert_allclose(W @ r1.X, (W * kappa) @ r2.X, rtol=1e-12)
+    q1 = oracle.w_step(V, W, H)
+    q2 = oracle.w_step(V, W * kappa[None, :], H / kappa[:, None])
+    np.testing.assert_array_equal(q1.chose_newton, q2.chose_newton)
+    np.testing.assert_allclose(q1.X @ H, q2.X @ (H / kappa[:, None]), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- P9
+
+def test_convex_subproblem_three_solvers_agree():
+    """Eq. (5) is convex in h for fixed W: H-only DNA, long MU runs and a generic
+    bound-constrained solver reach the same minimiser; KKT (eq. 8) holds."""
+    scipy_opt = pytest.importorskip("scipy.optimize")
+    rng = np.random.default_rng(9)
+    N, R, T = 8, 3, 4
+    W = rng.uniform(0.1, 1.0, (N, R))
+    Htrue = rng.uniform(0.5, 2.0, (R, T))
+    V = (W @ Htrue) * rng.uniform(0.9, 1.1, (N, T))      # interior minimiser
+    H = np.ones((R, T))
+    for _ in range(200):
+        H = oracle.h_step(V, W, H).X
+    Hm = np.ones((R, T))
+    for _ in range(100000):
+        Hm, _ = oracle.mu_h_step(V, W, Hm)
+    for t in range(T):
+        v = V[:, t]
+
+        def f(h):
+            z = W @ h
+            return float(np.sum(v * np.log(v / z)) - v.sum() + z.sum())
+
+        def grad(h):
+            return W.sum(0) - W.T @ (v / (W @ h))
+
+        res = scipy_opt.minimize(f, np.ones(R), jac=grad, method="L-BFGS-B",
+                                 bounds=[(0, None)] * R,
+                                 options={"ftol": 1e-15, "gtol": 1e-13, "maxiter": 10000})
+        np.testing.assert_allclose(H[:, t], res.x, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(Hm[:, t], res.x, rtol=1e-6, atol=1e-7)
+    r = oracle.h_step(V, W, H)
+    assert np.max(np.abs(r.A * H)) < 1e-9
+    # a boundary case: one basis useless for a column -> h_r -> 0 with a_r <= 0
+    V2 = (W[:, :2] @ Htrue[:2]) * rng.uniform(0.95, 1.05, (N, T))
+    H2 = np.ones((R, T))
+    for _ in range(300):
+        H2 = oracle.h_step(V2, W, H2).X
+    r2 = oracle.h_step(V2, W, H2)
+    assert np.max(np.abs(r2.A * H2)) < 1e-6
+    assert np.all(r2.A[H2 < 1e-8] <= 1e-9)
+
+
+# --------------------------------------------------------------------------- P10
+
+def _scalar_h_step(V, W, H, eps=0.01, alpha=4.0):
+    """Pure-Python loops over Algorithm 1 steps 4-15 (eq. 7, 11, 14, 15, 17, 10)."""
+    N, R = len(W), len(W[0])
+    T = len(H[0])
+    out = [[0.0] * T for _ in range(R)]
+    choose = []
+    for t in range(T):
+        c = [sum(W[n][r] for n in range(N)) for r in range(R)]
+        z = [sum(W[n][r] * H[r][t] for r in range(R)) for n in range(N)]
+        a, b = [], []
+        for r in range(R):
+            num = sum(W[n][r] * V[n][t] / z[n] for n in range(N) if V[n][t] > 0)
+            hes = sum(W[n][r] ** 2 * V[n][t] / z[n] ** 2 for n in range(N) if V[n][t] > 0)
+            a.append(num / c[r] - 1.0)
+            b.append(hes / c[r])
+        hmu = [H[r][t] * (1.0 + a[r]) for r in range(R)]
+        hn = []
+        for r in range(R):
+            h = H[r][t]
+            if a[r] < 0:
+                hn.append(h * max(h * b[r] / (h * b[r] - a[r]), eps))
+            else:
+                hn.append(h + min(a[r] / b[r], alpha * h))
+        s = sum(V[n][t] for n in range(N))
+        den = sum(c[r] * hn[r] for r in range(R))
+        hn = [x * s / den for x in hn]
+
+        def cost(hc):
+            tot = 0.0
+            for n in range(N):
+                if V[n][t] > 0:
+                    zz = sum(W[n][r] * hc[r] for r in range(R))
+                    tot += V[n][t] * math.log(V[n][t] / zz)
+            return tot
+
+        dm, dn = cost(hmu), cost(hn)
+        pick = dn < dm
+        choose.append(pick)
+        for r in range(R):
+            out[r][t] = hn[r] if pick else hmu[r]
+    return out, choose
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (3, 2, 4), (4, 1, 3), (2, 3, 1)])
+def test_brute_force_matches_vectorised(shape):
+    N, R, T = shape
+    w = synth.random_problem(N, T, R, 10 + N, zero_frac=0.25)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    V[0] += 1.0
+    ref, ch = _scalar_h_step(V.tolist(), W.tolist(), H.tolist())
+    r = oracle.h_step(V, W, H)
+    np.testing.assert_allclose(r.X, np.array(ref), rtol=1e-13)
+    if R > 1:
+        np.testing.assert_array_equal(r.chose_newton, np.array(ch))
+    # the W step through the same loops on the transposed problem
+    refw, _ = _scalar_h_step(V.T.tolist(), H.T.tolist(), W.T.tolist())
+    np.testing.assert_allclose(oracle.w_step(V, W, H).X, np.array(refw).T, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- P11
+
+def test_mu_with_normalisation_equals_textbook_mu():
+    w = synth.random_problem(30, 40, 6, 11, zero_frac=0.2)
+    a = oracle.fit_mu(w.V, w.W, w.H, 25, normalize=True)
+    b = oracle.fit_mu(w.V, w.W, w.H, 25, normalize=False)
+    np.testing.assert_allclose(a.kl, b.kl, rtol=1e-12)
+    np.testing.assert_allclose(a.W @ a.H, b.W @ b.H, rtol=1e-10)
+
+
+def test_lee_seung_textbook_formula():
+    """Ref. [1]: H <- H .* (W^t (V./WH)) ./ (W^t 1) in one line of NumPy."""
+    w = synth.random_problem(15, 12, 3, 12)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    Z = W @ H
+    ref = H * (W.T @ np.divide(V, Z)) / W.sum(0)[:, None]
+    np.testing.assert_allclose(oracle.mu_h_step(V, W, H)[0], ref, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- zeros, domain
+
+def test_zero_data_entries_do_not_contribute():
+    """End of Sec. 3: zeros of V contribute nothing even where z would be 0."""
+    V = np.array([[0.0, 1.0], [2.0, 0.0]])
+    Z = np.array([[0.0, 1.0], [1.0, 0.0]])
+    Q, Qb = oracle.ratios(V, Z)
+    np.testing.assert_array_equal(Q, [[0.0, 1.0], [2.0, 0.0]])
+    np.testing.assert_array_equal(Qb, [[0.0, 1.0], [2.0, 0.0]])
+    np.testing.assert_allclose(O.partial_cost(V, Z, 0), [2 * math.log(2), 0.0])
+    with pytest.raises(oracle.DomainError):
+        oracle.ratios(np.array([[1.0]]), np.array([[0.0]]))
+    with pytest.raises(oracle.DomainError):
+        oracle.h_step(np.ones((2, 2)), np.array([[1.0, 0.0], [1.0, 0.0]]), np.ones((2, 2)))
+
+
+def test_newton_candidate_branches():
+    """Floor (eq. 15 gain below eps), cap (eq. 17 step above alpha h), h = 0."""
+    X = np.array([[1.0, 1.0, 1.0, 0.0, 2.0]])
+    A = np.array([[-0.999, -0.5, 100.0, -0.3, 0.5]])
+    B = np.array([[0.001, 1.0, 1.0, 1.0, 0.0]])
+    out = O.newton_candidate(X, A, B, eps=0.01, alpha=4.0)
+    assert out[0, 0] == pytest.approx(0.01)          # gain 0.001/1.0 floored
+    assert out[0, 1] == pytest.approx(1.0 / 1.5)     # 1*1/(1+0.5)
+    assert out[0, 2] == pytest.approx(5.0)           # step 100 capped at 4h
+    assert out[0, 3] == 0.0
+    assert out[0, 4] == pytest.approx(10.0)          # b = 0, a > 0: cap
+
+
+def test_normalisations_leave_product_unchanged():
+    w = synth.random_problem(10, 12, 3, 13)
+    W, H = w.W.astype(float), w.H.astype(float)
+    W1, H1 = oracle.normalize_w_columns(W, H)
+    np.testing.assert_allclose(W1.sum(0), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(W1 @ H1, W @ H, rtol=1e-13)
+    W2, H2 = oracle.normalize_h_rows(W, H)
+    np.testing.assert_allclose(H2.sum(1), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(W2 @ H2, W @ H, rtol=1e-13)
