@@ -1,0 +1,206 @@
+/*
+ * dna.h -- C ABI of libdna: the Diagonalized Newton Algorithm (DNA) for
+ * non-negative matrix factorisation under the Kullback-Leibler divergence
+ * (H. Van hamme, "The Diagonalized Newton Algorithm for Non-negative Matrix
+ * Factorization"), as HIP kernels for gfx950 (MI355X).
+ *
+ * Problem (Sec. 1, eq. 1): V (N x T) ~ W H with W (N x R), H (R x T), all
+ * entries >= 0, cost d_KL(V, WH) = sum v log(v/z) - sum v + sum z, Z = W H.
+ * Regularisation weights rho = lambda = 0 (the setting of Sec. 4).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are float32, row-major and contiguous: V[N][T], W[N][R],
+ *    H[R][T].  Every matrix pointer is DEVICE memory owned by the caller.
+ *  - Scalars/vectors named d_*, margin, out are device float64 buffers;
+ *    chose_newton masks are device uint8 buffers (1 = Newton candidate).
+ *  - `ws` is a caller-owned device workspace of at least the number of bytes
+ *    the matching *_workspace_bytes() function returns; the library never
+ *    allocates, frees or synchronises (except in checked mode, below).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *    enqueued on it; calls return before the GPU finishes.
+ *  - Arguments are validated on the host before anything is enqueued; an
+ *    invalid call returns a status != DNA_OK and enqueues nothing.
+ *  - A kernel launch failure returns DNA_EHIP; dna_last_error() gives the
+ *    HIP error text (thread-local).  No C++ exception crosses this ABI.
+ *  - Zeros of V contribute nothing to Q, Q-bar or any cost (end of Sec. 3).
+ *  - Results are deterministic: every reduction runs in a fixed order.
+ */
+#ifndef DNA_H_
+#define DNA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DNA_OK = 0,
+  DNA_EINVAL = 1,       /* null pointer, non-positive size, bad option value  */
+  DNA_EWORKSPACE = 2,   /* workspace smaller than *_workspace_bytes()         */
+  DNA_EDOMAIN = 3,      /* checked mode: negative entry, zero W column / H row
+                           sum, or z = 0 where v > 0 (Sec. 2 assumes nonzero
+                           column sums)                                         */
+  DNA_ENONFINITE = 4,   /* checked mode: NaN or Inf in an input                */
+  DNA_EHIP = 5,         /* HIP runtime or launch error                         */
+  DNA_EUNSUPPORTED = 6  /* valid request this build does not implement         */
+} dna_status;
+
+/* Operand type of the matrix products (the accumulation is always float32 and
+ * every cost sum is float64). */
+typedef enum {
+  DNA_GEMM_FP32 = 0,
+  DNA_GEMM_BF16 = 1,
+  DNA_GEMM_FP16 = 2
+} dna_gemm_type;
+
+typedef struct {
+  float eps;     /* floor of the multiplicative Newton gain, eq. (15); Sec. 4: 0.01 */
+  float alpha;   /* ceiling: additive Newton step <= alpha*x, eq. (17); Sec. 4: 4   */
+  int gemm;      /* dna_gemm_type                                                  */
+  int checked;   /* 1: device-side domain checks, then a stream synchronise and a
+                    read-back of the check flags (tests and debugging only)        */
+} dna_opts;
+
+/* eps = 0.01, alpha = 4 (Sec. 4), FP32 products, unchecked. */
+void dna_default_opts(dna_opts* opts);
+
+/* Bytes of workspace any call below needs for an N x T x R problem with these
+ * options (one size serves every entry point except the unrolled adjoint).
+ * Returns 0 for non-positive sizes. */
+size_t dna_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* opts);
+
+/* Algorithm 1 steps 1, 16, 29 at rho = lambda = 0: rescale so W H is unchanged.
+ * side 0 (steps 1, 29): divide column r of W by its sum, multiply row r of H
+ *                       by the same number.
+ * side 1 (step 16):     divide row r of H by its sum, multiply column r of W
+ *                       by the same number.
+ * W and H are updated in place.  A zero sum leaves that column/row unchanged
+ * (checked mode reports it as DNA_EDOMAIN). */
+dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                         const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* One DNA update of H with W fixed: Algorithm 1 steps 4-15 (Sec. 2-3).
+ *   c = W^t 1;  Z = W H;  Q = V/Z;  Q-bar = V/Z^2                  (steps 2-3, 10)
+ *   A = W^t Q / c - 1            eq. (7), step 5
+ *   B = (W*W)^t Q-bar / c        eq. (14), step 10
+ *   MU candidate     H (1 + A)                                      eq. (11), step 6
+ *   Newton candidate a < 0:  h max(hb/(hb - a), eps)                eq. (15)
+ *                    a >= 0: h + min(a/b, alpha h)                  eq. (17)
+ *                    then each column scaled so sum_r c_r h_r = sum_n v_n  eq. (10)
+ *   per column t: d_MU, d_DNA = sum_{v>0} v log(v/z) of each candidate  steps 9, 14
+ *   H[:, t] <- Newton candidate iff d_DNA < d_MU, else MU            step 15
+ * H (R x T) is overwritten.  Optional outputs (NULL to skip), length T:
+ *   chose_newton[t] (uint8), d_sel[t] = cost of the kept candidate,
+ *   margin[t] = d_MU - d_DNA (computed directly from W (H_MU - H_DNA), so it
+ *   resolves differences far below the size of the costs). */
+dna_status dna_update_H(const float* V, const float* W, float* H,
+                        int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                        void* ws, size_t ws_bytes, uint8_t* chose_newton,
+                        double* d_sel, double* margin, void* stream);
+
+/* One DNA update of W with H fixed: Algorithm 1 steps 17-28, the mirror of
+ * dna_update_H on the transposed problem (Sec. 2: d(V, WH) = d(V^t, H^t W^t)).
+ * g = H 1 replaces c; rows of W replace columns of H; each Newton row n is
+ * scaled so that sum_r g_r w_nr = sum_t v_nt.  W (N x R) is overwritten;
+ * optional outputs have length N. */
+dna_status dna_update_W(const float* V, float* W, const float* H,
+                        int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                        void* ws, size_t ws_bytes, uint8_t* chose_newton,
+                        double* d_sel, double* margin, void* stream);
+
+/* Plain multiplicative update (eq. 11 at lambda = 0; Lee-Seung):
+ *   side 0: H <- H * (W^t Q) / (W^t 1)      side 1: W <- W * (Q H^t) / (H 1)
+ * with Q = V / (W H).  If with_cost != 0, d_out (length T for side 0, N for
+ * side 1) receives sum_{v>0} v log(v/z) per column (row) of the INPUT state,
+ * computed from the same Z ("MU with cost", Table 1); otherwise d_out is
+ * ignored and no logarithm is evaluated ("MU without cost"). */
+dna_status mu_update(int side, const float* V, float* W, float* H,
+                     int64_t N, int64_t T, int64_t R, int with_cost, double* d_out,
+                     const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* Eq. (1): *out = sum_{v>0} v log(v/z) - sum v + sum z with Z = W H, written
+ * to one device double. */
+dna_status kl_cost(const float* V, const float* W, const float* H,
+                   int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                   void* ws, size_t ws_bytes, double* out, void* stream);
+
+/* ---- Stages of one half-step (the same kernels dna_update_* runs) -------- */
+
+/* Steps 2-5 and 10: A and B of eq. (7) and eq. (14).
+ * side 0: A_out, B_out are R x T;  side 1: N x R (A = Q H^t / g - 1,
+ * B = Q-bar (H*H)^t / g). */
+dna_status dna_gradient_hessian(int side, const float* V, const float* W, const float* H,
+                                int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                                float* A_out, float* B_out,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* Steps 2-6, 10-11: the MU candidate and the renormalised Newton candidate.
+ * side 0: X_mu, X_newton are R x T (candidates for H); side 1: N x R. */
+dna_status dna_candidates(int side, const float* V, const float* W, const float* H,
+                          int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                          float* X_mu, float* X_newton,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Steps 7-9, 12-15 given both candidates: per-column (side 0) or per-row
+ * (side 1) costs, selection and the kept factor written to X_out.
+ * F is the fixed factor (W for side 0, H for side 1). */
+dna_status dna_select(int side, const float* V, const float* F,
+                      const float* X_mu, const float* X_newton, float* X_out,
+                      int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                      uint8_t* chose_newton, double* d_sel, double* margin,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Differentiable unrolled H-solve (K DNA H-updates with W fixed) ------ */
+
+/* Workspace for the two calls below (larger than dna_workspace_bytes). */
+size_t dna_unrolled_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* opts);
+
+/* Forward: H_ckpt[0] = H_init, H_ckpt[k+1] = dna_update_H(H_ckpt[k]) for
+ * k < K; sel_ckpt[k][t] is that update's selection.  H_ckpt is
+ * [K+1][R][T] float32, sel_ckpt [K][T] uint8, both device. */
+dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_init, int K,
+                              int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                              float* H_ckpt, uint8_t* sel_ckpt,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Backward: given dH_K = dL/dH_K, the vector-Jacobian product through the K
+ * updates with each selection frozen at its forward value and each entry
+ * differentiated along the branch it took (a < 0 or a >= 0, floor, cap).
+ * Writes dW (N x R) and dV (N x T), and dH_init (R x T) unless NULL; all three
+ * are overwritten.  Requires z = (W H_k)_nt > 0 everywhere; the gradient with
+ * respect to v at v = 0 is that of the expressions v/z, v/z^2. */
+dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckpt,
+                              const uint8_t* sel_ckpt, int K,
+                              int64_t N, int64_t T, int64_t R, const float* dH_K,
+                              float* dW, float* dV, float* dH_init, const dna_opts* opts,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Diagnostics ---------------------------------------------------------- */
+
+const char* dna_status_string(dna_status s);
+const char* dna_last_error(void);
+
+/* Kernel timing: while enabled, every kernel the library launches is bracketed
+ * by hipEvents on its stream.  dna_profile_read() synchronises those events and
+ * fills up to max_entries records (one per kernel name, aggregated over
+ * launches since the last reset), returning how many exist. */
+typedef struct {
+  const char* name;
+  int64_t launches;
+  double total_ms;
+} dna_kernel_stat;
+
+void dna_profile_enable(int on);
+void dna_profile_reset(void);
+int dna_profile_read(dna_kernel_stat* out, int max_entries);
+
+/* Library build identification (gfx target and compile options). */
+const char* dna_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DNA_H_ */

@@ -1,0 +1,491 @@
+// api.hip -- the C ABI of libdna (declared in include/dna.h): argument checks,
+// workspace carving and the kernel sequence of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dna.h"
+#include "kernels.hpp"
+
+namespace dna {
+
+// ---------------------------------------------------------------------------
+// Error text and kernel timing.
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+static dna_status fail(dna_status s, const char* msg) {
+  std::snprintf(g_err, sizeof(g_err), "%s", msg);
+  return s;
+}
+static dna_status hip_fail(hipError_t e, const char* where) {
+  std::snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
+  return DNA_EHIP;
+}
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof = false;
+static std::vector<ProfRec> g_pending;
+static std::vector<hipEvent_t> g_pool;
+static std::map<std::string, std::pair<int64_t, double>> g_stats;
+static std::vector<std::string> g_names;   // stable storage for returned names
+
+static hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof) return;
+  hipEvent_t a = take_event();
+  if (!a) return;
+  hipEventRecord(a, s);
+  g_pending.push_back({name, a, nullptr});
+}
+
+void prof_end(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof || g_pending.empty() || g_pending.back().b != nullptr) return;
+  hipEvent_t b = take_event();
+  if (!b) return;
+  hipEventRecord(b, s);
+  g_pending.back().b = b;
+  (void)name;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (one layout serves every forward entry point).
+// ---------------------------------------------------------------------------
+constexpr int64_t TARGET_WG = 512;     // aim for this many workgroups in split GEMMs
+constexpr int64_t MIN_KCHUNK = 256;    // never split the contraction finer than this
+
+struct Split {
+  int splits;
+  int64_t kchunk;
+};
+
+static Split choose_split(int64_t K, int64_t base_tiles) {
+  int64_t sp = std::max<int64_t>(1, cdiv(TARGET_WG, std::max<int64_t>(1, base_tiles)));
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / MIN_KCHUNK));
+  sp = std::min<int64_t>(sp, 1024);
+  int64_t kchunk = cdiv(cdiv(K, sp), GEMM_BK) * GEMM_BK;
+  Split s;
+  s.kchunk = kchunk;
+  s.splits = (int)cdiv(K, kchunk);
+  return s;
+}
+
+struct Layout {
+  Split sh, sw;
+  int tiles_m, tiles_n;      // row tiles (N / ZT_BM), column tiles (T / ZT_BN)
+  size_t q, qb, pu, py, xmu, xn, c32, c64, vpart, cpart, fpart, check, total;
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+static Layout make_layout(int64_t N, int64_t T, int64_t R) {
+  Layout L;
+  L.sh = choose_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM));
+  L.sw = choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM));
+  L.tiles_m = (int)cdiv(N, ZT_BM);
+  L.tiles_n = (int)cdiv(T, ZT_BN);
+  const size_t nt = (size_t)N * T, fac = (size_t)std::max(R * T, N * R);
+  const size_t psplit = (size_t)std::max<int64_t>((int64_t)L.sh.splits * R * T, (int64_t)L.sw.splits * N * R);
+  const size_t red = (size_t)std::max<int64_t>((int64_t)L.tiles_m * T, (int64_t)L.tiles_n * N);
+  const size_t klt = (size_t)L.tiles_m * L.tiles_n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  L.q = take(nt * 4);
+  L.qb = take(nt * 4);
+  L.pu = take(psplit * 4);
+  L.py = take(psplit * 4);
+  L.xmu = take(fac * 4);
+  L.xn = take(fac * 4);
+  L.c32 = take((size_t)R * 4);
+  L.c64 = take((size_t)R * 8);
+  L.vpart = take(red * 8);
+  L.cpart = take(std::max(3 * red, klt) * 8);
+  L.fpart = take(red * 4);
+  L.check = take(16);
+  L.total = off;
+  return L;
+}
+
+template <class T>
+static T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks.
+// ---------------------------------------------------------------------------
+static dna_status check_opts(const dna_opts* o) {
+  if (!o) return fail(DNA_EINVAL, "opts is NULL");
+  if (!(o->eps >= 0.f && o->eps <= 1.f)) return fail(DNA_EINVAL, "eps must lie in [0, 1]");
+  if (!(o->alpha > 0.f) || !std::isfinite(o->alpha)) return fail(DNA_EINVAL, "alpha must be finite and > 0");
+  if (o->gemm < DNA_GEMM_FP32 || o->gemm > DNA_GEMM_FP16) return fail(DNA_EINVAL, "unknown gemm type");
+  if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "16-bit products are not available in this entry point");
+  return DNA_OK;
+}
+
+static dna_status check_dims(int64_t N, int64_t T, int64_t R) {
+  if (N <= 0 || T <= 0 || R <= 0) return fail(DNA_EINVAL, "N, T and R must be positive");
+  if (cdiv(N, ZT_BM) > 65535 || cdiv(R, GH_BM) > 65535)
+    return fail(DNA_EUNSUPPORTED, "N or R exceeds the launch grid limit");
+  if ((double)N * (double)T > 4.0e9 || (double)N * (double)R > 4.0e9 || (double)R * (double)T > 4.0e9)
+    return fail(DNA_EUNSUPPORTED, "matrix too large (more than 4e9 entries)");
+  return DNA_OK;
+}
+
+static dna_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (!ws) return fail(DNA_EINVAL, "workspace is NULL");
+  if (ws_bytes < need) return fail(DNA_EWORKSPACE, "workspace smaller than dna_workspace_bytes()");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(DNA_EINVAL, "workspace must be 256-byte aligned");
+  return DNA_OK;
+}
+
+#define DNA_TRY(expr)                              \
+  do {                                             \
+    dna_status _s = (expr);                        \
+    if (_s != DNA_OK) return _s;                   \
+  } while (0)
+#define DNA_HIP(expr, where)                       \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+// Checked mode: clear the flag word and scan the inputs.
+static dna_status checked_begin(int* chk, const float* const* bufs, const int64_t* sizes, int nb,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, chk);
+  DNA_HIP(hipGetLastError(), "check flag reset");
+  for (int i = 0; i < nb; ++i) DNA_HIP(launch_check(bufs[i], sizes[i], chk, s), "input check");
+  return DNA_OK;
+}
+
+static dna_status checked_end(int* chk, hipStream_t s) {
+  int h = 0;
+  DNA_HIP(hipMemcpyAsync(&h, chk, sizeof(int), hipMemcpyDeviceToHost, s), "check flag read-back");
+  DNA_HIP(hipStreamSynchronize(s), "checked-mode synchronise");
+  if (h & CHK_NONFINITE) return fail(DNA_ENONFINITE, "non-finite entry in an input");
+  if (h & CHK_DOMAIN) return fail(DNA_EDOMAIN, "negative entry, zero W column / H row sum, or z = 0 where v > 0");
+  return DNA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Shared stages.
+// ---------------------------------------------------------------------------
+// side 0: candidates for H (R x T) given W;  side 1: candidates for W (N x R) given H.
+static dna_status run_candidates(int side, const float* V, const float* W, const float* H, int64_t N,
+                                 int64_t T, int64_t R, const dna_opts* o, const Layout& L, void* ws,
+                                 float* Xmu, float* Xn, float* Aout, float* Bout, int* chk, hipStream_t s) {
+  float* Q = at<float>(ws, L.q);
+  float* Qb = at<float>(ws, L.qb);
+  float* pu = at<float>(ws, L.pu);
+  float* py = at<float>(ws, L.py);
+  float* c32 = at<float>(ws, L.c32);
+  double* c64 = at<double>(ws, L.c64);
+  double* vpart = at<double>(ws, L.vpart);
+  RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk};
+  if (side == 0) {
+    DNA_HIP(launch_colsum_W(W, N, R, c64, c32, chk, s), "colsum_W");
+    DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
+    DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, py, s), "gh_H");
+    DNA_HIP(launch_cand_H(H, pu, py, L.sh.splits, c32, vpart, L.tiles_m, T, R, o->eps, o->alpha, Xmu, Xn,
+                          Aout, Bout, s), "cand_H");
+  } else {
+    DNA_HIP(launch_rowsum_H(H, T, R, c64, c32, chk, s), "rowsum_H");
+    DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
+    DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, py, s), "gh_W");
+    DNA_HIP(launch_cand_W(W, pu, py, L.sw.splits, c32, vpart, L.tiles_n, N, R, o->eps, o->alpha, Xmu, Xn,
+                          Aout, Bout, s), "cand_W");
+  }
+  return DNA_OK;
+}
+
+static dna_status run_select(int side, const float* V, const float* F, const float* Xmu, const float* Xn,
+                             float* Xout, int64_t N, int64_t T, int64_t R, const Layout& L, void* ws,
+                             uint8_t* mask, double* dsel, double* margin, hipStream_t s) {
+  double* cpart = at<double>(ws, L.cpart);
+  int* fpart = at<int>(ws, L.fpart);
+  if (side == 0) {
+    DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_H");
+    DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.tiles_m, T, R, mask, dsel, margin, s), "select_H");
+  } else {
+    DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_W");
+    DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, L.tiles_n, N, R, mask, dsel, margin, s), "select_W");
+  }
+  return DNA_OK;
+}
+
+struct Common {
+  Layout L;
+  int* chk;
+  hipStream_t s;
+};
+
+static dna_status prologue(const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
+                           const dna_opts* o, void* ws, size_t ws_bytes, void* stream, Common& c) {
+  DNA_TRY(check_dims(N, T, R));
+  DNA_TRY(check_opts(o));
+  c.L = make_layout(N, T, R);
+  DNA_TRY(check_ws(ws, ws_bytes, c.L.total));
+  c.s = static_cast<hipStream_t>(stream);
+  c.chk = o->checked ? at<int>(ws, c.L.check) : nullptr;
+  if (c.chk) {
+    const float* bufs[3] = {W, H, V};
+    const int64_t sizes[3] = {N * R, R * T, N * T};
+    DNA_TRY(checked_begin(c.chk, bufs, sizes, V ? 3 : 2, c.s));
+  }
+  return DNA_OK;
+}
+
+static dna_status epilogue(const Common& c) {
+  if (c.chk) return checked_end(c.chk, c.s);
+  return DNA_OK;
+}
+
+}  // namespace dna
+
+using namespace dna;
+
+// ---------------------------------------------------------------------------
+// Exported entry points.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void dna_default_opts(dna_opts* o) {
+  if (!o) return;
+  o->eps = 0.01f;
+  o->alpha = 4.0f;
+  o->gemm = DNA_GEMM_FP32;
+  o->checked = 0;
+}
+
+size_t dna_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* o) {
+  (void)o;
+  if (N <= 0 || T <= 0 || R <= 0) return 0;
+  return make_layout(N, T, R).total;
+}
+
+dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const dna_opts* o,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  Common c;
+  DNA_TRY(prologue(nullptr, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  double* f = at<double>(ws, c.L.c64);
+  if (side == 0) DNA_HIP(launch_colsum_W(W, N, R, f, nullptr, c.chk, c.s), "colsum_W");
+  else DNA_HIP(launch_rowsum_H(H, T, R, f, nullptr, c.chk, c.s), "rowsum_H");
+  DNA_HIP(launch_scale(side, W, H, N, T, R, f, c.s), "scale");
+  return epilogue(c);
+}
+
+dna_status dna_update_H(const float* V, const float* W, float* H, int64_t N, int64_t T, int64_t R,
+                        const dna_opts* o, void* ws, size_t ws_bytes, uint8_t* chose_newton, double* d_sel,
+                        double* margin, void* stream) {
+  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  float* Xmu = at<float>(ws, c.L.xmu);
+  float* Xn = at<float>(ws, c.L.xn);
+  DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s));
+  DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, c.L, ws, chose_newton, d_sel, margin, c.s));
+  return epilogue(c);
+}
+
+dna_status dna_update_W(const float* V, float* W, const float* H, int64_t N, int64_t T, int64_t R,
+                        const dna_opts* o, void* ws, size_t ws_bytes, uint8_t* chose_newton, double* d_sel,
+                        double* margin, void* stream) {
+  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  float* Xmu = at<float>(ws, c.L.xmu);
+  float* Xn = at<float>(ws, c.L.xn);
+  DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s));
+  DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, c.L, ws, chose_newton, d_sel, margin, c.s));
+  return epilogue(c);
+}
+
+dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                     int with_cost, double* d_out, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  if (with_cost && !d_out) return fail(DNA_EINVAL, "with_cost requires d_out");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  const Layout& L = c.L;
+  float* Q = at<float>(ws, L.q);
+  float* pu = at<float>(ws, L.pu);
+  float* c32 = at<float>(ws, L.c32);
+  double* cpart = at<double>(ws, L.cpart);
+  RatioArgs ra{V, W, H, N, T, R, Q, nullptr, nullptr, cpart, c.chk};
+  if (side == 0) {
+    DNA_HIP(launch_colsum_W(W, N, R, nullptr, c32, c.chk, c.s), "colsum_W");
+    DNA_HIP(launch_ratio(with_cost ? RM_MU_H_COST : RM_MU_H, ra, c.s), "ratio_mu_H");
+    DNA_HIP(launch_gh_H(W, Q, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, pu, c.s), "gh_mu_H");
+    DNA_HIP(launch_mu_H(H, pu, L.sh.splits, c32, T, R, cpart, L.tiles_m, with_cost ? d_out : nullptr, c.s), "mu_H");
+  } else {
+    DNA_HIP(launch_rowsum_H(H, T, R, nullptr, c32, c.chk, c.s), "rowsum_H");
+    DNA_HIP(launch_ratio(with_cost ? RM_MU_W_COST : RM_MU_W, ra, c.s), "ratio_mu_W");
+    DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, pu, c.s), "gh_mu_W");
+    DNA_HIP(launch_mu_W(W, pu, L.sw.splits, c32, N, R, cpart, L.tiles_n, with_cost ? d_out : nullptr, c.s), "mu_W");
+  }
+  return epilogue(c);
+}
+
+dna_status kl_cost(const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
+                   const dna_opts* o, void* ws, size_t ws_bytes, double* out, void* stream) {
+  if (!V || !W || !H || !out) return fail(DNA_EINVAL, "V, W, H or out is NULL");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  double* cpart = at<double>(ws, c.L.cpart);
+  RatioArgs ra{V, W, H, N, T, R, nullptr, nullptr, nullptr, cpart, c.chk};
+  DNA_HIP(launch_ratio(RM_KL, ra, c.s), "kl_terms");
+  DNA_HIP(launch_kl_final(cpart, c.L.tiles_m * c.L.tiles_n, out, c.s), "kl_final");
+  return epilogue(c);
+}
+
+dna_status dna_gradient_hessian(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T,
+                                int64_t R, const dna_opts* o, float* A_out, float* B_out, void* ws,
+                                size_t ws_bytes, void* stream) {
+  if (!V || !W || !H || !A_out || !B_out) return fail(DNA_EINVAL, "NULL argument");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  float* Xmu = at<float>(ws, c.L.xmu);
+  float* Xn = at<float>(ws, c.L.xn);
+  DNA_TRY(run_candidates(side, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, A_out, B_out, c.chk, c.s));
+  return epilogue(c);
+}
+
+dna_status dna_candidates(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T,
+                          int64_t R, const dna_opts* o, float* X_mu, float* X_newton, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!V || !W || !H || !X_mu || !X_newton) return fail(DNA_EINVAL, "NULL argument");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  DNA_TRY(run_candidates(side, V, W, H, N, T, R, o, c.L, ws, X_mu, X_newton, nullptr, nullptr, c.chk, c.s));
+  return epilogue(c);
+}
+
+dna_status dna_select(int side, const float* V, const float* F, const float* X_mu, const float* X_newton,
+                      float* X_out, int64_t N, int64_t T, int64_t R, const dna_opts* o, uint8_t* chose_newton,
+                      double* d_sel, double* margin, void* ws, size_t ws_bytes, void* stream) {
+  if (!V || !F || !X_mu || !X_newton || !X_out) return fail(DNA_EINVAL, "NULL argument");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  Common c;
+  DNA_TRY(check_dims(N, T, R));
+  DNA_TRY(check_opts(o));
+  c.L = make_layout(N, T, R);
+  DNA_TRY(check_ws(ws, ws_bytes, c.L.total));
+  c.s = static_cast<hipStream_t>(stream);
+  c.chk = nullptr;
+  DNA_TRY(run_select(side, V, F, X_mu, X_newton, X_out, N, T, R, c.L, ws, chose_newton, d_sel, margin, c.s));
+  return DNA_OK;
+}
+
+size_t dna_unrolled_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* o) {
+  (void)N; (void)T; (void)R; (void)o;
+  return 0;
+}
+
+dna_status dna_unrolled_H_fwd(const float*, const float*, const float*, int, int64_t, int64_t, int64_t,
+                              const dna_opts*, float*, uint8_t*, void*, size_t, void*) {
+  return fail(DNA_EUNSUPPORTED, "unrolled adjoint not built yet");
+}
+
+dna_status dna_unrolled_H_bwd(const float*, const float*, const float*, const uint8_t*, int, int64_t, int64_t,
+                              int64_t, const float*, float*, float*, float*, const dna_opts*, void*, size_t, void*) {
+  return fail(DNA_EUNSUPPORTED, "unrolled adjoint not built yet");
+}
+
+const char* dna_status_string(dna_status s) {
+  switch (s) {
+    case DNA_OK: return "DNA_OK";
+    case DNA_EINVAL: return "DNA_EINVAL: invalid argument";
+    case DNA_EWORKSPACE: return "DNA_EWORKSPACE: workspace too small";
+    case DNA_EDOMAIN: return "DNA_EDOMAIN: input outside the domain of the method";
+    case DNA_ENONFINITE: return "DNA_ENONFINITE: non-finite input";
+    case DNA_EHIP: return "DNA_EHIP: HIP runtime error";
+    case DNA_EUNSUPPORTED: return "DNA_EUNSUPPORTED: not supported by this build";
+  }
+  return "unknown dna_status";
+}
+
+const char* dna_last_error(void) { return g_err; }
+
+void dna_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof = on != 0;
+}
+
+void dna_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_pending) {
+    hipEventSynchronize(r.b ? r.b : r.a);
+    g_pool.push_back(r.a);
+    if (r.b) g_pool.push_back(r.b);
+  }
+  g_pending.clear();
+  g_stats.clear();
+}
+
+int dna_profile_read(dna_kernel_stat* out, int max_entries) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_pending) {
+    float ms = 0.f;
+    if (r.b && hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& e = g_stats[r.name];
+      e.first += 1;
+      e.second += ms;
+    }
+    g_pool.push_back(r.a);
+    if (r.b) g_pool.push_back(r.b);
+  }
+  g_pending.clear();
+  g_names.clear();
+  for (auto& kv : g_stats) g_names.push_back(kv.first);
+  int i = 0;
+  for (auto& kv : g_stats) {
+    if (out && i < max_entries) {
+      out[i].name = g_names[i].c_str();
+      out[i].launches = kv.second.first;
+      out[i].total_ms = kv.second.second;
+    }
+    ++i;
+  }
+  return (int)g_stats.size();
+}
+
+const char* dna_build_info(void) {
+  return "libdna gfx950 fp32-mfma32x32x2"
+#ifdef DNA_BUILD_FLAGS
+         " " DNA_BUILD_FLAGS
+#endif
+      ;
+}
+
+}  // extern "C"

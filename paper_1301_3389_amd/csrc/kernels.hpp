@@ -1,0 +1,103 @@
+// kernels.hpp -- internal (C++) launch interface between the C ABI layer and
+// the HIP kernels.  Nothing here is exported from libdna.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dna {
+
+// Kernel timing hooks (implemented by the ABI layer).
+void prof_begin(const char* name, hipStream_t s);
+void prof_end(const char* name, hipStream_t s);
+
+// Bits of the device check word (checked mode).
+enum CheckBits { CHK_DOMAIN = 1, CHK_NONFINITE = 2 };
+
+// Tile sizes the host uses to size partial-sum buffers.
+constexpr int ZT_BM = 128;   // rows (n) per tile of the Z = W H products
+constexpr int ZT_BN = 128;   // columns (t) per tile of the Z = W H products
+constexpr int GH_BM = 64;    // H orientation gradient GEMM: rows (r) per tile
+constexpr int GH_BN = 128;   //                              columns (t) per tile
+constexpr int GW_BM = 128;   // W orientation gradient GEMM: rows (n) per tile
+constexpr int GW_BN = 64;    //                              columns (r) per tile
+constexpr int GEMM_BK = 16;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// What the ratio pass (Z = W H and its epilogue) produces.
+enum RatioMode {
+  RM_H = 0,        // Q, Q-bar, column sums of V         (DNA H step)
+  RM_W = 1,        // Q, Q-bar, row sums of V            (DNA W step)
+  RM_MU_H = 2,     // Q only                              (MU H step)
+  RM_MU_H_COST = 3,// Q, per-column cost of the input
+  RM_MU_W = 4,     // Q only                              (MU W step)
+  RM_MU_W_COST = 5,// Q, per-row cost of the input
+  RM_KL = 6        // per-tile sums of the eq. (1) terms only
+};
+
+struct RatioArgs {
+  const float* V; const float* W; const float* H;
+  int64_t N, T, R;
+  float* Q; float* Qb;
+  double* vpart;      // [tiles_m][T] (column sums) or [tiles_n][N] (row sums)
+  double* cpart;      // cost partials, same layouts; RM_KL: [tiles]
+  int* check;         // nullptr unless checked
+};
+hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s);
+
+// Gradient / Hessian numerators, split over the contraction index.
+//   H orientation: pu[sp][r][t] = sum_{n in split} w_nr q_nt, py with w^2, q-bar
+//   W orientation: pu[sp][n][r] = sum_{t in split} q_nt h_rt, py with q-bar, h^2
+hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t N, int64_t T,
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* py,
+                       hipStream_t s);
+hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t N, int64_t T,
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* py,
+                       hipStream_t s);
+
+// Candidates (MU and renormalised Newton) from the split partials.
+hipError_t launch_cand_H(const float* H, const float* pu, const float* py, int splits,
+                         const float* c, const double* vpart, int tiles_m, int64_t T, int64_t R,
+                         float eps, float alpha, float* Xmu, float* Xn, float* Aout, float* Bout,
+                         hipStream_t s);
+hipError_t launch_cand_W(const float* W, const float* pu, const float* py, int splits,
+                         const float* g, const double* vpart, int tiles_n, int64_t N, int64_t R,
+                         float eps, float alpha, float* Xmu, float* Xn, float* Aout, float* Bout,
+                         hipStream_t s);
+
+// Fused candidate reconstruction + log + reduction (costs of both candidates).
+//   part: [3][tiles][L] float64 (sum_N, margin, MU-only rows), fpart: [tiles][L] int
+hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn,
+                         int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s);
+hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const float* Xn,
+                         int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s);
+
+// Selection and write-back.
+hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,
+                           const int* fpart, int tiles_m, int64_t T, int64_t R, uint8_t* mask,
+                           double* dsel, double* margin, hipStream_t s);
+hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const double* part,
+                           const int* fpart, int tiles_n, int64_t N, int64_t R, uint8_t* mask,
+                           double* dsel, double* margin, hipStream_t s);
+
+// MU update from split partials (+ optional cost finalisation).
+hipError_t launch_mu_H(float* H, const float* pu, int splits, const float* c, int64_t T, int64_t R,
+                       const double* cpart, int tiles_m, double* d_out, hipStream_t s);
+hipError_t launch_mu_W(float* W, const float* pu, int splits, const float* g, int64_t N, int64_t R,
+                       const double* cpart, int tiles_n, double* d_out, hipStream_t s);
+
+// Column sums of W (R values) / row sums of H (R values), float64 and float32.
+hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* sum64, float* sum32,
+                           int* check, hipStream_t s);
+hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* sum64, float* sum32,
+                           int* check, hipStream_t s);
+// side 0: W[:,r] /= f_r, H[r,:] *= f_r;  side 1: H[r,:] /= f_r, W[:,r] *= f_r
+hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                        const double* f, hipStream_t s);
+
+hipError_t launch_kl_final(const double* cpart, int ntiles, double* out, hipStream_t s);
+
+// Checked mode: negative or non-finite entries in a buffer.
+hipError_t launch_check(const float* X, int64_t n, int* check, hipStream_t s);
+
+}  // namespace dna

@@ -1,0 +1,857 @@
+// kernels_fwd.hip -- forward HIP kernels of one DNA / MU half-step (gfx950).
+//
+// H half-step (Algorithm 1 steps 4-15), kernel by kernel:
+//   k_ratio     Z = W H tile on MFMA (K = R); epilogue Q = V/Z, Q-bar = V/Z^2,
+//               column sums of V.  Z never leaves registers.
+//   k_gh_H      [A-numerator, B-numerator] = [W, W*W]^t [Q, Q-bar] on MFMA, the
+//               W tile staged once and squared in registers; split over N.
+//   k_cand_H    A (eq. 7), B (eq. 14), MU candidate (eq. 11), Newton candidate
+//               (eq. 15/17 with floor and ceiling) and its renormalisation (eq. 10).
+//   k_cost_H    Z_DNA = W H_DNA and dZ = W (H_MU - H_DNA) on MFMA with two
+//               accumulators; epilogue v log(v/z_DNA) and -v log1p(dZ/z_DNA),
+//               column sums in float64 (steps 7-9, 12-14).
+//   k_select_H  per column: d_DNA < d_MU ? Newton : MU (step 15), write H.
+// The W half-step runs the same stages in the transposed orientation
+// (contractions over T, per-row reductions).
+#include <math.h>
+
+#include <algorithm>
+
+#include "core.hpp"
+#include "kernels.hpp"
+
+namespace dna {
+
+using GZ = Geo<ZT_BM, ZT_BN, GEMM_BK, 2, 2>;   // Z-type products, M = N, N = T, K = R
+using GCW = Geo<64, ZT_BN, GEMM_BK, 2, 2>;     // W-orientation cost (row reductions)
+using GH = Geo<GH_BM, GH_BN, GEMM_BK, 2, 2>;   // H orientation gradient, M = R, N = T, K = N
+using GW = Geo<GW_BM, GW_BN, GEMM_BK, 2, 2>;   // W orientation gradient, M = N, N = R, K = T
+
+// ---------------------------------------------------------------------------
+// Deterministic tile reductions of per-lane partials.
+// Column form: cp[q][j] holds this lane's partial for column (j, lane&31).
+// Row form:    rp[q][i][v] holds this lane's partial for row blk_row(v) of block i.
+// `red` is LDS scratch of NQ * max(WGM*BN, WGN*BM) doubles.
+// ---------------------------------------------------------------------------
+template <class G, int NQ, class OUT>
+__device__ __forceinline__ void reduce_cols(double (&cp)[NQ][G::FN], double* red, OUT&& out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % G::WGM, wn = wave / G::WGM;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const double s = cp[q][j] + __shfl_xor(cp[q][j], 32);
+      if (lane < 32) red[(q * G::WGM + wm) * G::BN + wn * G::WN + j * 32 + lane] = s;
+    }
+  __syncthreads();
+  for (int c = tid; c < G::BN; c += G::NT) {
+    double s[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      s[q] = 0.0;
+      for (int m = 0; m < G::WGM; ++m) s[q] += red[(q * G::WGM + m) * G::BN + c];
+    }
+    out(c, s);
+  }
+  __syncthreads();
+}
+
+template <class G, int NQ, class OUT>
+__device__ __forceinline__ void reduce_rows(double (&rp)[NQ][G::FM][16], double* red, OUT&& out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % G::WGM, wn = wave / G::WGM;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i) {
+      const double y = halfwave_slot_sum(rp[q][i], lane);
+      if ((lane & 1) == 0) red[(q * G::WGN + wn) * G::BM + wm * G::WM + i * 32 + slot_row(lane)] = y;
+    }
+  __syncthreads();
+  for (int r = tid; r < G::BM; r += G::NT) {
+    double s[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      s[q] = 0.0;
+      for (int w = 0; w < G::WGN; ++w) s[q] += red[(q * G::WGN + w) * G::BM + r];
+    }
+    out(r, s);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double xlogx_over(float v, float z) {
+  // v log(v/z) for v > 0, z > 0 (the summand of eq. 1 and steps 9/14)
+  return (double)v * (double)logf(v / z);
+}
+
+// ---------------------------------------------------------------------------
+// k_ratio: Z = W H (MFMA, K = R) and its epilogue.
+// ---------------------------------------------------------------------------
+struct RatioKArgs {
+  const float* V;
+  Opnd W, H;
+  int64_t N, T, R;
+  float* Q; float* Qb;
+  double* vpart; double* cpart;
+  int* check;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(GZ::NT) void k_ratio(RatioKArgs a) {
+  using TL = Tile<GZ, ProdSingle, true, false>;
+  __shared__ __align__(16) float lds[TL::LDS_FLOATS];
+  const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
+  TL t;
+  t.zero();
+  {
+    const Opnd A[1] = {a.W};
+    const Opnd B[1] = {a.H};
+    t.run(A, B, m0, n0, 0, a.R, lds);
+  }
+  constexpr bool WANT_Q = MODE != RM_KL;
+  constexpr bool WANT_QB = MODE == RM_H || MODE == RM_W;
+  constexpr bool COLS = MODE == RM_H || MODE == RM_MU_H_COST;     // column partials
+  constexpr bool ROWS = MODE == RM_W || MODE == RM_MU_W_COST;     // row partials
+  constexpr bool COST = MODE == RM_MU_H_COST || MODE == RM_MU_W_COST;
+  const int64_t N = a.N, T = a.T;
+  double cp[1][GZ::FN];
+  double rp[1][GZ::FM][16];
+  double klsum = 0.0;
+#pragma unroll
+  for (int j = 0; j < GZ::FN; ++j) cp[0][j] = 0.0;
+#pragma unroll
+  for (int i = 0; i < GZ::FM; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) rp[0][i][v] = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int i = 0; i < GZ::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < GZ::FN; ++j) {
+      const int64_t col = TL::col_of(n0, j);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = TL::row_of(m0, i, v);
+        if (row < N && col < T) {
+          const float x = a.V[row * T + col];
+          const float z = t.acc[i][j][0][v];
+          float q = 0.f, qb = 0.f;
+          double term = 0.0;
+          if (x > 0.f) {
+            q = x / z;
+            qb = q / z;
+            if (!(z > 0.f)) bad = 1;
+            if (COST || MODE == RM_KL) term = xlogx_over(x, z);
+          }
+          if (WANT_Q) a.Q[row * T + col] = q;
+          if (WANT_QB) a.Qb[row * T + col] = qb;
+          if (MODE == RM_KL) klsum += term - (double)x + (double)z;
+          const double val = COST ? term : (double)x;
+          if (COLS) cp[0][j] += val;
+          if (ROWS) rp[0][i][v] += val;
+        }
+      }
+    }
+  if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
+  double* red = reinterpret_cast<double*>(lds);
+  if (COLS) {
+    double* dst = COST ? a.cpart : a.vpart;
+    reduce_cols<GZ, 1>(cp, red, [&](int c, const double (&s)[1]) {
+      if (n0 + c < T) dst[(int64_t)blockIdx.y * T + n0 + c] = s[0];
+    });
+  }
+  if (ROWS) {
+    double* dst = COST ? a.cpart : a.vpart;
+    reduce_rows<GZ, 1>(rp, red, [&](int r, const double (&s)[1]) {
+      if (m0 + r < N) dst[(int64_t)blockIdx.x * N + m0 + r] = s[0];
+    });
+  }
+  if (MODE == RM_KL) {
+    const int tid = threadIdx.x;
+    const double w = wave_sum(klsum);
+    if ((tid & 63) == 0) red[tid >> 6] = w;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int k = 0; k < GZ::WAVES; ++k) s += red[k];
+      a.cpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
+  RatioKArgs k;
+  k.V = a.V;
+  k.W = make_opnd(a.W, a.R, a.N);
+  k.H = make_opnd(a.H, a.T, a.T);
+  k.N = a.N; k.T = a.T; k.R = a.R;
+  k.Q = a.Q; k.Qb = a.Qb; k.vpart = a.vpart; k.cpart = a.cpart; k.check = a.check;
+  dim3 grid((unsigned)cdiv(a.T, GZ::BN), (unsigned)cdiv(a.N, GZ::BM));
+  const char* nm = "ratio";
+#define DNA_RATIO_CASE(M, NAME)                                         \
+  case M:                                                                \
+    nm = NAME;                                                           \
+    prof_begin(nm, s);                                                   \
+    hipLaunchKernelGGL(k_ratio<M>, grid, dim3(GZ::NT), 0, s, k);         \
+    break;
+  switch (mode) {
+    DNA_RATIO_CASE(RM_H, "ratio_H")
+    DNA_RATIO_CASE(RM_W, "ratio_W")
+    DNA_RATIO_CASE(RM_MU_H, "ratio_mu_H")
+    DNA_RATIO_CASE(RM_MU_H_COST, "ratio_mu_H_cost")
+    DNA_RATIO_CASE(RM_MU_W, "ratio_mu_W")
+    DNA_RATIO_CASE(RM_MU_W_COST, "ratio_mu_W_cost")
+    DNA_RATIO_CASE(RM_KL, "kl_terms")
+    default: return hipErrorInvalidValue;
+  }
+#undef DNA_RATIO_CASE
+  prof_end(nm, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gradient / Hessian numerators.
+// ---------------------------------------------------------------------------
+template <class PR>
+__global__ __launch_bounds__(GH::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64_t N, int64_t T,
+                                                  int64_t R, int64_t kchunk, float* pu, float* py) {
+  using TL = Tile<GH, PR, false, false>;
+  __shared__ __align__(16) float lds[TL::LDS_FLOATS];
+  const int64_t m0 = (int64_t)blockIdx.y * GH::BM, n0 = (int64_t)blockIdx.x * GH::BN;
+  const int64_t sp = blockIdx.z;
+  const int64_t k0 = sp * kchunk, k1 = min(N, k0 + kchunk);
+  TL t;
+  t.zero();
+  {
+    const Opnd A[PR::NA] = {Wt};
+    Opnd B[PR::NB];
+    B[0] = Q;
+    if constexpr (PR::NB > 1) B[PR::NB - 1] = Qb;
+    t.run(A, B, m0, n0, k0, k1, lds);
+  }
+  float* du = pu + sp * R * T;
+  float* dy = py + sp * R * T;
+#pragma unroll
+  for (int i = 0; i < GH::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < GH::FN; ++j) {
+      const int64_t col = TL::col_of(n0, j);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = TL::row_of(m0, i, v);
+        if (row < R && col < T) {
+          du[row * T + col] = t.acc[i][j][0][v];
+          if constexpr (PR::NC > 1) dy[row * T + col] = t.acc[i][j][PR::NC - 1][v];
+        }
+      }
+    }
+}
+
+hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t N, int64_t T,
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* py, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(T, GH::BN), (unsigned)cdiv(R, GH::BM), (unsigned)splits);
+  const Opnd wt = make_opnd(W, R, R);     // element (r, n) at W[n*R + r]: MN-contiguous
+  const Opnd q = make_opnd(Q, T, T);      // element (t, n) at Q[n*T + t]: MN-contiguous
+  if (Qb) {
+    const Opnd qb = make_opnd(Qb, T, T);
+    prof_begin("gh_H", s);
+    hipLaunchKernelGGL(k_gh_H<ProdDualB_SqA>, grid, dim3(GH::NT), 0, s, wt, q, qb, N, T, R, kchunk, pu, py);
+    prof_end("gh_H", s);
+  } else {
+    prof_begin("gh_mu_H", s);
+    hipLaunchKernelGGL(k_gh_H<ProdSingle>, grid, dim3(GH::NT), 0, s, wt, q, q, N, T, R, kchunk, pu, pu);
+    prof_end("gh_mu_H", s);
+  }
+  return hipGetLastError();
+}
+
+template <class PR>
+__global__ __launch_bounds__(GW::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64_t N, int64_t T,
+                                                  int64_t R, int64_t kchunk, float* pu, float* py) {
+  using TL = Tile<GW, PR, true, true>;
+  __shared__ __align__(16) float lds[TL::LDS_FLOATS];
+  const int64_t m0 = (int64_t)blockIdx.y * GW::BM, n0 = (int64_t)blockIdx.x * GW::BN;
+  const int64_t sp = blockIdx.z;
+  const int64_t k0 = sp * kchunk, k1 = min(T, k0 + kchunk);
+  TL t;
+  t.zero();
+  {
+    Opnd A[PR::NA];
+    A[0] = Q;
+    if constexpr (PR::NA > 1) A[PR::NA - 1] = Qb;
+    const Opnd B[PR::NB] = {Ht};
+    t.run(A, B, m0, n0, k0, k1, lds);
+  }
+  float* du = pu + sp * N * R;
+  float* dy = py + sp * N * R;
+#pragma unroll
+  for (int i = 0; i < GW::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < GW::FN; ++j) {
+      const int64_t col = TL::col_of(n0, j);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = TL::row_of(m0, i, v);
+        if (row < N && col < R) {
+          du[row * R + col] = t.acc[i][j][0][v];
+          if constexpr (PR::NC > 1) dy[row * R + col] = t.acc[i][j][PR::NC - 1][v];
+        }
+      }
+    }
+}
+
+hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t N, int64_t T,
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* py, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(R, GW::BN), (unsigned)cdiv(N, GW::BM), (unsigned)splits);
+  const Opnd q = make_opnd(Q, T, N);      // element (n, t) at Q[n*T + t]: K-contiguous
+  const Opnd ht = make_opnd(H, T, R);     // element (r, t) at H[r*T + t]: K-contiguous
+  if (Qb) {
+    const Opnd qb = make_opnd(Qb, T, N);
+    prof_begin("gh_W", s);
+    hipLaunchKernelGGL(k_gh_W<ProdDualA_SqB>, grid, dim3(GW::NT), 0, s, q, qb, ht, N, T, R, kchunk, pu, py);
+    prof_end("gh_W", s);
+  } else {
+    prof_begin("gh_mu_W", s);
+    hipLaunchKernelGGL(k_gh_W<ProdSingle>, grid, dim3(GW::NT), 0, s, q, q, ht, N, T, R, kchunk, pu, pu);
+    prof_end("gh_mu_W", s);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Candidates.
+// ---------------------------------------------------------------------------
+struct Cand {
+  float mu, newton, A, B;
+};
+
+// One coordinate: numerators u = (F^t q)_r, y = ((F*F)^t q-bar)_r, scale c_r.
+__device__ __forceinline__ Cand candidate(float x, float u, float y, float c, float eps, float alpha) {
+  Cand o;
+  const float g = u / c;            // MU gain (W^t q)_r / (W^t 1)_r, eq. (11)
+  o.A = g - 1.f;                    // eq. (7)
+  o.B = y / c;                      // eq. (14)
+  o.mu = x * g;
+  if (o.A < 0.f) {                  // eq. (15), gain floored at eps
+    const float xb = x * o.B;
+    o.newton = x * fmaxf(xb / (xb - o.A), eps);
+  } else {                          // eq. (17), step capped at alpha x
+    const float step = (o.B > 0.f) ? o.A / o.B : (o.A > 0.f ? INFINITY : 0.f);
+    o.newton = x + fminf(step, alpha * x);
+  }
+  return o;
+}
+
+// 64 columns per block, 4 row groups; renormalisation eq. (10) per column.
+__global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu, const float* py, int splits,
+                                                const float* c, const double* vpart, int tiles_m,
+                                                int64_t T, int64_t R, float eps, float alpha,
+                                                float* Xmu, float* Xn, float* Aout, float* Bout) {
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 64 + cl;
+  const bool ok = t < T;
+  double den = 0.0;
+  if (ok) {
+    for (int64_t r = rg; r < R; r += 4) {
+      float u = 0.f, y = 0.f;
+      for (int sp = 0; sp < splits; ++sp) {
+        u += pu[(sp * R + r) * T + t];
+        y += py[(sp * R + r) * T + t];
+      }
+      const Cand k = candidate(H[r * T + t], u, y, c[r], eps, alpha);
+      Xmu[r * T + t] = k.mu;
+      Xn[r * T + t] = k.newton;
+      if (Aout) Aout[r * T + t] = k.A;
+      if (Bout) Bout[r * T + t] = k.B;
+      den += (double)c[r] * (double)k.newton;
+    }
+  }
+  red[rg][cl] = den;
+  __syncthreads();
+  if (ok) {
+    const double d = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+    double s = 0.0;
+    for (int m = 0; m < tiles_m; ++m) s += vpart[(int64_t)m * T + t];
+    const double f = d > 0.0 ? s / d : 1.0;
+    for (int64_t r = rg; r < R; r += 4) Xn[r * T + t] = (float)((double)Xn[r * T + t] * f);
+  }
+}
+
+hipError_t launch_cand_H(const float* H, const float* pu, const float* py, int splits, const float* c,
+                         const double* vpart, int tiles_m, int64_t T, int64_t R, float eps, float alpha,
+                         float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
+  prof_begin("cand_H", s);
+  hipLaunchKernelGGL(k_cand_H, dim3((unsigned)cdiv(T, 64)), dim3(256), 0, s, H, pu, py, splits, c, vpart,
+                     tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
+  prof_end("cand_H", s);
+  return hipGetLastError();
+}
+
+// One wave per row n of W; lanes stride over r.
+__global__ __launch_bounds__(256) void k_cand_W(const float* W, const float* pu, const float* py, int splits,
+                                                const float* g, const double* vpart, int tiles_n,
+                                                int64_t N, int64_t R, float eps, float alpha,
+                                                float* Xmu, float* Xn, float* Aout, float* Bout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= N) return;
+  double den = 0.0;
+  for (int64_t r = lane; r < R; r += 64) {
+    float u = 0.f, y = 0.f;
+    for (int sp = 0; sp < splits; ++sp) {
+      u += pu[(sp * N + n) * R + r];
+      y += py[(sp * N + n) * R + r];
+    }
+    const Cand k = candidate(W[n * R + r], u, y, g[r], eps, alpha);
+    Xmu[n * R + r] = k.mu;
+    Xn[n * R + r] = k.newton;
+    if (Aout) Aout[n * R + r] = k.A;
+    if (Bout) Bout[n * R + r] = k.B;
+    den += (double)g[r] * (double)k.newton;
+  }
+  double s = 0.0;
+  for (int64_t m = lane; m < tiles_n; m += 64) s += vpart[m * N + n];
+  den = __shfl(wave_sum(den), 0);
+  s = __shfl(wave_sum(s), 0);
+  const double f = den > 0.0 ? s / den : 1.0;
+  for (int64_t r = lane; r < R; r += 64) Xn[n * R + r] = (float)((double)Xn[n * R + r] * f);
+}
+
+hipError_t launch_cand_W(const float* W, const float* pu, const float* py, int splits, const float* g,
+                         const double* vpart, int tiles_n, int64_t N, int64_t R, float eps, float alpha,
+                         float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
+  prof_begin("cand_W", s);
+  hipLaunchKernelGGL(k_cand_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, W, pu, py, splits, g, vpart,
+                     tiles_n, N, R, eps, alpha, Xmu, Xn, Aout, Bout);
+  prof_end("cand_W", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused candidate costs.  Per element with v > 0 and z_DNA, z_MU the two
+// reconstructions (z_MU = z_DNA + dZ):
+//   q0 += v log(v/z_DNA)          (d_DNA; rows with z_DNA <= 0 flag bit 1)
+//   q1 += -v log1p(dZ/z_DNA)      (d_MU - d_DNA; rows where both z > 0)
+//   q2 += v log(v/z_MU)           (rows with z_DNA <= 0 < z_MU; bit 2 if z_MU <= 0)
+// so that, absent flags, d_MU = q0 + q1 and margin = q1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cost_terms(float x, float zN, float dz, double (&q)[3], int& fl) {
+  const float zM = zN + dz;
+  const bool okN = zN > 0.f, okM = zM > 0.f;
+  if (okN) q[0] = xlogx_over(x, zN); else fl |= 1;
+  if (okN && okM) q[1] = -(double)x * (double)log1pf(dz / zN);
+  else if (okM) q[2] = xlogx_over(x, zM);
+  if (!okM) fl |= 2;
+}
+
+__global__ __launch_bounds__(GZ::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,
+                                                    int64_t T, int64_t R, double* part, int* fpart) {
+  using TL = Tile<GZ, ProdDualB, true, false>;
+  __shared__ __align__(16) float lds[TL::LDS_FLOATS];
+  __shared__ int fl_s[GZ::BN];
+  const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
+  const int tid = threadIdx.x;
+  for (int c = tid; c < GZ::BN; c += GZ::NT) fl_s[c] = 0;
+  TL t;
+  t.zero();
+  {
+    const Opnd A[1] = {W};
+    const Opnd B[2] = {Hn, Hd};
+    t.run(A, B, m0, n0, 0, R, lds);
+  }
+  double cp[3][GZ::FN];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int j = 0; j < GZ::FN; ++j) cp[q][j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < GZ::FN; ++j) {
+    const int64_t col = TL::col_of(n0, j);
+    int fl = 0;
+#pragma unroll
+    for (int i = 0; i < GZ::FM; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = TL::row_of(m0, i, v);
+        if (row < N && col < T) {
+          const float x = V[row * T + col];
+          if (x > 0.f) {
+            double q[3] = {0.0, 0.0, 0.0};
+            cost_terms(x, t.acc[i][j][0][v], t.acc[i][j][1][v], q, fl);
+            cp[0][j] += q[0];
+            cp[1][j] += q[1];
+            cp[2][j] += q[2];
+          }
+        }
+      }
+    if (fl) atomicOr(&fl_s[col - n0], fl);
+  }
+  const int64_t L = T, base = (int64_t)blockIdx.y * T;
+  const int64_t stride = (int64_t)gridDim.y * T;
+  reduce_cols<GZ, 3>(cp, reinterpret_cast<double*>(lds), [&](int c, const double (&s)[3]) {
+    if (n0 + c < L) {
+      part[base + n0 + c] = s[0];
+      part[stride + base + n0 + c] = s[1];
+      part[2 * stride + base + n0 + c] = s[2];
+      fpart[base + n0 + c] = fl_s[c];
+    }
+  });
+}
+
+hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn, int64_t N,
+                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(T, GZ::BN), (unsigned)cdiv(N, GZ::BM));
+  const Opnd w = make_opnd(W, R, N);
+  const Opnd hn = make_opnd(Xn, T, T);
+  const Opnd hd = make_opnd(Xmu, T, T, Xn);
+  prof_begin("cost_H", s);
+  hipLaunchKernelGGL(k_cost_H, grid, dim3(GZ::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart);
+  prof_end("cost_H", s);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(GCW::NT) void k_cost_W(const float* V, Opnd Wn, Opnd Wd, Opnd H, int64_t N,
+                                                     int64_t T, int64_t R, double* part, int* fpart) {
+  using TL = Tile<GCW, ProdDualA, true, false>;
+  __shared__ __align__(16) float lds[TL::LDS_FLOATS];
+  __shared__ int fl_s[GCW::BM];
+  const int64_t m0 = (int64_t)blockIdx.y * GCW::BM, n0 = (int64_t)blockIdx.x * GCW::BN;
+  const int tid = threadIdx.x;
+  for (int r = tid; r < GCW::BM; r += GCW::NT) fl_s[r] = 0;
+  TL t;
+  t.zero();
+  {
+    const Opnd A[2] = {Wn, Wd};
+    const Opnd B[1] = {H};
+    t.run(A, B, m0, n0, 0, R, lds);
+  }
+  double rp[3][GCW::FM][16];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int i = 0; i < GCW::FM; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) rp[q][i][v] = 0.0;
+#pragma unroll
+  for (int i = 0; i < GCW::FM; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = TL::row_of(m0, i, v);
+      int fl = 0;
+#pragma unroll
+      for (int j = 0; j < GCW::FN; ++j) {
+        const int64_t col = TL::col_of(n0, j);
+        if (row < N && col < T) {
+          const float x = V[row * T + col];
+          if (x > 0.f) {
+            double q[3] = {0.0, 0.0, 0.0};
+            cost_terms(x, t.acc[i][j][0][v], t.acc[i][j][1][v], q, fl);
+            rp[0][i][v] += q[0];
+            rp[1][i][v] += q[1];
+            rp[2][i][v] += q[2];
+          }
+        }
+      }
+      if (fl) atomicOr(&fl_s[row - m0], fl);
+    }
+  const int64_t base = (int64_t)blockIdx.x * N;
+  const int64_t stride = (int64_t)gridDim.x * N;
+  reduce_rows<GCW, 3>(rp, reinterpret_cast<double*>(lds), [&](int r, const double (&s)[3]) {
+    if (m0 + r < N) {
+      part[base + m0 + r] = s[0];
+      part[stride + base + m0 + r] = s[1];
+      part[2 * stride + base + m0 + r] = s[2];
+      fpart[base + m0 + r] = fl_s[r];
+    }
+  });
+}
+
+hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const float* Xn, int64_t N,
+                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(T, GCW::BN), (unsigned)cdiv(N, GCW::BM));
+  const Opnd wn = make_opnd(Xn, R, N);
+  const Opnd wd = make_opnd(Xmu, R, N, Xn);
+  const Opnd h = make_opnd(H, T, T);
+  prof_begin("cost_W", s);
+  hipLaunchKernelGGL(k_cost_W, grid, dim3(GCW::NT), 0, s, V, wn, wd, h, N, T, R, part, fpart);
+  prof_end("cost_W", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Selection (steps 15 and 28).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool decide(double q0, double q1, double q2, int fl, double& dsel, double& margin) {
+  const double dN = (fl & 1) ? INFINITY : q0;
+  const double dM = (fl & 2) ? INFINITY : q0 + q1 + q2;
+  bool newton;
+  if (fl == 0) {
+    newton = q1 > 0.0;        // d_DNA < d_MU, decided on the directly computed difference
+    margin = q1;
+  } else {
+    newton = dN < dM;
+    margin = dM - dN;
+  }
+  dsel = newton ? dN : dM;
+  return newton;
+}
+
+__global__ __launch_bounds__(256) void k_select_H(const float* Xmu, const float* Xn, float* Hout,
+                                                  const double* part, const int* fpart, int tiles,
+                                                  int64_t T, int64_t R, uint8_t* mask, double* dsel,
+                                                  double* margin) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= T) return;
+  const int64_t stride = (int64_t)tiles * T;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  int fl = 0;
+  for (int m = 0; m < tiles; ++m) {
+    const int64_t o = (int64_t)m * T + t;
+    q0 += part[o];
+    q1 += part[stride + o];
+    q2 += part[2 * stride + o];
+    fl |= fpart[o];
+  }
+  double ds, mg;
+  const bool nw = decide(q0, q1, q2, fl, ds, mg);
+  if (mask) mask[t] = nw ? 1 : 0;
+  if (dsel) dsel[t] = ds;
+  if (margin) margin[t] = mg;
+  const float* src = nw ? Xn : Xmu;
+  for (int64_t r = 0; r < R; ++r) Hout[r * T + t] = src[r * T + t];
+}
+
+hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,
+                           const int* fpart, int tiles_m, int64_t T, int64_t R, uint8_t* mask,
+                           double* dsel, double* margin, hipStream_t s) {
+  prof_begin("select_H", s);
+  hipLaunchKernelGGL(k_select_H, dim3((unsigned)cdiv(T, 256)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
+                     tiles_m, T, R, mask, dsel, margin);
+  prof_end("select_H", s);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_select_W(const float* Xmu, const float* Xn, float* Wout,
+                                                  const double* part, const int* fpart, int tiles,
+                                                  int64_t N, int64_t R, uint8_t* mask, double* dsel,
+                                                  double* margin) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= N) return;
+  const int64_t stride = (int64_t)tiles * N;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  int fl = 0;
+  for (int64_t m = lane; m < tiles; m += 64) {
+    const int64_t o = m * N + n;
+    q0 += part[o];
+    q1 += part[stride + o];
+    q2 += part[2 * stride + o];
+    fl |= fpart[o];
+  }
+  q0 = __shfl(wave_sum(q0), 0);
+  q1 = __shfl(wave_sum(q1), 0);
+  q2 = __shfl(wave_sum(q2), 0);
+  fl = wave_or(fl);
+  double ds, mg;
+  const bool nw = decide(q0, q1, q2, fl, ds, mg);
+  if (lane == 0) {
+    if (mask) mask[n] = nw ? 1 : 0;
+    if (dsel) dsel[n] = ds;
+    if (margin) margin[n] = mg;
+  }
+  const float* src = nw ? Xn : Xmu;
+  for (int64_t r = lane; r < R; r += 64) Wout[n * R + r] = src[n * R + r];
+}
+
+hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const double* part,
+                           const int* fpart, int tiles_n, int64_t N, int64_t R, uint8_t* mask,
+                           double* dsel, double* margin, hipStream_t s) {
+  prof_begin("select_W", s);
+  hipLaunchKernelGGL(k_select_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, Xmu, Xn, Wout, part, fpart,
+                     tiles_n, N, R, mask, dsel, margin);
+  prof_end("select_W", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MU updates (eq. 11): X <- X * numerator / scale.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mu_H(float* H, const float* pu, int splits, const float* c,
+                                              int64_t T, int64_t R, const double* cpart, int tiles,
+                                              double* d_out) {
+  const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 64 + cl;
+  if (t >= T) return;
+  for (int64_t r = rg; r < R; r += 4) {
+    float u = 0.f;
+    for (int sp = 0; sp < splits; ++sp) u += pu[(sp * R + r) * T + t];
+    H[r * T + t] = H[r * T + t] * (u / c[r]);
+  }
+  if (d_out && rg == 0) {
+    double s = 0.0;
+    for (int m = 0; m < tiles; ++m) s += cpart[(int64_t)m * T + t];
+    d_out[t] = s;
+  }
+}
+
+hipError_t launch_mu_H(float* H, const float* pu, int splits, const float* c, int64_t T, int64_t R,
+                       const double* cpart, int tiles_m, double* d_out, hipStream_t s) {
+  prof_begin("mu_H", s);
+  hipLaunchKernelGGL(k_mu_H, dim3((unsigned)cdiv(T, 64)), dim3(256), 0, s, H, pu, splits, c, T, R, cpart,
+                     tiles_m, d_out);
+  prof_end("mu_H", s);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_mu_W(float* W, const float* pu, int splits, const float* g,
+                                              int64_t N, int64_t R, const double* cpart, int tiles,
+                                              double* d_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= N) return;
+  for (int64_t r = lane; r < R; r += 64) {
+    float u = 0.f;
+    for (int sp = 0; sp < splits; ++sp) u += pu[(sp * N + n) * R + r];
+    W[n * R + r] = W[n * R + r] * (u / g[r]);
+  }
+  if (d_out) {
+    double s = 0.0;
+    for (int64_t m = lane; m < tiles; m += 64) s += cpart[m * N + n];
+    s = wave_sum(s);
+    if (lane == 0) d_out[n] = s;
+  }
+}
+
+hipError_t launch_mu_W(float* W, const float* pu, int splits, const float* g, int64_t N, int64_t R,
+                       const double* cpart, int tiles_n, double* d_out, hipStream_t s) {
+  prof_begin("mu_W", s);
+  hipLaunchKernelGGL(k_mu_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, W, pu, splits, g, N, R, cpart,
+                     tiles_n, d_out);
+  prof_end("mu_W", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Normalisation (steps 1, 16, 29) and the column / row sums they need.
+// ---------------------------------------------------------------------------
+// Column sums of W (N x R): 64 columns per block, 16 row groups.
+__global__ __launch_bounds__(1024) void k_colsum_W(const float* W, int64_t N, int64_t R, double* s64,
+                                                   float* s32, int* check) {
+  __shared__ double red[16][64];
+  const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 64 + cl;
+  double s = 0.0;
+  if (r < R)
+    for (int64_t n = rg; n < N; n += 16) s += (double)W[n * R + r];
+  red[rg][cl] = s;
+  __syncthreads();
+  if (rg == 0 && r < R) {
+    double tot = 0.0;
+    for (int k = 0; k < 16; ++k) tot += red[k][cl];
+    if (s64) s64[r] = tot;
+    if (s32) s32[r] = (float)tot;
+    if (check && !(tot > 0.0)) atomicOr(check, CHK_DOMAIN);
+  }
+}
+
+hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* sum64, float* sum32, int* check,
+                           hipStream_t s) {
+  prof_begin("colsum_W", s);
+  hipLaunchKernelGGL(k_colsum_W, dim3((unsigned)cdiv(R, 64)), dim3(1024), 0, s, W, N, R, sum64, sum32, check);
+  prof_end("colsum_W", s);
+  return hipGetLastError();
+}
+
+// Row sums of H (R x T): one block per row.
+__global__ __launch_bounds__(256) void k_rowsum_H(const float* H, int64_t T, int64_t R, double* s64,
+                                                  float* s32, int* check) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int64_t r = blockIdx.x;
+  double s = 0.0;
+  for (int64_t t = tid; t < T; t += 256) s += (double)H[r * T + t];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+    if (s64) s64[r] = tot;
+    if (s32) s32[r] = (float)tot;
+    if (check && !(tot > 0.0)) atomicOr(check, CHK_DOMAIN);
+  }
+}
+
+hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* sum64, float* sum32, int* check,
+                           hipStream_t s) {
+  prof_begin("rowsum_H", s);
+  hipLaunchKernelGGL(k_rowsum_H, dim3((unsigned)R), dim3(256), 0, s, H, T, R, sum64, sum32, check);
+  prof_end("rowsum_H", s);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                                               const double* f) {
+  const int64_t nw = N * R, total = nw + R * T;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    if (e < nw) {
+      const double fr = f[e % R];
+      if (fr > 0.0) W[e] = (float)(side == 0 ? (double)W[e] / fr : (double)W[e] * fr);
+    } else {
+      const int64_t h = e - nw;
+      const double fr = f[h / T];
+      if (fr > 0.0) H[h] = (float)(side == 0 ? (double)H[h] * fr : (double)H[h] / fr);
+    }
+  }
+}
+
+hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const double* f,
+                        hipStream_t s) {
+  const int64_t total = N * R + R * T;
+  const unsigned blocks = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
+  prof_begin("scale", s);
+  hipLaunchKernelGGL(k_scale, dim3(blocks), dim3(256), 0, s, side, W, H, N, T, R, f);
+  prof_end("scale", s);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_kl_final(const double* cpart, int ntiles, double* out) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int k = tid; k < ntiles; k += 256) s += cpart[k];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_kl_final(const double* cpart, int ntiles, double* out, hipStream_t s) {
+  prof_begin("kl_final", s);
+  hipLaunchKernelGGL(k_kl_final, dim3(1), dim3(256), 0, s, cpart, ntiles, out);
+  prof_end("kl_final", s);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_check(const float* X, int64_t n, int* check) {
+  int fl = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const float x = X[e];
+    if (!isfinite(x)) fl |= CHK_NONFINITE;
+    else if (x < 0.f) fl |= CHK_DOMAIN;
+  }
+  fl = wave_or(fl);
+  if ((threadIdx.x & 63) == 0 && fl) atomicOr(check, fl);
+}
+
+hipError_t launch_check(const float* X, int64_t n, int* check, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<int64_t>(cdiv(n, 256), 4096);
+  prof_begin("check", s);
+  hipLaunchKernelGGL(k_check, dim3(blocks), dim3(256), 0, s, X, n, check);
+  prof_end("check", s);
+  return hipGetLastError();
+}
+
+}  // namespace dna

@@ -1,0 +1,330 @@
+"""Python binding of libdna (ctypes): argument marshalling only.
+
+Every computation runs in the HIP kernels behind the C ABI declared in
+include/dna.h; this module checks tensors, allocates the workspace and the
+optional outputs with torch, and passes torch's current HIP stream.  Importing
+it raises if libdna.so has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdna.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1301_3389_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+_int = ctypes.c_int
+_sz = ctypes.c_size_t
+
+GEMM_TYPES = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+STATUS = {0: "DNA_OK", 1: "DNA_EINVAL", 2: "DNA_EWORKSPACE", 3: "DNA_EDOMAIN",
+          4: "DNA_ENONFINITE", 5: "DNA_EHIP", 6: "DNA_EUNSUPPORTED"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("gemm", ctypes.c_int), ("checked", ctypes.c_int)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+def _decl(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_OP = ctypes.POINTER(Opts)
+_lib_default_opts = _decl("dna_default_opts", None, _OP)
+_lib_ws = _decl("dna_workspace_bytes", _sz, _i64, _i64, _i64, _OP)
+_lib_uws = _decl("dna_unrolled_workspace_bytes", _sz, _i64, _i64, _i64, _OP)
+_lib_normalize = _decl("dna_normalize", _int, _int, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p)
+_lib_update_H = _decl("dna_update_H", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
+_lib_update_W = _decl("dna_update_W", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
+_lib_mu = _decl("mu_update", _int, _int, _p, _p, _p, _i64, _i64, _i64, _int, _p, _OP, _p, _sz, _p)
+_lib_kl = _decl("kl_cost", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
+_lib_gh = _decl("dna_gradient_hessian", _int, _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _p, _p, _sz, _p)
+_lib_cand = _decl("dna_candidates", _int, _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _p, _p, _sz, _p)
+_lib_select = _decl("dna_select", _int, _int, _p, _p, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _p, _p,
+                    _p, _sz, _p)
+_lib_ufwd = _decl("dna_unrolled_H_fwd", _int, _p, _p, _p, _int, _i64, _i64, _i64, _OP, _p, _p, _p, _sz, _p)
+_lib_ubwd = _decl("dna_unrolled_H_bwd", _int, _p, _p, _p, _p, _int, _i64, _i64, _i64, _p, _p, _p, _p,
+                  _OP, _p, _sz, _p)
+_lib_status_string = _decl("dna_status_string", ctypes.c_char_p, _int)
+_lib_last_error = _decl("dna_last_error", ctypes.c_char_p)
+_lib_prof_enable = _decl("dna_profile_enable", None, _int)
+_lib_prof_reset = _decl("dna_profile_reset", None)
+_lib_prof_read = _decl("dna_profile_read", _int, ctypes.POINTER(KernelStat), _int)
+_lib_build_info = _decl("dna_build_info", ctypes.c_char_p)
+
+EXPORTED = [
+    "dna_default_opts", "dna_workspace_bytes", "dna_normalize", "dna_update_H", "dna_update_W",
+    "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
+    "dna_unrolled_workspace_bytes", "dna_unrolled_H_fwd", "dna_unrolled_H_bwd",
+    "dna_status_string", "dna_last_error", "dna_profile_enable", "dna_profile_reset",
+    "dna_profile_read", "dna_build_info",
+]
+
+
+class DNAError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(status):
+    if status != 0:
+        raise DNAError(status, _lib_last_error().decode())
+
+
+def make_opts(eps=0.01, alpha=4.0, gemm="fp32", checked=False):
+    o = Opts()
+    _lib_default_opts(ctypes.byref(o))
+    o.eps = float(eps)
+    o.alpha = float(alpha)
+    o.gemm = GEMM_TYPES[gemm] if isinstance(gemm, str) else int(gemm)
+    o.checked = 1 if checked else 0
+    return o
+
+
+def build_info():
+    return _lib_build_info().decode()
+
+
+# --------------------------------------------------------------------------- helpers
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _mat(x, name, shape=None):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2:
+        raise ValueError(f"{name} must be a contiguous 2-D float32 tensor on the GPU")
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(shape)}")
+    return x
+
+
+def _dims(V, W, H):
+    N, T = V.shape
+    R = W.shape[1]
+    _mat(V, "V")
+    _mat(W, "W", (N, R))
+    _mat(H, "H", (R, T))
+    return N, T, R
+
+
+_ws_cache = {}
+
+
+def workspace(N, T, R, opts=None, unrolled=False):
+    """Device workspace for an N x T x R problem (cached per size and device)."""
+    o = opts or make_opts()
+    nbytes = (_lib_uws if unrolled else _lib_ws)(N, T, R, ctypes.byref(o))
+    dev = torch.cuda.current_device()
+    key = (dev, unrolled)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{dev}")
+        _ws_cache[key] = buf
+    return buf, nbytes
+
+
+def release_workspace():
+    _ws_cache.clear()
+
+
+def _opt_out(flag, n, dtype, device):
+    if flag is None or flag is False:
+        return None
+    if isinstance(flag, torch.Tensor):
+        return flag
+    return torch.empty(n, dtype=dtype, device=device)
+
+
+# --------------------------------------------------------------------------- entry points
+
+def normalize(side, W, H, **kw):
+    """Algorithm 1 steps 1/29 (side 0) or 16 (side 1), in place."""
+    _mat(W, "W")
+    N, R = W.shape
+    _mat(H, "H", (R, H.shape[1]))
+    T = H.shape[1]
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    _check(_lib_normalize(int(side), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
+                          _stream()))
+
+
+def update_H(V, W, H, *, mask=False, d_sel=False, margin=False, **kw):
+    """One DNA update of H in place (Algorithm 1 steps 4-15).
+    Returns (mask, d_sel, margin); each is None unless requested."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    m = _opt_out(mask, T, torch.uint8, V.device)
+    d = _opt_out(d_sel, T, torch.float64, V.device)
+    g = _opt_out(margin, T, torch.float64, V.device)
+    _check(_lib_update_H(_ptr(V), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
+                         _ptr(m), _ptr(d), _ptr(g), _stream()))
+    return m, d, g
+
+
+def update_W(V, W, H, *, mask=False, d_sel=False, margin=False, **kw):
+    """One DNA update of W in place (Algorithm 1 steps 17-28)."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    m = _opt_out(mask, N, torch.uint8, V.device)
+    d = _opt_out(d_sel, N, torch.float64, V.device)
+    g = _opt_out(margin, N, torch.float64, V.device)
+    _check(_lib_update_W(_ptr(V), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
+                         _ptr(m), _ptr(d), _ptr(g), _stream()))
+    return m, d, g
+
+
+def mu_update(side, V, W, H, with_cost=False, **kw):
+    """Plain MU update (eq. 11) of H (side 0) or W (side 1), in place.  With
+    cost: returns the per-column (row) cost of the input state."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    d = torch.empty(T if side == 0 else N, dtype=torch.float64, device=V.device) if with_cost else None
+    _check(_lib_mu(int(side), _ptr(V), _ptr(W), _ptr(H), N, T, R, 1 if with_cost else 0, _ptr(d),
+                   ctypes.byref(o), _ptr(ws), ws.numel(), _stream()))
+    return d
+
+
+def kl_cost(V, W, H, out=None, **kw):
+    """Eq. (1) at Z = W H; returns a 1-element float64 device tensor."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    out = torch.empty(1, dtype=torch.float64, device=V.device) if out is None else out
+    _check(_lib_kl(_ptr(V), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(), _ptr(out),
+                   _stream()))
+    return out
+
+
+def gradient_hessian(side, V, W, H, **kw):
+    """A (eq. 7) and B (eq. 14): R x T for side 0, N x R for side 1."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    shape = (R, T) if side == 0 else (N, R)
+    A = torch.empty(shape, dtype=torch.float32, device=V.device)
+    B = torch.empty(shape, dtype=torch.float32, device=V.device)
+    _check(_lib_gh(int(side), _ptr(V), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(A), _ptr(B),
+                   _ptr(ws), ws.numel(), _stream()))
+    return A, B
+
+
+def candidates(side, V, W, H, **kw):
+    """MU and renormalised Newton candidates (steps 6 and 11 / 19 and 24)."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    shape = (R, T) if side == 0 else (N, R)
+    Xmu = torch.empty(shape, dtype=torch.float32, device=V.device)
+    Xn = torch.empty(shape, dtype=torch.float32, device=V.device)
+    _check(_lib_cand(int(side), _ptr(V), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(Xmu), _ptr(Xn),
+                     _ptr(ws), ws.numel(), _stream()))
+    return Xmu, Xn
+
+
+def select(side, V, F, X_mu, X_newton, **kw):
+    """Costs of both candidates, selection, kept factor (steps 7-9, 12-15 / 20-28).
+    F is the fixed factor: W for side 0, H for side 1."""
+    _mat(V, "V")
+    N, T = V.shape
+    if side == 0:
+        R = F.shape[1]
+        _mat(F, "W", (N, R))
+        shape, L = (R, T), T
+    else:
+        R = F.shape[0]
+        _mat(F, "H", (R, T))
+        shape, L = (N, R), N
+    _mat(X_mu, "X_mu", shape)
+    _mat(X_newton, "X_newton", shape)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    out = torch.empty(shape, dtype=torch.float32, device=V.device)
+    m = torch.empty(L, dtype=torch.uint8, device=V.device)
+    d = torch.empty(L, dtype=torch.float64, device=V.device)
+    g = torch.empty(L, dtype=torch.float64, device=V.device)
+    _check(_lib_select(int(side), _ptr(V), _ptr(F), _ptr(X_mu), _ptr(X_newton), _ptr(out), N, T, R,
+                       ctypes.byref(o), _ptr(m), _ptr(d), _ptr(g), _ptr(ws), ws.numel(), _stream()))
+    return out, m, d, g
+
+
+# --------------------------------------------------------------------------- profiling
+
+def profile_enable(on=True):
+    _lib_prof_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib_prof_reset()
+
+
+def profile_read():
+    """{kernel name: (launches, total_ms)} since the last reset (synchronises)."""
+    n = _lib_prof_read(None, 0)
+    arr = (KernelStat * max(n, 1))()
+    n = _lib_prof_read(arr, n)
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n)}
+
+
+# --------------------------------------------------------------------------- drivers
+
+def dna_iteration(V, W, H, **kw):
+    """One full DNA iteration of Algorithm 1: H step, step 16, W step, step 29."""
+    update_H(V, W, H, **kw)
+    normalize(1, W, H, **kw)
+    update_W(V, W, H, **kw)
+    normalize(0, W, H, **kw)
+
+
+def mu_iteration(V, W, H, with_cost=False, **kw):
+    """One MU iteration (MU-labelled steps of Algorithm 1)."""
+    mu_update(0, V, W, H, with_cost=with_cost, **kw)
+    normalize(1, W, H, **kw)
+    mu_update(1, V, W, H, with_cost=with_cost, **kw)
+    normalize(0, W, H, **kw)
+
+
+def fit(V, W, H, iters, method="dna", record_kl=False, **kw):
+    """Algorithm 1 (method='dna') or MU (method='mu') for ``iters`` iterations,
+    in place, starting with step 1.  Returns the KL after each iteration as a
+    float64 device tensor when ``record_kl`` (index 0 = start)."""
+    normalize(0, W, H, **kw)
+    kls = torch.empty(iters + 1, dtype=torch.float64, device=V.device) if record_kl else None
+    if record_kl:
+        kl_cost(V, W, H, out=kls[0:1], **kw)
+    step = dna_iteration if method == "dna" else mu_iteration
+    for k in range(iters):
+        step(V, W, H, **kw)
+        if record_kl:
+            kl_cost(V, W, H, out=kls[k + 1:k + 2], **kw)
+    return kls

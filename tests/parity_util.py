@@ -1,0 +1,82 @@
+"""Shared helpers for the GPU parity tests (comparison norms, transfers, logging)."""
+import json
+import os
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LOG_DIR = os.path.join(ROOT, "gpurun_out")
+
+# Per-step tolerance in FP32 (from identical states): max-norm per column (row)
+# relative to the oracle's max-norm of that column (row).
+STEP_TOL = 1e-5
+# Trajectory tolerance: relative KL after every iteration.
+TRAJ_TOL = 1e-4
+# Selection from identical candidates (oracle re-scores the GPU's candidates in
+# float64): every column with |d_MU - d_DNA| / |d_MU| above this must agree.
+SELECT_TIE = 1e-12
+# Selection from an identical state (both sides form their own candidates, the
+# GPU in float32): decisions may differ only where the oracle's relative margin
+# is below this bound, which is the float32 resolution of the candidates
+# propagated to the cost (see the derivation in the design doc).
+STATE_TIE = 1e-5
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float32))).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_cols(got, ref, axis=0):
+    """max over columns (axis=0) or rows (axis=1) of ||got-ref||_inf / ||ref||_inf."""
+    got, ref = np.asarray(got, float), np.asarray(ref, float)
+    num = np.max(np.abs(got - ref), axis=axis)
+    den = np.max(np.abs(ref), axis=axis)
+    den = np.where(den > 0, den, 1.0)
+    return num / den
+
+
+def log_result(name, payload):
+    os.makedirs(LOG_DIR, exist_ok=True)
+    with open(os.path.join(LOG_DIR, "parity_log.jsonl"), "a") as f:
+        f.write(json.dumps({"test": name, **payload}) + "\n")
+
+
+# Two candidates whose reconstructions agree to this relative precision at every
+# data entry are the same point to float32 resolution: their costs tie whatever
+# their size (e.g. N = 1, where both reproduce v exactly, or R = 1).
+Z_TIE = 1e-6
+
+
+def recon_gap(Z_mu, Z_newton, axis):
+    """max over the data entries of a column (axis=0) / row (axis=1) of
+    |z_MU - z_DNA| / max(z_MU, z_DNA)."""
+    Z_mu, Z_newton = np.asarray(Z_mu, float), np.asarray(Z_newton, float)
+    den = np.maximum(np.maximum(np.abs(Z_mu), np.abs(Z_newton)), 1e-300)
+    return np.max(np.abs(Z_mu - Z_newton) / den, axis=axis)
+
+
+def selection_report(mask_gpu, mask_ref, margin_ref, d_mu_ref, tie, zgap=None):
+    """Flips between two selections, each with the oracle's relative margin.  A
+    flip is a tie (allowed) when |margin| <= tie * |d_MU| or, given ``zgap``, when
+    the two candidates reconstruct the same Z to within Z_TIE."""
+    mask_gpu = np.asarray(mask_gpu).astype(bool)
+    mask_ref = np.asarray(mask_ref).astype(bool)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rel = np.abs(margin_ref) / np.maximum(np.abs(d_mu_ref), 1e-300)
+    if zgap is None:
+        zgap = np.full(mask_ref.shape, np.inf)
+    flips = np.nonzero(mask_gpu != mask_ref)[0]
+    bad = [int(i) for i in flips if not (rel[i] <= tie or zgap[i] <= Z_TIE)]
+    return {
+        "n": int(mask_ref.size),
+        "newton_frac": float(mask_ref.mean()) if mask_ref.size else 0.0,
+        "flips": int(flips.size),
+        "flip_margins": [float(rel[i]) for i in flips[:20]],
+        "flips_above_tie": bad[:20],
+        "n_flips_above_tie": len(bad),
+    }
