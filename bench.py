@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-target", action="store_true", help="skip the time-to-target-KL runs")
     ap.add_argument("--mu-iters", type=int, default=1000, help="MU iterations that fix the target KL")
-    ap.add_argument("--dna-iters", type=int, default=200, help="DNA iteration budget for the target")
+    ap.add_argument("--dna-iters", type=int, default=1000, help="DNA iteration budget for the target")
     return ap.parse_args()
 
 

@@ -23,8 +23,9 @@ import torch
 from .dna_oracle import ALPHA, EPS, unrolled_h
 
 
-def h_update_torch(V, W, H, chose_newton, eps=EPS, alpha=ALPHA):
-    """One H-update as torch float64 ops, selection given by ``chose_newton``."""
+def h_update_torch(V, W, H, chose_newton, eps=EPS, alpha=ALPHA, value_floor=0.0):
+    """One H-update as torch float64 ops, selection given by ``chose_newton``.
+    ``value_floor`` as in dna_oracle.h_step (clamped entries carry no gradient)."""
     c = W.sum(dim=0)
     Z = W @ H
     Q = V / Z
@@ -46,30 +47,33 @@ def h_update_torch(V, W, H, chose_newton, eps=EPS, alpha=ALPHA):
     s = V.sum(dim=0)
     den = (c[:, None] * Hn).sum(dim=0)                  # eq. (10) denominator
     Hn = Hn * (s / den)[None, :]
+    if value_floor > 0:
+        Hn = torch.clamp(Hn, min=value_floor)
+        H_mu = torch.clamp(H_mu, min=value_floor)
     sel = torch.as_tensor(np.asarray(chose_newton, dtype=bool))[None, :]
     return torch.where(sel, Hn, H_mu)
 
 
-def unrolled_loss(V, W, H_init, H0, K, masks, eps=EPS, alpha=ALPHA):
+def unrolled_loss(V, W, H_init, H0, K, masks, eps=EPS, alpha=ALPHA, value_floor=0.0):
     """L = ||H_K - H0||^2 over K frozen-selection updates, as a torch graph."""
     H = H_init
     for k in range(K):
-        H = h_update_torch(V, W, H, masks[k], eps, alpha)
+        H = h_update_torch(V, W, H, masks[k], eps, alpha, value_floor)
     return ((H - H0) ** 2).sum(), H
 
 
-def unrolled_h_grad(V, W, H_init, H0, K, masks=None, eps=EPS, alpha=ALPHA):
+def unrolled_h_grad(V, W, H_init, H0, K, masks=None, eps=EPS, alpha=ALPHA, value_floor=0.0):
     """Loss and gradients (dL/dW, dL/dV, dL/dH_init) of L = ||H_K - H0||^2.
 
     ``masks`` (K boolean arrays of length T) freeze the selections; by default
     they come from the NumPy oracle's forward pass from the same inputs.
     Returns (L, H_K, dW, dV, dH_init) as float64 NumPy arrays."""
     if masks is None:
-        _, masks = unrolled_h(V, W, H_init, K, eps, alpha)
+        _, masks = unrolled_h(V, W, H_init, K, eps, alpha, value_floor)
     t = lambda x: torch.tensor(np.asarray(x, dtype=np.float64), requires_grad=True)
     Vt, Wt, Ht = t(V), t(W), t(H_init)
     H0t = torch.tensor(np.asarray(H0, dtype=np.float64))
-    L, HK = unrolled_loss(Vt, Wt, Ht, H0t, K, masks, eps, alpha)
+    L, HK = unrolled_loss(Vt, Wt, Ht, H0t, K, masks, eps, alpha, value_floor)
     L.backward()
-    return (float(L), HK.detach().numpy(), Wt.grad.numpy(), Vt.grad.numpy(),
-            Ht.grad.numpy())
+    g = lambda x: x.grad.numpy() if x.grad is not None else np.zeros(tuple(x.shape))
+    return float(L), HK.detach().numpy(), g(Wt), g(Vt), g(Ht)

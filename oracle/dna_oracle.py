@@ -21,6 +21,13 @@ Readings of the paper that this oracle fixes (each is stated where it is used):
 * Zeros of V contribute nothing to Q, Q-bar or the costs (end of Sec. 3).
 * Selection: Newton iff d_DNA < d_MU (step 15: ties go to MU).
 * Renormalisation eq. (10) with a zero denominator leaves the column at 0.
+* ``value_floor`` (default 0: the paper's method on the positive reals): when
+  positive, both candidates are raised to at least this value after the
+  renormalisation.  In exact arithmetic no update maps a positive entry to 0
+  (the floor eps bounds the shrink per step), but a floating-point format
+  underflows an entry that keeps shrinking, and 0 is a fixed point of every
+  update; passing the smallest positive normal number of the storage format
+  (float32: 2**-126) keeps the run on the positive reals that format can hold.
 
 Functions with no independent pin are marked "parity unpinned" in their
 docstring; at present there are none (the pins live in tests/).
@@ -160,7 +167,7 @@ def _select(d_mu, d_nr, X_mu, X_nr, axis):
     return choose, X, d_sel, margin
 
 
-def h_step(V, W, H, eps=EPS, alpha=ALPHA):
+def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0):
     """One DNA update of H with W fixed: Algorithm 1 steps 4-15 (Sec. 2-3).
 
     c = W^t 1; Z = W H; Q, Q-bar (steps 2-3, 10); A = W^t Q / c - 1 (eq. 7,
@@ -176,15 +183,16 @@ def h_step(V, W, H, eps=EPS, alpha=ALPHA):
     Q, Qb = ratios(V, W @ H)
     A = (W.T @ Q) / c[:, None] - 1.0
     B = ((W * W).T @ Qb) / c[:, None]
-    H_mu = H * (1.0 + A)
-    H_nr = renormalize(newton_candidate(H, A, B, eps, alpha), c, V.sum(axis=0), axis=0)
+    H_mu = np.maximum(H * (1.0 + A), value_floor)
+    H_nr = np.maximum(renormalize(newton_candidate(H, A, B, eps, alpha), c, V.sum(axis=0), axis=0),
+                      value_floor)
     d_mu = partial_cost(V, W @ H_mu, axis=0)
     d_nr = partial_cost(V, W @ H_nr, axis=0)
     choose, X, d_sel, margin = _select(d_mu, d_nr, H_mu, H_nr, axis=0)
     return StepResult(X, choose, d_sel, d_mu, d_nr, margin, A, B, H_mu, H_nr)
 
 
-def w_step(V, W, H, eps=EPS, alpha=ALPHA):
+def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0):
     """One DNA update of W with H fixed: Algorithm 1 steps 17-28.
 
     The mirror of ``h_step`` written out directly: g = H 1; A = Q H^t / g - 1
@@ -200,15 +208,16 @@ def w_step(V, W, H, eps=EPS, alpha=ALPHA):
     Q, Qb = ratios(V, W @ H)
     A = (Q @ H.T) / g[None, :] - 1.0
     B = (Qb @ (H * H).T) / g[None, :]
-    W_mu = W * (1.0 + A)
-    W_nr = renormalize(newton_candidate(W, A, B, eps, alpha), g, V.sum(axis=1), axis=1)
+    W_mu = np.maximum(W * (1.0 + A), value_floor)
+    W_nr = np.maximum(renormalize(newton_candidate(W, A, B, eps, alpha), g, V.sum(axis=1), axis=1),
+                      value_floor)
     d_mu = partial_cost(V, W_mu @ H, axis=1)
     d_nr = partial_cost(V, W_nr @ H, axis=1)
     choose, X, d_sel, margin = _select(d_mu, d_nr, W_mu, W_nr, axis=1)
     return StepResult(X, choose, d_sel, d_mu, d_nr, margin, A, B, W_mu, W_nr)
 
 
-def mu_h_step(V, W, H):
+def mu_h_step(V, W, H, value_floor=0.0):
     """Plain MU update of H (eq. 11 at lambda = 0; Lee-Seung):
     H <- H * (W^t Q) / (W^t 1).  Also returns the per-column partial cost
     sum_{v>0} v log(v/z) of the INPUT state (the cost that "MU with cost"
@@ -219,10 +228,10 @@ def mu_h_step(V, W, H):
         raise DomainError("a column of W sums to zero")
     Z = W @ H
     Q, _ = ratios(V, Z)
-    return H * (W.T @ Q) / c[:, None], partial_cost(V, Z, axis=0)
+    return np.maximum(H * (W.T @ Q) / c[:, None], value_floor), partial_cost(V, Z, axis=0)
 
 
-def mu_w_step(V, W, H):
+def mu_w_step(V, W, H, value_floor=0.0):
     """Plain MU update of W: W <- W * (Q H^t) / (H 1); per-row input cost."""
     V, W, H = _f64(V), _f64(W), _f64(H)
     g = H.sum(axis=1)
@@ -230,7 +239,7 @@ def mu_w_step(V, W, H):
         raise DomainError("a row of H sums to zero")
     Z = W @ H
     Q, _ = ratios(V, Z)
-    return W * (Q @ H.T) / g[None, :], partial_cost(V, Z, axis=1)
+    return np.maximum(W * (Q @ H.T) / g[None, :], value_floor), partial_cost(V, Z, axis=1)
 
 
 # ---------------------------------------------------------------------------
@@ -266,7 +275,7 @@ class FitResult:
     newton_frac_w: list       # fraction of rows taking Newton, per iteration
 
 
-def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA):
+def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA, value_floor=0.0):
     """Algorithm 1: step 1, then per iteration H half-step (4-15), step 16,
     W half-step (17-28), step 29.  Z and Q are recomputed from W H at the start
     of each half-step, which equals carrying them because the normalisations
@@ -276,11 +285,11 @@ def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA):
     kl = [kl_cost(V, W, H)]
     fh, fw = [], []
     for _ in range(iters):
-        r = h_step(V, W, H, eps, alpha)
+        r = h_step(V, W, H, eps, alpha, value_floor)
         H = r.X
         fh.append(float(r.chose_newton.mean()))
         W, H = normalize_h_rows(W, H)
-        r = w_step(V, W, H, eps, alpha)
+        r = w_step(V, W, H, eps, alpha, value_floor)
         W = r.X
         fw.append(float(r.chose_newton.mean()))
         W, H = normalize_w_columns(W, H)
@@ -288,7 +297,7 @@ def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA):
     return FitResult(W, H, kl, fh, fw)
 
 
-def fit_mu(V, W, H, iters, normalize=True):
+def fit_mu(V, W, H, iters, normalize=True, value_floor=0.0):
     """MU reference: Algorithm 1 with only the MU-labelled steps.  With
     ``normalize=False`` it is textbook Lee-Seung MU without steps 1/16/29."""
     V = _f64(V)
@@ -297,17 +306,17 @@ def fit_mu(V, W, H, iters, normalize=True):
         W, H = normalize_w_columns(W, H)
     kl = [kl_cost(V, W, H)]
     for _ in range(iters):
-        H, _ = mu_h_step(V, W, H)
+        H, _ = mu_h_step(V, W, H, value_floor)
         if normalize:
             W, H = normalize_h_rows(W, H)
-        W, _ = mu_w_step(V, W, H)
+        W, _ = mu_w_step(V, W, H, value_floor)
         if normalize:
             W, H = normalize_w_columns(W, H)
         kl.append(kl_cost(V, W, H))
     return FitResult(W, H, kl, [], [])
 
 
-def unrolled_h(V, W, H_init, K, eps=EPS, alpha=ALPHA):
+def unrolled_h(V, W, H_init, K, eps=EPS, alpha=ALPHA, value_floor=0.0):
     """K DNA H-updates with W fixed (no normalisation between them).
 
     Returns the list [H_0 .. H_K] and the K selection masks.  This is the
@@ -315,7 +324,7 @@ def unrolled_h(V, W, H_init, K, eps=EPS, alpha=ALPHA):
     Hs = [_f64(H_init)]
     masks = []
     for _ in range(K):
-        r = h_step(V, W, Hs[-1], eps, alpha)
+        r = h_step(V, W, Hs[-1], eps, alpha, value_floor)
         Hs.append(r.X)
         masks.append(r.chose_newton)
     return Hs, masks

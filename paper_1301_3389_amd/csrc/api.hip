@@ -13,6 +13,7 @@
 
 #include "../../include/dna.h"
 #include "kernels.hpp"
+#include "kernels_adj.hpp"
 
 namespace dna {
 
@@ -95,8 +96,9 @@ static Split choose_split(int64_t K, int64_t base_tiles) {
 
 struct Layout {
   Split sh, sw;
-  int tiles_m, tiles_n;      // row tiles (N / ZT_BM), column tiles (T / ZT_BN)
-  size_t q, qb, pu, py, xmu, xn, c32, c64, vpart, cpart, fpart, check, total;
+  int rt_m, rt_n;            // ratio-pass tiles along N and along T
+  int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
+  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, vpart, cpart, fpart, check, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -105,28 +107,64 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R) {
   Layout L;
   L.sh = choose_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM));
   L.sw = choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM));
-  L.tiles_m = (int)cdiv(N, ZT_BM);
-  L.tiles_n = (int)cdiv(T, ZT_BN);
+  L.rt_m = (int)cdiv(N, RT_BM);
+  L.rt_n = (int)cdiv(T, RT_BN);
+  L.ch_m = (int)cdiv(N, CH_BM);
+  L.cw_n = (int)cdiv(T, CW_BN);
   const size_t nt = (size_t)N * T, fac = (size_t)std::max(R * T, N * R);
   const size_t psplit = (size_t)std::max<int64_t>((int64_t)L.sh.splits * R * T, (int64_t)L.sw.splits * N * R);
-  const size_t red = (size_t)std::max<int64_t>((int64_t)L.tiles_m * T, (int64_t)L.tiles_n * N);
-  const size_t klt = (size_t)L.tiles_m * L.tiles_n;
+  const size_t red = (size_t)std::max(std::max<int64_t>((int64_t)L.rt_m * T, (int64_t)L.rt_n * N),
+                                      std::max<int64_t>((int64_t)L.ch_m * T, (int64_t)L.cw_n * N));
+  const size_t klt = (size_t)L.rt_m * L.rt_n;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   L.q = take(nt * 4);
   L.qb = take(nt * 4);
   L.pu = take(psplit * 4);
+  L.puc = take(psplit * 4);
   L.py = take(psplit * 4);
   L.xmu = take(fac * 4);
   L.xn = take(fac * 4);
   L.c32 = take((size_t)R * 4);
   L.c64 = take((size_t)R * 8);
+  L.sump = take((size_t)SUM_PARTS * R * 8);
   L.vpart = take(red * 8);
   L.cpart = take(std::max(3 * red, klt) * 8);
   L.fpart = take(red * 4);
   L.check = take(16);
   L.total = off;
   return L;
+}
+
+// The adjoint needs the forward layout plus Z, Z-bar, the per-entry adjoint
+// quantities, two ping-pong H-gradients and the W-gradient split partials.
+struct AdjLayout {
+  Layout base;
+  Split swb;
+  size_t z, zbar, ubar, ybar, hd, cbar, g0, g1, sbar, cbar64, wp0, wp1, total;
+};
+
+static AdjLayout make_adj_layout(int64_t N, int64_t T, int64_t R) {
+  AdjLayout A;
+  A.base = make_layout(N, T, R);
+  A.swb = choose_split(T, cdiv(R, WB_BN) * cdiv(N, WB_BM));
+  size_t off = A.base.total;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  const size_t nt = (size_t)N * T, rt = (size_t)R * T, nr = (size_t)N * R;
+  A.z = take(nt * 4);
+  A.zbar = take(nt * 4);
+  A.ubar = take(rt * 4);
+  A.ybar = take(rt * 4);
+  A.hd = take(rt * 4);
+  A.cbar = take(rt * 4);
+  A.g0 = take(rt * 4);
+  A.g1 = take(rt * 4);
+  A.sbar = take((size_t)T * 4);
+  A.cbar64 = take((size_t)R * 8);
+  A.wp0 = take((size_t)A.swb.splits * nr * 4);
+  A.wp1 = take((size_t)A.swb.splits * nr * 4);
+  A.total = off;
+  return A;
 }
 
 template <class T>
@@ -148,7 +186,7 @@ static dna_status check_opts(const dna_opts* o) {
 
 static dna_status check_dims(int64_t N, int64_t T, int64_t R) {
   if (N <= 0 || T <= 0 || R <= 0) return fail(DNA_EINVAL, "N, T and R must be positive");
-  if (cdiv(N, ZT_BM) > 65535 || cdiv(R, GH_BM) > 65535)
+  if (cdiv(N, CW_BM) > 65535 || cdiv(R, GH_BM) > 65535)
     return fail(DNA_EUNSUPPORTED, "N or R exceeds the launch grid limit");
   if ((double)N * (double)T > 4.0e9 || (double)N * (double)R > 4.0e9 || (double)R * (double)T > 4.0e9)
     return fail(DNA_EUNSUPPORTED, "matrix too large (more than 4e9 entries)");
@@ -203,22 +241,23 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
   float* Q = at<float>(ws, L.q);
   float* Qb = at<float>(ws, L.qb);
   float* pu = at<float>(ws, L.pu);
+  float* puc = at<float>(ws, L.puc);
   float* py = at<float>(ws, L.py);
   float* c32 = at<float>(ws, L.c32);
   double* c64 = at<double>(ws, L.c64);
   double* vpart = at<double>(ws, L.vpart);
-  RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk};
+  RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk, nullptr};
   if (side == 0) {
-    DNA_HIP(launch_colsum_W(W, N, R, c64, c32, chk, s), "colsum_W");
+    DNA_HIP(launch_colsum_W(W, N, R, at<double>(ws, L.sump), c64, c32, chk, s), "colsum_W");
     DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
-    DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, py, s), "gh_H");
-    DNA_HIP(launch_cand_H(H, pu, py, L.sh.splits, c32, vpart, L.tiles_m, T, R, o->eps, o->alpha, Xmu, Xn,
+    DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
+    DNA_HIP(launch_cand_H(H, pu, puc, py, L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps, o->alpha, Xmu, Xn,
                           Aout, Bout, s), "cand_H");
   } else {
-    DNA_HIP(launch_rowsum_H(H, T, R, c64, c32, chk, s), "rowsum_H");
+    DNA_HIP(launch_rowsum_H(H, T, R, at<double>(ws, L.sump), c64, c32, chk, s), "rowsum_H");
     DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
-    DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, py, s), "gh_W");
-    DNA_HIP(launch_cand_W(W, pu, py, L.sw.splits, c32, vpart, L.tiles_n, N, R, o->eps, o->alpha, Xmu, Xn,
+    DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc, py, s), "gh_W");
+    DNA_HIP(launch_cand_W(W, pu, puc, py, L.sw.splits, c32, vpart, L.rt_n, N, R, o->eps, o->alpha, Xmu, Xn,
                           Aout, Bout, s), "cand_W");
   }
   return DNA_OK;
@@ -231,10 +270,10 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
   int* fpart = at<int>(ws, L.fpart);
   if (side == 0) {
     DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_H");
-    DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.tiles_m, T, R, mask, dsel, margin, s), "select_H");
+    DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.ch_m, T, R, mask, dsel, margin, s), "select_H");
   } else {
     DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_W");
-    DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, L.tiles_n, N, R, mask, dsel, margin, s), "select_W");
+    DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, L.cw_n, N, R, mask, dsel, margin, s), "select_W");
   }
   return DNA_OK;
 }
@@ -296,8 +335,9 @@ dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int
   Common c;
   DNA_TRY(prologue(nullptr, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* f = at<double>(ws, c.L.c64);
-  if (side == 0) DNA_HIP(launch_colsum_W(W, N, R, f, nullptr, c.chk, c.s), "colsum_W");
-  else DNA_HIP(launch_rowsum_H(H, T, R, f, nullptr, c.chk, c.s), "rowsum_H");
+  double* sp = at<double>(ws, c.L.sump);
+  if (side == 0) DNA_HIP(launch_colsum_W(W, N, R, sp, f, nullptr, c.chk, c.s), "colsum_W");
+  else DNA_HIP(launch_rowsum_H(H, T, R, sp, f, nullptr, c.chk, c.s), "rowsum_H");
   DNA_HIP(launch_scale(side, W, H, N, T, R, f, c.s), "scale");
   return epilogue(c);
 }
@@ -340,17 +380,17 @@ dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, in
   float* pu = at<float>(ws, L.pu);
   float* c32 = at<float>(ws, L.c32);
   double* cpart = at<double>(ws, L.cpart);
-  RatioArgs ra{V, W, H, N, T, R, Q, nullptr, nullptr, cpart, c.chk};
+  RatioArgs ra{V, W, H, N, T, R, Q, nullptr, nullptr, cpart, c.chk, nullptr};
   if (side == 0) {
-    DNA_HIP(launch_colsum_W(W, N, R, nullptr, c32, c.chk, c.s), "colsum_W");
+    DNA_HIP(launch_colsum_W(W, N, R, at<double>(ws, L.sump), nullptr, c32, c.chk, c.s), "colsum_W");
     DNA_HIP(launch_ratio(with_cost ? RM_MU_H_COST : RM_MU_H, ra, c.s), "ratio_mu_H");
-    DNA_HIP(launch_gh_H(W, Q, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, pu, c.s), "gh_mu_H");
-    DNA_HIP(launch_mu_H(H, pu, L.sh.splits, c32, T, R, cpart, L.tiles_m, with_cost ? d_out : nullptr, c.s), "mu_H");
+    DNA_HIP(launch_gh_H(W, Q, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_H");
+    DNA_HIP(launch_mu_H(H, pu, L.sh.splits, c32, T, R, cpart, L.rt_m, with_cost ? d_out : nullptr, c.s), "mu_H");
   } else {
-    DNA_HIP(launch_rowsum_H(H, T, R, nullptr, c32, c.chk, c.s), "rowsum_H");
+    DNA_HIP(launch_rowsum_H(H, T, R, at<double>(ws, L.sump), nullptr, c32, c.chk, c.s), "rowsum_H");
     DNA_HIP(launch_ratio(with_cost ? RM_MU_W_COST : RM_MU_W, ra, c.s), "ratio_mu_W");
-    DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, pu, c.s), "gh_mu_W");
-    DNA_HIP(launch_mu_W(W, pu, L.sw.splits, c32, N, R, cpart, L.tiles_n, with_cost ? d_out : nullptr, c.s), "mu_W");
+    DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_W");
+    DNA_HIP(launch_mu_W(W, pu, L.sw.splits, c32, N, R, cpart, L.rt_n, with_cost ? d_out : nullptr, c.s), "mu_W");
   }
   return epilogue(c);
 }
@@ -361,9 +401,9 @@ dna_status kl_cost(const float* V, const float* W, const float* H, int64_t N, in
   Common c;
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* cpart = at<double>(ws, c.L.cpart);
-  RatioArgs ra{V, W, H, N, T, R, nullptr, nullptr, nullptr, cpart, c.chk};
+  RatioArgs ra{V, W, H, N, T, R, nullptr, nullptr, nullptr, cpart, c.chk, nullptr};
   DNA_HIP(launch_ratio(RM_KL, ra, c.s), "kl_terms");
-  DNA_HIP(launch_kl_final(cpart, c.L.tiles_m * c.L.tiles_n, out, c.s), "kl_final");
+  DNA_HIP(launch_kl_final(cpart, c.L.rt_m * c.L.rt_n, out, c.s), "kl_final");
   return epilogue(c);
 }
 
@@ -408,18 +448,99 @@ dna_status dna_select(int side, const float* V, const float* F, const float* X_m
 }
 
 size_t dna_unrolled_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* o) {
-  (void)N; (void)T; (void)R; (void)o;
-  return 0;
+  (void)o;
+  if (N <= 0 || T <= 0 || R <= 0) return 0;
+  return make_adj_layout(N, T, R).total;
 }
 
-dna_status dna_unrolled_H_fwd(const float*, const float*, const float*, int, int64_t, int64_t, int64_t,
-                              const dna_opts*, float*, uint8_t*, void*, size_t, void*) {
-  return fail(DNA_EUNSUPPORTED, "unrolled adjoint not built yet");
+dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_init, int K, int64_t N, int64_t T,
+                              int64_t R, const dna_opts* o, float* H_ckpt, uint8_t* sel_ckpt, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (!V || !W || !H_init || !H_ckpt || (K > 0 && !sel_ckpt)) return fail(DNA_EINVAL, "NULL argument");
+  if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
+  DNA_TRY(check_dims(N, T, R));
+  DNA_TRY(check_opts(o));
+  const AdjLayout A = make_adj_layout(N, T, R);
+  DNA_TRY(check_ws(ws, ws_bytes, A.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int* chk = o->checked ? at<int>(ws, A.base.check) : nullptr;
+  if (chk) {
+    const float* bufs[3] = {W, H_init, V};
+    const int64_t sizes[3] = {N * R, R * T, N * T};
+    DNA_TRY(checked_begin(chk, bufs, sizes, 3, s));
+  }
+  const int64_t RT = R * T;
+  DNA_HIP(launch_copy(H_init, H_ckpt, RT, s), "copy");
+  float* Xmu = at<float>(ws, A.base.xmu);
+  float* Xn = at<float>(ws, A.base.xn);
+  for (int k = 0; k < K; ++k) {
+    const float* Hk = H_ckpt + (int64_t)k * RT;
+    float* Hk1 = H_ckpt + (int64_t)(k + 1) * RT;
+    DNA_TRY(run_candidates(0, V, W, Hk, N, T, R, o, A.base, ws, Xmu, Xn, nullptr, nullptr, chk, s));
+    DNA_TRY(run_select(0, V, W, Xmu, Xn, Hk1, N, T, R, A.base, ws, sel_ckpt + (int64_t)k * T, nullptr, nullptr, s));
+  }
+  if (chk) return checked_end(chk, s);
+  return DNA_OK;
 }
 
-dna_status dna_unrolled_H_bwd(const float*, const float*, const float*, const uint8_t*, int, int64_t, int64_t,
-                              int64_t, const float*, float*, float*, float*, const dna_opts*, void*, size_t, void*) {
-  return fail(DNA_EUNSUPPORTED, "unrolled adjoint not built yet");
+dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckpt, const uint8_t* sel_ckpt, int K,
+                              int64_t N, int64_t T, int64_t R, const float* dH_K, float* dW, float* dV,
+                              float* dH_init, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!V || !W || !H_ckpt || !dH_K || !dW || !dV || (K > 0 && !sel_ckpt)) return fail(DNA_EINVAL, "NULL argument");
+  if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
+  DNA_TRY(check_dims(N, T, R));
+  DNA_TRY(check_opts(o));
+  const AdjLayout A = make_adj_layout(N, T, R);
+  DNA_TRY(check_ws(ws, ws_bytes, A.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = A.base;
+  const int64_t RT = R * T;
+  if (K == 0) {
+    DNA_HIP(launch_fill(dW, 0.f, N * R, s), "fill");
+    DNA_HIP(launch_fill(dV, 0.f, N * T, s), "fill");
+    if (dH_init) DNA_HIP(launch_copy(dH_K, dH_init, RT, s), "copy");
+    return DNA_OK;
+  }
+  float* Q = at<float>(ws, L.q);
+  float* Qb = at<float>(ws, L.qb);
+  float* pu = at<float>(ws, L.pu);
+  float* puc = at<float>(ws, L.puc);
+  float* py = at<float>(ws, L.py);
+  float* c32 = at<float>(ws, L.c32);
+  double* vpart = at<double>(ws, L.vpart);
+  float* Z = at<float>(ws, A.z);
+  float* Zbar = at<float>(ws, A.zbar);
+  float* Ub = at<float>(ws, A.ubar);
+  float* Yb = at<float>(ws, A.ybar);
+  float* Hd = at<float>(ws, A.hd);
+  float* Cb = at<float>(ws, A.cbar);
+  float* G[2] = {at<float>(ws, A.g0), at<float>(ws, A.g1)};
+  float* sbar = at<float>(ws, A.sbar);
+  double* cbar64 = at<double>(ws, A.cbar64);
+  float* p0 = at<float>(ws, A.wp0);
+  float* p1 = at<float>(ws, A.wp1);
+  DNA_HIP(launch_colsum_W(W, N, R, at<double>(ws, L.sump), nullptr, c32, nullptr, s), "colsum_W");
+  const float* Gin = dH_K;
+  for (int k = K - 1; k >= 0; --k) {
+    const float* Hk = H_ckpt + (int64_t)k * RT;
+    const int acc = k != K - 1;
+    float* Gout = (k == 0) ? dH_init : G[k & 1];
+    RatioArgs ra{V, W, Hk, N, T, R, Q, Qb, vpart, nullptr, nullptr, Z};
+    DNA_HIP(launch_ratio(RM_ADJ, ra, s), "ratio_adj");
+    DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
+    DNA_HIP(launch_cand_bwd_H(Hk, pu, puc, py, L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps, o->alpha,
+                              sel_ckpt + (int64_t)k * T, Gin, Ub, Yb, Hd, Cb, sbar, s), "cand_bwd_H");
+    DNA_HIP(launch_zbar(V, Z, W, Ub, Yb, sbar, N, T, R, Zbar, dV, acc, s), "zbar");
+    DNA_HIP(launch_rowsum_H(Cb, T, R, at<double>(ws, L.sump), cbar64, nullptr, nullptr, s), "rowsum cbar");
+    DNA_HIP(launch_wbar(Q, Zbar, Qb, Ub, Hk, Yb, N, T, R, A.swb.splits, A.swb.kchunk, p0, p1, s), "wbar");
+    DNA_HIP(launch_dw_final(W, p0, p1, A.swb.splits, cbar64, N, R, dW, acc, s), "dw_final");
+    if (Gout) {
+      DNA_HIP(launch_gh_H(W, Zbar, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, s), "gh_zbar");
+      DNA_HIP(launch_dh_final(Hd, pu, L.sh.splits, R, T, Gout, s), "dh_final");
+    }
+    Gin = Gout;
+  }
+  return DNA_OK;
 }
 
 const char* dna_status_string(dna_status s) {

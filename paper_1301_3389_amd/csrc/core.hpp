@@ -216,6 +216,25 @@ struct Tile {
     }
   }
 
+  // Load X[row][col] (row-major, leading dimension ld) at this lane's accumulator
+  // positions.  Indices are clamped into the matrix so that every load is issued
+  // unconditionally (and early, before the K loop); callers ignore the clamped
+  // entries.
+  __device__ __forceinline__ static void load_frag(float (&out)[G::FM][G::FN][16], const float* X, int64_t ld,
+                                                   int64_t m0, int64_t n0, int64_t M, int64_t Ncols) {
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int64_t col = min(col_of(n0, j), Ncols - 1);
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = min(row_of(m0, i, v), M - 1);
+          out[i][j][v] = X[row * ld + col];
+        }
+    }
+  }
+
   // Global (row, col) of accumulator element (i, j, v) for this thread.
   __device__ __forceinline__ static int64_t row_of(int64_t m0, int i, int v) {
     const int tid = threadIdx.x, lane = tid & 63, wm = (tid >> 6) % G::WGM;
@@ -249,6 +268,28 @@ struct ProdDualA_SqB {  // C0 += A0 B, C1 += A1 (B*B)   (Q H^t and Q-bar (H*H)^t
     c[1] = mfma32(a[1], b[0] * b[0], c[1]);
   }
 };
+// Gradient / Hessian numerators with both forms of the gradient sum:
+//   C0 += w q          (u,  relative accuracy of the MU gain u/c)
+//   C1 += w (q - 1)    (u_c = u - c, absolute accuracy of A = u_c/c near 0)
+//   C2 += w^2 q-bar    (y)
+// Zero-filled padding contributes nothing: w = 0 there.
+struct ProdGH3_H {  // A = W^t (shared), B0 = Q, B1 = Q-bar
+  static constexpr int NA = 1, NB = 2, NC = 3;
+  __device__ __forceinline__ static void mma(const float (&a)[1], const float (&b)[2], f32x16 (&c)[3]) {
+    c[0] = mfma32(a[0], b[0], c[0]);
+    c[1] = mfma32(a[0], b[0] - 1.f, c[1]);
+    c[2] = mfma32(a[0] * a[0], b[1], c[2]);
+  }
+};
+struct ProdGH3_W {  // A0 = Q, A1 = Q-bar, B = H^t (shared)
+  static constexpr int NA = 2, NB = 1, NC = 3;
+  __device__ __forceinline__ static void mma(const float (&a)[2], const float (&b)[1], f32x16 (&c)[3]) {
+    c[0] = mfma32(a[0], b[0], c[0]);
+    c[1] = mfma32(a[0] - 1.f, b[0], c[1]);
+    c[2] = mfma32(a[1], b[0] * b[0], c[2]);
+  }
+};
+
 struct ProdDualB {  // C0 += A B0, C1 += A B1
   static constexpr int NA = 1, NB = 2, NC = 2;
   __device__ __forceinline__ static void mma(const float (&a)[1], const float (&b)[2], f32x16 (&c)[2]) {

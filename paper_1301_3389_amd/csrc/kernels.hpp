@@ -14,8 +14,14 @@ void prof_end(const char* name, hipStream_t s);
 enum CheckBits { CHK_DOMAIN = 1, CHK_NONFINITE = 2 };
 
 // Tile sizes the host uses to size partial-sum buffers.
-constexpr int ZT_BM = 128;   // rows (n) per tile of the Z = W H products
-constexpr int ZT_BN = 128;   // columns (t) per tile of the Z = W H products
+constexpr int ZT_BM = 128;   // rows (n) per tile of the adjoint Z-type products
+constexpr int ZT_BN = 128;   // columns (t) per tile of the adjoint Z-type products
+constexpr int RT_BM = 128;   // ratio pass (Z = W H + Q / Q-bar epilogue): rows (n) per tile
+constexpr int RT_BN = 64;    //                                            columns (t) per tile
+constexpr int CH_BM = 128;   // H-orientation cost pass: rows (n) per tile (column partials)
+constexpr int CH_BN = 64;
+constexpr int CW_BM = 64;    // W-orientation cost pass: rows (n) per tile
+constexpr int CW_BN = 128;   //                          columns (t) per tile (row partials)
 constexpr int GH_BM = 64;    // H orientation gradient GEMM: rows (r) per tile
 constexpr int GH_BN = 128;   //                              columns (t) per tile
 constexpr int GW_BM = 128;   // W orientation gradient GEMM: rows (n) per tile
@@ -23,6 +29,13 @@ constexpr int GW_BN = 64;    //                              columns (r) per til
 constexpr int GEMM_BK = 16;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Every updated factor entry is kept at or above the smallest positive normal
+// float32 (2^-126).  In exact arithmetic no update sends a positive entry to 0
+// (the eps floor bounds the shrink per step), but float32 underflows an entry
+// that keeps shrinking and 0 is a fixed point of every update; the floor keeps
+// such entries able to grow back.
+constexpr float VALUE_FLOOR = 1.17549435e-38f;
 
 // What the ratio pass (Z = W H and its epilogue) produces.
 enum RatioMode {
@@ -32,7 +45,8 @@ enum RatioMode {
   RM_MU_H_COST = 3,// Q, per-column cost of the input
   RM_MU_W = 4,     // Q only                              (MU W step)
   RM_MU_W_COST = 5,// Q, per-row cost of the input
-  RM_KL = 6        // per-tile sums of the eq. (1) terms only
+  RM_KL = 6,       // per-tile sums of the eq. (1) terms only
+  RM_ADJ = 7       // Q, Q-bar, Z and column sums of V      (adjoint recompute)
 };
 
 struct RatioArgs {
@@ -42,25 +56,28 @@ struct RatioArgs {
   double* vpart;      // [tiles_m][T] (column sums) or [tiles_n][N] (row sums)
   double* cpart;      // cost partials, same layouts; RM_KL: [tiles]
   int* check;         // nullptr unless checked
+  float* Z;           // RM_ADJ only: Z = W H
 };
 hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s);
 
 // Gradient / Hessian numerators, split over the contraction index.
 //   H orientation: pu[sp][r][t] = sum_{n in split} w_nr q_nt, py with w^2, q-bar
 //   W orientation: pu[sp][n][r] = sum_{t in split} q_nt h_rt, py with q-bar, h^2
+// With Qb == nullptr only pu is written (MU).  u_c = u - c is accumulated from
+// (q - 1) directly; see the candidate kernels for which form is used where.
 hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t N, int64_t T,
-                       int64_t R, int splits, int64_t kchunk, float* pu, float* py,
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s);
 hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t N, int64_t T,
-                       int64_t R, int splits, int64_t kchunk, float* pu, float* py,
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s);
 
 // Candidates (MU and renormalised Newton) from the split partials.
-hipError_t launch_cand_H(const float* H, const float* pu, const float* py, int splits,
+hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
                          const float* c, const double* vpart, int tiles_m, int64_t T, int64_t R,
                          float eps, float alpha, float* Xmu, float* Xn, float* Aout, float* Bout,
                          hipStream_t s);
-hipError_t launch_cand_W(const float* W, const float* pu, const float* py, int splits,
+hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits,
                          const float* g, const double* vpart, int tiles_n, int64_t N, int64_t R,
                          float eps, float alpha, float* Xmu, float* Xn, float* Aout, float* Bout,
                          hipStream_t s);
@@ -86,10 +103,12 @@ hipError_t launch_mu_H(float* H, const float* pu, int splits, const float* c, in
 hipError_t launch_mu_W(float* W, const float* pu, int splits, const float* g, int64_t N, int64_t R,
                        const double* cpart, int tiles_n, double* d_out, hipStream_t s);
 
-// Column sums of W (R values) / row sums of H (R values), float64 and float32.
-hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* sum64, float* sum32,
+// Column sums of W (R values) / row sums of H (R values), float64 and float32,
+// in two fixed-order levels through `part` (at most SUM_PARTS * R doubles).
+constexpr int SUM_PARTS = 256;
+hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* part, double* sum64, float* sum32,
                            int* check, hipStream_t s);
-hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* sum64, float* sum32,
+hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* part, double* sum64, float* sum32,
                            int* check, hipStream_t s);
 // side 0: W[:,r] /= f_r, H[r,:] *= f_r;  side 1: H[r,:] /= f_r, W[:,r] *= f_r
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,

@@ -22,8 +22,9 @@
 
 namespace dna {
 
-using GZ = Geo<ZT_BM, ZT_BN, GEMM_BK, 2, 2>;   // Z-type products, M = N, N = T, K = R
-using GCW = Geo<64, ZT_BN, GEMM_BK, 2, 2>;     // W-orientation cost (row reductions)
+using GR = Geo<RT_BM, RT_BN, GEMM_BK, 2, 2>;   // ratio pass, M = N, N = T, K = R
+using GCH = Geo<CH_BM, CH_BN, GEMM_BK, 2, 2>;  // H-orientation cost (column reductions)
+using GCW = Geo<CW_BM, CW_BN, GEMM_BK, 2, 2>;  // W-orientation cost (row reductions)
 using GH = Geo<GH_BM, GH_BN, GEMM_BK, 2, 2>;   // H orientation gradient, M = R, N = T, K = N
 using GW = Geo<GW_BM, GW_BN, GEMM_BK, 2, 2>;   // W orientation gradient, M = N, N = R, K = T
 
@@ -82,8 +83,9 @@ __device__ __forceinline__ void reduce_rows(double (&rp)[NQ][G::FM][16], double*
 }
 
 __device__ __forceinline__ double xlogx_over(float v, float z) {
-  // v log(v/z) for v > 0, z > 0 (the summand of eq. 1 and steps 9/14)
-  return (double)v * (double)logf(v / z);
+  // v log(v/z) for v > 0, z > 0 (the summand of eq. 1 and steps 9/14); the ratio
+  // uses the hardware reciprocal (<= 1 ulp), the logarithm is the accurate one.
+  return (double)v * (double)logf(v * __builtin_amdgcn_rcpf(z));
 }
 
 // ---------------------------------------------------------------------------
@@ -96,13 +98,17 @@ struct RatioKArgs {
   float* Q; float* Qb;
   double* vpart; double* cpart;
   int* check;
+  float* Z;
 };
 
 template <int MODE>
-__global__ __launch_bounds__(GZ::NT) void k_ratio(RatioKArgs a) {
+__global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
+  using GZ = GR;
   using TL = Tile<GZ, ProdSingle, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
+  float vf[GZ::FM][GZ::FN][16];
+  TL::load_frag(vf, a.V, a.T, m0, n0, a.N, a.T);     // in flight during the K loop
   TL t;
   t.zero();
   {
@@ -111,8 +117,9 @@ __global__ __launch_bounds__(GZ::NT) void k_ratio(RatioKArgs a) {
     t.run(A, B, m0, n0, 0, a.R, lds);
   }
   constexpr bool WANT_Q = MODE != RM_KL;
-  constexpr bool WANT_QB = MODE == RM_H || MODE == RM_W;
-  constexpr bool COLS = MODE == RM_H || MODE == RM_MU_H_COST;     // column partials
+  constexpr bool WANT_QB = MODE == RM_H || MODE == RM_W || MODE == RM_ADJ;
+  constexpr bool WANT_Z = MODE == RM_ADJ;
+  constexpr bool COLS = MODE == RM_H || MODE == RM_MU_H_COST || MODE == RM_ADJ;  // column partials
   constexpr bool ROWS = MODE == RM_W || MODE == RM_MU_W_COST;     // row partials
   constexpr bool COST = MODE == RM_MU_H_COST || MODE == RM_MU_W_COST;
   const int64_t N = a.N, T = a.T;
@@ -135,18 +142,18 @@ __global__ __launch_bounds__(GZ::NT) void k_ratio(RatioKArgs a) {
       for (int v = 0; v < 16; ++v) {
         const int64_t row = TL::row_of(m0, i, v);
         if (row < N && col < T) {
-          const float x = a.V[row * T + col];
+          const float x = vf[i][j][v];
           const float z = t.acc[i][j][0][v];
-          float q = 0.f, qb = 0.f;
+          const bool pos = x > 0.f;
+          const float iz = __builtin_amdgcn_rcpf(z);
+          const float q = pos ? x * iz : 0.f;
+          const float qb = pos ? q * iz : 0.f;
+          bad |= (pos && !(z > 0.f)) ? 1 : 0;
           double term = 0.0;
-          if (x > 0.f) {
-            q = x / z;
-            qb = q / z;
-            if (!(z > 0.f)) bad = 1;
-            if (COST || MODE == RM_KL) term = xlogx_over(x, z);
-          }
+          if (COST || MODE == RM_KL) term = (double)(x * logf(pos ? q : 1.f));
           if (WANT_Q) a.Q[row * T + col] = q;
           if (WANT_QB) a.Qb[row * T + col] = qb;
+          if (WANT_Z) a.Z[row * T + col] = z;
           if (MODE == RM_KL) klsum += term - (double)x + (double)z;
           const double val = COST ? term : (double)x;
           if (COLS) cp[0][j] += val;
@@ -187,14 +194,14 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
   k.W = make_opnd(a.W, a.R, a.N);
   k.H = make_opnd(a.H, a.T, a.T);
   k.N = a.N; k.T = a.T; k.R = a.R;
-  k.Q = a.Q; k.Qb = a.Qb; k.vpart = a.vpart; k.cpart = a.cpart; k.check = a.check;
-  dim3 grid((unsigned)cdiv(a.T, GZ::BN), (unsigned)cdiv(a.N, GZ::BM));
+  k.Q = a.Q; k.Qb = a.Qb; k.vpart = a.vpart; k.cpart = a.cpart; k.check = a.check; k.Z = a.Z;
+  dim3 grid((unsigned)cdiv(a.T, GR::BN), (unsigned)cdiv(a.N, GR::BM));
   const char* nm = "ratio";
 #define DNA_RATIO_CASE(M, NAME)                                         \
   case M:                                                                \
     nm = NAME;                                                           \
     prof_begin(nm, s);                                                   \
-    hipLaunchKernelGGL(k_ratio<M>, grid, dim3(GZ::NT), 0, s, k);         \
+    hipLaunchKernelGGL(k_ratio<M>, grid, dim3(GR::NT), 0, s, k);         \
     break;
   switch (mode) {
     DNA_RATIO_CASE(RM_H, "ratio_H")
@@ -204,6 +211,7 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
     DNA_RATIO_CASE(RM_MU_W, "ratio_mu_W")
     DNA_RATIO_CASE(RM_MU_W_COST, "ratio_mu_W_cost")
     DNA_RATIO_CASE(RM_KL, "kl_terms")
+    DNA_RATIO_CASE(RM_ADJ, "ratio_adj")
     default: return hipErrorInvalidValue;
   }
 #undef DNA_RATIO_CASE
@@ -214,9 +222,14 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Gradient / Hessian numerators.
 // ---------------------------------------------------------------------------
+// Outputs of the gradient kernels: split partials of u, u_c (= u - c) and y.
+struct GHOut {
+  float* p[3];
+};
+
 template <class PR>
 __global__ __launch_bounds__(GH::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64_t N, int64_t T,
-                                                  int64_t R, int64_t kchunk, float* pu, float* py) {
+                                                  int64_t R, int64_t kchunk, GHOut out) {
   using TL = Tile<GH, PR, false, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   const int64_t m0 = (int64_t)blockIdx.y * GH::BM, n0 = (int64_t)blockIdx.x * GH::BN;
@@ -231,8 +244,6 @@ __global__ __launch_bounds__(GH::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64
     if constexpr (PR::NB > 1) B[PR::NB - 1] = Qb;
     t.run(A, B, m0, n0, k0, k1, lds);
   }
-  float* du = pu + sp * R * T;
-  float* dy = py + sp * R * T;
 #pragma unroll
   for (int i = 0; i < GH::FM; ++i)
 #pragma unroll
@@ -242,26 +253,28 @@ __global__ __launch_bounds__(GH::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64
       for (int v = 0; v < 16; ++v) {
         const int64_t row = TL::row_of(m0, i, v);
         if (row < R && col < T) {
-          du[row * T + col] = t.acc[i][j][0][v];
-          if constexpr (PR::NC > 1) dy[row * T + col] = t.acc[i][j][PR::NC - 1][v];
+#pragma unroll
+          for (int c = 0; c < PR::NC; ++c) out.p[c][(sp * R + row) * T + col] = t.acc[i][j][c][v];
         }
       }
     }
 }
 
 hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t N, int64_t T,
-                       int64_t R, int splits, int64_t kchunk, float* pu, float* py, hipStream_t s) {
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
+                       hipStream_t s) {
   dim3 grid((unsigned)cdiv(T, GH::BN), (unsigned)cdiv(R, GH::BM), (unsigned)splits);
   const Opnd wt = make_opnd(W, R, R);     // element (r, n) at W[n*R + r]: MN-contiguous
   const Opnd q = make_opnd(Q, T, T);      // element (t, n) at Q[n*T + t]: MN-contiguous
+  GHOut out = {{pu, puc, py}};
   if (Qb) {
     const Opnd qb = make_opnd(Qb, T, T);
     prof_begin("gh_H", s);
-    hipLaunchKernelGGL(k_gh_H<ProdDualB_SqA>, grid, dim3(GH::NT), 0, s, wt, q, qb, N, T, R, kchunk, pu, py);
+    hipLaunchKernelGGL(k_gh_H<ProdGH3_H>, grid, dim3(GH::NT), 0, s, wt, q, qb, N, T, R, kchunk, out);
     prof_end("gh_H", s);
   } else {
     prof_begin("gh_mu_H", s);
-    hipLaunchKernelGGL(k_gh_H<ProdSingle>, grid, dim3(GH::NT), 0, s, wt, q, q, N, T, R, kchunk, pu, pu);
+    hipLaunchKernelGGL(k_gh_H<ProdSingle>, grid, dim3(GH::NT), 0, s, wt, q, q, N, T, R, kchunk, out);
     prof_end("gh_mu_H", s);
   }
   return hipGetLastError();
@@ -269,7 +282,7 @@ hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t 
 
 template <class PR>
 __global__ __launch_bounds__(GW::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64_t N, int64_t T,
-                                                  int64_t R, int64_t kchunk, float* pu, float* py) {
+                                                  int64_t R, int64_t kchunk, GHOut out) {
   using TL = Tile<GW, PR, true, true>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   const int64_t m0 = (int64_t)blockIdx.y * GW::BM, n0 = (int64_t)blockIdx.x * GW::BN;
@@ -284,8 +297,6 @@ __global__ __launch_bounds__(GW::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64
     const Opnd B[PR::NB] = {Ht};
     t.run(A, B, m0, n0, k0, k1, lds);
   }
-  float* du = pu + sp * N * R;
-  float* dy = py + sp * N * R;
 #pragma unroll
   for (int i = 0; i < GW::FM; ++i)
 #pragma unroll
@@ -295,26 +306,28 @@ __global__ __launch_bounds__(GW::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64
       for (int v = 0; v < 16; ++v) {
         const int64_t row = TL::row_of(m0, i, v);
         if (row < N && col < R) {
-          du[row * R + col] = t.acc[i][j][0][v];
-          if constexpr (PR::NC > 1) dy[row * R + col] = t.acc[i][j][PR::NC - 1][v];
+#pragma unroll
+          for (int c = 0; c < PR::NC; ++c) out.p[c][(sp * N + row) * R + col] = t.acc[i][j][c][v];
         }
       }
     }
 }
 
 hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t N, int64_t T,
-                       int64_t R, int splits, int64_t kchunk, float* pu, float* py, hipStream_t s) {
+                       int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
+                       hipStream_t s) {
   dim3 grid((unsigned)cdiv(R, GW::BN), (unsigned)cdiv(N, GW::BM), (unsigned)splits);
   const Opnd q = make_opnd(Q, T, N);      // element (n, t) at Q[n*T + t]: K-contiguous
   const Opnd ht = make_opnd(H, T, R);     // element (r, t) at H[r*T + t]: K-contiguous
+  GHOut out = {{pu, puc, py}};
   if (Qb) {
     const Opnd qb = make_opnd(Qb, T, N);
     prof_begin("gh_W", s);
-    hipLaunchKernelGGL(k_gh_W<ProdDualA_SqB>, grid, dim3(GW::NT), 0, s, q, qb, ht, N, T, R, kchunk, pu, py);
+    hipLaunchKernelGGL(k_gh_W<ProdGH3_W>, grid, dim3(GW::NT), 0, s, q, qb, ht, N, T, R, kchunk, out);
     prof_end("gh_W", s);
   } else {
     prof_begin("gh_mu_W", s);
-    hipLaunchKernelGGL(k_gh_W<ProdSingle>, grid, dim3(GW::NT), 0, s, q, q, ht, N, T, R, kchunk, pu, pu);
+    hipLaunchKernelGGL(k_gh_W<ProdSingle>, grid, dim3(GW::NT), 0, s, q, q, ht, N, T, R, kchunk, out);
     prof_end("gh_mu_W", s);
   }
   return hipGetLastError();
@@ -327,13 +340,29 @@ struct Cand {
   float mu, newton, A, B;
 };
 
-// One coordinate: numerators u = (F^t q)_r, y = ((F*F)^t q-bar)_r, scale c_r.
-__device__ __forceinline__ Cand candidate(float x, float u, float y, float c, float eps, float alpha) {
+// MU gain g = u/c and A = g - 1 (eq. 7) from the two forms of the gradient sum:
+// where g < 1/2 the plain sum u = (F^t q)_r carries g to float32 relative
+// accuracy; elsewhere the centred sum u_c = (F^t (q - 1))_r carries A to float32
+// accuracy near its zero (near-stationary coordinates, where the Newton step
+// divides by b).
+__device__ __forceinline__ void gain(float u, float uc, float c, float& g, float& A) {
+  const float gp = u / c;
+  if (gp < 0.5f) {
+    g = gp;
+    A = gp - 1.f;
+  } else {
+    A = uc / c;
+    g = 1.f + A;
+  }
+}
+
+// One coordinate: numerators u, u_c, y = ((F*F)^t q-bar)_r, scale c_r.
+__device__ __forceinline__ Cand candidate(float x, float u, float uc, float y, float c, float eps, float alpha) {
   Cand o;
-  const float g = u / c;            // MU gain (W^t q)_r / (W^t 1)_r, eq. (11)
-  o.A = g - 1.f;                    // eq. (7)
+  float g;
+  gain(u, uc, c, g, o.A);           // eq. (7)
   o.B = y / c;                      // eq. (14)
-  o.mu = x * g;
+  o.mu = fmaxf(x * g, VALUE_FLOOR); // eq. (11), kept a positive normal float
   if (o.A < 0.f) {                  // eq. (15), gain floored at eps
     const float xb = x * o.B;
     o.newton = x * fmaxf(xb / (xb - o.A), eps);
@@ -344,24 +373,29 @@ __device__ __forceinline__ Cand candidate(float x, float u, float y, float c, fl
   return o;
 }
 
-// 64 columns per block, 4 row groups; renormalisation eq. (10) per column.
-__global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu, const float* py, int splits,
+// CAND_COLS columns per block, 256 / CAND_COLS row groups; renormalisation eq. (10)
+// per column through a fixed-order LDS reduction.
+constexpr int CAND_COLS = 32, CAND_RG = 256 / CAND_COLS;
+
+__global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
                                                 const float* c, const double* vpart, int tiles_m,
                                                 int64_t T, int64_t R, float eps, float alpha,
                                                 float* Xmu, float* Xn, float* Aout, float* Bout) {
-  __shared__ double red[4][64];
-  const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
-  const int64_t t = (int64_t)blockIdx.x * 64 + cl;
+  __shared__ double red[CAND_RG][CAND_COLS];
+  __shared__ double fac[CAND_COLS];
+  const int tid = threadIdx.x, cl = tid % CAND_COLS, rg = tid / CAND_COLS;
+  const int64_t t = (int64_t)blockIdx.x * CAND_COLS + cl;
   const bool ok = t < T;
   double den = 0.0;
   if (ok) {
-    for (int64_t r = rg; r < R; r += 4) {
-      float u = 0.f, y = 0.f;
+    for (int64_t r = rg; r < R; r += CAND_RG) {
+      float u = 0.f, uc = 0.f, y = 0.f;
       for (int sp = 0; sp < splits; ++sp) {
         u += pu[(sp * R + r) * T + t];
+        uc += puc[(sp * R + r) * T + t];
         y += py[(sp * R + r) * T + t];
       }
-      const Cand k = candidate(H[r * T + t], u, y, c[r], eps, alpha);
+      const Cand k = candidate(H[r * T + t], u, uc, y, c[r], eps, alpha);
       Xmu[r * T + t] = k.mu;
       Xn[r * T + t] = k.newton;
       if (Aout) Aout[r * T + t] = k.A;
@@ -371,27 +405,33 @@ __global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu,
   }
   red[rg][cl] = den;
   __syncthreads();
-  if (ok) {
-    const double d = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+  if (rg == 0 && ok) {
+    double d = 0.0;
+    for (int k = 0; k < CAND_RG; ++k) d += red[k][cl];
     double s = 0.0;
     for (int m = 0; m < tiles_m; ++m) s += vpart[(int64_t)m * T + t];
-    const double f = d > 0.0 ? s / d : 1.0;
-    for (int64_t r = rg; r < R; r += 4) Xn[r * T + t] = (float)((double)Xn[r * T + t] * f);
+    fac[cl] = d > 0.0 ? s / d : 1.0;
+  }
+  __syncthreads();
+  if (ok) {
+    const double f = fac[cl];
+    for (int64_t r = rg; r < R; r += CAND_RG)
+      Xn[r * T + t] = fmaxf((float)((double)Xn[r * T + t] * f), VALUE_FLOOR);
   }
 }
 
-hipError_t launch_cand_H(const float* H, const float* pu, const float* py, int splits, const float* c,
+hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits, const float* c,
                          const double* vpart, int tiles_m, int64_t T, int64_t R, float eps, float alpha,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_H", s);
-  hipLaunchKernelGGL(k_cand_H, dim3((unsigned)cdiv(T, 64)), dim3(256), 0, s, H, pu, py, splits, c, vpart,
+  hipLaunchKernelGGL(k_cand_H, dim3((unsigned)cdiv(T, CAND_COLS)), dim3(256), 0, s, H, pu, puc, py, splits, c, vpart,
                      tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
   prof_end("cand_H", s);
   return hipGetLastError();
 }
 
 // One wave per row n of W; lanes stride over r.
-__global__ __launch_bounds__(256) void k_cand_W(const float* W, const float* pu, const float* py, int splits,
+__global__ __launch_bounds__(256) void k_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits,
                                                 const float* g, const double* vpart, int tiles_n,
                                                 int64_t N, int64_t R, float eps, float alpha,
                                                 float* Xmu, float* Xn, float* Aout, float* Bout) {
@@ -400,12 +440,13 @@ __global__ __launch_bounds__(256) void k_cand_W(const float* W, const float* pu,
   if (n >= N) return;
   double den = 0.0;
   for (int64_t r = lane; r < R; r += 64) {
-    float u = 0.f, y = 0.f;
+    float u = 0.f, uc = 0.f, y = 0.f;
     for (int sp = 0; sp < splits; ++sp) {
       u += pu[(sp * N + n) * R + r];
+      uc += puc[(sp * N + n) * R + r];
       y += py[(sp * N + n) * R + r];
     }
-    const Cand k = candidate(W[n * R + r], u, y, g[r], eps, alpha);
+    const Cand k = candidate(W[n * R + r], u, uc, y, g[r], eps, alpha);
     Xmu[n * R + r] = k.mu;
     Xn[n * R + r] = k.newton;
     if (Aout) Aout[n * R + r] = k.A;
@@ -417,14 +458,14 @@ __global__ __launch_bounds__(256) void k_cand_W(const float* W, const float* pu,
   den = __shfl(wave_sum(den), 0);
   s = __shfl(wave_sum(s), 0);
   const double f = den > 0.0 ? s / den : 1.0;
-  for (int64_t r = lane; r < R; r += 64) Xn[n * R + r] = (float)((double)Xn[n * R + r] * f);
+  for (int64_t r = lane; r < R; r += 64) Xn[n * R + r] = fmaxf((float)((double)Xn[n * R + r] * f), VALUE_FLOOR);
 }
 
-hipError_t launch_cand_W(const float* W, const float* pu, const float* py, int splits, const float* g,
+hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits, const float* g,
                          const double* vpart, int tiles_n, int64_t N, int64_t R, float eps, float alpha,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_W", s);
-  hipLaunchKernelGGL(k_cand_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, W, pu, py, splits, g, vpart,
+  hipLaunchKernelGGL(k_cand_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, W, pu, puc, py, splits, g, vpart,
                      tiles_n, N, R, eps, alpha, Xmu, Xn, Aout, Bout);
   prof_end("cand_W", s);
   return hipGetLastError();
@@ -438,23 +479,37 @@ hipError_t launch_cand_W(const float* W, const float* pu, const float* py, int s
 //   q2 += v log(v/z_MU)           (rows with z_DNA <= 0 < z_MU; bit 2 if z_MU <= 0)
 // so that, absent flags, d_MU = q0 + q1 and margin = q1.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void cost_terms(float x, float zN, float dz, double (&q)[3], int& fl) {
+// Branch-free for the common case (both reconstructions positive or v = 0): the
+// logarithms take neutral arguments where a term must vanish.  Returns the flag
+// bits of this element.
+__device__ __forceinline__ int cost_acc(float x, float zN, float dz, double& s0, double& s1, double& s2) {
   const float zM = zN + dz;
+  const bool pos = x > 0.f;
   const bool okN = zN > 0.f, okM = zM > 0.f;
-  if (okN) q[0] = xlogx_over(x, zN); else fl |= 1;
-  if (okN && okM) q[1] = -(double)x * (double)log1pf(dz / zN);
-  else if (okM) q[2] = xlogx_over(x, zM);
-  if (!okM) fl |= 2;
+  const float izN = __builtin_amdgcn_rcpf(zN);
+  const float l0 = logf((pos && okN) ? x * izN : 1.f);
+  const float l1 = log1pf((pos && okN && okM) ? dz * izN : 0.f);
+  s0 += (double)(x * l0);
+  s1 -= (double)(x * l1);
+  int fl = 0;
+  if (pos && !(okN && okM)) {            // a reconstruction vanished where v > 0
+    fl = (okN ? 0 : 1) | (okM ? 0 : 2);
+    if (!okN && okM) s2 += xlogx_over(x, zM);
+  }
+  return fl;
 }
 
-__global__ __launch_bounds__(GZ::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,
-                                                    int64_t T, int64_t R, double* part, int* fpart) {
+__global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,
+                                                     int64_t T, int64_t R, double* part, int* fpart) {
+  using GZ = GCH;
   using TL = Tile<GZ, ProdDualB, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   __shared__ int fl_s[GZ::BN];
   const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
   const int tid = threadIdx.x;
   for (int c = tid; c < GZ::BN; c += GZ::NT) fl_s[c] = 0;
+  float vf[GZ::FM][GZ::FN][16];
+  TL::load_frag(vf, V, T, m0, n0, N, T);
   TL t;
   t.zero();
   {
@@ -476,16 +531,8 @@ __global__ __launch_bounds__(GZ::NT) void k_cost_H(const float* V, Opnd W, Opnd 
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t row = TL::row_of(m0, i, v);
-        if (row < N && col < T) {
-          const float x = V[row * T + col];
-          if (x > 0.f) {
-            double q[3] = {0.0, 0.0, 0.0};
-            cost_terms(x, t.acc[i][j][0][v], t.acc[i][j][1][v], q, fl);
-            cp[0][j] += q[0];
-            cp[1][j] += q[1];
-            cp[2][j] += q[2];
-          }
-        }
+        const float x = (row < N && col < T) ? vf[i][j][v] : 0.f;
+        fl |= cost_acc(x, t.acc[i][j][0][v], t.acc[i][j][1][v], cp[0][j], cp[1][j], cp[2][j]);
       }
     if (fl) atomicOr(&fl_s[col - n0], fl);
   }
@@ -503,12 +550,12 @@ __global__ __launch_bounds__(GZ::NT) void k_cost_H(const float* V, Opnd W, Opnd 
 
 hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn, int64_t N,
                          int64_t T, int64_t R, double* part, int* fpart, hipStream_t s) {
-  dim3 grid((unsigned)cdiv(T, GZ::BN), (unsigned)cdiv(N, GZ::BM));
+  dim3 grid((unsigned)cdiv(T, GCH::BN), (unsigned)cdiv(N, GCH::BM));
   const Opnd w = make_opnd(W, R, N);
   const Opnd hn = make_opnd(Xn, T, T);
   const Opnd hd = make_opnd(Xmu, T, T, Xn);
   prof_begin("cost_H", s);
-  hipLaunchKernelGGL(k_cost_H, grid, dim3(GZ::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart);
+  hipLaunchKernelGGL(k_cost_H, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart);
   prof_end("cost_H", s);
   return hipGetLastError();
 }
@@ -521,6 +568,8 @@ __global__ __launch_bounds__(GCW::NT) void k_cost_W(const float* V, Opnd Wn, Opn
   const int64_t m0 = (int64_t)blockIdx.y * GCW::BM, n0 = (int64_t)blockIdx.x * GCW::BN;
   const int tid = threadIdx.x;
   for (int r = tid; r < GCW::BM; r += GCW::NT) fl_s[r] = 0;
+  float vf[GCW::FM][GCW::FN][16];
+  TL::load_frag(vf, V, T, m0, n0, N, T);
   TL t;
   t.zero();
   {
@@ -544,16 +593,8 @@ __global__ __launch_bounds__(GCW::NT) void k_cost_W(const float* V, Opnd Wn, Opn
 #pragma unroll
       for (int j = 0; j < GCW::FN; ++j) {
         const int64_t col = TL::col_of(n0, j);
-        if (row < N && col < T) {
-          const float x = V[row * T + col];
-          if (x > 0.f) {
-            double q[3] = {0.0, 0.0, 0.0};
-            cost_terms(x, t.acc[i][j][0][v], t.acc[i][j][1][v], q, fl);
-            rp[0][i][v] += q[0];
-            rp[1][i][v] += q[1];
-            rp[2][i][v] += q[2];
-          }
-        }
+        const float x = (row < N && col < T) ? vf[i][j][v] : 0.f;
+        fl |= cost_acc(x, t.acc[i][j][0][v], t.acc[i][j][1][v], rp[0][i][v], rp[1][i][v], rp[2][i][v]);
       }
       if (fl) atomicOr(&fl_s[row - m0], fl);
     }
@@ -603,32 +644,40 @@ __global__ __launch_bounds__(256) void k_select_H(const float* Xmu, const float*
                                                   const double* part, const int* fpart, int tiles,
                                                   int64_t T, int64_t R, uint8_t* mask, double* dsel,
                                                   double* margin) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= T) return;
-  const int64_t stride = (int64_t)tiles * T;
-  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
-  int fl = 0;
-  for (int m = 0; m < tiles; ++m) {
-    const int64_t o = (int64_t)m * T + t;
-    q0 += part[o];
-    q1 += part[stride + o];
-    q2 += part[2 * stride + o];
-    fl |= fpart[o];
+  // CAND_COLS columns per block: row group 0 decides, every row group copies.
+  __shared__ int pick[CAND_COLS];
+  const int tid = threadIdx.x, cl = tid % CAND_COLS, rg = tid / CAND_COLS;
+  const int64_t t = (int64_t)blockIdx.x * CAND_COLS + cl;
+  const bool ok = t < T;
+  if (rg == 0 && ok) {
+    const int64_t stride = (int64_t)tiles * T;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    int fl = 0;
+    for (int m = 0; m < tiles; ++m) {
+      const int64_t o = (int64_t)m * T + t;
+      q0 += part[o];
+      q1 += part[stride + o];
+      q2 += part[2 * stride + o];
+      fl |= fpart[o];
+    }
+    double ds, mg;
+    const bool nw = decide(q0, q1, q2, fl, ds, mg);
+    if (mask) mask[t] = nw ? 1 : 0;
+    if (dsel) dsel[t] = ds;
+    if (margin) margin[t] = mg;
+    pick[cl] = nw ? 1 : 0;
   }
-  double ds, mg;
-  const bool nw = decide(q0, q1, q2, fl, ds, mg);
-  if (mask) mask[t] = nw ? 1 : 0;
-  if (dsel) dsel[t] = ds;
-  if (margin) margin[t] = mg;
-  const float* src = nw ? Xn : Xmu;
-  for (int64_t r = 0; r < R; ++r) Hout[r * T + t] = src[r * T + t];
+  __syncthreads();
+  if (!ok) return;
+  const float* src = pick[cl] ? Xn : Xmu;
+  for (int64_t r = rg; r < R; r += CAND_RG) Hout[r * T + t] = src[r * T + t];
 }
 
 hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,
                            const int* fpart, int tiles_m, int64_t T, int64_t R, uint8_t* mask,
                            double* dsel, double* margin, hipStream_t s) {
   prof_begin("select_H", s);
-  hipLaunchKernelGGL(k_select_H, dim3((unsigned)cdiv(T, 256)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
+  hipLaunchKernelGGL(k_select_H, dim3((unsigned)cdiv(T, CAND_COLS)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
                      tiles_m, T, R, mask, dsel, margin);
   prof_end("select_H", s);
   return hipGetLastError();
@@ -688,7 +737,7 @@ __global__ __launch_bounds__(256) void k_mu_H(float* H, const float* pu, int spl
   for (int64_t r = rg; r < R; r += 4) {
     float u = 0.f;
     for (int sp = 0; sp < splits; ++sp) u += pu[(sp * R + r) * T + t];
-    H[r * T + t] = H[r * T + t] * (u / c[r]);
+    H[r * T + t] = fmaxf(H[r * T + t] * (u / c[r]), VALUE_FLOOR);     // eq. (11): h (W^t q)_r / c_r
   }
   if (d_out && rg == 0) {
     double s = 0.0;
@@ -715,7 +764,7 @@ __global__ __launch_bounds__(256) void k_mu_W(float* W, const float* pu, int spl
   for (int64_t r = lane; r < R; r += 64) {
     float u = 0.f;
     for (int sp = 0; sp < splits; ++sp) u += pu[(sp * N + n) * R + r];
-    W[n * R + r] = W[n * R + r] * (u / g[r]);
+    W[n * R + r] = fmaxf(W[n * R + r] * (u / g[r]), VALUE_FLOOR);
   }
   if (d_out) {
     double s = 0.0;
@@ -737,58 +786,75 @@ hipError_t launch_mu_W(float* W, const float* pu, int splits, const float* g, in
 // ---------------------------------------------------------------------------
 // Normalisation (steps 1, 16, 29) and the column / row sums they need.
 // ---------------------------------------------------------------------------
-// Column sums of W (N x R): 64 columns per block, 16 row groups.
-__global__ __launch_bounds__(1024) void k_colsum_W(const float* W, int64_t N, int64_t R, double* s64,
-                                                   float* s32, int* check) {
-  __shared__ double red[16][64];
+// Column sums of W (N x R) and row sums of H (R x T), each in two fixed-order
+// levels: `nparts` blocks per column / row write partial float64 sums to
+// part[p][r], then one thread per r adds the parts in order.
+__global__ __launch_bounds__(256) void k_colsum_part(const float* W, int64_t N, int64_t R, int64_t rows,
+                                                     double* part) {
+  __shared__ double red[4][64];
   const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
   const int64_t r = (int64_t)blockIdx.x * 64 + cl;
+  const int64_t p = blockIdx.y;
+  const int64_t n1 = std::min<int64_t>(N, (p + 1) * rows);
   double s = 0.0;
   if (r < R)
-    for (int64_t n = rg; n < N; n += 16) s += (double)W[n * R + r];
+    for (int64_t n = p * rows + rg; n < n1; n += 4) s += (double)W[n * R + r];
   red[rg][cl] = s;
   __syncthreads();
-  if (rg == 0 && r < R) {
-    double tot = 0.0;
-    for (int k = 0; k < 16; ++k) tot += red[k][cl];
-    if (s64) s64[r] = tot;
-    if (s32) s32[r] = (float)tot;
-    if (check && !(tot > 0.0)) atomicOr(check, CHK_DOMAIN);
-  }
+  if (rg == 0 && r < R) part[p * R + r] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
 }
 
-hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* sum64, float* sum32, int* check,
-                           hipStream_t s) {
-  prof_begin("colsum_W", s);
-  hipLaunchKernelGGL(k_colsum_W, dim3((unsigned)cdiv(R, 64)), dim3(1024), 0, s, W, N, R, sum64, sum32, check);
-  prof_end("colsum_W", s);
-  return hipGetLastError();
-}
-
-// Row sums of H (R x T): one block per row.
-__global__ __launch_bounds__(256) void k_rowsum_H(const float* H, int64_t T, int64_t R, double* s64,
-                                                  float* s32, int* check) {
+__global__ __launch_bounds__(256) void k_rowsum_part(const float* H, int64_t T, int64_t R, int64_t cols,
+                                                     double* part) {
   __shared__ double red[4];
   const int tid = threadIdx.x;
-  const int64_t r = blockIdx.x;
+  const int64_t p = blockIdx.x, r = blockIdx.y;
+  const int64_t t1 = std::min<int64_t>(T, (p + 1) * cols);
   double s = 0.0;
-  for (int64_t t = tid; t < T; t += 256) s += (double)H[r * T + t];
+  for (int64_t t = p * cols + tid; t < t1; t += 256) s += (double)H[r * T + t];
   s = wave_sum(s);
   if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
-  if (tid == 0) {
-    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
-    if (s64) s64[r] = tot;
-    if (s32) s32[r] = (float)tot;
-    if (check && !(tot > 0.0)) atomicOr(check, CHK_DOMAIN);
-  }
+  if (tid == 0) part[p * R + r] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* sum64, float* sum32, int* check,
-                           hipStream_t s) {
+__global__ __launch_bounds__(256) void k_sum_final(const double* part, int nparts, int64_t R, double* s64,
+                                                   float* s32, int* check) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  double tot = 0.0;
+  for (int p = 0; p < nparts; ++p) tot += part[(int64_t)p * R + r];
+  if (s64) s64[r] = tot;
+  if (s32) s32[r] = (float)tot;
+  if (check && !(tot > 0.0)) atomicOr(check, CHK_DOMAIN);
+}
+
+hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* part, double* sum64, float* sum32,
+                           int* check, hipStream_t s) {
+  const int64_t nparts = std::min<int64_t>(SUM_PARTS, cdiv(N, 64));
+  const int64_t rows = cdiv(N, nparts);
+  prof_begin("colsum_W", s);
+  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)cdiv(R, 64), (unsigned)nparts), dim3(256), 0, s, W, N, R,
+                     rows, part);
+  prof_end("colsum_W", s);
+  prof_begin("sum_final", s);
+  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)cdiv(R, 256)), dim3(256), 0, s, part, (int)nparts, R, sum64,
+                     sum32, check);
+  prof_end("sum_final", s);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* part, double* sum64, float* sum32,
+                           int* check, hipStream_t s) {
+  const int64_t nparts = std::min<int64_t>(SUM_PARTS, cdiv(T, 2048));
+  const int64_t cols = cdiv(T, nparts);
   prof_begin("rowsum_H", s);
-  hipLaunchKernelGGL(k_rowsum_H, dim3((unsigned)R), dim3(256), 0, s, H, T, R, sum64, sum32, check);
+  hipLaunchKernelGGL(k_rowsum_part, dim3((unsigned)nparts, (unsigned)R), dim3(256), 0, s, H, T, R, cols, part);
   prof_end("rowsum_H", s);
+  prof_begin("sum_final", s);
+  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)cdiv(R, 256)), dim3(256), 0, s, part, (int)nparts, R, sum64,
+                     sum32, check);
+  prof_end("sum_final", s);
   return hipGetLastError();
 }
 

@@ -278,6 +278,66 @@ def select(side, V, F, X_mu, X_newton, **kw):
     return out, m, d, g
 
 
+# --------------------------------------------------------------------------- unrolled H-solve
+
+def unrolled_forward(V, W, H_init, K, **kw):
+    """K DNA H-updates with W fixed.  Returns (H_ckpt [K+1,R,T], sel [K,T])."""
+    N, T, R = _dims(V, W, H_init)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o, unrolled=True)
+    H_ckpt = torch.empty((K + 1, R, T), dtype=torch.float32, device=V.device)
+    sel = torch.empty((max(K, 1), T), dtype=torch.uint8, device=V.device)
+    _check(_lib_ufwd(_ptr(V), _ptr(W), _ptr(H_init), int(K), N, T, R, ctypes.byref(o), _ptr(H_ckpt),
+                     _ptr(sel), _ptr(ws), ws.numel(), _stream()))
+    return H_ckpt, sel[:K]
+
+
+def unrolled_backward(V, W, H_ckpt, sel, K, dH_K, want_dH_init=True, **kw):
+    """Vector-Jacobian product of the K updates: returns (dW, dV, dH_init)."""
+    N, T = V.shape
+    R = W.shape[1]
+    _mat(V, "V")
+    _mat(W, "W", (N, R))
+    if tuple(H_ckpt.shape) != (K + 1, R, T) or not H_ckpt.is_contiguous():
+        raise ValueError("H_ckpt must be a contiguous (K+1, R, T) tensor")
+    _mat(dH_K, "dH_K", (R, T))
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o, unrolled=True)
+    dW = torch.empty((N, R), dtype=torch.float32, device=V.device)
+    dV = torch.empty((N, T), dtype=torch.float32, device=V.device)
+    dH0 = torch.empty((R, T), dtype=torch.float32, device=V.device) if want_dH_init else None
+    sel = sel.contiguous()
+    _check(_lib_ubwd(_ptr(V), _ptr(W), _ptr(H_ckpt), _ptr(sel), int(K), N, T, R, _ptr(dH_K), _ptr(dW), _ptr(dV),
+                     _ptr(dH0), ctypes.byref(o), _ptr(ws), ws.numel(), _stream()))
+    return dW, dV, dH0
+
+
+class DNAUnrolledH(torch.autograd.Function):
+    """H_K = K DNA H-updates of H_init with W fixed; differentiable in W, V and
+    H_init through the hand-written adjoint (selections frozen at their forward
+    values, per-iteration checkpoints of H)."""
+
+    @staticmethod
+    def forward(ctx, W, V, H_init, K, eps=0.01, alpha=4.0):
+        W, V, H_init = W.detach().contiguous(), V.detach().contiguous(), H_init.detach().contiguous()
+        H_ckpt, sel = unrolled_forward(V, W, H_init, K, eps=eps, alpha=alpha)
+        ctx.save_for_backward(W, V, H_ckpt, sel)
+        ctx.K, ctx.eps, ctx.alpha = K, eps, alpha
+        return H_ckpt[K].clone()
+
+    @staticmethod
+    def backward(ctx, gH):
+        W, V, H_ckpt, sel = ctx.saved_tensors
+        dW, dV, dH0 = unrolled_backward(V, W, H_ckpt, sel, ctx.K, gH.contiguous().float(),
+                                        want_dH_init=ctx.needs_input_grad[2], eps=ctx.eps, alpha=ctx.alpha)
+        return (dW if ctx.needs_input_grad[0] else None, dV if ctx.needs_input_grad[1] else None,
+                dH0, None, None, None)
+
+
+def unrolled_h(W, V, H_init, K, eps=0.01, alpha=4.0):
+    return DNAUnrolledH.apply(W, V, H_init, K, eps, alpha)
+
+
 # --------------------------------------------------------------------------- profiling
 
 def profile_enable(on=True):

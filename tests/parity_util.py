@@ -23,6 +23,25 @@ SELECT_TIE = 1e-12
 STATE_TIE = 1e-5
 
 
+EPS32 = 2.0 ** -24
+# Smallest positive normal float32: the factors' storage format.  The oracle is
+# run with this value floor wherever it is compared with the float32 path.
+FLOOR32 = float(np.finfo(np.float32).tiny)
+
+
+def cost_err(d_gpu, d_ref, vsum):
+    """max over columns of |d_gpu - d_ref| / (|d_ref| + 8 eps32 sum v / STEP_TOL).
+
+    A cost sum_{v>0} v log(v/z) evaluated from float32 reconstructions carries an
+    absolute error of a few float32 ulps of each log, i.e. about eps32 * sum v,
+    whatever the size of the cost itself (which may be ~0 when z fits v); the
+    floor keeps the comparison relative where d is large and absolute where it
+    vanishes.  <= 1 means within STEP_TOL."""
+    d_gpu, d_ref, vsum = (np.asarray(x, float) for x in (d_gpu, d_ref, vsum))
+    den = STEP_TOL * np.abs(d_ref) + 8 * EPS32 * vsum
+    return float(np.max(np.abs(d_gpu - d_ref) / np.maximum(den, 1e-300))) if d_ref.size else 0.0
+
+
 def gpu(x):
     return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float32))).cuda()
 

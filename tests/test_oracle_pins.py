@@ -401,6 +401,27 @@ def test_newton_candidate_branches():
     assert out[0, 4] == pytest.approx(10.0)          # b = 0, a > 0: cap
 
 
+def test_value_floor_reading():
+    """The value floor changes nothing where every entry stays above it, and keeps
+    an entry whose repeated eps-floored shrink would underflow float32 positive."""
+    w = synth.random_problem(30, 20, 4, 14, zero_frac=0.2)
+    V, W, H = [x.astype(float) for x in (w.V, w.W, w.H)]
+    tiny = float(np.finfo(np.float32).tiny)
+    a = oracle.h_step(V, W, H)
+    b = oracle.h_step(V, W, H, value_floor=tiny)
+    np.testing.assert_array_equal(a.X, b.X)
+    np.testing.assert_array_equal(a.chose_newton, b.chose_newton)
+    # a column whose data lies on basis 0 only: the other coordinates shrink by
+    # at most eps per step and would pass below 2^-126 within ~20 steps
+    Wd = np.eye(3) + 0.0
+    Vd = np.outer(np.array([5.0, 0.0, 0.0]), np.ones(2))
+    Hd = np.ones((3, 2))
+    for _ in range(40):
+        Hd = oracle.h_step(Vd, Wd, Hd, value_floor=tiny).X
+    assert np.all(Hd[1:] >= tiny) and np.all(Hd[1:] < 1e-30)
+    np.testing.assert_allclose(Hd[0], 5.0, rtol=1e-12)
+
+
 def test_normalisations_leave_product_unchanged():
     w = synth.random_problem(10, 12, 3, 13)
     W, H = w.W.astype(float), w.H.astype(float)
