@@ -22,7 +22,9 @@ if ROOT not in sys.path:
 
 METRIC = "DNA iters/s and time-to-target-KL vs MU (N×T×R), MFMA util %, 1 MI355X"
 PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 matrix peak
+PEAK_16_TFLOPS = 2500.0       # MI355X dense BF16 / FP16 matrix peak
 PEAK_HBM_GBS = 8000.0
+DTYPE = {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}
 
 WORKLOADS = {
     2: "Gamma(0.5) factors, 30%-dense H0, Poisson counts at mean 5",
@@ -40,11 +42,14 @@ def kernel_work(name, N, T, R):
     which the paper carries over instead; it is reported but is not algorithmic.
     """
     nrt = float(N) * R * T
-    table = {
-        "gh_H": ("flops", 4 * nrt), "gh_W": ("flops", 4 * nrt),
-        "cost_H": ("flops", 4 * nrt), "cost_W": ("flops", 4 * nrt),
-        "ratio_H": ("flops_recompute", 2 * nrt), "ratio_W": ("flops_recompute", 2 * nrt),
-    }
+    table = {}
+    for sfx in ("", "16"):
+        table.update({
+            f"gh{sfx}_H": ("flops", 4 * nrt), f"gh{sfx}_W": ("flops", 4 * nrt),
+            f"cost{sfx}_H": ("flops", 4 * nrt), f"cost{sfx}_W": ("flops", 4 * nrt),
+            f"ratio{sfx}_H": ("flops_recompute", 2 * nrt), f"ratio{sfx}_W": ("flops_recompute", 2 * nrt),
+        })
+    table["qmax16"] = ("flops_recompute", 2 * nrt)
     return table.get(name)
 
 
@@ -60,7 +65,56 @@ def parse():
     ap.add_argument("--no-target", action="store_true", help="skip the time-to-target-KL runs")
     ap.add_argument("--mu-iters", type=int, default=1000, help="MU iterations that fix the target KL")
     ap.add_argument("--dna-iters", type=int, default=1000, help="DNA iteration budget for the target")
+    ap.add_argument("--gemm", default="fp32", choices=["fp32", "bf16", "fp16"],
+                    help="operand type of the DNA matrix products (16-bit: FP32 accumulate, FP64 sums)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB five times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size: 256 MiB read + 256 MiB written per launch."""
+    import torch
+    n = 64 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+
+
+def timed_steps(dna, V, W, H, steps, gemm):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dna.dna_iteration(V, W, H, gemm=gemm)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def iters_to_target(dna, V, W0, H0, kl_target, budget, gemm, chunk=10):
+    """DNA iterations (from the same start) until the KL is at or below the target;
+    the KL after every iteration is recorded on the device and checked every
+    `chunk` iterations.  Returns (iterations or None, last KL)."""
+    import numpy as np
+    import torch
+    W, H = W0.clone(), H0.clone()
+    dna.normalize(0, W, H)
+    kls = torch.empty(budget + 1, dtype=torch.float64, device=V.device)
+    dna.kl_cost(V, W, H, out=kls[0:1])
+    done = 0
+    while done < budget:
+        m = min(chunk, budget - done)
+        for k in range(m):
+            dna.dna_iteration(V, W, H, gemm=gemm)
+            dna.kl_cost(V, W, H, out=kls[done + k + 1:done + k + 2])
+        done += m
+        hit = np.nonzero(kls[:done + 1].cpu().numpy() <= kl_target)[0]
+        if hit.size:
+            return int(hit[0]), float(kls[hit[0]].item())
+    return None, float(kls[done].item())
 
 
 def cpu_baseline(w, seconds):
@@ -92,11 +146,14 @@ def cpu_baseline(w, seconds):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the H half-step would shard over columns and the W half-step needs one "
-              "all-reduce of its partial sums; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(with V sharded by columns, the H half-step is local and the W half-step "
+              "needs one all-reduce of its N x R gradient sums and per-row costs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -112,10 +169,11 @@ def main():
     W0 = torch.from_numpy(w.W).to(dev)
     H0 = torch.from_numpy(w.H).to(dev)
 
+    gemm = args.gemm
     W, H = W0.clone(), H0.clone()
     dna.normalize(0, W, H)                                   # Algorithm 1 step 1
     for _ in range(args.warmup):
-        dna.dna_iteration(V, W, H)
+        dna.dna_iteration(V, W, H, gemm=gemm)
     torch.cuda.synchronize()
 
     # ---- timed region -----------------------------------------------------
@@ -125,7 +183,7 @@ def main():
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        dna.dna_iteration(V, W, H)
+        dna.dna_iteration(V, W, H, gemm=gemm)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -139,7 +197,7 @@ def main():
     torch.cuda.synchronize()
     tp = time.perf_counter()
     for _ in range(args.steps):
-        dna.dna_iteration(V, W, H)
+        dna.dna_iteration(V, W, H, gemm=gemm)
     torch.cuda.synchronize()
     prof_wall = time.perf_counter() - tp
     stats = dna.profile_read()
@@ -150,9 +208,9 @@ def main():
     dom, rec = ranked[0]
     flops = kernel_work(dom, N, T, R)[1]
     achieved = flops / (rec["avg_ms"] * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if gemm == "fp32" else PEAK_16_TFLOPS
     roofline = {"bound": "mfma", "kernel": dom, "avg_ms": rec["avg_ms"], "achieved": achieved,
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": None}
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
 
     alg_flops_iter = 16.0 * N * R * T
     gflops = alg_flops_iter * value / 1e9
@@ -178,34 +236,33 @@ def main():
             dna.mu_iteration(V, Wc, Hc, with_cost=True)
         torch.cuda.synchronize()
         mu_cost_ms = 1e3 * (time.perf_counter() - tc) / nc
-        Wd, Hd = W0.clone(), H0.clone()
-        kls = dna.fit(V, Wd, Hd, args.dna_iters, method="dna", record_kl=True)
-        kls = kls.cpu().numpy()
-        hit = np.nonzero(kls <= kl_target)[0]
-        k_hit = int(hit[0]) if hit.size else None
-        target = {
-            "target_kl": kl_target, "mu_iters": args.mu_iters,
-            "mu_ms_per_iter_no_cost": 1e3 * mu_wall / args.mu_iters,
-            "mu_ms_per_iter_with_cost": mu_cost_ms,
-            "mu_time_to_target_s": mu_wall,
-            "dna_iters_to_target": k_hit,
-            "dna_time_to_target_s": (k_hit * ms_per_step / 1e3) if k_hit is not None else None,
-            "dna_kl_after_budget": float(kls[-1]), "dna_iter_budget": args.dna_iters,
-        }
-        if k_hit is not None:
-            target["speedup_vs_mu_no_cost"] = mu_wall / (k_hit * ms_per_step / 1e3) if k_hit else None
+        target = {"target_kl": kl_target, "mu_iters": args.mu_iters,
+                  "mu_ms_per_iter_no_cost": 1e3 * mu_wall / args.mu_iters,
+                  "mu_ms_per_iter_with_cost": mu_cost_ms, "mu_time_to_target_s": mu_wall,
+                  "dna_iter_budget": args.dna_iters}
+        forms = [gemm] + (["fp32"] if gemm != "fp32" else [])
+        for g in forms:
+            ms = ms_per_step if g == gemm else timed_steps(dna, V, W.clone(), H.clone(), 20, g)
+            k_hit, kl_last = iters_to_target(dna, V, W0, H0, kl_target, args.dna_iters, g)
+            rec = {"ms_per_iter": ms, "iters_to_target": k_hit,
+                   "time_to_target_s": (k_hit * ms / 1e3) if k_hit is not None else None,
+                   "kl_at_stop": kl_last}
+            if k_hit:
+                rec["speedup_vs_mu_no_cost"] = mu_wall / (k_hit * ms / 1e3)
+            target[f"dna_{g}"] = rec
 
     out = {
         "metric": METRIC, "value": value, "unit": "DNA iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[gemm],
+        "accumulate": "f32 products, f64 cost and selection sums",
         "data": "synthetic",
         "config": {"workload": f"DNA KL-NMF, N={N} T={T} R={R}, {WORKLOADS[args.config]}",
                    "N": N, "T": T, "R": R, "iteration": "H step, step 16, W step, step 29",
                    "parallelism": "single GPU"},
         "gpu_ms_per_step": gpu_ms / args.steps,
         "algorithmic_gflops": gflops,
-        "mfma_frac_algorithmic": gflops / 1e3 / PEAK_FP32_TFLOPS,
+        "mfma_frac_algorithmic": gflops / 1e3 / peak,
         "roofline": roofline,
         "kernels": kernels,
         "profiled_ms_per_step": 1e3 * prof_wall / args.steps,

@@ -48,7 +48,18 @@ typedef enum {
 } dna_status;
 
 /* Operand type of the matrix products (the accumulation is always float32 and
- * every cost sum is float64). */
+ * every cost sum is float64).  The 16-bit types apply to the three products of
+ * the DNA half-steps (Z = W H with its ratio epilogue, the gradient / Hessian
+ * products, the candidate-cost reconstructions) in dna_update_H/W,
+ * dna_gradient_hessian, dna_candidates and dna_select.  Inputs and outputs stay
+ * float32 in HBM; operands are rounded to 16 bits when staged.  BF16 rounds
+ * directly; FP16 first applies power-of-two scales (per rank component from the
+ * W column / H row maxima, per column or row of Q, Q - 1 and Q-bar from a max
+ * pass) that are undone in float32, so FP16 neither overflows nor flushes to
+ * zero where the fp32 values are normal.  The candidates, the selection sums
+ * and the update itself stay in float32 / float64.  dna_mu_update and
+ * dna_kl_cost ignore the field (float32 products); the unrolled adjoint returns
+ * DNA_EUNSUPPORTED for 16-bit types. */
 typedef enum {
   DNA_GEMM_FP32 = 0,
   DNA_GEMM_BF16 = 1,

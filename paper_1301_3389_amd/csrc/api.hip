@@ -13,6 +13,7 @@
 
 #include "../../include/dna.h"
 #include "kernels.hpp"
+#include "kernels_16.hpp"
 #include "kernels_adj.hpp"
 
 namespace dna {
@@ -87,7 +88,8 @@ static Split choose_split(int64_t K, int64_t base_tiles) {
   int64_t sp = std::max<int64_t>(1, cdiv(TARGET_WG, std::max<int64_t>(1, base_tiles)));
   sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / MIN_KCHUNK));
   sp = std::min<int64_t>(sp, 1024);
-  int64_t kchunk = cdiv(cdiv(K, sp), GEMM_BK) * GEMM_BK;
+  // multiple of 32: the K-tile of the 16-bit kernels (and two of the fp32 ones)
+  int64_t kchunk = cdiv(cdiv(K, sp), 32) * 32;
   Split s;
   s.kchunk = kchunk;
   s.splits = (int)cdiv(K, kchunk);
@@ -98,7 +100,7 @@ struct Layout {
   Split sh, sw;
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
-  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, vpart, cpart, fpart, check, total;
+  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, vpart, cpart, fpart, s16, check, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -131,6 +133,8 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R) {
   L.vpart = take(red * 8);
   L.cpart = take(std::max(3 * red, klt) * 8);
   L.fpart = take(red * 4);
+  const size_t mx = (size_t)std::max(N, T);
+  L.s16 = take(((size_t)R + 3 * mx) * 4 + 3 * (size_t)R * 4 + 6 * mx * 4);
   L.check = take(16);
   L.total = off;
   return L;
@@ -180,7 +184,6 @@ static dna_status check_opts(const dna_opts* o) {
   if (!(o->eps >= 0.f && o->eps <= 1.f)) return fail(DNA_EINVAL, "eps must lie in [0, 1]");
   if (!(o->alpha > 0.f) || !std::isfinite(o->alpha)) return fail(DNA_EINVAL, "alpha must be finite and > 0");
   if (o->gemm < DNA_GEMM_FP32 || o->gemm > DNA_GEMM_FP16) return fail(DNA_EINVAL, "unknown gemm type");
-  if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "16-bit products are not available in this entry point");
   return DNA_OK;
 }
 
@@ -233,6 +236,24 @@ static dna_status checked_end(int* chk, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Shared stages.
+// The 16-bit path reuses the Q / Q-bar buffers (16-bit Q and Q - 1 fit in the
+// fp32 Q buffer, 16-bit Q-bar in the fp32 one) and carves its scale buffers.
+static Scratch16 scratch16(void* ws, const Layout& L, int64_t N, int64_t T, int64_t R) {
+  Scratch16 S;
+  const size_t mx = (size_t)std::max(N, T);
+  S.q16 = at<char>(ws, L.q);
+  S.qb16 = at<char>(ws, L.qb);
+  char* b = at<char>(ws, L.s16);
+  S.bits = reinterpret_cast<unsigned*>(b);
+  b += ((size_t)R + 3 * mx) * 4;
+  S.rs = reinterpret_cast<float*>(b);
+  S.irs = S.rs + R;
+  S.irs2 = S.irs + R;
+  S.qs = S.irs2 + R;
+  S.iqs = S.qs + 3 * mx;
+  return S;
+}
+
 // ---------------------------------------------------------------------------
 // side 0: candidates for H (R x T) given W;  side 1: candidates for W (N x R) given H.
 static dna_status run_candidates(int side, const float* V, const float* W, const float* H, int64_t N,
@@ -247,16 +268,28 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
   double* c64 = at<double>(ws, L.c64);
   double* vpart = at<double>(ws, L.vpart);
   RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk, nullptr};
+  const bool p16 = o->gemm != DNA_GEMM_FP32;
+  const Scratch16 S = scratch16(ws, L, N, T, R);
   if (side == 0) {
     DNA_HIP(launch_colsum_W(W, N, R, at<double>(ws, L.sump), c64, c32, chk, s), "colsum_W");
-    DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
-    DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
+    if (p16) {
+      DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh.splits, L.sh.kchunk, pu, puc, py, vpart,
+                                chk, s), "ratio_gh16_H");
+    } else {
+      DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
+      DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
+    }
     DNA_HIP(launch_cand_H(H, pu, puc, py, L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps, o->alpha, Xmu, Xn,
                           Aout, Bout, s), "cand_H");
   } else {
     DNA_HIP(launch_rowsum_H(H, T, R, at<double>(ws, L.sump), c64, c32, chk, s), "rowsum_H");
-    DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
-    DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc, py, s), "gh_W");
+    if (p16) {
+      DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw.splits, L.sw.kchunk, pu, puc, py, vpart,
+                                chk, s), "ratio_gh16_W");
+    } else {
+      DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
+      DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc, py, s), "gh_W");
+    }
     DNA_HIP(launch_cand_W(W, pu, puc, py, L.sw.splits, c32, vpart, L.rt_n, N, R, o->eps, o->alpha, Xmu, Xn,
                           Aout, Bout, s), "cand_W");
   }
@@ -264,10 +297,19 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
 }
 
 static dna_status run_select(int side, const float* V, const float* F, const float* Xmu, const float* Xn,
-                             float* Xout, int64_t N, int64_t T, int64_t R, const Layout& L, void* ws,
-                             uint8_t* mask, double* dsel, double* margin, hipStream_t s) {
+                             float* Xout, int64_t N, int64_t T, int64_t R, const dna_opts* o, const Layout& L,
+                             void* ws, uint8_t* mask, double* dsel, double* margin, hipStream_t s) {
   double* cpart = at<double>(ws, L.cpart);
   int* fpart = at<int>(ws, L.fpart);
+  if (o->gemm != DNA_GEMM_FP32) {
+    DNA_HIP(launch_cost16(o->gemm, side, V, F, Xmu, Xn, N, T, R, scratch16(ws, L, N, T, R), cpart, fpart, s),
+            "cost16");
+    if (side == 0)
+      DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.ch_m, T, R, mask, dsel, margin, s), "select_H");
+    else
+      DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, L.cw_n, N, R, mask, dsel, margin, s), "select_W");
+    return DNA_OK;
+  }
   if (side == 0) {
     DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_H");
     DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.ch_m, T, R, mask, dsel, margin, s), "select_H");
@@ -351,7 +393,7 @@ dna_status dna_update_H(const float* V, const float* W, float* H, int64_t N, int
   float* Xmu = at<float>(ws, c.L.xmu);
   float* Xn = at<float>(ws, c.L.xn);
   DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s));
-  DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, c.L, ws, chose_newton, d_sel, margin, c.s));
+  DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, chose_newton, d_sel, margin, c.s));
   return epilogue(c);
 }
 
@@ -364,7 +406,7 @@ dna_status dna_update_W(const float* V, float* W, const float* H, int64_t N, int
   float* Xmu = at<float>(ws, c.L.xmu);
   float* Xn = at<float>(ws, c.L.xn);
   DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s));
-  DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, c.L, ws, chose_newton, d_sel, margin, c.s));
+  DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, chose_newton, d_sel, margin, c.s));
   return epilogue(c);
 }
 
@@ -443,7 +485,7 @@ dna_status dna_select(int side, const float* V, const float* F, const float* X_m
   DNA_TRY(check_ws(ws, ws_bytes, c.L.total));
   c.s = static_cast<hipStream_t>(stream);
   c.chk = nullptr;
-  DNA_TRY(run_select(side, V, F, X_mu, X_newton, X_out, N, T, R, c.L, ws, chose_newton, d_sel, margin, c.s));
+  DNA_TRY(run_select(side, V, F, X_mu, X_newton, X_out, N, T, R, o, c.L, ws, chose_newton, d_sel, margin, c.s));
   return DNA_OK;
 }
 
@@ -460,6 +502,7 @@ dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_ini
   if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
+  if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint runs in fp32 only");
   const AdjLayout A = make_adj_layout(N, T, R);
   DNA_TRY(check_ws(ws, ws_bytes, A.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -477,7 +520,7 @@ dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_ini
     const float* Hk = H_ckpt + (int64_t)k * RT;
     float* Hk1 = H_ckpt + (int64_t)(k + 1) * RT;
     DNA_TRY(run_candidates(0, V, W, Hk, N, T, R, o, A.base, ws, Xmu, Xn, nullptr, nullptr, chk, s));
-    DNA_TRY(run_select(0, V, W, Xmu, Xn, Hk1, N, T, R, A.base, ws, sel_ckpt + (int64_t)k * T, nullptr, nullptr, s));
+    DNA_TRY(run_select(0, V, W, Xmu, Xn, Hk1, N, T, R, o, A.base, ws, sel_ckpt + (int64_t)k * T, nullptr, nullptr, s));
   }
   if (chk) return checked_end(chk, s);
   return DNA_OK;
@@ -490,6 +533,7 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
   if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
+  if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint runs in fp32 only");
   const AdjLayout A = make_adj_layout(N, T, R);
   DNA_TRY(check_ws(ws, ws_bytes, A.total));
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "core.hpp"
+#include "epilogue.hpp"
 #include "kernels.hpp"
 
 namespace dna {
@@ -27,66 +28,6 @@ using GCH = Geo<CH_BM, CH_BN, GEMM_BK, 2, 2>;  // H-orientation cost (column red
 using GCW = Geo<CW_BM, CW_BN, GEMM_BK, 2, 2>;  // W-orientation cost (row reductions)
 using GH = Geo<GH_BM, GH_BN, GEMM_BK, 2, 2>;   // H orientation gradient, M = R, N = T, K = N
 using GW = Geo<GW_BM, GW_BN, GEMM_BK, 2, 2>;   // W orientation gradient, M = N, N = R, K = T
-
-// ---------------------------------------------------------------------------
-// Deterministic tile reductions of per-lane partials.
-// Column form: cp[q][j] holds this lane's partial for column (j, lane&31).
-// Row form:    rp[q][i][v] holds this lane's partial for row blk_row(v) of block i.
-// `red` is LDS scratch of NQ * max(WGM*BN, WGN*BM) doubles.
-// ---------------------------------------------------------------------------
-template <class G, int NQ, class OUT>
-__device__ __forceinline__ void reduce_cols(double (&cp)[NQ][G::FN], double* red, OUT&& out) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % G::WGM, wn = wave / G::WGM;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int j = 0; j < G::FN; ++j) {
-      const double s = cp[q][j] + __shfl_xor(cp[q][j], 32);
-      if (lane < 32) red[(q * G::WGM + wm) * G::BN + wn * G::WN + j * 32 + lane] = s;
-    }
-  __syncthreads();
-  for (int c = tid; c < G::BN; c += G::NT) {
-    double s[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      s[q] = 0.0;
-      for (int m = 0; m < G::WGM; ++m) s[q] += red[(q * G::WGM + m) * G::BN + c];
-    }
-    out(c, s);
-  }
-  __syncthreads();
-}
-
-template <class G, int NQ, class OUT>
-__device__ __forceinline__ void reduce_rows(double (&rp)[NQ][G::FM][16], double* red, OUT&& out) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % G::WGM, wn = wave / G::WGM;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i) {
-      const double y = halfwave_slot_sum(rp[q][i], lane);
-      if ((lane & 1) == 0) red[(q * G::WGN + wn) * G::BM + wm * G::WM + i * 32 + slot_row(lane)] = y;
-    }
-  __syncthreads();
-  for (int r = tid; r < G::BM; r += G::NT) {
-    double s[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      s[q] = 0.0;
-      for (int w = 0; w < G::WGN; ++w) s[q] += red[(q * G::WGN + w) * G::BM + r];
-    }
-    out(r, s);
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double xlogx_over(float v, float z) {
-  // v log(v/z) for v > 0, z > 0 (the summand of eq. 1 and steps 9/14); the ratio
-  // uses the hardware reciprocal (<= 1 ulp), the logarithm is the accurate one.
-  return (double)v * (double)logf(v * __builtin_amdgcn_rcpf(z));
-}
 
 // ---------------------------------------------------------------------------
 // k_ratio: Z = W H (MFMA, K = R) and its epilogue.
@@ -469,34 +410,6 @@ hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, cons
                      tiles_n, N, R, eps, alpha, Xmu, Xn, Aout, Bout);
   prof_end("cand_W", s);
   return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Fused candidate costs.  Per element with v > 0 and z_DNA, z_MU the two
-// reconstructions (z_MU = z_DNA + dZ):
-//   q0 += v log(v/z_DNA)          (d_DNA; rows with z_DNA <= 0 flag bit 1)
-//   q1 += -v log1p(dZ/z_DNA)      (d_MU - d_DNA; rows where both z > 0)
-//   q2 += v log(v/z_MU)           (rows with z_DNA <= 0 < z_MU; bit 2 if z_MU <= 0)
-// so that, absent flags, d_MU = q0 + q1 and margin = q1.
-// ---------------------------------------------------------------------------
-// Branch-free for the common case (both reconstructions positive or v = 0): the
-// logarithms take neutral arguments where a term must vanish.  Returns the flag
-// bits of this element.
-__device__ __forceinline__ int cost_acc(float x, float zN, float dz, double& s0, double& s1, double& s2) {
-  const float zM = zN + dz;
-  const bool pos = x > 0.f;
-  const bool okN = zN > 0.f, okM = zM > 0.f;
-  const float izN = __builtin_amdgcn_rcpf(zN);
-  const float l0 = logf((pos && okN) ? x * izN : 1.f);
-  const float l1 = log1pf((pos && okN && okM) ? dz * izN : 0.f);
-  s0 += (double)(x * l0);
-  s1 -= (double)(x * l1);
-  int fl = 0;
-  if (pos && !(okN && okM)) {            // a reconstruction vanished where v > 0
-    fl = (okN ? 0 : 1) | (okM ? 0 : 2);
-    if (!okN && okM) s2 += xlogx_over(x, zM);
-  }
-  return fl;
 }
 
 __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,

@@ -19,7 +19,10 @@ SELECT_TIE = 1e-12
 # Selection from an identical state (both sides form their own candidates, the
 # GPU in float32): decisions may differ only where the oracle's relative margin
 # is below this bound, which is the float32 resolution of the candidates
-# propagated to the cost (see the derivation in the design doc).
+# propagated to the cost: a relative perturbation of order 8 eps32 in each
+# candidate entry moves each column cost by a relative amount of the same
+# order, well below 1e-5, and the margin of two float32 costs cannot be
+# resolved below that.
 STATE_TIE = 1e-5
 
 
