@@ -270,11 +270,14 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
   RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk, nullptr};
   const bool p16 = o->gemm != DNA_GEMM_FP32;
   const Scratch16 S = scratch16(ws, L, N, T, R);
+  SumJob job;
   if (side == 0) {
-    DNA_HIP(launch_colsum_W(W, N, R, at<double>(ws, L.sump), c64, c32, chk, s), "colsum_W");
+    DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
+    job.s64 = c64; job.s32 = c32; job.check = chk;
+    ra.fin = job;                                   // c = W^t 1 finished inside the ratio pass
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh.splits, L.sh.kchunk, pu, puc, py, vpart,
-                                chk, s), "ratio_gh16_H");
+                                chk, job, s), "ratio_gh16_H");
     } else {
       DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
       DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
@@ -282,10 +285,12 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     DNA_HIP(launch_cand_H(H, pu, puc, py, L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps, o->alpha, Xmu, Xn,
                           Aout, Bout, s), "cand_H");
   } else {
-    DNA_HIP(launch_rowsum_H(H, T, R, at<double>(ws, L.sump), c64, c32, chk, s), "rowsum_H");
+    DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, s), "rowsum_H");
+    job.s64 = c64; job.s32 = c32; job.check = chk;
+    ra.fin = job;                                   // c' = H 1 finished inside the ratio pass
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw.splits, L.sw.kchunk, pu, puc, py, vpart,
-                                chk, s), "ratio_gh16_W");
+                                chk, job, s), "ratio_gh16_W");
     } else {
       DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
       DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc, py, s), "gh_W");
@@ -376,11 +381,12 @@ dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int
   if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
   Common c;
   DNA_TRY(prologue(nullptr, W, H, N, T, R, o, ws, ws_bytes, stream, c));
-  double* f = at<double>(ws, c.L.c64);
   double* sp = at<double>(ws, c.L.sump);
-  if (side == 0) DNA_HIP(launch_colsum_W(W, N, R, sp, f, nullptr, c.chk, c.s), "colsum_W");
-  else DNA_HIP(launch_rowsum_H(H, T, R, sp, f, nullptr, c.chk, c.s), "rowsum_H");
-  DNA_HIP(launch_scale(side, W, H, N, T, R, f, c.s), "scale");
+  SumJob job;
+  if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");
+  else DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");
+  job.check = c.chk;
+  DNA_HIP(launch_scale(side, W, H, N, T, R, job, c.s), "scale");
   return epilogue(c);
 }
 
@@ -423,13 +429,18 @@ dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, in
   float* c32 = at<float>(ws, L.c32);
   double* cpart = at<double>(ws, L.cpart);
   RatioArgs ra{V, W, H, N, T, R, Q, nullptr, nullptr, cpart, c.chk, nullptr};
+  SumJob job;
   if (side == 0) {
-    DNA_HIP(launch_colsum_W(W, N, R, at<double>(ws, L.sump), nullptr, c32, c.chk, c.s), "colsum_W");
+    DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
+    job.s32 = c32; job.check = c.chk;
+    ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_H_COST : RM_MU_H, ra, c.s), "ratio_mu_H");
     DNA_HIP(launch_gh_H(W, Q, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_H");
     DNA_HIP(launch_mu_H(H, pu, L.sh.splits, c32, T, R, cpart, L.rt_m, with_cost ? d_out : nullptr, c.s), "mu_H");
   } else {
-    DNA_HIP(launch_rowsum_H(H, T, R, at<double>(ws, L.sump), nullptr, c32, c.chk, c.s), "rowsum_H");
+    DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
+    job.s32 = c32; job.check = c.chk;
+    ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_W_COST : RM_MU_W, ra, c.s), "ratio_mu_W");
     DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_W");
     DNA_HIP(launch_mu_W(W, pu, L.sw.splits, c32, N, R, cpart, L.rt_n, with_cost ? d_out : nullptr, c.s), "mu_W");
@@ -563,7 +574,12 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
   double* cbar64 = at<double>(ws, A.cbar64);
   float* p0 = at<float>(ws, A.wp0);
   float* p1 = at<float>(ws, A.wp1);
-  DNA_HIP(launch_colsum_W(W, N, R, at<double>(ws, L.sump), nullptr, c32, nullptr, s), "colsum_W");
+  {
+    SumJob job;
+    DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
+    job.s32 = c32;
+    DNA_HIP(launch_sum_final(job, s), "sum_final");
+  }
   const float* Gin = dH_K;
   for (int k = K - 1; k >= 0; --k) {
     const float* Hk = H_ckpt + (int64_t)k * RT;
@@ -575,7 +591,12 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
     DNA_HIP(launch_cand_bwd_H(Hk, pu, puc, py, L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps, o->alpha,
                               sel_ckpt + (int64_t)k * T, Gin, Ub, Yb, Hd, Cb, sbar, s), "cand_bwd_H");
     DNA_HIP(launch_zbar(V, Z, W, Ub, Yb, sbar, N, T, R, Zbar, dV, acc, s), "zbar");
-    DNA_HIP(launch_rowsum_H(Cb, T, R, at<double>(ws, L.sump), cbar64, nullptr, nullptr, s), "rowsum cbar");
+    {
+      SumJob job;
+      DNA_HIP(launch_rowsum_part(Cb, T, R, at<double>(ws, L.sump), job, s), "rowsum cbar");
+      job.s64 = cbar64;
+      DNA_HIP(launch_sum_final(job, s), "sum_final cbar");
+    }
     DNA_HIP(launch_wbar(Q, Zbar, Qb, Ub, Hk, Yb, N, T, R, A.swb.splits, A.swb.kchunk, p0, p1, s), "wbar");
     DNA_HIP(launch_dw_final(W, p0, p1, A.swb.splits, cbar64, N, R, dW, acc, s), "dw_final");
     if (Gout) {

@@ -4,8 +4,26 @@
 #include <math.h>
 
 #include "core.hpp"
+#include "kernels.hpp"
 
 namespace dna {
+
+// ---------------------------------------------------------------------------
+// Second level of a factor sum (struct SumJob), spread over every block of the
+// grid that carries it: r-th sum = parts added in order p = 0, 1, ...
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sum_job(const SumJob& j) {
+  if (!j.part) return;
+  const int64_t nb = (int64_t)gridDim.x * gridDim.y * gridDim.z;
+  const int64_t lin = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  for (int64_t r = lin * blockDim.x + threadIdx.x; r < j.R; r += nb * blockDim.x) {
+    double tot = 0.0;
+    for (int p = 0; p < j.nparts; ++p) tot += j.part[(int64_t)p * j.R + r];
+    if (j.s64) j.s64[r] = tot;
+    if (j.s32) j.s32[r] = (float)tot;
+    if (j.check && !(tot > 0.0)) atomicOr(j.check, CHK_DOMAIN);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Deterministic tile reductions of per-lane partials.
@@ -61,17 +79,34 @@ __device__ __forceinline__ void reduce_rows(double (&rp)[NQ][G::FM][16], double*
   __syncthreads();
 }
 
-__device__ __forceinline__ double xlogx_over(float v, float z) {
-  // v log(v/z) for v > 0, z > 0 (the summand of eq. 1 and steps 9/14); the ratio
-  // uses the hardware reciprocal (<= 1 ulp), the logarithm is the accurate one.
-  return (double)v * (double)logf(v * __builtin_amdgcn_rcpf(z));
+// The cost terms use the hardware base-2 logarithm (v_log_f32, within 1 ulp
+// over the whole float range, including arguments near 1) and are summed in
+// base-2 units; LN2 converts a finished sum to natural units.
+constexpr double LN2 = 0.69314718055994530942;
+
+__device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
+
+// log2(1 + u) for u > -1, accurate for small |u|: with w = 1 + u rounded,
+// log2(w) * u / (w - 1) cancels the rounding of w to first order (Goldberg's
+// log1p construction); w == 1 takes the first series term.
+// u is clamped to FLT_MAX (an overflowed ratio still gives a finite, huge term).
+__device__ __forceinline__ float log2_1p(float u) {
+  u = fminf(u, 3.402823466e38f);
+  const float w = 1.f + u;
+  const float d = w - 1.f;
+  return (d == 0.f) ? u * 1.44269504088896341f : log2_hw(w) * (u * __builtin_amdgcn_rcpf(d));
 }
 
-// Per-element cost terms with v > 0 and z_DNA, z_MU the two reconstructions
-// (z_MU = z_DNA + dZ):
-//   s0 += v log(v/z_DNA)          (d_DNA; rows with z_DNA <= 0 flag bit 1)
-//   s1 += -v log1p(dZ/z_DNA)      (d_MU - d_DNA; rows where both z > 0)
-//   s2 += v log(v/z_MU)           (rows with z_DNA <= 0 < z_MU; bit 2 if z_MU <= 0)
+__device__ __forceinline__ double xlog2x_over(float v, float z) {
+  // v log2(v/z) for v > 0, z > 0 (the summand of eq. 1 and steps 9/14, base 2)
+  return (double)(v * log2_hw(v * __builtin_amdgcn_rcpf(z)));
+}
+
+// Per-element cost terms, in base-2 units, with v > 0 and z_DNA, z_MU the two
+// reconstructions (z_MU = z_DNA + dZ):
+//   s0 += v log2(v/z_DNA)         (d_DNA; rows with z_DNA <= 0 flag bit 1)
+//   s1 += -v log2(1 + dZ/z_DNA)   (d_MU - d_DNA; rows where both z > 0)
+//   s2 += v log2(v/z_MU)          (rows with z_DNA <= 0 < z_MU; bit 2 if z_MU <= 0)
 // so that, absent flags, d_MU = s0 + s1 and the margin is s1.
 // Branch-free for the common case (both reconstructions positive or v = 0): the
 // logarithms take neutral arguments where a term must vanish.  Returns the flag
@@ -81,16 +116,114 @@ __device__ __forceinline__ int cost_acc(float x, float zN, float dz, double& s0,
   const bool pos = x > 0.f;
   const bool okN = zN > 0.f, okM = zM > 0.f;
   const float izN = __builtin_amdgcn_rcpf(zN);
-  const float l0 = logf((pos && okN) ? x * izN : 1.f);
-  const float l1 = log1pf((pos && okN && okM) ? dz * izN : 0.f);
+  const float l0 = log2_hw((pos && okN) ? x * izN : 1.f);
+  const float l1 = log2_1p((pos && okN && okM) ? dz * izN : 0.f);
   s0 += (double)(x * l0);
   s1 -= (double)(x * l1);
   int fl = 0;
   if (pos && !(okN && okM)) {            // a reconstruction vanished where v > 0
     fl = (okN ? 0 : 1) | (okM ? 0 : 2);
-    if (!okN && okM) s2 += xlogx_over(x, zM);
+    if (!okN && okM) s2 += xlog2x_over(x, zM);
   }
   return fl;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues of the candidate-cost passes (steps 7-9, 12-14), shared by the fp32
+// and 16-bit kernels.  acc[..][0] holds z_DNA, acc[..][1] holds dZ = z_MU - z_DNA
+// at this lane's accumulator positions; vf holds v there.  Partials (natural
+// log units) go to part[q * stride + base + index], q = 0, 1, 2 for s0, s1, s2,
+// and the OR of the flags to fpart[base + index].
+// ---------------------------------------------------------------------------
+template <class G>
+__device__ __forceinline__ int64_t epi_row(int64_t m0, int i, int v) {
+  const int tid = threadIdx.x, lane = tid & 63, wm = (tid >> 6) % G::WGM;
+  return m0 + wm * G::WM + i * 32 + blk_row(v, lane);
+}
+template <class G>
+__device__ __forceinline__ int64_t epi_col(int64_t n0, int j) {
+  const int tid = threadIdx.x, lane = tid & 63, wn = (tid >> 6) / G::WGM;
+  return n0 + wn * G::WN + j * 32 + blk_col(lane);
+}
+
+// Column form (H orientation: one partial per column t of the tile).
+template <class G, int NC>
+__device__ __forceinline__ void cost_cols_acc(const float (&vf)[G::FM][G::FN][16],
+                                              const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
+                                              int64_t N, int64_t T, double (&cp)[3][G::FN], int* fl_s) {
+#pragma unroll
+  for (int j = 0; j < G::FN; ++j) {
+    const int64_t col = epi_col<G>(n0, j);
+    int fl = 0;
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float x = (epi_row<G>(m0, i, v) < N && col < T) ? vf[i][j][v] : 0.f;
+        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], cp[0][j], cp[1][j], cp[2][j]);
+      }
+    if (fl) atomicOr(&fl_s[col - n0], fl);
+  }
+}
+
+template <class G, int NC>
+__device__ __forceinline__ void cost_cols(const float (&vf)[G::FM][G::FN][16],
+                                          const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
+                                          int64_t N, int64_t T, double* red, int* fl_s, double* part, int* fpart,
+                                          int64_t base, int64_t stride) {
+  double cp[3][G::FN];
+#pragma unroll
+  for (int j = 0; j < G::FN; ++j) cp[0][j] = cp[1][j] = cp[2][j] = 0.0;
+  cost_cols_acc<G>(vf, acc, m0, n0, N, T, cp, fl_s);
+  reduce_cols<G, 3>(cp, red, [&](int c, const double (&s)[3]) {
+    if (n0 + c < T) {
+      part[base + n0 + c] = s[0] * LN2;
+      part[stride + base + n0 + c] = s[1] * LN2;
+      part[2 * stride + base + n0 + c] = s[2] * LN2;
+      fpart[base + n0 + c] = fl_s[c];
+    }
+  });
+}
+
+// Row form (W orientation: one partial per row n of the tile).
+template <class G, int NC>
+__device__ __forceinline__ void cost_rows_acc(const float (&vf)[G::FM][G::FN][16],
+                                              const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
+                                              int64_t N, int64_t T, double (&rp)[3][G::FM][16], int* fl_s) {
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = epi_row<G>(m0, i, v);
+      int fl = 0;
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+        const float x = (row < N && epi_col<G>(n0, j) < T) ? vf[i][j][v] : 0.f;
+        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], rp[0][i][v], rp[1][i][v], rp[2][i][v]);
+      }
+      if (fl) atomicOr(&fl_s[row - m0], fl);
+    }
+}
+
+template <class G, int NC>
+__device__ __forceinline__ void cost_rows(const float (&vf)[G::FM][G::FN][16],
+                                          const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
+                                          int64_t N, int64_t T, double* red, int* fl_s, double* part, int* fpart,
+                                          int64_t base, int64_t stride) {
+  double rp[3][G::FM][16];
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) rp[0][i][v] = rp[1][i][v] = rp[2][i][v] = 0.0;
+  cost_rows_acc<G>(vf, acc, m0, n0, N, T, rp, fl_s);
+  reduce_rows<G, 3>(rp, red, [&](int r, const double (&s)[3]) {
+    if (m0 + r < N) {
+      part[base + m0 + r] = s[0] * LN2;
+      part[stride + base + m0 + r] = s[1] * LN2;
+      part[2 * stride + base + m0 + r] = s[2] * LN2;
+      fpart[base + m0 + r] = fl_s[r];
+    }
+  });
 }
 
 }  // namespace dna

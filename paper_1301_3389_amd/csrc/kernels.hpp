@@ -49,6 +49,19 @@ enum RatioMode {
   RM_ADJ = 7       // Q, Q-bar, Z and column sums of V      (adjoint recompute)
 };
 
+// Second level of a column / row sum of a factor (see launch_colsum_part): the
+// parts are added in a fixed order into s64 / s32 (either may be nullptr), and
+// a sum <= 0 sets CHK_DOMAIN in *check (if not nullptr).  A kernel that receives
+// a SumJob with part != nullptr performs it on the side, before its own work.
+struct SumJob {
+  const double* part;
+  int nparts;
+  int64_t R;
+  double* s64;
+  float* s32;
+  int* check;
+};
+
 struct RatioArgs {
   const float* V; const float* W; const float* H;
   int64_t N, T, R;
@@ -57,6 +70,7 @@ struct RatioArgs {
   double* cpart;      // cost partials, same layouts; RM_KL: [tiles]
   int* check;         // nullptr unless checked
   float* Z;           // RM_ADJ only: Z = W H
+  SumJob fin;         // folded second level of the preceding factor sum (part = nullptr: none)
 };
 hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s);
 
@@ -103,16 +117,20 @@ hipError_t launch_mu_H(float* H, const float* pu, int splits, const float* c, in
 hipError_t launch_mu_W(float* W, const float* pu, int splits, const float* g, int64_t N, int64_t R,
                        const double* cpart, int tiles_n, double* d_out, hipStream_t s);
 
-// Column sums of W (R values) / row sums of H (R values), float64 and float32,
-// in two fixed-order levels through `part` (at most SUM_PARTS * R doubles).
-constexpr int SUM_PARTS = 256;
-hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* part, double* sum64, float* sum32,
-                           int* check, hipStream_t s);
-hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* part, double* sum64, float* sum32,
-                           int* check, hipStream_t s);
-// side 0: W[:,r] /= f_r, H[r,:] *= f_r;  side 1: H[r,:] /= f_r, W[:,r] *= f_r
-hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                        const double* f, hipStream_t s);
+// Column sums of W (R values) / row sums of H (R values) in two fixed-order
+// levels: the part kernels write float64 partials to `part` (at most SUM_PARTS *
+// R doubles) and return, in `job`, the second level (nparts, R; the caller sets
+// s64 / s32 / check), to be folded into a later kernel or run by
+// launch_sum_final.
+constexpr int SUM_PARTS = 32;
+hipError_t launch_colsum_part(const float* W, int64_t N, int64_t R, double* part, SumJob& job, hipStream_t s);
+hipError_t launch_rowsum_part(const float* H, int64_t T, int64_t R, double* part, SumJob& job, hipStream_t s);
+hipError_t launch_sum_final(const SumJob& job, hipStream_t s);
+// Steps 1 / 29 (side 0, f = column sums of W: W[:,r] /= f_r, H[r,:] *= f_r) and
+// step 16 (side 1, f = row sums of H: H[r,:] /= f_r, W[:,r] *= f_r), with the
+// second level of the sums (job) done per tile.
+hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
+                        hipStream_t s);
 
 hipError_t launch_kl_final(const double* cpart, int ntiles, double* out, hipStream_t s);
 

@@ -216,6 +216,7 @@ struct Ratio16Args {
   const float* qs[3];               // output scales of Q, Q - 1, Q-bar (nullptr = 1)
   unsigned* qmax[3];                // max pass: float bits of max |.| per column / row
   int* check;
+  SumJob fin;                       // folded second level of the factor sum (not in the max pass)
 };
 
 // SIDE 0: H step (column sums of V, scales per column t); SIDE 1: W step (rows n).
@@ -229,6 +230,7 @@ __global__ __launch_bounds__(G16R::NT) void k_ratio16(Ratio16Args a) {
   typedef PolZ<G, TE, 1, 1, SPLIT> P;
   __shared__ __align__(16) TE lds[P::LDS_ELEMS > 4 * G::BM * 8 ? P::LDS_ELEMS : 4 * G::BM * 8];
   const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
+  if (!MAXONLY) sum_job(a.fin);
   float vf[G::FM][G::FN][16];
 #pragma unroll
   for (int j = 0; j < G::FN; ++j) {
@@ -446,34 +448,8 @@ __global__ __launch_bounds__(G16CH::NT) void k_cost16_H(const float* V, Op16 W, 
   pol.m0 = m0;
   pol.n0 = n0;
   run16<G, P, TE>(pol, acc, 0, R, lds);
-  double cp[3][G::FN];
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int j = 0; j < G::FN; ++j) cp[q][j] = 0.0;
-#pragma unroll
-  for (int j = 0; j < G::FN; ++j) {
-    const int64_t col = col16<G>(n0, j);
-    int fl = 0;
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = row16<G>(m0, i, v);
-        const float x = (row < N && col < T) ? vf[i][j][v] : 0.f;
-        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], cp[0][j], cp[1][j], cp[2][j]);
-      }
-    if (fl) atomicOr(&fl_s[col - n0], fl);
-  }
   const int64_t base = (int64_t)blockIdx.y * T, stride = (int64_t)gridDim.y * T;
-  reduce_cols<G, 3>(cp, reinterpret_cast<double*>(lds), [&](int c, const double (&s)[3]) {
-    if (n0 + c < T) {
-      part[base + n0 + c] = s[0];
-      part[stride + base + n0 + c] = s[1];
-      part[2 * stride + base + n0 + c] = s[2];
-      fpart[base + n0 + c] = fl_s[c];
-    }
-  });
+  cost_cols<G>(vf, acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 template <typename TE>
@@ -504,36 +480,8 @@ __global__ __launch_bounds__(G16CW::NT) void k_cost16_W(const float* V, Op16 Wn,
   pol.m0 = m0;
   pol.n0 = n0;
   run16<G, P, TE>(pol, acc, 0, R, lds);
-  double rp[3][G::FM][16];
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) rp[q][i][v] = 0.0;
-#pragma unroll
-  for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = row16<G>(m0, i, v);
-      int fl = 0;
-#pragma unroll
-      for (int j = 0; j < G::FN; ++j) {
-        const int64_t col = col16<G>(n0, j);
-        const float x = (row < N && col < T) ? vf[i][j][v] : 0.f;
-        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], rp[0][i][v], rp[1][i][v], rp[2][i][v]);
-      }
-      if (fl) atomicOr(&fl_s[row - m0], fl);
-    }
   const int64_t base = (int64_t)blockIdx.x * N, stride = (int64_t)gridDim.x * N;
-  reduce_rows<G, 3>(rp, reinterpret_cast<double*>(lds), [&](int r, const double (&s)[3]) {
-    if (m0 + r < N) {
-      part[base + m0 + r] = s[0];
-      part[stride + base + m0 + r] = s[1];
-      part[2 * stride + base + m0 + r] = s[2];
-      fpart[base + m0 + r] = fl_s[r];
-    }
-  });
+  cost_rows<G>(vf, acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,7 +558,8 @@ static void rank_scales(int side, const float* W, const float* H, int64_t N, int
 template <typename TE>
 static hipError_t ratio_gh16(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T,
                              int64_t R, const Scratch16& S, bool scaled, int splits, int64_t kchunk, float* pu,
-                             float* puc, float* py, double* vpart, int* check, hipStream_t s) {
+                             float* puc, float* py, double* vpart, int* check, const SumJob& fin,
+                             hipStream_t s) {
   TE* Qp = reinterpret_cast<TE*>(S.q16);
   TE* Qc = Qp + N * T;
   TE* Qb = reinterpret_cast<TE*>(S.qb16);
@@ -629,7 +578,7 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
   const Op16 h = make_op16<float>(H, T, T, nullptr, side == 0 ? irs : rs);
   Ratio16Args ra;
   ra.V = V; ra.W = w; ra.H = h; ra.N = N; ra.T = T; ra.R = R;
-  ra.Q = Qp; ra.Qc = Qc; ra.Qb = Qb; ra.vpart = vpart; ra.check = check;
+  ra.Q = Qp; ra.Qc = Qc; ra.Qb = Qb; ra.vpart = vpart; ra.check = check; ra.fin = fin;
   for (int k = 0; k < 3; ++k) { ra.qs[k] = nullptr; ra.qmax[k] = nullptr; }
   dim3 rgrid((unsigned)cdiv(T, G16R::BN), (unsigned)cdiv(N, G16R::BM));
   if (scaled) {
@@ -717,10 +666,11 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
 
 hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W, const float* H, int64_t N,
                              int64_t T, int64_t R, const Scratch16& S, int splits, int64_t kchunk, float* pu,
-                             float* puc, float* py, double* vpart, int* check, hipStream_t s) {
+                             float* puc, float* py, double* vpart, int* check, const SumJob& fin,
+                             hipStream_t s) {
   if (gemm == 1)
-    return ratio_gh16<__bf16>(side, V, W, H, N, T, R, S, false, splits, kchunk, pu, puc, py, vpart, check, s);
-  return ratio_gh16<_Float16>(side, V, W, H, N, T, R, S, true, splits, kchunk, pu, puc, py, vpart, check, s);
+    return ratio_gh16<__bf16>(side, V, W, H, N, T, R, S, false, splits, kchunk, pu, puc, py, vpart, check, fin, s);
+  return ratio_gh16<_Float16>(side, V, W, H, N, T, R, S, true, splits, kchunk, pu, puc, py, vpart, check, fin, s);
 }
 
 hipError_t launch_cost16(int gemm, int side, const float* V, const float* F, const float* Xmu, const float* Xn,

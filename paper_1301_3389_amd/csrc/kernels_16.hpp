@@ -23,7 +23,8 @@ struct Scratch16 {
 // fp32 split partials of u, u_c, y that the fp32 candidate kernels consume.
 hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W, const float* H, int64_t N,
                              int64_t T, int64_t R, const Scratch16& S, int splits, int64_t kchunk, float* pu,
-                             float* puc, float* py, double* vpart, int* check, hipStream_t s);
+                             float* puc, float* py, double* vpart, int* check, const SumJob& fin,
+                             hipStream_t s);
 
 // Steps 7-9, 12-14 with 16-bit reconstruction products (float64 cost sums).
 hipError_t launch_cost16(int gemm, int side, const float* V, const float* F, const float* Xmu, const float* Xn,

@@ -28,6 +28,10 @@ using GCH = Geo<CH_BM, CH_BN, GEMM_BK, 2, 2>;  // H-orientation cost (column red
 using GCW = Geo<CW_BM, CW_BN, GEMM_BK, 2, 2>;  // W-orientation cost (row reductions)
 using GH = Geo<GH_BM, GH_BN, GEMM_BK, 2, 2>;   // H orientation gradient, M = R, N = T, K = N
 using GW = Geo<GW_BM, GW_BN, GEMM_BK, 2, 2>;   // W orientation gradient, M = N, N = R, K = T
+using GS = Geo<64, 64, GEMM_BK, 2, 2>;         // either gradient orientation when the grid is small
+// Below this many workgroups the gradient products switch to 64 x 64 tiles, so
+// that small problems still put two workgroups (eight waves) on every CU.
+constexpr int64_t GH_SMALL_GRID = 512;
 
 // ---------------------------------------------------------------------------
 // k_ratio: Z = W H (MFMA, K = R) and its epilogue.
@@ -40,6 +44,7 @@ struct RatioKArgs {
   double* vpart; double* cpart;
   int* check;
   float* Z;
+  SumJob fin;
 };
 
 template <int MODE>
@@ -48,6 +53,7 @@ __global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
   using TL = Tile<GZ, ProdSingle, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
+  sum_job(a.fin);
   float vf[GZ::FM][GZ::FN][16];
   TL::load_frag(vf, a.V, a.T, m0, n0, a.N, a.T);     // in flight during the K loop
   TL t;
@@ -91,7 +97,7 @@ __global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
           const float qb = pos ? q * iz : 0.f;
           bad |= (pos && !(z > 0.f)) ? 1 : 0;
           double term = 0.0;
-          if (COST || MODE == RM_KL) term = (double)(x * logf(pos ? q : 1.f));
+          if (COST || MODE == RM_KL) term = (double)(x * log2_hw(pos ? q : 1.f)) * LN2;
           if (WANT_Q) a.Q[row * T + col] = q;
           if (WANT_QB) a.Qb[row * T + col] = qb;
           if (WANT_Z) a.Z[row * T + col] = z;
@@ -136,6 +142,7 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
   k.H = make_opnd(a.H, a.T, a.T);
   k.N = a.N; k.T = a.T; k.R = a.R;
   k.Q = a.Q; k.Qb = a.Qb; k.vpart = a.vpart; k.cpart = a.cpart; k.check = a.check; k.Z = a.Z;
+  k.fin = a.fin;
   dim3 grid((unsigned)cdiv(a.T, GR::BN), (unsigned)cdiv(a.N, GR::BM));
   const char* nm = "ratio";
 #define DNA_RATIO_CASE(M, NAME)                                         \
@@ -168,12 +175,12 @@ struct GHOut {
   float* p[3];
 };
 
-template <class PR>
-__global__ __launch_bounds__(GH::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64_t N, int64_t T,
-                                                  int64_t R, int64_t kchunk, GHOut out) {
-  using TL = Tile<GH, PR, false, false>;
+template <class G, class PR>
+__global__ __launch_bounds__(G::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64_t N, int64_t T,
+                                                 int64_t R, int64_t kchunk, GHOut out) {
+  using TL = Tile<G, PR, false, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * GH::BM, n0 = (int64_t)blockIdx.x * GH::BN;
+  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
   const int64_t sp = blockIdx.z;
   const int64_t k0 = sp * kchunk, k1 = min(N, k0 + kchunk);
   TL t;
@@ -186,9 +193,9 @@ __global__ __launch_bounds__(GH::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64
     t.run(A, B, m0, n0, k0, k1, lds);
   }
 #pragma unroll
-  for (int i = 0; i < GH::FM; ++i)
+  for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < GH::FN; ++j) {
+    for (int j = 0; j < G::FN; ++j) {
       const int64_t col = TL::col_of(n0, j);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -204,29 +211,33 @@ __global__ __launch_bounds__(GH::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64
 hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t N, int64_t T,
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s) {
+  const bool small = cdiv(T, GH::BN) * cdiv(R, GH::BM) * splits < GH_SMALL_GRID;
   dim3 grid((unsigned)cdiv(T, GH::BN), (unsigned)cdiv(R, GH::BM), (unsigned)splits);
+  if (small) grid = dim3((unsigned)cdiv(T, GS::BN), (unsigned)cdiv(R, GS::BM), (unsigned)splits);
   const Opnd wt = make_opnd(W, R, R);     // element (r, n) at W[n*R + r]: MN-contiguous
   const Opnd q = make_opnd(Q, T, T);      // element (t, n) at Q[n*T + t]: MN-contiguous
   GHOut out = {{pu, puc, py}};
   if (Qb) {
     const Opnd qb = make_opnd(Qb, T, T);
     prof_begin("gh_H", s);
-    hipLaunchKernelGGL(k_gh_H<ProdGH3_H>, grid, dim3(GH::NT), 0, s, wt, q, qb, N, T, R, kchunk, out);
+    if (small) hipLaunchKernelGGL((k_gh_H<GS, ProdGH3_H>), grid, dim3(GS::NT), 0, s, wt, q, qb, N, T, R, kchunk, out);
+    else hipLaunchKernelGGL((k_gh_H<GH, ProdGH3_H>), grid, dim3(GH::NT), 0, s, wt, q, qb, N, T, R, kchunk, out);
     prof_end("gh_H", s);
   } else {
     prof_begin("gh_mu_H", s);
-    hipLaunchKernelGGL(k_gh_H<ProdSingle>, grid, dim3(GH::NT), 0, s, wt, q, q, N, T, R, kchunk, out);
+    if (small) hipLaunchKernelGGL((k_gh_H<GS, ProdSingle>), grid, dim3(GS::NT), 0, s, wt, q, q, N, T, R, kchunk, out);
+    else hipLaunchKernelGGL((k_gh_H<GH, ProdSingle>), grid, dim3(GH::NT), 0, s, wt, q, q, N, T, R, kchunk, out);
     prof_end("gh_mu_H", s);
   }
   return hipGetLastError();
 }
 
-template <class PR>
-__global__ __launch_bounds__(GW::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64_t N, int64_t T,
-                                                  int64_t R, int64_t kchunk, GHOut out) {
-  using TL = Tile<GW, PR, true, true>;
+template <class G, class PR>
+__global__ __launch_bounds__(G::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64_t N, int64_t T,
+                                                 int64_t R, int64_t kchunk, GHOut out) {
+  using TL = Tile<G, PR, true, true>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * GW::BM, n0 = (int64_t)blockIdx.x * GW::BN;
+  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
   const int64_t sp = blockIdx.z;
   const int64_t k0 = sp * kchunk, k1 = min(T, k0 + kchunk);
   TL t;
@@ -239,9 +250,9 @@ __global__ __launch_bounds__(GW::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64
     t.run(A, B, m0, n0, k0, k1, lds);
   }
 #pragma unroll
-  for (int i = 0; i < GW::FM; ++i)
+  for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < GW::FN; ++j) {
+    for (int j = 0; j < G::FN; ++j) {
       const int64_t col = TL::col_of(n0, j);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -257,18 +268,22 @@ __global__ __launch_bounds__(GW::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64
 hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t N, int64_t T,
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s) {
+  const bool small = cdiv(R, GW::BN) * cdiv(N, GW::BM) * splits < GH_SMALL_GRID;
   dim3 grid((unsigned)cdiv(R, GW::BN), (unsigned)cdiv(N, GW::BM), (unsigned)splits);
+  if (small) grid = dim3((unsigned)cdiv(R, GS::BN), (unsigned)cdiv(N, GS::BM), (unsigned)splits);
   const Opnd q = make_opnd(Q, T, N);      // element (n, t) at Q[n*T + t]: K-contiguous
   const Opnd ht = make_opnd(H, T, R);     // element (r, t) at H[r*T + t]: K-contiguous
   GHOut out = {{pu, puc, py}};
   if (Qb) {
     const Opnd qb = make_opnd(Qb, T, N);
     prof_begin("gh_W", s);
-    hipLaunchKernelGGL(k_gh_W<ProdGH3_W>, grid, dim3(GW::NT), 0, s, q, qb, ht, N, T, R, kchunk, out);
+    if (small) hipLaunchKernelGGL((k_gh_W<GS, ProdGH3_W>), grid, dim3(GS::NT), 0, s, q, qb, ht, N, T, R, kchunk, out);
+    else hipLaunchKernelGGL((k_gh_W<GW, ProdGH3_W>), grid, dim3(GW::NT), 0, s, q, qb, ht, N, T, R, kchunk, out);
     prof_end("gh_W", s);
   } else {
     prof_begin("gh_mu_W", s);
-    hipLaunchKernelGGL(k_gh_W<ProdSingle>, grid, dim3(GW::NT), 0, s, q, q, ht, N, T, R, kchunk, out);
+    if (small) hipLaunchKernelGGL((k_gh_W<GS, ProdSingle>), grid, dim3(GS::NT), 0, s, q, q, ht, N, T, R, kchunk, out);
+    else hipLaunchKernelGGL((k_gh_W<GW, ProdSingle>), grid, dim3(GW::NT), 0, s, q, q, ht, N, T, R, kchunk, out);
     prof_end("gh_mu_W", s);
   }
   return hipGetLastError();
@@ -430,35 +445,8 @@ __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd
     const Opnd B[2] = {Hn, Hd};
     t.run(A, B, m0, n0, 0, R, lds);
   }
-  double cp[3][GZ::FN];
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int j = 0; j < GZ::FN; ++j) cp[q][j] = 0.0;
-#pragma unroll
-  for (int j = 0; j < GZ::FN; ++j) {
-    const int64_t col = TL::col_of(n0, j);
-    int fl = 0;
-#pragma unroll
-    for (int i = 0; i < GZ::FM; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = TL::row_of(m0, i, v);
-        const float x = (row < N && col < T) ? vf[i][j][v] : 0.f;
-        fl |= cost_acc(x, t.acc[i][j][0][v], t.acc[i][j][1][v], cp[0][j], cp[1][j], cp[2][j]);
-      }
-    if (fl) atomicOr(&fl_s[col - n0], fl);
-  }
-  const int64_t L = T, base = (int64_t)blockIdx.y * T;
-  const int64_t stride = (int64_t)gridDim.y * T;
-  reduce_cols<GZ, 3>(cp, reinterpret_cast<double*>(lds), [&](int c, const double (&s)[3]) {
-    if (n0 + c < L) {
-      part[base + n0 + c] = s[0];
-      part[stride + base + n0 + c] = s[1];
-      part[2 * stride + base + n0 + c] = s[2];
-      fpart[base + n0 + c] = fl_s[c];
-    }
-  });
+  const int64_t base = (int64_t)blockIdx.y * T, stride = (int64_t)gridDim.y * T;
+  cost_cols<GZ>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn, int64_t N,
@@ -490,37 +478,8 @@ __global__ __launch_bounds__(GCW::NT) void k_cost_W(const float* V, Opnd Wn, Opn
     const Opnd B[1] = {H};
     t.run(A, B, m0, n0, 0, R, lds);
   }
-  double rp[3][GCW::FM][16];
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int i = 0; i < GCW::FM; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) rp[q][i][v] = 0.0;
-#pragma unroll
-  for (int i = 0; i < GCW::FM; ++i)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = TL::row_of(m0, i, v);
-      int fl = 0;
-#pragma unroll
-      for (int j = 0; j < GCW::FN; ++j) {
-        const int64_t col = TL::col_of(n0, j);
-        const float x = (row < N && col < T) ? vf[i][j][v] : 0.f;
-        fl |= cost_acc(x, t.acc[i][j][0][v], t.acc[i][j][1][v], rp[0][i][v], rp[1][i][v], rp[2][i][v]);
-      }
-      if (fl) atomicOr(&fl_s[row - m0], fl);
-    }
-  const int64_t base = (int64_t)blockIdx.x * N;
-  const int64_t stride = (int64_t)gridDim.x * N;
-  reduce_rows<GCW, 3>(rp, reinterpret_cast<double*>(lds), [&](int r, const double (&s)[3]) {
-    if (m0 + r < N) {
-      part[base + m0 + r] = s[0];
-      part[stride + base + m0 + r] = s[1];
-      part[2 * stride + base + m0 + r] = s[2];
-      fpart[base + m0 + r] = fl_s[r];
-    }
-  });
+  const int64_t base = (int64_t)blockIdx.x * N, stride = (int64_t)gridDim.x * N;
+  cost_rows<GCW>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const float* Xn, int64_t N,
@@ -701,7 +660,7 @@ hipError_t launch_mu_W(float* W, const float* pu, int splits, const float* g, in
 // ---------------------------------------------------------------------------
 // Column sums of W (N x R) and row sums of H (R x T), each in two fixed-order
 // levels: `nparts` blocks per column / row write partial float64 sums to
-// part[p][r], then one thread per r adds the parts in order.
+// part[p][r]; the second level adds the parts in order (sum_job).
 __global__ __launch_bounds__(256) void k_colsum_part(const float* W, int64_t N, int64_t R, int64_t rows,
                                                      double* part) {
   __shared__ double red[4][64];
@@ -731,67 +690,92 @@ __global__ __launch_bounds__(256) void k_rowsum_part(const float* H, int64_t T, 
   if (tid == 0) part[p * R + r] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ __launch_bounds__(256) void k_sum_final(const double* part, int nparts, int64_t R, double* s64,
-                                                   float* s32, int* check) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= R) return;
-  double tot = 0.0;
-  for (int p = 0; p < nparts; ++p) tot += part[(int64_t)p * R + r];
-  if (s64) s64[r] = tot;
-  if (s32) s32[r] = (float)tot;
-  if (check && !(tot > 0.0)) atomicOr(check, CHK_DOMAIN);
-}
+__global__ __launch_bounds__(256) void k_sum_final(SumJob j) { sum_job(j); }
 
-hipError_t launch_colsum_W(const float* W, int64_t N, int64_t R, double* part, double* sum64, float* sum32,
-                           int* check, hipStream_t s) {
+hipError_t launch_colsum_part(const float* W, int64_t N, int64_t R, double* part, SumJob& job, hipStream_t s) {
   const int64_t nparts = std::min<int64_t>(SUM_PARTS, cdiv(N, 64));
   const int64_t rows = cdiv(N, nparts);
   prof_begin("colsum_W", s);
   hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)cdiv(R, 64), (unsigned)nparts), dim3(256), 0, s, W, N, R,
                      rows, part);
   prof_end("colsum_W", s);
-  prof_begin("sum_final", s);
-  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)cdiv(R, 256)), dim3(256), 0, s, part, (int)nparts, R, sum64,
-                     sum32, check);
-  prof_end("sum_final", s);
+  job = SumJob{part, (int)nparts, R, nullptr, nullptr, nullptr};
   return hipGetLastError();
 }
 
-hipError_t launch_rowsum_H(const float* H, int64_t T, int64_t R, double* part, double* sum64, float* sum32,
-                           int* check, hipStream_t s) {
+hipError_t launch_rowsum_part(const float* H, int64_t T, int64_t R, double* part, SumJob& job, hipStream_t s) {
   const int64_t nparts = std::min<int64_t>(SUM_PARTS, cdiv(T, 2048));
   const int64_t cols = cdiv(T, nparts);
   prof_begin("rowsum_H", s);
   hipLaunchKernelGGL(k_rowsum_part, dim3((unsigned)nparts, (unsigned)R), dim3(256), 0, s, H, T, R, cols, part);
   prof_end("rowsum_H", s);
+  job = SumJob{part, (int)nparts, R, nullptr, nullptr, nullptr};
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
   prof_begin("sum_final", s);
-  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)cdiv(R, 256)), dim3(256), 0, s, part, (int)nparts, R, sum64,
-                     sum32, check);
+  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)cdiv(job.R, 256)), dim3(256), 0, s, job);
   prof_end("sum_final", s);
   return hipGetLastError();
 }
 
+// Normalisation with the second level of the sums done per tile: blocks
+// [0, wtiles) scale 64 x 64 tiles of W (64 columns r, each block summing the
+// parts of its 64 factors into LDS); the remaining blocks scale SC_TCHUNK
+// entries of one row r of H.  Multiplying by the float64 reciprocal of f
+// rounds like dividing except in double-rounding ties.
+constexpr int SC_TCHUNK = 2048;
 __global__ __launch_bounds__(256) void k_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                                               const double* f) {
-  const int64_t nw = N * R, total = nw + R * T;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    if (e < nw) {
-      const double fr = f[e % R];
-      if (fr > 0.0) W[e] = (float)(side == 0 ? (double)W[e] / fr : (double)W[e] * fr);
-    } else {
-      const int64_t h = e - nw;
-      const double fr = f[h / T];
-      if (fr > 0.0) H[h] = (float)(side == 0 ? (double)H[h] * fr : (double)H[h] / fr);
+                                               SumJob j, int64_t rtiles, int64_t wtiles, int64_t tchunks) {
+  __shared__ double fs[64];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  if (b < wtiles) {
+    const int64_t rt = b % rtiles, nt = b / rtiles;
+    if (tid < 64) {
+      const int64_t r = rt * 64 + tid;
+      double f = 0.0;
+      if (r < R) {
+        for (int p = 0; p < j.nparts; ++p) f += j.part[(int64_t)p * R + r];
+        if (j.check && !(f > 0.0)) atomicOr(j.check, CHK_DOMAIN);
+      }
+      fs[tid] = f;
     }
+    __syncthreads();
+#pragma unroll 4
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int64_t n = nt * 64 + e / 64, r = rt * 64 + (e & 63);
+      const double f = fs[e & 63];
+      if (n < N && r < R && f > 0.0) {
+        float& w = W[n * R + r];
+        w = (float)(side == 0 ? (double)w * (1.0 / f) : (double)w * f);
+      }
+    }
+  } else {
+    const int64_t hb = b - wtiles;
+    const int64_t r = hb / tchunks, t0 = (hb % tchunks) * SC_TCHUNK;
+    if (tid == 0) {
+      double f = 0.0;
+      for (int p = 0; p < j.nparts; ++p) f += j.part[(int64_t)p * R + r];
+      fs[0] = f;
+    }
+    __syncthreads();
+    const double f = fs[0];
+    if (!(f > 0.0)) return;
+    const double m = side == 0 ? f : 1.0 / f;
+    const int64_t t1 = std::min<int64_t>(T, t0 + SC_TCHUNK);
+    for (int64_t t = t0 + tid; t < t1; t += 256) H[r * T + t] = (float)((double)H[r * T + t] * m);
   }
 }
 
-hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const double* f,
+hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
                         hipStream_t s) {
-  const int64_t total = N * R + R * T;
-  const unsigned blocks = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
+  const int64_t rtiles = cdiv(R, 64), wtiles = rtiles * cdiv(N, 64), tchunks = cdiv(T, SC_TCHUNK);
+  const int64_t blocks = wtiles + R * tchunks;
   prof_begin("scale", s);
-  hipLaunchKernelGGL(k_scale, dim3(blocks), dim3(256), 0, s, side, W, H, N, T, R, f);
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, rtiles, wtiles,
+                     tchunks);
   prof_end("scale", s);
   return hipGetLastError();
 }
