@@ -97,7 +97,8 @@ static Split choose_split(int64_t K, int64_t base_tiles) {
 }
 
 struct Layout {
-  Split sh, sw;
+  Split sh, sw;              // split-K of the fp32 gradient products (H / W orientation)
+  Split sh16, sw16;          // the same for the 16-bit products (128 x 128 tiles)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
   size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, vpart, cpart, fpart, s16, check, total;
@@ -105,16 +106,19 @@ struct Layout {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-static Layout make_layout(int64_t N, int64_t T, int64_t R) {
+static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   Layout L;
   L.sh = choose_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM));
   L.sw = choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM));
+  L.sh16 = choose_split(N, cdiv(T, 128) * cdiv(R, 128));
+  L.sw16 = choose_split(T, cdiv(R, 128) * cdiv(N, 128));
   L.rt_m = (int)cdiv(N, RT_BM);
   L.rt_n = (int)cdiv(T, RT_BN);
   L.ch_m = (int)cdiv(N, CH_BM);
   L.cw_n = (int)cdiv(T, CW_BN);
   const size_t nt = (size_t)N * T, fac = (size_t)std::max(R * T, N * R);
-  const size_t psplit = (size_t)std::max<int64_t>((int64_t)L.sh.splits * R * T, (int64_t)L.sw.splits * N * R);
+  const int64_t sph = std::max(L.sh.splits, L.sh16.splits), spw = std::max(L.sw.splits, L.sw16.splits);
+  const size_t psplit = (size_t)std::max<int64_t>(sph * R * T, spw * N * R);
   const size_t red = (size_t)std::max(std::max<int64_t>((int64_t)L.rt_m * T, (int64_t)L.rt_n * N),
                                       std::max<int64_t>((int64_t)L.ch_m * T, (int64_t)L.cw_n * N));
   const size_t klt = (size_t)L.rt_m * L.rt_n;
@@ -133,8 +137,7 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R) {
   L.vpart = take(red * 8);
   L.cpart = take(std::max(3 * red, klt) * 8);
   L.fpart = take(red * 4);
-  const size_t mx = (size_t)std::max(N, T);
-  L.s16 = take(((size_t)R + 3 * mx) * 4 + 3 * (size_t)R * 4 + 6 * mx * 4);
+  L.s16 = take(with16 ? scratch16_bytes(N, T, R) : 0);
   L.check = take(16);
   L.total = off;
   return L;
@@ -150,7 +153,7 @@ struct AdjLayout {
 
 static AdjLayout make_adj_layout(int64_t N, int64_t T, int64_t R) {
   AdjLayout A;
-  A.base = make_layout(N, T, R);
+  A.base = make_layout(N, T, R, false);
   A.swb = choose_split(T, cdiv(R, WB_BN) * cdiv(N, WB_BM));
   size_t off = A.base.total;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -239,19 +242,7 @@ static dna_status checked_end(int* chk, hipStream_t s) {
 // The 16-bit path reuses the Q / Q-bar buffers (16-bit Q and Q - 1 fit in the
 // fp32 Q buffer, 16-bit Q-bar in the fp32 one) and carves its scale buffers.
 static Scratch16 scratch16(void* ws, const Layout& L, int64_t N, int64_t T, int64_t R) {
-  Scratch16 S;
-  const size_t mx = (size_t)std::max(N, T);
-  S.q16 = at<char>(ws, L.q);
-  S.qb16 = at<char>(ws, L.qb);
-  char* b = at<char>(ws, L.s16);
-  S.bits = reinterpret_cast<unsigned*>(b);
-  b += ((size_t)R + 3 * mx) * 4;
-  S.rs = reinterpret_cast<float*>(b);
-  S.irs = S.rs + R;
-  S.irs2 = S.irs + R;
-  S.qs = S.irs2 + R;
-  S.iqs = S.qs + 3 * mx;
-  return S;
+  return scratch16_carve(at<char>(ws, L.s16), N, T, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -276,27 +267,30 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     job.s64 = c64; job.s32 = c32; job.check = chk;
     ra.fin = job;                                   // c = W^t 1 finished inside the ratio pass
     if (p16) {
-      DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh.splits, L.sh.kchunk, pu, puc, py, vpart,
-                                chk, job, s), "ratio_gh16_H");
+      DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh16.splits, L.sh16.kchunk, pu, puc, py,
+                                vpart, chk, job, s), "ratio_gh16_H");
     } else {
       DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
       DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
     }
-    DNA_HIP(launch_cand_H(H, pu, puc, py, L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps, o->alpha, Xmu, Xn,
-                          Aout, Bout, s), "cand_H");
+    // the 16-bit Z pass tiles N by 128 like the fp32 one (RT_BM)
+    DNA_HIP(launch_cand_H(H, pu, puc, py, p16 ? L.sh16.splits : L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps,
+                          o->alpha, Xmu, Xn, Aout, Bout, s), "cand_H");
   } else {
     DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, s), "rowsum_H");
     job.s64 = c64; job.s32 = c32; job.check = chk;
     ra.fin = job;                                   // c' = H 1 finished inside the ratio pass
     if (p16) {
-      DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw.splits, L.sw.kchunk, pu, puc, py, vpart,
-                                chk, job, s), "ratio_gh16_W");
+      DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw16.splits, L.sw16.kchunk, pu, puc, py,
+                                vpart, chk, job, s), "ratio_gh16_W");
     } else {
       DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
       DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc, py, s), "gh_W");
     }
-    DNA_HIP(launch_cand_W(W, pu, puc, py, L.sw.splits, c32, vpart, L.rt_n, N, R, o->eps, o->alpha, Xmu, Xn,
-                          Aout, Bout, s), "cand_W");
+    // the 16-bit Z pass tiles T by 128, the fp32 one by RT_BN
+    DNA_HIP(launch_cand_W(W, pu, puc, py, p16 ? L.sw16.splits : L.sw.splits, c32, vpart,
+                          p16 ? (int)cdiv(T, 128) : L.rt_n, N, R, o->eps, o->alpha, Xmu, Xn, Aout, Bout, s),
+            "cand_W");
   }
   return DNA_OK;
 }
@@ -335,7 +329,7 @@ static dna_status prologue(const float* V, const float* W, const float* H, int64
                            const dna_opts* o, void* ws, size_t ws_bytes, void* stream, Common& c) {
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
-  c.L = make_layout(N, T, R);
+  c.L = make_layout(N, T, R, o->gemm != DNA_GEMM_FP32);
   DNA_TRY(check_ws(ws, ws_bytes, c.L.total));
   c.s = static_cast<hipStream_t>(stream);
   c.chk = o->checked ? at<int>(ws, c.L.check) : nullptr;
@@ -372,7 +366,7 @@ void dna_default_opts(dna_opts* o) {
 size_t dna_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* o) {
   (void)o;
   if (N <= 0 || T <= 0 || R <= 0) return 0;
-  return make_layout(N, T, R).total;
+  return make_layout(N, T, R, o->gemm != DNA_GEMM_FP32).total;
 }
 
 dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const dna_opts* o,
@@ -492,7 +486,7 @@ dna_status dna_select(int side, const float* V, const float* F, const float* X_m
   Common c;
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
-  c.L = make_layout(N, T, R);
+  c.L = make_layout(N, T, R, o->gemm != DNA_GEMM_FP32);
   DNA_TRY(check_ws(ws, ws_bytes, c.L.total));
   c.s = static_cast<hipStream_t>(stream);
   c.chk = nullptr;

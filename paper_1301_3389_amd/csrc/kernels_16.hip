@@ -1,14 +1,25 @@
-// kernels_16.hip -- the precision form: the five products of a DNA half-step
-// (Z, the gradient/Hessian pair, the two candidate reconstructions) with bf16 or
-// fp16 MFMA operands and fp32 accumulation; Q, Q - 1 and Q-bar handed between
-// kernels in 16-bit.  Candidates, costs (float64 sums) and selection are the
-// fp32 path's.  fp16 needs power-of-two scales to stay in range:
-//   * rank scales: W columns scaled to max 1 (and H rows by the inverse) inside
-//     the Z-type products, where they cancel exactly; in the gradient products
-//     the scale of W^t (H^t) is folded out of the result;
+// kernels_16.hip -- the precision form: the products of a DNA half-step (Z, the
+// gradient/Hessian sums, the two candidate reconstructions) with bf16 or fp16
+// MFMA operands and fp32 accumulation.  Candidates, costs (float64 sums) and
+// selection are the fp32 path's.
+//
+// Each half-step first converts its fp32 factors into zero-padded, K-contiguous
+// 16-bit operands (k_conv16), so that every product runs the bounds-free engine
+// of core16.hpp.  The Z pass writes Q, Q - 1 and Q-bar in 16 bits, transposed
+// in the H step (the gradient products there contract over n).
+//
+// The factor being updated (H in the H step, W in the W step) enters Z as a
+// two-term split hi + lo (BF16: both factors): with a single rounding the
+// gradient would be taken a relative 16-bit rounding away from the point the
+// step is applied to, an error that does not shrink as the fit converges.
+//
+// fp16 needs power-of-two scales to stay in range:
+//   * rank scales: W columns scaled to max 1 (H rows by the inverse) where they
+//     cancel in the Z-type products; in the gradient products the scale of the
+//     fixed factor is folded out of the result;
 //   * Q, Q - 1, Q-bar scaled per column (H step) / per row (W step) so that each
-//     column's (row's) maximum is 2^13, from a max pass over the same Z tiles,
-//     and folded out of the gradient sums.
+//     column's (row's) maximum lies in [2^12, 2^13), from a max pass over the
+//     same Z tiles, and folded out of the gradient sums.
 // bf16 keeps fp32's exponent range and uses no scales.
 #include <math.h>
 
@@ -21,197 +32,126 @@
 
 namespace dna {
 
-constexpr int BK16 = 32;
-using G16R = Geo16<RT_BM, RT_BN, BK16, 2, 2>;    // ratio / max pass: M = N, N = T, K = R
-using G16CH = Geo16<CH_BM, CH_BN, BK16, 2, 2>;   // H-orientation cost
-using G16CW = Geo16<CW_BM, CW_BN, BK16, 2, 2>;   // W-orientation cost
-using G16H = Geo16<GH_BM, GH_BN, BK16, 2, 2>;    // H-orientation gradient: M = R, N = T, K = N
-using G16W = Geo16<GW_BM, GW_BN, BK16, 2, 2>;    // W-orientation gradient: M = N, N = R, K = T
+using G128 = G16<128, 128>;
 
 // ---------------------------------------------------------------------------
-// Policies: which global sources are staged into which LDS tiles, and the
-// products formed from them.
+// Workspace.
 // ---------------------------------------------------------------------------
-
-// Z-type products (K = R).  A sources are K-major fp32 (W or W candidates), B
-// sources MN-major fp32 (H or H candidates).  NA_ x NB_ sources; products:
-//   NA = NB = 1: C0 = A0 B0
-//   NA = 1, NB = 2: C0 = A0 B0, C1 = A0 B1
-//   NA = 2, NB = 1: C0 = A0 B0, C1 = A1 B0
-// SPLIT (NA = NB = 1 only): bit 0 stages B as hi + lo 16-bit parts, bit 1 does
-// the same for A, and the product adds the cross terms A_hi B_lo / A_lo B_hi, so
-// that the split operand enters with about twice the 16-bit precision.
-template <class G, typename TE, int NA_, int NB_, int SPLIT = 0>
-struct PolZ {
-  static_assert(SPLIT == 0 || (NA_ == 1 && NB_ == 1), "split operands only in the single product");
-  static constexpr bool SA = (SPLIT & 2) != 0, SB = (SPLIT & 1) != 0;
-  static constexpr int NC = (NA_ > NB_) ? NA_ : NB_;
-  static constexpr int TA = G::BM * G::PITCH, TB = G::BN * G::PITCH;
-  static constexpr int LA = NA_ + (SA ? 1 : 0), LB = NB_ + (SB ? 1 : 0);   // LDS tiles per side
-  static constexpr int LDS_ELEMS = LA * TA + LB * TB;
-  typedef typename MF<TE>::v8 V8;
-  Stage16<G::BM, G::BK, G::NT, float, TE, true> sa[NA_];
-  Stage16<G::BN, G::BK, G::NT, float, TE, false> sb[NB_];
-  Op16 A[NA_], B[NB_];
-  int64_t m0, n0;
-
-  __device__ __forceinline__ void load(int64_t k0, int64_t k_end, int tid) {
-#pragma unroll
-    for (int a = 0; a < NA_; ++a) sa[a].load(A[a], m0, k0, k_end, tid);
-#pragma unroll
-    for (int b = 0; b < NB_; ++b) sb[b].load(B[b], n0, k0, k_end, tid);
-  }
-  __device__ __forceinline__ void store(TE* lds, int64_t k0, int64_t k_end, int tid) {
-#pragma unroll
-    for (int a = 0; a < NA_; ++a) sa[a].template store<XF_ID>(lds + a * TA, A[a], m0, k0, k_end, tid);
-    if (SA) sa[0].template store<XF_LO>(lds + NA_ * TA, A[0], m0, k0, k_end, tid);
-#pragma unroll
-    for (int b = 0; b < NB_; ++b) sb[b].template store<XF_ID>(lds + LA * TA + b * TB, B[b], n0, k0, k_end, tid);
-    if (SB) sb[0].template store<XF_LO>(lds + LA * TA + NB_ * TB, B[0], n0, k0, k_end, tid);
-  }
-  __device__ __forceinline__ void compute(const TE* lds, f32x16 (&acc)[G::FM][G::FN][NC], int lane, int wm, int wn) {
-#pragma unroll
-    for (int kk = 0; kk < G::BK / 16; ++kk) {
-      V8 a[LA][G::FM], b[LB][G::FN];
-#pragma unroll
-      for (int x = 0; x < LA; ++x)
-#pragma unroll
-        for (int i = 0; i < G::FM; ++i)
-          a[x][i] = frag16<TE>(lds + x * TA, G::PITCH, wm * G::WM + i * 32 + (lane & 31), kk, lane);
-#pragma unroll
-      for (int y = 0; y < LB; ++y)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          b[y][j] = frag16<TE>(lds + LA * TA + y * TB, G::PITCH, wn * G::WN + j * 32 + (lane & 31), kk, lane);
-#pragma unroll
-      for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j) {
-          if (SPLIT) {
-            // small cross terms first, then the hi x hi product
-            if (SB) acc[i][j][0] = MF<TE>::mma(a[0][i], b[1][j], acc[i][j][0]);
-            if (SA) acc[i][j][0] = MF<TE>::mma(a[1][i], b[0][j], acc[i][j][0]);
-            acc[i][j][0] = MF<TE>::mma(a[0][i], b[0][j], acc[i][j][0]);
-          } else {
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-              acc[i][j][c] = MF<TE>::mma(a[NA_ > 1 ? c : 0][i], b[NB_ > 1 ? c : 0][j], acc[i][j][c]);
-          }
-        }
-    }
-  }
+struct Off16 {
+  size_t fa_hi, fa_lo, fb_hi, fb_lo, g0, g1, x0, x1, q3, bits, rs, irs, irs2, qs, iqs, total;
 };
 
-// H-orientation gradient (M = R, N = T, K = N).  Sources: W (fp32, element
-// (r, n) MN-contiguous) staged as w and w^2; Q, Q - 1, Q-bar (16-bit, element
-// (t, n) MN-contiguous).  C0 = W^t Q (u), C1 = W^t (Q - 1) (u_c), C2 = (W*W)^t Q-bar (y).
-template <class G, typename TE>
-struct PolGH_H {
-  static constexpr int NC = 3;
-  static constexpr int TA = G::BM * G::PITCH, TB = G::BN * G::PITCH;
-  static constexpr int LDS_ELEMS = 2 * TA + 3 * TB;
-  typedef typename MF<TE>::v8 V8;
-  Stage16<G::BM, G::BK, G::NT, float, TE, false> sw;
-  Stage16<G::BN, G::BK, G::NT, TE, TE, false> sq[3];
-  Op16 W, Q[3];
-  int64_t m0, n0;
+static Off16 offsets16(int64_t N, int64_t T, int64_t R) {
+  const Dims16 d = dims16(N, T, R);
+  const size_t mx = (size_t)std::max(d.Np, d.Tp);
+  Off16 o;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t p = off; off = (off + bytes + 255) & ~size_t(255); return p; };
+  o.fa_hi = take((size_t)d.Np * d.Rk * 2);
+  o.fa_lo = take((size_t)d.Np * d.Rk * 2);
+  o.fb_hi = take((size_t)d.Tp * d.Rk * 2);
+  o.fb_lo = take((size_t)d.Tp * d.Rk * 2);
+  o.g0 = take((size_t)d.Rm * mx * 2);
+  o.g1 = take((size_t)d.Rm * mx * 2);
+  o.x0 = take(mx * d.Rk * 2);
+  o.x1 = take(mx * d.Rk * 2);
+  o.q3 = take((size_t)3 * d.Np * d.Tp * 2);
+  o.bits = take(((size_t)d.Rm + 3 * mx) * 4);
+  o.rs = take((size_t)d.Rm * 4);
+  o.irs = take((size_t)d.Rm * 4);
+  o.irs2 = take((size_t)d.Rm * 4);
+  o.qs = take(3 * mx * 4);
+  o.iqs = take(3 * mx * 4);
+  o.total = off;
+  return o;
+}
 
-  __device__ __forceinline__ void load(int64_t k0, int64_t k_end, int tid) {
-    sw.load(W, m0, k0, k_end, tid);
-#pragma unroll
-    for (int x = 0; x < 3; ++x) sq[x].load(Q[x], n0, k0, k_end, tid);
-  }
-  __device__ __forceinline__ void store(TE* lds, int64_t k0, int64_t k_end, int tid) {
-    sw.template store<XF_ID>(lds, W, m0, k0, k_end, tid);
-    sw.template store<XF_SQ>(lds + TA, W, m0, k0, k_end, tid);
-#pragma unroll
-    for (int x = 0; x < 3; ++x) sq[x].template store<XF_ID>(lds + 2 * TA + x * TB, Q[x], n0, k0, k_end, tid);
-  }
-  __device__ __forceinline__ void compute(const TE* lds, f32x16 (&acc)[G::FM][G::FN][NC], int lane, int wm, int wn) {
-#pragma unroll
-    for (int kk = 0; kk < G::BK / 16; ++kk) {
-      V8 a[2][G::FM], b[3][G::FN];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int i = 0; i < G::FM; ++i)
-          a[x][i] = frag16<TE>(lds + x * TA, G::PITCH, wm * G::WM + i * 32 + (lane & 31), kk, lane);
-#pragma unroll
-      for (int y = 0; y < 3; ++y)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          b[y][j] = frag16<TE>(lds + 2 * TA + y * TB, G::PITCH, wn * G::WN + j * 32 + (lane & 31), kk, lane);
-#pragma unroll
-      for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j) {
-          acc[i][j][0] = MF<TE>::mma(a[0][i], b[0][j], acc[i][j][0]);
-          acc[i][j][1] = MF<TE>::mma(a[0][i], b[1][j], acc[i][j][1]);
-          acc[i][j][2] = MF<TE>::mma(a[1][i], b[2][j], acc[i][j][2]);
-        }
-    }
-  }
-};
+size_t scratch16_bytes(int64_t N, int64_t T, int64_t R) { return offsets16(N, T, R).total; }
 
-// W-orientation gradient (M = N, N = R, K = T).  Sources: Q, Q - 1, Q-bar (16-bit,
-// element (n, t) K-contiguous); H (fp32, element (r, t) K-contiguous) staged as h
-// and h^2.  C0 = Q H^t (u), C1 = (Q - 1) H^t (u_c), C2 = Q-bar (H*H)^t (y).
-template <class G, typename TE>
-struct PolGH_W {
-  static constexpr int NC = 3;
-  static constexpr int TA = G::BM * G::PITCH, TB = G::BN * G::PITCH;
-  static constexpr int LDS_ELEMS = 3 * TA + 2 * TB;
-  typedef typename MF<TE>::v8 V8;
-  Stage16<G::BM, G::BK, G::NT, TE, TE, true> sq[3];
-  Stage16<G::BN, G::BK, G::NT, float, TE, true> sh;
-  Op16 Q[3], H;
-  int64_t m0, n0;
-
-  __device__ __forceinline__ void load(int64_t k0, int64_t k_end, int tid) {
-#pragma unroll
-    for (int x = 0; x < 3; ++x) sq[x].load(Q[x], m0, k0, k_end, tid);
-    sh.load(H, n0, k0, k_end, tid);
-  }
-  __device__ __forceinline__ void store(TE* lds, int64_t k0, int64_t k_end, int tid) {
-#pragma unroll
-    for (int x = 0; x < 3; ++x) sq[x].template store<XF_ID>(lds + x * TA, Q[x], m0, k0, k_end, tid);
-    sh.template store<XF_ID>(lds + 3 * TA, H, n0, k0, k_end, tid);
-    sh.template store<XF_SQ>(lds + 3 * TA + TB, H, n0, k0, k_end, tid);
-  }
-  __device__ __forceinline__ void compute(const TE* lds, f32x16 (&acc)[G::FM][G::FN][NC], int lane, int wm, int wn) {
-#pragma unroll
-    for (int kk = 0; kk < G::BK / 16; ++kk) {
-      V8 a[3][G::FM], b[2][G::FN];
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int i = 0; i < G::FM; ++i)
-          a[x][i] = frag16<TE>(lds + x * TA, G::PITCH, wm * G::WM + i * 32 + (lane & 31), kk, lane);
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          b[y][j] = frag16<TE>(lds + 3 * TA + y * TB, G::PITCH, wn * G::WN + j * 32 + (lane & 31), kk, lane);
-#pragma unroll
-      for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < G::FN; ++j) {
-          acc[i][j][0] = MF<TE>::mma(a[0][i], b[0][j], acc[i][j][0]);
-          acc[i][j][1] = MF<TE>::mma(a[1][i], b[0][j], acc[i][j][1]);
-          acc[i][j][2] = MF<TE>::mma(a[2][i], b[1][j], acc[i][j][2]);
-        }
-    }
-  }
-};
+Scratch16 scratch16_carve(void* base, int64_t N, int64_t T, int64_t R) {
+  const Off16 o = offsets16(N, T, R);
+  char* b = static_cast<char*>(base);
+  Scratch16 S;
+  S.fa_hi = b + o.fa_hi; S.fa_lo = b + o.fa_lo; S.fb_hi = b + o.fb_hi; S.fb_lo = b + o.fb_lo;
+  S.g0 = b + o.g0; S.g1 = b + o.g1; S.x0 = b + o.x0; S.x1 = b + o.x1; S.q3 = b + o.q3;
+  S.bits = reinterpret_cast<unsigned*>(b + o.bits);
+  S.rs = reinterpret_cast<float*>(b + o.rs);
+  S.irs = reinterpret_cast<float*>(b + o.irs);
+  S.irs2 = reinterpret_cast<float*>(b + o.irs2);
+  S.qs = reinterpret_cast<float*>(b + o.qs);
+  S.iqs = reinterpret_cast<float*>(b + o.iqs);
+  return S;
+}
 
 // ---------------------------------------------------------------------------
-// Ratio pass (and its max-only variant for the fp16 scales).
+// Conversion: dst (Dr x Dc, leading dimension ldd, 16-bit) from an fp32 source
+// (Sr x Sc, leading dimension lds), transposed or not; zero outside the source.
+//   x = (src - src2) * sr[source row] * sc[source column]   (nullptr: 0 / 1)
+//   out0 = round16(x);  out1 = round16(x - out0) (MODE1 = 1) or round16(x * x) (2)
+// 64 x 64 tiles through LDS so that both sides are read / written along rows.
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+  const float* src; const float* src2;
+  int64_t Sr, Sc, lds;
+  const float* sr; const float* sc;
+  void* out0; void* out1;
+  int mode1;
+  int64_t Dr, Dc, ldd;
+};
+
+template <typename TE, bool TR>
+__global__ __launch_bounds__(256) void k_conv16(ConvArgs a) {
+  __shared__ float t[64][65];
+  const int tid = threadIdx.x;
+  const int64_t d0 = (int64_t)blockIdx.y * 64, e0 = (int64_t)blockIdx.x * 64;   // dest rows / cols
+  // source tile: rows / cols of the source covered by this dest tile
+  const int64_t s0 = TR ? e0 : d0, c0 = TR ? d0 : e0;
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int rr = idx / 64, cc = idx % 64;
+    const int64_t r = s0 + rr, c = c0 + cc;
+    float x = 0.f;
+    if (r < a.Sr && c < a.Sc) {
+      x = a.src[r * a.lds + c];
+      if (a.src2) x -= a.src2[r * a.lds + c];
+      if (a.sr) x *= a.sr[r];
+      if (a.sc) x *= a.sc[c];
+    }
+    t[rr][cc] = x;
+  }
+  __syncthreads();
+  TE* o0 = reinterpret_cast<TE*>(a.out0);
+  TE* o1 = reinterpret_cast<TE*>(a.out1);
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int dr = idx / 64, dc = idx % 64;
+    const int64_t r = d0 + dr, c = e0 + dc;
+    if (r >= a.Dr || c >= a.Dc) continue;
+    const float x = TR ? t[dc][dr] : t[dr][dc];
+    const TE h = (TE)x;
+    o0[r * a.ldd + c] = h;
+    if (o1) o1[r * a.ldd + c] = (TE)(a.mode1 == 1 ? x - (float)h : x * x);
+  }
+}
+
+template <typename TE>
+static void conv16(const ConvArgs& a, bool tr, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(a.Dc, 64), (unsigned)cdiv(a.Dr, 64));
+  if (tr) hipLaunchKernelGGL((k_conv16<TE, true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_conv16<TE, false>), grid, dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// Z pass: Z = W H from the converted operands; epilogue Q = v/z, Q - 1 =
+// (v - z)/z, Q-bar = q/z (zero where v = 0, except Q - 1 = -1; zero in the
+// padding), optional per-column / per-row scales, 16-bit output through LDS
+// (SIDE 0: transposed, [t][n]; SIDE 1: [n][t], both with leading dimension of
+// the padded extent), plus V column (SIDE 0) / row (SIDE 1) sums.
+// MAXONLY: only the maxima of |Q|, |Q - 1|, Q-bar per column / row (fp16 scales).
 // ---------------------------------------------------------------------------
 struct Ratio16Args {
   const float* V;
-  Op16 W, H;
-  int64_t N, T, R;
-  void* Q; void* Qc; void* Qb;      // 16-bit outputs (element type of the instantiation)
+  Mat16 A[2], B[2];
+  int64_t N, T, Rk, Np, Tp;
+  void* q3;                         // 3 x Np x Tp, 16-bit
   double* vpart;
   const float* qs[3];               // output scales of Q, Q - 1, Q-bar (nullptr = 1)
   unsigned* qmax[3];                // max pass: float bits of max |.| per column / row
@@ -219,91 +159,94 @@ struct Ratio16Args {
   SumJob fin;                       // folded second level of the factor sum (not in the max pass)
 };
 
-// SIDE 0: H step (column sums of V, scales per column t); SIDE 1: W step (rows n).
-// SPLIT as in PolZ: the factor being updated (H in the H step, W in the W step)
-// must enter Z with more than 16-bit precision -- otherwise the gradient is
-// taken at a point a relative 16-bit rounding away from the one the step is
-// applied to, an error that does not shrink as the fit converges.
+template <int SPLIT> struct ZProds;
+template <> struct ZProds<0> { typedef Prods<1, 1, 1, 1, 0, 0, 0> P; };
+template <> struct ZProds<1> { typedef Prods<1, 2, 2, 1, 0, 1, 0, 0, 0, 0> P; };          // B split
+template <> struct ZProds<2> { typedef Prods<2, 1, 2, 1, 1, 0, 0, 0, 0, 0> P; };          // A split
+template <> struct ZProds<3> { typedef Prods<2, 2, 3, 1, 1, 0, 0, 0, 1, 0, 0, 0, 0> P; }; // both
+
+constexpr int OUT_PITCH = 128 + 8;   // LDS pitch of the 128 x 128 output staging tile
+
 template <typename TE, int SIDE, bool MAXONLY, int SPLIT>
-__global__ __launch_bounds__(G16R::NT) void k_ratio16(Ratio16Args a) {
-  using G = G16R;
-  typedef PolZ<G, TE, 1, 1, SPLIT> P;
-  __shared__ __align__(16) TE lds[P::LDS_ELEMS > 4 * G::BM * 8 ? P::LDS_ELEMS : 4 * G::BM * 8];
+__global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
+  using G = G128;
+  typedef typename ZProds<SPLIT>::P PR;
+  typedef Gemm16<G, TE, PR> E;
+  static_assert(E::LDS_ELEMS >= 128 * OUT_PITCH, "output staging must fit in the operand LDS");
+  extern __shared__ __align__(16) uint16_t lds_dyn[];
+  uint16_t* lds = lds_dyn;
   const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
+  const int64_t N = a.N, T = a.T;
   if (!MAXONLY) sum_job(a.fin);
   float vf[G::FM][G::FN][16];
 #pragma unroll
   for (int j = 0; j < G::FN; ++j) {
-    const int64_t col = std::min<int64_t>(col16<G>(n0, j), a.T - 1);
+    const int64_t col = std::min<int64_t>(col16<G>(n0, j), T - 1);
 #pragma unroll
     for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) vf[i][j][v] = a.V[std::min<int64_t>(row16<G>(m0, i, v), a.N - 1) * a.T + col];
+      for (int v = 0; v < 16; ++v) vf[i][j][v] = a.V[std::min<int64_t>(row16<G>(m0, i, v), N - 1) * T + col];
   }
   f32x16 acc[G::FM][G::FN][1];
   zero16<G, 1>(acc);
-  P pol;
-  pol.A[0] = a.W;
-  pol.B[0] = a.H;
-  pol.m0 = m0;
-  pol.n0 = n0;
-  run16<G, P, TE>(pol, acc, 0, a.R, lds);
-  const int64_t N = a.N, T = a.T;
-  double cp[1][G::FN];
-  double rp[1][G::FM][16];
+  {
+    Mat16 A[PR::NA], B[PR::NB];
 #pragma unroll
-  for (int j = 0; j < G::FN; ++j) cp[0][j] = 0.0;
+    for (int x = 0; x < PR::NA; ++x) A[x] = a.A[x];
 #pragma unroll
-  for (int i = 0; i < G::FM; ++i)
+    for (int y = 0; y < PR::NB; ++y) B[y] = a.B[y];
+    E::run(A, B, m0, n0, 0, a.Rk, lds, acc);
+  }
+  const int lane = threadIdx.x & 63;
+  if (MAXONLY) {
+    float mx[3][G::FN] = {};
+    int bad = 0;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) rp[0][i][v] = 0.0;
-  float mx[3][G::FN] = {};        // max pass, SIDE 0: per column of this lane
-  int bad = 0;
+    for (int i = 0; i < G::FM; ++i) {
+      float rmx[3][16] = {};        // SIDE 1: per-row maxima of this lane's columns
 #pragma unroll
-  for (int i = 0; i < G::FM; ++i)
+      for (int j = 0; j < G::FN; ++j) {
+        const int64_t col = col16<G>(n0, j);
 #pragma unroll
-    for (int j = 0; j < G::FN; ++j) {
-      const int64_t col = col16<G>(n0, j);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = row16<G>(m0, i, v);
-        if (row < N && col < T) {
-          const float x = vf[i][j][v];
-          const float z = acc[i][j][0][v];
-          const bool pos = x > 0.f;
-          const float iz = __builtin_amdgcn_rcpf(z);
-          const float q = pos ? x * iz : 0.f;
-          const float qc = pos ? (x - z) * iz : -1.f;
-          const float qb = pos ? q * iz : 0.f;
-          bad |= (pos && !(z > 0.f)) ? 1 : 0;
-          if (MAXONLY) {
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = row16<G>(m0, i, v);
+          if (row < N && col < T) {
+            const float x = vf[i][j][v], z = acc[i][j][0][v];
+            const bool pos = x > 0.f;
+            const float iz = __builtin_amdgcn_rcpf(z);
+            const float q = pos ? x * iz : 0.f;
+            const float qc = pos ? (x - z) * iz : -1.f;
+            const float qb = pos ? q * iz : 0.f;
+            bad |= (pos && !(z > 0.f)) ? 1 : 0;
             if (SIDE == 0) {
               mx[0][j] = fmaxf(mx[0][j], q);
               mx[1][j] = fmaxf(mx[1][j], fabsf(qc));
               mx[2][j] = fmaxf(mx[2][j], qb);
             } else {
-              atomicMax(a.qmax[0] + row, __float_as_uint(q));
-              atomicMax(a.qmax[1] + row, __float_as_uint(fabsf(qc)));
-              atomicMax(a.qmax[2] + row, __float_as_uint(qb));
+              rmx[0][v] = fmaxf(rmx[0][v], q);
+              rmx[1][v] = fmaxf(rmx[1][v], fabsf(qc));
+              rmx[2][v] = fmaxf(rmx[2][v], qb);
             }
-          } else {
-            const int64_t si = SIDE == 0 ? col : row;
-            const float s0 = a.qs[0] ? a.qs[0][si] : 1.f;
-            const float s1 = a.qs[1] ? a.qs[1][si] : 1.f;
-            const float s2 = a.qs[2] ? a.qs[2][si] : 1.f;
-            reinterpret_cast<TE*>(a.Q)[row * T + col] = (TE)(q * s0);
-            reinterpret_cast<TE*>(a.Qc)[row * T + col] = (TE)(qc * s1);
-            reinterpret_cast<TE*>(a.Qb)[row * T + col] = (TE)(qb * s2);
-            if (SIDE == 0) cp[0][j] += (double)x;
-            else rp[0][i][v] += (double)x;
           }
         }
       }
+      if (SIDE == 1) {
+        // the 32 lanes of a half-wave hold the same rows: reduce across them,
+        // then one atomic per row from lanes 0 and 32
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            float m = rmx[k][v];
+#pragma unroll
+            for (int sh = 1; sh < 32; sh <<= 1) m = fmaxf(m, __shfl_xor(m, sh));
+            const int64_t row = row16<G>(m0, i, v);
+            if ((lane & 31) == 0 && row < N && m > 0.f) atomicMax(a.qmax[k] + row, __float_as_uint(m));
+          }
+      }
     }
-  if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
-  if (MAXONLY) {
+    if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
     if (SIDE == 0) {
-      const int lane = threadIdx.x & 63;
 #pragma unroll
       for (int j = 0; j < G::FN; ++j) {
         const int64_t col = col16<G>(n0, j);
@@ -316,16 +259,87 @@ __global__ __launch_bounds__(G16R::NT) void k_ratio16(Ratio16Args a) {
     }
     return;
   }
-  double* red = reinterpret_cast<double*>(lds);
-  if (SIDE == 0) {
-    reduce_cols<G, 1>(cp, red, [&](int c, const double (&s)[1]) {
-      if (n0 + c < T) a.vpart[(int64_t)blockIdx.y * T + n0 + c] = s[0];
-    });
-  } else {
-    reduce_rows<G, 1>(rp, red, [&](int r, const double (&s)[1]) {
-      if (m0 + r < N) a.vpart[(int64_t)blockIdx.x * N + m0 + r] = s[0];
-    });
+  // V sums of this tile (column sums in the H step, row sums in the W step)
+  {
+    double* red = reinterpret_cast<double*>(lds);
+    if (SIDE == 0) {
+      double cp[1][G::FN];
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+        cp[0][j] = 0.0;
+        const int64_t col = col16<G>(n0, j);
+#pragma unroll
+        for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+          for (int v = 0; v < 16; ++v)
+            if (row16<G>(m0, i, v) < N && col < T) cp[0][j] += (double)vf[i][j][v];
+      }
+      reduce_cols<G, 1>(cp, red, [&](int c, const double (&s)[1]) {
+        if (n0 + c < T) a.vpart[(int64_t)blockIdx.y * T + n0 + c] = s[0];
+      });
+    } else {
+      double rp[1][G::FM][16];
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          rp[0][i][v] = 0.0;
+          const int64_t row = row16<G>(m0, i, v);
+#pragma unroll
+          for (int j = 0; j < G::FN; ++j)
+            if (row < N && col16<G>(n0, j) < T) rp[0][i][v] += (double)vf[i][j][v];
+        }
+      reduce_rows<G, 1>(rp, red, [&](int r, const double (&s)[1]) {
+        if (m0 + r < N) a.vpart[(int64_t)blockIdx.x * N + m0 + r] = s[0];
+      });
+    }
   }
+  // the three outputs, one at a time through the LDS staging tile
+  TE* st = reinterpret_cast<TE*>(lds);
+  int bad = 0;
+#pragma unroll 1
+  for (int o = 0; o < 3; ++o) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+        const int64_t col = col16<G>(n0, j);
+        const int cl = (int)(col - n0);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = row16<G>(m0, i, v);
+          const int rl = (int)(row - m0);
+          float val = 0.f;
+          if (row < N && col < T) {
+            const float x = vf[i][j][v], z = acc[i][j][0][v];
+            const bool pos = x > 0.f;
+            const float iz = __builtin_amdgcn_rcpf(z);
+            if (o == 0) val = pos ? x * iz : 0.f;
+            else if (o == 1) val = pos ? (x - z) * iz : -1.f;
+            else val = pos ? x * iz * iz : 0.f;
+            if (o == 0) bad |= (pos && !(z > 0.f)) ? 1 : 0;
+            if (a.qs[o]) val *= a.qs[o][SIDE == 0 ? col : row];
+          }
+          if (SIDE == 0) st[cl * OUT_PITCH + rl] = (TE)val;
+          else st[rl * OUT_PITCH + cl] = (TE)val;
+        }
+      }
+    __syncthreads();
+    // copy out: 128 rows of 128 elements, 16-byte chunks
+    const int64_t ld = SIDE == 0 ? a.Np : a.Tp;
+    const int64_t r0 = SIDE == 0 ? n0 : m0, c0 = SIDE == 0 ? m0 : n0;
+    uint16_t* dst = reinterpret_cast<uint16_t*>(a.q3) + (int64_t)o * a.Np * a.Tp;
+    const uint16_t* src = reinterpret_cast<const uint16_t*>(st);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int f = threadIdx.x + k * 256;
+      const int rr = f / 16, ch = (f % 16) * 8;
+      *reinterpret_cast<u32x4*>(dst + (r0 + rr) * ld + c0 + ch) =
+          *reinterpret_cast<const u32x4*>(src + rr * OUT_PITCH + ch);
+    }
+  }
+  if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,66 +352,39 @@ struct Fold {
   const float* c[3];
 };
 
-template <typename TE>
-__global__ __launch_bounds__(G16H::NT) void k_gh16_H(Op16 W, Op16 Q, Op16 Qc, Op16 Qb, int64_t N, int64_t T,
-                                                     int64_t R, int64_t kchunk, float* pu, float* puc, float* py,
-                                                     Fold f) {
-  using G = G16H;
-  typedef PolGH_H<G, TE> P;
-  __shared__ __align__(16) TE lds[P::LDS_ELEMS];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
-  const int64_t sp = blockIdx.z;
-  const int64_t k0 = sp * kchunk, k1 = std::min<int64_t>(N, k0 + kchunk);
-  f32x16 acc[G::FM][G::FN][3];
-  zero16<G, 3>(acc);
-  P pol;
-  pol.W = W;
-  pol.Q[0] = Qc;     // tile B0: Q - 1
-  pol.Q[1] = Q;      // tile B1: Q
-  pol.Q[2] = Qb;     // tile B2: Q-bar
-  pol.m0 = m0;
-  pol.n0 = n0;
-  run16<G, P, TE>(pol, acc, k0, k1, lds);
-  float* out[3] = {pu, puc, py};
-#pragma unroll
-  for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < G::FN; ++j) {
-      const int64_t col = col16<G>(n0, j);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = row16<G>(m0, i, v);
-        if (row < R && col < T) {
-          const int64_t e = (sp * R + row) * T + col;
-          const int src[3] = {1, 0, 2};          // u = W^t Q, u_c = W^t (Q - 1), y
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            out[c][e] = acc[i][j][src[c]][v] * (f.r[c] ? f.r[c][row] : 1.f) * (f.c[c] ? f.c[c][col] : 1.f);
-        }
-      }
-    }
-}
+// Operand table of a product kernel (A operands first, then B operands).
+struct Ops16 {
+  Mat16 m[5];
+};
 
-template <typename TE>
-__global__ __launch_bounds__(G16W::NT) void k_gh16_W(Op16 Q, Op16 Qc, Op16 Qb, Op16 H, int64_t N, int64_t T,
-                                                     int64_t R, int64_t kchunk, float* pu, float* puc, float* py,
-                                                     Fold f) {
-  using G = G16W;
-  typedef PolGH_W<G, TE> P;
-  __shared__ __align__(16) TE lds[P::LDS_ELEMS];
+// H orientation: M = R (rows r), N = T (cols t), K = N.  A = {W^t, (W*W)^t},
+// B = {Q^t, (Q - 1)^t, Q-bar^t}:  u = A0 B0, u_c = A0 B1, y = A1 B2.
+typedef Prods<2, 3, 3, 3, 0, 0, 0, 0, 1, 1, 1, 2, 2> GHH_P;
+// W orientation: M = N (rows n), N = R (cols r), K = T.  A = {Q, Q - 1, Q-bar},
+// B = {H, H*H}:  u = A0 B0, u_c = A1 B0, y = A2 B1.
+typedef Prods<3, 2, 3, 3, 0, 0, 0, 1, 0, 1, 2, 1, 2> GHW_P;
+
+template <typename TE, int SIDE>
+__global__ __launch_bounds__(256) void k_gh16(Ops16 ops, int64_t M, int64_t Ncol,
+                                              int64_t K32, int64_t kchunk, float* pu, float* puc, float* py,
+                                              Fold f) {
+  using G = G128;
+  typedef typename std::conditional<SIDE == 0, GHH_P, GHW_P>::type PR;
+  typedef Gemm16<G, TE, PR> E;
+  extern __shared__ __align__(16) uint16_t lds_dyn[];
   const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
   const int64_t sp = blockIdx.z;
-  const int64_t k0 = sp * kchunk, k1 = std::min<int64_t>(T, k0 + kchunk);
+  const int64_t k0 = sp * kchunk, k1 = std::min<int64_t>(K32, k0 + kchunk);
   f32x16 acc[G::FM][G::FN][3];
   zero16<G, 3>(acc);
-  P pol;
-  pol.Q[0] = Q;      // tile A0: Q
-  pol.Q[1] = Qc;     // tile A1: Q - 1
-  pol.Q[2] = Qb;     // tile A2: Q-bar
-  pol.H = H;
-  pol.m0 = m0;
-  pol.n0 = n0;
-  run16<G, P, TE>(pol, acc, k0, k1, lds);
+  {
+    Mat16 A[PR::NA], B[PR::NB];
+#pragma unroll
+    for (int x = 0; x < PR::NA; ++x) A[x] = ops.m[x];
+#pragma unroll
+    for (int y = 0; y < PR::NB; ++y) B[y] = ops.m[PR::NA + y];
+    E::run(A, B, m0, n0, k0, k1, lds_dyn, acc);
+  }
   float* out[3] = {pu, puc, py};
 #pragma unroll
   for (int i = 0; i < G::FM; ++i)
@@ -407,8 +394,8 @@ __global__ __launch_bounds__(G16W::NT) void k_gh16_W(Op16 Q, Op16 Qc, Op16 Qb, O
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t row = row16<G>(m0, i, v);
-        if (row < N && col < R) {
-          const int64_t e = (sp * N + row) * R + col;
+        if (row < M && col < Ncol) {
+          const int64_t e = (sp * M + row) * Ncol + col;
 #pragma unroll
           for (int c = 0; c < 3; ++c)
             out[c][e] = acc[i][j][c][v] * (f.r[c] ? f.r[c][row] : 1.f) * (f.c[c] ? f.c[c][col] : 1.f);
@@ -418,50 +405,24 @@ __global__ __launch_bounds__(G16W::NT) void k_gh16_W(Op16 Q, Op16 Qc, Op16 Qb, O
 }
 
 // ---------------------------------------------------------------------------
-// Candidate costs (as the fp32 kernels, with 16-bit reconstruction products).
+// Candidate costs (epilogues shared with the fp32 kernels), 16-bit products:
+// H orientation A = {W}, B = {X_DNA^t, (X_MU - X_DNA)^t}; W orientation
+// A = {X_DNA, X_MU - X_DNA}, B = {H^t}.  acc 0 = z_DNA, acc 1 = dZ.
 // ---------------------------------------------------------------------------
-template <typename TE>
-__global__ __launch_bounds__(G16CH::NT) void k_cost16_H(const float* V, Op16 W, Op16 Hn, Op16 Hd, int64_t N,
-                                                        int64_t T, int64_t R, double* part, int* fpart) {
-  using G = G16CH;
-  typedef PolZ<G, TE, 1, 2> P;
-  __shared__ __align__(16) TE lds[P::LDS_ELEMS > 12 * G::BN * 4 ? P::LDS_ELEMS : 12 * G::BN * 4];
-  __shared__ int fl_s[G::BN];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
-  const int tid = threadIdx.x;
-  for (int c = tid; c < G::BN; c += G::NT) fl_s[c] = 0;
-  float vf[G::FM][G::FN][16];
-#pragma unroll
-  for (int j = 0; j < G::FN; ++j) {
-    const int64_t col = std::min<int64_t>(col16<G>(n0, j), T - 1);
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) vf[i][j][v] = V[std::min<int64_t>(row16<G>(m0, i, v), N - 1) * T + col];
-  }
-  f32x16 acc[G::FM][G::FN][2];
-  zero16<G, 2>(acc);
-  P pol;
-  pol.A[0] = W;
-  pol.B[0] = Hn;
-  pol.B[1] = Hd;
-  pol.m0 = m0;
-  pol.n0 = n0;
-  run16<G, P, TE>(pol, acc, 0, R, lds);
-  const int64_t base = (int64_t)blockIdx.y * T, stride = (int64_t)gridDim.y * T;
-  cost_cols<G>(vf, acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
-}
+typedef Prods<1, 2, 2, 2, 0, 0, 0, 0, 1, 1> CH_P;
+typedef Prods<2, 1, 2, 2, 0, 0, 0, 1, 0, 1> CW_P;
 
-template <typename TE>
-__global__ __launch_bounds__(G16CW::NT) void k_cost16_W(const float* V, Op16 Wn, Op16 Wd, Op16 H, int64_t N,
-                                                        int64_t T, int64_t R, double* part, int* fpart) {
-  using G = G16CW;
-  typedef PolZ<G, TE, 2, 1> P;
-  __shared__ __align__(16) TE lds[P::LDS_ELEMS > 12 * G::BM * 4 ? P::LDS_ELEMS : 12 * G::BM * 4];
-  __shared__ int fl_s[G::BM];
+template <typename TE, int SIDE>
+__global__ __launch_bounds__(256) void k_cost16(const float* V, Ops16 ops, int64_t N, int64_t T,
+                                                int64_t Rk, double* part, int* fpart) {
+  using G = G128;
+  typedef typename std::conditional<SIDE == 0, CH_P, CW_P>::type PR;
+  typedef Gemm16<G, TE, PR> E;
+  extern __shared__ __align__(16) uint16_t lds_dyn[];
+  __shared__ int fl_s[128];
   const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
   const int tid = threadIdx.x;
-  for (int r = tid; r < G::BM; r += G::NT) fl_s[r] = 0;
+  if (tid < 128) fl_s[tid] = 0;
   float vf[G::FM][G::FN][16];
 #pragma unroll
   for (int j = 0; j < G::FN; ++j) {
@@ -473,15 +434,22 @@ __global__ __launch_bounds__(G16CW::NT) void k_cost16_W(const float* V, Op16 Wn,
   }
   f32x16 acc[G::FM][G::FN][2];
   zero16<G, 2>(acc);
-  P pol;
-  pol.A[0] = Wn;
-  pol.A[1] = Wd;
-  pol.B[0] = H;
-  pol.m0 = m0;
-  pol.n0 = n0;
-  run16<G, P, TE>(pol, acc, 0, R, lds);
-  const int64_t base = (int64_t)blockIdx.x * N, stride = (int64_t)gridDim.x * N;
-  cost_rows<G>(vf, acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
+  {
+    Mat16 A[PR::NA], B[PR::NB];
+#pragma unroll
+    for (int x = 0; x < PR::NA; ++x) A[x] = ops.m[x];
+#pragma unroll
+    for (int y = 0; y < PR::NB; ++y) B[y] = ops.m[PR::NA + y];
+    E::run(A, B, m0, n0, 0, Rk, lds_dyn, acc);
+  }
+  double* red = reinterpret_cast<double*>(lds_dyn);
+  if (SIDE == 0) {
+    const int64_t base = (int64_t)blockIdx.y * T, stride = (int64_t)gridDim.y * T;
+    cost_cols<G>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
+  } else {
+    const int64_t base = (int64_t)blockIdx.x * N, stride = (int64_t)gridDim.x * N;
+    cost_rows<G>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -539,20 +507,34 @@ __global__ __launch_bounds__(256) void k_scales(const unsigned* bits, int64_t n,
 static unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 4096)); }
 
 // Rank scales for fp16: H step -> from the column maxima of W, W step -> from the
-// row maxima of H; rs = 2^-ceil(log2 max) (max scaled to at most 1).
+// row maxima of H; rs = 2^-ceil(log2 max) (max scaled into [1/2, 1)).
 static void rank_scales(int side, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
                         const Scratch16& S, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(grid1(R)), dim3(256), 0, s, S.bits, R);
   if (side == 0) {
-    const int64_t parts = std::min<int64_t>(SUM_PARTS, cdiv(N, 64));
+    const int64_t parts = std::min<int64_t>(256, cdiv(N, 64));
     hipLaunchKernelGGL(k_colmax_W, dim3((unsigned)cdiv(R, 64), (unsigned)parts), dim3(256), 0, s, W, N, R,
                        cdiv(N, parts), S.bits);
   } else {
-    const int64_t parts = std::min<int64_t>(SUM_PARTS, cdiv(T, 2048));
+    const int64_t parts = std::min<int64_t>(256, cdiv(T, 2048));
     hipLaunchKernelGGL(k_rowmax_H, dim3((unsigned)parts, (unsigned)R), dim3(256), 0, s, H, T, R, cdiv(T, parts),
                        S.bits);
   }
   hipLaunchKernelGGL(k_scales, dim3(grid1(R)), dim3(256), 0, s, S.bits, R, 0, S.rs, S.irs, S.irs2);
+}
+
+// Dynamic LDS above the default 64 KiB needs the attribute once per kernel.
+template <typename F>
+static void lds_attr(F* fn, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename K>
+static void launch_ratio_k(K* fn, int lds_elems, dim3 grid, const Ratio16Args& ra, hipStream_t s) {
+  const size_t lb = (size_t)lds_elems * 2;
+  lds_attr(fn, lb);
+  hipLaunchKernelGGL(fn, grid, dim3(256), lb, s, ra);
 }
 
 template <typename TE>
@@ -560,75 +542,100 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
                              int64_t R, const Scratch16& S, bool scaled, int splits, int64_t kchunk, float* pu,
                              float* puc, float* py, double* vpart, int* check, const SumJob& fin,
                              hipStream_t s) {
-  TE* Qp = reinterpret_cast<TE*>(S.q16);
-  TE* Qc = Qp + N * T;
-  TE* Qb = reinterpret_cast<TE*>(S.qb16);
-  const int64_t L = side == 0 ? T : N;     // index range of the Q scales
+  const Dims16 d = dims16(N, T, R);
   const float* rs = nullptr;
   const float* irs = nullptr;
   const float* irs2 = nullptr;
-  const float* qs[3] = {nullptr, nullptr, nullptr};
-  const float* iqs[3] = {nullptr, nullptr, nullptr};
   if (scaled) {
     rank_scales(side, W, H, N, T, R, S, s);
     rs = S.rs; irs = S.irs; irs2 = S.irs2;
   }
-  // Z-type product: the rank scales cancel between W and H
-  const Op16 w = make_op16<float>(W, R, N, nullptr, side == 0 ? rs : irs);
-  const Op16 h = make_op16<float>(H, T, T, nullptr, side == 0 ? irs : rs);
+  // bf16: both factors split; fp16: the updated factor only
+  const int split = scaled ? (side == 0 ? 1 : 2) : 3;
+  const bool split_a = (split & 2) != 0, split_b = (split & 1) != 0;
+  // Z operands: A = W (Np x Rk), B = H^t (Tp x Rk); the rank scales cancel
+  prof_begin(side == 0 ? "conv16_H" : "conv16_W", s);
+  conv16<TE>(ConvArgs{W, nullptr, N, R, R, nullptr, side == 0 ? rs : irs, S.fa_hi, split_a ? S.fa_lo : nullptr,
+                      1, d.Np, d.Rk, d.Rk}, false, s);
+  conv16<TE>(ConvArgs{H, nullptr, R, T, T, side == 0 ? irs : rs, nullptr, S.fb_hi, split_b ? S.fb_lo : nullptr,
+                      1, d.Tp, d.Rk, d.Rk}, true, s);
+  // gradient operands of the fixed factor: W^t, (W*W)^t (H step) or H, H*H (W step)
+  if (side == 0)
+    conv16<TE>(ConvArgs{W, nullptr, N, R, R, nullptr, rs, S.g0, S.g1, 2, d.Rm, d.Np, d.Np}, true, s);
+  else
+    conv16<TE>(ConvArgs{H, nullptr, R, T, T, rs, nullptr, S.g0, S.g1, 2, d.Rm, d.Tp, d.Tp}, false, s);
+  prof_end(side == 0 ? "conv16_H" : "conv16_W", s);
+
   Ratio16Args ra;
-  ra.V = V; ra.W = w; ra.H = h; ra.N = N; ra.T = T; ra.R = R;
-  ra.Q = Qp; ra.Qc = Qc; ra.Qb = Qb; ra.vpart = vpart; ra.check = check; ra.fin = fin;
+  ra.V = V;
+  ra.A[0] = Mat16{S.fa_hi, d.Rk};
+  ra.A[1] = Mat16{split_a ? S.fa_lo : S.fa_hi, d.Rk};
+  ra.B[0] = Mat16{S.fb_hi, d.Rk};
+  ra.B[1] = Mat16{split_b ? S.fb_lo : S.fb_hi, d.Rk};
+  ra.N = N; ra.T = T; ra.Rk = d.Rk; ra.Np = d.Np; ra.Tp = d.Tp;
+  ra.q3 = S.q3; ra.vpart = vpart; ra.check = check; ra.fin = fin;
   for (int k = 0; k < 3; ++k) { ra.qs[k] = nullptr; ra.qmax[k] = nullptr; }
-  dim3 rgrid((unsigned)cdiv(T, G16R::BN), (unsigned)cdiv(N, G16R::BM));
+  const dim3 rgrid((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128));
+  const int64_t L = side == 0 ? T : N;     // index range of the Q scales
+  const float* iqs[3] = {nullptr, nullptr, nullptr};
   if (scaled) {
-    unsigned* qbits = S.bits + R;
+    unsigned* qbits = S.bits + d.Rm;
     hipLaunchKernelGGL(k_zero_u32, dim3(grid1(3 * L)), dim3(256), 0, s, qbits, 3 * L);
     for (int k = 0; k < 3; ++k) ra.qmax[k] = qbits + k * L;
     // the scales only need the maxima to a few bits: unsplit product
     prof_begin("qmax16", s);
-    if (side == 0) hipLaunchKernelGGL((k_ratio16<TE, 0, true, 0>), rgrid, dim3(G16R::NT), 0, s, ra);
-    else hipLaunchKernelGGL((k_ratio16<TE, 1, true, 0>), rgrid, dim3(G16R::NT), 0, s, ra);
+    if (side == 0) launch_ratio_k(k_ratio16<TE, 0, true, 0>, Gemm16<G128, TE, ZProds<0>::P>::LDS_ELEMS, rgrid, ra, s);
+    else launch_ratio_k(k_ratio16<TE, 1, true, 0>, Gemm16<G128, TE, ZProds<0>::P>::LDS_ELEMS, rgrid, ra, s);
     prof_end("qmax16", s);
     for (int k = 0; k < 3; ++k) {
       hipLaunchKernelGGL(k_scales, dim3(grid1(L)), dim3(256), 0, s, qbits + k * L, L, 13, S.qs + k * L,
                          S.iqs + k * L, (float*)nullptr);
-      qs[k] = S.qs + k * L;
+      ra.qs[k] = S.qs + k * L;
       iqs[k] = S.iqs + k * L;
     }
   }
-  for (int k = 0; k < 3; ++k) ra.qs[k] = qs[k];
-  // bf16: both factors split (its 8-bit significand in the fixed factor also
-  // biases the fit); fp16: the updated factor only
   prof_begin(side == 0 ? "ratio16_H" : "ratio16_W", s);
-  if (scaled) {
-    if (side == 0) hipLaunchKernelGGL((k_ratio16<TE, 0, false, 1>), rgrid, dim3(G16R::NT), 0, s, ra);
-    else hipLaunchKernelGGL((k_ratio16<TE, 1, false, 2>), rgrid, dim3(G16R::NT), 0, s, ra);
+  if (side == 0) {
+    if (split == 1) launch_ratio_k(k_ratio16<TE, 0, false, 1>, Gemm16<G128, TE, ZProds<1>::P>::LDS_ELEMS, rgrid, ra, s);
+    else launch_ratio_k(k_ratio16<TE, 0, false, 3>, Gemm16<G128, TE, ZProds<3>::P>::LDS_ELEMS, rgrid, ra, s);
   } else {
-    if (side == 0) hipLaunchKernelGGL((k_ratio16<TE, 0, false, 3>), rgrid, dim3(G16R::NT), 0, s, ra);
-    else hipLaunchKernelGGL((k_ratio16<TE, 1, false, 3>), rgrid, dim3(G16R::NT), 0, s, ra);
+    if (split == 2) launch_ratio_k(k_ratio16<TE, 1, false, 2>, Gemm16<G128, TE, ZProds<2>::P>::LDS_ELEMS, rgrid, ra, s);
+    else launch_ratio_k(k_ratio16<TE, 1, false, 3>, Gemm16<G128, TE, ZProds<3>::P>::LDS_ELEMS, rgrid, ra, s);
   }
   prof_end(side == 0 ? "ratio16_H" : "ratio16_W", s);
+
+  // gradient products
+  const int64_t npt = d.Np * d.Tp;
+  const uint16_t* q = reinterpret_cast<const uint16_t*>(S.q3);
   Fold f;
-  if (side == 0) {          // rows r carry the W^t scale, columns t the Q scales
+  Ops16 ops;
+  int64_t M, Ncol, K32;
+  dim3 grid;
+  if (side == 0) {   // rows r carry the W^t scale, columns t the Q scales
     const float* rr[3] = {irs, irs, irs2};
     for (int k = 0; k < 3; ++k) { f.r[k] = rr[k]; f.c[k] = iqs[k]; }
-    const Op16 wt = make_op16<float>(W, R, R, nullptr, nullptr, rs);
-    const Op16 q = make_op16<TE>(Qp, T, T), qc = make_op16<TE>(Qc, T, T), qb = make_op16<TE>(Qb, T, T);
-    dim3 grid((unsigned)cdiv(T, G16H::BN), (unsigned)cdiv(R, G16H::BM), (unsigned)splits);
-    prof_begin("gh16_H", s);
-    hipLaunchKernelGGL(k_gh16_H<TE>, grid, dim3(G16H::NT), 0, s, wt, q, qc, qb, N, T, R, kchunk, pu, puc, py, f);
-    prof_end("gh16_H", s);
-  } else {                  // rows n carry the Q scales, columns r the H^t scale
+    ops.m[0] = Mat16{S.g0, d.Np}; ops.m[1] = Mat16{S.g1, d.Np};
+    for (int k = 0; k < 3; ++k) ops.m[2 + k] = Mat16{q + k * npt, d.Np};
+    M = R; Ncol = T; K32 = cdiv(N, 32) * 32;
+    grid = dim3((unsigned)(d.Tp / 128), (unsigned)(d.Rm / 128), (unsigned)splits);
+  } else {           // rows n carry the Q scales, columns r the H scale
     const float* cc[3] = {irs, irs, irs2};
     for (int k = 0; k < 3; ++k) { f.r[k] = iqs[k]; f.c[k] = cc[k]; }
-    const Op16 q = make_op16<TE>(Qp, T, N), qc = make_op16<TE>(Qc, T, N), qb = make_op16<TE>(Qb, T, N);
-    const Op16 ht = make_op16<float>(H, T, R, nullptr, nullptr, rs);
-    dim3 grid((unsigned)cdiv(R, G16W::BN), (unsigned)cdiv(N, G16W::BM), (unsigned)splits);
-    prof_begin("gh16_W", s);
-    hipLaunchKernelGGL(k_gh16_W<TE>, grid, dim3(G16W::NT), 0, s, q, qc, qb, ht, N, T, R, kchunk, pu, puc, py, f);
-    prof_end("gh16_W", s);
+    for (int k = 0; k < 3; ++k) ops.m[k] = Mat16{q + k * npt, d.Tp};
+    ops.m[3] = Mat16{S.g0, d.Tp}; ops.m[4] = Mat16{S.g1, d.Tp};
+    M = N; Ncol = R; K32 = cdiv(T, 32) * 32;
+    grid = dim3((unsigned)(d.Rm / 128), (unsigned)(d.Np / 128), (unsigned)splits);
   }
+  const size_t lb = (size_t)Gemm16<G128, TE, GHH_P>::LDS_ELEMS * 2;
+  prof_begin(side == 0 ? "gh16_H" : "gh16_W", s);
+  if (side == 0) {
+    lds_attr(k_gh16<TE, 0>, lb);
+    hipLaunchKernelGGL((k_gh16<TE, 0>), grid, dim3(256), lb, s, ops, M, Ncol, K32, kchunk, pu, puc, py, f);
+  } else {
+    lds_attr(k_gh16<TE, 1>, lb);
+    hipLaunchKernelGGL((k_gh16<TE, 1>), grid, dim3(256), lb, s, ops, M, Ncol, K32, kchunk, pu, puc, py, f);
+  }
+  prof_end(side == 0 ? "gh16_H" : "gh16_W", s);
   return hipGetLastError();
 }
 
@@ -636,6 +643,7 @@ template <typename TE>
 static hipError_t cost16(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
                          int64_t T, int64_t R, const Scratch16& S, bool scaled, double* part, int* fpart,
                          hipStream_t s) {
+  const Dims16 d = dims16(N, T, R);
   const float* rs = nullptr;
   const float* irs = nullptr;
   if (scaled) {
@@ -644,23 +652,31 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
     rs = S.rs;
     irs = S.irs;
   }
-  if (side == 0) {
-    const Op16 w = make_op16<float>(F, R, N, nullptr, rs);
-    const Op16 hn = make_op16<float>(Xn, T, T, nullptr, irs);
-    const Op16 hd = make_op16<float>(Xmu, T, T, Xn, irs);
-    dim3 grid((unsigned)cdiv(T, G16CH::BN), (unsigned)cdiv(N, G16CH::BM));
-    prof_begin("cost16_H", s);
-    hipLaunchKernelGGL(k_cost16_H<TE>, grid, dim3(G16CH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart);
-    prof_end("cost16_H", s);
-  } else {
-    const Op16 wn = make_op16<float>(Xn, R, N, nullptr, irs);
-    const Op16 wd = make_op16<float>(Xmu, R, N, Xn, irs);
-    const Op16 h = make_op16<float>(F, T, T, nullptr, rs);
-    dim3 grid((unsigned)cdiv(T, G16CW::BN), (unsigned)cdiv(N, G16CW::BM));
-    prof_begin("cost16_W", s);
-    hipLaunchKernelGGL(k_cost16_W<TE>, grid, dim3(G16CW::NT), 0, s, V, wn, wd, h, N, T, R, part, fpart);
-    prof_end("cost16_W", s);
+  Ops16 ops;
+  prof_begin(side == 0 ? "conv16c_H" : "conv16c_W", s);
+  if (side == 0) {   // A = W (scaled rs), B = X^t (scaled irs)
+    conv16<TE>(ConvArgs{F, nullptr, N, R, R, nullptr, rs, S.fa_hi, nullptr, 0, d.Np, d.Rk, d.Rk}, false, s);
+    conv16<TE>(ConvArgs{Xn, nullptr, R, T, T, irs, nullptr, S.x0, nullptr, 0, d.Tp, d.Rk, d.Rk}, true, s);
+    conv16<TE>(ConvArgs{Xmu, Xn, R, T, T, irs, nullptr, S.x1, nullptr, 0, d.Tp, d.Rk, d.Rk}, true, s);
+    ops.m[0] = Mat16{S.fa_hi, d.Rk}; ops.m[1] = Mat16{S.x0, d.Rk}; ops.m[2] = Mat16{S.x1, d.Rk};
+  } else {           // A = X (scaled irs), B = H^t (scaled rs)
+    conv16<TE>(ConvArgs{Xn, nullptr, N, R, R, nullptr, irs, S.x0, nullptr, 0, d.Np, d.Rk, d.Rk}, false, s);
+    conv16<TE>(ConvArgs{Xmu, Xn, N, R, R, nullptr, irs, S.x1, nullptr, 0, d.Np, d.Rk, d.Rk}, false, s);
+    conv16<TE>(ConvArgs{F, nullptr, R, T, T, rs, nullptr, S.fb_hi, nullptr, 0, d.Tp, d.Rk, d.Rk}, true, s);
+    ops.m[0] = Mat16{S.x0, d.Rk}; ops.m[1] = Mat16{S.x1, d.Rk}; ops.m[2] = Mat16{S.fb_hi, d.Rk};
   }
+  prof_end(side == 0 ? "conv16c_H" : "conv16c_W", s);
+  const dim3 grid((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128));
+  const size_t lb = (size_t)Gemm16<G128, TE, CH_P>::LDS_ELEMS * 2;
+  prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
+  if (side == 0) {
+    lds_attr(k_cost16<TE, 0>, lb);
+    hipLaunchKernelGGL((k_cost16<TE, 0>), grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
+  } else {
+    lds_attr(k_cost16<TE, 1>, lb);
+    hipLaunchKernelGGL((k_cost16<TE, 1>), grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
+  }
+  prof_end(side == 0 ? "cost16_H" : "cost16_W", s);
   return hipGetLastError();
 }
 

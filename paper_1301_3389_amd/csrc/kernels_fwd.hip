@@ -344,8 +344,10 @@ __global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu,
   const bool ok = t < T;
   double den = 0.0;
   if (ok) {
+#pragma unroll 4
     for (int64_t r = rg; r < R; r += CAND_RG) {
       float u = 0.f, uc = 0.f, y = 0.f;
+#pragma unroll 4
       for (int sp = 0; sp < splits; ++sp) {
         u += pu[(sp * R + r) * T + t];
         uc += puc[(sp * R + r) * T + t];
@@ -371,6 +373,7 @@ __global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu,
   __syncthreads();
   if (ok) {
     const double f = fac[cl];
+#pragma unroll 4
     for (int64_t r = rg; r < R; r += CAND_RG)
       Xn[r * T + t] = fmaxf((float)((double)Xn[r * T + t] * f), VALUE_FLOOR);
   }
