@@ -54,35 +54,6 @@ struct Mat16 {
   int64_t ld;
 };
 
-// Registers of one MN x BK tile in flight: 16-byte chunks of 8 k-values.
-template <int MN, int BK, int NT>
-struct Ld16 {
-  static constexpr int CPR = BK / 8;
-  static constexpr int CH = MN * CPR;
-  static_assert(CH % NT == 0, "tile chunks must divide among the threads");
-  static constexpr int PT = CH / NT;
-  static constexpr int PITCH = BK + 8;
-  u32x4 r[PT];
-
-  __device__ __forceinline__ void load(const Mat16& m, int64_t mn0, int64_t k0, int tid) {
-    const uint16_t* p = reinterpret_cast<const uint16_t*>(m.p);
-#pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const int f = tid + i * NT;
-      const int row = f / CPR, kq = (f % CPR) * 8;
-      r[i] = *reinterpret_cast<const u32x4*>(p + (mn0 + row) * m.ld + k0 + kq);
-    }
-  }
-  __device__ __forceinline__ void store(uint16_t* lds, int tid) const {
-#pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const int f = tid + i * NT;
-      const int row = f / CPR, kq = (f % CPR) * 8;
-      *reinterpret_cast<u32x4*>(lds + row * PITCH + kq) = r[i];
-    }
-  }
-};
-
 // Product list: product c adds A operand aof(c) times B operand bof(c) into
 // accumulator cof(c).  NACC accumulators in all.
 template <int NA_, int NB_, int NC_, int NACC_, int A0, int B0, int C0, int A1 = 0, int B1 = 0, int C1 = 0,
@@ -94,34 +65,71 @@ struct Prods {
   __device__ __forceinline__ static constexpr int cof(int c) { return c == 0 ? C0 : (c == 1 ? C1 : C2); }
 };
 
-// The K loop over k in [k0, k1), (k1 - k0) a multiple of BK.  LDS holds two
-// buffers of NA A tiles and NB B tiles (uint16_t elements, LDS_ELEMS in all);
-// the next K tile is loaded into registers while the current one feeds the
-// matrix cores, one barrier per K tile.
-template <class G, typename TE, class PR>
+// s_waitcnt immediate that waits until at most n vector-memory operations of
+// this wave are outstanding (gfx9 encoding: vmcnt in bits 3:0 and 15:14;
+// expcnt and lgkmcnt left at their no-wait maxima).
+__host__ __device__ constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// The K loop over k in [k0, k1), (k1 - k0) a multiple of BK = 32.
+//
+// Operand tiles go from global memory straight into LDS (global_load_lds, 16
+// bytes per lane) through STAGES ring buffers, so that STAGES - 1 K tiles are
+// in flight while one feeds the matrix cores; one barrier per K tile.  A tile is
+// MN rows of 64 bytes (32 k-values); the 16-byte chunk cq of row r sits at
+// chunk position cq ^ ((r >> 2) & 3) of that row, which makes the 16-lane
+// passes of the fragment reads hit 64 distinct banks.  The DMA writes 64
+// consecutive chunks per wave instruction, so each lane fetches the global
+// chunk that belongs at its position.
+template <class G, typename TE, class PR, int STAGES>
 struct Gemm16 {
   static constexpr int NA = PR::NA, NB = PR::NB, NC = PR::NC, NACC = PR::NACC;
-  static constexpr int BUF = NA * G::TA + NB * G::TB;
-  static constexpr int LDS_ELEMS = 2 * BUF;
+  static_assert(G::BK == 32, "tile rows are 64 bytes");
+  static constexpr int TAB = G::BM * 64, TBB = G::BN * 64;          // bytes per A / B tile
+  static constexpr int STAGE_BYTES = NA * TAB + NB * TBB;
+  static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
+  static constexpr int LOADS = NA * (G::BM / 64) + NB * (G::BN / 64); // DMA instructions per thread and stage
   typedef typename MF<TE>::v8 V8;
 
-  __device__ __forceinline__ static void compute(const uint16_t* buf, f32x16 (&acc)[G::FM][G::FN][NACC], int lane,
-                                                 int wm, int wn) {
+  template <int MN>
+  __device__ __forceinline__ static void issue(const Mat16& m, int64_t mn0, int64_t k0, char* tile, int tid) {
+    const int wave = tid >> 6, lane = tid & 63;
+    const char* base = reinterpret_cast<const char*>(m.p);
 #pragma unroll
-    for (int kk = 0; kk < G::BK / 16; ++kk) {
-      const int ko = kk * 16 + 8 * (lane >> 5);
+    for (int i = 0; i < MN / 64; ++i) {
+      const int b = i * 4 + wave;                 // 1 KiB block of the tile written by this instruction
+      const int p = b * 64 + lane;                // chunk position in the tile
+      const int r = p >> 2, cq = (p & 3) ^ ((r >> 2) & 3);
+      const char* g = base + ((mn0 + r) * m.ld + k0 + cq * 8) * 2;
+      __builtin_amdgcn_global_load_lds((void*)g, (__attribute__((address_space(3))) void*)(tile + b * 1024), 16, 0, 0);
+    }
+  }
+
+  __device__ __forceinline__ static void issue_stage(const Mat16 (&A)[NA], const Mat16 (&B)[NB], int64_t m0, int64_t n0,
+                                                     int64_t k, char* st, int tid) {
+#pragma unroll
+    for (int x = 0; x < NA; ++x) issue<G::BM>(A[x], m0, k, st + x * TAB, tid);
+#pragma unroll
+    for (int y = 0; y < NB; ++y) issue<G::BN>(B[y], n0, k, st + NA * TAB + y * TBB, tid);
+  }
+
+  __device__ __forceinline__ static V8 frag(const char* tile, int row, int cq) {
+    return *reinterpret_cast<const V8*>(tile + row * 64 + ((cq ^ ((row >> 2) & 3)) << 4));
+  }
+
+  __device__ __forceinline__ static void compute(const char* st, f32x16 (&acc)[G::FM][G::FN][NACC], int lane, int wm,
+                                                 int wn) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int cq = 2 * kk + (lane >> 5);
       V8 af[NA][G::FM], bf[NB][G::FN];
 #pragma unroll
       for (int x = 0; x < NA; ++x)
 #pragma unroll
-        for (int i = 0; i < G::FM; ++i)
-          af[x][i] = *reinterpret_cast<const V8*>(buf + x * G::TA + (wm * G::WM + i * 32 + (lane & 31)) * G::PITCH + ko);
+        for (int i = 0; i < G::FM; ++i) af[x][i] = frag(st + x * TAB, wm * G::WM + i * 32 + (lane & 31), cq);
 #pragma unroll
       for (int y = 0; y < NB; ++y)
 #pragma unroll
-        for (int j = 0; j < G::FN; ++j)
-          bf[y][j] = *reinterpret_cast<const V8*>(buf + NA * G::TA + y * G::TB +
-                                                  (wn * G::WN + j * 32 + (lane & 31)) * G::PITCH + ko);
+        for (int j = 0; j < G::FN; ++j) bf[y][j] = frag(st + NA * TAB + y * TBB, wn * G::WN + j * 32 + (lane & 31), cq);
 #pragma unroll
       for (int i = 0; i < G::FM; ++i)
 #pragma unroll
@@ -132,45 +140,63 @@ struct Gemm16 {
     }
   }
 
+  // Wait for this thread's DMA of the oldest outstanding stage (N younger
+  // stages may stay in flight), then make every thread's data visible.
+  template <int N>
+  __device__ __forceinline__ static void wait_stage() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(N * LOADS));
+    asm volatile("s_barrier" ::: "memory");
+  }
+
   __device__ __forceinline__ static void run(const Mat16 (&A)[NA], const Mat16 (&B)[NB], int64_t m0, int64_t n0,
-                                             int64_t k0, int64_t k1, uint16_t* lds,
+                                             int64_t k0, int64_t k1, char* lds,
                                              f32x16 (&acc)[G::FM][G::FN][NACC]) {
+    static_assert(STAGES >= 2 && STAGES <= 4, "2 to 4 stages");
+    static_assert((STAGES - 1) * LOADS <= 63, "vmcnt holds at most 63 outstanding operations");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % G::WGM, wn = wave / G::WGM;
     const int64_t nk = (k1 - k0) / G::BK;
     if (nk <= 0) return;
-    Ld16<G::BM, G::BK, G::NT> la[NA];
-    Ld16<G::BN, G::BK, G::NT> lb[NB];
-#pragma unroll
-    for (int x = 0; x < NA; ++x) la[x].load(A[x], m0, k0, tid);
-#pragma unroll
-    for (int y = 0; y < NB; ++y) lb[y].load(B[y], n0, k0, tid);
-#pragma unroll
-    for (int x = 0; x < NA; ++x) la[x].store(lds + x * G::TA, tid);
-#pragma unroll
-    for (int y = 0; y < NB; ++y) lb[y].store(lds + NA * G::TA + y * G::TB, tid);
+    // all earlier LDS use of the block (a previous epilogue) is finished
     __syncthreads();
+#pragma unroll
+    for (int s = 0; s < STAGES - 1; ++s)
+      if (s < nk) issue_stage(A, B, m0, n0, k0 + s * G::BK, lds + s * STAGE_BYTES, tid);
     for (int64_t kt = 0; kt < nk; ++kt) {
-      const bool more = kt + 1 < nk;
-      if (more) {
-        const int64_t kn = k0 + (kt + 1) * G::BK;
-#pragma unroll
-        for (int x = 0; x < NA; ++x) la[x].load(A[x], m0, kn, tid);
-#pragma unroll
-        for (int y = 0; y < NB; ++y) lb[y].load(B[y], n0, kn, tid);
-      }
-      compute(lds + (kt & 1) * BUF, acc, lane, wm, wn);
-      if (more) {
-        uint16_t* nb = lds + ((kt + 1) & 1) * BUF;
-#pragma unroll
-        for (int x = 0; x < NA; ++x) la[x].store(nb + x * G::TA, tid);
-#pragma unroll
-        for (int y = 0; y < NB; ++y) lb[y].store(nb + NA * G::TA + y * G::TB, tid);
-      }
-      __syncthreads();
+      // stages issued so far: min(kt + STAGES - 2, nk - 1); younger than kt: that minus kt
+      const int64_t younger = std::min<int64_t>(STAGES - 2, nk - 1 - kt);
+      if (younger >= 2) wait_stage<2>();
+      else if (younger == 1) wait_stage<1>();
+      else wait_stage<0>();
+      const int64_t kn = kt + STAGES - 1;
+      if (kn < nk) issue_stage(A, B, m0, n0, k0 + kn * G::BK, lds + (kn % STAGES) * STAGE_BYTES, tid);
+      compute(lds + (kt % STAGES) * STAGE_BYTES, acc, lane, wm, wn);
     }
+    // the epilogue may reuse the LDS: every wave is done with its last stage
+    __syncthreads();
   }
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap the dispatch order so that every XCD receives one contiguous range of
+// the logical tile order (x fastest): tiles that are neighbours along x -- and
+// share an operand block -- then run on the same XCD at the same time.
+struct Tile3 {
+  int64_t x, y, z;
+};
+__device__ __forceinline__ Tile3 xcd_tile() {
+  const int64_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int64_t total = gx * gy * gz;
+  const int64_t b = (int64_t)blockIdx.x + gx * ((int64_t)blockIdx.y + gy * (int64_t)blockIdx.z);
+  const int64_t q = total / 8, rem = total % 8, x = b % 8, s = b / 8;
+  const int64_t L = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + s;
+  Tile3 t;
+  t.x = L % gx;
+  t.y = (L / gx) % gy;
+  t.z = L / (gx * gy);
+  return t;
+}
 
 template <class G>
 __device__ __forceinline__ int64_t row16(int64_t m0, int i, int v) {

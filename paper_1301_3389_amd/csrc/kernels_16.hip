@@ -165,17 +165,24 @@ template <> struct ZProds<1> { typedef Prods<1, 2, 2, 1, 0, 1, 0, 0, 0, 0> P; };
 template <> struct ZProds<2> { typedef Prods<2, 1, 2, 1, 1, 0, 0, 0, 0, 0> P; };          // A split
 template <> struct ZProds<3> { typedef Prods<2, 2, 3, 1, 1, 0, 0, 0, 1, 0, 0, 0, 0> P; }; // both
 
-constexpr int OUT_PITCH = 128 + 8;   // LDS pitch of the 128 x 128 output staging tile
+constexpr int OUT_PITCH = 128 + 8;   // LDS pitch of the 128 x 128 output staging tiles
+constexpr int RATIO_OUT_BYTES = 3 * 128 * OUT_PITCH * 2;
+
+constexpr int RATIO_STAGES = 4, GH_STAGES = 3, COST_STAGES = 4;
+
+template <typename TE, int SPLIT>
+using ZEng = Gemm16<G128, TE, typename ZProds<SPLIT>::P, RATIO_STAGES>;
 
 template <typename TE, int SIDE, bool MAXONLY, int SPLIT>
 __global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
   using G = G128;
   typedef typename ZProds<SPLIT>::P PR;
-  typedef Gemm16<G, TE, PR> E;
-  static_assert(E::LDS_ELEMS >= 128 * OUT_PITCH, "output staging must fit in the operand LDS");
-  extern __shared__ __align__(16) uint16_t lds_dyn[];
-  uint16_t* lds = lds_dyn;
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
+  typedef ZEng<TE, SPLIT> E;
+  // launched with at least RATIO_OUT_BYTES of dynamic LDS (the staging tiles)
+  extern __shared__ __align__(16) char lds_dyn[];
+  char* lds = lds_dyn;
+  const Tile3 tl = xcd_tile();
+  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
   const int64_t N = a.N, T = a.T;
   if (!MAXONLY) sum_job(a.fin);
   float vf[G::FM][G::FN][16];
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
             if (row16<G>(m0, i, v) < N && col < T) cp[0][j] += (double)vf[i][j][v];
       }
       reduce_cols<G, 1>(cp, red, [&](int c, const double (&s)[1]) {
-        if (n0 + c < T) a.vpart[(int64_t)blockIdx.y * T + n0 + c] = s[0];
+        if (n0 + c < T) a.vpart[tl.y * T + n0 + c] = s[0];
       });
     } else {
       double rp[1][G::FM][16];
@@ -290,53 +297,85 @@ __global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
             if (row < N && col16<G>(n0, j) < T) rp[0][i][v] += (double)vf[i][j][v];
         }
       reduce_rows<G, 1>(rp, red, [&](int r, const double (&s)[1]) {
-        if (m0 + r < N) a.vpart[(int64_t)blockIdx.x * N + m0 + r] = s[0];
+        if (m0 + r < N) a.vpart[tl.x * N + m0 + r] = s[0];
       });
     }
   }
-  // the three outputs, one at a time through the LDS staging tile
+  // The three outputs in one pass through three LDS staging tiles.  In the H
+  // step (transposed tiles, [t][n]) the four consecutive rows a lane holds per
+  // group of four accumulator slots are adjacent: one 8-byte store.
   TE* st = reinterpret_cast<TE*>(lds);
   int bad = 0;
-#pragma unroll 1
-  for (int o = 0; o < 3; ++o) {
-    __syncthreads();
+  __syncthreads();
 #pragma unroll
-    for (int i = 0; i < G::FM; ++i)
+  for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-      for (int j = 0; j < G::FN; ++j) {
-        const int64_t col = col16<G>(n0, j);
-        const int cl = (int)(col - n0);
+    for (int j = 0; j < G::FN; ++j) {
+      const int64_t col = col16<G>(n0, j);
+      const int cl = (int)(col - n0);
+      const float s0 = (SIDE == 0 && a.qs[0] && col < T) ? a.qs[0][col] : 1.f;
+      const float s1 = (SIDE == 0 && a.qs[1] && col < T) ? a.qs[1][col] : 1.f;
+      const float s2 = (SIDE == 0 && a.qs[2] && col < T) ? a.qs[2][col] : 1.f;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
+      for (int g = 0; g < 4; ++g) {
+        TE out[3][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int v = 4 * g + u;
           const int64_t row = row16<G>(m0, i, v);
-          const int rl = (int)(row - m0);
-          float val = 0.f;
+          float q = 0.f, qc = 0.f, qb = 0.f;
           if (row < N && col < T) {
             const float x = vf[i][j][v], z = acc[i][j][0][v];
             const bool pos = x > 0.f;
             const float iz = __builtin_amdgcn_rcpf(z);
-            if (o == 0) val = pos ? x * iz : 0.f;
-            else if (o == 1) val = pos ? (x - z) * iz : -1.f;
-            else val = pos ? x * iz * iz : 0.f;
-            if (o == 0) bad |= (pos && !(z > 0.f)) ? 1 : 0;
-            if (a.qs[o]) val *= a.qs[o][SIDE == 0 ? col : row];
+            q = pos ? x * iz : 0.f;
+            qc = pos ? (x - z) * iz : -1.f;
+            qb = q * iz;
+            bad |= (pos && !(z > 0.f)) ? 1 : 0;
+            if (SIDE == 0) {
+              q *= s0; qc *= s1; qb *= s2;
+            } else {
+              if (a.qs[0]) q *= a.qs[0][row];
+              if (a.qs[1]) qc *= a.qs[1][row];
+              if (a.qs[2]) qb *= a.qs[2][row];
+            }
           }
-          if (SIDE == 0) st[cl * OUT_PITCH + rl] = (TE)val;
-          else st[rl * OUT_PITCH + cl] = (TE)val;
+          out[0][u] = (TE)q;
+          out[1][u] = (TE)qc;
+          out[2][u] = (TE)qb;
+        }
+        const int rl0 = (int)(row16<G>(m0, i, 4 * g) - m0);    // rows rl0 .. rl0 + 3
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          TE* t = st + o * 128 * OUT_PITCH;
+          if (SIDE == 0) {
+            typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+            u32x2 w;
+            w[0] = (unsigned)__builtin_bit_cast(uint16_t, out[o][0]) |
+                   ((unsigned)__builtin_bit_cast(uint16_t, out[o][1]) << 16);
+            w[1] = (unsigned)__builtin_bit_cast(uint16_t, out[o][2]) |
+                   ((unsigned)__builtin_bit_cast(uint16_t, out[o][3]) << 16);
+            *reinterpret_cast<u32x2*>(t + cl * OUT_PITCH + rl0) = w;
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[(rl0 + u) * OUT_PITCH + cl] = out[o][u];
+          }
         }
       }
-    __syncthreads();
-    // copy out: 128 rows of 128 elements, 16-byte chunks
+    }
+  __syncthreads();
+  // copy out: three tiles of 128 rows of 128 elements, 16-byte chunks
+  {
     const int64_t ld = SIDE == 0 ? a.Np : a.Tp;
     const int64_t r0 = SIDE == 0 ? n0 : m0, c0 = SIDE == 0 ? m0 : n0;
-    uint16_t* dst = reinterpret_cast<uint16_t*>(a.q3) + (int64_t)o * a.Np * a.Tp;
     const uint16_t* src = reinterpret_cast<const uint16_t*>(st);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 24; ++k) {
       const int f = threadIdx.x + k * 256;
-      const int rr = f / 16, ch = (f % 16) * 8;
+      const int o = f / 2048, rr = (f % 2048) / 16, ch = (f % 16) * 8;
+      uint16_t* dst = reinterpret_cast<uint16_t*>(a.q3) + (int64_t)o * a.Np * a.Tp;
       *reinterpret_cast<u32x4*>(dst + (r0 + rr) * ld + c0 + ch) =
-          *reinterpret_cast<const u32x4*>(src + rr * OUT_PITCH + ch);
+          *reinterpret_cast<const u32x4*>(src + o * 128 * OUT_PITCH + rr * OUT_PITCH + ch);
     }
   }
   if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
@@ -370,10 +409,13 @@ __global__ __launch_bounds__(256) void k_gh16(Ops16 ops, int64_t M, int64_t Ncol
                                               Fold f) {
   using G = G128;
   typedef typename std::conditional<SIDE == 0, GHH_P, GHW_P>::type PR;
-  typedef Gemm16<G, TE, PR> E;
-  extern __shared__ __align__(16) uint16_t lds_dyn[];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
-  const int64_t sp = blockIdx.z;
+  typedef Gemm16<G, TE, PR, GH_STAGES> E;
+  extern __shared__ __align__(16) char lds_dyn[];
+  // grid x walks the tiles that share the large operand block: SIDE 0 (r-blocks,
+  // t-blocks) share Q^t, SIDE 1 (r-blocks, n-blocks) share Q
+  const Tile3 tl = xcd_tile();
+  const int64_t m0 = (SIDE == 0 ? tl.x : tl.y) * G::BM, n0 = (SIDE == 0 ? tl.y : tl.x) * G::BN;
+  const int64_t sp = tl.z;
   const int64_t k0 = sp * kchunk, k1 = std::min<int64_t>(K32, k0 + kchunk);
   f32x16 acc[G::FM][G::FN][3];
   zero16<G, 3>(acc);
@@ -417,10 +459,11 @@ __global__ __launch_bounds__(256) void k_cost16(const float* V, Ops16 ops, int64
                                                 int64_t Rk, double* part, int* fpart) {
   using G = G128;
   typedef typename std::conditional<SIDE == 0, CH_P, CW_P>::type PR;
-  typedef Gemm16<G, TE, PR> E;
-  extern __shared__ __align__(16) uint16_t lds_dyn[];
+  typedef Gemm16<G, TE, PR, COST_STAGES> E;
+  extern __shared__ __align__(16) char lds_dyn[];
   __shared__ int fl_s[128];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
+  const Tile3 tl = xcd_tile();
+  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
   const int tid = threadIdx.x;
   if (tid < 128) fl_s[tid] = 0;
   float vf[G::FM][G::FN][16];
@@ -444,10 +487,10 @@ __global__ __launch_bounds__(256) void k_cost16(const float* V, Ops16 ops, int64
   }
   double* red = reinterpret_cast<double*>(lds_dyn);
   if (SIDE == 0) {
-    const int64_t base = (int64_t)blockIdx.y * T, stride = (int64_t)gridDim.y * T;
+    const int64_t base = tl.y * T, stride = (int64_t)gridDim.y * T;
     cost_cols<G>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
   } else {
-    const int64_t base = (int64_t)blockIdx.x * N, stride = (int64_t)gridDim.x * N;
+    const int64_t base = tl.x * N, stride = (int64_t)gridDim.x * N;
     cost_rows<G>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
   }
 }
@@ -531,8 +574,8 @@ static void lds_attr(F* fn, size_t bytes) {
 }
 
 template <typename K>
-static void launch_ratio_k(K* fn, int lds_elems, dim3 grid, const Ratio16Args& ra, hipStream_t s) {
-  const size_t lb = (size_t)lds_elems * 2;
+static void launch_ratio_k(K* fn, int lds_bytes, dim3 grid, const Ratio16Args& ra, hipStream_t s) {
+  const size_t lb = (size_t)std::max(lds_bytes, RATIO_OUT_BYTES);
   lds_attr(fn, lb);
   hipLaunchKernelGGL(fn, grid, dim3(256), lb, s, ra);
 }
@@ -584,8 +627,8 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
     for (int k = 0; k < 3; ++k) ra.qmax[k] = qbits + k * L;
     // the scales only need the maxima to a few bits: unsplit product
     prof_begin("qmax16", s);
-    if (side == 0) launch_ratio_k(k_ratio16<TE, 0, true, 0>, Gemm16<G128, TE, ZProds<0>::P>::LDS_ELEMS, rgrid, ra, s);
-    else launch_ratio_k(k_ratio16<TE, 1, true, 0>, Gemm16<G128, TE, ZProds<0>::P>::LDS_ELEMS, rgrid, ra, s);
+    if (side == 0) launch_ratio_k(k_ratio16<TE, 0, true, 0>, ZEng<TE, 0>::LDS_BYTES, rgrid, ra, s);
+    else launch_ratio_k(k_ratio16<TE, 1, true, 0>, ZEng<TE, 0>::LDS_BYTES, rgrid, ra, s);
     prof_end("qmax16", s);
     for (int k = 0; k < 3; ++k) {
       hipLaunchKernelGGL(k_scales, dim3(grid1(L)), dim3(256), 0, s, qbits + k * L, L, 13, S.qs + k * L,
@@ -596,11 +639,11 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
   }
   prof_begin(side == 0 ? "ratio16_H" : "ratio16_W", s);
   if (side == 0) {
-    if (split == 1) launch_ratio_k(k_ratio16<TE, 0, false, 1>, Gemm16<G128, TE, ZProds<1>::P>::LDS_ELEMS, rgrid, ra, s);
-    else launch_ratio_k(k_ratio16<TE, 0, false, 3>, Gemm16<G128, TE, ZProds<3>::P>::LDS_ELEMS, rgrid, ra, s);
+    if (split == 1) launch_ratio_k(k_ratio16<TE, 0, false, 1>, ZEng<TE, 1>::LDS_BYTES, rgrid, ra, s);
+    else launch_ratio_k(k_ratio16<TE, 0, false, 3>, ZEng<TE, 3>::LDS_BYTES, rgrid, ra, s);
   } else {
-    if (split == 2) launch_ratio_k(k_ratio16<TE, 1, false, 2>, Gemm16<G128, TE, ZProds<2>::P>::LDS_ELEMS, rgrid, ra, s);
-    else launch_ratio_k(k_ratio16<TE, 1, false, 3>, Gemm16<G128, TE, ZProds<3>::P>::LDS_ELEMS, rgrid, ra, s);
+    if (split == 2) launch_ratio_k(k_ratio16<TE, 1, false, 2>, ZEng<TE, 2>::LDS_BYTES, rgrid, ra, s);
+    else launch_ratio_k(k_ratio16<TE, 1, false, 3>, ZEng<TE, 3>::LDS_BYTES, rgrid, ra, s);
   }
   prof_end(side == 0 ? "ratio16_H" : "ratio16_W", s);
 
@@ -617,7 +660,7 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
     ops.m[0] = Mat16{S.g0, d.Np}; ops.m[1] = Mat16{S.g1, d.Np};
     for (int k = 0; k < 3; ++k) ops.m[2 + k] = Mat16{q + k * npt, d.Np};
     M = R; Ncol = T; K32 = cdiv(N, 32) * 32;
-    grid = dim3((unsigned)(d.Tp / 128), (unsigned)(d.Rm / 128), (unsigned)splits);
+    grid = dim3((unsigned)(d.Rm / 128), (unsigned)(d.Tp / 128), (unsigned)splits);
   } else {           // rows n carry the Q scales, columns r the H scale
     const float* cc[3] = {irs, irs, irs2};
     for (int k = 0; k < 3; ++k) { f.r[k] = iqs[k]; f.c[k] = cc[k]; }
@@ -626,7 +669,7 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
     M = N; Ncol = R; K32 = cdiv(T, 32) * 32;
     grid = dim3((unsigned)(d.Rm / 128), (unsigned)(d.Np / 128), (unsigned)splits);
   }
-  const size_t lb = (size_t)Gemm16<G128, TE, GHH_P>::LDS_ELEMS * 2;
+  const size_t lb = (size_t)Gemm16<G128, TE, GHH_P, GH_STAGES>::LDS_BYTES;
   prof_begin(side == 0 ? "gh16_H" : "gh16_W", s);
   if (side == 0) {
     lds_attr(k_gh16<TE, 0>, lb);
@@ -667,7 +710,7 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
   }
   prof_end(side == 0 ? "conv16c_H" : "conv16c_W", s);
   const dim3 grid((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128));
-  const size_t lb = (size_t)Gemm16<G128, TE, CH_P>::LDS_ELEMS * 2;
+  const size_t lb = (size_t)Gemm16<G128, TE, CH_P, COST_STAGES>::LDS_BYTES;
   prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
   if (side == 0) {
     lds_attr(k_cost16<TE, 0>, lb);
