@@ -53,6 +53,86 @@ def kernel_work(name, N, T, R):
     return table.get(name)
 
 
+def kernel_key(rocprof_name):
+    """Bench kernel key of a rocprofv3 kernel name (the names prof_begin uses)."""
+    import re
+    nm = rocprof_name.split("(")[0].replace("void ", "").replace("dna::", "")
+    base = re.sub(r"<.*>", "", nm)
+    targs = re.search(r"<(.*)>", nm)
+    side = None
+    if targs:
+        parts = [t.strip() for t in targs.group(1).split(",")]
+        if base in ("k_gh16", "k_cost16") and len(parts) >= 2:
+            side = parts[1]
+        if base == "k_ratio16" and len(parts) >= 3:
+            side, maxonly = parts[1], parts[2]
+            if maxonly == "true":
+                return "qmax16"
+        if base == "k_ratio":
+            return {"0": "ratio_H", "1": "ratio_W"}.get(parts[0], "ratio_" + parts[0])
+    if side is not None:
+        return base[2:] + ("_H" if side == "0" else "_W")
+    return base[2:] if base.startswith("k_") else base
+
+
+def source_hash():
+    """Hash of the HIP sources: traffic counters are only valid for the build they were taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1301_3389_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_summary(args):
+    """Write profiles/traffic_<tag>.json from four rocprofv3 --pmc output folders: FETCH_SIZE and
+    WRITE_SIZE of the benchmark, and of the plain copy (--copy-calibration) that scales them."""
+    import csv
+    import glob
+
+    def per_kernel(folder, counter):
+        f = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)[0]
+        acc = {}
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(kernel_key(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write, cfetch, cwrite = args.traffic_summary
+    copy_bytes = 256 * 1024 * 1024
+    cf = max(v for k, v in per_kernel(cfetch, "FETCH_SIZE").items() if "copy" in k.lower())
+    cw = max(v for k, v in per_kernel(cwrite, "WRITE_SIZE").items() if "copy" in k.lower())
+    out = {"source_hash": source_hash(), "unit": "bytes per dispatch",
+           "fetch_scale": copy_bytes / (cf * 1024), "write_scale": copy_bytes / (cw * 1024),
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "kernels": {}}
+    fk, wk = per_kernel(fetch, "FETCH_SIZE"), per_kernel(write, "WRITE_SIZE")
+    for k in sorted(set(fk) & set(wk)):
+        out["kernels"][k] = {"fetch_kib": fk[k], "write_kib": wk[k],
+                             "bytes": fk[k] * 1024 * out["fetch_scale"] + wk[k] * 1024 * out["write_scale"]}
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.traffic_tag}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(path)
+
+
+def traffic_of(kernel, tag):
+    """Measured HBM bytes per launch of `kernel` from profiles/traffic_<tag>.json, or None when
+    the file is missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,7 +149,14 @@ def parse():
                     help="operand type of the DNA matrix products (16-bit: FP32 accumulate, FP64 sums)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (HBM counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write profiles/traffic_<tag>.json from four rocprofv3 --pmc output folders")
+    ap.add_argument("--traffic-tag", default=None, help="tag of the traffic file (default: workload tag)")
     return ap.parse_args()
+
+
+def workload_tag(config, gemm):
+    return f"config{config}_{gemm}"
 
 
 def copy_calibration():
@@ -146,6 +233,11 @@ def cpu_baseline(w, seconds):
 
 def main():
     args = parse()
+    if args.traffic_tag is None:
+        args.traffic_tag = workload_tag(args.config, args.gemm)
+    if args.traffic_summary:
+        traffic_summary(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -210,7 +302,10 @@ def main():
     achieved = flops / (rec["avg_ms"] * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if gemm == "fp32" else PEAK_16_TFLOPS
     roofline = {"bound": "mfma", "kernel": dom, "avg_ms": rec["avg_ms"], "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic_of(dom, args.traffic_tag)}
+    if roofline["traffic"] is not None:
+        roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     alg_flops_iter = 16.0 * N * R * T
     gflops = alg_flops_iter * value / 1e9

@@ -96,9 +96,21 @@ static Split choose_split(int64_t K, int64_t base_tiles) {
   return s;
 }
 
+// Chunks of the fused kernels along the contraction (multiples of 64), aiming
+// at two workgroups per CU.
+static Split fused_split(int64_t K, int64_t base_tiles) {
+  int64_t sp = std::max<int64_t>(1, cdiv(2 * 256, std::max<int64_t>(1, base_tiles)));
+  sp = std::min<int64_t>(sp, cdiv(K, 64));
+  Split s;
+  s.kchunk = cdiv(cdiv(K, sp), 64) * 64;
+  s.splits = (int)cdiv(K, s.kchunk);
+  return s;
+}
+
 struct Layout {
   Split sh, sw;              // split-K of the fp32 gradient products (H / W orientation)
   Split sh16, sw16;          // the same for the 16-bit products (128 x 128 tiles)
+  Split shf, swf;            // row / column chunks of the fused kernels (R <= FUSED_MAX_R)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
   size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, vpart, cpart, fpart, s16, check, total;
@@ -112,15 +124,18 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   L.sw = choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM));
   L.sh16 = choose_split(N, cdiv(T, 128) * cdiv(R, 128));
   L.sw16 = choose_split(T, cdiv(R, 128) * cdiv(N, 128));
+  L.shf = fused_split(N, cdiv(T, 64));
+  L.swf = fused_split(T, cdiv(N, 64));
   L.rt_m = (int)cdiv(N, RT_BM);
   L.rt_n = (int)cdiv(T, RT_BN);
   L.ch_m = (int)cdiv(N, CH_BM);
   L.cw_n = (int)cdiv(T, CW_BN);
   const size_t nt = (size_t)N * T, fac = (size_t)std::max(R * T, N * R);
-  const int64_t sph = std::max(L.sh.splits, L.sh16.splits), spw = std::max(L.sw.splits, L.sw16.splits);
+  const int64_t sph = std::max({L.sh.splits, L.sh16.splits, L.shf.splits});
+  const int64_t spw = std::max({L.sw.splits, L.sw16.splits, L.swf.splits});
   const size_t psplit = (size_t)std::max<int64_t>(sph * R * T, spw * N * R);
-  const size_t red = (size_t)std::max(std::max<int64_t>((int64_t)L.rt_m * T, (int64_t)L.rt_n * N),
-                                      std::max<int64_t>((int64_t)L.ch_m * T, (int64_t)L.cw_n * N));
+  const size_t red = (size_t)std::max({(int64_t)L.rt_m * T, (int64_t)L.rt_n * N, (int64_t)L.ch_m * T,
+                                       (int64_t)L.cw_n * N, sph * T, spw * N});
   const size_t klt = (size_t)L.rt_m * L.rt_n;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -266,30 +281,40 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
     job.s64 = c64; job.s32 = c32; job.check = chk;
     ra.fin = job;                                   // c = W^t 1 finished inside the ratio pass
+    const bool fused = !p16 && R <= FUSED_MAX_R;
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh16.splits, L.sh16.kchunk, pu, puc, py,
                                 vpart, chk, job, s), "ratio_gh16_H");
+    } else if (fused) {
+      DNA_HIP(launch_rgh(0, V, W, H, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, job, chk, s),
+              "rgh_H");
     } else {
       DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
       DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
     }
     // the 16-bit Z pass tiles N by 128 like the fp32 one (RT_BM)
-    DNA_HIP(launch_cand_H(H, pu, puc, py, p16 ? L.sh16.splits : L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps,
-                          o->alpha, Xmu, Xn, Aout, Bout, s), "cand_H");
+    const int sp = p16 ? L.sh16.splits : (fused ? L.shf.splits : L.sh.splits);
+    DNA_HIP(launch_cand_H(H, pu, puc, py, sp, c32, vpart, fused ? L.shf.splits : L.rt_m, T, R, o->eps, o->alpha,
+                          Xmu, Xn, Aout, Bout, s), "cand_H");
   } else {
     DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, s), "rowsum_H");
     job.s64 = c64; job.s32 = c32; job.check = chk;
     ra.fin = job;                                   // c' = H 1 finished inside the ratio pass
+    const bool fused = !p16 && R <= FUSED_MAX_R;
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw16.splits, L.sw16.kchunk, pu, puc, py,
                                 vpart, chk, job, s), "ratio_gh16_W");
+    } else if (fused) {
+      DNA_HIP(launch_rgh(1, V, W, H, N, T, R, L.swf.splits, L.swf.kchunk, pu, puc, py, vpart, job, chk, s),
+              "rgh_W");
     } else {
       DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
       DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc, py, s), "gh_W");
     }
     // the 16-bit Z pass tiles T by 128, the fp32 one by RT_BN
-    DNA_HIP(launch_cand_W(W, pu, puc, py, p16 ? L.sw16.splits : L.sw.splits, c32, vpart,
-                          p16 ? (int)cdiv(T, 128) : L.rt_n, N, R, o->eps, o->alpha, Xmu, Xn, Aout, Bout, s),
+    const int sp = p16 ? L.sw16.splits : (fused ? L.swf.splits : L.sw.splits);
+    const int tiles = p16 ? (int)cdiv(T, 128) : (fused ? L.swf.splits : L.rt_n);
+    DNA_HIP(launch_cand_W(W, pu, puc, py, sp, c32, vpart, tiles, N, R, o->eps, o->alpha, Xmu, Xn, Aout, Bout, s),
             "cand_W");
   }
   return DNA_OK;

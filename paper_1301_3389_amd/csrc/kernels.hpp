@@ -132,6 +132,15 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s);
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
                         hipStream_t s);
 
+// Steps 2-5 and 10 in one kernel per half-step when R <= 64 (side 0: H step,
+// rows n split into `splits` chunks of `chunk`; side 1: W step, columns t split
+// likewise): the split partials of u, u_c, y and the per-split V sums, as the
+// ratio + gradient kernel pair writes them.  R > 64: hipErrorInvalidValue.
+constexpr int64_t FUSED_MAX_R = 64;
+hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
+                      int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart, const SumJob& fin,
+                      int* check, hipStream_t s);
+
 hipError_t launch_kl_final(const double* cpart, int ntiles, double* out, hipStream_t s);
 
 // Checked mode: negative or non-finite entries in a buffer.

@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
             const float iz = __builtin_amdgcn_rcpf(z);
             q = pos ? x * iz : 0.f;
             qc = pos ? (x - z) * iz : -1.f;
-            qb = q * iz;
+            qb = pos ? q * iz : 0.f;
             bad |= (pos && !(z > 0.f)) ? 1 : 0;
             if (SIDE == 0) {
               q *= s0; qc *= s1; qb *= s2;
