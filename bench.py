@@ -50,6 +50,9 @@ def kernel_work(name, N, T, R):
             f"ratio{sfx}_H": ("flops_recompute", 2 * nrt), f"ratio{sfx}_W": ("flops_recompute", 2 * nrt),
         })
     table["qmax16"] = ("flops_recompute", 2 * nrt)
+    # fused kernels (R <= 64): Z recompute + gradient products / the two reconstructions
+    table["rgh_H"] = table["rgh_W"] = ("flops", 4 * nrt)
+    table["costf_H"] = table["costf_W"] = ("flops", 4 * nrt)
     return table.get(name)
 
 

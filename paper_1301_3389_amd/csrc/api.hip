@@ -334,12 +334,21 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
       DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, L.cw_n, N, R, mask, dsel, margin, s), "select_W");
     return DNA_OK;
   }
+  const bool fused = R <= FUSED_MAX_R;   // candidates' block resident in LDS
   if (side == 0) {
-    DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_H");
-    DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.ch_m, T, R, mask, dsel, margin, s), "select_H");
+    if (fused)
+      DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.shf.splits, L.shf.kchunk, cpart, fpart, s), "costf_H");
+    else
+      DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_H");
+    DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, fused ? L.shf.splits : L.ch_m, T, R, mask, dsel, margin,
+                            s), "select_H");
   } else {
-    DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_W");
-    DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, L.cw_n, N, R, mask, dsel, margin, s), "select_W");
+    if (fused)
+      DNA_HIP(launch_costf(1, V, F, Xmu, Xn, N, T, R, L.swf.splits, L.swf.kchunk, cpart, fpart, s), "costf_W");
+    else
+      DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_W");
+    DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, fused ? L.swf.splits : L.cw_n, N, R, mask, dsel, margin,
+                            s), "select_W");
   }
   return DNA_OK;
 }

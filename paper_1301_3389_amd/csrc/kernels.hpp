@@ -141,6 +141,12 @@ hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, 
                       int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart, const SumJob& fin,
                       int* check, hipStream_t s);
 
+// Steps 7-9, 12-14 for R <= 64 with the candidates' block resident in LDS:
+// cost partials over `splits` chunks of rows n (side 0) or columns t (side 1),
+// in the layout of launch_cost_H / launch_cost_W with tiles = splits.
+hipError_t launch_costf(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
+                        int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s);
+
 hipError_t launch_kl_final(const double* cpart, int ntiles, double* out, hipStream_t s);
 
 // Checked mode: negative or non-finite entries in a buffer.

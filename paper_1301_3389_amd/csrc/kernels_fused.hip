@@ -264,6 +264,183 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   if (check && bad) atomicOr(check, CHK_DOMAIN);
 }
 
+// ---------------------------------------------------------------------------
+// Candidate costs (steps 7-9, 12-14) for R <= 64, the candidates' block
+// resident in LDS.  acc 0 = z_DNA, acc 1 = dZ = z_MU - z_DNA; cost terms as in
+// cost_acc (base-2 units, scaled by LN2 on output).
+//
+// H orientation: a workgroup owns 64 columns t (H_DNA and H_MU - H_DNA blocks,
+// [r][t]) and a range of rows n (W rows streamed, [n][r]); each lane keeps
+// float64 column partials over the whole range.  Partials: part[q][sp][t].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float* W, const float* Xmu,
+                                                    const float* Xn, int64_t N, int64_t T, int64_t R,
+                                                    int64_t nchunk, double* part, int* fpart) {
+  __shared__ __align__(16) float ln[FT];
+  __shared__ __align__(16) float ld[FT];
+  __shared__ __align__(16) float lw[FT];
+  __shared__ int fl_s[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % 2, wn = wave / 2;
+  const int64_t t0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
+  const int64_t nb0 = sp * nchunk, nb1 = std::min<int64_t>(N, nb0 + nchunk);
+  const int cl = wn * 32 + (lane & 31);
+  const int64_t col = t0 + cl;
+  if (tid < 64) fl_s[tid] = 0;
+  {
+    f32x4 a[4], b[4];
+    fetch_block(Xn, T, 0, t0, R, T, a, tid);
+    fetch_block(Xmu, T, 0, t0, R, T, b, tid);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] -= a[i];
+    store_block(ln, a, tid);
+    store_block(ld, b, tid);
+  }
+  double cp[3][GF::FN];
+  cp[0][0] = cp[1][0] = cp[2][0] = 0.0;
+  int fl = 0;
+  f32x4 wr[4];
+  float vf[16];
+  fetch_block(W, R, nb0, 0, N, R, wr, tid);
+  fetch_v(V, N, T, nb0 + wm * 32, t0 + wn * 32, lane, vf);
+  for (int64_t nb = nb0; nb < nb1; nb += 64) {
+    store_block(lw, wr, tid);
+    __syncthreads();
+    f32x16 zn, dz;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) zn[v] = dz[v] = 0.f;
+#pragma unroll 4
+    for (int k = 0; k < 64; k += 2) {
+      const int kr = k + (lane >> 5);
+      const float a = lw[(wm * 32 + (lane & 31)) * FP + kr];
+      zn = mfma32(a, ln[kr * FP + cl], zn);
+      dz = mfma32(a, ld[kr * FP + cl], dz);
+    }
+    const bool more = nb + 64 < nb1;
+    if (more) fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = nb + wm * 32 + blk_row(v, lane);
+      const float x = (row < N && col < T) ? vf[v] : 0.f;
+      fl |= cost_acc(x, zn[v], dz[v], cp[0][0], cp[1][0], cp[2][0]);
+    }
+    if (more) fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vf);
+    __syncthreads();
+  }
+  if (fl) atomicOr(&fl_s[cl], fl);
+  const int64_t stride = (int64_t)gridDim.y * T;
+  reduce_cols<GF, 3>(cp, reinterpret_cast<double*>(lw), [&](int c, const double (&s)[3]) {
+    if (t0 + c < T) {
+      part[sp * T + t0 + c] = s[0] * LN2;
+      part[stride + sp * T + t0 + c] = s[1] * LN2;
+      part[2 * stride + sp * T + t0 + c] = s[2] * LN2;
+      fpart[sp * T + t0 + c] = fl_s[c];
+    }
+  });
+}
+
+// W orientation: a workgroup owns 64 rows n (W_DNA and W_MU - W_DNA blocks,
+// [n][r]) and a range of columns t (H streamed, [r][t]).  Row partials of each
+// sub-tile are reduced across the half-wave at once (halfwave_slot_sum) and
+// kept per lane in float64.  Partials: part[q][sp][n].
+__global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float* H, const float* Xmu,
+                                                    const float* Xn, int64_t N, int64_t T, int64_t R,
+                                                    int64_t tchunk, double* part, int* fpart) {
+  __shared__ __align__(16) float ln[FT];
+  __shared__ __align__(16) float ld[FT];
+  __shared__ __align__(16) float lh[FT];
+  __shared__ int fl_s[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % 2, wn = wave / 2;
+  const int64_t n0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
+  const int64_t tb0 = sp * tchunk, tb1 = std::min<int64_t>(T, tb0 + tchunk);
+  const int tl = wn * 32 + (lane & 31);
+  if (tid < 64) fl_s[tid] = 0;
+  {
+    f32x4 a[4], b[4];
+    fetch_block(Xn, R, n0, 0, N, R, a, tid);
+    fetch_block(Xmu, R, n0, 0, N, R, b, tid);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] -= a[i];
+    store_block(ln, a, tid);
+    store_block(ld, b, tid);
+  }
+  double rs[3] = {0.0, 0.0, 0.0};                 // this lane's slot of the row partials
+  int flr[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) flr[v] = 0;
+  f32x4 hr[4];
+  float vf[16];
+  fetch_block(H, T, 0, tb0, R, T, hr, tid);
+  fetch_v(V, N, T, n0 + wm * 32, tb0 + wn * 32, lane, vf);
+  for (int64_t tb = tb0; tb < tb1; tb += 64) {
+    store_block(lh, hr, tid);
+    __syncthreads();
+    f32x16 zn, dz;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) zn[v] = dz[v] = 0.f;
+#pragma unroll 4
+    for (int k = 0; k < 64; k += 2) {
+      const int kr = k + (lane >> 5);
+      const float b = lh[kr * FP + tl];
+      const int nl = (wm * 32 + (lane & 31)) * FP + kr;
+      zn = mfma32(ln[nl], b, zn);
+      dz = mfma32(ld[nl], b, dz);
+    }
+    const bool more = tb + 64 < tb1;
+    if (more) fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
+    const int64_t col = tb + tl;
+    double s0[16], s1[16], s2[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      s0[v] = s1[v] = s2[v] = 0.0;
+      const int64_t row = n0 + wm * 32 + blk_row(v, lane);
+      const float x = (row < N && col < T) ? vf[v] : 0.f;
+      flr[v] |= cost_acc(x, zn[v], dz[v], s0[v], s1[v], s2[v]);
+    }
+    rs[0] += halfwave_slot_sum(s0, lane);
+    rs[1] += halfwave_slot_sum(s1, lane);
+    rs[2] += halfwave_slot_sum(s2, lane);
+    if (more) fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vf);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+    if (flr[v]) atomicOr(&fl_s[wm * 32 + blk_row(v, lane)], flr[v]);
+  // the two waves along t hold partials of the same rows: add them in LDS
+  double* red = reinterpret_cast<double*>(lh);
+  if ((lane & 1) == 0) {
+    const int r = wm * 32 + slot_row(lane);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) red[(q * 2 + wn) * 64 + r] = rs[q];
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.y * N;
+  if (tid < 64 && n0 + tid < N) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      part[q * stride + sp * N + n0 + tid] = (red[(q * 2) * 64 + tid] + red[(q * 2 + 1) * 64 + tid]) * LN2;
+    fpart[sp * N + n0 + tid] = fl_s[tid];
+  }
+}
+
+hipError_t launch_costf(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
+                        int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s) {
+  if (R > FUSED_MAX_R) return hipErrorInvalidValue;
+  if (side == 0) {
+    prof_begin("costf_H", s);
+    hipLaunchKernelGGL(k_costf_H, dim3((unsigned)cdiv(T, 64), (unsigned)splits), dim3(256), 0, s, V, F, Xmu, Xn, N,
+                       T, R, chunk, part, fpart);
+    prof_end("costf_H", s);
+  } else {
+    prof_begin("costf_W", s);
+    hipLaunchKernelGGL(k_costf_W, dim3((unsigned)cdiv(N, 64), (unsigned)splits), dim3(256), 0, s, V, F, Xmu, Xn, N,
+                       T, R, chunk, part, fpart);
+    prof_end("costf_W", s);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
                       int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart, const SumJob& fin,
                       int* check, hipStream_t s) {
