@@ -732,17 +732,23 @@ constexpr int SC_TCHUNK = 2048;
 __global__ __launch_bounds__(256) void k_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
                                                SumJob j, int64_t rtiles, int64_t wtiles, int64_t tchunks) {
   __shared__ double fs[64];
+  __shared__ double red[4][64];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;
   if (b < wtiles) {
     const int64_t rt = b % rtiles, nt = b / rtiles;
-    if (tid < 64) {
-      const int64_t r = rt * 64 + tid;
+    {  // four groups of 64 threads add every fourth part, then one thread per r adds the groups
+      const int g = tid >> 6;
+      const int64_t r = rt * 64 + (tid & 63);
       double f = 0.0;
-      if (r < R) {
-        for (int p = 0; p < j.nparts; ++p) f += j.part[(int64_t)p * R + r];
-        if (j.check && !(f > 0.0)) atomicOr(j.check, CHK_DOMAIN);
-      }
+      if (r < R)
+        for (int p = g; p < j.nparts; p += 4) f += j.part[(int64_t)p * R + r];
+      red[g][tid & 63] = f;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const double f = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+      if (j.check && rt * 64 + tid < R && !(f > 0.0)) atomicOr(j.check, CHK_DOMAIN);
       fs[tid] = f;
     }
     __syncthreads();
@@ -758,10 +764,11 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* W, float* H, int
   } else {
     const int64_t hb = b - wtiles;
     const int64_t r = hb / tchunks, t0 = (hb % tchunks) * SC_TCHUNK;
-    if (tid == 0) {
-      double f = 0.0;
-      for (int p = 0; p < j.nparts; ++p) f += j.part[(int64_t)p * R + r];
-      fs[0] = f;
+    if (tid < 64) {  // one wave: a lane per part (at most SUM_PARTS), fixed-order butterfly
+      double f = tid < j.nparts ? j.part[(int64_t)tid * R + r] : 0.0;
+      for (int p = tid + 64; p < j.nparts; p += 64) f += j.part[(int64_t)p * R + r];
+      f = wave_sum(f);
+      if (tid == 0) fs[0] = f;
     }
     __syncthreads();
     const double f = fs[0];
