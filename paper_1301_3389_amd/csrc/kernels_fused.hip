@@ -104,6 +104,12 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   fetch_v(V, N, T, nb0 + wm * 32, t0 + wn * 32, lane, vf);
   for (int64_t nb = nb0; nb < nb1; nb += 64) {
     store_block(lw, wr, tid);
+    float vn[16];
+    const bool more = nb + 64 < nb1;
+    if (more) {                                   // next sub-tile, in flight from here
+      fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
+      fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+    }
     __syncthreads();                              // lw (and lh) ready; lq free
     f32x16 z;
 #pragma unroll
@@ -112,13 +118,6 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
     for (int k = 0; k < 64; k += 2) {
       const int kr = k + (lane >> 5);
       z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + cl], z);
-    }
-    float vn[16];
-    f32x4 wn4[4];
-    const bool more = nb + 64 < nb1;
-    if (more) {                                   // next sub-tile, in flight from here
-      fetch_block(W, R, nb + 64, 0, N, R, wn4, tid);
-      fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -143,12 +142,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       acc[1] = mfma32(a, b0 - 1.f, acc[1]);
       acc[2] = mfma32(a * a, b1, acc[2]);
     }
-    if (more) {
+    if (more)
 #pragma unroll
       for (int v = 0; v < 16; ++v) vf[v] = vn[v];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) wr[i] = wn4[i];
-    }
     __syncthreads();                              // lw and lq free for the next sub-tile
   }
   float* out[3] = {pu, puc, py};
@@ -204,6 +200,8 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   fetch_v(V, N, T, n0 + wm * 32, tb0 + wn * 32, lane, vf);
   for (int64_t tb = tb0; tb < tb1; tb += 64) {
     store_block(lh, hr, tid);
+    const bool more = tb + 64 < tb1;
+    if (more) fetch_block(H, T, 0, tb + 64, R, T, hr, tid);   // next sub-tile, in flight from here
     __syncthreads();
     f32x16 z;
 #pragma unroll
@@ -213,9 +211,6 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       const int kr = k + (lane >> 5);
       z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + tl], z);
     }
-    f32x4 hn[4];
-    const bool more = tb + 64 < tb1;
-    if (more) fetch_block(H, T, 0, tb + 64, R, T, hn, tid);
     const int64_t col = tb + tl;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -241,12 +236,8 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       acc[1] = mfma32(a0 - 1.f, b, acc[1]);
       acc[2] = mfma32(a1, b * b, acc[2]);
     }
-    if (more) {
-      // V of the next sub-tile (the row sums keep this kernel at its register limit)
-      fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vf);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) hr[i] = hn[i];
-    }
+    // V of the next sub-tile (the row sums keep this kernel at its register limit)
+    if (more) fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vf);
     __syncthreads();
   }
   float* out[3] = {pu, puc, py};
@@ -305,6 +296,12 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
   fetch_v(V, N, T, nb0 + wm * 32, t0 + wn * 32, lane, vf);
   for (int64_t nb = nb0; nb < nb1; nb += 64) {
     store_block(lw, wr, tid);
+    float vn[16];
+    const bool more = nb + 64 < nb1;
+    if (more) {                                   // next sub-tile, in flight from here
+      fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
+      fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+    }
     __syncthreads();
     f32x16 zn, dz;
 #pragma unroll
@@ -316,15 +313,15 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
       zn = mfma32(a, ln[kr * FP + cl], zn);
       dz = mfma32(a, ld[kr * FP + cl], dz);
     }
-    const bool more = nb + 64 < nb1;
-    if (more) fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t row = nb + wm * 32 + blk_row(v, lane);
       const float x = (row < N && col < T) ? vf[v] : 0.f;
       fl |= cost_acc(x, zn[v], dz[v], cp[0][0], cp[1][0], cp[2][0]);
     }
-    if (more) fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vf);
+    if (more)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) vf[v] = vn[v];
     __syncthreads();
   }
   if (fl) atomicOr(&fl_s[cl], fl);
@@ -375,6 +372,12 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
   fetch_v(V, N, T, n0 + wm * 32, tb0 + wn * 32, lane, vf);
   for (int64_t tb = tb0; tb < tb1; tb += 64) {
     store_block(lh, hr, tid);
+    float vn[16];
+    const bool more = tb + 64 < tb1;
+    if (more) {                                   // next sub-tile, in flight from here
+      fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
+      fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+    }
     __syncthreads();
     f32x16 zn, dz;
 #pragma unroll
@@ -387,8 +390,6 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
       zn = mfma32(ln[nl], b, zn);
       dz = mfma32(ld[nl], b, dz);
     }
-    const bool more = tb + 64 < tb1;
-    if (more) fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
     const int64_t col = tb + tl;
     double s0[16], s1[16], s2[16];
 #pragma unroll
@@ -401,7 +402,9 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
     rs[0] += halfwave_slot_sum(s0, lane);
     rs[1] += halfwave_slot_sum(s1, lane);
     rs[2] += halfwave_slot_sum(s2, lane);
-    if (more) fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vf);
+    if (more)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) vf[v] = vn[v];
     __syncthreads();
   }
 #pragma unroll
