@@ -58,12 +58,20 @@ __device__ __forceinline__ void store_block(float* t, const f32x4 (&x)[4], int t
   }
 }
 
-// V at this lane's positions of a 32 x 32 block (rows n0.., columns t0..), clamped.
+// V at this lane's positions of a 32 x 32 block (rows n0.., columns t0..);
+// entries outside the matrix read as 0, so the epilogues need no bounds tests.
 __device__ __forceinline__ void fetch_v(const float* V, int64_t N, int64_t T, int64_t n0, int64_t t0, int lane,
                                         float (&vf)[16]) {
-  const int64_t col = std::min<int64_t>(t0 + (lane & 31), T - 1);
+  const int64_t col = t0 + (lane & 31);
+  const bool cok = col < T;
+  const int64_t nr = N - n0;                      // rows available from n0
+  const int rb = (lane >> 5) * 4;
+  const float* p = V + n0 * T + (cok ? col : 0) + rb * T;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) vf[v] = V[std::min<int64_t>(n0 + blk_row(v, lane), N - 1) * T + col];
+  for (int v = 0; v < 16; ++v) {
+    const int r = (v >> 2) * 8 + (v & 3);         // blk_row(v, lane) - rb
+    vf[v] = (cok && r + rb < nr) ? p[(int64_t)r * T] : 0.f;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -122,8 +130,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int rl = wm * 32 + blk_row(v, lane);
-      const int64_t row = nb + rl;
-      const float x = (row < N && col < T) ? vf[v] : 0.f;
+      const float x = vf[v];                      // 0 outside the matrix
       const float iz = __builtin_amdgcn_rcpf(z[v]);
       const float q = x > 0.f ? x * iz : 0.f;
       bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
@@ -201,7 +208,11 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   for (int64_t tb = tb0; tb < tb1; tb += 64) {
     store_block(lh, hr, tid);
     const bool more = tb + 64 < tb1;
-    if (more) fetch_block(H, T, 0, tb + 64, R, T, hr, tid);   // next sub-tile, in flight from here
+    float vn[16];
+    if (more) {                                   // next sub-tile, in flight from here
+      fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
+      fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+    }
     __syncthreads();
     f32x16 z;
 #pragma unroll
@@ -211,12 +222,10 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       const int kr = k + (lane >> 5);
       z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + tl], z);
     }
-    const int64_t col = tb + tl;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int rl = wm * 32 + blk_row(v, lane);
-      const int64_t row = n0 + rl;
-      const float x = (row < N && col < T) ? vf[v] : 0.f;
+      const float x = vf[v];                      // 0 outside the matrix
       const float iz = __builtin_amdgcn_rcpf(z[v]);
       const float q = x > 0.f ? x * iz : 0.f;
       bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
@@ -236,8 +245,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       acc[1] = mfma32(a0 - 1.f, b, acc[1]);
       acc[2] = mfma32(a1, b * b, acc[2]);
     }
-    // V of the next sub-tile (the row sums keep this kernel at its register limit)
-    if (more) fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vf);
+    if (more)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) vf[v] = vn[v];
     __syncthreads();
   }
   float* out[3] = {pu, puc, py};
@@ -315,8 +325,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int64_t row = nb + wm * 32 + blk_row(v, lane);
-      const float x = (row < N && col < T) ? vf[v] : 0.f;
+      const float x = vf[v];                      // 0 outside the matrix
       fl |= cost_acc(x, zn[v], dz[v], cp[0][0], cp[1][0], cp[2][0]);
     }
     if (more)
@@ -390,13 +399,11 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
       zn = mfma32(ln[nl], b, zn);
       dz = mfma32(ld[nl], b, dz);
     }
-    const int64_t col = tb + tl;
     double s0[16], s1[16], s2[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       s0[v] = s1[v] = s2[v] = 0.0;
-      const int64_t row = n0 + wm * 32 + blk_row(v, lane);
-      const float x = (row < N && col < T) ? vf[v] : 0.f;
+      const float x = vf[v];                      // 0 outside the matrix
       flr[v] |= cost_acc(x, zn[v], dz[v], s0[v], s1[v], s2[v]);
     }
     rs[0] += halfwave_slot_sum(s0, lane);
