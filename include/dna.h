@@ -22,6 +22,9 @@
  *    invalid call returns a status != DNA_OK and enqueues nothing.
  *  - A kernel launch failure returns DNA_EHIP; dna_last_error() gives the
  *    HIP error text (thread-local).  No C++ exception crosses this ABI.
+ *  - Output buffers overlap neither the inputs nor each other nor `ws`; the
+ *    factor an update, normalisation or unrolled solve rewrites in place is
+ *    the one exception.
  *  - Zeros of V contribute nothing to Q, Q-bar or any cost (end of Sec. 3).
  *  - Results are deterministic: every reduction runs in a fixed order.
  */

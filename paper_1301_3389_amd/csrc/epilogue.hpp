@@ -90,11 +90,14 @@ __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf
 // log2(w) * u / (w - 1) cancels the rounding of w to first order (Goldberg's
 // log1p construction); w == 1 takes the first series term.
 // u is clamped to FLT_MAX (an overflowed ratio still gives a finite, huge term).
+// Both forms are evaluated and one is selected, so the code has no branch.
 __device__ __forceinline__ float log2_1p(float u) {
   u = fminf(u, 3.402823466e38f);
   const float w = 1.f + u;
   const float d = w - 1.f;
-  return (d == 0.f) ? u * 1.44269504088896341f : log2_hw(w) * (u * __builtin_amdgcn_rcpf(d));
+  const float general = log2_hw(w) * (u * __builtin_amdgcn_rcpf(d));
+  const float series = u * 1.44269504088896341f;
+  return (d == 0.f) ? series : general;
 }
 
 __device__ __forceinline__ double xlog2x_over(float v, float z) {

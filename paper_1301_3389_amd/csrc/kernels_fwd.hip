@@ -329,43 +329,83 @@ __device__ __forceinline__ Cand candidate(float x, float u, float uc, float y, f
   return o;
 }
 
-// CAND_COLS columns per block, 256 / CAND_COLS row groups; renormalisation eq. (10)
-// per column through a fixed-order LDS reduction.
+// CAND_COLS columns per block, RG row groups; renormalisation eq. (10) per
+// column through a fixed-order LDS reduction.  With RPT > 0 (R <= RPT * RG)
+// each thread keeps its RPT Newton values in registers between the two passes
+// and issues the loads of all its rows for one split together; RPT = 0 is the
+// general form for any R.
 constexpr int CAND_COLS = 32, CAND_RG = 256 / CAND_COLS;
 
-__global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
-                                                const float* c, const double* vpart, int tiles_m,
-                                                int64_t T, int64_t R, float eps, float alpha,
-                                                float* Xmu, float* Xn, float* Aout, float* Bout) {
-  __shared__ double red[CAND_RG][CAND_COLS];
+template <int RPT, int RG>
+__global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
+    const float* __restrict__ H, const float* __restrict__ pu, const float* __restrict__ puc,
+    const float* __restrict__ py, int splits, const float* __restrict__ c, const double* __restrict__ vpart,
+    int tiles_m, int64_t T, int64_t R, float eps, float alpha, float* __restrict__ Xmu, float* __restrict__ Xn,
+    float* __restrict__ Aout, float* __restrict__ Bout) {
+  __shared__ double red[RG][CAND_COLS];
   __shared__ double fac[CAND_COLS];
   const int tid = threadIdx.x, cl = tid % CAND_COLS, rg = tid / CAND_COLS;
   const int64_t t = (int64_t)blockIdx.x * CAND_COLS + cl;
   const bool ok = t < T;
   double den = 0.0;
+  constexpr int KEEP = RPT > 0 ? RPT : 1;
+  float keep[KEEP];
   if (ok) {
-#pragma unroll 4
-    for (int64_t r = rg; r < R; r += CAND_RG) {
-      float u = 0.f, uc = 0.f, y = 0.f;
-#pragma unroll 4
+    if constexpr (RPT > 0) {
+      float u[RPT], uc[RPT], y[RPT];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) u[i] = uc[i] = y[i] = 0.f;
+      constexpr int SPU = RPT <= 8 ? 2 : 1;      // loads in flight: 3 x RPT x SPU
+#pragma unroll SPU
       for (int sp = 0; sp < splits; ++sp) {
-        u += pu[(sp * R + r) * T + t];
-        uc += puc[(sp * R + r) * T + t];
-        y += py[(sp * R + r) * T + t];
+        const int64_t o = (int64_t)sp * R * T + t;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int64_t r = rg + i * RG;
+          if (r < R) {
+            u[i] += pu[o + r * T];
+            uc[i] += puc[o + r * T];
+            y[i] += py[o + r * T];
+          }
+        }
       }
-      const Cand k = candidate(H[r * T + t], u, uc, y, c[r], eps, alpha);
-      Xmu[r * T + t] = k.mu;
-      Xn[r * T + t] = k.newton;
-      if (Aout) Aout[r * T + t] = k.A;
-      if (Bout) Bout[r * T + t] = k.B;
-      den += (double)c[r] * (double)k.newton;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int64_t r = rg + i * RG;
+        keep[i] = 0.f;
+        if (r < R) {
+          const Cand k = candidate(H[r * T + t], u[i], uc[i], y[i], c[r], eps, alpha);
+          Xmu[r * T + t] = k.mu;
+          keep[i] = k.newton;
+          if (Aout) Aout[r * T + t] = k.A;
+          if (Bout) Bout[r * T + t] = k.B;
+          den += (double)c[r] * (double)k.newton;
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int64_t r = rg; r < R; r += RG) {
+        float u = 0.f, uc = 0.f, y = 0.f;
+#pragma unroll 4
+        for (int sp = 0; sp < splits; ++sp) {
+          u += pu[(sp * R + r) * T + t];
+          uc += puc[(sp * R + r) * T + t];
+          y += py[(sp * R + r) * T + t];
+        }
+        const Cand k = candidate(H[r * T + t], u, uc, y, c[r], eps, alpha);
+        Xmu[r * T + t] = k.mu;
+        Xn[r * T + t] = k.newton;
+        if (Aout) Aout[r * T + t] = k.A;
+        if (Bout) Bout[r * T + t] = k.B;
+        den += (double)c[r] * (double)k.newton;
+      }
     }
   }
   red[rg][cl] = den;
   __syncthreads();
   if (rg == 0 && ok) {
     double d = 0.0;
-    for (int k = 0; k < CAND_RG; ++k) d += red[k][cl];
+    for (int k = 0; k < RG; ++k) d += red[k][cl];
     double s = 0.0;
     for (int m = 0; m < tiles_m; ++m) s += vpart[(int64_t)m * T + t];
     fac[cl] = d > 0.0 ? s / d : 1.0;
@@ -373,9 +413,17 @@ __global__ __launch_bounds__(256) void k_cand_H(const float* H, const float* pu,
   __syncthreads();
   if (ok) {
     const double f = fac[cl];
+    if constexpr (RPT > 0) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int64_t r = rg + i * RG;
+        if (r < R) Xn[r * T + t] = fmaxf((float)((double)keep[i] * f), VALUE_FLOOR);
+      }
+    } else {
 #pragma unroll 4
-    for (int64_t r = rg; r < R; r += CAND_RG)
-      Xn[r * T + t] = fmaxf((float)((double)Xn[r * T + t] * f), VALUE_FLOOR);
+      for (int64_t r = rg; r < R; r += RG)
+        Xn[r * T + t] = fmaxf((float)((double)Xn[r * T + t] * f), VALUE_FLOOR);
+    }
   }
 }
 
@@ -383,49 +431,141 @@ hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, cons
                          const double* vpart, int tiles_m, int64_t T, int64_t R, float eps, float alpha,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_H", s);
-  hipLaunchKernelGGL(k_cand_H, dim3((unsigned)cdiv(T, CAND_COLS)), dim3(256), 0, s, H, pu, puc, py, splits, c, vpart,
-                     tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
+  // for R <= 128, 32 row groups (1024 threads) give every CU 16 waves of
+  // independent loads; larger R takes the general loop with 8 row groups
+  const dim3 grid((unsigned)cdiv(T, CAND_COLS));
+  constexpr int RG = 32;
+  if (R <= 2 * RG)
+    hipLaunchKernelGGL((k_cand_H<2, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
+                       tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
+  else if (R <= 4 * RG)
+    hipLaunchKernelGGL((k_cand_H<4, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
+                       tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
+  else
+    hipLaunchKernelGGL((k_cand_H<0, CAND_RG>), grid, dim3(CAND_COLS * CAND_RG), 0, s, H, pu, puc, py, splits, c,
+                       vpart, tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
   prof_end("cand_H", s);
   return hipGetLastError();
 }
 
-// One wave per row n of W; lanes stride over r.
-__global__ __launch_bounds__(256) void k_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits,
-                                                const float* g, const double* vpart, int tiles_n,
-                                                int64_t N, int64_t R, float eps, float alpha,
-                                                float* Xmu, float* Xn, float* Aout, float* Bout) {
-  const int lane = threadIdx.x & 63;
-  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (n >= N) return;
-  double den = 0.0;
-  for (int64_t r = lane; r < R; r += 64) {
-    float u = 0.f, uc = 0.f, y = 0.f;
-    for (int sp = 0; sp < splits; ++sp) {
-      u += pu[(sp * N + n) * R + r];
-      uc += puc[(sp * N + n) * R + r];
-      y += py[(sp * N + n) * R + r];
+// One block per row n of W: the four waves each add a quarter of the splits
+// (lane = r, RPW values of r per lane, RPW = 0 for the general form), the
+// quarters are added in LDS in fixed order, then wave 0 forms the candidates.
+template <int RPW>
+__global__ __launch_bounds__(256) void k_cand_W(const float* __restrict__ W, const float* __restrict__ pu,
+                                                const float* __restrict__ puc, const float* __restrict__ py,
+                                                int splits, const float* __restrict__ g,
+                                                const double* __restrict__ vpart, int tiles_n, int64_t N, int64_t R,
+                                                float eps, float alpha, float* __restrict__ Xmu,
+                                                float* __restrict__ Xn, float* __restrict__ Aout,
+                                                float* __restrict__ Bout) {
+  constexpr int NR = RPW > 0 ? RPW : 1;
+  __shared__ float red[3][4][64 * NR];
+  __shared__ double vs[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n = blockIdx.x;
+  if constexpr (RPW == 0) {
+    // general form: wave 0 alone, lanes stride over r
+    if (wave != 0) return;
+    double den = 0.0;
+    for (int64_t r = lane; r < R; r += 64) {
+      float u = 0.f, uc = 0.f, y = 0.f;
+#pragma unroll 4
+      for (int sp = 0; sp < splits; ++sp) {
+        u += pu[(sp * N + n) * R + r];
+        uc += puc[(sp * N + n) * R + r];
+        y += py[(sp * N + n) * R + r];
+      }
+      const Cand k = candidate(W[n * R + r], u, uc, y, g[r], eps, alpha);
+      Xmu[n * R + r] = k.mu;
+      Xn[n * R + r] = k.newton;
+      if (Aout) Aout[n * R + r] = k.A;
+      if (Bout) Bout[n * R + r] = k.B;
+      den += (double)g[r] * (double)k.newton;
     }
-    const Cand k = candidate(W[n * R + r], u, uc, y, g[r], eps, alpha);
-    Xmu[n * R + r] = k.mu;
-    Xn[n * R + r] = k.newton;
-    if (Aout) Aout[n * R + r] = k.A;
-    if (Bout) Bout[n * R + r] = k.B;
-    den += (double)g[r] * (double)k.newton;
+    double s = 0.0;
+    for (int64_t m = lane; m < tiles_n; m += 64) s += vpart[m * N + n];
+    den = __shfl(wave_sum(den), 0);
+    s = __shfl(wave_sum(s), 0);
+    const double f = den > 0.0 ? s / den : 1.0;
+    for (int64_t r = lane; r < R; r += 64)
+      Xn[n * R + r] = fmaxf((float)((double)Xn[n * R + r] * f), VALUE_FLOOR);
+  } else {
+    float u[RPW], uc[RPW], y[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) u[i] = uc[i] = y[i] = 0.f;
+#pragma unroll 4
+    for (int sp = wave; sp < splits; sp += 4) {
+      const int64_t o = ((int64_t)sp * N + n) * R;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int64_t r = lane + 64 * i;
+        if (r < R) {
+          u[i] += pu[o + r];
+          uc[i] += puc[o + r];
+          y[i] += py[o + r];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      red[0][wave][i * 64 + lane] = u[i];
+      red[1][wave][i * 64 + lane] = uc[i];
+      red[2][wave][i * 64 + lane] = y[i];
+    }
+    {  // the V row sum, one part per lane of wave 1
+      double s = 0.0;
+      if (wave == 1)
+        for (int64_t m = lane; m < tiles_n; m += 64) s += vpart[m * N + n];
+      s = wave_sum(s);
+      if (wave == 1 && lane == 0) vs[0] = s;
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double den = 0.0;
+    float keep[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int64_t r = lane + 64 * i;
+      keep[i] = 0.f;
+      if (r < R) {
+        const int e = i * 64 + lane;
+        const float uu = (red[0][0][e] + red[0][1][e]) + (red[0][2][e] + red[0][3][e]);
+        const float ucc = (red[1][0][e] + red[1][1][e]) + (red[1][2][e] + red[1][3][e]);
+        const float yy = (red[2][0][e] + red[2][1][e]) + (red[2][2][e] + red[2][3][e]);
+        const Cand k = candidate(W[n * R + r], uu, ucc, yy, g[r], eps, alpha);
+        Xmu[n * R + r] = k.mu;
+        keep[i] = k.newton;
+        if (Aout) Aout[n * R + r] = k.A;
+        if (Bout) Bout[n * R + r] = k.B;
+        den += (double)g[r] * (double)k.newton;
+      }
+    }
+    den = __shfl(wave_sum(den), 0);
+    const double s = vs[0];
+    const double f = den > 0.0 ? s / den : 1.0;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int64_t r = lane + 64 * i;
+      if (r < R) Xn[n * R + r] = fmaxf((float)((double)keep[i] * f), VALUE_FLOOR);
+    }
   }
-  double s = 0.0;
-  for (int64_t m = lane; m < tiles_n; m += 64) s += vpart[m * N + n];
-  den = __shfl(wave_sum(den), 0);
-  s = __shfl(wave_sum(s), 0);
-  const double f = den > 0.0 ? s / den : 1.0;
-  for (int64_t r = lane; r < R; r += 64) Xn[n * R + r] = fmaxf((float)((double)Xn[n * R + r] * f), VALUE_FLOOR);
 }
 
 hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits, const float* g,
                          const double* vpart, int tiles_n, int64_t N, int64_t R, float eps, float alpha,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_W", s);
-  hipLaunchKernelGGL(k_cand_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, W, pu, puc, py, splits, g, vpart,
-                     tiles_n, N, R, eps, alpha, Xmu, Xn, Aout, Bout);
+  const dim3 grid((unsigned)N);
+  if (R <= 64)
+    hipLaunchKernelGGL(k_cand_W<1>, grid, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R, eps,
+                       alpha, Xmu, Xn, Aout, Bout);
+  else if (R <= 128)
+    hipLaunchKernelGGL(k_cand_W<2>, grid, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R, eps,
+                       alpha, Xmu, Xn, Aout, Bout);
+  else
+    hipLaunchKernelGGL(k_cand_W<0>, grid, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R, eps,
+                       alpha, Xmu, Xn, Aout, Bout);
   prof_end("cand_W", s);
   return hipGetLastError();
 }
@@ -515,7 +655,8 @@ __device__ __forceinline__ bool decide(double q0, double q1, double q2, int fl, 
   return newton;
 }
 
-__global__ __launch_bounds__(256) void k_select_H(const float* Xmu, const float* Xn, float* Hout,
+__global__ __launch_bounds__(256) void k_select_H(const float* __restrict__ Xmu, const float* __restrict__ Xn,
+                                                  float* __restrict__ Hout,
                                                   const double* part, const int* fpart, int tiles,
                                                   int64_t T, int64_t R, uint8_t* mask, double* dsel,
                                                   double* margin) {
@@ -545,6 +686,7 @@ __global__ __launch_bounds__(256) void k_select_H(const float* Xmu, const float*
   __syncthreads();
   if (!ok) return;
   const float* src = pick[cl] ? Xn : Xmu;
+#pragma unroll 8
   for (int64_t r = rg; r < R; r += CAND_RG) Hout[r * T + t] = src[r * T + t];
 }
 
@@ -558,7 +700,8 @@ hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_select_W(const float* Xmu, const float* Xn, float* Wout,
+__global__ __launch_bounds__(256) void k_select_W(const float* __restrict__ Xmu, const float* __restrict__ Xn,
+                                                  float* __restrict__ Wout,
                                                   const double* part, const int* fpart, int tiles,
                                                   int64_t N, int64_t R, uint8_t* mask, double* dsel,
                                                   double* margin) {
@@ -672,8 +815,10 @@ __global__ __launch_bounds__(256) void k_colsum_part(const float* W, int64_t N, 
   const int64_t p = blockIdx.y;
   const int64_t n1 = std::min<int64_t>(N, (p + 1) * rows);
   double s = 0.0;
-  if (r < R)
+  if (r < R) {
+#pragma unroll 16
     for (int64_t n = p * rows + rg; n < n1; n += 4) s += (double)W[n * R + r];
+  }
   red[rg][cl] = s;
   __syncthreads();
   if (rg == 0 && r < R) part[p * R + r] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
@@ -686,6 +831,7 @@ __global__ __launch_bounds__(256) void k_rowsum_part(const float* H, int64_t T, 
   const int64_t p = blockIdx.x, r = blockIdx.y;
   const int64_t t1 = std::min<int64_t>(T, (p + 1) * cols);
   double s = 0.0;
+#pragma unroll 8
   for (int64_t t = p * cols + tid; t < t1; t += 256) s += (double)H[r * T + t];
   s = wave_sum(s);
   if ((tid & 63) == 0) red[tid >> 6] = s;
@@ -726,20 +872,30 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 // Normalisation with the second level of the sums done per tile: blocks
 // [0, wtiles) scale 64 x 64 tiles of W (64 columns r, each block summing the
 // parts of its 64 factors into LDS); the remaining blocks scale SC_TCHUNK
-// entries of one row r of H.  Multiplying by the float64 reciprocal of f
-// rounds like dividing except in double-rounding ties.
+// entries of one row r of H.  Every block loads its factor entries before it
+// adds the parts, so the two latencies overlap.  Multiplying by the float64
+// reciprocal of f rounds like dividing except in double-rounding ties.
 constexpr int SC_TCHUNK = 2048;
-__global__ __launch_bounds__(256) void k_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                                               SumJob j, int64_t rtiles, int64_t wtiles, int64_t tchunks) {
+constexpr int SC_W_PER = 64 * 64 / 256, SC_H_PER = SC_TCHUNK / 256;
+__global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, float* __restrict__ H, int64_t N,
+                                               int64_t T, int64_t R, SumJob j, int64_t rtiles, int64_t wtiles,
+                                               int64_t tchunks) {
   __shared__ double fs[64];
   __shared__ double red[4][64];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;
   if (b < wtiles) {
     const int64_t rt = b % rtiles, nt = b / rtiles;
+    const int64_t r = rt * 64 + (tid & 63);
+    const int64_t nb = nt * 64 + (tid >> 6);
+    float w[SC_W_PER];
+#pragma unroll
+    for (int k = 0; k < SC_W_PER; ++k) {
+      const int64_t n = nb + 4 * k;
+      w[k] = (n < N && r < R) ? W[n * R + r] : 0.f;
+    }
     {  // four groups of 64 threads add every fourth part, then one thread per r adds the groups
       const int g = tid >> 6;
-      const int64_t r = rt * 64 + (tid & 63);
       double f = 0.0;
       if (r < R)
         for (int p = g; p < j.nparts; p += 4) f += j.part[(int64_t)p * R + r];
@@ -752,19 +908,25 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* W, float* H, int
       fs[tid] = f;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int64_t n = nt * 64 + e / 64, r = rt * 64 + (e & 63);
-      const double f = fs[e & 63];
-      if (n < N && r < R && f > 0.0) {
-        float& w = W[n * R + r];
-        w = (float)(side == 0 ? (double)w * (1.0 / f) : (double)w * f);
+    const double f = fs[tid & 63];
+    if (r < R && f > 0.0) {
+      const double m = side == 0 ? 1.0 / f : f;
+#pragma unroll
+      for (int k = 0; k < SC_W_PER; ++k) {
+        const int64_t n = nb + 4 * k;
+        if (n < N) W[n * R + r] = (float)((double)w[k] * m);
       }
     }
   } else {
     const int64_t hb = b - wtiles;
-    const int64_t r = hb / tchunks, t0 = (hb % tchunks) * SC_TCHUNK;
-    if (tid < 64) {  // one wave: a lane per part (at most SUM_PARTS), fixed-order butterfly
+    const int64_t r = hb / tchunks, t0 = (hb % tchunks) * SC_TCHUNK + tid;
+    float h[SC_H_PER];
+#pragma unroll
+    for (int k = 0; k < SC_H_PER; ++k) {
+      const int64_t t = t0 + 256 * k;
+      h[k] = t < T ? H[r * T + t] : 0.f;
+    }
+    if (tid < 64) {  // one wave: a lane per part, fixed-order butterfly
       double f = tid < j.nparts ? j.part[(int64_t)tid * R + r] : 0.0;
       for (int p = tid + 64; p < j.nparts; p += 64) f += j.part[(int64_t)p * R + r];
       f = wave_sum(f);
@@ -774,8 +936,11 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* W, float* H, int
     const double f = fs[0];
     if (!(f > 0.0)) return;
     const double m = side == 0 ? f : 1.0 / f;
-    const int64_t t1 = std::min<int64_t>(T, t0 + SC_TCHUNK);
-    for (int64_t t = t0 + tid; t < t1; t += 256) H[r * T + t] = (float)((double)H[r * T + t] * m);
+#pragma unroll
+    for (int k = 0; k < SC_H_PER; ++k) {
+      const int64_t t = t0 + 256 * k;
+      if (t < T) H[r * T + t] = (float)((double)h[k] * m);
+    }
   }
 }
 

@@ -26,6 +26,7 @@ SHAPES = [
     (130, 1, 4, 0.0, 7),
     (1, 90, 3, 0.0, 8),
     (200, 300, 129, 0.05, 9),
+    (150, 170, 100, 0.1, 10),    # 64 < R <= 128: the register-resident candidate forms
 ]
 
 
