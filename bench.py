@@ -178,8 +178,7 @@ def timed_steps(dna, V, W, H, steps, gemm):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        dna.dna_iteration(V, W, H, gemm=gemm)
+    dna.iterate(V, W, H, steps, gemm=gemm)
     torch.cuda.synchronize()
     return 1e3 * (time.perf_counter() - t0) / steps
 
@@ -198,7 +197,7 @@ def iters_to_target(dna, V, W0, H0, kl_target, budget, gemm, chunk=10):
     while done < budget:
         m = min(chunk, budget - done)
         for k in range(m):
-            dna.dna_iteration(V, W, H, gemm=gemm)
+            dna.iterate(V, W, H, 1, gemm=gemm)
             dna.kl_cost(V, W, H, out=kls[done + k + 1:done + k + 2])
         done += m
         hit = np.nonzero(kls[:done + 1].cpu().numpy() <= kl_target)[0]
@@ -267,8 +266,7 @@ def main():
     gemm = args.gemm
     W, H = W0.clone(), H0.clone()
     dna.normalize(0, W, H)                                   # Algorithm 1 step 1
-    for _ in range(args.warmup):
-        dna.dna_iteration(V, W, H, gemm=gemm)
+    dna.iterate(V, W, H, args.warmup, gemm=gemm)
     torch.cuda.synchronize()
 
     # ---- timed region -----------------------------------------------------
@@ -277,8 +275,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
-        dna.dna_iteration(V, W, H, gemm=gemm)
+    dna.iterate(V, W, H, args.steps, gemm=gemm)          # args.steps full iterations, one call
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -291,8 +288,7 @@ def main():
     dna.profile_enable(True)
     torch.cuda.synchronize()
     tp = time.perf_counter()
-    for _ in range(args.steps):
-        dna.dna_iteration(V, W, H, gemm=gemm)
+    dna.iterate(V, W, H, args.steps, gemm=gemm)
     torch.cuda.synchronize()
     prof_wall = time.perf_counter() - tp
     stats = dna.profile_read()

@@ -124,6 +124,19 @@ dna_status dna_update_W(const float* V, float* W, const float* H,
                         void* ws, size_t ws_bytes, uint8_t* chose_newton,
                         double* d_sel, double* margin, void* stream);
 
+/* `iters` full iterations of Algorithm 1 in place, each: dna_update_H
+ * (steps 4-15), dna_normalize(1) (step 16), dna_update_W (steps 17-28),
+ * dna_normalize(0) (step 29) -- the same kernels those entry points run, in one
+ * call.  Each normalisation also writes the partial sums of the factor it
+ * rescaled, so the half-step that follows reads c = W^t 1 (or g = H 1) from
+ * them instead of summing the factor again; results therefore equal those of
+ * the four separate calls up to the order of those float64 sums.  Step 1 (the
+ * initial dna_normalize(0)) is the caller's.  iters = 0 does nothing;
+ * iters < 0 is DNA_EINVAL.  Uses the dna_workspace_bytes() workspace. */
+dna_status dna_iterate(const float* V, float* W, float* H,
+                       int64_t N, int64_t T, int64_t R, int iters,
+                       const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
 /* Plain multiplicative update (eq. 11 at lambda = 0; Lee-Seung):
  *   side 0: H <- H * (W^t Q) / (W^t 1)      side 1: W <- W * (Q H^t) / (H 1)
  * with Q = V / (W H).  If with_cost != 0, d_out (length T for side 0, N for

@@ -113,7 +113,7 @@ struct Layout {
   Split shf, swf;            // row / column chunks of the fused kernels (R <= FUSED_MAX_R)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
-  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, vpart, cpart, fpart, s16, check, total;
+  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sume, vpart, cpart, fpart, s16, check, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -149,6 +149,8 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   L.c32 = take((size_t)R * 4);
   L.c64 = take((size_t)R * 8);
   L.sump = take((size_t)SUM_PARTS * R * 8);
+  // sums emitted by the normalisation for the next half-step (dna_iterate)
+  L.sume = take((size_t)std::max(scale_emit_parts(0, N, T), scale_emit_parts(1, N, T)) * R * 8);
   L.vpart = take(red * 8);
   L.cpart = take(std::max(3 * red, klt) * 8);
   L.fpart = take(red * 4);
@@ -262,9 +264,12 @@ static Scratch16 scratch16(void* ws, const Layout& L, int64_t N, int64_t T, int6
 
 // ---------------------------------------------------------------------------
 // side 0: candidates for H (R x T) given W;  side 1: candidates for W (N x R) given H.
+// `pre`, if given, holds the first level of c (side 0) / g (side 1) already
+// written by the preceding normalisation; otherwise a sum kernel writes it.
 static dna_status run_candidates(int side, const float* V, const float* W, const float* H, int64_t N,
                                  int64_t T, int64_t R, const dna_opts* o, const Layout& L, void* ws,
-                                 float* Xmu, float* Xn, float* Aout, float* Bout, int* chk, hipStream_t s) {
+                                 float* Xmu, float* Xn, float* Aout, float* Bout, int* chk, hipStream_t s,
+                                 const SumJob* pre = nullptr) {
   float* Q = at<float>(ws, L.q);
   float* Qb = at<float>(ws, L.qb);
   float* pu = at<float>(ws, L.pu);
@@ -278,7 +283,8 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
   const Scratch16 S = scratch16(ws, L, N, T, R);
   SumJob job;
   if (side == 0) {
-    DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
+    if (pre) job = *pre;
+    else DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
     job.s64 = c64; job.s32 = c32; job.check = chk;
     ra.fin = job;                                   // c = W^t 1 finished inside the ratio pass
     const bool fused = !p16 && R <= FUSED_MAX_R;
@@ -297,7 +303,8 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     DNA_HIP(launch_cand_H(H, pu, puc, py, sp, c32, vpart, fused ? L.shf.splits : L.rt_m, T, R, o->eps, o->alpha,
                           Xmu, Xn, Aout, Bout, s), "cand_H");
   } else {
-    DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, s), "rowsum_H");
+    if (pre) job = *pre;
+    else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, s), "rowsum_H");
     job.s64 = c64; job.s32 = c32; job.check = chk;
     ra.fin = job;                                   // c' = H 1 finished inside the ratio pass
     const bool fused = !p16 && R <= FUSED_MAX_R;
@@ -414,7 +421,7 @@ dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int
   if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");
   else DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");
   job.check = c.chk;
-  DNA_HIP(launch_scale(side, W, H, N, T, R, job, c.s), "scale");
+  DNA_HIP(launch_scale(side, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
   return epilogue(c);
 }
 
@@ -441,6 +448,42 @@ dna_status dna_update_W(const float* V, float* W, const float* H, int64_t N, int
   float* Xn = at<float>(ws, c.L.xn);
   DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s));
   DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, chose_newton, d_sel, margin, c.s));
+  return epilogue(c);
+}
+
+// Normalisation inside dna_iterate: the sum of the factor being normalised
+// (`pre`: emitted by the kernel that wrote that factor, else a sum kernel), then
+// the scale kernel, which emits the first level of the next half-step's sum.
+static dna_status iterate_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                                    const Common& c, void* ws, SumJob& next) {
+  SumJob job;
+  if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, c.L.sump), job, c.s), "colsum_W");
+  else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, c.L.sump), job, c.s), "rowsum_H");
+  job.check = c.chk;
+  DNA_HIP(launch_scale(side, W, H, N, T, R, job, at<double>(ws, c.L.sume), &next, c.s), "scale");
+  return DNA_OK;
+}
+
+dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R, int iters,
+                       const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
+  if (iters < 0) return fail(DNA_EINVAL, "iters must be >= 0");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  float* Xmu = at<float>(ws, c.L.xmu);
+  float* Xn = at<float>(ws, c.L.xn);
+  SumJob next;
+  bool have = false;                                // `next` holds c for the coming H step
+  for (int it = 0; it < iters; ++it) {
+    DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
+                           have ? &next : nullptr));
+    DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s));
+    DNA_TRY(iterate_normalize(1, W, H, N, T, R, c, ws, next));          // step 16; next = g
+    DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s, &next));
+    DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s));
+    DNA_TRY(iterate_normalize(0, W, H, N, T, R, c, ws, next));          // step 29; next = c
+    have = true;
+  }
   return epilogue(c);
 }
 

@@ -18,6 +18,7 @@ __device__ __forceinline__ void sum_job(const SumJob& j) {
   const int64_t lin = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   for (int64_t r = lin * blockDim.x + threadIdx.x; r < j.R; r += nb * blockDim.x) {
     double tot = 0.0;
+#pragma unroll 8
     for (int p = 0; p < j.nparts; ++p) tot += j.part[(int64_t)p * j.R + r];
     if (j.s64) j.s64[r] = tot;
     if (j.s32) j.s32[r] = (float)tot;

@@ -128,9 +128,15 @@ hipError_t launch_rowsum_part(const float* H, int64_t T, int64_t R, double* part
 hipError_t launch_sum_final(const SumJob& job, hipStream_t s);
 // Steps 1 / 29 (side 0, f = column sums of W: W[:,r] /= f_r, H[r,:] *= f_r) and
 // step 16 (side 1, f = row sums of H: H[r,:] /= f_r, W[:,r] *= f_r), with the
-// second level of the sums (job) done per tile.
+// second level of the sums (job) done per tile.  With `emit` non-null the
+// kernel also writes the first level of the sums of the factor it normalised
+// (side 0: column sums of the new W, cdiv(N, 64) parts; side 1: row sums of
+// the new H, cdiv(T, SC_TCHUNK) parts) and returns their second level in
+// `emitted`, for the half-step that follows.
+constexpr int SC_TCHUNK = 2048;
+int64_t scale_emit_parts(int side, int64_t N, int64_t T);
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
-                        hipStream_t s);
+                        double* emit, SumJob* emitted, hipStream_t s);
 
 // Steps 2-5 and 10 in one kernel per half-step when R <= 64 (side 0: H step,
 // rows n split into `splits` chunks of `chunk`; side 1: W step, columns t split

@@ -874,12 +874,14 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 // parts of its 64 factors into LDS); the remaining blocks scale SC_TCHUNK
 // entries of one row r of H.  Every block loads its factor entries before it
 // adds the parts, so the two latencies overlap.  Multiplying by the float64
-// reciprocal of f rounds like dividing except in double-rounding ties.
-constexpr int SC_TCHUNK = 2048;
+// reciprocal of f rounds like dividing except in double-rounding ties.  With
+// `emit`, the blocks of the normalised factor (W tiles for side 0, H chunks for
+// side 1) also write the float64 sum of the values they stored (an unchanged
+// column / row where f is not positive): emit[tile * R + r].
 constexpr int SC_W_PER = 64 * 64 / 256, SC_H_PER = SC_TCHUNK / 256;
 __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, float* __restrict__ H, int64_t N,
                                                int64_t T, int64_t R, SumJob j, int64_t rtiles, int64_t wtiles,
-                                               int64_t tchunks) {
+                                               int64_t tchunks, double* __restrict__ emit) {
   __shared__ double fs[64];
   __shared__ double red[4][64];
   const int tid = threadIdx.x;
@@ -909,17 +911,25 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
     }
     __syncthreads();
     const double f = fs[tid & 63];
-    if (r < R && f > 0.0) {
-      const double m = side == 0 ? 1.0 / f : f;
+    const bool sc = r < R && f > 0.0;
+    const double m = side == 0 ? 1.0 / f : f;
+    double cs = 0.0;
 #pragma unroll
-      for (int k = 0; k < SC_W_PER; ++k) {
-        const int64_t n = nb + 4 * k;
-        if (n < N) W[n * R + r] = (float)((double)w[k] * m);
-      }
+    for (int k = 0; k < SC_W_PER; ++k) {
+      const int64_t n = nb + 4 * k;
+      const float x = sc ? (float)((double)w[k] * m) : w[k];
+      if (sc && n < N) W[n * R + r] = x;
+      cs += (double)x;                            // 0 outside the matrix
+    }
+    if (emit && side == 0) {                      // column sums of this tile of the new W
+      red[tid >> 6][tid & 63] = cs;
+      __syncthreads();
+      if (tid < 64 && rt * 64 + tid < R)
+        emit[nt * R + rt * 64 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
     }
   } else {
     const int64_t hb = b - wtiles;
-    const int64_t r = hb / tchunks, t0 = (hb % tchunks) * SC_TCHUNK + tid;
+    const int64_t r = hb / tchunks, ch = hb % tchunks, t0 = ch * SC_TCHUNK + tid;
     float h[SC_H_PER];
 #pragma unroll
     for (int k = 0; k < SC_H_PER; ++k) {
@@ -934,24 +944,38 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
     }
     __syncthreads();
     const double f = fs[0];
-    if (!(f > 0.0)) return;
+    const bool sc = f > 0.0;
     const double m = side == 0 ? f : 1.0 / f;
+    double rs = 0.0;
 #pragma unroll
     for (int k = 0; k < SC_H_PER; ++k) {
       const int64_t t = t0 + 256 * k;
-      if (t < T) H[r * T + t] = (float)((double)h[k] * m);
+      const float x = sc ? (float)((double)h[k] * m) : h[k];
+      if (sc && t < T) H[r * T + t] = x;
+      rs += (double)x;                            // 0 outside the matrix
+    }
+    if (emit && side == 1) {                      // row sum of this chunk of the new H
+      rs = wave_sum(rs);
+      if ((tid & 63) == 0) red[0][tid >> 6] = rs;
+      __syncthreads();
+      if (tid == 0) emit[ch * R + r] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
     }
   }
 }
 
+int64_t scale_emit_parts(int side, int64_t N, int64_t T) {
+  return side == 0 ? cdiv(N, 64) : cdiv(T, SC_TCHUNK);
+}
+
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
-                        hipStream_t s) {
+                        double* emit, SumJob* emitted, hipStream_t s) {
   const int64_t rtiles = cdiv(R, 64), wtiles = rtiles * cdiv(N, 64), tchunks = cdiv(T, SC_TCHUNK);
   const int64_t blocks = wtiles + R * tchunks;
   prof_begin("scale", s);
   hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, rtiles, wtiles,
-                     tchunks);
+                     tchunks, emit);
   prof_end("scale", s);
+  if (emit && emitted) *emitted = SumJob{emit, (int)scale_emit_parts(side, N, T), R, nullptr, nullptr, nullptr};
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ _lib_uws = _decl("dna_unrolled_workspace_bytes", _sz, _i64, _i64, _i64, _OP)
 _lib_normalize = _decl("dna_normalize", _int, _int, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p)
 _lib_update_H = _decl("dna_update_H", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_update_W = _decl("dna_update_W", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
+_lib_iterate = _decl("dna_iterate", _int, _p, _p, _p, _i64, _i64, _i64, _int, _OP, _p, _sz, _p)
 _lib_mu = _decl("mu_update", _int, _int, _p, _p, _p, _i64, _i64, _i64, _int, _p, _OP, _p, _sz, _p)
 _lib_kl = _decl("kl_cost", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
 _lib_gh = _decl("dna_gradient_hessian", _int, _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _p, _p, _sz, _p)
@@ -73,7 +74,7 @@ _lib_build_info = _decl("dna_build_info", ctypes.c_char_p)
 
 EXPORTED = [
     "dna_default_opts", "dna_workspace_bytes", "dna_normalize", "dna_update_H", "dna_update_W",
-    "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
+    "dna_iterate", "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
     "dna_unrolled_workspace_bytes", "dna_unrolled_H_fwd", "dna_unrolled_H_bwd",
     "dna_status_string", "dna_last_error", "dna_profile_enable", "dna_profile_reset",
     "dna_profile_read", "dna_build_info",
@@ -201,6 +202,16 @@ def update_W(V, W, H, *, mask=False, d_sel=False, margin=False, **kw):
     _check(_lib_update_W(_ptr(V), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
                          _ptr(m), _ptr(d), _ptr(g), _stream()))
     return m, d, g
+
+
+def iterate(V, W, H, iters, **kw):
+    """``iters`` full DNA iterations in place (Algorithm 1 steps 4-29), one
+    native call; the normalisations hand their factor sums to the next step."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    _check(_lib_iterate(_ptr(V), _ptr(W), _ptr(H), N, T, R, int(iters), ctypes.byref(o), _ptr(ws), ws.numel(),
+                        _stream()))
 
 
 def mu_update(side, V, W, H, with_cost=False, **kw):
@@ -359,7 +370,8 @@ def profile_read():
 # --------------------------------------------------------------------------- drivers
 
 def dna_iteration(V, W, H, **kw):
-    """One full DNA iteration of Algorithm 1: H step, step 16, W step, step 29."""
+    """One full DNA iteration of Algorithm 1 (H step, step 16, W step, step 29)
+    as four separate entry-point calls; ``iterate`` runs the same in one call."""
     update_H(V, W, H, **kw)
     normalize(1, W, H, **kw)
     update_W(V, W, H, **kw)
@@ -382,9 +394,14 @@ def fit(V, W, H, iters, method="dna", record_kl=False, **kw):
     kls = torch.empty(iters + 1, dtype=torch.float64, device=V.device) if record_kl else None
     if record_kl:
         kl_cost(V, W, H, out=kls[0:1], **kw)
-    step = dna_iteration if method == "dna" else mu_iteration
+    if method == "dna" and not record_kl:
+        iterate(V, W, H, iters, **kw)
+        return None
     for k in range(iters):
-        step(V, W, H, **kw)
+        if method == "dna":
+            iterate(V, W, H, 1, **kw)
+        else:
+            mu_iteration(V, W, H, **kw)
         if record_kl:
             kl_cost(V, W, H, out=kls[k + 1:k + 2], **kw)
     return kls

@@ -87,6 +87,12 @@ def test_invalid_arguments_rejected_before_launch():
     assert dna._lib_normalize(2, fake, fake, 8, 8, 2, ctypes.byref(o), ws, 1 << 30, null) == 1
     assert dna._lib_mu(0, fake, fake, fake, 8, 8, 2, 1, null, ctypes.byref(o), ws, 1 << 30, null) == 1
     assert dna._lib_kl(fake, fake, fake, 8, 8, 2, ctypes.byref(o), ws, 1 << 30, null, null) == 1
+    # whole iterations: null factor, negative count, small workspace; zero iterations enqueue nothing
+    It = dna._lib_iterate
+    assert It(fake, fake, null, 8, 8, 2, 3, ctypes.byref(o), ws, 1 << 30, null) == 1
+    assert It(fake, fake, fake, 8, 8, 2, -1, ctypes.byref(o), ws, 1 << 30, null) == 1
+    assert It(fake, fake, fake, 8, 8, 2, 3, ctypes.byref(o), ws, 16, null) == 2
+    assert It(fake, fake, fake, 8, 8, 2, 0, ctypes.byref(o), ws, 1 << 30, null) == 0
 
 
 def test_build_info_names_target():
