@@ -54,12 +54,12 @@ enum RatioMode {
 // a sum <= 0 sets CHK_DOMAIN in *check (if not nullptr).  A kernel that receives
 // a SumJob with part != nullptr performs it on the side, before its own work.
 struct SumJob {
-  const double* part;
-  int nparts;
-  int64_t R;
-  double* s64;
-  float* s32;
-  int* check;
+  const double* part = nullptr;
+  int nparts = 0;
+  int64_t R = 0;
+  double* s64 = nullptr;
+  float* s32 = nullptr;
+  int* check = nullptr;
 };
 
 struct RatioArgs {

@@ -12,7 +12,12 @@
 // partials and V sums that the candidate kernels read from the two-kernel path.
 //
 // Every operand tile is 64 x 64 fp32 in LDS with a 68-float row pitch; MFMA
-// v_mfma_f32_32x32x2_f32, four waves each owning one 32 x 32 block.
+// v_mfma_f32_32x32x2_f32, four waves each owning one 32 x 32 block.  An operand
+// whose contraction index runs along the LDS row (read down a column by the
+// 32 lanes of a half-wave) is read four k at a time with one 16-byte load, which
+// the 68-float pitch keeps free of bank conflicts: the eight k of a group g are
+// shared as k = 8g + 4h + m, lane half h, instruction m = 0..3 (kq), and the
+// other operand follows the same order.
 #include <math.h>
 
 #include <algorithm>
@@ -26,6 +31,10 @@ namespace dna {
 using GF = Geo<64, 64, GEMM_BK, 2, 2>;     // 64 x 64 tiles, waves 2 x 2 of 32 x 32 (reductions)
 constexpr int FP = 64 + 4;                   // LDS row pitch (floats)
 constexpr int FT = 64 * FP;                  // floats per LDS tile
+
+// Contraction index of lane half (lane >> 5), group g, instruction m; 16-byte LDS read.
+__device__ __forceinline__ int kq(int g, int lane, int m) { return 8 * g + 4 * (lane >> 5) + m; }
+__device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
 
 // Load a 64 x 64 block of a row-major fp32 matrix (rows r0.., columns c0..,
 // zero outside rows < nr, columns < nc) into registers: four float4 per thread.
@@ -123,7 +132,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
 #pragma unroll
     for (int v = 0; v < 16; ++v) z[v] = 0.f;
 #pragma unroll 4
-    for (int k = 0; k < 64; k += 2) {
+    for (int k = 0; k < 64; k += 2) {             // (measured faster here than the 16-byte form)
       const int kr = k + (lane >> 5);
       z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + cl], z);
     }
@@ -217,10 +226,14 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
     f32x16 z;
 #pragma unroll
     for (int v = 0; v < 16; ++v) z[v] = 0.f;
-#pragma unroll 4
-    for (int k = 0; k < 64; k += 2) {
-      const int kr = k + (lane >> 5);
-      z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + tl], z);
+    {
+      const float* pa = lw + (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
+#pragma unroll 2
+      for (int g = 0; g < 8; ++g) {
+        const f32x4 a4 = ld4(pa + 8 * g);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) z = mfma32(a4[m], lh[kq(g, lane, m) * FP + tl], z);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -234,16 +247,21 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       rp[0][0][v] += (double)x;
     }
     __syncthreads();
+    {
+      const int o = (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
+      const float* pb = lh + tl * FP + 4 * (lane >> 5);   // H[r = tl][t]
 #pragma unroll 2
-    for (int k = 0; k < 64; k += 2) {
-      const int kr = k + (lane >> 5);
-      const int nl = wm * 32 + (lane & 31);
-      const float a0 = lq[0][nl * FP + kr];
-      const float a1 = lq[1][nl * FP + kr];
-      const float b = lh[tl * FP + kr];           // H[r = tl][t = kr]
-      acc[0] = mfma32(a0, b, acc[0]);
-      acc[1] = mfma32(a0 - 1.f, b, acc[1]);
-      acc[2] = mfma32(a1, b * b, acc[2]);
+      for (int g = 0; g < 8; ++g) {
+        const f32x4 a0 = ld4(lq[0] + o + 8 * g);
+        const f32x4 a1 = ld4(lq[1] + o + 8 * g);
+        const f32x4 b = ld4(pb + 8 * g);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          acc[0] = mfma32(a0[m], b[m], acc[0]);
+          acc[1] = mfma32(a0[m] - 1.f, b[m], acc[1]);
+          acc[2] = mfma32(a1[m], b[m] * b[m], acc[2]);
+        }
+      }
     }
     if (more)
 #pragma unroll
@@ -316,12 +334,18 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
     f32x16 zn, dz;
 #pragma unroll
     for (int v = 0; v < 16; ++v) zn[v] = dz[v] = 0.f;
-#pragma unroll 4
-    for (int k = 0; k < 64; k += 2) {
-      const int kr = k + (lane >> 5);
-      const float a = lw[(wm * 32 + (lane & 31)) * FP + kr];
-      zn = mfma32(a, ln[kr * FP + cl], zn);
-      dz = mfma32(a, ld[kr * FP + cl], dz);
+    {
+      const float* pa = lw + (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
+#pragma unroll 2
+      for (int g = 0; g < 8; ++g) {
+        const f32x4 a4 = ld4(pa + 8 * g);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int kk = kq(g, lane, m) * FP + cl;
+          zn = mfma32(a4[m], ln[kk], zn);
+          dz = mfma32(a4[m], ld[kk], dz);
+        }
+      }
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -391,13 +415,19 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
     f32x16 zn, dz;
 #pragma unroll
     for (int v = 0; v < 16; ++v) zn[v] = dz[v] = 0.f;
-#pragma unroll 4
-    for (int k = 0; k < 64; k += 2) {
-      const int kr = k + (lane >> 5);
-      const float b = lh[kr * FP + tl];
-      const int nl = (wm * 32 + (lane & 31)) * FP + kr;
-      zn = mfma32(ln[nl], b, zn);
-      dz = mfma32(ld[nl], b, dz);
+    {
+      const int o = (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
+#pragma unroll 2
+      for (int g = 0; g < 8; ++g) {
+        const f32x4 an = ld4(ln + o + 8 * g);
+        const f32x4 ad = ld4(ld + o + 8 * g);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const float b = lh[kq(g, lane, m) * FP + tl];
+          zn = mfma32(an[m], b, zn);
+          dz = mfma32(ad[m], b, dz);
+        }
+      }
     }
     double s0[16], s1[16], s2[16];
 #pragma unroll
