@@ -137,6 +137,71 @@ dna_status dna_iterate(const float* V, float* W, float* H,
                        int64_t N, int64_t T, int64_t R, int iters,
                        const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Sparse V (Sec. 4.2: term-document matrices with 0.2-0.35% nonzeros) ---
+ * Only the nonzeros of V enter Q, Q-bar and the costs (end of Sec. 3), so the
+ * O(NRT) products become O(nnz R) gathers.  V is described by its nonzeros (all
+ * values > 0) in two orders plus segment tables; every array is device memory
+ * owned by the caller (int32 indices, float32 values); the struct itself is a
+ * host object:
+ *   col_idx, val, row_of  [nnz]  CSR order (rows ascending, columns ascending
+ *                                within a row): column, value and row of each entry
+ *   csc_row, csc_col, csc_pos [nnz]  the same entries in CSC order (columns
+ *                                ascending): row, column, and position in the
+ *                                CSR arrays
+ *   segr_start [nseg_r + 1], segr_ptr [N + 1]  the CSR positions cut into
+ *                                segments of at most 64 entries of one row
+ *                                (segr_start ascending from 0, last = nnz); row n
+ *                                owns segments segr_ptr[n] .. segr_ptr[n+1] - 1
+ *   segc_start [nseg_c + 1], segc_ptr [T + 1]  the same for the CSC positions
+ *                                and the columns.
+ * The Python binding builds all of them from a COO or CSR matrix.  An index out
+ * of range is clamped in the kernels (wrong numbers, never an out-of-bounds
+ * access); checked mode additionally rejects non-finite or negative values.
+ * FP32 products only (opts->gemm must be DNA_GEMM_FP32), R <= 256, nnz < 2^31. */
+typedef struct {
+  int64_t nnz;
+  const int32_t* col_idx;
+  const float* val;
+  const int32_t* row_of;
+  const int32_t* csc_row;
+  const int32_t* csc_col;
+  const int32_t* csc_pos;
+  int64_t nseg_r, nseg_c;
+  const int32_t* segr_start;
+  const int32_t* segr_ptr;
+  const int32_t* segc_start;
+  const int32_t* segc_ptr;
+} dna_sparse_v;
+
+/* Workspace for the dna_sparse_* calls below (0 on invalid sizes). */
+size_t dna_sparse_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_sparse_v* V, const dna_opts* opts);
+
+/* dna_update_H / dna_update_W (Algorithm 1 steps 4-15 / 17-28) with a sparse
+ * V: the same candidates (eq. 7, 11, 14, 15, 17, 10), the same costs over the
+ * nonzeros and the same selection, with the same optional outputs.  The
+ * gradient sum u_c = sum_n w_nr (q_nt - 1) takes the zeros of V as q = 0: it is
+ * formed as the sum over the nonzeros minus (c_r - sum of w_nr over them). */
+dna_status dna_sparse_update_H(const dna_sparse_v* V, const float* W, float* H,
+                               int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                               void* ws, size_t ws_bytes, uint8_t* chose_newton,
+                               double* d_sel, double* margin, void* stream);
+dna_status dna_sparse_update_W(const dna_sparse_v* V, float* W, const float* H,
+                               int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                               void* ws, size_t ws_bytes, uint8_t* chose_newton,
+                               double* d_sel, double* margin, void* stream);
+
+/* eq. 1 with a sparse V: sum over the nonzeros of v log(v/z) - v, plus
+ * sum z = sum_r c_r (H 1)_r in closed form.  out: one device double. */
+dna_status dna_sparse_kl_cost(const dna_sparse_v* V, const float* W, const float* H,
+                              int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                              void* ws, size_t ws_bytes, double* out, void* stream);
+
+/* `iters` full iterations (dna_sparse_update_H, dna_normalize(1),
+ * dna_sparse_update_W, dna_normalize(0)) in place.  iters < 0: DNA_EINVAL. */
+dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H,
+                              int64_t N, int64_t T, int64_t R, int iters,
+                              const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
 /* Plain multiplicative update (eq. 11 at lambda = 0; Lee-Seung):
  *   side 0: H <- H * (W^t Q) / (W^t 1)      side 1: W <- W * (Q H^t) / (H 1)
  * with Q = V / (W H).  If with_cost != 0, d_out (length T for side 0, N for

@@ -26,7 +26,8 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
 ]
-SOURCES = ["api.hip", "kernels_fwd.hip", "kernels_adj.hip", "kernels_16.hip", "kernels_fused.hip"]
+SOURCES = ["api.hip", "kernels_fwd.hip", "kernels_adj.hip", "kernels_16.hip", "kernels_fused.hip",
+           "kernels_sparse.hip"]
 
 
 def _compile(src: str) -> str:

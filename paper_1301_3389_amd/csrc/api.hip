@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 #include "kernels_16.hpp"
 #include "kernels_adj.hpp"
+#include "kernels_sparse.hpp"
 
 namespace dna {
 
@@ -677,6 +678,212 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
     Gin = Gout;
   }
   return DNA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sparse V.
+// ---------------------------------------------------------------------------
+struct SpLayout {
+  int64_t nseg;
+  size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, vpart, cseg, fseg, part,
+      fpart, check, total;
+};
+
+static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse_v* V) {
+  SpLayout L;
+  L.nseg = std::max<int64_t>({V->nseg_r, V->nseg_c, 1});
+  const size_t fac = (size_t)std::max(R * T, N * R), mx = (size_t)std::max(N, T), nnz = (size_t)V->nnz;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  L.ht = take((size_t)T * R * 4);
+  L.q = take(nnz * 4);
+  L.qb = take(nnz * 4);
+  L.gp = take(4 * (size_t)L.nseg * R * 4);
+  L.vseg = take((size_t)L.nseg * 8);
+  L.pu = take(fac * 4);
+  L.puc = take(fac * 4);
+  L.py = take(fac * 4);
+  L.xmu = take(fac * 4);
+  L.xn = take(fac * 4);
+  L.xd = take(fac * 4);
+  L.xnt = take((size_t)R * T * 4);
+  L.xdt = take((size_t)R * T * 4);
+  L.c32 = take((size_t)R * 4);
+  L.c64 = take((size_t)R * 8);
+  L.g64 = take((size_t)R * 8);
+  L.sump = take((size_t)SUM_PARTS * R * 8);
+  L.vpart = take(mx * 8);
+  L.cseg = take(3 * (size_t)L.nseg * 8);
+  L.fseg = take((size_t)L.nseg * 4);
+  L.part = take(3 * mx * 8);
+  L.fpart = take(mx * 4);
+  L.check = take(16);
+  L.total = off;
+  return L;
+}
+
+static dna_status check_sparse(const dna_sparse_v* V, int64_t N, int64_t T, int64_t R, const dna_opts* o) {
+  if (!V) return fail(DNA_EINVAL, "sparse V is NULL");
+  DNA_TRY(check_dims(N, T, R));
+  DNA_TRY(check_opts(o));
+  if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "sparse V supports FP32 products only");
+  if (R > SP_MAX_R) return fail(DNA_EUNSUPPORTED, "sparse V supports R <= 256");
+  if (V->nnz < 0 || V->nnz >= ((int64_t)1 << 31)) return fail(DNA_EINVAL, "nnz must lie in [0, 2^31)");
+  if (V->nseg_r < 0 || V->nseg_c < 0 || V->nseg_r > V->nnz || V->nseg_c > V->nnz)
+    return fail(DNA_EINVAL, "segment counts must lie in [0, nnz]");
+  if (!V->segr_start || !V->segr_ptr || !V->segc_start || !V->segc_ptr)
+    return fail(DNA_EINVAL, "segment tables must not be NULL");
+  if (V->nnz > 0 && (!V->col_idx || !V->val || !V->row_of || !V->csc_row || !V->csc_col || !V->csc_pos))
+    return fail(DNA_EINVAL, "an index or value array is NULL");
+  return DNA_OK;
+}
+
+static SpV sp_view(const dna_sparse_v* V) {
+  return SpV{V->nnz, V->col_idx, V->val, V->row_of, V->csc_row, V->csc_col, V->csc_pos, V->nseg_r, V->nseg_c,
+             V->segr_start, V->segr_ptr, V->segc_start, V->segc_ptr};
+}
+
+struct SpCommon {
+  SpLayout L;
+  int* chk;
+  hipStream_t s;
+};
+
+static dna_status sp_prologue(const dna_sparse_v* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
+                              const dna_opts* o, void* ws, size_t ws_bytes, void* stream, SpCommon& c) {
+  DNA_TRY(check_sparse(V, N, T, R, o));
+  c.L = make_sp_layout(N, T, R, V);
+  DNA_TRY(check_ws(ws, ws_bytes, c.L.total));
+  c.s = static_cast<hipStream_t>(stream);
+  c.chk = o->checked ? at<int>(ws, c.L.check) : nullptr;
+  if (c.chk) {
+    const float* bufs[3] = {W, H, V->val};
+    const int64_t sizes[3] = {N * R, R * T, V->nnz};
+    DNA_TRY(checked_begin(c.chk, bufs, sizes, V->nnz > 0 ? 3 : 2, c.s));
+  }
+  return DNA_OK;
+}
+
+static dna_status sp_epilogue(const SpCommon& c) {
+  if (c.chk) return checked_end(c.chk, c.s);
+  return DNA_OK;
+}
+
+// One sparse half-step: side 0 updates H (R x T) given W, side 1 updates W.
+static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                               const dna_opts* o, const SpCommon& c, void* ws, uint8_t* mask, double* dsel,
+                               double* margin) {
+  const SpLayout& L = c.L;
+  const SpV v = sp_view(V);
+  float* Ht = at<float>(ws, L.ht);
+  float* q = at<float>(ws, L.q);
+  float* qb = at<float>(ws, L.qb);
+  float* pu = at<float>(ws, L.pu);
+  float* puc = at<float>(ws, L.puc);
+  float* py = at<float>(ws, L.py);
+  float* Xmu = at<float>(ws, L.xmu);
+  float* Xn = at<float>(ws, L.xn);
+  float* Xd = at<float>(ws, L.xd);
+  float* c32 = at<float>(ws, L.c32);
+  double* c64 = at<double>(ws, L.c64);
+  double* vpart = at<double>(ws, L.vpart);
+  double* part = at<double>(ws, L.part);
+  int* fpart = at<int>(ws, L.fpart);
+  DNA_HIP(launch_sp_transpose(H, Ht, R, T, c.s), "sp_transpose H");
+  SumJob job;
+  if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
+  else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
+  job.s64 = c64; job.s32 = c32; job.check = c.chk;  // c = W^t 1 (side 0) or g = H 1 (side 1)
+  DNA_HIP(launch_sp_zq(v, W, Ht, N, T, R, q, qb, c.chk, job, c.s), "sp_zq");
+  DNA_HIP(launch_sp_grad(side, v, side == 0 ? W : Ht, q, qb, c64, N, T, R, at<float>(ws, L.gp),
+                         at<double>(ws, L.vseg), pu, puc, py, vpart, c.s), "sp_grad");
+  if (side == 0) {
+    DNA_HIP(launch_cand_H(H, pu, puc, py, 1, c32, vpart, 1, T, R, o->eps, o->alpha, Xmu, Xn, nullptr, nullptr, c.s),
+            "cand_H");
+    DNA_HIP(launch_sp_diff(Xmu, Xn, Xd, R * T, c.s), "sp_diff");
+    float* XnT = at<float>(ws, L.xnt);
+    float* XdT = at<float>(ws, L.xdt);
+    DNA_HIP(launch_sp_transpose(Xn, XnT, R, T, c.s), "sp_transpose X_DNA");
+    DNA_HIP(launch_sp_transpose(Xd, XdT, R, T, c.s), "sp_transpose X_MU - X_DNA");
+    DNA_HIP(launch_sp_cost(0, v, W, XnT, XdT, N, T, R, at<double>(ws, L.cseg), at<int>(ws, L.fseg), part, fpart,
+                           c.s), "sp_cost_H");
+    DNA_HIP(launch_select_H(Xmu, Xn, H, part, fpart, 1, T, R, mask, dsel, margin, c.s), "select_H");
+  } else {
+    DNA_HIP(launch_cand_W(W, pu, puc, py, 1, c32, vpart, 1, N, R, o->eps, o->alpha, Xmu, Xn, nullptr, nullptr, c.s),
+            "cand_W");
+    DNA_HIP(launch_sp_diff(Xmu, Xn, Xd, N * R, c.s), "sp_diff");
+    DNA_HIP(launch_sp_cost(1, v, Ht, Xn, Xd, N, T, R, at<double>(ws, L.cseg), at<int>(ws, L.fseg), part, fpart,
+                           c.s), "sp_cost_W");
+    DNA_HIP(launch_select_W(Xmu, Xn, W, part, fpart, 1, N, R, mask, dsel, margin, c.s), "select_W");
+  }
+  return DNA_OK;
+}
+
+size_t dna_sparse_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_sparse_v* V, const dna_opts* o) {
+  if (!V || !o || N <= 0 || T <= 0 || R <= 0 || V->nnz < 0) return 0;
+  return make_sp_layout(N, T, R, V).total;
+}
+
+dna_status dna_sparse_update_H(const dna_sparse_v* V, const float* W, float* H, int64_t N, int64_t T, int64_t R,
+                               const dna_opts* o, void* ws, size_t ws_bytes, uint8_t* chose_newton,
+                               double* d_sel, double* margin, void* stream) {
+  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
+  SpCommon c;
+  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  DNA_TRY(sp_half_step(0, V, const_cast<float*>(W), H, N, T, R, o, c, ws, chose_newton, d_sel, margin));
+  return sp_epilogue(c);
+}
+
+dna_status dna_sparse_update_W(const dna_sparse_v* V, float* W, const float* H, int64_t N, int64_t T, int64_t R,
+                               const dna_opts* o, void* ws, size_t ws_bytes, uint8_t* chose_newton,
+                               double* d_sel, double* margin, void* stream) {
+  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
+  SpCommon c;
+  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  DNA_TRY(sp_half_step(1, V, W, const_cast<float*>(H), N, T, R, o, c, ws, chose_newton, d_sel, margin));
+  return sp_epilogue(c);
+}
+
+dna_status dna_sparse_kl_cost(const dna_sparse_v* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
+                              const dna_opts* o, void* ws, size_t ws_bytes, double* out, void* stream) {
+  if (!W || !H || !out) return fail(DNA_EINVAL, "W, H or out is NULL");
+  SpCommon c;
+  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  const SpLayout& L = c.L;
+  float* Ht = at<float>(ws, L.ht);
+  double* sp = at<double>(ws, L.sump);
+  DNA_HIP(launch_sp_transpose(H, Ht, R, T, c.s), "sp_transpose H");
+  SumJob job;
+  DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");
+  job.s64 = at<double>(ws, L.c64);
+  DNA_HIP(launch_sum_final(job, c.s), "sum_final c");
+  DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");
+  job.s64 = at<double>(ws, L.g64);
+  DNA_HIP(launch_sum_final(job, c.s), "sum_final g");
+  DNA_HIP(launch_sp_kl(sp_view(V), W, Ht, N, T, R, at<double>(ws, L.cseg), at<double>(ws, L.c64),
+                       at<double>(ws, L.g64), out, c.s), "sp_kl");
+  return sp_epilogue(c);
+}
+
+dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T, int64_t R, int iters,
+                              const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
+  if (iters < 0) return fail(DNA_EINVAL, "iters must be >= 0");
+  SpCommon c;
+  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  double* sp = at<double>(ws, c.L.sump);
+  for (int it = 0; it < iters; ++it) {
+    DNA_TRY(sp_half_step(0, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
+    SumJob job;
+    DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");           // step 16
+    job.check = c.chk;
+    DNA_HIP(launch_scale(1, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+    DNA_TRY(sp_half_step(1, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
+    DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");           // step 29
+    job.check = c.chk;
+    DNA_HIP(launch_scale(0, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+  }
+  return sp_epilogue(c);
 }
 
 const char* dna_status_string(dna_status s) {

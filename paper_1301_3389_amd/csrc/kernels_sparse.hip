@@ -1,0 +1,432 @@
+// kernels_sparse.hip -- DNA half-steps for a sparse V (the sparse data matrices
+// of Sec. 4.2), float32 products, float64 cost sums.
+//
+// Only the nonzeros of V enter Q, Q-bar and the costs (end of Sec. 3), so every
+// O(NRT) product of the dense path becomes O(nnz R) work:
+//   k_sp_zq        z = W[n,:] . H[:,t] at each nonzero (one thread per nonzero,
+//                  CSR order), q = v/z, q-bar = q/z            (steps 2-3, 10)
+//   k_sp_grad_H    per column segment of the CSC order: the partial sums over
+//                  its nonzeros of W q, W (q - 1), W and (W*W) q-bar, one lane
+//                  per r                                         (steps 4-5, 10)
+//   k_sp_comb_H    per column t: the segment partials in order, then
+//                  u_c = sum_nz W (q - 1) - sum_{v = 0} W, the last term as
+//                  c - sum_nz W in float64 (zeros of V contribute q = 0)
+//   k_sp_cost_H    per column segment, one lane per nonzero: z_DNA and
+//                  dZ = W (H_MU - H_DNA) at that entry, the cost terms of the
+//                  dense path, wave sums in float64                 (steps 7-9, 12-14)
+// and the W half-step mirrors them over the CSR row segments with H^t rows.
+// The candidate, selection and normalisation kernels of the dense path serve
+// unchanged (one "split", one cost tile).  Segments hold at most SP_SEG
+// nonzeros of one row (column), so a few long rows of a skewed matrix do not
+// serialise the launch; they are added back in a fixed order.
+#include <math.h>
+
+#include <algorithm>
+
+#include "core.hpp"
+#include "epilogue.hpp"
+#include "kernels.hpp"
+#include "kernels_sparse.hpp"
+
+namespace dna {
+
+// a . b over R floats (rows of row-major matrices), vector loads when both rows
+// are 16-byte aligned.
+__device__ __forceinline__ float dot_rows(const float* __restrict__ a, const float* __restrict__ b, int64_t R,
+                                          bool vec) {
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int64_t r = 0;
+  if (vec) {
+    for (; r + 4 <= R; r += 4) {
+      const f32x4 x = *reinterpret_cast<const f32x4*>(a + r);
+      const f32x4 y = *reinterpret_cast<const f32x4*>(b + r);
+      s0 = fmaf(x[0], y[0], s0);
+      s1 = fmaf(x[1], y[1], s1);
+      s2 = fmaf(x[2], y[2], s2);
+      s3 = fmaf(x[3], y[3], s3);
+    }
+  }
+  for (; r < R; ++r) s0 = fmaf(a[r], b[r], s0);
+  return (s0 + s1) + (s2 + s3);
+}
+
+__device__ __forceinline__ bool rows_aligned(const void* a, const void* b, int64_t R) {
+  return (R & 3) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+}
+
+// Indices read from the caller's arrays are clamped into range, so a malformed
+// structure gives wrong numbers, never an out-of-bounds access.
+__device__ __forceinline__ int64_t clampi(int64_t i, int64_t n) { return (i >= 0 && i < n) ? i : 0; }
+// A range [a, b) read from a segment table, clamped into [0, n].
+__device__ __forceinline__ void clamp_range(int64_t& a, int64_t& b, int64_t n) {
+  a = std::min<int64_t>(std::max<int64_t>(a, 0), n);
+  b = std::min<int64_t>(std::max<int64_t>(b, a), n);
+}
+
+// ---------------------------------------------------------------------------
+// Transpose of an R x T row-major matrix into T x R (H^t rows for the gathers).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sp_transpose(const float* __restrict__ X, float* __restrict__ Y, int64_t R,
+                                                      int64_t T) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int64_t t0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t r = r0 + ty + 8 * k, t = t0 + tx;
+    tile[ty + 8 * k][tx] = (r < R && t < T) ? X[r * T + t] : 0.f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t t = t0 + ty + 8 * k, r = r0 + tx;
+    if (r < R && t < T) Y[t * R + r] = tile[tx][ty + 8 * k];
+  }
+}
+
+hipError_t launch_sp_transpose(const float* X, float* Y, int64_t R, int64_t T, hipStream_t s) {
+  prof_begin("sp_transpose", s);
+  hipLaunchKernelGGL(k_sp_transpose, dim3((unsigned)cdiv(T, 32), (unsigned)cdiv(R, 32)), dim3(256), 0, s, X, Y, R, T);
+  prof_end("sp_transpose", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// z, q, q-bar at every nonzero (CSR order).  `fin` folds the second level of a
+// factor sum into this launch (as the dense ratio pass does).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sp_zq(SpV v, const float* __restrict__ W, const float* __restrict__ Ht,
+                                               int64_t N, int64_t T, int64_t R, float* __restrict__ q,
+                                               float* __restrict__ qb, int* check, SumJob fin) {
+  sum_job(fin);
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int bad = 0;
+  if (j < v.nnz) {
+    const int64_t n = clampi(v.row_of[j], N), t = clampi(v.col_idx[j], T);
+    const float* a = W + n * R;
+    const float* b = Ht + t * R;
+    const float z = dot_rows(a, b, R, rows_aligned(a, b, R));
+    const float x = v.val[j];
+    const bool pos = x > 0.f;
+    const float iz = __builtin_amdgcn_rcpf(z);
+    const float qq = pos ? x * iz : 0.f;
+    q[j] = qq;
+    qb[j] = pos ? qq * iz : 0.f;
+    bad = (pos && !(z > 0.f)) ? 1 : 0;
+  }
+  bad = wave_or(bad);
+  if (check && bad && (threadIdx.x & 63) == 0) atomicOr(check, CHK_DOMAIN);
+}
+
+hipError_t launch_sp_zq(const SpV& v, const float* W, const float* Ht, int64_t N, int64_t T, int64_t R, float* q,
+                        float* qb, int* check, const SumJob& fin, hipStream_t s) {
+  prof_begin("sp_zq", s);
+  hipLaunchKernelGGL(k_sp_zq, dim3((unsigned)std::max<int64_t>(1, cdiv(v.nnz, 256))), dim3(256), 0, s, v, W, Ht, N, T,
+                     R, q, qb, check, fin);
+  prof_end("sp_zq", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gradient sums.  One wave per segment, lane r (+64 k, k < KR); segment partials
+// gp[4][seg][R] = (F q, F (q - 1), F, (F*F) q-bar) and the V sum of the segment.
+//   SIDE 0 (H step): segments of the CSC order, F = W[n, :] of each entry's row.
+//   SIDE 1 (W step): segments of the CSR order, F = H^t[t, :] of each entry's column.
+// ---------------------------------------------------------------------------
+template <int SIDE, int KR>
+__global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict__ F, const float* __restrict__ q,
+                                                 const float* __restrict__ qb, int64_t N, int64_t T, int64_t R,
+                                                 float* __restrict__ gp, double* __restrict__ vseg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
+  if (sg >= nseg) return;
+  const int32_t* start = SIDE == 0 ? v.segc_start : v.segr_start;
+  int64_t i0 = start[sg], i1 = start[sg + 1];
+  clamp_range(i0, i1, v.nnz);
+  const int64_t nF = SIDE == 0 ? N : T;
+  float u[KR], uc[KR], fs[KR], y[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) u[k] = uc[k] = fs[k] = y[k] = 0.f;
+  double vs = 0.0;
+#pragma unroll 4
+  for (int64_t i = i0; i < i1; ++i) {
+    int64_t p, row;
+    if (SIDE == 0) {
+      p = clampi(v.csc_pos[i], v.nnz);
+      row = clampi(v.csc_row[i], nF);
+    } else {
+      p = i;
+      row = clampi(v.col_idx[i], nF);
+    }
+    const float qq = q[p], qbb = qb[p];
+    vs += (double)v.val[p];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int64_t r = lane + 64 * k;
+      const float f = r < R ? F[row * R + r] : 0.f;
+      u[k] = fmaf(f, qq, u[k]);
+      uc[k] = fmaf(f, qq - 1.f, uc[k]);
+      fs[k] += f;
+      y[k] = fmaf(f * f, qbb, y[k]);
+    }
+  }
+  const int64_t stride = nseg * R;
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int64_t r = lane + 64 * k;
+    if (r < R) {
+      gp[sg * R + r] = u[k];
+      gp[stride + sg * R + r] = uc[k];
+      gp[2 * stride + sg * R + r] = fs[k];
+      gp[3 * stride + sg * R + r] = y[k];
+    }
+  }
+  if (lane == 0) vseg[sg] = vs;
+}
+
+// Per column t (SIDE 0) / row n (SIDE 1): the segment partials in order, written
+// in the layout of the dense split partials with one split (SIDE 0: [r][t],
+// SIDE 1: [n][r]) and the V sums as one tile; u_c adds the entries where v = 0
+// (q = 0, so q - 1 = -1): minus (c_r - sum_nz F_r), formed in float64.
+template <int SIDE>
+__global__ __launch_bounds__(256) void k_sp_comb(SpV v, const float* __restrict__ gp, const double* __restrict__ vseg,
+                                                 const double* __restrict__ c64, int64_t N, int64_t T, int64_t R,
+                                                 float* __restrict__ pu, float* __restrict__ puc,
+                                                 float* __restrict__ py, double* __restrict__ vpart) {
+  const int lane = threadIdx.x & 63;
+  const int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // column t / row n
+  const int64_t no = SIDE == 0 ? T : N;
+  if (o >= no) return;
+  const int32_t* segp = SIDE == 0 ? v.segc_ptr : v.segr_ptr;
+  const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
+  int64_t s0 = segp[o], s1 = segp[o + 1];
+  clamp_range(s0, s1, nseg);
+  const int64_t stride = nseg * R;
+  for (int64_t r = lane; r < R; r += 64) {
+    float u = 0.f, uc = 0.f, fs = 0.f, y = 0.f;
+    for (int64_t sg = s0; sg < s1; ++sg) {
+      u += gp[sg * R + r];
+      uc += gp[stride + sg * R + r];
+      fs += gp[2 * stride + sg * R + r];
+      y += gp[3 * stride + sg * R + r];
+    }
+    const float ucz = (float)((double)uc - (c64[r] - (double)fs));
+    const int64_t idx = SIDE == 0 ? r * T + o : o * R + r;
+    pu[idx] = u;
+    puc[idx] = ucz;
+    py[idx] = y;
+  }
+  if (lane == 0) {
+    double vs = 0.0;
+    for (int64_t sg = s0; sg < s1; ++sg) vs += vseg[sg];
+    vpart[o] = vs;
+  }
+}
+
+template <int SIDE>
+static hipError_t grad_launch(const SpV& v, const float* F, const float* q, const float* qb, int64_t N, int64_t T,
+                              int64_t R, float* gp, double* vseg, hipStream_t s) {
+  const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
+  const dim3 grid((unsigned)std::max<int64_t>(1, cdiv(nseg, 4)));
+  if (R <= 64)
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 1>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+  else if (R <= 128)
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 2>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+  else
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 4>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+  return hipGetLastError();
+}
+
+hipError_t launch_sp_grad(int side, const SpV& v, const float* F, const float* q, const float* qb, const double* c64,
+                          int64_t N, int64_t T, int64_t R, float* gp, double* vseg, float* pu, float* puc, float* py,
+                          double* vpart, hipStream_t s) {
+  if (R > SP_MAX_R) return hipErrorInvalidValue;
+  prof_begin(side == 0 ? "sp_grad_H" : "sp_grad_W", s);
+  hipError_t e = side == 0 ? grad_launch<0>(v, F, q, qb, N, T, R, gp, vseg, s)
+                           : grad_launch<1>(v, F, q, qb, N, T, R, gp, vseg, s);
+  prof_end(side == 0 ? "sp_grad_H" : "sp_grad_W", s);
+  if (e != hipSuccess) return e;
+  prof_begin(side == 0 ? "sp_comb_H" : "sp_comb_W", s);
+  const int64_t no = side == 0 ? T : N;
+  if (side == 0)
+    hipLaunchKernelGGL(k_sp_comb<0>, dim3((unsigned)cdiv(no, 4)), dim3(256), 0, s, v, gp, vseg, c64, N, T, R, pu, puc,
+                       py, vpart);
+  else
+    hipLaunchKernelGGL(k_sp_comb<1>, dim3((unsigned)cdiv(no, 4)), dim3(256), 0, s, v, gp, vseg, c64, N, T, R, pu, puc,
+                       py, vpart);
+  prof_end(side == 0 ? "sp_comb_H" : "sp_comb_W", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Candidate costs.  One wave per segment, one lane per nonzero (segments hold
+// at most 64): z_DNA = F_row . X_DNA and dZ = F_row . (X_MU - X_DNA) at the
+// entry, the dense path's cost terms (cost_acc), then wave sums in float64 and
+// the OR of the flags -> cseg[3][seg], fseg[seg].
+//   SIDE 0: CSC segments, F_row = W[n, :], X rows = candidates^t[t, :] (T x R).
+//   SIDE 1: CSR segments, F_row = H^t[t, :], X rows = candidates[n, :] (N x R).
+// ---------------------------------------------------------------------------
+template <int SIDE>
+__global__ __launch_bounds__(256) void k_sp_cost(SpV v, const float* __restrict__ F, const float* __restrict__ Xn,
+                                                 const float* __restrict__ Xd, int64_t N, int64_t T, int64_t R,
+                                                 double* __restrict__ cseg, int* __restrict__ fseg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
+  if (sg >= nseg) return;
+  const int32_t* start = SIDE == 0 ? v.segc_start : v.segr_start;
+  int64_t i0 = start[sg], i1 = start[sg + 1];
+  clamp_range(i0, i1, v.nnz);
+  const int64_t i = i0 + lane;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  int fl = 0;
+  if (i < i1) {
+    int64_t p, n, t;
+    if (SIDE == 0) {
+      p = clampi(v.csc_pos[i], v.nnz);
+      n = clampi(v.csc_row[i], N);
+      t = clampi(v.csc_col[i], T);
+    } else {
+      p = i;
+      n = clampi(v.row_of[i], N);
+      t = clampi(v.col_idx[i], T);
+    }
+    const float* f = SIDE == 0 ? F + n * R : F + t * R;
+    const float* xn = SIDE == 0 ? Xn + t * R : Xn + n * R;
+    const float* xd = SIDE == 0 ? Xd + t * R : Xd + n * R;
+    const bool al = rows_aligned(f, xn, R) && rows_aligned(f, xd, R);
+    const float zN = dot_rows(f, xn, R, al);
+    const float dz = dot_rows(f, xd, R, al);
+    fl = cost_acc(v.val[p], zN, dz, s0, s1, s2);
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  fl = wave_or(fl);
+  if (lane == 0) {
+    cseg[sg] = s0 * LN2;
+    cseg[nseg + sg] = s1 * LN2;
+    cseg[2 * nseg + sg] = s2 * LN2;
+    fseg[sg] = fl;
+  }
+}
+
+// Per column (row): the segment sums in order, in the dense cost pass's part
+// layout with one tile: part[q][o], fpart[o].
+template <int SIDE>
+__global__ __launch_bounds__(256) void k_sp_cost_comb(SpV v, const double* __restrict__ cseg,
+                                                      const int* __restrict__ fseg, int64_t no,
+                                                      double* __restrict__ part, int* __restrict__ fpart) {
+  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= no) return;
+  const int32_t* segp = SIDE == 0 ? v.segc_ptr : v.segr_ptr;
+  const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
+  double a = 0.0, b = 0.0, c = 0.0;
+  int fl = 0;
+  int64_t s0 = segp[o], s1 = segp[o + 1];
+  clamp_range(s0, s1, nseg);
+  for (int64_t sg = s0; sg < s1; ++sg) {
+    a += cseg[sg];
+    b += cseg[nseg + sg];
+    c += cseg[2 * nseg + sg];
+    fl |= fseg[sg];
+  }
+  part[o] = a;
+  part[no + o] = b;
+  part[2 * no + o] = c;
+  fpart[o] = fl;
+}
+
+hipError_t launch_sp_cost(int side, const SpV& v, const float* F, const float* Xn, const float* Xd, int64_t N,
+                          int64_t T, int64_t R, double* cseg, int* fseg, double* part, int* fpart, hipStream_t s) {
+  const int64_t nseg = side == 0 ? v.nseg_c : v.nseg_r;
+  const dim3 grid((unsigned)std::max<int64_t>(1, cdiv(nseg, 4)));
+  prof_begin(side == 0 ? "sp_cost_H" : "sp_cost_W", s);
+  if (side == 0)
+    hipLaunchKernelGGL(k_sp_cost<0>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg);
+  else
+    hipLaunchKernelGGL(k_sp_cost<1>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg);
+  prof_end(side == 0 ? "sp_cost_H" : "sp_cost_W", s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t no = side == 0 ? T : N;
+  prof_begin(side == 0 ? "sp_cost_comb_H" : "sp_cost_comb_W", s);
+  if (side == 0)
+    hipLaunchKernelGGL(k_sp_cost_comb<0>, dim3((unsigned)cdiv(no, 256)), dim3(256), 0, s, v, cseg, fseg, no, part,
+                       fpart);
+  else
+    hipLaunchKernelGGL(k_sp_cost_comb<1>, dim3((unsigned)cdiv(no, 256)), dim3(256), 0, s, v, cseg, fseg, no, part,
+                       fpart);
+  prof_end(side == 0 ? "sp_cost_comb_H" : "sp_cost_comb_W", s);
+  return hipGetLastError();
+}
+
+// X_MU - X_DNA (elementwise, n elements), the second operand of the dZ product.
+__global__ __launch_bounds__(256) void k_sp_diff(const float* __restrict__ a, const float* __restrict__ b,
+                                                 float* __restrict__ d, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) d[e] = a[e] - b[e];
+}
+
+hipError_t launch_sp_diff(const float* Xmu, const float* Xn, float* D, int64_t n, hipStream_t s) {
+  prof_begin("sp_diff", s);
+  hipLaunchKernelGGL(k_sp_diff, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 4096)), dim3(256), 0, s, Xmu, Xn, D,
+                     n);
+  prof_end("sp_diff", s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// KL cost (eq. 1) of a sparse V: sum_nz v log(v/z) - sum v + sum z, with
+// sum z = sum_r c_r (H 1)_r.  Per CSR segment (one lane per nonzero) the float64
+// sum of v log(v/z) - v; the final kernel adds the segments in order and the
+// closed-form sum of Z.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sp_kl_seg(SpV v, const float* __restrict__ W, const float* __restrict__ Ht,
+                                                   int64_t N, int64_t T, int64_t R, double* __restrict__ kseg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (sg >= v.nseg_r) return;
+  int64_t i0 = v.segr_start[sg], i1 = v.segr_start[sg + 1];
+  clamp_range(i0, i1, v.nnz);
+  const int64_t i = i0 + lane;
+  double term = 0.0;
+  if (i < i1) {
+    const int64_t n = clampi(v.row_of[i], N), t = clampi(v.col_idx[i], T);
+    const float* a = W + n * R;
+    const float* b = Ht + t * R;
+    const float z = dot_rows(a, b, R, rows_aligned(a, b, R));
+    const float x = v.val[i];
+    if (x > 0.f) term = (double)(x * log2_hw(x * __builtin_amdgcn_rcpf(z))) * LN2 - (double)x;
+  }
+  term = wave_sum(term);
+  if (lane == 0) kseg[sg] = term;
+}
+
+// One block: segments in a fixed order (256 strided lanes, then a fixed tree),
+// plus sum_r c_r g_r from the float64 factor sums.
+__global__ __launch_bounds__(256) void k_sp_kl_final(const double* __restrict__ kseg, int64_t nseg,
+                                                     const double* __restrict__ c, const double* __restrict__ g,
+                                                     int64_t R, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int64_t k = tid; k < nseg; k += 256) s += kseg[k];
+  for (int64_t r = tid; r < R; r += 256) s += c[r] * g[r];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_sp_kl(const SpV& v, const float* W, const float* Ht, int64_t N, int64_t T, int64_t R,
+                        double* kseg, const double* c, const double* g, double* out, hipStream_t s) {
+  prof_begin("sp_kl", s);
+  hipLaunchKernelGGL(k_sp_kl_seg, dim3((unsigned)std::max<int64_t>(1, cdiv(v.nseg_r, 4))), dim3(256), 0, s, v, W, Ht,
+                     N, T, R, kseg);
+  hipLaunchKernelGGL(k_sp_kl_final, dim3(1), dim3(256), 0, s, kseg, v.nseg_r, c, g, R, out);
+  prof_end("sp_kl", s);
+  return hipGetLastError();
+}
+
+}  // namespace dna

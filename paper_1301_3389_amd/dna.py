@@ -56,6 +56,20 @@ _lib_normalize = _decl("dna_normalize", _int, _int, _p, _p, _i64, _i64, _i64, _O
 _lib_update_H = _decl("dna_update_H", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_update_W = _decl("dna_update_W", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_iterate = _decl("dna_iterate", _int, _p, _p, _p, _i64, _i64, _i64, _int, _OP, _p, _sz, _p)
+class SparseVStruct(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int64), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("row_of", ctypes.c_void_p), ("csc_row", ctypes.c_void_p), ("csc_col", ctypes.c_void_p),
+                ("csc_pos", ctypes.c_void_p), ("nseg_r", ctypes.c_int64), ("nseg_c", ctypes.c_int64),
+                ("segr_start", ctypes.c_void_p), ("segr_ptr", ctypes.c_void_p),
+                ("segc_start", ctypes.c_void_p), ("segc_ptr", ctypes.c_void_p)]
+
+
+_SP = ctypes.POINTER(SparseVStruct)
+_lib_sp_ws = _decl("dna_sparse_workspace_bytes", _sz, _i64, _i64, _i64, _SP, _OP)
+_lib_sp_H = _decl("dna_sparse_update_H", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
+_lib_sp_W = _decl("dna_sparse_update_W", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
+_lib_sp_kl = _decl("dna_sparse_kl_cost", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
+_lib_sp_it = _decl("dna_sparse_iterate", _int, _SP, _p, _p, _i64, _i64, _i64, _int, _OP, _p, _sz, _p)
 _lib_mu = _decl("mu_update", _int, _int, _p, _p, _p, _i64, _i64, _i64, _int, _p, _OP, _p, _sz, _p)
 _lib_kl = _decl("kl_cost", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
 _lib_gh = _decl("dna_gradient_hessian", _int, _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _p, _p, _sz, _p)
@@ -74,7 +88,8 @@ _lib_build_info = _decl("dna_build_info", ctypes.c_char_p)
 
 EXPORTED = [
     "dna_default_opts", "dna_workspace_bytes", "dna_normalize", "dna_update_H", "dna_update_W",
-    "dna_iterate", "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
+    "dna_iterate", "dna_sparse_workspace_bytes", "dna_sparse_update_H", "dna_sparse_update_W",
+    "dna_sparse_kl_cost", "dna_sparse_iterate", "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
     "dna_unrolled_workspace_bytes", "dna_unrolled_H_fwd", "dna_unrolled_H_bwd",
     "dna_status_string", "dna_last_error", "dna_profile_enable", "dna_profile_reset",
     "dna_profile_read", "dna_build_info",
@@ -350,6 +365,159 @@ def unrolled_h(W, V, H_init, K, eps=0.01, alpha=4.0):
 
 
 # --------------------------------------------------------------------------- profiling
+
+# --------------------------------------------------------------------------- sparse V
+
+SP_SEG = 64     # entries per segment at most (the header's segment tables)
+
+
+def _segments(keys, ngroups, nnz):
+    """Cut positions 0..nnz-1, whose group keys ascend, into segments of at most
+    SP_SEG positions of one group: (start[nseg + 1], group_ptr[ngroups + 1])."""
+    import numpy as np
+    counts = np.bincount(keys, minlength=ngroups).astype(np.int64)
+    first = np.concatenate([[0], np.cumsum(counts)])[:-1]
+    nseg_g = (counts + SP_SEG - 1) // SP_SEG
+    ptr = np.concatenate([[0], np.cumsum(nseg_g)])
+    total = int(ptr[-1])
+    grp = np.repeat(np.arange(ngroups), nseg_g)
+    within = np.arange(total) - np.repeat(ptr[:-1], nseg_g)
+    start = np.concatenate([first[grp] + SP_SEG * within, [nnz]])
+    return start.astype(np.int32), ptr.astype(np.int32)
+
+
+class SparseV:
+    """A sparse V (N x T, nonzero values > 0) on the GPU in the layout of
+    dna_sparse_v: CSR and CSC orders of the nonzeros and their segment tables,
+    built on the host from COO triplets (duplicates are added, explicit zeros
+    dropped).  Holds the device arrays; ``.c`` is the struct passed to the ABI."""
+
+    def __init__(self, rows, cols, vals, N, T, device=None):
+        import numpy as np
+        rows = np.asarray(rows, dtype=np.int64)
+        cols = np.asarray(cols, dtype=np.int64)
+        vals = np.asarray(vals, dtype=np.float32)
+        if rows.shape != cols.shape or rows.shape != vals.shape or rows.ndim != 1:
+            raise ValueError("rows, cols and vals must be 1-D arrays of one length")
+        if rows.size and (rows.min() < 0 or rows.max() >= N or cols.min() < 0 or cols.max() >= T):
+            raise ValueError("an index lies outside the N x T matrix")
+        key = rows * T + cols
+        order = np.argsort(key, kind="stable")
+        key, vals = key[order], vals[order]
+        uniq, first = np.unique(key, return_index=True)
+        vals = np.add.reduceat(vals, first) if key.size else vals
+        keep = vals != 0
+        uniq, vals = uniq[keep], vals[keep].astype(np.float32)
+        r, c = (uniq // T).astype(np.int32), (uniq % T).astype(np.int32)
+        nnz = int(uniq.size)
+        pos = np.lexsort((r, c)).astype(np.int32)            # CSR positions in CSC order
+        segr_start, segr_ptr = _segments(r, N, nnz)
+        segc_start, segc_ptr = _segments(c[pos], T, nnz)
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.N, self.T, self.nnz = int(N), int(T), nnz
+        self.col_idx, self.val, self.row_of = up(c), up(vals), up(r)
+        self.csc_row, self.csc_col, self.csc_pos = up(r[pos]), up(c[pos]), up(pos)
+        self.segr_start, self.segr_ptr = up(segr_start), up(segr_ptr)
+        self.segc_start, self.segc_ptr = up(segc_start), up(segc_ptr)
+        self.c = SparseVStruct(nnz, self.col_idx.data_ptr(), self.val.data_ptr(), self.row_of.data_ptr(),
+                               self.csc_row.data_ptr(), self.csc_col.data_ptr(), self.csc_pos.data_ptr(),
+                               int(segr_start.size - 1), int(segc_start.size - 1), self.segr_start.data_ptr(),
+                               self.segr_ptr.data_ptr(), self.segc_start.data_ptr(), self.segc_ptr.data_ptr())
+
+    @classmethod
+    def from_dense(cls, V, device=None):
+        """From a dense host array (its nonzero entries)."""
+        import numpy as np
+        V = np.asarray(V)
+        rows, cols = np.nonzero(V)
+        return cls(rows, cols, V[rows, cols], V.shape[0], V.shape[1], device=device)
+
+
+def _sp_dims(V, W, H):
+    if not isinstance(V, SparseV):
+        raise TypeError("V must be a SparseV")
+    N, T = V.N, V.T
+    R = W.shape[1]
+    _mat(W, "W", (N, R))
+    _mat(H, "H", (R, T))
+    return N, T, R
+
+
+def sparse_workspace(V, R, opts):
+    nbytes = _lib_sp_ws(V.N, V.T, R, ctypes.byref(V.c), ctypes.byref(opts))
+    if nbytes == 0:
+        raise DNAError(1, "invalid sparse problem size")
+    dev = torch.cuda.current_device()
+    key = (dev, "sparse")
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{dev}")
+        _ws_cache[key] = buf
+    return buf, nbytes
+
+
+def sparse_update_H(V, W, H, *, mask=False, d_sel=False, margin=False, **kw):
+    """dna_update_H with a sparse V (SparseV), in place; returns (mask, d_sel, margin)."""
+    N, T, R = _sp_dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = sparse_workspace(V, R, o)
+    m = _opt_out(mask, T, torch.uint8, W.device)
+    d = _opt_out(d_sel, T, torch.float64, W.device)
+    g = _opt_out(margin, T, torch.float64, W.device)
+    _check(_lib_sp_H(ctypes.byref(V.c), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
+                     _ptr(m), _ptr(d), _ptr(g), _stream()))
+    return m, d, g
+
+
+def sparse_update_W(V, W, H, *, mask=False, d_sel=False, margin=False, **kw):
+    """dna_update_W with a sparse V (SparseV), in place; returns (mask, d_sel, margin)."""
+    N, T, R = _sp_dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = sparse_workspace(V, R, o)
+    m = _opt_out(mask, N, torch.uint8, W.device)
+    d = _opt_out(d_sel, N, torch.float64, W.device)
+    g = _opt_out(margin, N, torch.float64, W.device)
+    _check(_lib_sp_W(ctypes.byref(V.c), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
+                     _ptr(m), _ptr(d), _ptr(g), _stream()))
+    return m, d, g
+
+
+def sparse_kl_cost(V, W, H, out=None, **kw):
+    """eq. 1 with a sparse V; returns a 1-element float64 device tensor."""
+    N, T, R = _sp_dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = sparse_workspace(V, R, o)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=W.device)
+    _check(_lib_sp_kl(ctypes.byref(V.c), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
+                      _ptr(out), _stream()))
+    return out
+
+
+def sparse_iterate(V, W, H, iters, **kw):
+    """``iters`` full DNA iterations with a sparse V, in place."""
+    N, T, R = _sp_dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = sparse_workspace(V, R, o)
+    _check(_lib_sp_it(ctypes.byref(V.c), _ptr(W), _ptr(H), N, T, R, int(iters), ctypes.byref(o), _ptr(ws),
+                      ws.numel(), _stream()))
+
+
+def sparse_fit(V, W, H, iters, record_kl=False, **kw):
+    """Algorithm 1 with a sparse V from step 1, in place; the KL after each
+    iteration as a float64 device tensor when ``record_kl`` (index 0 = start)."""
+    normalize(0, W, H, **kw)
+    if not record_kl:
+        sparse_iterate(V, W, H, iters, **kw)
+        return None
+    kls = torch.empty(iters + 1, dtype=torch.float64, device=W.device)
+    sparse_kl_cost(V, W, H, out=kls[0:1], **kw)
+    for k in range(iters):
+        sparse_iterate(V, W, H, 1, **kw)
+        sparse_kl_cost(V, W, H, out=kls[k + 1:k + 2], **kw)
+    return kls
+
 
 def profile_enable(on=True):
     _lib_prof_enable(1 if on else 0)

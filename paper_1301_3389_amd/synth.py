@@ -195,5 +195,63 @@ def config5(T=None):
                     None, H0.astype(np.float32), {"config": 5})
 
 
+def sparse_counts(N, T, density, seed, zipf=1.0, max_row_frac=0.3):
+    """Term-document-like sparse counts with the structure of the sparse
+    matrices of Sec. 4.2 (few nonzeros, a skewed number of them per row): row
+    (term) n occurs in a number of columns (documents) proportional to
+    rank^-zipf, the ranks a random permutation of the rows, scaled to the
+    requested overall density and capped at max_row_frac * T; its columns are
+    drawn uniformly without replacement; each count is 1 + Poisson(1.5).
+    Returns (rows, cols, vals) in row order, vals float32."""
+    rng = np.random.default_rng(seed)
+    rank = rng.permutation(N) + 1.0
+    w = rank ** -float(zipf)
+    target, cap = density * N * T, float(int(max_row_frac * T))
+    k = w / w.sum() * target
+    for _ in range(50):                   # capped rows hand their excess to the others
+        k = np.minimum(k, cap)
+        free = k < cap
+        deficit = target - k.sum()
+        if deficit <= 0.5 or not free.any():
+            break
+        k[free] *= 1.0 + deficit / k[free].sum()
+    k = np.rint(np.minimum(k, cap)).astype(np.int64)
+    rows = np.repeat(np.arange(N, dtype=np.int64), k)
+    cols = np.concatenate([rng.choice(T, size=int(kn), replace=False) for kn in k if kn > 0] or
+                          [np.zeros(0, dtype=np.int64)]).astype(np.int64)
+    vals = (1.0 + rng.poisson(1.5, size=rows.size)).astype(np.float32)
+    return rows, cols, vals
+
+
+def sparse_problem(N, T, R, density, seed, zipf=1.0):
+    """A sparse-V parity problem: sparse_counts as a dense float32 V (the oracle's
+    input) and uniform(0.1, 1) initial factors."""
+    rows, cols, vals = sparse_counts(N, T, density, seed, zipf=zipf)
+    V = np.zeros((N, T), dtype=np.float32)
+    V[rows, cols] = vals
+    rng = np.random.default_rng(seed + 7)
+    W = rng.uniform(0.1, 1.0, size=(N, R)).astype(np.float32)
+    H = rng.uniform(0.1, 1.0, size=(R, T)).astype(np.float32)
+    return Workload(V, W, H, None, None, {"kind": "sparse", "seed": seed, "density": density, "zipf": zipf})
+
+
+# Shapes of the paper's sparse matrices (Sec. 4.2): TDT2 36771 terms x 10212
+# documents at 0.35% nonzeros, Newsgroup 61188 x 18774 at 0.2%.  The rank is not
+# stated there; R = 40 is one of the ranks of its dense experiments.
+SPARSE_SHAPES = {"tdt2": (36771, 10212, 0.0035), "newsgroup": (61188, 18774, 0.002)}
+
+
+def sparse_workload(name, R=40):
+    """(rows, cols, vals, N, T, W, H) of a synthetic stand-in for a Sec. 4.2
+    matrix (no dense V is formed)."""
+    N, T, density = SPARSE_SHAPES[name]
+    seed = DATA_SEED_BASE + 10 + sorted(SPARSE_SHAPES).index(name)
+    rows, cols, vals = sparse_counts(N, T, density, seed)
+    rng = np.random.default_rng(seed + 1000)
+    W = rng.uniform(0.1, 1.0, size=(N, R)).astype(np.float32)
+    H = rng.uniform(0.1, 1.0, size=(R, T)).astype(np.float32)
+    return rows, cols, vals, N, T, W, H
+
+
 def config(k, **kw):
     return {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k](**kw)

@@ -1,0 +1,172 @@
+"""Sparse V (Sec. 4.2): the sparse entry points against the FP64 oracle run on
+the same V stored densely (its zeros excluded, end of Sec. 3), and against the
+dense GPU path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import dna_oracle as O
+from paper_1301_3389_amd import synth
+from parity_util import (FLOOR32, STATE_TIE, STEP_TOL, TRAJ_TOL, cost_err, gpu, host, log_result, recon_gap,
+                         rel_cols, selection_report)
+
+# N, T, R, density, seed: ragged sizes; rows longer than one 64-entry segment;
+# empty rows and columns at the lowest densities
+SHAPES = [
+    (300, 333, 37, 0.05, 1),
+    (257, 130, 10, 0.2, 2),
+    (1000, 515, 64, 0.02, 3),
+    (130, 200, 1, 0.1, 4),
+    (200, 300, 100, 0.05, 5),
+    (150, 170, 200, 0.08, 6),
+    (400, 90, 16, 0.004, 7),
+]
+
+
+def _problem(N, T, R, density, seed):
+    w = synth.sparse_problem(N, T, R, density, seed)
+    return w.V, w.W, w.H
+
+
+# --------------------------------------------------------------------------- host side (CPU)
+
+def test_sparse_layout_host():
+    """CSR / CSC orders, the CSR positions of the CSC entries, duplicates added,
+    zeros dropped, and segments of at most 64 entries of one row / column."""
+    from paper_1301_3389_amd.dna import SP_SEG, SparseV
+    rng = np.random.default_rng(0)
+    N, T = 70, 300
+    rows = np.concatenate([rng.integers(0, N, 3000), np.full(200, 5), [3, 3]])
+    cols = np.concatenate([rng.integers(0, T, 3000), rng.integers(0, T, 200), [7, 7]])
+    vals = rng.uniform(0.5, 2.0, rows.size).astype(np.float32)
+    vals[:10] = 0.0
+    sv = SparseV(rows, cols, vals, N, T, device="cpu")
+    dense = np.zeros((N, T))
+    np.add.at(dense, (rows, cols), vals.astype(np.float64))
+    r, c, v = sv.row_of.numpy(), sv.col_idx.numpy(), sv.val.numpy()
+    assert sv.nnz == int((dense != 0).sum())
+    assert np.all(np.diff(r.astype(np.int64) * T + c) > 0)                  # CSR order, unique
+    np.testing.assert_allclose(v, dense[r, c], rtol=1e-6)
+    pos = sv.csc_pos.numpy()
+    assert np.array_equal(np.sort(pos), np.arange(sv.nnz))
+    assert np.array_equal(sv.csc_row.numpy(), r[pos]) and np.array_equal(sv.csc_col.numpy(), c[pos])
+    cc, cr = sv.csc_col.numpy().astype(np.int64), sv.csc_row.numpy().astype(np.int64)
+    assert np.all(np.diff(cc * N + cr) > 0)                                   # CSC order
+    for start, ptr, key, n in ((sv.segr_start, sv.segr_ptr, r, N), (sv.segc_start, sv.segc_ptr, cc, T)):
+        start, ptr = start.numpy().astype(np.int64), ptr.numpy().astype(np.int64)
+        assert start[0] == 0 and start[-1] == sv.nnz and np.all(np.diff(start) > 0)
+        assert np.all(np.diff(start) <= SP_SEG)
+        assert ptr[0] == 0 and ptr[-1] == start.size - 1 and np.all(np.diff(ptr) >= 0)
+        for g in range(n):
+            seg = range(ptr[g], ptr[g + 1])
+            ent = np.concatenate([np.arange(start[s], start[s + 1]) for s in seg]) if len(seg) else []
+            assert np.array_equal(np.asarray(ent, dtype=np.int64), np.nonzero(key == g)[0])
+
+
+def test_sparse_counts_recipe():
+    rows, cols, vals = synth.sparse_counts(2000, 900, 0.01, 3)
+    assert rows.size == np.unique(rows * 900 + cols).size                    # no duplicate entries
+    assert abs(rows.size / (2000 * 900) - 0.01) < 5e-4
+    assert vals.min() >= 1.0
+    assert np.bincount(rows, minlength=2000).max() <= 0.3 * 900
+
+
+# --------------------------------------------------------------------------- GPU parity
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("side", [0, 1])
+def test_sparse_update(dna, shape, side):
+    V, W, H = _problem(*shape)
+    sv = dna.SparseV.from_dense(V)
+    Wg, Hg = gpu(W), gpu(H)
+    if side == 0:
+        m, d, g = dna.sparse_update_H(sv, Wg, Hg, mask=True, d_sel=True, margin=True)
+        got = host(Hg)
+        r = oracle.h_step(V, W, H, value_floor=FLOOR32)
+    else:
+        m, d, g = dna.sparse_update_W(sv, Wg, Hg, mask=True, d_sel=True, margin=True)
+        got = host(Wg)
+        r = oracle.w_step(V, W, H, value_floor=FLOOR32)
+    ax = 0 if side == 0 else 1
+    mask = host(m).astype(bool)
+    Wd, Hd = W.astype(float), H.astype(float)
+    zgap = recon_gap(Wd @ r.X_mu, Wd @ r.X_newton, 0) if side == 0 else recon_gap(r.X_mu @ Hd, r.X_newton @ Hd, 1)
+    rep = selection_report(mask, r.chose_newton, r.margin, r.d_mu, STATE_TIE, zgap)
+    same = mask == r.chose_newton
+    err = rel_cols(got, r.X, ax)[same]
+    sel = r.chose_newton[None, :] if side == 0 else r.chose_newton[:, None]
+    err_other = rel_cols(got, np.where(sel, r.X_mu, r.X_newton), ax)[~same]
+    vsum = V.astype(float).sum(axis=0 if side == 0 else 1)
+    err_d = cost_err(host(d)[same], r.d_sel[same], vsum[same])
+    err_m = cost_err(host(g), r.margin, vsum)
+    log_result("sparse_update", {"shape": shape, "side": side, **rep,
+                                 "max_err": float(err.max()) if err.size else 0.0, "err_dsel": err_d})
+    assert rep["n_flips_above_tie"] == 0, rep
+    assert err.size == 0 or err.max() <= STEP_TOL
+    assert err_other.size == 0 or err_other.max() <= STEP_TOL
+    assert err_d <= 1.0 and err_m <= 1.0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", SHAPES[:4])
+def test_sparse_kl_cost(dna, shape):
+    V, W, H = _problem(*shape)
+    sv = dna.SparseV.from_dense(V)
+    got = dna.sparse_kl_cost(sv, gpu(W), gpu(H)).item()
+    ref = O.kl_cost(V, W, H)
+    log_result("sparse_kl", {"shape": shape, "rel": abs(got - ref) / abs(ref)})
+    assert abs(got - ref) <= 1e-6 * abs(ref)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [SHAPES[0], SHAPES[2], SHAPES[4]])
+def test_sparse_matches_dense(dna, shape):
+    """Two full iterations with the sparse and the dense entry points from one
+    state: the KL agrees to 1e-6 and all but tie-flipped entries to 1e-4."""
+    V, W, H = _problem(*shape)
+    sv = dna.SparseV.from_dense(V)
+    Vg = gpu(V)
+    Wa, Ha = gpu(W), gpu(H)
+    dna.normalize(0, Wa, Ha)
+    Wb, Hb = Wa.clone(), Ha.clone()
+    dna.sparse_iterate(sv, Wa, Ha, 2)
+    dna.iterate(Vg, Wb, Hb, 2)
+    kla, klb = dna.kl_cost(Vg, Wa, Ha).item(), dna.kl_cost(Vg, Wb, Hb).item()
+    assert abs(kla - klb) <= 1e-6 * abs(klb)
+    for a, b in ((Wa, Wb), (Ha, Hb)):
+        a, b = host(a), host(b)
+        rel = np.abs(a - b) / np.maximum(np.abs(b), 1e-30)
+        assert np.mean(rel > 1e-4) <= 0.01, float(rel.max())
+
+
+@pytest.mark.gpu
+def test_sparse_trajectory(dna):
+    """20 iterations of Algorithm 1 on a 600 x 500 matrix at 2% density (R = 20):
+    the KL after every iteration within 1e-4 of the oracle's, non-increasing."""
+    V, W, H = _problem(600, 500, 20, 0.02, 11)
+    sv = dna.SparseV.from_dense(V)
+    kls = host(dna.sparse_fit(sv, gpu(W), gpu(H), 20, record_kl=True))
+    ref = np.array(oracle.fit_dna(V, W, H, 20, value_floor=FLOOR32).kl)
+    rel = np.abs(kls - ref) / np.abs(ref)
+    log_result("sparse_trajectory", {"max_rel": float(rel.max()), "kl_last": float(kls[-1])})
+    assert rel.max() <= TRAJ_TOL
+    assert np.all(np.diff(kls) <= 1e-6 * np.abs(kls[:-1]))
+
+
+@pytest.mark.gpu
+def test_sparse_unsupported(dna):
+    V, W, H = _problem(50, 40, 8, 0.1, 12)
+    sv = dna.SparseV.from_dense(V)
+    with pytest.raises(dna.DNAError) as e:
+        dna.sparse_update_H(sv, gpu(W), gpu(H), gemm="bf16")
+    assert e.value.status == 6
+    Wb = torch.rand(50, 300, device="cuda")
+    Hb = torch.rand(300, 40, device="cuda")
+    with pytest.raises(dna.DNAError) as e:
+        dna.sparse_update_W(sv, Wb, Hb)
+    assert e.value.status == 6
+    with pytest.raises(dna.DNAError) as e:
+        dna.sparse_iterate(sv, gpu(W), gpu(H), -1)
+    assert e.value.status == 1
