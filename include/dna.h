@@ -196,6 +196,13 @@ dna_status dna_sparse_kl_cost(const dna_sparse_v* V, const float* W, const float
                               int64_t N, int64_t T, int64_t R, const dna_opts* opts,
                               void* ws, size_t ws_bytes, double* out, void* stream);
 
+/* mu_update (eq. 11) with a sparse V, without the cost output:
+ * side 0: H <- H * (W^t Q) / (W^t 1); side 1: W <- W * (Q H^t) / (H 1), Q at
+ * the nonzeros only. */
+dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float* H,
+                                int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                                void* ws, size_t ws_bytes, void* stream);
+
 /* `iters` full iterations (dna_sparse_update_H, dna_normalize(1),
  * dna_sparse_update_W, dna_normalize(0)) in place.  iters < 0: DNA_EINVAL. */
 dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H,

@@ -795,7 +795,7 @@ static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float*
   else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
   job.s64 = c64; job.s32 = c32; job.check = c.chk;  // c = W^t 1 (side 0) or g = H 1 (side 1)
   DNA_HIP(launch_sp_zq(v, W, Ht, N, T, R, q, qb, c.chk, job, c.s), "sp_zq");
-  DNA_HIP(launch_sp_grad(side, v, side == 0 ? W : Ht, q, qb, c64, N, T, R, at<float>(ws, L.gp),
+  DNA_HIP(launch_sp_grad(side, false, v, side == 0 ? W : Ht, q, qb, c64, N, T, R, at<float>(ws, L.gp),
                          at<double>(ws, L.vseg), pu, puc, py, vpart, c.s), "sp_grad");
   if (side == 0) {
     DNA_HIP(launch_cand_H(H, pu, puc, py, 1, c32, vpart, 1, T, R, o->eps, o->alpha, Xmu, Xn, nullptr, nullptr, c.s),
@@ -862,6 +862,32 @@ dna_status dna_sparse_kl_cost(const dna_sparse_v* V, const float* W, const float
   DNA_HIP(launch_sum_final(job, c.s), "sum_final g");
   DNA_HIP(launch_sp_kl(sp_view(V), W, Ht, N, T, R, at<double>(ws, L.cseg), at<double>(ws, L.c64),
                        at<double>(ws, L.g64), out, c.s), "sp_kl");
+  return sp_epilogue(c);
+}
+
+dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T,
+                                int64_t R, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  SpCommon c;
+  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  const SpLayout& L = c.L;
+  const SpV v = sp_view(V);
+  float* Ht = at<float>(ws, L.ht);
+  float* q = at<float>(ws, L.q);
+  float* pu = at<float>(ws, L.pu);
+  float* c32 = at<float>(ws, L.c32);
+  double* c64 = at<double>(ws, L.c64);
+  DNA_HIP(launch_sp_transpose(H, Ht, R, T, c.s), "sp_transpose H");
+  SumJob job;
+  if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
+  else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
+  job.s64 = c64; job.s32 = c32; job.check = c.chk;
+  DNA_HIP(launch_sp_zq(v, W, Ht, N, T, R, q, at<float>(ws, L.qb), c.chk, job, c.s), "sp_zq");
+  DNA_HIP(launch_sp_grad(side, true, v, side == 0 ? W : Ht, q, nullptr, c64, N, T, R, at<float>(ws, L.gp),
+                         nullptr, pu, nullptr, nullptr, nullptr, c.s), "sp_grad_mu");
+  if (side == 0) DNA_HIP(launch_mu_H(H, pu, 1, c32, T, R, nullptr, 1, nullptr, c.s), "mu_H");
+  else DNA_HIP(launch_mu_W(W, pu, 1, c32, N, R, nullptr, 1, nullptr, c.s), "mu_W");
   return sp_epilogue(c);
 }
 

@@ -133,7 +133,7 @@ hipError_t launch_sp_zq(const SpV& v, const float* W, const float* Ht, int64_t N
 //   SIDE 0 (H step): segments of the CSC order, F = W[n, :] of each entry's row.
 //   SIDE 1 (W step): segments of the CSR order, F = H^t[t, :] of each entry's column.
 // ---------------------------------------------------------------------------
-template <int SIDE, int KR>
+template <int SIDE, int KR, bool MU>
 __global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict__ F, const float* __restrict__ q,
                                                  const float* __restrict__ qb, int64_t N, int64_t T, int64_t R,
                                                  float* __restrict__ gp, double* __restrict__ vseg) {
@@ -159,16 +159,18 @@ __global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict_
       p = i;
       row = clampi(v.col_idx[i], nF);
     }
-    const float qq = q[p], qbb = qb[p];
-    vs += (double)v.val[p];
+    const float qq = q[p], qbb = MU ? 0.f : qb[p];
+    if (!MU) vs += (double)v.val[p];
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
       const int64_t r = lane + 64 * k;
       const float f = r < R ? F[row * R + r] : 0.f;
       u[k] = fmaf(f, qq, u[k]);
-      uc[k] = fmaf(f, qq - 1.f, uc[k]);
-      fs[k] += f;
-      y[k] = fmaf(f * f, qbb, y[k]);
+      if (!MU) {
+        uc[k] = fmaf(f, qq - 1.f, uc[k]);
+        fs[k] += f;
+        y[k] = fmaf(f * f, qbb, y[k]);
+      }
     }
   }
   const int64_t stride = nseg * R;
@@ -177,19 +179,21 @@ __global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict_
     const int64_t r = lane + 64 * k;
     if (r < R) {
       gp[sg * R + r] = u[k];
-      gp[stride + sg * R + r] = uc[k];
-      gp[2 * stride + sg * R + r] = fs[k];
-      gp[3 * stride + sg * R + r] = y[k];
+      if (!MU) {
+        gp[stride + sg * R + r] = uc[k];
+        gp[2 * stride + sg * R + r] = fs[k];
+        gp[3 * stride + sg * R + r] = y[k];
+      }
     }
   }
-  if (lane == 0) vseg[sg] = vs;
+  if (!MU && lane == 0) vseg[sg] = vs;
 }
 
 // Per column t (SIDE 0) / row n (SIDE 1): the segment partials in order, written
 // in the layout of the dense split partials with one split (SIDE 0: [r][t],
 // SIDE 1: [n][r]) and the V sums as one tile; u_c adds the entries where v = 0
 // (q = 0, so q - 1 = -1): minus (c_r - sum_nz F_r), formed in float64.
-template <int SIDE>
+template <int SIDE, bool MU>
 __global__ __launch_bounds__(256) void k_sp_comb(SpV v, const float* __restrict__ gp, const double* __restrict__ vseg,
                                                  const double* __restrict__ c64, int64_t N, int64_t T, int64_t R,
                                                  float* __restrict__ pu, float* __restrict__ puc,
@@ -207,56 +211,61 @@ __global__ __launch_bounds__(256) void k_sp_comb(SpV v, const float* __restrict_
     float u = 0.f, uc = 0.f, fs = 0.f, y = 0.f;
     for (int64_t sg = s0; sg < s1; ++sg) {
       u += gp[sg * R + r];
-      uc += gp[stride + sg * R + r];
-      fs += gp[2 * stride + sg * R + r];
-      y += gp[3 * stride + sg * R + r];
+      if (!MU) {
+        uc += gp[stride + sg * R + r];
+        fs += gp[2 * stride + sg * R + r];
+        y += gp[3 * stride + sg * R + r];
+      }
     }
-    const float ucz = (float)((double)uc - (c64[r] - (double)fs));
     const int64_t idx = SIDE == 0 ? r * T + o : o * R + r;
     pu[idx] = u;
-    puc[idx] = ucz;
-    py[idx] = y;
+    if (!MU) {
+      puc[idx] = (float)((double)uc - (c64[r] - (double)fs));
+      py[idx] = y;
+    }
   }
-  if (lane == 0) {
+  if (!MU && lane == 0) {
     double vs = 0.0;
     for (int64_t sg = s0; sg < s1; ++sg) vs += vseg[sg];
     vpart[o] = vs;
   }
 }
 
-template <int SIDE>
-static hipError_t grad_launch(const SpV& v, const float* F, const float* q, const float* qb, int64_t N, int64_t T,
-                              int64_t R, float* gp, double* vseg, hipStream_t s) {
+template <int SIDE, bool MU>
+static hipError_t grad_launch(const SpV& v, const float* F, const float* q, const float* qb, const double* c64,
+                              int64_t N, int64_t T, int64_t R, float* gp, double* vseg, float* pu, float* puc,
+                              float* py, double* vpart, hipStream_t s) {
   const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
   const dim3 grid((unsigned)std::max<int64_t>(1, cdiv(nseg, 4)));
+  const char* gname = SIDE == 0 ? (MU ? "sp_grad_mu_H" : "sp_grad_H") : (MU ? "sp_grad_mu_W" : "sp_grad_W");
+  prof_begin(gname, s);
   if (R <= 64)
-    hipLaunchKernelGGL((k_sp_grad<SIDE, 1>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 1, MU>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
   else if (R <= 128)
-    hipLaunchKernelGGL((k_sp_grad<SIDE, 2>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 2, MU>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
   else
-    hipLaunchKernelGGL((k_sp_grad<SIDE, 4>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 4, MU>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+  prof_end(gname, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t no = SIDE == 0 ? T : N;
+  const char* cname = SIDE == 0 ? "sp_comb_H" : "sp_comb_W";
+  prof_begin(cname, s);
+  hipLaunchKernelGGL((k_sp_comb<SIDE, MU>), dim3((unsigned)cdiv(no, 4)), dim3(256), 0, s, v, gp, vseg, c64, N, T, R,
+                     pu, puc, py, vpart);
+  prof_end(cname, s);
   return hipGetLastError();
 }
 
-hipError_t launch_sp_grad(int side, const SpV& v, const float* F, const float* q, const float* qb, const double* c64,
-                          int64_t N, int64_t T, int64_t R, float* gp, double* vseg, float* pu, float* puc, float* py,
-                          double* vpart, hipStream_t s) {
+hipError_t launch_sp_grad(int side, bool mu_only, const SpV& v, const float* F, const float* q, const float* qb,
+                          const double* c64, int64_t N, int64_t T, int64_t R, float* gp, double* vseg, float* pu,
+                          float* puc, float* py, double* vpart, hipStream_t s) {
   if (R > SP_MAX_R) return hipErrorInvalidValue;
-  prof_begin(side == 0 ? "sp_grad_H" : "sp_grad_W", s);
-  hipError_t e = side == 0 ? grad_launch<0>(v, F, q, qb, N, T, R, gp, vseg, s)
-                           : grad_launch<1>(v, F, q, qb, N, T, R, gp, vseg, s);
-  prof_end(side == 0 ? "sp_grad_H" : "sp_grad_W", s);
-  if (e != hipSuccess) return e;
-  prof_begin(side == 0 ? "sp_comb_H" : "sp_comb_W", s);
-  const int64_t no = side == 0 ? T : N;
   if (side == 0)
-    hipLaunchKernelGGL(k_sp_comb<0>, dim3((unsigned)cdiv(no, 4)), dim3(256), 0, s, v, gp, vseg, c64, N, T, R, pu, puc,
-                       py, vpart);
-  else
-    hipLaunchKernelGGL(k_sp_comb<1>, dim3((unsigned)cdiv(no, 4)), dim3(256), 0, s, v, gp, vseg, c64, N, T, R, pu, puc,
-                       py, vpart);
-  prof_end(side == 0 ? "sp_comb_H" : "sp_comb_W", s);
-  return hipGetLastError();
+    return mu_only ? grad_launch<0, true>(v, F, q, qb, c64, N, T, R, gp, vseg, pu, puc, py, vpart, s)
+                   : grad_launch<0, false>(v, F, q, qb, c64, N, T, R, gp, vseg, pu, puc, py, vpart, s);
+  return mu_only ? grad_launch<1, true>(v, F, q, qb, c64, N, T, R, gp, vseg, pu, puc, py, vpart, s)
+                 : grad_launch<1, false>(v, F, q, qb, c64, N, T, R, gp, vseg, pu, puc, py, vpart, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -30,10 +30,11 @@ hipError_t launch_sp_zq(const SpV& v, const float* W, const float* Ht, int64_t N
 // Gradient sums (side 0: F = W, CSC segments, outputs [r][t]; side 1: F = H^t,
 // CSR segments, outputs [n][r]) in the layout of the dense split partials with
 // one split, and the V sums per column / row.  c64: the factor sums (c or g).
-// gp: 4 x nseg x R floats, vseg: nseg doubles.  R > SP_MAX_R: hipErrorInvalidValue.
-hipError_t launch_sp_grad(int side, const SpV& v, const float* F, const float* q, const float* qb, const double* c64,
-                          int64_t N, int64_t T, int64_t R, float* gp, double* vseg, float* pu, float* puc, float* py,
-                          double* vpart, hipStream_t s);
+// gp: 4 x nseg x R floats, vseg: nseg doubles.  mu_only: the MU numerator u
+// alone (puc, py, vpart untouched).  R > SP_MAX_R: hipErrorInvalidValue.
+hipError_t launch_sp_grad(int side, bool mu_only, const SpV& v, const float* F, const float* q, const float* qb,
+                          const double* c64, int64_t N, int64_t T, int64_t R, float* gp, double* vseg, float* pu,
+                          float* puc, float* py, double* vpart, hipStream_t s);
 // Candidate costs (side 0: F = W, X rows = candidates^t (T x R); side 1: F = H^t,
 // X rows = candidates (N x R)); Xd = X_MU - X_DNA in the same layout as Xn.
 // cseg: 3 x nseg doubles, fseg: nseg ints; part/fpart in the dense cost layout

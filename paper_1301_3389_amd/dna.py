@@ -69,6 +69,7 @@ _lib_sp_ws = _decl("dna_sparse_workspace_bytes", _sz, _i64, _i64, _i64, _SP, _OP
 _lib_sp_H = _decl("dna_sparse_update_H", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_sp_W = _decl("dna_sparse_update_W", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_sp_kl = _decl("dna_sparse_kl_cost", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
+_lib_sp_mu = _decl("dna_sparse_mu_update", _int, _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p)
 _lib_sp_it = _decl("dna_sparse_iterate", _int, _SP, _p, _p, _i64, _i64, _i64, _int, _OP, _p, _sz, _p)
 _lib_mu = _decl("mu_update", _int, _int, _p, _p, _p, _i64, _i64, _i64, _int, _p, _OP, _p, _sz, _p)
 _lib_kl = _decl("kl_cost", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
@@ -89,7 +90,7 @@ _lib_build_info = _decl("dna_build_info", ctypes.c_char_p)
 EXPORTED = [
     "dna_default_opts", "dna_workspace_bytes", "dna_normalize", "dna_update_H", "dna_update_W",
     "dna_iterate", "dna_sparse_workspace_bytes", "dna_sparse_update_H", "dna_sparse_update_W",
-    "dna_sparse_kl_cost", "dna_sparse_iterate", "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
+    "dna_sparse_kl_cost", "dna_sparse_mu_update", "dna_sparse_iterate", "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
     "dna_unrolled_workspace_bytes", "dna_unrolled_H_fwd", "dna_unrolled_H_bwd",
     "dna_status_string", "dna_last_error", "dna_profile_enable", "dna_profile_reset",
     "dna_profile_read", "dna_build_info",
@@ -493,6 +494,23 @@ def sparse_kl_cost(V, W, H, out=None, **kw):
     _check(_lib_sp_kl(ctypes.byref(V.c), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws), ws.numel(),
                       _ptr(out), _stream()))
     return out
+
+
+def sparse_mu_update(side, V, W, H, **kw):
+    """mu_update with a sparse V (no cost output), in place."""
+    N, T, R = _sp_dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = sparse_workspace(V, R, o)
+    _check(_lib_sp_mu(int(side), ctypes.byref(V.c), _ptr(W), _ptr(H), N, T, R, ctypes.byref(o), _ptr(ws),
+                      ws.numel(), _stream()))
+
+
+def sparse_mu_iteration(V, W, H, **kw):
+    """One MU iteration with a sparse V (H step, step 16, W step, step 29)."""
+    sparse_mu_update(0, V, W, H, **kw)
+    normalize(1, W, H, **kw)
+    sparse_mu_update(1, V, W, H, **kw)
+    normalize(0, W, H, **kw)
 
 
 def sparse_iterate(V, W, H, iters, **kw):

@@ -110,6 +110,23 @@ def test_sparse_update(dna, shape, side):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("side", [0, 1])
+def test_sparse_mu_update(dna, shape, side):
+    V, W, H = _problem(*shape)
+    sv = dna.SparseV.from_dense(V)
+    Wg, Hg = gpu(W), gpu(H)
+    dna.sparse_mu_update(side, sv, Wg, Hg)
+    if side == 0:
+        ref, _ = oracle.mu_h_step(V, W, H, value_floor=FLOOR32)
+        err = rel_cols(host(Hg), ref, 0).max()
+    else:
+        ref, _ = oracle.mu_w_step(V, W, H, value_floor=FLOOR32)
+        err = rel_cols(host(Wg), ref, 1).max()
+    assert err <= STEP_TOL
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("shape", SHAPES[:4])
 def test_sparse_kl_cost(dna, shape):
     V, W, H = _problem(*shape)
