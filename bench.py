@@ -142,6 +142,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4])
+    ap.add_argument("--sparse", default=None, choices=["tdt2", "newsgroup"],
+                    help="sparse-V workload shaped like a Sec. 4.2 matrix instead of a dense config")
+    ap.add_argument("--rank", type=int, default=40, help="R of the sparse workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -233,8 +236,100 @@ def cpu_baseline(w, seconds):
             "sample": f"{n} full DNA iterations (FP64 NumPy) of the same workload from the same initial state"}
 
 
+def sparse_kernel_bytes(name, N, T, R, nnz, nseg_r, nseg_c):
+    """Algorithmic HBM bytes of one launch of a sparse-V kernel: the index and
+    value streams it must read, the factor rows it gathers counted once, and
+    what it writes (segment tables and small vectors left out)."""
+    f = 4.0
+    table = {
+        "sp_zq": 12 * nnz + f * R * (N + T) + 8 * nnz,                 # row, col, val; W, H^t; q, q-bar
+        "sp_grad_H": 20 * nnz + f * N * R + 16 * nseg_c * R,            # pos, row, q, q-bar, val; W; partials
+        "sp_grad_W": 16 * nnz + f * T * R + 16 * nseg_r * R,            # col, q, q-bar, val; H^t; partials
+        "sp_cost_H": 16 * nnz + f * N * R + 2 * f * T * R,              # pos, row, col, val; W; candidates^t
+        "sp_cost_W": 16 * nnz + f * T * R + 2 * f * N * R,              # row, col, val (+pos); H^t; candidates
+    }
+    return table.get(name)
+
+
+def sparse_main(args):
+    """One JSON line for a sparse-V workload (Sec. 4.2 shapes): DNA iterations/s,
+    the dominant kernel against the HBM roofline, and the time to MU's KL."""
+    import torch
+    from paper_1301_3389_amd import dna, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    rows, cols, vals, N, T, W0n, H0n = synth.sparse_workload(args.sparse, R=args.rank)
+    R = args.rank
+    sv = dna.SparseV(rows, cols, vals, N, T, device=dev)
+    W0, H0 = torch.from_numpy(W0n).to(dev), torch.from_numpy(H0n).to(dev)
+    W, H = W0.clone(), H0.clone()
+    dna.normalize(0, W, H)
+    dna.sparse_iterate(sv, W, H, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dna.sparse_iterate(sv, W, H, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = 1e3 * wall / args.steps
+    dna.profile_reset()
+    dna.profile_enable(True)
+    dna.sparse_iterate(sv, W, H, args.steps)
+    torch.cuda.synchronize()
+    stats = dna.profile_read()
+    dna.profile_enable(False)
+    kernels = {k: {"launches": n, "avg_ms": t / max(n, 1), "total_ms": t} for k, (n, t) in stats.items()}
+    nseg_r, nseg_c = sv.c.nseg_r, sv.c.nseg_c
+    cands = {k: v for k, v in kernels.items() if sparse_kernel_bytes(k, N, T, R, sv.nnz, nseg_r, nseg_c)}
+    dom = max(cands, key=lambda k: cands[k]["total_ms"])
+    nbytes = sparse_kernel_bytes(dom, N, T, R, sv.nnz, nseg_r, nseg_c)
+    achieved = nbytes / (cands[dom]["avg_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "avg_ms": cands[dom]["avg_ms"], "achieved": achieved,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    target = None
+    if not args.no_target:
+        Wm, Hm = W0.clone(), H0.clone()
+        dna.normalize(0, Wm, Hm)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        for _ in range(args.mu_iters):
+            dna.sparse_mu_iteration(sv, Wm, Hm)
+        torch.cuda.synchronize()
+        mu_wall = time.perf_counter() - tm
+        kl_target = dna.sparse_kl_cost(sv, Wm, Hm).item()
+        Wd, Hd = W0.clone(), H0.clone()
+        kls = dna.sparse_fit(sv, Wd, Hd, args.dna_iters, record_kl=True).cpu().numpy()
+        hit = [k for k, x in enumerate(kls) if x <= kl_target]
+        k_hit = hit[0] if hit else None
+        target = {"target_kl": kl_target, "mu_iters": args.mu_iters,
+                  "mu_ms_per_iter": 1e3 * mu_wall / args.mu_iters, "mu_time_to_target_s": mu_wall,
+                  "dna_ms_per_iter": ms, "dna_iters_to_target": k_hit,
+                  "dna_time_to_target_s": k_hit * ms / 1e3 if k_hit is not None else None,
+                  "kl_at_stop": float(kls[k_hit] if k_hit is not None else kls[-1])}
+        if k_hit:
+            target["speedup_vs_mu"] = mu_wall / (k_hit * ms / 1e3)
+    shape = {"tdt2": "TDT2", "newsgroup": "Newsgroup"}[args.sparse]
+    out = {
+        "metric": "DNA iterations/s, sparse V", "value": args.steps / wall, "unit": "DNA iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "accumulate": "f32 sums, f64 cost and selection sums",
+        "data": "synthetic",
+        "config": {"workload": f"sparse term-document counts shaped like {shape} ({N} x {T}, "
+                               f"{sv.nnz / (N * T) * 100:.2f}% nonzeros, Zipf row lengths), R={R}",
+                   "N": N, "T": T, "R": R, "nnz": sv.nnz, "parallelism": "single GPU"},
+        "roofline": roofline, "kernels": kernels, "time_to_target": target,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.sparse:
+        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        sparse_main(args)
+        return
     if args.traffic_tag is None:
         args.traffic_tag = workload_tag(args.config, args.gemm)
     if args.traffic_summary:
