@@ -144,23 +144,31 @@ __global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict_
   const int32_t* start = SIDE == 0 ? v.segc_start : v.segr_start;
   int64_t i0 = start[sg], i1 = start[sg + 1];
   clamp_range(i0, i1, v.nnz);
+  const int cnt = (int)std::min<int64_t>(i1 - i0, SP_SEG);
   const int64_t nF = SIDE == 0 ? N : T;
+  // lane l loads entry i0 + l of the segment (its factor row, q, q-bar, v) at
+  // once; the loop then broadcasts one entry at a time from its lane
+  int rowl = 0;
+  float ql = 0.f, qbl = 0.f;
+  double vl = 0.0;
+  if (lane < cnt) {
+    const int64_t i = i0 + lane;
+    const int64_t p = SIDE == 0 ? clampi(v.csc_pos[i], v.nnz) : i;
+    rowl = (int)clampi(SIDE == 0 ? v.csc_row[i] : v.col_idx[i], nF);
+    ql = q[p];
+    if (!MU) {
+      qbl = qb[p];
+      vl = (double)v.val[p];
+    }
+  }
   float u[KR], uc[KR], fs[KR], y[KR];
 #pragma unroll
   for (int k = 0; k < KR; ++k) u[k] = uc[k] = fs[k] = y[k] = 0.f;
-  double vs = 0.0;
-#pragma unroll 4
-  for (int64_t i = i0; i < i1; ++i) {
-    int64_t p, row;
-    if (SIDE == 0) {
-      p = clampi(v.csc_pos[i], v.nnz);
-      row = clampi(v.csc_row[i], nF);
-    } else {
-      p = i;
-      row = clampi(v.col_idx[i], nF);
-    }
-    const float qq = q[p], qbb = MU ? 0.f : qb[p];
-    if (!MU) vs += (double)v.val[p];
+#pragma unroll 8
+  for (int j = 0; j < cnt; ++j) {
+    const int64_t row = __builtin_amdgcn_readlane(rowl, j);
+    const float qq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, ql), j));
+    const float qbb = MU ? 0.f : __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qbl), j));
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
       const int64_t r = lane + 64 * k;
@@ -186,7 +194,10 @@ __global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict_
       }
     }
   }
-  if (!MU && lane == 0) vseg[sg] = vs;
+  if (!MU) {
+    const double vs = wave_sum(vl);
+    if (lane == 0) vseg[sg] = vs;
+  }
 }
 
 // Per column t (SIDE 0) / row n (SIDE 1): the segment partials in order, written
@@ -290,15 +301,19 @@ __global__ __launch_bounds__(256) void k_sp_cost(SpV v, const float* __restrict_
   const int64_t i = i0 + lane;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   int fl = 0;
+  // every entry of a segment lies in one column (SIDE 0) / row (SIDE 1): that
+  // index is uniform, so its candidate rows are read once for the wave
+  const int64_t own = i0 < i1 ? (SIDE == 0 ? v.csc_col[i0] : v.row_of[i0]) : 0;
+  const int64_t fixed = clampi(__builtin_amdgcn_readfirstlane((int)own), SIDE == 0 ? T : N);
   if (i < i1) {
     int64_t p, n, t;
     if (SIDE == 0) {
       p = clampi(v.csc_pos[i], v.nnz);
       n = clampi(v.csc_row[i], N);
-      t = clampi(v.csc_col[i], T);
+      t = fixed;
     } else {
       p = i;
-      n = clampi(v.row_of[i], N);
+      n = fixed;
       t = clampi(v.col_idx[i], T);
     }
     const float* f = SIDE == 0 ? F + n * R : F + t * R;
