@@ -145,6 +145,8 @@ def parse():
     ap.add_argument("--sparse", default=None, choices=["tdt2", "newsgroup"],
                     help="sparse-V workload shaped like a Sec. 4.2 matrix instead of a dense config")
     ap.add_argument("--rank", type=int, default=40, help="R of the sparse workload")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="per-iteration MU / MU+cost / DNA times at the paper's dense shapes (Table 1)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -292,8 +294,7 @@ def sparse_main(args):
         dna.normalize(0, Wm, Hm)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        for _ in range(args.mu_iters):
-            dna.sparse_mu_iteration(sv, Wm, Hm)
+        dna.sparse_mu_iterate(sv, Wm, Hm, args.mu_iters)
         torch.cuda.synchronize()
         mu_wall = time.perf_counter() - tm
         kl_target = dna.sparse_kl_cost(sv, Wm, Hm).item()
@@ -322,8 +323,64 @@ def sparse_main(args):
     print(json.dumps(out))
 
 
+def paper_sweep(args):
+    """Table 1 of the paper at its dense shapes (ORL 4096 x 165, PIE 1024 x 11554;
+    R = 10, 20, 40, 80) with synthetic data of those shapes: ms per iteration of
+    MU without cost, MU with cost and DNA, and the DNA iterations needed to reach
+    the KL of 500 MU iterations (the paper's Fig. 1 comparison)."""
+    import torch
+    from paper_1301_3389_amd import dna, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    def per_iter(step, W, H, k):
+        step(W, H, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(W, H, k)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / k
+
+    rows = []
+    for name in ("orl", "pie"):
+        for R in (10, 20, 40, 80):
+            w = synth.paper_dense(name, R)
+            V = torch.from_numpy(w.V).to(dev)
+            W0, H0 = torch.from_numpy(w.W).to(dev), torch.from_numpy(w.H).to(dev)
+            W, H = W0.clone(), H0.clone()
+            dna.normalize(0, W, H)
+            k = args.steps
+
+            def mu(Wx, Hx, n, cost):
+                dna.mu_iterate(V, Wx, Hx, n, with_cost=cost)
+            mu_ms = per_iter(lambda a, b, n: mu(a, b, n, False), W.clone(), H.clone(), k)
+            muc_ms = per_iter(lambda a, b, n: mu(a, b, n, True), W.clone(), H.clone(), k)
+            dna_ms = per_iter(lambda a, b, n: dna.iterate(V, a, b, n), W.clone(), H.clone(), k)
+            Wm, Hm = W.clone(), H.clone()
+            mu(Wm, Hm, 500, False)
+            target = dna.kl_cost(V, Wm, Hm).item()
+            Wd, Hd = W0.clone(), H0.clone()
+            kls = dna.fit(V, Wd, Hd, 500, record_kl=True).cpu().numpy()
+            hit = [i for i, x in enumerate(kls) if x <= target]
+            rows.append({"dataset": name, "N": w.V.shape[0], "T": w.V.shape[1], "R": R,
+                         "mu_ms": mu_ms, "mu_cost_ms": muc_ms, "dna_ms": dna_ms,
+                         "dna_over_mu_cost": dna_ms / muc_ms, "mu_cost_over_mu": muc_ms / mu_ms,
+                         "dna_iters_to_mu500_kl": hit[0] if hit else None})
+    out = {"metric": "ms per iteration at the paper's dense shapes (Table 1)", "unit": "ms",
+           "n_gpus": 1, "steps": args.steps, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "ORL-shaped 4096 x 165 and PIE-shaped 1024 x 11554 Poisson counts of a "
+                                  "Gamma(0.5) product at mean 60, R = 10, 20, 40, 80",
+                      "parallelism": "single GPU"},
+           "sweep": rows}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.paper_sweep:
+        paper_sweep(args)
+        return
     if args.sparse:
         if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
@@ -411,8 +468,7 @@ def main():
         dna.normalize(0, Wm, Hm)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        for _ in range(args.mu_iters):
-            dna.mu_iteration(V, Wm, Hm, with_cost=False)
+        dna.mu_iterate(V, Wm, Hm, args.mu_iters, with_cost=False)
         torch.cuda.synchronize()
         mu_wall = time.perf_counter() - tm
         kl_target = dna.kl_cost(V, Wm, Hm).item()
@@ -421,8 +477,7 @@ def main():
         nc = min(100, args.mu_iters)
         torch.cuda.synchronize()
         tc = time.perf_counter()
-        for _ in range(nc):
-            dna.mu_iteration(V, Wc, Hc, with_cost=True)
+        dna.mu_iterate(V, Wc, Hc, nc, with_cost=True)
         torch.cuda.synchronize()
         mu_cost_ms = 1e3 * (time.perf_counter() - tc) / nc
         target = {"target_kl": kl_target, "mu_iters": args.mu_iters,

@@ -203,6 +203,12 @@ dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float
                                 int64_t N, int64_t T, int64_t R, const dna_opts* opts,
                                 void* ws, size_t ws_bytes, void* stream);
 
+/* `iters` MU iterations with a sparse V in place (the steps of mu_iterate).
+ * iters < 0: DNA_EINVAL. */
+dna_status dna_sparse_mu_iterate(const dna_sparse_v* V, float* W, float* H,
+                                 int64_t N, int64_t T, int64_t R, int iters,
+                                 const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
 /* `iters` full iterations (dna_sparse_update_H, dna_normalize(1),
  * dna_sparse_update_W, dna_normalize(0)) in place.  iters < 0: DNA_EINVAL. */
 dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H,
@@ -218,6 +224,15 @@ dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H,
 dna_status mu_update(int side, const float* V, float* W, float* H,
                      int64_t N, int64_t T, int64_t R, int with_cost, double* d_out,
                      const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* `iters` MU iterations in place: mu_update(0), dna_normalize(1),
+ * mu_update(1), dna_normalize(0) per iteration (the MU-labelled steps of
+ * Algorithm 1).  with_cost != 0 also forms each half-step's per-column / per-row
+ * cost of its input state ("MU with cost", Table 1) in the workspace; it is not
+ * returned.  iters < 0: DNA_EINVAL. */
+dna_status mu_iterate(const float* V, float* W, float* H,
+                      int64_t N, int64_t T, int64_t R, int iters, int with_cost,
+                      const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* Eq. (1): *out = sum_{v>0} v log(v/z) - sum v + sum z with Z = W H, written
  * to one device double. */

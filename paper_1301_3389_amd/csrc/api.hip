@@ -488,13 +488,10 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
   return epilogue(c);
 }
 
-dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                     int with_cost, double* d_out, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
-  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
-  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
-  if (with_cost && !d_out) return fail(DNA_EINVAL, "with_cost requires d_out");
-  Common c;
-  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+// One MU half-step (eq. 11) on the prologue's state; with_cost writes the input
+// state's per-column (row) cost to d_out.
+static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                         int with_cost, double* d_out, const Common& c, void* ws) {
   const Layout& L = c.L;
   float* Q = at<float>(ws, L.q);
   float* pu = at<float>(ws, L.pu);
@@ -516,6 +513,39 @@ dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, in
     DNA_HIP(launch_ratio(with_cost ? RM_MU_W_COST : RM_MU_W, ra, c.s), "ratio_mu_W");
     DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_W");
     DNA_HIP(launch_mu_W(W, pu, L.sw.splits, c32, N, R, cpart, L.rt_n, with_cost ? d_out : nullptr, c.s), "mu_W");
+  }
+  return DNA_OK;
+}
+
+dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                     int with_cost, double* d_out, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  if (with_cost && !d_out) return fail(DNA_EINVAL, "with_cost requires d_out");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  DNA_TRY(run_mu(side, V, W, H, N, T, R, with_cost, d_out, c, ws));
+  return epilogue(c);
+}
+
+dna_status mu_iterate(const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R, int iters,
+                      int with_cost, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
+  if (iters < 0) return fail(DNA_EINVAL, "iters must be >= 0");
+  Common c;
+  DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  double* dcost = at<double>(ws, c.L.vpart);        // the with-cost outputs, not returned
+  double* sp = at<double>(ws, c.L.sump);
+  for (int it = 0; it < iters; ++it) {
+    DNA_TRY(run_mu(0, V, W, H, N, T, R, with_cost, dcost, c, ws));
+    SumJob job;
+    DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");      // step 16
+    job.check = c.chk;
+    DNA_HIP(launch_scale(1, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+    DNA_TRY(run_mu(1, V, W, H, N, T, R, with_cost, dcost, c, ws));
+    DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");      // step 29
+    job.check = c.chk;
+    DNA_HIP(launch_scale(0, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
   }
   return epilogue(c);
 }
@@ -865,12 +895,9 @@ dna_status dna_sparse_kl_cost(const dna_sparse_v* V, const float* W, const float
   return sp_epilogue(c);
 }
 
-dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T,
-                                int64_t R, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
-  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
-  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
-  SpCommon c;
-  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+// One sparse MU half-step on the prologue's state.
+static dna_status sp_run_mu(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                            const SpCommon& c, void* ws) {
   const SpLayout& L = c.L;
   const SpV v = sp_view(V);
   float* Ht = at<float>(ws, L.ht);
@@ -888,6 +915,37 @@ dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float
                          nullptr, pu, nullptr, nullptr, nullptr, c.s), "sp_grad_mu");
   if (side == 0) DNA_HIP(launch_mu_H(H, pu, 1, c32, T, R, nullptr, 1, nullptr, c.s), "mu_H");
   else DNA_HIP(launch_mu_W(W, pu, 1, c32, N, R, nullptr, 1, nullptr, c.s), "mu_W");
+  return DNA_OK;
+}
+
+dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T,
+                                int64_t R, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
+  if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
+  SpCommon c;
+  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  DNA_TRY(sp_run_mu(side, V, W, H, N, T, R, c, ws));
+  return sp_epilogue(c);
+}
+
+dna_status dna_sparse_mu_iterate(const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
+                                 int iters, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  if (!W || !H) return fail(DNA_EINVAL, "W or H is NULL");
+  if (iters < 0) return fail(DNA_EINVAL, "iters must be >= 0");
+  SpCommon c;
+  DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  double* sp = at<double>(ws, c.L.sump);
+  for (int it = 0; it < iters; ++it) {
+    DNA_TRY(sp_run_mu(0, V, W, H, N, T, R, c, ws));
+    SumJob job;
+    DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");           // step 16
+    job.check = c.chk;
+    DNA_HIP(launch_scale(1, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+    DNA_TRY(sp_run_mu(1, V, W, H, N, T, R, c, ws));
+    DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");           // step 29
+    job.check = c.chk;
+    DNA_HIP(launch_scale(0, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+  }
   return sp_epilogue(c);
 }
 

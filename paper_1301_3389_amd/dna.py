@@ -70,7 +70,9 @@ _lib_sp_H = _decl("dna_sparse_update_H", _int, _SP, _p, _p, _i64, _i64, _i64, _O
 _lib_sp_W = _decl("dna_sparse_update_W", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_sp_kl = _decl("dna_sparse_kl_cost", _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
 _lib_sp_mu = _decl("dna_sparse_mu_update", _int, _int, _SP, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p)
+_lib_sp_mu_it = _decl("dna_sparse_mu_iterate", _int, _SP, _p, _p, _i64, _i64, _i64, _int, _OP, _p, _sz, _p)
 _lib_sp_it = _decl("dna_sparse_iterate", _int, _SP, _p, _p, _i64, _i64, _i64, _int, _OP, _p, _sz, _p)
+_lib_mu_it = _decl("mu_iterate", _int, _p, _p, _p, _i64, _i64, _i64, _int, _int, _OP, _p, _sz, _p)
 _lib_mu = _decl("mu_update", _int, _int, _p, _p, _p, _i64, _i64, _i64, _int, _p, _OP, _p, _sz, _p)
 _lib_kl = _decl("kl_cost", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p)
 _lib_gh = _decl("dna_gradient_hessian", _int, _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _p, _p, _sz, _p)
@@ -90,7 +92,7 @@ _lib_build_info = _decl("dna_build_info", ctypes.c_char_p)
 EXPORTED = [
     "dna_default_opts", "dna_workspace_bytes", "dna_normalize", "dna_update_H", "dna_update_W",
     "dna_iterate", "dna_sparse_workspace_bytes", "dna_sparse_update_H", "dna_sparse_update_W",
-    "dna_sparse_kl_cost", "dna_sparse_mu_update", "dna_sparse_iterate", "mu_update", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
+    "dna_sparse_kl_cost", "dna_sparse_mu_update", "dna_sparse_mu_iterate", "dna_sparse_iterate", "mu_update", "mu_iterate", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
     "dna_unrolled_workspace_bytes", "dna_unrolled_H_fwd", "dna_unrolled_H_bwd",
     "dna_status_string", "dna_last_error", "dna_profile_enable", "dna_profile_reset",
     "dna_profile_read", "dna_build_info",
@@ -506,11 +508,21 @@ def sparse_mu_update(side, V, W, H, **kw):
 
 
 def sparse_mu_iteration(V, W, H, **kw):
-    """One MU iteration with a sparse V (H step, step 16, W step, step 29)."""
+    """One MU iteration with a sparse V (H step, step 16, W step, step 29) as
+    separate calls; sparse_mu_iterate runs the same in one call."""
     sparse_mu_update(0, V, W, H, **kw)
     normalize(1, W, H, **kw)
     sparse_mu_update(1, V, W, H, **kw)
     normalize(0, W, H, **kw)
+
+
+def sparse_mu_iterate(V, W, H, iters, **kw):
+    """``iters`` MU iterations with a sparse V in place, one native call."""
+    N, T, R = _sp_dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = sparse_workspace(V, R, o)
+    _check(_lib_sp_mu_it(ctypes.byref(V.c), _ptr(W), _ptr(H), N, T, R, int(iters), ctypes.byref(o), _ptr(ws),
+                         ws.numel(), _stream()))
 
 
 def sparse_iterate(V, W, H, iters, **kw):
@@ -564,6 +576,15 @@ def dna_iteration(V, W, H, **kw):
     normalize(0, W, H, **kw)
 
 
+def mu_iterate(V, W, H, iters, with_cost=False, **kw):
+    """``iters`` MU iterations in place, one native call (mu_iteration's steps)."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    ws, nb = workspace(N, T, R, o)
+    _check(_lib_mu_it(_ptr(V), _ptr(W), _ptr(H), N, T, R, int(iters), 1 if with_cost else 0, ctypes.byref(o),
+                      _ptr(ws), ws.numel(), _stream()))
+
+
 def mu_iteration(V, W, H, with_cost=False, **kw):
     """One MU iteration (MU-labelled steps of Algorithm 1)."""
     mu_update(0, V, W, H, with_cost=with_cost, **kw)
@@ -583,11 +604,14 @@ def fit(V, W, H, iters, method="dna", record_kl=False, **kw):
     if method == "dna" and not record_kl:
         iterate(V, W, H, iters, **kw)
         return None
+    if method != "dna" and not record_kl:
+        mu_iterate(V, W, H, iters, **kw)
+        return None
     for k in range(iters):
         if method == "dna":
             iterate(V, W, H, 1, **kw)
         else:
-            mu_iteration(V, W, H, **kw)
+            mu_iterate(V, W, H, 1, **kw)
         if record_kl:
             kl_cost(V, W, H, out=kls[k + 1:k + 2], **kw)
     return kls

@@ -235,6 +235,21 @@ def sparse_problem(N, T, R, density, seed, zipf=1.0):
     return Workload(V, W, H, None, None, {"kind": "sparse", "seed": seed, "density": density, "zipf": zipf})
 
 
+# Shapes of the paper's dense image matrices (Sec. 4.1): ORL 400 faces of 64 x 64
+# pixels as a 4096 x 165 matrix (the shape the paper states), CMU PIE 11554
+# faces of 32 x 32 pixels, 1024 x 11554.
+PAPER_DENSE_SHAPES = {"orl": (4096, 165), "pie": (1024, 11554)}
+
+
+def paper_dense(name, R):
+    """Stand-in for a Sec. 4.1 image matrix at rank R: V = Poisson counts of a
+    Gamma(0.5) product scaled to mean 60 (grey levels, few zeros), uniform
+    initial factors (random_problem's recipe at the paper's shape)."""
+    N, T = PAPER_DENSE_SHAPES[name]
+    seed = DATA_SEED_BASE + 20 + sorted(PAPER_DENSE_SHAPES).index(name) * 10 + R
+    return random_problem(N, T, R, seed, mean=60.0)
+
+
 # Shapes of the paper's sparse matrices (Sec. 4.2): TDT2 36771 terms x 10212
 # documents at 0.35% nonzeros, Newsgroup 61188 x 18774 at 0.2%.  The rank is not
 # stated there; R = 40 is one of the ranks of its dense experiments.

@@ -93,6 +93,10 @@ def test_invalid_arguments_rejected_before_launch():
     assert It(fake, fake, fake, 8, 8, 2, -1, ctypes.byref(o), ws, 1 << 30, null) == 1
     assert It(fake, fake, fake, 8, 8, 2, 3, ctypes.byref(o), ws, 16, null) == 2
     assert It(fake, fake, fake, 8, 8, 2, 0, ctypes.byref(o), ws, 1 << 30, null) == 0
+    Mi = dna._lib_mu_it
+    assert Mi(fake, null, fake, 8, 8, 2, 3, 0, ctypes.byref(o), ws, 1 << 30, null) == 1
+    assert Mi(fake, fake, fake, 8, 8, 2, -2, 0, ctypes.byref(o), ws, 1 << 30, null) == 1
+    assert Mi(fake, fake, fake, 8, 8, 2, 0, 1, ctypes.byref(o), ws, 1 << 30, null) == 0
 
 
 def test_build_info_names_target():

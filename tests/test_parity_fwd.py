@@ -267,6 +267,24 @@ def test_iterate_matches_separate_calls(dna, shape):
     assert torch.equal(Wz, Wa) and torch.equal(Hz, Ha)
 
 
+@pytest.mark.parametrize("with_cost", [False, True])
+def test_mu_iterate_matches_separate_calls(dna, with_cost):
+    """mu_iterate runs the same kernels as mu_update / dna_normalize in the same
+    order: the state after three iterations is bit-identical."""
+    V, W, H = _problem(*SHAPES[0])
+    Vg = gpu(V)
+    Wa, Ha = gpu(W), gpu(H)
+    dna.normalize(0, Wa, Ha)
+    Wb, Hb = Wa.clone(), Ha.clone()
+    dna.mu_iterate(Vg, Wa, Ha, 3, with_cost=with_cost)
+    for _ in range(3):
+        dna.mu_update(0, Vg, Wb, Hb, with_cost=with_cost)
+        dna.normalize(1, Wb, Hb)
+        dna.mu_update(1, Vg, Wb, Hb, with_cost=with_cost)
+        dna.normalize(0, Wb, Hb)
+    assert torch.equal(Wa, Wb) and torch.equal(Ha, Hb)
+
+
 def _trajectory(dna, V, W, H, iters, method):
     Vg, Wg, Hg = gpu(V), gpu(W), gpu(H)
     kls = host(dna.fit(Vg, Wg, Hg, iters, method=method, record_kl=True))

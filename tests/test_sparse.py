@@ -127,6 +127,19 @@ def test_sparse_mu_update(dna, shape, side):
 
 
 @pytest.mark.gpu
+def test_sparse_mu_iterate_matches_separate_calls(dna):
+    V, W, H = _problem(*SHAPES[0])
+    sv = dna.SparseV.from_dense(V)
+    Wa, Ha = gpu(W), gpu(H)
+    dna.normalize(0, Wa, Ha)
+    Wb, Hb = Wa.clone(), Ha.clone()
+    dna.sparse_mu_iterate(sv, Wa, Ha, 3)
+    for _ in range(3):
+        dna.sparse_mu_iteration(sv, Wb, Hb)
+    assert torch.equal(Wa, Wb) and torch.equal(Ha, Hb)
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("shape", SHAPES[:4])
 def test_sparse_kl_cost(dna, shape):
     V, W, H = _problem(*shape)
