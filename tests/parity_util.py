@@ -5,8 +5,9 @@ import os
 import numpy as np
 import torch
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LOG_DIR = os.path.join(ROOT, "gpurun_out")
+# Measured errors of each parity test are appended as JSON lines to the file
+# named by DNA_PARITY_LOG (nothing is logged when it is unset).
+LOG_PATH = os.environ.get("DNA_PARITY_LOG")
 
 # Per-step tolerance in FP32 (from identical states): max-norm per column (row)
 # relative to the oracle's max-norm of that column (row).
@@ -63,8 +64,10 @@ def rel_cols(got, ref, axis=0):
 
 
 def log_result(name, payload):
-    os.makedirs(LOG_DIR, exist_ok=True)
-    with open(os.path.join(LOG_DIR, "parity_log.jsonl"), "a") as f:
+    if not LOG_PATH:
+        return
+    os.makedirs(os.path.dirname(os.path.abspath(LOG_PATH)), exist_ok=True)
+    with open(LOG_PATH, "a") as f:
         f.write(json.dumps({"test": name, **payload}) + "\n")
 
 
