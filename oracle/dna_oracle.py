@@ -8,7 +8,9 @@ and this module imports nothing from the product package.
 Everything is NumPy float64.  Inputs may be float32 arrays: they are upcast, so
 an oracle run "from the same state" as the GPU starts from exactly the GPU's
 numbers.  Notation follows the paper: V (N x T) data, W (N x R), H (R x T),
-Z = W H, eps the gain floor, alpha the step ceiling, rho = lambda = 0 (Sec. 4).
+Z = W H, eps the gain floor, alpha the step ceiling, rho and lambda the
+regularisation weights of eq. (2) (``rho``, ``lam``; 0 in the experiments of
+Sec. 4, and 0 by default here).
 
 Readings of the paper that this oracle fixes (each is stated where it is used):
 
@@ -21,6 +23,25 @@ Readings of the paper that this oracle fixes (each is stated where it is used):
 * Zeros of V contribute nothing to Q, Q-bar or the costs (end of Sec. 3).
 * Selection: Newton iff d_DNA < d_MU (step 15: ties go to MU).
 * Renormalisation eq. (10) with a zero denominator leaves the column at 0.
+* Regularisation (eq. 2-5): lambda enters the H step as printed in eq. (7),
+  (10), (11) and (14), i.e. every division by c_r becomes one by c_r + lambda;
+  the W step is its mirror with g_r + rho.  The selection stays on the
+  log-ratio sums of steps 9/14: both candidates satisfy eq. (9), so the rest of
+  the regularised per-column cost, sum_r (c_r + lambda) x_r - sum_n v_n, is the
+  same (zero) for both.
+* Normalisations under regularisation (steps 1, 16, 29).  The printed steps
+  (divide by sum + lambda, or + rho) do not give c_r + lambda = 1, which the
+  printed step 5 (A = W^t Q - 1) would need, and they change the penalty
+  rho sum w + lambda sum h, which is not invariant under moving scale between a
+  W column and an H row.  This oracle reads them as: with rho = lambda = 0, the
+  paper's unit column sums of W (steps 1, 29) and unit row sums of H (step 16);
+  with rho > 0 and lambda > 0, every normalisation applies the scale
+  s_r = sqrt(lambda G_r / (rho C_r)) (C = W^t 1, G = H 1) to W column r and
+  1/s_r to H row r, the scale that minimises the penalty with W H fixed (after
+  it rho C_r = lambda G_r), so no normalisation raises eq. (2); with one weight
+  zero, eq. (2) has no minimiser unless the unpenalised factor's scale is fixed,
+  so every normalisation sets that factor to unit sums (W columns when only
+  lambda > 0, H rows when only rho > 0).
 * ``value_floor`` (default 0: the paper's method on the positive reals): when
   positive, both candidates are raised to at least this value after the
   renormalisation.  In exact arithmetic no update maps a positive entry to 0
@@ -67,6 +88,12 @@ def kl_divergence(V, Z):
 def kl_cost(V, W, H):
     """Eq. (1) at Z = W H."""
     return kl_divergence(V, _f64(W) @ _f64(H))
+
+
+def objective(V, W, H, rho=0.0, lam=0.0):
+    """Eq. (2): d_KL(V, W H) + rho sum w + lambda sum h."""
+    W, H = _f64(W), _f64(H)
+    return kl_cost(V, W, H) + rho * float(W.sum()) + lam * float(H.sum())
 
 
 def partial_cost(V, Z, axis=0):
@@ -126,8 +153,9 @@ def newton_candidate(X, A, B, eps=EPS, alpha=ALPHA):
 
 
 def renormalize(X, c, s, axis=0):
-    """Eq. (10) at lambda = 0: scale each column (axis=0) or row (axis=1) of X
-    so that sum_r c_r x_r equals s (the data sum of that column / row).  A zero
+    """Eq. (10): scale each column (axis=0) or row (axis=1) of X so that
+    sum_r c_r x_r equals s (the data sum of that column / row); the caller
+    passes c_r = (W^t 1)_r + lambda (H step) or (H 1)_r + rho (W step).  A zero
     denominator leaves the column (row) unchanged (it is all zero)."""
     X = _f64(X)
     if axis == 0:
@@ -167,19 +195,20 @@ def _select(d_mu, d_nr, X_mu, X_nr, axis):
     return choose, X, d_sel, margin
 
 
-def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0):
+def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, lam=0.0):
     """One DNA update of H with W fixed: Algorithm 1 steps 4-15 (Sec. 2-3).
 
-    c = W^t 1; Z = W H; Q, Q-bar (steps 2-3, 10); A = W^t Q / c - 1 (eq. 7,
-    step 5); B = (W*W)^t Q-bar / c (eq. 14, step 10); MU candidate H(1+A)
-    (eq. 11, step 6); Newton candidate (eq. 15/17, step 11) renormalised by
-    eq. (10) with s = 1^t V; per-column costs (steps 7-9, 12-14); selection
-    (step 15).
+    c = W^t 1 + lambda; Z = W H; Q, Q-bar (steps 2-3, 10); A = W^t Q / c - 1
+    (eq. 7, step 5); B = (W*W)^t Q-bar / c (eq. 14, step 10); MU candidate
+    H(1+A) (eq. 11, step 6); Newton candidate (eq. 15/17, step 11)
+    renormalised by eq. (10) with s = 1^t V; per-column costs (steps 7-9,
+    12-14); selection (step 15).  ``lam`` is the H weight of eq. (2).
     """
     V, W, H = _f64(V), _f64(W), _f64(H)
     c = W.sum(axis=0)
     if np.any(c <= 0):
         raise DomainError("a column of W sums to zero")
+    c = c + lam
     Q, Qb = ratios(V, W @ H)
     A = (W.T @ Q) / c[:, None] - 1.0
     B = ((W * W).T @ Qb) / c[:, None]
@@ -192,19 +221,21 @@ def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0):
     return StepResult(X, choose, d_sel, d_mu, d_nr, margin, A, B, H_mu, H_nr)
 
 
-def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0):
+def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0):
     """One DNA update of W with H fixed: Algorithm 1 steps 17-28.
 
-    The mirror of ``h_step`` written out directly: g = H 1; A = Q H^t / g - 1
-    (step 18); B = Q-bar (H*H)^t / g (step 23); MU candidate W(1+A) (step 19);
-    Newton candidate (step 24 read as eq. 15/17) with each row renormalised so
-    that sum_r g_r w_nr = (V 1)_n; per-row costs (steps 20-22, 25-27);
-    selection per row (step 28).
+    The mirror of ``h_step`` written out directly: g = H 1 + rho;
+    A = Q H^t / g - 1 (step 18); B = Q-bar (H*H)^t / g (step 23); MU candidate
+    W(1+A) (step 19); Newton candidate (step 24 read as eq. 15/17) with each
+    row renormalised so that sum_r g_r w_nr = (V 1)_n; per-row costs
+    (steps 20-22, 25-27); selection per row (step 28).  ``rho`` is the W weight
+    of eq. (2).
     """
     V, W, H = _f64(V), _f64(W), _f64(H)
     g = H.sum(axis=1)
     if np.any(g <= 0):
         raise DomainError("a row of H sums to zero")
+    g = g + rho
     Q, Qb = ratios(V, W @ H)
     A = (Q @ H.T) / g[None, :] - 1.0
     B = (Qb @ (H * H).T) / g[None, :]
@@ -217,26 +248,28 @@ def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0):
     return StepResult(X, choose, d_sel, d_mu, d_nr, margin, A, B, W_mu, W_nr)
 
 
-def mu_h_step(V, W, H, value_floor=0.0):
-    """Plain MU update of H (eq. 11 at lambda = 0; Lee-Seung):
-    H <- H * (W^t Q) / (W^t 1).  Also returns the per-column partial cost
-    sum_{v>0} v log(v/z) of the INPUT state (the cost that "MU with cost"
+def mu_h_step(V, W, H, value_floor=0.0, lam=0.0):
+    """Plain MU update of H (eq. 11; Lee-Seung at lambda = 0):
+    H <- H * (W^t Q) / (W^t 1 + lambda).  Also returns the per-column partial
+    cost sum_{v>0} v log(v/z) of the INPUT state (the cost that "MU with cost"
     monitors, computed from the same Z)."""
     V, W, H = _f64(V), _f64(W), _f64(H)
     c = W.sum(axis=0)
     if np.any(c <= 0):
         raise DomainError("a column of W sums to zero")
+    c = c + lam
     Z = W @ H
     Q, _ = ratios(V, Z)
     return np.maximum(H * (W.T @ Q) / c[:, None], value_floor), partial_cost(V, Z, axis=0)
 
 
-def mu_w_step(V, W, H, value_floor=0.0):
-    """Plain MU update of W: W <- W * (Q H^t) / (H 1); per-row input cost."""
+def mu_w_step(V, W, H, value_floor=0.0, rho=0.0):
+    """Plain MU update of W: W <- W * (Q H^t) / (H 1 + rho); per-row input cost."""
     V, W, H = _f64(V), _f64(W), _f64(H)
     g = H.sum(axis=1)
     if np.any(g <= 0):
         raise DomainError("a row of H sums to zero")
+    g = g + rho
     Z = W @ H
     Q, _ = ratios(V, Z)
     return np.maximum(W * (Q @ H.T) / g[None, :], value_floor), partial_cost(V, Z, axis=1)
@@ -266,6 +299,37 @@ def normalize_h_rows(W, H):
     return W * g[None, :], H / g[:, None]
 
 
+def normalize(W, H, side, rho=0.0, lam=0.0):
+    """Steps 1 and 29 (side 0) and step 16 (side 1) under the regularisation
+    weights of eq. (2), in the reading stated in the module header:
+
+    rho = lambda = 0  side 0: unit W column sums; side 1: unit H row sums
+    rho > 0, lambda > 0  either side: W column r times s_r, H row r divided by
+                      s_r, s_r = sqrt(lambda G_r / (rho C_r)) (C = W^t 1,
+                      G = H 1), the scale minimising rho C_r s + lambda G_r / s
+    lambda > 0 only   either side: unit W column sums
+    rho > 0 only      either side: unit H row sums
+
+    W H is unchanged in every case."""
+    if rho < 0 or lam < 0:
+        raise ValueError("rho and lambda must be >= 0")
+    if rho > 0 and lam > 0:
+        W, H = _f64(W), _f64(H)
+        C, G = W.sum(axis=0), H.sum(axis=1)
+        if np.any(C <= 0) or np.any(G <= 0):
+            raise DomainError("a column of W or a row of H sums to zero")
+        s = np.sqrt(lam * G / (rho * C))
+        return W * s[None, :], H / s[:, None]
+    if lam > 0:
+        side = 0
+    elif rho > 0:
+        side = 1
+    return normalize_w_columns(W, H) if side == 0 else normalize_h_rows(W, H)
+
+
+_normalize = normalize      # fit_mu's ``normalize`` argument shadows the name
+
+
 @dataclasses.dataclass
 class FitResult:
     W: np.ndarray
@@ -273,47 +337,52 @@ class FitResult:
     kl: list                  # eq. (1) after every full iteration (index 0 = start)
     newton_frac_h: list       # fraction of columns taking Newton, per iteration
     newton_frac_w: list       # fraction of rows taking Newton, per iteration
+    obj: list = dataclasses.field(default_factory=list)   # eq. (2), same points as kl
 
 
-def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA, value_floor=0.0):
+def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0, lam=0.0):
     """Algorithm 1: step 1, then per iteration H half-step (4-15), step 16,
     W half-step (17-28), step 29.  Z and Q are recomputed from W H at the start
     of each half-step, which equals carrying them because the normalisations
     leave W H unchanged."""
     V = _f64(V)
-    W, H = normalize_w_columns(W, H)
+    W, H = normalize(W, H, 0, rho, lam)
     kl = [kl_cost(V, W, H)]
+    obj = [objective(V, W, H, rho, lam)]
     fh, fw = [], []
     for _ in range(iters):
-        r = h_step(V, W, H, eps, alpha, value_floor)
+        r = h_step(V, W, H, eps, alpha, value_floor, lam=lam)
         H = r.X
         fh.append(float(r.chose_newton.mean()))
-        W, H = normalize_h_rows(W, H)
-        r = w_step(V, W, H, eps, alpha, value_floor)
+        W, H = normalize(W, H, 1, rho, lam)
+        r = w_step(V, W, H, eps, alpha, value_floor, rho=rho)
         W = r.X
         fw.append(float(r.chose_newton.mean()))
-        W, H = normalize_w_columns(W, H)
+        W, H = normalize(W, H, 0, rho, lam)
         kl.append(kl_cost(V, W, H))
-    return FitResult(W, H, kl, fh, fw)
+        obj.append(objective(V, W, H, rho, lam))
+    return FitResult(W, H, kl, fh, fw, obj)
 
 
-def fit_mu(V, W, H, iters, normalize=True, value_floor=0.0):
+def fit_mu(V, W, H, iters, normalize=True, value_floor=0.0, rho=0.0, lam=0.0):
     """MU reference: Algorithm 1 with only the MU-labelled steps.  With
     ``normalize=False`` it is textbook Lee-Seung MU without steps 1/16/29."""
     V = _f64(V)
     W, H = _f64(W), _f64(H)
     if normalize:
-        W, H = normalize_w_columns(W, H)
+        W, H = _normalize(W, H, 0, rho, lam)
     kl = [kl_cost(V, W, H)]
+    obj = [objective(V, W, H, rho, lam)]
     for _ in range(iters):
-        H, _ = mu_h_step(V, W, H, value_floor)
+        H, _ = mu_h_step(V, W, H, value_floor, lam=lam)
         if normalize:
-            W, H = normalize_h_rows(W, H)
-        W, _ = mu_w_step(V, W, H, value_floor)
+            W, H = _normalize(W, H, 1, rho, lam)
+        W, _ = mu_w_step(V, W, H, value_floor, rho=rho)
         if normalize:
-            W, H = normalize_w_columns(W, H)
+            W, H = _normalize(W, H, 0, rho, lam)
         kl.append(kl_cost(V, W, H))
-    return FitResult(W, H, kl, [], [])
+        obj.append(objective(V, W, H, rho, lam))
+    return FitResult(W, H, kl, [], [], obj)
 
 
 def unrolled_h(V, W, H_init, K, eps=EPS, alpha=ALPHA, value_floor=0.0):
