@@ -6,7 +6,9 @@
  *
  * Problem (Sec. 1, eq. 1): V (N x T) ~ W H with W (N x R), H (R x T), all
  * entries >= 0, cost d_KL(V, WH) = sum v log(v/z) - sum v + sum z, Z = W H.
- * Regularisation weights rho = lambda = 0 (the setting of Sec. 4).
+ * With regularisation weights rho, lambda >= 0 (dna_opts) the cost is eq. (2),
+ * d_KL(V, WH) + rho sum w + lambda sum h; rho = lambda = 0 is the setting of
+ * Sec. 4 and the default.
  *
  * Conventions shared by every entry point
  *  - Matrices are float32, row-major and contiguous: V[N][T], W[N][R],
@@ -75,9 +77,11 @@ typedef struct {
   int gemm;      /* dna_gemm_type                                                  */
   int checked;   /* 1: device-side domain checks, then a stream synchronise and a
                     read-back of the check flags (tests and debugging only)        */
+  float rho;     /* eq. (2) weight of sum w (W half-steps, normalisations); >= 0   */
+  float lambda;  /* eq. (2) weight of sum h (H half-steps, normalisations); >= 0   */
 } dna_opts;
 
-/* eps = 0.01, alpha = 4 (Sec. 4), FP32 products, unchecked. */
+/* eps = 0.01, alpha = 4 (Sec. 4), FP32 products, unchecked, rho = lambda = 0. */
 void dna_default_opts(dna_opts* opts);
 
 /* Bytes of workspace any call below needs for an N x T x R problem with these
@@ -85,18 +89,30 @@ void dna_default_opts(dna_opts* opts);
  * Returns 0 for non-positive sizes. */
 size_t dna_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* opts);
 
-/* Algorithm 1 steps 1, 16, 29 at rho = lambda = 0: rescale so W H is unchanged.
- * side 0 (steps 1, 29): divide column r of W by its sum, multiply row r of H
- *                       by the same number.
- * side 1 (step 16):     divide row r of H by its sum, multiply column r of W
- *                       by the same number.
+/* Algorithm 1 steps 1, 16, 29: rescale column r of W and row r of H by
+ * reciprocal factors, so W H is unchanged.  At rho = lambda = 0:
+ *   side 0 (steps 1, 29): divide column r of W by its sum, multiply row r of H
+ *                         by the same number.
+ *   side 1 (step 16):     divide row r of H by its sum, multiply column r of W
+ *                         by the same number.
+ * With regularisation (eq. 2; the printed steps add lambda or rho to the sums,
+ * which neither yields the unit scale the rest of the algorithm assumes nor
+ * keeps eq. 2 from rising, since the penalty depends on how scale is split
+ * between W and H):
+ *   rho > 0, lambda > 0: either side multiplies column r of W by
+ *     s_r = sqrt(lambda G_r / (rho C_r)) and divides row r of H by it
+ *     (C = W^t 1, G = H 1): the split minimising rho sum w + lambda sum h, after
+ *     which rho C_r = lambda G_r;
+ *   lambda > 0 only: either side acts as side 0 (the unpenalised W keeps unit
+ *     column sums; eq. 2 has no minimiser otherwise);
+ *   rho > 0 only: either side acts as side 1.
  * W and H are updated in place.  A zero sum leaves that column/row unchanged
  * (checked mode reports it as DNA_EDOMAIN). */
 dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
                          const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* One DNA update of H with W fixed: Algorithm 1 steps 4-15 (Sec. 2-3).
- *   c = W^t 1;  Z = W H;  Q = V/Z;  Q-bar = V/Z^2                  (steps 2-3, 10)
+ *   c = W^t 1 + lambda;  Z = W H;  Q = V/Z;  Q-bar = V/Z^2         (steps 2-3, 10)
  *   A = W^t Q / c - 1            eq. (7), step 5
  *   B = (W*W)^t Q-bar / c        eq. (14), step 10
  *   MU candidate     H (1 + A)                                      eq. (11), step 6
@@ -105,6 +121,8 @@ dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int
  *                    then each column scaled so sum_r c_r h_r = sum_n v_n  eq. (10)
  *   per column t: d_MU, d_DNA = sum_{v>0} v log(v/z) of each candidate  steps 9, 14
  *   H[:, t] <- Newton candidate iff d_DNA < d_MU, else MU            step 15
+ * Both candidates satisfy sum_r c_r h_r = sum_n v_n (eq. 9), so with lambda > 0
+ * the selection on d is also the selection on the regularised column cost.
  * H (R x T) is overwritten.  Optional outputs (NULL to skip), length T:
  *   chose_newton[t] (uint8), d_sel[t] = cost of the kept candidate,
  *   margin[t] = d_MU - d_DNA (computed directly from W (H_MU - H_DNA), so it
@@ -116,8 +134,8 @@ dna_status dna_update_H(const float* V, const float* W, float* H,
 
 /* One DNA update of W with H fixed: Algorithm 1 steps 17-28, the mirror of
  * dna_update_H on the transposed problem (Sec. 2: d(V, WH) = d(V^t, H^t W^t)).
- * g = H 1 replaces c; rows of W replace columns of H; each Newton row n is
- * scaled so that sum_r g_r w_nr = sum_t v_nt.  W (N x R) is overwritten;
+ * g = H 1 + rho replaces c; rows of W replace columns of H; each Newton row n
+ * is scaled so that sum_r g_r w_nr = sum_t v_nt.  W (N x R) is overwritten;
  * optional outputs have length N. */
 dna_status dna_update_W(const float* V, float* W, const float* H,
                         int64_t N, int64_t T, int64_t R, const dna_opts* opts,
@@ -127,7 +145,7 @@ dna_status dna_update_W(const float* V, float* W, const float* H,
 /* `iters` full iterations of Algorithm 1 in place, each: dna_update_H
  * (steps 4-15), dna_normalize(1) (step 16), dna_update_W (steps 17-28),
  * dna_normalize(0) (step 29) -- the same kernels those entry points run, in one
- * call.  Each normalisation also writes the partial sums of the factor it
+ * call, with the normalisations chosen by rho and lambda as in dna_normalize.  Each normalisation also writes the partial sums of the factor it
  * rescaled, so the half-step that follows reads c = W^t 1 (or g = H 1) from
  * them instead of summing the factor again; results therefore equal those of
  * the four separate calls up to the order of those float64 sums.  Step 1 (the
@@ -191,14 +209,15 @@ dna_status dna_sparse_update_W(const dna_sparse_v* V, float* W, const float* H,
                                double* d_sel, double* margin, void* stream);
 
 /* eq. 1 with a sparse V: sum over the nonzeros of v log(v/z) - v, plus
- * sum z = sum_r c_r (H 1)_r in closed form.  out: one device double. */
+ * sum z = sum_r c_r (H 1)_r in closed form; with rho or lambda > 0 also
+ * rho sum w + lambda sum h (eq. 2).  out: one device double. */
 dna_status dna_sparse_kl_cost(const dna_sparse_v* V, const float* W, const float* H,
                               int64_t N, int64_t T, int64_t R, const dna_opts* opts,
                               void* ws, size_t ws_bytes, double* out, void* stream);
 
 /* mu_update (eq. 11) with a sparse V, without the cost output:
- * side 0: H <- H * (W^t Q) / (W^t 1); side 1: W <- W * (Q H^t) / (H 1), Q at
- * the nonzeros only. */
+ * side 0: H <- H * (W^t Q) / (W^t 1 + lambda); side 1: W <- W * (Q H^t) /
+ * (H 1 + rho), Q at the nonzeros only. */
 dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float* H,
                                 int64_t N, int64_t T, int64_t R, const dna_opts* opts,
                                 void* ws, size_t ws_bytes, void* stream);
@@ -215,8 +234,9 @@ dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H,
                               int64_t N, int64_t T, int64_t R, int iters,
                               const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
-/* Plain multiplicative update (eq. 11 at lambda = 0; Lee-Seung):
- *   side 0: H <- H * (W^t Q) / (W^t 1)      side 1: W <- W * (Q H^t) / (H 1)
+/* Plain multiplicative update (eq. 11; Lee-Seung at rho = lambda = 0):
+ *   side 0: H <- H * (W^t Q) / (W^t 1 + lambda)
+ *   side 1: W <- W * (Q H^t) / (H 1 + rho)
  * with Q = V / (W H).  If with_cost != 0, d_out (length T for side 0, N for
  * side 1) receives sum_{v>0} v log(v/z) per column (row) of the INPUT state,
  * computed from the same Z ("MU with cost", Table 1); otherwise d_out is
@@ -235,16 +255,17 @@ dna_status mu_iterate(const float* V, float* W, float* H,
                       const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* Eq. (1): *out = sum_{v>0} v log(v/z) - sum v + sum z with Z = W H, written
- * to one device double. */
+ * to one device double; with rho or lambda > 0, eq. (2): that plus
+ * rho sum w + lambda sum h. */
 dna_status kl_cost(const float* V, const float* W, const float* H,
                    int64_t N, int64_t T, int64_t R, const dna_opts* opts,
                    void* ws, size_t ws_bytes, double* out, void* stream);
 
 /* ---- Stages of one half-step (the same kernels dna_update_* runs) -------- */
 
-/* Steps 2-5 and 10: A and B of eq. (7) and eq. (14).
+/* Steps 2-5 and 10: A and B of eq. (7) and eq. (14) (c = W^t 1 + lambda).
  * side 0: A_out, B_out are R x T;  side 1: N x R (A = Q H^t / g - 1,
- * B = Q-bar (H*H)^t / g). */
+ * B = Q-bar (H*H)^t / g, g = H 1 + rho). */
 dna_status dna_gradient_hessian(int side, const float* V, const float* W, const float* H,
                                 int64_t N, int64_t T, int64_t R, const dna_opts* opts,
                                 float* A_out, float* B_out,
@@ -259,7 +280,8 @@ dna_status dna_candidates(int side, const float* V, const float* W, const float*
 
 /* Steps 7-9, 12-15 given both candidates: per-column (side 0) or per-row
  * (side 1) costs, selection and the kept factor written to X_out.
- * F is the fixed factor (W for side 0, H for side 1). */
+ * F is the fixed factor (W for side 0, H for side 1).  rho and lambda do not
+ * enter (the selection compares the log-ratio sums only). */
 dna_status dna_select(int side, const float* V, const float* F,
                       const float* X_mu, const float* X_newton, float* X_out,
                       int64_t N, int64_t T, int64_t R, const dna_opts* opts,
@@ -267,6 +289,7 @@ dna_status dna_select(int side, const float* V, const float* F,
                       void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Differentiable unrolled H-solve (K DNA H-updates with W fixed) ------ */
+/* lambda != 0 returns DNA_EUNSUPPORTED from both calls (rho does not enter). */
 
 /* Workspace for the two calls below (larger than dna_workspace_bytes). */
 size_t dna_unrolled_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* opts);

@@ -114,7 +114,7 @@ struct Layout {
   Split shf, swf;            // row / column chunks of the fused kernels (R <= FUSED_MAX_R)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
-  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sume, vpart, cpart, fpart, s16, check, total;
+  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, bal, sume, vpart, cpart, fpart, s16, check, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -150,6 +150,8 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   L.c32 = take((size_t)R * 4);
   L.c64 = take((size_t)R * 8);
   L.sump = take((size_t)SUM_PARTS * R * 8);
+  L.sump2 = take((size_t)SUM_PARTS * R * 8);          // the other factor's parts (eq. 2 normalisation, penalty)
+  L.bal = take((size_t)R * 8);                         // balanced normalisation factors
   // sums emitted by the normalisation for the next half-step (dna_iterate)
   L.sume = take((size_t)std::max(scale_emit_parts(0, N, T), scale_emit_parts(1, N, T)) * R * 8);
   L.vpart = take(red * 8);
@@ -205,6 +207,8 @@ static dna_status check_opts(const dna_opts* o) {
   if (!(o->eps >= 0.f && o->eps <= 1.f)) return fail(DNA_EINVAL, "eps must lie in [0, 1]");
   if (!(o->alpha > 0.f) || !std::isfinite(o->alpha)) return fail(DNA_EINVAL, "alpha must be finite and > 0");
   if (o->gemm < DNA_GEMM_FP32 || o->gemm > DNA_GEMM_FP16) return fail(DNA_EINVAL, "unknown gemm type");
+  if (!(o->rho >= 0.f) || !std::isfinite(o->rho) || !(o->lambda >= 0.f) || !std::isfinite(o->lambda))
+    return fail(DNA_EINVAL, "rho and lambda must be finite and >= 0");
   return DNA_OK;
 }
 
@@ -286,8 +290,8 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
   if (side == 0) {
     if (pre) job = *pre;
     else DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
-    job.s64 = c64; job.s32 = c32; job.check = chk;
-    ra.fin = job;                                   // c = W^t 1 finished inside the ratio pass
+    job.s64 = c64; job.s32 = c32; job.check = chk; job.reg = o->lambda;
+    ra.fin = job;                                   // c = W^t 1 (+ lambda) finished inside the ratio pass
     const bool fused = !p16 && R <= FUSED_MAX_R;
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh16.splits, L.sh16.kchunk, pu, puc, py,
@@ -302,12 +306,12 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     // the 16-bit Z pass tiles N by 128 like the fp32 one (RT_BM)
     const int sp = p16 ? L.sh16.splits : (fused ? L.shf.splits : L.sh.splits);
     DNA_HIP(launch_cand_H(H, pu, puc, py, sp, c32, vpart, fused ? L.shf.splits : L.rt_m, T, R, o->eps, o->alpha,
-                          Xmu, Xn, Aout, Bout, s), "cand_H");
+                          o->lambda, Xmu, Xn, Aout, Bout, s), "cand_H");
   } else {
     if (pre) job = *pre;
     else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, s), "rowsum_H");
-    job.s64 = c64; job.s32 = c32; job.check = chk;
-    ra.fin = job;                                   // c' = H 1 finished inside the ratio pass
+    job.s64 = c64; job.s32 = c32; job.check = chk; job.reg = o->rho;
+    ra.fin = job;                                   // g = H 1 (+ rho) finished inside the ratio pass
     const bool fused = !p16 && R <= FUSED_MAX_R;
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw16.splits, L.sw16.kchunk, pu, puc, py,
@@ -322,8 +326,8 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     // the 16-bit Z pass tiles T by 128, the fp32 one by RT_BN
     const int sp = p16 ? L.sw16.splits : (fused ? L.swf.splits : L.sw.splits);
     const int tiles = p16 ? (int)cdiv(T, 128) : (fused ? L.swf.splits : L.rt_n);
-    DNA_HIP(launch_cand_W(W, pu, puc, py, sp, c32, vpart, tiles, N, R, o->eps, o->alpha, Xmu, Xn, Aout, Bout, s),
-            "cand_W");
+    DNA_HIP(launch_cand_W(W, pu, puc, py, sp, c32, vpart, tiles, N, R, o->eps, o->alpha, o->rho, Xmu, Xn, Aout,
+                          Bout, s), "cand_W");
   }
   return DNA_OK;
 }
@@ -388,6 +392,50 @@ static dna_status epilogue(const Common& c) {
   return DNA_OK;
 }
 
+// Algorithm 1 steps 1, 16, 29 under the eq. 2 weights: the form `side` names
+// when rho = lambda = 0 or both are positive (then the balanced scale, whose
+// factors either form applies), else the unit sums of the unpenalised factor
+// (W columns when only lambda > 0, H rows when only rho > 0).
+static int norm_side(const dna_opts* o, int side) {
+  const bool r = o->rho > 0.f, l = o->lambda > 0.f;
+  if (r != l) return l ? 0 : 1;
+  return side;
+}
+
+// One normalisation.  sump / sump2: SUM_PARTS x R doubles each; bal: R doubles.
+// With `emit`, the scale kernel also leaves the first level of the sums of the
+// factor of side norm_side(o, side) in `emitted` (W column sums for 0, H row
+// sums for 1).
+static dna_status run_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const dna_opts* o,
+                                double* sump, double* sump2, double* bal, int* chk, hipStream_t s, double* emit,
+                                SumJob* emitted) {
+  const int es = norm_side(o, side);
+  SumJob job;
+  if (o->rho > 0.f && o->lambda > 0.f) {
+    SumJob cj, gj;
+    DNA_HIP(launch_colsum_part(W, N, R, sump, cj, s), "colsum_W");
+    DNA_HIP(launch_rowsum_part(H, T, R, sump2, gj, s), "rowsum_H");
+    DNA_HIP(launch_balance(es, cj, gj, o->rho, o->lambda, bal, chk, job, s), "balance");
+  } else {
+    if (es == 0) DNA_HIP(launch_colsum_part(W, N, R, sump, job, s), "colsum_W");
+    else DNA_HIP(launch_rowsum_part(H, T, R, sump, job, s), "rowsum_H");
+    job.check = chk;
+  }
+  DNA_HIP(launch_scale(es, W, H, N, T, R, job, emit, emitted, s), "scale");
+  return DNA_OK;
+}
+
+// Adds rho sum w + lambda sum h to out[0] when either weight is positive.
+static dna_status add_penalty(const float* W, const float* H, int64_t N, int64_t T, int64_t R, const dna_opts* o,
+                              double* sump, double* sump2, double* out, hipStream_t s) {
+  if (!(o->rho > 0.f) && !(o->lambda > 0.f)) return DNA_OK;
+  SumJob cj, gj;
+  DNA_HIP(launch_colsum_part(W, N, R, sump, cj, s), "colsum_W");
+  DNA_HIP(launch_rowsum_part(H, T, R, sump2, gj, s), "rowsum_H");
+  DNA_HIP(launch_penalty(cj, gj, o->rho, o->lambda, out, s), "penalty");
+  return DNA_OK;
+}
+
 }  // namespace dna
 
 using namespace dna;
@@ -403,12 +451,13 @@ void dna_default_opts(dna_opts* o) {
   o->alpha = 4.0f;
   o->gemm = DNA_GEMM_FP32;
   o->checked = 0;
+  o->rho = 0.f;
+  o->lambda = 0.f;
 }
 
 size_t dna_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* o) {
-  (void)o;
   if (N <= 0 || T <= 0 || R <= 0) return 0;
-  return make_layout(N, T, R, o->gemm != DNA_GEMM_FP32).total;
+  return make_layout(N, T, R, o && o->gemm != DNA_GEMM_FP32).total;
 }
 
 dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const dna_opts* o,
@@ -417,12 +466,8 @@ dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int
   if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
   Common c;
   DNA_TRY(prologue(nullptr, W, H, N, T, R, o, ws, ws_bytes, stream, c));
-  double* sp = at<double>(ws, c.L.sump);
-  SumJob job;
-  if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");
-  else DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");
-  job.check = c.chk;
-  DNA_HIP(launch_scale(side, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+  DNA_TRY(run_normalize(side, W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2),
+                        at<double>(ws, c.L.bal), c.chk, c.s, nullptr, nullptr));
   return epilogue(c);
 }
 
@@ -452,16 +497,15 @@ dna_status dna_update_W(const float* V, float* W, const float* H, int64_t N, int
   return epilogue(c);
 }
 
-// Normalisation inside dna_iterate: the sum of the factor being normalised
-// (`pre`: emitted by the kernel that wrote that factor, else a sum kernel), then
-// the scale kernel, which emits the first level of the next half-step's sum.
+// Normalisation inside dna_iterate: the scale kernel emits the first level of
+// the sums of the factor it normalised; they are the next half-step's c (g)
+// when that factor is W (H), i.e. unless one eq. 2 weight alone is positive
+// and fixes the other factor's scale.
 static dna_status iterate_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                                    const Common& c, void* ws, SumJob& next) {
-  SumJob job;
-  if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, c.L.sump), job, c.s), "colsum_W");
-  else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, c.L.sump), job, c.s), "rowsum_H");
-  job.check = c.chk;
-  DNA_HIP(launch_scale(side, W, H, N, T, R, job, at<double>(ws, c.L.sume), &next, c.s), "scale");
+                                    const dna_opts* o, const Common& c, void* ws, SumJob& next, bool& valid) {
+  DNA_TRY(run_normalize(side, W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2),
+                        at<double>(ws, c.L.bal), c.chk, c.s, at<double>(ws, c.L.sume), &next));
+  valid = norm_side(o, side) == side;
   return DNA_OK;
 }
 
@@ -479,11 +523,11 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
     DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
                            have ? &next : nullptr));
     DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s));
-    DNA_TRY(iterate_normalize(1, W, H, N, T, R, c, ws, next));          // step 16; next = g
-    DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s, &next));
+    DNA_TRY(iterate_normalize(1, W, H, N, T, R, o, c, ws, next, have));  // step 16; next = g
+    DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
+                           have ? &next : nullptr));
     DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s));
-    DNA_TRY(iterate_normalize(0, W, H, N, T, R, c, ws, next));          // step 29; next = c
-    have = true;
+    DNA_TRY(iterate_normalize(0, W, H, N, T, R, o, c, ws, next, have));  // step 29; next = c
   }
   return epilogue(c);
 }
@@ -491,7 +535,7 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
 // One MU half-step (eq. 11) on the prologue's state; with_cost writes the input
 // state's per-column (row) cost to d_out.
 static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                         int with_cost, double* d_out, const Common& c, void* ws) {
+                         int with_cost, double* d_out, const dna_opts* o, const Common& c, void* ws) {
   const Layout& L = c.L;
   float* Q = at<float>(ws, L.q);
   float* pu = at<float>(ws, L.pu);
@@ -501,14 +545,14 @@ static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N
   SumJob job;
   if (side == 0) {
     DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
-    job.s32 = c32; job.check = c.chk;
+    job.s32 = c32; job.check = c.chk; job.reg = o->lambda;
     ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_H_COST : RM_MU_H, ra, c.s), "ratio_mu_H");
     DNA_HIP(launch_gh_H(W, Q, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_H");
     DNA_HIP(launch_mu_H(H, pu, L.sh.splits, c32, T, R, cpart, L.rt_m, with_cost ? d_out : nullptr, c.s), "mu_H");
   } else {
     DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
-    job.s32 = c32; job.check = c.chk;
+    job.s32 = c32; job.check = c.chk; job.reg = o->rho;
     ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_W_COST : RM_MU_W, ra, c.s), "ratio_mu_W");
     DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_W");
@@ -524,7 +568,7 @@ dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, in
   if (with_cost && !d_out) return fail(DNA_EINVAL, "with_cost requires d_out");
   Common c;
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
-  DNA_TRY(run_mu(side, V, W, H, N, T, R, with_cost, d_out, c, ws));
+  DNA_TRY(run_mu(side, V, W, H, N, T, R, with_cost, d_out, o, c, ws));
   return epilogue(c);
 }
 
@@ -536,16 +580,13 @@ dna_status mu_iterate(const float* V, float* W, float* H, int64_t N, int64_t T, 
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* dcost = at<double>(ws, c.L.vpart);        // the with-cost outputs, not returned
   double* sp = at<double>(ws, c.L.sump);
+  double* sp2 = at<double>(ws, c.L.sump2);
+  double* bal = at<double>(ws, c.L.bal);
   for (int it = 0; it < iters; ++it) {
-    DNA_TRY(run_mu(0, V, W, H, N, T, R, with_cost, dcost, c, ws));
-    SumJob job;
-    DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");      // step 16
-    job.check = c.chk;
-    DNA_HIP(launch_scale(1, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
-    DNA_TRY(run_mu(1, V, W, H, N, T, R, with_cost, dcost, c, ws));
-    DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");      // step 29
-    job.check = c.chk;
-    DNA_HIP(launch_scale(0, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+    DNA_TRY(run_mu(0, V, W, H, N, T, R, with_cost, dcost, o, c, ws));
+    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 16
+    DNA_TRY(run_mu(1, V, W, H, N, T, R, with_cost, dcost, o, c, ws));
+    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 29
   }
   return epilogue(c);
 }
@@ -559,6 +600,7 @@ dna_status kl_cost(const float* V, const float* W, const float* H, int64_t N, in
   RatioArgs ra{V, W, H, N, T, R, nullptr, nullptr, nullptr, cpart, c.chk, nullptr};
   DNA_HIP(launch_ratio(RM_KL, ra, c.s), "kl_terms");
   DNA_HIP(launch_kl_final(cpart, c.L.rt_m * c.L.rt_n, out, c.s), "kl_final");
+  DNA_TRY(add_penalty(W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2), out, c.s));
   return epilogue(c);
 }
 
@@ -616,6 +658,7 @@ dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_ini
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
   if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint runs in fp32 only");
+  if (o->lambda != 0.f) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint has no lambda terms");
   const AdjLayout A = make_adj_layout(N, T, R);
   DNA_TRY(check_ws(ws, ws_bytes, A.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -647,6 +690,7 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
   if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint runs in fp32 only");
+  if (o->lambda != 0.f) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint has no lambda terms");
   const AdjLayout A = make_adj_layout(N, T, R);
   DNA_TRY(check_ws(ws, ws_bytes, A.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -715,8 +759,8 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
 // ---------------------------------------------------------------------------
 struct SpLayout {
   int64_t nseg;
-  size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, vpart, cseg, fseg, part,
-      fpart, check, total;
+  size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, sump2, bal, vpart, cseg,
+      fseg, part, fpart, check, total;
 };
 
 static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse_v* V) {
@@ -742,6 +786,8 @@ static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse
   L.c64 = take((size_t)R * 8);
   L.g64 = take((size_t)R * 8);
   L.sump = take((size_t)SUM_PARTS * R * 8);
+  L.sump2 = take((size_t)SUM_PARTS * R * 8);
+  L.bal = take((size_t)R * 8);
   L.vpart = take(mx * 8);
   L.cseg = take(3 * (size_t)L.nseg * 8);
   L.fseg = take((size_t)L.nseg * 4);
@@ -824,12 +870,13 @@ static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float*
   if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
   else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
   job.s64 = c64; job.s32 = c32; job.check = c.chk;  // c = W^t 1 (side 0) or g = H 1 (side 1)
+  job.reg = side == 0 ? o->lambda : o->rho;         // c32 = c + lambda or g + rho; c64 without
   DNA_HIP(launch_sp_zq(v, W, Ht, N, T, R, q, qb, c.chk, job, c.s), "sp_zq");
   DNA_HIP(launch_sp_grad(side, false, v, side == 0 ? W : Ht, q, qb, c64, N, T, R, at<float>(ws, L.gp),
                          at<double>(ws, L.vseg), pu, puc, py, vpart, c.s), "sp_grad");
   if (side == 0) {
-    DNA_HIP(launch_cand_H(H, pu, puc, py, 1, c32, vpart, 1, T, R, o->eps, o->alpha, Xmu, Xn, nullptr, nullptr, c.s),
-            "cand_H");
+    DNA_HIP(launch_cand_H(H, pu, puc, py, 1, c32, vpart, 1, T, R, o->eps, o->alpha, o->lambda, Xmu, Xn, nullptr,
+                          nullptr, c.s), "cand_H");
     DNA_HIP(launch_sp_diff(Xmu, Xn, Xd, R * T, c.s), "sp_diff");
     float* XnT = at<float>(ws, L.xnt);
     float* XdT = at<float>(ws, L.xdt);
@@ -839,8 +886,8 @@ static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float*
                            c.s), "sp_cost_H");
     DNA_HIP(launch_select_H(Xmu, Xn, H, part, fpart, 1, T, R, mask, dsel, margin, c.s), "select_H");
   } else {
-    DNA_HIP(launch_cand_W(W, pu, puc, py, 1, c32, vpart, 1, N, R, o->eps, o->alpha, Xmu, Xn, nullptr, nullptr, c.s),
-            "cand_W");
+    DNA_HIP(launch_cand_W(W, pu, puc, py, 1, c32, vpart, 1, N, R, o->eps, o->alpha, o->rho, Xmu, Xn, nullptr,
+                          nullptr, c.s), "cand_W");
     DNA_HIP(launch_sp_diff(Xmu, Xn, Xd, N * R, c.s), "sp_diff");
     DNA_HIP(launch_sp_cost(1, v, Ht, Xn, Xd, N, T, R, at<double>(ws, L.cseg), at<int>(ws, L.fseg), part, fpart,
                            c.s), "sp_cost_W");
@@ -892,12 +939,15 @@ dna_status dna_sparse_kl_cost(const dna_sparse_v* V, const float* W, const float
   DNA_HIP(launch_sum_final(job, c.s), "sum_final g");
   DNA_HIP(launch_sp_kl(sp_view(V), W, Ht, N, T, R, at<double>(ws, L.cseg), at<double>(ws, L.c64),
                        at<double>(ws, L.g64), out, c.s), "sp_kl");
+  if (o->rho > 0.f || o->lambda > 0.f)
+    DNA_HIP(launch_penalty(SumJob{at<double>(ws, L.c64), 1, R}, SumJob{at<double>(ws, L.g64), 1, R}, o->rho,
+                           o->lambda, out, c.s), "penalty");
   return sp_epilogue(c);
 }
 
 // One sparse MU half-step on the prologue's state.
 static dna_status sp_run_mu(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                            const SpCommon& c, void* ws) {
+                            const dna_opts* o, const SpCommon& c, void* ws) {
   const SpLayout& L = c.L;
   const SpV v = sp_view(V);
   float* Ht = at<float>(ws, L.ht);
@@ -909,7 +959,7 @@ static dna_status sp_run_mu(int side, const dna_sparse_v* V, float* W, float* H,
   SumJob job;
   if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
   else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
-  job.s64 = c64; job.s32 = c32; job.check = c.chk;
+  job.s64 = c64; job.s32 = c32; job.check = c.chk; job.reg = side == 0 ? o->lambda : o->rho;
   DNA_HIP(launch_sp_zq(v, W, Ht, N, T, R, q, at<float>(ws, L.qb), c.chk, job, c.s), "sp_zq");
   DNA_HIP(launch_sp_grad(side, true, v, side == 0 ? W : Ht, q, nullptr, c64, N, T, R, at<float>(ws, L.gp),
                          nullptr, pu, nullptr, nullptr, nullptr, c.s), "sp_grad_mu");
@@ -924,7 +974,7 @@ dna_status dna_sparse_mu_update(int side, const dna_sparse_v* V, float* W, float
   if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
   SpCommon c;
   DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
-  DNA_TRY(sp_run_mu(side, V, W, H, N, T, R, c, ws));
+  DNA_TRY(sp_run_mu(side, V, W, H, N, T, R, o, c, ws));
   return sp_epilogue(c);
 }
 
@@ -935,16 +985,13 @@ dna_status dna_sparse_mu_iterate(const dna_sparse_v* V, float* W, float* H, int6
   SpCommon c;
   DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* sp = at<double>(ws, c.L.sump);
+  double* sp2 = at<double>(ws, c.L.sump2);
+  double* bal = at<double>(ws, c.L.bal);
   for (int it = 0; it < iters; ++it) {
-    DNA_TRY(sp_run_mu(0, V, W, H, N, T, R, c, ws));
-    SumJob job;
-    DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");           // step 16
-    job.check = c.chk;
-    DNA_HIP(launch_scale(1, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
-    DNA_TRY(sp_run_mu(1, V, W, H, N, T, R, c, ws));
-    DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");           // step 29
-    job.check = c.chk;
-    DNA_HIP(launch_scale(0, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+    DNA_TRY(sp_run_mu(0, V, W, H, N, T, R, o, c, ws));
+    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 16
+    DNA_TRY(sp_run_mu(1, V, W, H, N, T, R, o, c, ws));
+    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 29
   }
   return sp_epilogue(c);
 }
@@ -956,16 +1003,13 @@ dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H, int64_t
   SpCommon c;
   DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* sp = at<double>(ws, c.L.sump);
+  double* sp2 = at<double>(ws, c.L.sump2);
+  double* bal = at<double>(ws, c.L.bal);
   for (int it = 0; it < iters; ++it) {
     DNA_TRY(sp_half_step(0, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
-    SumJob job;
-    DNA_HIP(launch_rowsum_part(H, T, R, sp, job, c.s), "rowsum_H");           // step 16
-    job.check = c.chk;
-    DNA_HIP(launch_scale(1, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 16
     DNA_TRY(sp_half_step(1, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
-    DNA_HIP(launch_colsum_part(W, N, R, sp, job, c.s), "colsum_W");           // step 29
-    job.check = c.chk;
-    DNA_HIP(launch_scale(0, W, H, N, T, R, job, nullptr, nullptr, c.s), "scale");
+    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 29
   }
   return sp_epilogue(c);
 }

@@ -21,7 +21,7 @@ __device__ __forceinline__ void sum_job(const SumJob& j) {
 #pragma unroll 8
     for (int p = 0; p < j.nparts; ++p) tot += j.part[(int64_t)p * j.R + r];
     if (j.s64) j.s64[r] = tot;
-    if (j.s32) j.s32[r] = (float)tot;
+    if (j.s32) j.s32[r] = (float)(tot + j.reg);
     if (j.check && !(tot > 0.0)) atomicOr(j.check, CHK_DOMAIN);
   }
 }

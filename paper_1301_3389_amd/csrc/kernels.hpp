@@ -51,8 +51,10 @@ enum RatioMode {
 
 // Second level of a column / row sum of a factor (see launch_colsum_part): the
 // parts are added in a fixed order into s64 / s32 (either may be nullptr), and
-// a sum <= 0 sets CHK_DOMAIN in *check (if not nullptr).  A kernel that receives
-// a SumJob with part != nullptr performs it on the side, before its own work.
+// a sum <= 0 sets CHK_DOMAIN in *check (if not nullptr).  s32 receives the sum
+// plus `reg` (the eq. 2 weight of the half-step that divides by it: lambda for
+// c = W^t 1, rho for g = H 1); s64 the sum alone.  A kernel that receives a
+// SumJob with part != nullptr performs it on the side, before its own work.
 struct SumJob {
   const double* part = nullptr;
   int nparts = 0;
@@ -60,6 +62,7 @@ struct SumJob {
   double* s64 = nullptr;
   float* s32 = nullptr;
   int* check = nullptr;
+  double reg = 0.0;
 };
 
 struct RatioArgs {
@@ -86,14 +89,15 @@ hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t 
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s);
 
-// Candidates (MU and renormalised Newton) from the split partials.
+// Candidates (MU and renormalised Newton) from the split partials.  c (g) holds
+// the factor sums plus reg, the eq. 2 weight of this half-step (lambda / rho).
 hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
                          const float* c, const double* vpart, int tiles_m, int64_t T, int64_t R,
-                         float eps, float alpha, float* Xmu, float* Xn, float* Aout, float* Bout,
+                         float eps, float alpha, float reg, float* Xmu, float* Xn, float* Aout, float* Bout,
                          hipStream_t s);
 hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits,
                          const float* g, const double* vpart, int tiles_n, int64_t N, int64_t R,
-                         float eps, float alpha, float* Xmu, float* Xn, float* Aout, float* Bout,
+                         float eps, float alpha, float reg, float* Xmu, float* Xn, float* Aout, float* Bout,
                          hipStream_t s);
 
 // Fused candidate reconstruction + log + reduction (costs of both candidates).
@@ -134,6 +138,12 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s);
 // the new H, cdiv(T, SC_TCHUNK) parts) and returns their second level in
 // `emitted`, for the half-step that follows.
 constexpr int SC_TCHUNK = 2048;
+// Normalisation factors of the balanced (rho, lambda > 0) normalisation into
+// f[R]; `job` becomes the one-part SumJob that launch_scale(side, ...) takes.
+hipError_t launch_balance(int side, const SumJob& cj, const SumJob& gj, double rho, double lam, double* f,
+                          int* check, SumJob& job, hipStream_t s);
+// out[0] += rho sum C + lambda sum G from the parts of C = W^t 1, G = H 1.
+hipError_t launch_penalty(const SumJob& cj, const SumJob& gj, double rho, double lam, double* out, hipStream_t s);
 int64_t scale_emit_parts(int side, int64_t N, int64_t T);
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
                         double* emit, SumJob* emitted, hipStream_t s);

@@ -296,27 +296,30 @@ struct Cand {
   float mu, newton, A, B;
 };
 
-// MU gain g = u/c and A = g - 1 (eq. 7) from the two forms of the gradient sum:
-// where g < 1/2 the plain sum u = (F^t q)_r carries g to float32 relative
-// accuracy; elsewhere the centred sum u_c = (F^t (q - 1))_r carries A to float32
-// accuracy near its zero (near-stationary coordinates, where the Newton step
-// divides by b).
-__device__ __forceinline__ void gain(float u, float uc, float c, float& g, float& A) {
+// MU gain g = u/c and A = g - 1 (eq. 7) from the two forms of the gradient sum,
+// c = (F^t 1)_r + reg (reg: the eq. 2 weight, lambda or rho): where g < 1/2 the
+// plain sum u = (F^t q)_r carries g to float32 relative accuracy; elsewhere the
+// centred sum u_c = (F^t (q - 1))_r = u - (c - reg) carries A = (u_c - reg)/c to
+// float32 accuracy near its zero (near-stationary coordinates, where the Newton
+// step divides by b).
+__device__ __forceinline__ void gain(float u, float uc, float c, float reg, float& g, float& A) {
   const float gp = u / c;
   if (gp < 0.5f) {
     g = gp;
     A = gp - 1.f;
   } else {
-    A = uc / c;
+    A = (uc - reg) / c;
     g = 1.f + A;
   }
 }
 
-// One coordinate: numerators u, u_c, y = ((F*F)^t q-bar)_r, scale c_r.
-__device__ __forceinline__ Cand candidate(float x, float u, float uc, float y, float c, float eps, float alpha) {
+// One coordinate: numerators u, u_c, y = ((F*F)^t q-bar)_r, scale c_r (which
+// includes reg).
+__device__ __forceinline__ Cand candidate(float x, float u, float uc, float y, float c, float eps, float alpha,
+                                          float reg) {
   Cand o;
   float g;
-  gain(u, uc, c, g, o.A);           // eq. (7)
+  gain(u, uc, c, reg, g, o.A);      // eq. (7)
   o.B = y / c;                      // eq. (14)
   o.mu = fmaxf(x * g, VALUE_FLOOR); // eq. (11), kept a positive normal float
   if (o.A < 0.f) {                  // eq. (15), gain floored at eps
@@ -340,7 +343,8 @@ template <int RPT, int RG>
 __global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
     const float* __restrict__ H, const float* __restrict__ pu, const float* __restrict__ puc,
     const float* __restrict__ py, int splits, const float* __restrict__ c, const double* __restrict__ vpart,
-    int tiles_m, int64_t T, int64_t R, float eps, float alpha, float* __restrict__ Xmu, float* __restrict__ Xn,
+    int tiles_m, int64_t T, int64_t R, float eps, float alpha, float reg, float* __restrict__ Xmu,
+    float* __restrict__ Xn,
     float* __restrict__ Aout, float* __restrict__ Bout) {
   __shared__ double red[RG][CAND_COLS];
   __shared__ double fac[CAND_COLS];
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
         const int64_t r = rg + i * RG;
         keep[i] = 0.f;
         if (r < R) {
-          const Cand k = candidate(H[r * T + t], u[i], uc[i], y[i], c[r], eps, alpha);
+          const Cand k = candidate(H[r * T + t], u[i], uc[i], y[i], c[r], eps, alpha, reg);
           Xmu[r * T + t] = k.mu;
           keep[i] = k.newton;
           if (Aout) Aout[r * T + t] = k.A;
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
           uc += puc[(sp * R + r) * T + t];
           y += py[(sp * R + r) * T + t];
         }
-        const Cand k = candidate(H[r * T + t], u, uc, y, c[r], eps, alpha);
+        const Cand k = candidate(H[r * T + t], u, uc, y, c[r], eps, alpha, reg);
         Xmu[r * T + t] = k.mu;
         Xn[r * T + t] = k.newton;
         if (Aout) Aout[r * T + t] = k.A;
@@ -428,7 +432,7 @@ __global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
 }
 
 hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits, const float* c,
-                         const double* vpart, int tiles_m, int64_t T, int64_t R, float eps, float alpha,
+                         const double* vpart, int tiles_m, int64_t T, int64_t R, float eps, float alpha, float reg,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_H", s);
   // for R <= 128, 32 row groups (1024 threads) give every CU 16 waves of
@@ -437,13 +441,13 @@ hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, cons
   constexpr int RG = 32;
   if (R <= 2 * RG)
     hipLaunchKernelGGL((k_cand_H<2, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
-                       tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
+                       tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
   else if (R <= 4 * RG)
     hipLaunchKernelGGL((k_cand_H<4, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
-                       tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
+                       tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
   else
     hipLaunchKernelGGL((k_cand_H<0, CAND_RG>), grid, dim3(CAND_COLS * CAND_RG), 0, s, H, pu, puc, py, splits, c,
-                       vpart, tiles_m, T, R, eps, alpha, Xmu, Xn, Aout, Bout);
+                       vpart, tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
   prof_end("cand_H", s);
   return hipGetLastError();
 }
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(256) void k_cand_W(const float* __restrict__ W, con
                                                 const float* __restrict__ puc, const float* __restrict__ py,
                                                 int splits, const float* __restrict__ g,
                                                 const double* __restrict__ vpart, int tiles_n, int64_t N, int64_t R,
-                                                float eps, float alpha, float* __restrict__ Xmu,
+                                                float eps, float alpha, float reg, float* __restrict__ Xmu,
                                                 float* __restrict__ Xn, float* __restrict__ Aout,
                                                 float* __restrict__ Bout) {
   constexpr int NR = RPW > 0 ? RPW : 1;
@@ -476,7 +480,7 @@ __global__ __launch_bounds__(256) void k_cand_W(const float* __restrict__ W, con
         uc += puc[(sp * N + n) * R + r];
         y += py[(sp * N + n) * R + r];
       }
-      const Cand k = candidate(W[n * R + r], u, uc, y, g[r], eps, alpha);
+      const Cand k = candidate(W[n * R + r], u, uc, y, g[r], eps, alpha, reg);
       Xmu[n * R + r] = k.mu;
       Xn[n * R + r] = k.newton;
       if (Aout) Aout[n * R + r] = k.A;
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(256) void k_cand_W(const float* __restrict__ W, con
         const float uu = (red[0][0][e] + red[0][1][e]) + (red[0][2][e] + red[0][3][e]);
         const float ucc = (red[1][0][e] + red[1][1][e]) + (red[1][2][e] + red[1][3][e]);
         const float yy = (red[2][0][e] + red[2][1][e]) + (red[2][2][e] + red[2][3][e]);
-        const Cand k = candidate(W[n * R + r], uu, ucc, yy, g[r], eps, alpha);
+        const Cand k = candidate(W[n * R + r], uu, ucc, yy, g[r], eps, alpha, reg);
         Xmu[n * R + r] = k.mu;
         keep[i] = k.newton;
         if (Aout) Aout[n * R + r] = k.A;
@@ -553,19 +557,19 @@ __global__ __launch_bounds__(256) void k_cand_W(const float* __restrict__ W, con
 }
 
 hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits, const float* g,
-                         const double* vpart, int tiles_n, int64_t N, int64_t R, float eps, float alpha,
+                         const double* vpart, int tiles_n, int64_t N, int64_t R, float eps, float alpha, float reg,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_W", s);
   const dim3 grid((unsigned)N);
   if (R <= 64)
     hipLaunchKernelGGL(k_cand_W<1>, grid, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R, eps,
-                       alpha, Xmu, Xn, Aout, Bout);
+                       alpha, reg, Xmu, Xn, Aout, Bout);
   else if (R <= 128)
     hipLaunchKernelGGL(k_cand_W<2>, grid, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R, eps,
-                       alpha, Xmu, Xn, Aout, Bout);
+                       alpha, reg, Xmu, Xn, Aout, Bout);
   else
     hipLaunchKernelGGL(k_cand_W<0>, grid, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R, eps,
-                       alpha, Xmu, Xn, Aout, Bout);
+                       alpha, reg, Xmu, Xn, Aout, Bout);
   prof_end("cand_W", s);
   return hipGetLastError();
 }
@@ -961,6 +965,59 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
       if (tid == 0) emit[ch * R + r] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
     }
   }
+}
+
+// Balanced normalisation factors (eq. 2 with rho, lambda > 0): with C = W^t 1
+// and G = H 1 finished from their parts, f_r = sqrt(rho C_r / (lambda G_r)) for
+// side 0 (k_scale then divides W column r by f_r and multiplies H row r by it)
+// and its reciprocal for side 1; either way W column r is multiplied by
+// s_r = sqrt(lambda G_r / (rho C_r)).  A sum that is not positive gives f_r = 0,
+// which k_scale leaves unscaled, and sets CHK_DOMAIN.
+__global__ __launch_bounds__(256) void k_balance(int side, SumJob cj, SumJob gj, double rho, double lam,
+                                                 double* __restrict__ f, int* check) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= cj.R) return;
+  double C = 0.0, G = 0.0;
+  for (int p = 0; p < cj.nparts; ++p) C += cj.part[(int64_t)p * cj.R + r];
+  for (int p = 0; p < gj.nparts; ++p) G += gj.part[(int64_t)p * gj.R + r];
+  double v = 0.0;
+  if (C > 0.0 && G > 0.0) v = side == 0 ? sqrt((rho * C) / (lam * G)) : sqrt((lam * G) / (rho * C));
+  else if (check) atomicOr(check, CHK_DOMAIN);
+  f[r] = v;
+}
+
+hipError_t launch_balance(int side, const SumJob& cj, const SumJob& gj, double rho, double lam, double* f,
+                          int* check, SumJob& job, hipStream_t s) {
+  prof_begin("balance", s);
+  hipLaunchKernelGGL(k_balance, dim3((unsigned)cdiv(cj.R, 256)), dim3(256), 0, s, side, cj, gj, rho, lam, f, check);
+  prof_end("balance", s);
+  job = SumJob{f, 1, cj.R, nullptr, nullptr, nullptr};
+  return hipGetLastError();
+}
+
+// out[0] += rho sum_r C_r + lambda sum_r G_r (the penalty of eq. 2), C and G
+// finished from their parts; one block, fixed-order reduction.
+__global__ __launch_bounds__(256) void k_penalty(SumJob cj, SumJob gj, double rho, double lam, double* out) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t r = tid; r < cj.R; r += 256) {
+    double C = 0.0, G = 0.0;
+    for (int p = 0; p < cj.nparts; ++p) C += cj.part[(int64_t)p * cj.R + r];
+    for (int p = 0; p < gj.nparts; ++p) G += gj.part[(int64_t)p * gj.R + r];
+    acc += rho * C + lam * G;
+  }
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) out[0] += (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_penalty(const SumJob& cj, const SumJob& gj, double rho, double lam, double* out, hipStream_t s) {
+  prof_begin("penalty", s);
+  hipLaunchKernelGGL(k_penalty, dim3(1), dim3(256), 0, s, cj, gj, rho, lam, out);
+  prof_end("penalty", s);
+  return hipGetLastError();
 }
 
 int64_t scale_emit_parts(int side, int64_t N, int64_t T) {

@@ -33,7 +33,8 @@ STATUS = {0: "DNA_OK", 1: "DNA_EINVAL", 2: "DNA_EWORKSPACE", 3: "DNA_EDOMAIN",
 
 class Opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("alpha", ctypes.c_float),
-                ("gemm", ctypes.c_int), ("checked", ctypes.c_int)]
+                ("gemm", ctypes.c_int), ("checked", ctypes.c_int),
+                ("rho", ctypes.c_float), ("lam", ctypes.c_float)]   # dna_opts.rho, dna_opts.lambda
 
 
 class KernelStat(ctypes.Structure):
@@ -110,13 +111,17 @@ def _check(status):
         raise DNAError(status, _lib_last_error().decode())
 
 
-def make_opts(eps=0.01, alpha=4.0, gemm="fp32", checked=False):
+def make_opts(eps=0.01, alpha=4.0, gemm="fp32", checked=False, rho=0.0, lam=0.0):
+    """dna_opts: eps, alpha (Sec. 2.3), product type, checked mode, and the
+    eq. (2) weights rho (sum of W) and lam (lambda, sum of H)."""
     o = Opts()
     _lib_default_opts(ctypes.byref(o))
     o.eps = float(eps)
     o.alpha = float(alpha)
     o.gemm = GEMM_TYPES[gemm] if isinstance(gemm, str) else int(gemm)
     o.checked = 1 if checked else 0
+    o.rho = float(rho)
+    o.lam = float(lam)
     return o
 
 
@@ -536,7 +541,8 @@ def sparse_iterate(V, W, H, iters, **kw):
 
 def sparse_fit(V, W, H, iters, record_kl=False, **kw):
     """Algorithm 1 with a sparse V from step 1, in place; the KL after each
-    iteration as a float64 device tensor when ``record_kl`` (index 0 = start)."""
+    iteration as a float64 device tensor when ``record_kl`` (index 0 = start;
+    eq. 2 with ``rho`` / ``lam`` in ``kw``)."""
     normalize(0, W, H, **kw)
     if not record_kl:
         sparse_iterate(V, W, H, iters, **kw)
@@ -596,7 +602,8 @@ def mu_iteration(V, W, H, with_cost=False, **kw):
 def fit(V, W, H, iters, method="dna", record_kl=False, **kw):
     """Algorithm 1 (method='dna') or MU (method='mu') for ``iters`` iterations,
     in place, starting with step 1.  Returns the KL after each iteration as a
-    float64 device tensor when ``record_kl`` (index 0 = start)."""
+    float64 device tensor when ``record_kl`` (index 0 = start); with ``rho`` or
+    ``lam`` in ``kw``, the regularised cost of eq. (2) instead."""
     normalize(0, W, H, **kw)
     kls = torch.empty(iters + 1, dtype=torch.float64, device=V.device) if record_kl else None
     if record_kl:

@@ -83,6 +83,16 @@ def test_invalid_arguments_rejected_before_launch():
     assert dna._lib_update_H(fake, fake, fake, 8, 8, 2, None, ws, 1 << 30, null, null, null, null) == 1
     msg = dna._lib_last_error().decode()
     assert "opts" in msg
+    # eq. (2) weights: finite and >= 0
+    for kw in ({"rho": -0.5}, {"lam": -1e-3}, {"rho": float("nan")}, {"lam": float("inf")}):
+        bad = dna.make_opts(**kw)
+        assert E(fake, fake, fake, 8, 8, 2, ctypes.byref(bad), ws, 1 << 30, null, null, null, null) == 1, kw
+        assert "rho and lambda" in dna._lib_last_error().decode()
+    # the unrolled adjoint has no lambda terms
+    reg = dna.make_opts(lam=0.5)
+    assert dna._lib_ufwd(fake, fake, fake, 2, 8, 8, 2, ctypes.byref(reg), fake, fake, ws, 1 << 30, null) == 6
+    assert dna._lib_ubwd(fake, fake, fake, fake, 2, 8, 8, 2, fake, fake, fake, null, ctypes.byref(reg), ws,
+                         1 << 30, null) == 6
     # side out of range, with_cost without output
     assert dna._lib_normalize(2, fake, fake, 8, 8, 2, ctypes.byref(o), ws, 1 << 30, null) == 1
     assert dna._lib_mu(0, fake, fake, fake, 8, 8, 2, 1, null, ctypes.byref(o), ws, 1 << 30, null) == 1
