@@ -160,6 +160,10 @@ def parse():
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/traffic_<tag>.json from four rocprofv3 --pmc output folders")
     ap.add_argument("--traffic-tag", default=None, help="tag of the traffic file (default: workload tag)")
+    ap.add_argument("--rho", type=float, default=0.0,
+                    help="eq. 2 weight of sum W (with --lam: time the regularised iteration; "
+                         "no time-to-target or CPU leg)")
+    ap.add_argument("--lam", type=float, default=0.0, help="eq. 2 weight of sum H")
     return ap.parse_args()
 
 
@@ -416,9 +420,13 @@ def main():
     H0 = torch.from_numpy(w.H).to(dev)
 
     gemm = args.gemm
+    reg = dict(rho=args.rho, lam=args.lam)
+    regularised = args.rho > 0 or args.lam > 0
+    if regularised:
+        args.no_target = args.no_cpu_baseline = True
     W, H = W0.clone(), H0.clone()
-    dna.normalize(0, W, H)                                   # Algorithm 1 step 1
-    dna.iterate(V, W, H, args.warmup, gemm=gemm)
+    dna.normalize(0, W, H, **reg)                            # Algorithm 1 step 1
+    dna.iterate(V, W, H, args.warmup, gemm=gemm, **reg)
     torch.cuda.synchronize()
 
     # ---- timed region -----------------------------------------------------
@@ -427,7 +435,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    dna.iterate(V, W, H, args.steps, gemm=gemm)          # args.steps full iterations, one call
+    dna.iterate(V, W, H, args.steps, gemm=gemm, **reg)   # args.steps full iterations, one call
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -440,7 +448,7 @@ def main():
     dna.profile_enable(True)
     torch.cuda.synchronize()
     tp = time.perf_counter()
-    dna.iterate(V, W, H, args.steps, gemm=gemm)
+    dna.iterate(V, W, H, args.steps, gemm=gemm, **reg)
     torch.cuda.synchronize()
     prof_wall = time.perf_counter() - tp
     stats = dna.profile_read()
@@ -503,7 +511,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"DNA KL-NMF, N={N} T={T} R={R}, {WORKLOADS[args.config]}",
                    "N": N, "T": T, "R": R, "iteration": "H step, step 16, W step, step 29",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", **({"rho": args.rho, "lambda": args.lam} if regularised else {})},
         "gpu_ms_per_step": gpu_ms / args.steps,
         "algorithmic_gflops": gflops,
         "mfma_frac_algorithmic": gflops / 1e3 / peak,
