@@ -161,12 +161,20 @@ def _dims(V, W, H):
 _ws_cache = {}
 
 
+def _ws_key(kind):
+    # one workspace per device and stream: calls enqueued on different streams
+    # may run concurrently, so they must not share scratch memory
+    dev = torch.cuda.current_device()
+    return dev, torch.cuda.current_stream(dev).cuda_stream, kind
+
+
 def workspace(N, T, R, opts=None, unrolled=False):
-    """Device workspace for an N x T x R problem (cached per size and device)."""
+    """Device workspace for an N x T x R problem (cached per device and stream,
+    grown to the largest size asked for)."""
     o = opts or make_opts()
     nbytes = (_lib_uws if unrolled else _lib_ws)(N, T, R, ctypes.byref(o))
-    dev = torch.cuda.current_device()
-    key = (dev, unrolled)
+    key = _ws_key("unrolled" if unrolled else "dense")
+    dev = key[0]
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{dev}")
@@ -456,8 +464,8 @@ def sparse_workspace(V, R, opts):
     nbytes = _lib_sp_ws(V.N, V.T, R, ctypes.byref(V.c), ctypes.byref(opts))
     if nbytes == 0:
         raise DNAError(1, "invalid sparse problem size")
-    dev = torch.cuda.current_device()
-    key = (dev, "sparse")
+    key = _ws_key("sparse")
+    dev = key[0]
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{dev}")

@@ -372,3 +372,30 @@ def test_full_size_sampled(dna, k):
     assert err_w.size == 0 or err_w.max() <= STEP_TOL
     del w
     torch.cuda.empty_cache()
+
+
+def test_concurrent_streams_match_sequential(dna):
+    """Independent problems issued on three streams at once, their iterations
+    interleaved (each stream gets its own workspace from the binding), end
+    bit-identical to the same problems run one after another."""
+    probs = [_problem(300, 333, 37, 0.2, s) for s in (21, 22, 23)]
+    seq = []
+    for V, W, H in probs:
+        Vg, Wg, Hg = gpu(V), gpu(W), gpu(H)
+        dna.normalize(0, Wg, Hg)
+        for _ in range(4):
+            dna.iterate(Vg, Wg, Hg, 1)
+        seq.append((host(Wg), host(Hg)))
+    state = [(gpu(V), gpu(W), gpu(H)) for V, W, H in probs]
+    streams = [torch.cuda.Stream() for _ in probs]
+    for st, (Vg, Wg, Hg) in zip(streams, state):
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            dna.normalize(0, Wg, Hg)
+    for _ in range(4):
+        for st, (Vg, Wg, Hg) in zip(streams, state):
+            with torch.cuda.stream(st):
+                dna.iterate(Vg, Wg, Hg, 1)
+    torch.cuda.synchronize()
+    for (Wr, Hr), (_, Wg, Hg) in zip(seq, state):
+        assert np.array_equal(host(Wg), Wr) and np.array_equal(host(Hg), Hr)
