@@ -114,7 +114,7 @@ struct Layout {
   Split shf, swf;            // row / column chunks of the fused kernels (R <= FUSED_MAX_R)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
-  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, bal, sume, vpart, cpart, fpart, s16, check, total;
+  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, sume, vpart, cpart, fpart, s16, check, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -151,7 +151,6 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   L.c64 = take((size_t)R * 8);
   L.sump = take((size_t)SUM_PARTS * R * 8);
   L.sump2 = take((size_t)SUM_PARTS * R * 8);          // the other factor's parts (eq. 2 normalisation, penalty)
-  L.bal = take((size_t)R * 8);                         // balanced normalisation factors
   // sums emitted by the normalisation for the next half-step (dna_iterate)
   L.sume = take((size_t)std::max(scale_emit_parts(0, N, T), scale_emit_parts(1, N, T)) * R * 8);
   L.vpart = take(red * 8);
@@ -402,25 +401,28 @@ static int norm_side(const dna_opts* o, int side) {
   return side;
 }
 
-// One normalisation.  sump / sump2: SUM_PARTS x R doubles each; bal: R doubles.
+// One normalisation.  sump / sump2: SUM_PARTS x R doubles each.
 // With `emit`, the scale kernel also leaves the first level of the sums of the
 // factor of side norm_side(o, side) in `emitted` (W column sums for 0, H row
 // sums for 1).
 static dna_status run_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const dna_opts* o,
-                                double* sump, double* sump2, double* bal, int* chk, hipStream_t s, double* emit,
+                                double* sump, double* sump2, int* chk, hipStream_t s, double* emit,
                                 SumJob* emitted) {
   const int es = norm_side(o, side);
-  SumJob job;
-  if (o->rho > 0.f && o->lambda > 0.f) {
-    SumJob cj, gj;
+  SumJob cj, gj;
+  if (o->rho > 0.f && o->lambda > 0.f) {          // balanced: the scale kernel takes both factors' sums
     DNA_HIP(launch_colsum_part(W, N, R, sump, cj, s), "colsum_W");
     DNA_HIP(launch_rowsum_part(H, T, R, sump2, gj, s), "rowsum_H");
-    DNA_HIP(launch_balance(es, cj, gj, o->rho, o->lambda, bal, chk, job, s), "balance");
-  } else {
-    if (es == 0) DNA_HIP(launch_colsum_part(W, N, R, sump, job, s), "colsum_W");
-    else DNA_HIP(launch_rowsum_part(H, T, R, sump, job, s), "rowsum_H");
-    job.check = chk;
+    SumJob& mine = es == 0 ? cj : gj;
+    mine.check = chk;
+    DNA_HIP(launch_scale(es, W, H, N, T, R, mine, emit, emitted, s, es == 0 ? gj : cj,
+                         es == 0 ? o->rho : o->lambda, es == 0 ? o->lambda : o->rho), "scale");
+    return DNA_OK;
   }
+  SumJob& job = es == 0 ? cj : gj;
+  if (es == 0) DNA_HIP(launch_colsum_part(W, N, R, sump, job, s), "colsum_W");
+  else DNA_HIP(launch_rowsum_part(H, T, R, sump, job, s), "rowsum_H");
+  job.check = chk;
   DNA_HIP(launch_scale(es, W, H, N, T, R, job, emit, emitted, s), "scale");
   return DNA_OK;
 }
@@ -466,8 +468,8 @@ dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int
   if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
   Common c;
   DNA_TRY(prologue(nullptr, W, H, N, T, R, o, ws, ws_bytes, stream, c));
-  DNA_TRY(run_normalize(side, W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2),
-                        at<double>(ws, c.L.bal), c.chk, c.s, nullptr, nullptr));
+  DNA_TRY(run_normalize(side, W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2), c.chk, c.s,
+                        nullptr, nullptr));
   return epilogue(c);
 }
 
@@ -503,8 +505,8 @@ dna_status dna_update_W(const float* V, float* W, const float* H, int64_t N, int
 // and fixes the other factor's scale.
 static dna_status iterate_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
                                     const dna_opts* o, const Common& c, void* ws, SumJob& next, bool& valid) {
-  DNA_TRY(run_normalize(side, W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2),
-                        at<double>(ws, c.L.bal), c.chk, c.s, at<double>(ws, c.L.sume), &next));
+  DNA_TRY(run_normalize(side, W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2), c.chk, c.s,
+                        at<double>(ws, c.L.sume), &next));
   valid = norm_side(o, side) == side;
   return DNA_OK;
 }
@@ -581,12 +583,11 @@ dna_status mu_iterate(const float* V, float* W, float* H, int64_t N, int64_t T, 
   double* dcost = at<double>(ws, c.L.vpart);        // the with-cost outputs, not returned
   double* sp = at<double>(ws, c.L.sump);
   double* sp2 = at<double>(ws, c.L.sump2);
-  double* bal = at<double>(ws, c.L.bal);
   for (int it = 0; it < iters; ++it) {
     DNA_TRY(run_mu(0, V, W, H, N, T, R, with_cost, dcost, o, c, ws));
-    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 16
+    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 16
     DNA_TRY(run_mu(1, V, W, H, N, T, R, with_cost, dcost, o, c, ws));
-    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 29
+    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 29
   }
   return epilogue(c);
 }
@@ -759,8 +760,8 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
 // ---------------------------------------------------------------------------
 struct SpLayout {
   int64_t nseg;
-  size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, sump2, bal, vpart, cseg,
-      fseg, part, fpart, check, total;
+  size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, sump2, vpart, cseg, fseg,
+      part, fpart, check, total;
 };
 
 static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse_v* V) {
@@ -787,7 +788,6 @@ static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse
   L.g64 = take((size_t)R * 8);
   L.sump = take((size_t)SUM_PARTS * R * 8);
   L.sump2 = take((size_t)SUM_PARTS * R * 8);
-  L.bal = take((size_t)R * 8);
   L.vpart = take(mx * 8);
   L.cseg = take(3 * (size_t)L.nseg * 8);
   L.fseg = take((size_t)L.nseg * 4);
@@ -986,12 +986,11 @@ dna_status dna_sparse_mu_iterate(const dna_sparse_v* V, float* W, float* H, int6
   DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* sp = at<double>(ws, c.L.sump);
   double* sp2 = at<double>(ws, c.L.sump2);
-  double* bal = at<double>(ws, c.L.bal);
   for (int it = 0; it < iters; ++it) {
     DNA_TRY(sp_run_mu(0, V, W, H, N, T, R, o, c, ws));
-    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 16
+    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 16
     DNA_TRY(sp_run_mu(1, V, W, H, N, T, R, o, c, ws));
-    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 29
+    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 29
   }
   return sp_epilogue(c);
 }
@@ -1004,12 +1003,11 @@ dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H, int64_t
   DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* sp = at<double>(ws, c.L.sump);
   double* sp2 = at<double>(ws, c.L.sump2);
-  double* bal = at<double>(ws, c.L.bal);
   for (int it = 0; it < iters; ++it) {
     DNA_TRY(sp_half_step(0, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
-    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 16
+    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 16
     DNA_TRY(sp_half_step(1, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
-    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, bal, c.chk, c.s, nullptr, nullptr));   // step 29
+    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 29
   }
   return sp_epilogue(c);
 }

@@ -138,15 +138,14 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s);
 // the new H, cdiv(T, SC_TCHUNK) parts) and returns their second level in
 // `emitted`, for the half-step that follows.
 constexpr int SC_TCHUNK = 2048;
-// Normalisation factors of the balanced (rho, lambda > 0) normalisation into
-// f[R]; `job` becomes the one-part SumJob that launch_scale(side, ...) takes.
-hipError_t launch_balance(int side, const SumJob& cj, const SumJob& gj, double rho, double lam, double* f,
-                          int* check, SumJob& job, hipStream_t s);
 // out[0] += rho sum C + lambda sum G from the parts of C = W^t 1, G = H 1.
 hipError_t launch_penalty(const SumJob& cj, const SumJob& gj, double rho, double lam, double* out, hipStream_t s);
 int64_t scale_emit_parts(int side, int64_t N, int64_t T);
+// `other`, wj, wo: the balanced form (see k_scale); other.part == nullptr: the
+// unit-sum form.
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
-                        double* emit, SumJob* emitted, hipStream_t s);
+                        double* emit, SumJob* emitted, hipStream_t s, const SumJob& other = SumJob{},
+                        double wj = 0.0, double wo = 0.0);
 
 // Steps 2-5 and 10 in one kernel per half-step when R <= 64 (side 0: H step,
 // rows n split into `splits` chunks of `chunk`; side 1: W step, columns t split

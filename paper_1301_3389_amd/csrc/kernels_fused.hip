@@ -430,15 +430,18 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
       }
     }
     double s0[16], s1[16], s2[16];
+    int fsub = 0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       s0[v] = s1[v] = s2[v] = 0.0;
       const float x = vf[v];                      // 0 outside the matrix
-      flr[v] |= cost_acc(x, zn[v], dz[v], s0[v], s1[v], s2[v]);
+      const int f = cost_acc(x, zn[v], dz[v], s0[v], s1[v], s2[v]);
+      flr[v] |= f;
+      fsub |= f;
     }
     rs[0] += halfwave_slot_sum(s0, lane);
     rs[1] += halfwave_slot_sum(s1, lane);
-    rs[2] += halfwave_slot_sum(s2, lane);
+    if (__any(fsub)) rs[2] += halfwave_slot_sum(s2, lane);   // s2 is 0 unless an element flagged
     if (more)
 #pragma unroll
       for (int v = 0; v < 16; ++v) vf[v] = vn[v];

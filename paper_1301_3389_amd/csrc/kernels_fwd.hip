@@ -882,12 +882,27 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 // `emit`, the blocks of the normalised factor (W tiles for side 0, H chunks for
 // side 1) also write the float64 sum of the values they stored (an unchanged
 // column / row where f is not positive): emit[tile * R + r].
+//
+// With `o.part` (the balanced normalisation of eq. 2, both weights positive)
+// the other factor's sums come in `o` and f becomes sqrt(w_j * S_j / (w_o * S_o))
+// (S: the two sums, w: their eq. 2 weights; side 0: S_j = C with rho, S_o = G
+// with lambda; side 1 the reverse), so W column r is multiplied by
+// sqrt(lambda G_r / (rho C_r)) either way; a sum that is not positive leaves
+// the column / row unscaled and sets CHK_DOMAIN.
 constexpr int SC_W_PER = 64 * 64 / 256, SC_H_PER = SC_TCHUNK / 256;
+__device__ __forceinline__ double balance_factor(double sj, double so, double wj, double wo, int* check) {
+  if (sj > 0.0 && so > 0.0) return sqrt((wj * sj) / (wo * so));
+  if (check) atomicOr(check, CHK_DOMAIN);
+  return 0.0;
+}
+
 __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, float* __restrict__ H, int64_t N,
-                                               int64_t T, int64_t R, SumJob j, int64_t rtiles, int64_t wtiles,
-                                               int64_t tchunks, double* __restrict__ emit) {
+                                               int64_t T, int64_t R, SumJob j, SumJob o, double wj, double wo,
+                                               int64_t rtiles, int64_t wtiles, int64_t tchunks,
+                                               double* __restrict__ emit) {
   __shared__ double fs[64];
   __shared__ double red[4][64];
+  __shared__ double red2[4][64];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;
   if (b < wtiles) {
@@ -902,15 +917,25 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
     }
     {  // four groups of 64 threads add every fourth part, then one thread per r adds the groups
       const int g = tid >> 6;
-      double f = 0.0;
-      if (r < R)
+      double f = 0.0, f2 = 0.0;
+      if (r < R) {
         for (int p = g; p < j.nparts; p += 4) f += j.part[(int64_t)p * R + r];
+        if (o.part)
+          for (int p = g; p < o.nparts; p += 4) f2 += o.part[(int64_t)p * R + r];
+      }
       red[g][tid & 63] = f;
+      red2[g][tid & 63] = f2;
     }
     __syncthreads();
     if (tid < 64) {
-      const double f = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-      if (j.check && rt * 64 + tid < R && !(f > 0.0)) atomicOr(j.check, CHK_DOMAIN);
+      double f = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+      const bool in = rt * 64 + tid < R;
+      if (o.part) {
+        const double f2 = (red2[0][tid] + red2[1][tid]) + (red2[2][tid] + red2[3][tid]);
+        f = in ? balance_factor(f, f2, wj, wo, j.check) : 0.0;
+      } else if (j.check && in && !(f > 0.0)) {
+        atomicOr(j.check, CHK_DOMAIN);
+      }
       fs[tid] = f;
     }
     __syncthreads();
@@ -944,6 +969,12 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
       double f = tid < j.nparts ? j.part[(int64_t)tid * R + r] : 0.0;
       for (int p = tid + 64; p < j.nparts; p += 64) f += j.part[(int64_t)p * R + r];
       f = wave_sum(f);
+      if (o.part) {
+        double f2 = tid < o.nparts ? o.part[(int64_t)tid * R + r] : 0.0;
+        for (int p = tid + 64; p < o.nparts; p += 64) f2 += o.part[(int64_t)p * R + r];
+        f2 = wave_sum(f2);
+        if (tid == 0) f = balance_factor(f, f2, wj, wo, nullptr);   // the W tiles report
+      }
       if (tid == 0) fs[0] = f;
     }
     __syncthreads();
@@ -965,34 +996,6 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
       if (tid == 0) emit[ch * R + r] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
     }
   }
-}
-
-// Balanced normalisation factors (eq. 2 with rho, lambda > 0): with C = W^t 1
-// and G = H 1 finished from their parts, f_r = sqrt(rho C_r / (lambda G_r)) for
-// side 0 (k_scale then divides W column r by f_r and multiplies H row r by it)
-// and its reciprocal for side 1; either way W column r is multiplied by
-// s_r = sqrt(lambda G_r / (rho C_r)).  A sum that is not positive gives f_r = 0,
-// which k_scale leaves unscaled, and sets CHK_DOMAIN.
-__global__ __launch_bounds__(256) void k_balance(int side, SumJob cj, SumJob gj, double rho, double lam,
-                                                 double* __restrict__ f, int* check) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= cj.R) return;
-  double C = 0.0, G = 0.0;
-  for (int p = 0; p < cj.nparts; ++p) C += cj.part[(int64_t)p * cj.R + r];
-  for (int p = 0; p < gj.nparts; ++p) G += gj.part[(int64_t)p * gj.R + r];
-  double v = 0.0;
-  if (C > 0.0 && G > 0.0) v = side == 0 ? sqrt((rho * C) / (lam * G)) : sqrt((lam * G) / (rho * C));
-  else if (check) atomicOr(check, CHK_DOMAIN);
-  f[r] = v;
-}
-
-hipError_t launch_balance(int side, const SumJob& cj, const SumJob& gj, double rho, double lam, double* f,
-                          int* check, SumJob& job, hipStream_t s) {
-  prof_begin("balance", s);
-  hipLaunchKernelGGL(k_balance, dim3((unsigned)cdiv(cj.R, 256)), dim3(256), 0, s, side, cj, gj, rho, lam, f, check);
-  prof_end("balance", s);
-  job = SumJob{f, 1, cj.R, nullptr, nullptr, nullptr};
-  return hipGetLastError();
 }
 
 // out[0] += rho sum_r C_r + lambda sum_r G_r (the penalty of eq. 2), C and G
@@ -1025,12 +1028,12 @@ int64_t scale_emit_parts(int side, int64_t N, int64_t T) {
 }
 
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
-                        double* emit, SumJob* emitted, hipStream_t s) {
+                        double* emit, SumJob* emitted, hipStream_t s, const SumJob& other, double wj, double wo) {
   const int64_t rtiles = cdiv(R, 64), wtiles = rtiles * cdiv(N, 64), tchunks = cdiv(T, SC_TCHUNK);
   const int64_t blocks = wtiles + R * tchunks;
   prof_begin("scale", s);
-  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, rtiles, wtiles,
-                     tchunks, emit);
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, other, wj, wo,
+                     rtiles, wtiles, tchunks, emit);
   prof_end("scale", s);
   if (emit && emitted) *emitted = SumJob{emit, (int)scale_emit_parts(side, N, T), R, nullptr, nullptr, nullptr};
   return hipGetLastError();
