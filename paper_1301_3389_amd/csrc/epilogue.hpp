@@ -132,6 +132,25 @@ __device__ __forceinline__ int cost_acc(float x, float zN, float dz, double& s0,
   return fl;
 }
 
+// cost_acc with the first two terms added to float32 accumulators (a caller
+// that flushes them to float64 every few elements).
+__device__ __forceinline__ int cost_acc_f(float x, float zN, float dz, float& a0, float& a1, double& s2) {
+  const float zM = zN + dz;
+  const bool pos = x > 0.f;
+  const bool okN = zN > 0.f, okM = zM > 0.f;
+  const float izN = __builtin_amdgcn_rcpf(zN);
+  const float l0 = log2_hw((pos && okN) ? x * izN : 1.f);
+  const float l1 = log2_1p((pos && okN && okM) ? dz * izN : 0.f);
+  a0 += x * l0;
+  a1 -= x * l1;
+  int fl = 0;
+  if (pos && !(okN && okM)) {
+    fl = (okN ? 0 : 1) | (okM ? 0 : 2);
+    if (!okN && okM) s2 += xlog2x_over(x, zM);
+  }
+  return fl;
+}
+
 // ---------------------------------------------------------------------------
 // Epilogues of the candidate-cost passes (steps 7-9, 12-14), shared by the fp32
 // and 16-bit kernels.  acc[..][0] holds z_DNA, acc[..][1] holds dZ = z_MU - z_DNA

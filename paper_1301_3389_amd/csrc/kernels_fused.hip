@@ -399,6 +399,13 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
   int flr[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) flr[v] = 0;
+  // d_DNA and margin terms of up to CW_GROUP sub-tiles add up per element in
+  // float32 before one float64 half-wave reduction
+  constexpr int CW_GROUP = 4;
+  float a0[16], a1[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) a0[v] = a1[v] = 0.f;
+  int ng = 0;
   f32x4 hr[4];
   float vf[16];
   fetch_block(H, T, 0, tb0, R, T, hr, tid);
@@ -429,19 +436,29 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
         }
       }
     }
-    double s0[16], s1[16], s2[16];
+    double s2[16];
     int fsub = 0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      s0[v] = s1[v] = s2[v] = 0.0;
+      s2[v] = 0.0;
       const float x = vf[v];                      // 0 outside the matrix
-      const int f = cost_acc(x, zn[v], dz[v], s0[v], s1[v], s2[v]);
+      const int f = cost_acc_f(x, zn[v], dz[v], a0[v], a1[v], s2[v]);
       flr[v] |= f;
       fsub |= f;
     }
-    rs[0] += halfwave_slot_sum(s0, lane);
-    rs[1] += halfwave_slot_sum(s1, lane);
     if (__any(fsub)) rs[2] += halfwave_slot_sum(s2, lane);   // s2 is 0 unless an element flagged
+    if (++ng == CW_GROUP || !more) {
+      double s0[16], s1[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        s0[v] = (double)a0[v];
+        s1[v] = (double)a1[v];
+        a0[v] = a1[v] = 0.f;
+      }
+      rs[0] += halfwave_slot_sum(s0, lane);
+      rs[1] += halfwave_slot_sum(s1, lane);
+      ng = 0;
+    }
     if (more)
 #pragma unroll
       for (int v = 0; v < 16; ++v) vf[v] = vn[v];
