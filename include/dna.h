@@ -229,7 +229,10 @@ dna_status dna_sparse_mu_iterate(const dna_sparse_v* V, float* W, float* H,
                                  const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* `iters` full iterations (dna_sparse_update_H, dna_normalize(1),
- * dna_sparse_update_W, dna_normalize(0)) in place.  iters < 0: DNA_EINVAL. */
+ * dna_sparse_update_W, dna_normalize(0)) in place.  As in dna_iterate, each
+ * normalisation hands the partial sums of the factor it rescaled to the next
+ * half-step when they are that step's divisor, so results equal the separate
+ * calls up to the order of those float64 sums.  iters < 0: DNA_EINVAL. */
 dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H,
                               int64_t N, int64_t T, int64_t R, int iters,
                               const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);

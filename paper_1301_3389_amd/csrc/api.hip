@@ -760,8 +760,8 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
 // ---------------------------------------------------------------------------
 struct SpLayout {
   int64_t nseg;
-  size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, sump2, vpart, cseg, fseg,
-      part, fpart, check, total;
+  size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, sump2, sume, vpart, cseg,
+      fseg, part, fpart, check, total;
 };
 
 static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse_v* V) {
@@ -788,6 +788,7 @@ static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse
   L.g64 = take((size_t)R * 8);
   L.sump = take((size_t)SUM_PARTS * R * 8);
   L.sump2 = take((size_t)SUM_PARTS * R * 8);
+  L.sume = take((size_t)std::max(scale_emit_parts(0, N, T), scale_emit_parts(1, N, T)) * R * 8);
   L.vpart = take(mx * 8);
   L.cseg = take(3 * (size_t)L.nseg * 8);
   L.fseg = take((size_t)L.nseg * 4);
@@ -846,9 +847,11 @@ static dna_status sp_epilogue(const SpCommon& c) {
 }
 
 // One sparse half-step: side 0 updates H (R x T) given W, side 1 updates W.
+// `pre`, if given, holds the first level of c (side 0) / g (side 1) already
+// written by the preceding normalisation.
 static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
                                const dna_opts* o, const SpCommon& c, void* ws, uint8_t* mask, double* dsel,
-                               double* margin) {
+                               double* margin, const SumJob* pre = nullptr) {
   const SpLayout& L = c.L;
   const SpV v = sp_view(V);
   float* Ht = at<float>(ws, L.ht);
@@ -867,7 +870,8 @@ static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float*
   int* fpart = at<int>(ws, L.fpart);
   DNA_HIP(launch_sp_transpose(H, Ht, R, T, c.s), "sp_transpose H");
   SumJob job;
-  if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
+  if (pre) job = *pre;
+  else if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
   else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
   job.s64 = c64; job.s32 = c32; job.check = c.chk;  // c = W^t 1 (side 0) or g = H 1 (side 1)
   job.reg = side == 0 ? o->lambda : o->rho;         // c32 = c + lambda or g + rho; c64 without
@@ -1003,11 +1007,16 @@ dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H, int64_t
   DNA_TRY(sp_prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   double* sp = at<double>(ws, c.L.sump);
   double* sp2 = at<double>(ws, c.L.sump2);
+  double* se = at<double>(ws, c.L.sume);
+  SumJob next;                                      // sums emitted by a normalisation (as in dna_iterate)
+  bool have = false;
   for (int it = 0; it < iters; ++it) {
-    DNA_TRY(sp_half_step(0, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
-    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 16
-    DNA_TRY(sp_half_step(1, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr));
-    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, c.chk, c.s, nullptr, nullptr));   // step 29
+    DNA_TRY(sp_half_step(0, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr, have ? &next : nullptr));
+    DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, c.chk, c.s, se, &next));           // step 16
+    have = norm_side(o, 1) == 1;
+    DNA_TRY(sp_half_step(1, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr, have ? &next : nullptr));
+    DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, c.chk, c.s, se, &next));           // step 29
+    have = norm_side(o, 0) == 0;
   }
   return sp_epilogue(c);
 }

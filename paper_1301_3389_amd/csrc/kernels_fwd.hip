@@ -556,12 +556,75 @@ __global__ __launch_bounds__(256) void k_cand_W(const float* __restrict__ W, con
   }
 }
 
+// Few splits (at most 4, e.g. the sparse path's one): a wave per row, four rows
+// per block.  The split sums are added in the four-wave form's order
+// ((s0 + s1) + (s2 + s3)), so the results equal k_cand_W's bit for bit.
+template <int RPW>
+__global__ __launch_bounds__(256) void k_cand_W_rows(const float* __restrict__ W, const float* __restrict__ pu,
+                                                     const float* __restrict__ puc, const float* __restrict__ py,
+                                                     int splits, const float* __restrict__ g,
+                                                     const double* __restrict__ vpart, int tiles_n, int64_t N,
+                                                     int64_t R, float eps, float alpha, float reg,
+                                                     float* __restrict__ Xmu, float* __restrict__ Xn,
+                                                     float* __restrict__ Aout, float* __restrict__ Bout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= N) return;
+  double den = 0.0;
+  float keep[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int64_t r = lane + 64 * i;
+    keep[i] = 0.f;
+    if (r < R) {
+      float u[4], uc[4], y[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        u[w] = uc[w] = y[w] = 0.f;
+        if (w < splits) {
+          const int64_t o = ((int64_t)w * N + n) * R + r;
+          u[w] += pu[o];
+          uc[w] += puc[o];
+          y[w] += py[o];
+        }
+      }
+      const float uu = (u[0] + u[1]) + (u[2] + u[3]);
+      const float ucc = (uc[0] + uc[1]) + (uc[2] + uc[3]);
+      const float yy = (y[0] + y[1]) + (y[2] + y[3]);
+      const Cand k = candidate(W[n * R + r], uu, ucc, yy, g[r], eps, alpha, reg);
+      Xmu[n * R + r] = k.mu;
+      keep[i] = k.newton;
+      if (Aout) Aout[n * R + r] = k.A;
+      if (Bout) Bout[n * R + r] = k.B;
+      den += (double)g[r] * (double)k.newton;
+    }
+  }
+  double s = 0.0;
+  for (int64_t m = lane; m < tiles_n; m += 64) s += vpart[m * N + n];
+  s = wave_sum(s);
+  den = __shfl(wave_sum(den), 0);
+  const double f = den > 0.0 ? s / den : 1.0;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int64_t r = lane + 64 * i;
+    if (r < R) Xn[n * R + r] = fmaxf((float)((double)keep[i] * f), VALUE_FLOOR);
+  }
+}
+
 hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, const float* py, int splits, const float* g,
                          const double* vpart, int tiles_n, int64_t N, int64_t R, float eps, float alpha, float reg,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_W", s);
   const dim3 grid((unsigned)N);
-  if (R <= 64)
+  if (splits <= 4 && R <= 128) {
+    const dim3 g4((unsigned)cdiv(N, 4));
+    if (R <= 64)
+      hipLaunchKernelGGL(k_cand_W_rows<1>, g4, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R,
+                         eps, alpha, reg, Xmu, Xn, Aout, Bout);
+    else
+      hipLaunchKernelGGL(k_cand_W_rows<2>, g4, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R,
+                         eps, alpha, reg, Xmu, Xn, Aout, Bout);
+  } else if (R <= 64)
     hipLaunchKernelGGL(k_cand_W<1>, grid, dim3(256), 0, s, W, pu, puc, py, splits, g, vpart, tiles_n, N, R, eps,
                        alpha, reg, Xmu, Xn, Aout, Bout);
   else if (R <= 128)
@@ -704,6 +767,7 @@ hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const
   return hipGetLastError();
 }
 
+// A wave per row (four rows per block): the lanes add the tile partials.
 __global__ __launch_bounds__(256) void k_select_W(const float* __restrict__ Xmu, const float* __restrict__ Xn,
                                                   float* __restrict__ Wout,
                                                   const double* part, const int* fpart, int tiles,
@@ -737,12 +801,57 @@ __global__ __launch_bounds__(256) void k_select_W(const float* __restrict__ Xmu,
   for (int64_t r = lane; r < R; r += 64) Wout[n * R + r] = src[n * R + r];
 }
 
+// Few tile partials (at most SEL_FEW, e.g. the sparse path's one): SEL_ROWS
+// rows per block, one thread per row adds its partials in order and decides;
+// then each wave copies every fourth of the block's rows.
+constexpr int SEL_ROWS = 64, SEL_FEW = 4;
+__global__ __launch_bounds__(256) void k_select_W_rows(const float* __restrict__ Xmu, const float* __restrict__ Xn,
+                                                       float* __restrict__ Wout,
+                                                       const double* part, const int* fpart, int tiles,
+                                                       int64_t N, int64_t R, uint8_t* mask, double* dsel,
+                                                       double* margin) {
+  __shared__ int pick[SEL_ROWS];
+  const int tid = threadIdx.x;
+  const int64_t n0 = (int64_t)blockIdx.x * SEL_ROWS;
+  if (tid < SEL_ROWS && n0 + tid < N) {
+    const int64_t n = n0 + tid;
+    const int64_t stride = (int64_t)tiles * N;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    int fl = 0;
+    for (int m = 0; m < tiles; ++m) {
+      const int64_t o = (int64_t)m * N + n;
+      q0 += part[o];
+      q1 += part[stride + o];
+      q2 += part[2 * stride + o];
+      fl |= fpart[o];
+    }
+    double ds, mg;
+    const bool nw = decide(q0, q1, q2, fl, ds, mg);
+    if (mask) mask[n] = nw ? 1 : 0;
+    if (dsel) dsel[n] = ds;
+    if (margin) margin[n] = mg;
+    pick[tid] = nw ? 1 : 0;
+  }
+  __syncthreads();
+  const int64_t rows = std::min<int64_t>(SEL_ROWS, N - n0);
+  const int lane = tid & 63;
+  for (int64_t nl = tid >> 6; nl < rows; nl += 4) {
+    const int64_t o = (n0 + nl) * R;
+    const float* src = pick[nl] ? Xn : Xmu;
+    for (int64_t r = lane; r < R; r += 64) Wout[o + r] = src[o + r];
+  }
+}
+
 hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const double* part,
                            const int* fpart, int tiles_n, int64_t N, int64_t R, uint8_t* mask,
                            double* dsel, double* margin, hipStream_t s) {
   prof_begin("select_W", s);
-  hipLaunchKernelGGL(k_select_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, Xmu, Xn, Wout, part, fpart,
-                     tiles_n, N, R, mask, dsel, margin);
+  if (tiles_n <= SEL_FEW)
+    hipLaunchKernelGGL(k_select_W_rows, dim3((unsigned)cdiv(N, SEL_ROWS)), dim3(256), 0, s, Xmu, Xn, Wout, part,
+                       fpart, tiles_n, N, R, mask, dsel, margin);
+  else
+    hipLaunchKernelGGL(k_select_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, Xmu, Xn, Wout, part, fpart,
+                       tiles_n, N, R, mask, dsel, margin);
   prof_end("select_W", s);
   return hipGetLastError();
 }
@@ -811,21 +920,29 @@ hipError_t launch_mu_W(float* W, const float* pu, int splits, const float* g, in
 // Column sums of W (N x R) and row sums of H (R x T), each in two fixed-order
 // levels: `nparts` blocks per column / row write partial float64 sums to
 // part[p][r]; the second level adds the parts in order (sum_job).
-__global__ __launch_bounds__(256) void k_colsum_part(const float* W, int64_t N, int64_t R, int64_t rows,
-                                                     double* part) {
-  __shared__ double red[4][64];
+// 64 columns x CS_RG row groups per block (tall W with few parts keeps more
+// loads in flight per block); the row groups are added in a fixed tree.
+constexpr int CS_RG = 16;
+__global__ __launch_bounds__(64 * CS_RG) void k_colsum_part(const float* W, int64_t N, int64_t R, int64_t rows,
+                                                           double* part) {
+  __shared__ double red[CS_RG][64];
   const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
   const int64_t r = (int64_t)blockIdx.x * 64 + cl;
   const int64_t p = blockIdx.y;
   const int64_t n1 = std::min<int64_t>(N, (p + 1) * rows);
   double s = 0.0;
   if (r < R) {
-#pragma unroll 16
-    for (int64_t n = p * rows + rg; n < n1; n += 4) s += (double)W[n * R + r];
+#pragma unroll 8
+    for (int64_t n = p * rows + rg; n < n1; n += CS_RG) s += (double)W[n * R + r];
   }
   red[rg][cl] = s;
   __syncthreads();
-  if (rg == 0 && r < R) part[p * R + r] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+#pragma unroll
+  for (int h = CS_RG / 2; h >= 1; h >>= 1) {
+    if (rg < h) red[rg][cl] += red[rg + h][cl];
+    __syncthreads();
+  }
+  if (rg == 0 && r < R) part[p * R + r] = red[0][cl];
 }
 
 __global__ __launch_bounds__(256) void k_rowsum_part(const float* H, int64_t T, int64_t R, int64_t cols,
@@ -849,8 +966,8 @@ hipError_t launch_colsum_part(const float* W, int64_t N, int64_t R, double* part
   const int64_t nparts = std::min<int64_t>(SUM_PARTS, cdiv(N, 64));
   const int64_t rows = cdiv(N, nparts);
   prof_begin("colsum_W", s);
-  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)cdiv(R, 64), (unsigned)nparts), dim3(256), 0, s, W, N, R,
-                     rows, part);
+  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)cdiv(R, 64), (unsigned)nparts), dim3(64 * CS_RG), 0, s, W, N,
+                     R, rows, part);
   prof_end("colsum_W", s);
   job = SumJob{part, (int)nparts, R, nullptr, nullptr, nullptr};
   return hipGetLastError();
