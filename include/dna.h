@@ -231,8 +231,11 @@ dna_status dna_sparse_mu_iterate(const dna_sparse_v* V, float* W, float* H,
 /* `iters` full iterations (dna_sparse_update_H, dna_normalize(1),
  * dna_sparse_update_W, dna_normalize(0)) in place.  As in dna_iterate, each
  * normalisation hands the partial sums of the factor it rescaled to the next
- * half-step when they are that step's divisor, so results equal the separate
- * calls up to the order of those float64 sums.  iters < 0: DNA_EINVAL. */
+ * half-step when they are that step's divisor.  As Algorithm 1 does (steps 15,
+ * 28), each half-step after the first takes Z at the nonzeros from the
+ * candidate the preceding selection kept (the normalisation between leaves
+ * W H unchanged) instead of forming it again from the factors.  Results equal
+ * the separate calls up to float rounding.  iters < 0: DNA_EINVAL. */
 dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H,
                               int64_t N, int64_t T, int64_t R, int iters,
                               const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);

@@ -761,7 +761,7 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
 struct SpLayout {
   int64_t nseg;
   size_t ht, q, qb, gp, vseg, pu, puc, py, xmu, xn, xd, xnt, xdt, c32, c64, g64, sump, sump2, sume, vpart, cseg,
-      fseg, part, fpart, check, total;
+      fseg, part, fpart, zc, dzc, smask, check, total;
 };
 
 static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse_v* V) {
@@ -794,6 +794,10 @@ static SpLayout make_sp_layout(int64_t N, int64_t T, int64_t R, const dna_sparse
   L.fseg = take((size_t)L.nseg * 4);
   L.part = take(3 * mx * 8);
   L.fpart = take(mx * 4);
+  // the reconstruction a half-step's cost pass leaves for the next one
+  L.zc = take(nnz * 4);
+  L.dzc = take(nnz * 4);
+  L.smask = take(mx);
   L.check = take(16);
   L.total = off;
   return L;
@@ -848,10 +852,14 @@ static dna_status sp_epilogue(const SpCommon& c) {
 
 // One sparse half-step: side 0 updates H (R x T) given W, side 1 updates W.
 // `pre`, if given, holds the first level of c (side 0) / g (side 1) already
-// written by the preceding normalisation.
+// written by the preceding normalisation.  carry_in >= 0: the preceding
+// half-step (of side carry_in) left its reconstruction at the nonzeros and its
+// selection mask in the workspace, and Q, Q-bar come from them instead of new
+// dot products; carry_out: leave this step's for the next one.
 static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
                                const dna_opts* o, const SpCommon& c, void* ws, uint8_t* mask, double* dsel,
-                               double* margin, const SumJob* pre = nullptr) {
+                               double* margin, const SumJob* pre = nullptr, int carry_in = -1,
+                               bool carry_out = false) {
   const SpLayout& L = c.L;
   const SpV v = sp_view(V);
   float* Ht = at<float>(ws, L.ht);
@@ -868,14 +876,24 @@ static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float*
   double* vpart = at<double>(ws, L.vpart);
   double* part = at<double>(ws, L.part);
   int* fpart = at<int>(ws, L.fpart);
-  DNA_HIP(launch_sp_transpose(H, Ht, R, T, c.s), "sp_transpose H");
+  if (side == 1 || carry_in < 0)                    // H^t: the W step's factor rows and the fresh Z
+    DNA_HIP(launch_sp_transpose(H, Ht, R, T, c.s), "sp_transpose H");
   SumJob job;
   if (pre) job = *pre;
   else if (side == 0) DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
   else DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
   job.s64 = c64; job.s32 = c32; job.check = c.chk;  // c = W^t 1 (side 0) or g = H 1 (side 1)
   job.reg = side == 0 ? o->lambda : o->rho;         // c32 = c + lambda or g + rho; c64 without
-  DNA_HIP(launch_sp_zq(v, W, Ht, N, T, R, q, qb, c.chk, job, c.s), "sp_zq");
+  float* zc = at<float>(ws, L.zc);
+  float* dzc = at<float>(ws, L.dzc);
+  uint8_t* smask = at<uint8_t>(ws, L.smask);
+  if (carry_in >= 0)
+    DNA_HIP(launch_sp_qz(v, zc, dzc, smask, carry_in, N, T, q, qb, c.chk, job, c.s), "sp_qz");
+  else
+    DNA_HIP(launch_sp_zq(v, W, Ht, N, T, R, q, qb, c.chk, job, c.s), "sp_zq");
+  if (carry_out && !mask) mask = smask;
+  float* zo = carry_out ? zc : nullptr;
+  float* dzo = carry_out ? dzc : nullptr;
   DNA_HIP(launch_sp_grad(side, false, v, side == 0 ? W : Ht, q, qb, c64, N, T, R, at<float>(ws, L.gp),
                          at<double>(ws, L.vseg), pu, puc, py, vpart, c.s), "sp_grad");
   if (side == 0) {
@@ -887,14 +905,14 @@ static dna_status sp_half_step(int side, const dna_sparse_v* V, float* W, float*
     DNA_HIP(launch_sp_transpose(Xn, XnT, R, T, c.s), "sp_transpose X_DNA");
     DNA_HIP(launch_sp_transpose(Xd, XdT, R, T, c.s), "sp_transpose X_MU - X_DNA");
     DNA_HIP(launch_sp_cost(0, v, W, XnT, XdT, N, T, R, at<double>(ws, L.cseg), at<int>(ws, L.fseg), part, fpart,
-                           c.s), "sp_cost_H");
+                           c.s, zo, dzo), "sp_cost_H");
     DNA_HIP(launch_select_H(Xmu, Xn, H, part, fpart, 1, T, R, mask, dsel, margin, c.s), "select_H");
   } else {
     DNA_HIP(launch_cand_W(W, pu, puc, py, 1, c32, vpart, 1, N, R, o->eps, o->alpha, o->rho, Xmu, Xn, nullptr,
                           nullptr, c.s), "cand_W");
     DNA_HIP(launch_sp_diff(Xmu, Xn, Xd, N * R, c.s), "sp_diff");
     DNA_HIP(launch_sp_cost(1, v, Ht, Xn, Xd, N, T, R, at<double>(ws, L.cseg), at<int>(ws, L.fseg), part, fpart,
-                           c.s), "sp_cost_W");
+                           c.s, zo, dzo), "sp_cost_W");
     DNA_HIP(launch_select_W(Xmu, Xn, W, part, fpart, 1, N, R, mask, dsel, margin, c.s), "select_W");
   }
   return DNA_OK;
@@ -1010,11 +1028,13 @@ dna_status dna_sparse_iterate(const dna_sparse_v* V, float* W, float* H, int64_t
   double* se = at<double>(ws, c.L.sume);
   SumJob next;                                      // sums emitted by a normalisation (as in dna_iterate)
   bool have = false;
-  for (int it = 0; it < iters; ++it) {
-    DNA_TRY(sp_half_step(0, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr, have ? &next : nullptr));
+  for (int it = 0; it < iters; ++it) {                // Z carried from each selection to the next half-step
+    DNA_TRY(sp_half_step(0, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr, have ? &next : nullptr,
+                         it > 0 ? 1 : -1, true));
     DNA_TRY(run_normalize(1, W, H, N, T, R, o, sp, sp2, c.chk, c.s, se, &next));           // step 16
     have = norm_side(o, 1) == 1;
-    DNA_TRY(sp_half_step(1, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr, have ? &next : nullptr));
+    DNA_TRY(sp_half_step(1, V, W, H, N, T, R, o, c, ws, nullptr, nullptr, nullptr, have ? &next : nullptr, 0,
+                         it + 1 < iters));
     DNA_TRY(run_normalize(0, W, H, N, T, R, o, sp, sp2, c.chk, c.s, se, &next));           // step 29
     have = norm_side(o, 0) == 0;
   }

@@ -83,12 +83,29 @@ __device__ __forceinline__ void fetch_v(const float* V, int64_t N, int64_t T, in
   }
 }
 
+// The same two loads for a block known to lie inside the matrix (no tests).
+__device__ __forceinline__ void fetch_block_in(const float* X, int64_t ld, int64_t r0, int64_t c0, f32x4 (&x)[4],
+                                               int tid) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int f = tid + i * 256;
+    x[i] = *reinterpret_cast<const f32x4*>(X + (r0 + f / 16) * ld + c0 + (f % 16) * 4);
+  }
+}
+__device__ __forceinline__ void fetch_v_in(const float* V, int64_t T, int64_t n0, int64_t t0, int lane,
+                                           float (&vf)[16]) {
+  const float* p = V + (n0 + (lane >> 5) * 4) * T + t0 + (lane & 31);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) vf[v] = p[(int64_t)((v >> 2) * 8 + (v & 3)) * T];
+}
+
 // ---------------------------------------------------------------------------
 // H step.  LDS: lh = H block [r][t] (whole kernel), lw = W rows [n][r],
 // lq = Q and Q-bar [n][t] (per sub-tile).
 //   phase 1: Z[n][t] = sum_r lw[n][r] lh[r][t]      (wave block n = wm, t = wn)
 //   phase 2: acc[r][t] += sum_n lw[n][r] {Q, Q - 1, lw[n][r] Q-bar}[n][t]  (r = wm, t = wn)
 // ---------------------------------------------------------------------------
+template <bool CHK>
 __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W, const float* H, int64_t N,
                                                   int64_t T, int64_t R, int64_t nchunk, float* pu, float* puc,
                                                   float* py, double* vpart, SumJob fin, int* check) {
@@ -119,13 +136,20 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   float vf[16];
   fetch_block(W, R, nb0, 0, N, R, wr, tid);
   fetch_v(V, N, T, nb0 + wm * 32, t0 + wn * 32, lane, vf);
+  // sub-tiles inside the matrix (all 64 columns t, R = 64, aligned W rows) load without tests
+  const bool cols_in = t0 + 64 <= T && R == 64 && (reinterpret_cast<uintptr_t>(W) & 15) == 0;
   for (int64_t nb = nb0; nb < nb1; nb += 64) {
     store_block(lw, wr, tid);
     float vn[16];
     const bool more = nb + 64 < nb1;
     if (more) {                                   // next sub-tile, in flight from here
-      fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
-      fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+      if (cols_in && nb + 128 <= N) {
+        fetch_block_in(W, R, nb + 64, 0, wr, tid);
+        fetch_v_in(V, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+      } else {
+        fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
+        fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+      }
     }
     __syncthreads();                              // lw (and lh) ready; lq free
     f32x16 z;
@@ -142,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       const float x = vf[v];                      // 0 outside the matrix
       const float iz = __builtin_amdgcn_rcpf(z[v]);
       const float q = x > 0.f ? x * iz : 0.f;
-      bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
+      if (CHK) bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
       lq[0][rl * FP + cl] = q;
       lq[1][rl * FP + cl] = x > 0.f ? q * iz : 0.f;   // padding has z = 0: no 0 * inf
       cp[0][0] += (double)x;
@@ -175,7 +199,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   reduce_cols<GF, 1>(cp, reinterpret_cast<double*>(lw), [&](int c, const double (&s)[1]) {
     if (t0 + c < T) vpart[sp * T + t0 + c] = s[0];
   });
-  if (check && bad) atomicOr(check, CHK_DOMAIN);
+  if (CHK && bad) atomicOr(check, CHK_DOMAIN);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,6 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
 //   phase 1: Z[n][t] = sum_r lw[n][r] lh[r][t]      (wave block n = wm, t = wn)
 //   phase 2: acc[n][r] += sum_t {Q, Q - 1, Q-bar lh[r][t]}[n][t] lh[r][t]  (n = wm, r = wn)
 // ---------------------------------------------------------------------------
+template <bool CHK>
 __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W, const float* H, int64_t N,
                                                   int64_t T, int64_t R, int64_t tchunk, float* pu, float* puc,
                                                   float* py, double* vpart, SumJob fin, int* check) {
@@ -214,13 +239,20 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   float vf[16];
   fetch_block(H, T, 0, tb0, R, T, hr, tid);
   fetch_v(V, N, T, n0 + wm * 32, tb0 + wn * 32, lane, vf);
+  // sub-tiles inside the matrix (all 64 rows n, R = 64, aligned H rows) load without tests
+  const bool rows_in = n0 + 64 <= N && R == 64 && (T & 3) == 0 && (reinterpret_cast<uintptr_t>(H) & 15) == 0;
   for (int64_t tb = tb0; tb < tb1; tb += 64) {
     store_block(lh, hr, tid);
     const bool more = tb + 64 < tb1;
     float vn[16];
     if (more) {                                   // next sub-tile, in flight from here
-      fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
-      fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+      if (rows_in && tb + 128 <= T) {
+        fetch_block_in(H, T, 0, tb + 64, hr, tid);
+        fetch_v_in(V, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+      } else {
+        fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
+        fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+      }
     }
     __syncthreads();
     f32x16 z;
@@ -241,7 +273,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       const float x = vf[v];                      // 0 outside the matrix
       const float iz = __builtin_amdgcn_rcpf(z[v]);
       const float q = x > 0.f ? x * iz : 0.f;
-      bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
+      if (CHK) bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
       lq[0][rl * FP + tl] = q;
       lq[1][rl * FP + tl] = x > 0.f ? q * iz : 0.f;
       rp[0][0][v] += (double)x;
@@ -280,7 +312,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   reduce_rows<GF, 1>(rp, reinterpret_cast<double*>(lw), [&](int r, const double (&s)[1]) {
     if (n0 + r < N) vpart[sp * N + n0 + r] = s[0];
   });
-  if (check && bad) atomicOr(check, CHK_DOMAIN);
+  if (CHK && bad) atomicOr(check, CHK_DOMAIN);
 }
 
 // ---------------------------------------------------------------------------
@@ -322,13 +354,20 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
   float vf[16];
   fetch_block(W, R, nb0, 0, N, R, wr, tid);
   fetch_v(V, N, T, nb0 + wm * 32, t0 + wn * 32, lane, vf);
+  // sub-tiles inside the matrix (all 64 columns t, R = 64, aligned W rows) load without tests
+  const bool cols_in = t0 + 64 <= T && R == 64 && (reinterpret_cast<uintptr_t>(W) & 15) == 0;
   for (int64_t nb = nb0; nb < nb1; nb += 64) {
     store_block(lw, wr, tid);
     float vn[16];
     const bool more = nb + 64 < nb1;
     if (more) {                                   // next sub-tile, in flight from here
-      fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
-      fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+      if (cols_in && nb + 128 <= N) {
+        fetch_block_in(W, R, nb + 64, 0, wr, tid);
+        fetch_v_in(V, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+      } else {
+        fetch_block(W, R, nb + 64, 0, N, R, wr, tid);
+        fetch_v(V, N, T, nb + 64 + wm * 32, t0 + wn * 32, lane, vn);
+      }
     }
     __syncthreads();
     f32x16 zn, dz;
@@ -410,13 +449,20 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
   float vf[16];
   fetch_block(H, T, 0, tb0, R, T, hr, tid);
   fetch_v(V, N, T, n0 + wm * 32, tb0 + wn * 32, lane, vf);
+  // sub-tiles inside the matrix (all 64 rows n, R = 64, aligned H rows) load without tests
+  const bool rows_in = n0 + 64 <= N && R == 64 && (T & 3) == 0 && (reinterpret_cast<uintptr_t>(H) & 15) == 0;
   for (int64_t tb = tb0; tb < tb1; tb += 64) {
     store_block(lh, hr, tid);
     float vn[16];
     const bool more = tb + 64 < tb1;
     if (more) {                                   // next sub-tile, in flight from here
-      fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
-      fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+      if (rows_in && tb + 128 <= T) {
+        fetch_block_in(H, T, 0, tb + 64, hr, tid);
+        fetch_v_in(V, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+      } else {
+        fetch_block(H, T, 0, tb + 64, R, T, hr, tid);
+        fetch_v(V, N, T, n0 + wm * 32, tb + 64 + wn * 32, lane, vn);
+      }
     }
     __syncthreads();
     f32x16 zn, dz;
@@ -507,13 +553,21 @@ hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, 
   if (R > FUSED_MAX_R) return hipErrorInvalidValue;
   if (side == 0) {
     prof_begin("rgh_H", s);
-    hipLaunchKernelGGL(k_rgh_H, dim3((unsigned)cdiv(T, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N, T, R,
-                       chunk, pu, puc, py, vpart, fin, check);
+    if (check)
+      hipLaunchKernelGGL(k_rgh_H<true>, dim3((unsigned)cdiv(T, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N, T,
+                         R, chunk, pu, puc, py, vpart, fin, check);
+    else
+      hipLaunchKernelGGL(k_rgh_H<false>, dim3((unsigned)cdiv(T, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N,
+                         T, R, chunk, pu, puc, py, vpart, fin, check);
     prof_end("rgh_H", s);
   } else {
     prof_begin("rgh_W", s);
-    hipLaunchKernelGGL(k_rgh_W, dim3((unsigned)cdiv(N, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N, T, R,
-                       chunk, pu, puc, py, vpart, fin, check);
+    if (check)
+      hipLaunchKernelGGL(k_rgh_W<true>, dim3((unsigned)cdiv(N, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N, T,
+                         R, chunk, pu, puc, py, vpart, fin, check);
+    else
+      hipLaunchKernelGGL(k_rgh_W<false>, dim3((unsigned)cdiv(N, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N,
+                         T, R, chunk, pu, puc, py, vpart, fin, check);
     prof_end("rgh_W", s);
   }
   return hipGetLastError();

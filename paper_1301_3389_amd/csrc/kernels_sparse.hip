@@ -127,6 +127,42 @@ hipError_t launch_sp_zq(const SpV& v, const float* W, const float* Ht, int64_t N
   return hipGetLastError();
 }
 
+// q, q-bar at every nonzero from the reconstruction the preceding half-step's
+// cost pass left (Algorithm 1 carries Z from steps 15 / 28; the normalisation
+// between the half-steps leaves W H unchanged): z = z_DNA where that selection
+// kept the Newton candidate, z_DNA + dZ where it kept MU.  key 0: the mask is
+// per column t (after an H step), key 1: per row n (after a W step).
+__global__ __launch_bounds__(256) void k_sp_qz(SpV v, const float* __restrict__ zc, const float* __restrict__ dzc,
+                                               const uint8_t* __restrict__ mask, int key, int64_t N, int64_t T,
+                                               float* __restrict__ q, float* __restrict__ qb, int* check, SumJob fin) {
+  sum_job(fin);
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int bad = 0;
+  if (j < v.nnz) {
+    const int64_t g = key == 0 ? clampi(v.col_idx[j], T) : clampi(v.row_of[j], N);
+    const float zN = zc[j];
+    const float z = mask[g] ? zN : zN + dzc[j];
+    const float x = v.val[j];
+    const bool pos = x > 0.f;
+    const float iz = __builtin_amdgcn_rcpf(z);
+    const float qq = pos ? x * iz : 0.f;
+    q[j] = qq;
+    qb[j] = pos ? qq * iz : 0.f;
+    bad = (pos && !(z > 0.f)) ? 1 : 0;
+  }
+  bad = wave_or(bad);
+  if (check && bad && (threadIdx.x & 63) == 0) atomicOr(check, CHK_DOMAIN);
+}
+
+hipError_t launch_sp_qz(const SpV& v, const float* zc, const float* dzc, const uint8_t* mask, int key, int64_t N,
+                        int64_t T, float* q, float* qb, int* check, const SumJob& fin, hipStream_t s) {
+  prof_begin("sp_qz", s);
+  hipLaunchKernelGGL(k_sp_qz, dim3((unsigned)std::max<int64_t>(1, cdiv(v.nnz, 256))), dim3(256), 0, s, v, zc, dzc,
+                     mask, key, N, T, q, qb, check, fin);
+  prof_end("sp_qz", s);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Gradient sums.  One wave per segment, lane r (+64 k, k < KR); segment partials
 // gp[4][seg][R] = (F q, F (q - 1), F, (F*F) q-bar) and the V sum of the segment.
@@ -290,7 +326,8 @@ hipError_t launch_sp_grad(int side, bool mu_only, const SpV& v, const float* F, 
 template <int SIDE>
 __global__ __launch_bounds__(256) void k_sp_cost(SpV v, const float* __restrict__ F, const float* __restrict__ Xn,
                                                  const float* __restrict__ Xd, int64_t N, int64_t T, int64_t R,
-                                                 double* __restrict__ cseg, int* __restrict__ fseg) {
+                                                 double* __restrict__ cseg, int* __restrict__ fseg,
+                                                 float* __restrict__ zc, float* __restrict__ dzc) {
   const int lane = threadIdx.x & 63;
   const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
@@ -323,6 +360,10 @@ __global__ __launch_bounds__(256) void k_sp_cost(SpV v, const float* __restrict_
     const float zN = dot_rows(f, xn, R, al);
     const float dz = dot_rows(f, xd, R, al);
     fl = cost_acc(v.val[p], zN, dz, s0, s1, s2);
+    if (zc) {                                    // carried to the next half-step (CSR order)
+      zc[p] = zN;
+      dzc[p] = dz;
+    }
   }
   s0 = wave_sum(s0);
   s1 = wave_sum(s1);
@@ -363,14 +404,15 @@ __global__ __launch_bounds__(256) void k_sp_cost_comb(SpV v, const double* __res
 }
 
 hipError_t launch_sp_cost(int side, const SpV& v, const float* F, const float* Xn, const float* Xd, int64_t N,
-                          int64_t T, int64_t R, double* cseg, int* fseg, double* part, int* fpart, hipStream_t s) {
+                          int64_t T, int64_t R, double* cseg, int* fseg, double* part, int* fpart, hipStream_t s,
+                          float* zc, float* dzc) {
   const int64_t nseg = side == 0 ? v.nseg_c : v.nseg_r;
   const dim3 grid((unsigned)std::max<int64_t>(1, cdiv(nseg, 4)));
   prof_begin(side == 0 ? "sp_cost_H" : "sp_cost_W", s);
   if (side == 0)
-    hipLaunchKernelGGL(k_sp_cost<0>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg);
+    hipLaunchKernelGGL(k_sp_cost<0>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg, zc, dzc);
   else
-    hipLaunchKernelGGL(k_sp_cost<1>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg);
+    hipLaunchKernelGGL(k_sp_cost<1>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg, zc, dzc);
   prof_end(side == 0 ? "sp_cost_H" : "sp_cost_W", s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

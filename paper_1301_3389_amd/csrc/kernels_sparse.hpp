@@ -27,6 +27,11 @@ hipError_t launch_sp_transpose(const float* X, float* Y, int64_t R, int64_t T, h
 // z, q, q-bar at the nonzeros (CSR order), W (N x R) and H^t (T x R).
 hipError_t launch_sp_zq(const SpV& v, const float* W, const float* Ht, int64_t N, int64_t T, int64_t R, float* q,
                         float* qb, int* check, const SumJob& fin, hipStream_t s);
+// q, q-bar from a carried reconstruction (zc = z_DNA, dzc = z_MU - z_DNA at the
+// nonzeros, CSR order; mask[key == 0 ? t : n] = 1 where the Newton candidate
+// was kept).
+hipError_t launch_sp_qz(const SpV& v, const float* zc, const float* dzc, const uint8_t* mask, int key, int64_t N,
+                        int64_t T, float* q, float* qb, int* check, const SumJob& fin, hipStream_t s);
 // Gradient sums (side 0: F = W, CSC segments, outputs [r][t]; side 1: F = H^t,
 // CSR segments, outputs [n][r]) in the layout of the dense split partials with
 // one split, and the V sums per column / row.  c64: the factor sums (c or g).
@@ -38,9 +43,11 @@ hipError_t launch_sp_grad(int side, bool mu_only, const SpV& v, const float* F, 
 // Candidate costs (side 0: F = W, X rows = candidates^t (T x R); side 1: F = H^t,
 // X rows = candidates (N x R)); Xd = X_MU - X_DNA in the same layout as Xn.
 // cseg: 3 x nseg doubles, fseg: nseg ints; part/fpart in the dense cost layout
-// with one tile.
+// with one tile.  zc, dzc (nnz floats each, or nullptr): z_DNA and z_MU - z_DNA
+// at the nonzeros in CSR order, for launch_sp_qz.
 hipError_t launch_sp_cost(int side, const SpV& v, const float* F, const float* Xn, const float* Xd, int64_t N,
-                          int64_t T, int64_t R, double* cseg, int* fseg, double* part, int* fpart, hipStream_t s);
+                          int64_t T, int64_t R, double* cseg, int* fseg, double* part, int* fpart, hipStream_t s,
+                          float* zc = nullptr, float* dzc = nullptr);
 hipError_t launch_sp_diff(const float* Xmu, const float* Xn, float* D, int64_t n, hipStream_t s);
 // KL of eq. 1; kseg: nseg_r doubles; c, g: float64 column sums of W and row sums of H.
 hipError_t launch_sp_kl(const SpV& v, const float* W, const float* Ht, int64_t N, int64_t T, int64_t R,
