@@ -544,10 +544,19 @@ static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N
   float* c32 = at<float>(ws, L.c32);
   double* cpart = at<double>(ws, L.cpart);
   RatioArgs ra{V, W, H, N, T, R, Q, nullptr, nullptr, cpart, c.chk, nullptr};
+  const bool fused = R <= FUSED_MAX_R;            // Z, Q and u in one pass, Q never stored
+  const int mode = with_cost ? RGH_MU_COST : RGH_MU;
   SumJob job;
   if (side == 0) {
     DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, c.s), "colsum_W");
     job.s32 = c32; job.check = c.chk; job.reg = o->lambda;
+    if (fused) {
+      DNA_HIP(launch_rgh(0, V, W, H, N, T, R, L.shf.splits, L.shf.kchunk, pu, nullptr, nullptr, cpart, job, c.chk,
+                         c.s, mode), "rgh_mu_H");
+      DNA_HIP(launch_mu_H(H, pu, L.shf.splits, c32, T, R, cpart, L.shf.splits, with_cost ? d_out : nullptr, c.s),
+              "mu_H");
+      return DNA_OK;
+    }
     ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_H_COST : RM_MU_H, ra, c.s), "ratio_mu_H");
     DNA_HIP(launch_gh_H(W, Q, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_H");
@@ -555,6 +564,13 @@ static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N
   } else {
     DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
     job.s32 = c32; job.check = c.chk; job.reg = o->rho;
+    if (fused) {
+      DNA_HIP(launch_rgh(1, V, W, H, N, T, R, L.swf.splits, L.swf.kchunk, pu, nullptr, nullptr, cpart, job, c.chk,
+                         c.s, mode), "rgh_mu_W");
+      DNA_HIP(launch_mu_W(W, pu, L.swf.splits, c32, N, R, cpart, L.swf.splits, with_cost ? d_out : nullptr, c.s),
+              "mu_W");
+      return DNA_OK;
+    }
     ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_W_COST : RM_MU_W, ra, c.s), "ratio_mu_W");
     DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_W");

@@ -151,10 +151,14 @@ hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int6
 // rows n split into `splits` chunks of `chunk`; side 1: W step, columns t split
 // likewise): the split partials of u, u_c, y and the per-split V sums, as the
 // ratio + gradient kernel pair writes them.  R > 64: hipErrorInvalidValue.
+// mode RGH_MU: the MU numerator u alone (puc, py, vpart untouched); RGH_MU_COST:
+// u and, in vpart, the per-column (side 0) / per-row (side 1) cost
+// sum_{v>0} v log(v/z) of the input state, natural log.
 constexpr int64_t FUSED_MAX_R = 64;
+constexpr int RGH_DNA = 0, RGH_MU = 1, RGH_MU_COST = 2;
 hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
                       int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart, const SumJob& fin,
-                      int* check, hipStream_t s);
+                      int* check, hipStream_t s, int mode = RGH_DNA);
 
 // Steps 7-9, 12-14 for R <= 64 with the candidates' block resident in LDS:
 // cost partials over `splits` chunks of rows n (side 0) or columns t (side 1),

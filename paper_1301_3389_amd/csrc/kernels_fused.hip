@@ -105,13 +105,18 @@ __device__ __forceinline__ void fetch_v_in(const float* V, int64_t T, int64_t n0
 //   phase 1: Z[n][t] = sum_r lw[n][r] lh[r][t]      (wave block n = wm, t = wn)
 //   phase 2: acc[r][t] += sum_n lw[n][r] {Q, Q - 1, lw[n][r] Q-bar}[n][t]  (r = wm, t = wn)
 // ---------------------------------------------------------------------------
-template <bool CHK>
+// MODE (both orientations): RGH_DNA forms u, u_c, y and the V sums; RGH_MU the
+// MU numerator u alone (no Q-bar tile); RGH_MU_COST also the input state's
+// cost sum_{v>0} v log(v/z) per column (row) in place of the V sums, with the
+// ratio pass's per-entry arithmetic.
+template <bool CHK, int MODE>
 __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W, const float* H, int64_t N,
                                                   int64_t T, int64_t R, int64_t nchunk, float* pu, float* puc,
                                                   float* py, double* vpart, SumJob fin, int* check) {
+  constexpr int NA = MODE == RGH_DNA ? 3 : 1;     // accumulated products
   __shared__ __align__(16) float lh[FT];
   __shared__ __align__(16) float lw[FT];
-  __shared__ __align__(16) float lq[2][FT];
+  __shared__ __align__(16) float lq[MODE == RGH_DNA ? 2 : 1][FT];
   sum_job(fin);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
@@ -119,9 +124,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   const int64_t nb0 = sp * nchunk, nb1 = std::min<int64_t>(N, nb0 + nchunk);
   const int cl = wn * 32 + (lane & 31);           // this lane's column t in the tile
   const int64_t col = t0 + cl;
-  f32x16 acc[3];
+  f32x16 acc[NA];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < NA; ++c)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
   double cp[1][GF::FN];
@@ -168,8 +173,12 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       const float q = x > 0.f ? x * iz : 0.f;
       if (CHK) bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
       lq[0][rl * FP + cl] = q;
-      lq[1][rl * FP + cl] = x > 0.f ? q * iz : 0.f;   // padding has z = 0: no 0 * inf
-      cp[0][0] += (double)x;
+      if constexpr (MODE == RGH_DNA) {
+        lq[1][rl * FP + cl] = x > 0.f ? q * iz : 0.f;   // padding has z = 0: no 0 * inf
+        cp[0][0] += (double)x;
+      } else if constexpr (MODE == RGH_MU_COST) {
+        cp[0][0] += (double)(x * log2_hw(x > 0.f ? q : 1.f)) * LN2;
+      }
     }
     __syncthreads();                              // lq ready
 #pragma unroll 4
@@ -177,10 +186,12 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       const int kr = k + (lane >> 5);
       const float a = lw[kr * FP + wm * 32 + (lane & 31)];
       const float b0 = lq[0][kr * FP + cl];
-      const float b1 = lq[1][kr * FP + cl];
       acc[0] = mfma32(a, b0, acc[0]);
-      acc[1] = mfma32(a, b0 - 1.f, acc[1]);
-      acc[2] = mfma32(a * a, b1, acc[2]);
+      if constexpr (MODE == RGH_DNA) {
+        const float b1 = lq[NA - 2][kr * FP + cl];
+        acc[NA - 2] = mfma32(a, b0 - 1.f, acc[NA - 2]);
+        acc[NA - 1] = mfma32(a * a, b1, acc[NA - 1]);
+      }
     }
     if (more)
 #pragma unroll
@@ -193,12 +204,13 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
     const int64_t r = wm * 32 + blk_row(v, lane);
     if (r < R && col < T) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) out[c][(sp * R + r) * T + col] = acc[c][v];
+      for (int c = 0; c < NA; ++c) out[c][(sp * R + r) * T + col] = acc[c][v];
     }
   }
-  reduce_cols<GF, 1>(cp, reinterpret_cast<double*>(lw), [&](int c, const double (&s)[1]) {
-    if (t0 + c < T) vpart[sp * T + t0 + c] = s[0];
-  });
+  if constexpr (MODE != RGH_MU)                   // V sums (DNA) or input-state costs (MU with cost)
+    reduce_cols<GF, 1>(cp, reinterpret_cast<double*>(lw), [&](int c, const double (&s)[1]) {
+      if (t0 + c < T) vpart[sp * T + t0 + c] = s[0];
+    });
   if (CHK && bad) atomicOr(check, CHK_DOMAIN);
 }
 
@@ -208,22 +220,23 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
 //   phase 1: Z[n][t] = sum_r lw[n][r] lh[r][t]      (wave block n = wm, t = wn)
 //   phase 2: acc[n][r] += sum_t {Q, Q - 1, Q-bar lh[r][t]}[n][t] lh[r][t]  (n = wm, r = wn)
 // ---------------------------------------------------------------------------
-template <bool CHK>
+template <bool CHK, int MODE>
 __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W, const float* H, int64_t N,
                                                   int64_t T, int64_t R, int64_t tchunk, float* pu, float* puc,
                                                   float* py, double* vpart, SumJob fin, int* check) {
+  constexpr int NA = MODE == RGH_DNA ? 3 : 1;
   __shared__ __align__(16) float lw[FT];
   __shared__ __align__(16) float lh[FT];
-  __shared__ __align__(16) float lq[2][FT];
+  __shared__ __align__(16) float lq[MODE == RGH_DNA ? 2 : 1][FT];
   sum_job(fin);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
   const int64_t n0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
   const int64_t tb0 = sp * tchunk, tb1 = std::min<int64_t>(T, tb0 + tchunk);
   const int tl = wn * 32 + (lane & 31);           // this lane's column in the Z block / r in phase 2
-  f32x16 acc[3];
+  f32x16 acc[NA];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < NA; ++c)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
   double rp[1][GF::FM][16];
@@ -275,8 +288,12 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       const float q = x > 0.f ? x * iz : 0.f;
       if (CHK) bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
       lq[0][rl * FP + tl] = q;
-      lq[1][rl * FP + tl] = x > 0.f ? q * iz : 0.f;
-      rp[0][0][v] += (double)x;
+      if constexpr (MODE == RGH_DNA) {
+        lq[1][rl * FP + tl] = x > 0.f ? q * iz : 0.f;
+        rp[0][0][v] += (double)x;
+      } else if constexpr (MODE == RGH_MU_COST) {
+        rp[0][0][v] += (double)(x * log2_hw(x > 0.f ? q : 1.f)) * LN2;
+      }
     }
     __syncthreads();
     {
@@ -285,13 +302,18 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
 #pragma unroll 2
       for (int g = 0; g < 8; ++g) {
         const f32x4 a0 = ld4(lq[0] + o + 8 * g);
-        const f32x4 a1 = ld4(lq[1] + o + 8 * g);
         const f32x4 b = ld4(pb + 8 * g);
+        if constexpr (MODE == RGH_DNA) {
+          const f32x4 a1 = ld4(lq[NA - 2] + o + 8 * g);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          acc[0] = mfma32(a0[m], b[m], acc[0]);
-          acc[1] = mfma32(a0[m] - 1.f, b[m], acc[1]);
-          acc[2] = mfma32(a1[m], b[m] * b[m], acc[2]);
+          for (int m = 0; m < 4; ++m) {
+            acc[0] = mfma32(a0[m], b[m], acc[0]);
+            acc[NA - 2] = mfma32(a0[m] - 1.f, b[m], acc[NA - 2]);
+            acc[NA - 1] = mfma32(a1[m], b[m] * b[m], acc[NA - 1]);
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) acc[0] = mfma32(a0[m], b[m], acc[0]);
         }
       }
     }
@@ -306,12 +328,13 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
     const int64_t n = n0 + wm * 32 + blk_row(v, lane);
     if (n < N && tl < R) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) out[c][(sp * N + n) * R + tl] = acc[c][v];
+      for (int c = 0; c < NA; ++c) out[c][(sp * N + n) * R + tl] = acc[c][v];
     }
   }
-  reduce_rows<GF, 1>(rp, reinterpret_cast<double*>(lw), [&](int r, const double (&s)[1]) {
-    if (n0 + r < N) vpart[sp * N + n0 + r] = s[0];
-  });
+  if constexpr (MODE != RGH_MU)
+    reduce_rows<GF, 1>(rp, reinterpret_cast<double*>(lw), [&](int r, const double (&s)[1]) {
+      if (n0 + r < N) vpart[sp * N + n0 + r] = s[0];
+    });
   if (CHK && bad) atomicOr(check, CHK_DOMAIN);
 }
 
@@ -547,29 +570,42 @@ hipError_t launch_costf(int side, const float* V, const float* F, const float* X
   return hipGetLastError();
 }
 
+template <int MODE>
+static void launch_rgh_mode(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T,
+                            int64_t R, int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart,
+                            const SumJob& fin, int* check, hipStream_t s) {
+  if (side == 0) {
+    const dim3 grid((unsigned)cdiv(T, 64), (unsigned)splits);
+    if (check)
+      hipLaunchKernelGGL((k_rgh_H<true, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
+                         fin, check);
+    else
+      hipLaunchKernelGGL((k_rgh_H<false, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
+                         fin, check);
+  } else {
+    const dim3 grid((unsigned)cdiv(N, 64), (unsigned)splits);
+    if (check)
+      hipLaunchKernelGGL((k_rgh_W<true, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
+                         fin, check);
+    else
+      hipLaunchKernelGGL((k_rgh_W<false, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
+                         fin, check);
+  }
+}
+
 hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
                       int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart, const SumJob& fin,
-                      int* check, hipStream_t s) {
+                      int* check, hipStream_t s, int mode) {
   if (R > FUSED_MAX_R) return hipErrorInvalidValue;
-  if (side == 0) {
-    prof_begin("rgh_H", s);
-    if (check)
-      hipLaunchKernelGGL(k_rgh_H<true>, dim3((unsigned)cdiv(T, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N, T,
-                         R, chunk, pu, puc, py, vpart, fin, check);
-    else
-      hipLaunchKernelGGL(k_rgh_H<false>, dim3((unsigned)cdiv(T, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N,
-                         T, R, chunk, pu, puc, py, vpart, fin, check);
-    prof_end("rgh_H", s);
-  } else {
-    prof_begin("rgh_W", s);
-    if (check)
-      hipLaunchKernelGGL(k_rgh_W<true>, dim3((unsigned)cdiv(N, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N, T,
-                         R, chunk, pu, puc, py, vpart, fin, check);
-    else
-      hipLaunchKernelGGL(k_rgh_W<false>, dim3((unsigned)cdiv(N, 64), (unsigned)splits), dim3(256), 0, s, V, W, H, N,
-                         T, R, chunk, pu, puc, py, vpart, fin, check);
-    prof_end("rgh_W", s);
-  }
+  const char* name = mode == RGH_DNA ? (side == 0 ? "rgh_H" : "rgh_W") : (side == 0 ? "rgh_mu_H" : "rgh_mu_W");
+  prof_begin(name, s);
+  if (mode == RGH_DNA)
+    launch_rgh_mode<RGH_DNA>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, fin, check, s);
+  else if (mode == RGH_MU)
+    launch_rgh_mode<RGH_MU>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, fin, check, s);
+  else
+    launch_rgh_mode<RGH_MU_COST>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, fin, check, s);
+  prof_end(name, s);
   return hipGetLastError();
 }
 
