@@ -303,7 +303,11 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
       DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
     }
     // the 16-bit Z pass tiles N by 128 like the fp32 one (RT_BM)
-    const int sp = p16 ? L.sh16.splits : (fused ? L.shf.splits : L.sh.splits);
+    int sp = p16 ? L.sh16.splits : (fused ? L.shf.splits : L.sh.splits);
+    if (sp > 8 && T < 256 * 32) {                   // few column blocks, many splits: fold them first
+      DNA_HIP(launch_fold_splits(pu, puc, py, sp, R * T, s), "fold_splits");
+      sp = 1;
+    }
     DNA_HIP(launch_cand_H(H, pu, puc, py, sp, c32, vpart, fused ? L.shf.splits : L.rt_m, T, R, o->eps, o->alpha,
                           o->lambda, Xmu, Xn, Aout, Bout, s), "cand_H");
   } else {

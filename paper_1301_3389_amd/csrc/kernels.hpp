@@ -89,6 +89,9 @@ hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t 
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s);
 
+// Adds the `splits` partials of u, u_c, y (each splits x n floats) into split 0,
+// in split order.
+hipError_t launch_fold_splits(float* pu, float* puc, float* py, int splits, int64_t n, hipStream_t s);
 // Candidates (MU and renormalised Newton) from the split partials.  c (g) holds
 // the factor sums plus reg, the eq. 2 weight of this half-step (lambda / rho).
 hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits,

@@ -359,7 +359,7 @@ __global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
       float u[RPT], uc[RPT], y[RPT];
 #pragma unroll
       for (int i = 0; i < RPT; ++i) u[i] = uc[i] = y[i] = 0.f;
-      constexpr int SPU = RPT <= 8 ? 2 : 1;      // loads in flight: 3 x RPT x SPU
+      constexpr int SPU = RPT <= 2 ? 8 : (RPT <= 8 ? 2 : 1);   // loads in flight: 3 x RPT x SPU
 #pragma unroll SPU
       for (int sp = 0; sp < splits; ++sp) {
         const int64_t o = (int64_t)sp * R * T + t;
@@ -411,6 +411,7 @@ __global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
     double d = 0.0;
     for (int k = 0; k < RG; ++k) d += red[k][cl];
     double s = 0.0;
+#pragma unroll 8
     for (int m = 0; m < tiles_m; ++m) s += vpart[(int64_t)m * T + t];
     fac[cl] = d > 0.0 ? s / d : 1.0;
   }
@@ -429,6 +430,34 @@ __global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
         Xn[r * T + t] = fmaxf((float)((double)Xn[r * T + t] * f), VALUE_FLOOR);
     }
   }
+}
+
+// The split partials of u, u_c, y added into split 0 in split order, a thread
+// per entry (what k_cand_H adds per entry, so its result is unchanged); for
+// many splits over few columns, where k_cand_H's few workgroups would add
+// them one after another.
+__global__ __launch_bounds__(256) void k_fold_splits(float* __restrict__ pu, float* __restrict__ puc,
+                                                     float* __restrict__ py, int splits, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  float u = 0.f, uc = 0.f, y = 0.f;
+#pragma unroll 8
+  for (int sp = 0; sp < splits; ++sp) {
+    u += pu[sp * n + e];
+    uc += puc[sp * n + e];
+    y += py[sp * n + e];
+  }
+  pu[e] = u;
+  puc[e] = uc;
+  py[e] = y;
+}
+
+hipError_t launch_fold_splits(float* pu, float* puc, float* py, int splits, int64_t n, hipStream_t s) {
+  prof_begin("fold_splits", s);
+  hipLaunchKernelGGL(k_fold_splits, dim3((unsigned)std::max<int64_t>(1, cdiv(n, 256))), dim3(256), 0, s, pu, puc, py,
+                     splits, n);
+  prof_end("fold_splits", s);
+  return hipGetLastError();
 }
 
 hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, const float* py, int splits, const float* c,
@@ -736,6 +765,7 @@ __global__ __launch_bounds__(256) void k_select_H(const float* __restrict__ Xmu,
     const int64_t stride = (int64_t)tiles * T;
     double q0 = 0.0, q1 = 0.0, q2 = 0.0;
     int fl = 0;
+#pragma unroll 8
     for (int m = 0; m < tiles; ++m) {
       const int64_t o = (int64_t)m * T + t;
       q0 += part[o];
@@ -818,6 +848,7 @@ __global__ __launch_bounds__(256) void k_select_W_rows(const float* __restrict__
     const int64_t stride = (int64_t)tiles * N;
     double q0 = 0.0, q1 = 0.0, q2 = 0.0;
     int fl = 0;
+#pragma unroll 4
     for (int m = 0; m < tiles; ++m) {
       const int64_t o = (int64_t)m * N + n;
       q0 += part[o];
@@ -859,19 +890,24 @@ hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const
 // ---------------------------------------------------------------------------
 // MU updates (eq. 11): X <- X * numerator / scale.
 // ---------------------------------------------------------------------------
+// A thread per entry (r, t): 64 columns x 4 rows per block, rows over the
+// grid's y; the split sums are unrolled so their loads overlap (order kept).
 __global__ __launch_bounds__(256) void k_mu_H(float* H, const float* pu, int splits, const float* c,
                                               int64_t T, int64_t R, const double* cpart, int tiles,
                                               double* d_out) {
   const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
   const int64_t t = (int64_t)blockIdx.x * 64 + cl;
+  const int64_t r = (int64_t)blockIdx.y * 4 + rg;
   if (t >= T) return;
-  for (int64_t r = rg; r < R; r += 4) {
+  if (r < R) {
     float u = 0.f;
+#pragma unroll 8
     for (int sp = 0; sp < splits; ++sp) u += pu[(sp * R + r) * T + t];
     H[r * T + t] = fmaxf(H[r * T + t] * (u / c[r]), VALUE_FLOOR);     // eq. (11): h (W^t q)_r / c_r
   }
-  if (d_out && rg == 0) {
+  if (d_out && blockIdx.y == 0 && rg == 0) {
     double s = 0.0;
+#pragma unroll 8
     for (int m = 0; m < tiles; ++m) s += cpart[(int64_t)m * T + t];
     d_out[t] = s;
   }
@@ -880,8 +916,8 @@ __global__ __launch_bounds__(256) void k_mu_H(float* H, const float* pu, int spl
 hipError_t launch_mu_H(float* H, const float* pu, int splits, const float* c, int64_t T, int64_t R,
                        const double* cpart, int tiles_m, double* d_out, hipStream_t s) {
   prof_begin("mu_H", s);
-  hipLaunchKernelGGL(k_mu_H, dim3((unsigned)cdiv(T, 64)), dim3(256), 0, s, H, pu, splits, c, T, R, cpart,
-                     tiles_m, d_out);
+  hipLaunchKernelGGL(k_mu_H, dim3((unsigned)cdiv(T, 64), (unsigned)cdiv(R, 4)), dim3(256), 0, s, H, pu, splits, c,
+                     T, R, cpart, tiles_m, d_out);
   prof_end("mu_H", s);
   return hipGetLastError();
 }
@@ -894,6 +930,7 @@ __global__ __launch_bounds__(256) void k_mu_W(float* W, const float* pu, int spl
   if (n >= N) return;
   for (int64_t r = lane; r < R; r += 64) {
     float u = 0.f;
+#pragma unroll 8
     for (int sp = 0; sp < splits; ++sp) u += pu[(sp * N + n) * R + r];
     W[n * R + r] = fmaxf(W[n * R + r] * (u / g[r]), VALUE_FLOOR);
   }
