@@ -36,6 +36,11 @@ constexpr int FT = 64 * FP;                  // floats per LDS tile
 __device__ __forceinline__ int kq(int g, int lane, int m) { return 8 * g + 4 * (lane >> 5) + m; }
 __device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
 
+// Groups of 8 rank indices the Z contraction runs over: LDS holds zeros past
+// rank R in both operands, so stopping at R rounded up to 8 drops only exact
+// zero products (the same sums as the full 64-wide tile).
+__device__ __forceinline__ int rank_groups(int64_t R) { return (int)std::min<int64_t>(8, (R + 7) / 8); }
+
 // Load a 64 x 64 block of a row-major fp32 matrix (rows r0.., columns c0..,
 // zero outside rows < nr, columns < nc) into registers: four float4 per thread.
 __device__ __forceinline__ void fetch_block(const float* X, int64_t ld, int64_t r0, int64_t c0, int64_t nr,
@@ -120,6 +125,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   sum_job(fin);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
+  const int kz = 8 * rank_groups(R);
   const int64_t t0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
   const int64_t nb0 = sp * nchunk, nb1 = std::min<int64_t>(N, nb0 + nchunk);
   const int cl = wn * 32 + (lane & 31);           // this lane's column t in the tile
@@ -161,7 +167,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
 #pragma unroll
     for (int v = 0; v < 16; ++v) z[v] = 0.f;
 #pragma unroll 4
-    for (int k = 0; k < 64; k += 2) {             // (measured faster here than the 16-byte form)
+    for (int k = 0; k < kz; k += 2) {             // (measured faster here than the 16-byte form)
       const int kr = k + (lane >> 5);
       z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + cl], z);
     }
@@ -231,6 +237,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   sum_job(fin);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
+  const int gz = rank_groups(R);
   const int64_t n0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
   const int64_t tb0 = sp * tchunk, tb1 = std::min<int64_t>(T, tb0 + tchunk);
   const int tl = wn * 32 + (lane & 31);           // this lane's column in the Z block / r in phase 2
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
     {
       const float* pa = lw + (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
 #pragma unroll 2
-      for (int g = 0; g < 8; ++g) {
+      for (int g = 0; g < gz; ++g) {
         const f32x4 a4 = ld4(pa + 8 * g);
 #pragma unroll
         for (int m = 0; m < 4; ++m) z = mfma32(a4[m], lh[kq(g, lane, m) * FP + tl], z);
@@ -356,6 +363,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
   __shared__ int fl_s[64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
+  const int gz = rank_groups(R);
   const int64_t t0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
   const int64_t nb0 = sp * nchunk, nb1 = std::min<int64_t>(N, nb0 + nchunk);
   const int cl = wn * 32 + (lane & 31);
@@ -399,7 +407,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
     {
       const float* pa = lw + (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
 #pragma unroll 2
-      for (int g = 0; g < 8; ++g) {
+      for (int g = 0; g < gz; ++g) {
         const f32x4 a4 = ld4(pa + 8 * g);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -444,6 +452,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
   __shared__ int fl_s[64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
+  const int gz = rank_groups(R);
   const int64_t n0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
   const int64_t tb0 = sp * tchunk, tb1 = std::min<int64_t>(T, tb0 + tchunk);
   const int tl = wn * 32 + (lane & 31);
@@ -494,7 +503,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
     {
       const int o = (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
 #pragma unroll 2
-      for (int g = 0; g < 8; ++g) {
+      for (int g = 0; g < gz; ++g) {
         const f32x4 an = ld4(ln + o + 8 * g);
         const f32x4 ad = ld4(ld + o + 8 * g);
 #pragma unroll
