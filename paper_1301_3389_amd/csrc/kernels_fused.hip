@@ -41,6 +41,27 @@ __device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<
 // zero products (the same sums as the full 64-wide tile).
 __device__ __forceinline__ int rank_groups(int64_t R) { return (int)std::min<int64_t>(8, (R + 7) / 8); }
 
+// For R <= 32 the gradient products have one 32-row block of rank indices, so
+// the wave pair that would own ranks 32..63 takes the second half of each
+// sub-tile's contraction for ranks 0..31 instead; at the end it hands its
+// partial products through LDS (buf, NA x 2048 floats, free by then) to the
+// pair holding the same outputs, which adds them.  `giver` is uniform per wave;
+// every thread of the block calls this.
+template <int NA>
+__device__ __forceinline__ void fold_halves(f32x16 (&acc)[NA], float* buf, bool giver, int pair, int lane) {
+  if (giver)
+#pragma unroll
+    for (int c = 0; c < NA; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) buf[((c * 2 + pair) * 16 + v) * 64 + lane] = acc[c][v];
+  __syncthreads();
+  if (!giver)
+#pragma unroll
+    for (int c = 0; c < NA; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[c][v] += buf[((c * 2 + pair) * 16 + v) * 64 + lane];
+}
+
 // Load a 64 x 64 block of a row-major fp32 matrix (rows r0.., columns c0..,
 // zero outside rows < nr, columns < nc) into registers: four float4 per thread.
 __device__ __forceinline__ void fetch_block(const float* X, int64_t ld, int64_t r0, int64_t c0, int64_t nr,
@@ -126,6 +147,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
   const int kz = 8 * rank_groups(R);
+  // phase 2: rank block rb over rows k0 .. k0 + nk of each sub-tile (R <= 32: both pairs on ranks 0..31)
+  const bool half = R <= 32;
+  const int rb = half ? 0 : wm * 32, k0 = half ? wm * 32 : 0, nk = half ? 32 : 64;
   const int64_t t0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
   const int64_t nb0 = sp * nchunk, nb1 = std::min<int64_t>(N, nb0 + nchunk);
   const int cl = wn * 32 + (lane & 31);           // this lane's column t in the tile
@@ -187,16 +211,18 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       }
     }
     __syncthreads();                              // lq ready
-#pragma unroll 4
-    for (int k = 0; k < 64; k += 2) {
-      const int kr = k + (lane >> 5);
-      const float a = lw[kr * FP + wm * 32 + (lane & 31)];
-      const float b0 = lq[0][kr * FP + cl];
-      acc[0] = mfma32(a, b0, acc[0]);
-      if constexpr (MODE == RGH_DNA) {
-        const float b1 = lq[NA - 2][kr * FP + cl];
-        acc[NA - 2] = mfma32(a, b0 - 1.f, acc[NA - 2]);
-        acc[NA - 1] = mfma32(a * a, b1, acc[NA - 1]);
+    for (int kb = k0; kb < k0 + nk; kb += 8) {
+#pragma unroll
+      for (int k = kb; k < kb + 8; k += 2) {
+        const int kr = k + (lane >> 5);
+        const float a = lw[kr * FP + rb + (lane & 31)];
+        const float b0 = lq[0][kr * FP + cl];
+        acc[0] = mfma32(a, b0, acc[0]);
+        if constexpr (MODE == RGH_DNA) {
+          const float b1 = lq[NA - 2][kr * FP + cl];
+          acc[NA - 2] = mfma32(a, b0 - 1.f, acc[NA - 2]);
+          acc[NA - 1] = mfma32(a * a, b1, acc[NA - 1]);
+        }
       }
     }
     if (more)
@@ -204,6 +230,8 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       for (int v = 0; v < 16; ++v) vf[v] = vn[v];
     __syncthreads();                              // lw and lq free for the next sub-tile
   }
+  static_assert(NA * 2048 <= (MODE == RGH_DNA ? 2 : 1) * FT, "fold buffer");
+  if (half) fold_halves<NA>(acc, &lq[0][0], wm == 1, wn, lane);   // the wm = 1 pair holds no rank >= R
   float* out[3] = {pu, puc, py};
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -238,6 +266,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
   const int gz = rank_groups(R);
+  // phase 2: rank block rb over column groups g0 .. g0 + ng (R <= 32: both pairs on ranks 0..31)
+  const bool half = R <= 32;
+  const int rb = half ? 0 : wn * 32, g0 = half ? wn * 4 : 0, ng = half ? 4 : 8;
   const int64_t n0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
   const int64_t tb0 = sp * tchunk, tb1 = std::min<int64_t>(T, tb0 + tchunk);
   const int tl = wn * 32 + (lane & 31);           // this lane's column in the Z block / r in phase 2
@@ -305,9 +336,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
     __syncthreads();
     {
       const int o = (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
-      const float* pb = lh + tl * FP + 4 * (lane >> 5);   // H[r = tl][t]
+      const float* pb = lh + (rb + (lane & 31)) * FP + 4 * (lane >> 5);   // H[r][t]
 #pragma unroll 2
-      for (int g = 0; g < 8; ++g) {
+      for (int g = g0; g < g0 + ng; ++g) {
         const f32x4 a0 = ld4(lq[0] + o + 8 * g);
         const f32x4 b = ld4(pb + 8 * g);
         if constexpr (MODE == RGH_DNA) {
@@ -329,6 +360,8 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       for (int v = 0; v < 16; ++v) vf[v] = vn[v];
     __syncthreads();
   }
+  static_assert(NA * 2048 <= (MODE == RGH_DNA ? 2 : 1) * FT, "fold buffer");
+  if (half) fold_halves<NA>(acc, &lq[0][0], wn == 1, wm, lane);   // the wn = 1 pair holds no rank >= R
   float* out[3] = {pu, puc, py};
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
