@@ -144,7 +144,8 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   __shared__ __align__(16) float lw[FT];
   __shared__ __align__(16) float lq[MODE == RGH_DNA ? 2 : 1][FT];
   sum_job(fin);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave: scalar loop bounds
   const int wm = wave % 2, wn = wave / 2;
   const int kz = 8 * rank_groups(R);
   // phase 2: rank block rb over rows k0 .. k0 + nk of each sub-tile (R <= 32: both pairs on ranks 0..31)
@@ -190,10 +191,12 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
     f32x16 z;
 #pragma unroll
     for (int v = 0; v < 16; ++v) z[v] = 0.f;
-#pragma unroll 4
-    for (int k = 0; k < kz; k += 2) {             // (measured faster here than the 16-byte form)
-      const int kr = k + (lane >> 5);
-      z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + cl], z);
+    for (int kb = 0; kb < kz; kb += 8) {          // 4-byte reads: measured faster here than the 16-byte form
+#pragma unroll
+      for (int k = kb; k < kb + 8; k += 2) {
+        const int kr = k + (lane >> 5);
+        z = mfma32(lw[(wm * 32 + (lane & 31)) * FP + kr], lh[kr * FP + cl], z);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -263,7 +266,8 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   __shared__ __align__(16) float lh[FT];
   __shared__ __align__(16) float lq[MODE == RGH_DNA ? 2 : 1][FT];
   sum_job(fin);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave: scalar loop bounds
   const int wm = wave % 2, wn = wave / 2;
   const int gz = rank_groups(R);
   // phase 2: rank block rb over column groups g0 .. g0 + ng (R <= 32: both pairs on ranks 0..31)
@@ -394,7 +398,8 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
   __shared__ __align__(16) float ld[FT];
   __shared__ __align__(16) float lw[FT];
   __shared__ int fl_s[64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave: scalar loop bounds
   const int wm = wave % 2, wn = wave / 2;
   const int gz = rank_groups(R);
   const int64_t t0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
@@ -483,7 +488,8 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
   __shared__ __align__(16) float ld[FT];
   __shared__ __align__(16) float lh[FT];
   __shared__ int fl_s[64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave: scalar loop bounds
   const int wm = wave % 2, wn = wave / 2;
   const int gz = rank_groups(R);
   const int64_t n0 = (int64_t)blockIdx.x * 64, sp = blockIdx.y;
