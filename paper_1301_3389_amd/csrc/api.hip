@@ -108,10 +108,34 @@ static Split fused_split(int64_t K, int64_t base_tiles) {
   return s;
 }
 
+// Chunks for a fused kernel of which `per_cu` workgroups fit on a CU: all
+// workgroups resident at once, and the busiest CU's work (workgroups per CU x
+// 64-row sub-tiles per workgroup) as small as possible; on a tie, more
+// workgroups.
+static Split balanced_split(int64_t K, int64_t base_tiles, int64_t per_cu) {
+  const int64_t k64 = std::max<int64_t>(1, cdiv(K, 64)), base = std::max<int64_t>(1, base_tiles);
+  int64_t best_per = k64, best_load = INT64_MAX;
+  for (int64_t sp = 1; sp <= k64; ++sp) {
+    const int64_t per = cdiv(k64, sp);                    // sub-tiles per workgroup
+    const int64_t wgs = base * cdiv(k64, per);
+    const int64_t on_cu = cdiv(wgs, 256);
+    if (on_cu > per_cu && sp > 1) break;                  // wgs only grows with sp
+    if (on_cu * per <= best_load) {
+      best_load = on_cu * per;
+      best_per = per;
+    }
+  }
+  Split s;
+  s.kchunk = best_per * 64;
+  s.splits = (int)cdiv(K, s.kchunk);
+  return s;
+}
+
 struct Layout {
   Split sh, sw;              // split-K of the fp32 gradient products (H / W orientation)
   Split sh16, sw16;          // the same for the 16-bit products (128 x 128 tiles)
   Split shf, swf;            // row / column chunks of the fused kernels (R <= FUSED_MAX_R)
+  Split chf;                 // row chunks of the fused H-orientation cost pass (three workgroups per CU fit)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
   size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, sume, vpart, cpart, fpart, s16, check, total;
@@ -127,6 +151,7 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   L.sw16 = choose_split(T, cdiv(R, 128) * cdiv(N, 128));
   L.shf = fused_split(N, cdiv(T, 64));
   L.swf = fused_split(T, cdiv(N, 64));
+  L.chf = balanced_split(N, cdiv(T, 64), 3);
   L.rt_m = (int)cdiv(N, RT_BM);
   L.rt_n = (int)cdiv(T, RT_BN);
   L.ch_m = (int)cdiv(N, CH_BM);
@@ -136,7 +161,7 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   const int64_t spw = std::max({L.sw.splits, L.sw16.splits, L.swf.splits});
   const size_t psplit = (size_t)std::max<int64_t>(sph * R * T, spw * N * R);
   const size_t red = (size_t)std::max({(int64_t)L.rt_m * T, (int64_t)L.rt_n * N, (int64_t)L.ch_m * T,
-                                       (int64_t)L.cw_n * N, sph * T, spw * N});
+                                       (int64_t)L.cw_n * N, sph * T, (int64_t)L.chf.splits * T, spw * N});
   const size_t klt = (size_t)L.rt_m * L.rt_n;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -352,10 +377,10 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
   const bool fused = R <= FUSED_MAX_R;   // candidates' block resident in LDS
   if (side == 0) {
     if (fused)
-      DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.shf.splits, L.shf.kchunk, cpart, fpart, s), "costf_H");
+      DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.chf.splits, L.chf.kchunk, cpart, fpart, s), "costf_H");
     else
       DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_H");
-    DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, fused ? L.shf.splits : L.ch_m, T, R, mask, dsel, margin,
+    DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, fused ? L.chf.splits : L.ch_m, T, R, mask, dsel, margin,
                             s), "select_H");
   } else {
     if (fused)
