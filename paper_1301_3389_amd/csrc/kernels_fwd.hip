@@ -787,12 +787,54 @@ __global__ __launch_bounds__(256) void k_select_H(const float* __restrict__ Xmu,
   for (int64_t r = rg; r < R; r += CAND_RG) Hout[r * T + t] = src[r * T + t];
 }
 
+// Many tile partials over few columns: a wave per column (four per block), the
+// lanes add the partials, then the wave copies the chosen column (a strided
+// copy, so only for few columns: SEL_MANY_COLS).
+constexpr int SEL_MANY = 16;
+constexpr int64_t SEL_MANY_COLS = 4096;
+__global__ __launch_bounds__(256) void k_select_H_cols(const float* __restrict__ Xmu, const float* __restrict__ Xn,
+                                                       float* __restrict__ Hout,
+                                                       const double* part, const int* fpart, int tiles,
+                                                       int64_t T, int64_t R, uint8_t* mask, double* dsel,
+                                                       double* margin) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  const int64_t stride = (int64_t)tiles * T;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  int fl = 0;
+  for (int64_t m = lane; m < tiles; m += 64) {
+    const int64_t o = m * T + t;
+    q0 += part[o];
+    q1 += part[stride + o];
+    q2 += part[2 * stride + o];
+    fl |= fpart[o];
+  }
+  q0 = __shfl(wave_sum(q0), 0);
+  q1 = __shfl(wave_sum(q1), 0);
+  q2 = __shfl(wave_sum(q2), 0);
+  fl = wave_or(fl);
+  double ds, mg;
+  const bool nw = decide(q0, q1, q2, fl, ds, mg);
+  if (lane == 0) {
+    if (mask) mask[t] = nw ? 1 : 0;
+    if (dsel) dsel[t] = ds;
+    if (margin) margin[t] = mg;
+  }
+  const float* src = nw ? Xn : Xmu;
+  for (int64_t r = lane; r < R; r += 64) Hout[r * T + t] = src[r * T + t];
+}
+
 hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,
                            const int* fpart, int tiles_m, int64_t T, int64_t R, uint8_t* mask,
                            double* dsel, double* margin, hipStream_t s) {
   prof_begin("select_H", s);
-  hipLaunchKernelGGL(k_select_H, dim3((unsigned)cdiv(T, CAND_COLS)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
-                     tiles_m, T, R, mask, dsel, margin);
+  if (tiles_m > SEL_MANY && T <= SEL_MANY_COLS)
+    hipLaunchKernelGGL(k_select_H_cols, dim3((unsigned)cdiv(T, 4)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
+                       tiles_m, T, R, mask, dsel, margin);
+  else
+    hipLaunchKernelGGL(k_select_H, dim3((unsigned)cdiv(T, CAND_COLS)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
+                       tiles_m, T, R, mask, dsel, margin);
   prof_end("select_H", s);
   return hipGetLastError();
 }
