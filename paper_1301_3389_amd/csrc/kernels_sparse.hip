@@ -323,42 +323,107 @@ hipError_t launch_sp_grad(int side, bool mu_only, const SpV& v, const float* F, 
 //   SIDE 0: CSC segments, F_row = W[n, :], X rows = candidates^t[t, :] (T x R).
 //   SIDE 1: CSR segments, F_row = H^t[t, :], X rows = candidates[n, :] (N x R).
 // ---------------------------------------------------------------------------
+// The gathered factor rows pass through LDS SC_RC floats at a time: the wave
+// reads its (at most 64) rows with contiguous loads, eight lanes per 32-float
+// row chunk, instead of each lane walking its own row with loads that hit 64
+// different rows per instruction; each lane then forms its dot products from
+// LDS (row pitch SC_RC + 1: conflict-free column reads) in dot_rows' order,
+// so the sums are those of dot_rows.
+constexpr int SC_RC = 32, SC_PITCH = SC_RC + 1;
+
 template <int SIDE>
-__global__ __launch_bounds__(256) void k_sp_cost(SpV v, const float* __restrict__ F, const float* __restrict__ Xn,
-                                                 const float* __restrict__ Xd, int64_t N, int64_t T, int64_t R,
-                                                 double* __restrict__ cseg, int* __restrict__ fseg,
-                                                 float* __restrict__ zc, float* __restrict__ dzc) {
-  const int lane = threadIdx.x & 63;
-  const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(64) void k_sp_cost(SpV v, const float* __restrict__ F, const float* __restrict__ Xn,
+                                                const float* __restrict__ Xd, int64_t N, int64_t T, int64_t R,
+                                                double* __restrict__ cseg, int* __restrict__ fseg,
+                                                float* __restrict__ zc, float* __restrict__ dzc) {
+  __shared__ float st[64 * SC_PITCH];
+  __shared__ float sx[2 * SC_RC];
+  const int lane = threadIdx.x;
+  const int64_t sg = blockIdx.x;
   const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
-  if (sg >= nseg) return;
+  if (sg >= nseg) return;                         // the whole workgroup (one wave)
   const int32_t* start = SIDE == 0 ? v.segc_start : v.segr_start;
   int64_t i0 = start[sg], i1 = start[sg + 1];
   clamp_range(i0, i1, v.nnz);
+  const int cnt = (int)std::min<int64_t>(64, i1 - i0);
   const int64_t i = i0 + lane;
+  const bool act = lane < cnt;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   int fl = 0;
   // every entry of a segment lies in one column (SIDE 0) / row (SIDE 1): that
   // index is uniform, so its candidate rows are read once for the wave
   const int64_t own = i0 < i1 ? (SIDE == 0 ? v.csc_col[i0] : v.row_of[i0]) : 0;
   const int64_t fixed = clampi(__builtin_amdgcn_readfirstlane((int)own), SIDE == 0 ? T : N);
-  if (i < i1) {
-    int64_t p, n, t;
+  int64_t p = 0;
+  int gi = 0;                                     // this lane's gathered row (n or t)
+  if (act) {
     if (SIDE == 0) {
       p = clampi(v.csc_pos[i], v.nnz);
-      n = clampi(v.csc_row[i], N);
-      t = fixed;
+      gi = (int)clampi(v.csc_row[i], N);
     } else {
       p = i;
-      n = fixed;
-      t = clampi(v.col_idx[i], T);
+      gi = (int)clampi(v.col_idx[i], T);
     }
-    const float* f = SIDE == 0 ? F + n * R : F + t * R;
-    const float* xn = SIDE == 0 ? Xn + t * R : Xn + n * R;
-    const float* xd = SIDE == 0 ? Xd + t * R : Xd + n * R;
-    const bool al = rows_aligned(f, xn, R) && rows_aligned(f, xd, R);
-    const float zN = dot_rows(f, xn, R, al);
-    const float dz = dot_rows(f, xd, R, al);
+  }
+  const float* xn = Xn + fixed * R;
+  const float* xd = Xd + fixed * R;
+  const bool vec = (R & 3) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(F) | reinterpret_cast<uintptr_t>(Xn) |
+                     reinterpret_cast<uintptr_t>(Xd)) & 15) == 0;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;   // z_DNA partials (dot_rows' four)
+  float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;   // dZ partials
+  for (int64_t c0 = 0; c0 < R; c0 += SC_RC) {
+    const int rc = (int)std::min<int64_t>(SC_RC, R - c0);
+    __syncthreads();                              // the previous chunk's reads are done
+    if (lane < SC_RC) {
+      if (lane < rc) sx[lane] = xn[c0 + lane];
+    } else if (lane - SC_RC < rc) {
+      sx[lane] = xd[c0 + lane - SC_RC];
+    }
+    if (vec) {
+#pragma unroll
+      for (int j = 0; j < SC_RC / 4; ++j) {       // row e = q / 8, float4 k = q % 8
+        const int q = j * 64 + lane, e = q >> 3, k = q & 7;
+        const int ge = __shfl(gi, e);
+        if (e < cnt && 4 * k < rc) {
+          const f32x4 x = *reinterpret_cast<const f32x4*>(F + (int64_t)ge * R + c0 + 4 * k);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) st[e * SC_PITCH + 4 * k + m] = x[m];
+        }
+      }
+    } else {
+#pragma unroll 8
+      for (int j = 0; j < SC_RC; ++j) {           // row e = q / 32, float r = q % 32
+        const int q = j * 64 + lane, e = q >> 5, r = q & 31;
+        const int ge = __shfl(gi, e);
+        if (e < cnt && r < rc) st[e * SC_PITCH + r] = F[(int64_t)ge * R + c0 + r];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const float* f = st + lane * SC_PITCH;
+      if (vec) {                                  // rc is a multiple of 4 here
+        for (int r = 0; r < rc; r += 4) {
+          a0 = fmaf(f[r], sx[r], a0);
+          a1 = fmaf(f[r + 1], sx[r + 1], a1);
+          a2 = fmaf(f[r + 2], sx[r + 2], a2);
+          a3 = fmaf(f[r + 3], sx[r + 3], a3);
+          b0 = fmaf(f[r], sx[SC_RC + r], b0);
+          b1 = fmaf(f[r + 1], sx[SC_RC + r + 1], b1);
+          b2 = fmaf(f[r + 2], sx[SC_RC + r + 2], b2);
+          b3 = fmaf(f[r + 3], sx[SC_RC + r + 3], b3);
+        }
+      } else {
+        for (int r = 0; r < rc; ++r) {
+          a0 = fmaf(f[r], sx[r], a0);
+          b0 = fmaf(f[r], sx[SC_RC + r], b0);
+        }
+      }
+    }
+  }
+  if (act) {
+    const float zN = (a0 + a1) + (a2 + a3);
+    const float dz = (b0 + b1) + (b2 + b3);
     fl = cost_acc(v.val[p], zN, dz, s0, s1, s2);
     if (zc) {                                    // carried to the next half-step (CSR order)
       zc[p] = zN;
@@ -407,12 +472,12 @@ hipError_t launch_sp_cost(int side, const SpV& v, const float* F, const float* X
                           int64_t T, int64_t R, double* cseg, int* fseg, double* part, int* fpart, hipStream_t s,
                           float* zc, float* dzc) {
   const int64_t nseg = side == 0 ? v.nseg_c : v.nseg_r;
-  const dim3 grid((unsigned)std::max<int64_t>(1, cdiv(nseg, 4)));
+  const dim3 grid((unsigned)std::max<int64_t>(1, nseg));      // a workgroup (one wave) per segment
   prof_begin(side == 0 ? "sp_cost_H" : "sp_cost_W", s);
   if (side == 0)
-    hipLaunchKernelGGL(k_sp_cost<0>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg, zc, dzc);
+    hipLaunchKernelGGL(k_sp_cost<0>, grid, dim3(64), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg, zc, dzc);
   else
-    hipLaunchKernelGGL(k_sp_cost<1>, grid, dim3(256), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg, zc, dzc);
+    hipLaunchKernelGGL(k_sp_cost<1>, grid, dim3(64), 0, s, v, F, Xn, Xd, N, T, R, cseg, fseg, zc, dzc);
   prof_end(side == 0 ? "sp_cost_H" : "sp_cost_W", s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
