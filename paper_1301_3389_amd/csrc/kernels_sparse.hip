@@ -169,12 +169,20 @@ hipError_t launch_sp_qz(const SpV& v, const float* zc, const float* dzc, const u
 //   SIDE 0 (H step): segments of the CSC order, F = W[n, :] of each entry's row.
 //   SIDE 1 (W step): segments of the CSR order, F = H^t[t, :] of each entry's column.
 // ---------------------------------------------------------------------------
+// A segment of more than SG_DIRECT entries first copies its factor rows into
+// LDS (pitch P floats: R rounded up to 4, or 64 per chunk of 64 ranks), all
+// loads issued before any is used, 16 bytes per lane when the rows are 16-byte
+// aligned; a shorter one reads each row in the loop.  The sums are formed in
+// the same order either way.
+constexpr int SG_DIRECT = 16;
+
 template <int SIDE, int KR, bool MU>
-__global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict__ F, const float* __restrict__ q,
-                                                 const float* __restrict__ qb, int64_t N, int64_t T, int64_t R,
-                                                 float* __restrict__ gp, double* __restrict__ vseg) {
-  const int lane = threadIdx.x & 63;
-  const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(64) void k_sp_grad(SpV v, const float* __restrict__ F, const float* __restrict__ q,
+                                                const float* __restrict__ qb, int64_t N, int64_t T, int64_t R,
+                                                float* __restrict__ gp, double* __restrict__ vseg) {
+  extern __shared__ float sgr[];                  // 64 entries x P rank values
+  const int lane = threadIdx.x;
+  const int64_t sg = blockIdx.x;
   const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
   if (sg >= nseg) return;
   const int32_t* start = SIDE == 0 ? v.segc_start : v.segr_start;
@@ -200,22 +208,53 @@ __global__ __launch_bounds__(256) void k_sp_grad(SpV v, const float* __restrict_
   float u[KR], uc[KR], fs[KR], y[KR];
 #pragma unroll
   for (int k = 0; k < KR; ++k) u[k] = uc[k] = fs[k] = y[k] = 0.f;
-#pragma unroll 8
-  for (int j = 0; j < cnt; ++j) {
-    const int64_t row = __builtin_amdgcn_readlane(rowl, j);
-    const float qq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, ql), j));
-    const float qbb = MU ? 0.f : __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qbl), j));
+  const int P = KR == 1 ? (int)((R + 3) & ~3) : 64;
+  const bool vec = (R & 3) == 0 && (reinterpret_cast<uintptr_t>(F) & 15) == 0;
+  const bool staged = cnt > SG_DIRECT;
 #pragma unroll
-    for (int k = 0; k < KR; ++k) {
-      const int64_t r = lane + 64 * k;
-      const float f = r < R ? F[row * R + r] : 0.f;
+  for (int k = 0; k < KR; ++k) {                  // ranks 64 k .. 64 k + rw
+    const int64_t rb = 64 * k;
+    const int rw = (int)std::min<int64_t>(64, R - rb);
+    if (rw <= 0) break;
+    // entry j's value of this lane's rank (f), added to the four sums in entry order
+    auto add = [&](int j, float f) {
+      const float qq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, ql), j));
+      const float qbb =
+          MU ? 0.f : __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qbl), j));
       u[k] = fmaf(f, qq, u[k]);
       if (!MU) {
         uc[k] = fmaf(f, qq - 1.f, uc[k]);
         fs[k] += f;
         y[k] = fmaf(f * f, qbb, y[k]);
       }
+    };
+    if (!staged) {
+#pragma unroll 8
+      for (int j = 0; j < cnt; ++j) {
+        const int64_t re = __builtin_amdgcn_readlane(rowl, j);
+        add(j, lane < rw ? F[re * R + rb + lane] : 0.f);
+      }
+      continue;
     }
+    if (k > 0) __syncthreads();                   // the previous chunk's reads are done
+    if (vec) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {              // entry e = d / 16, float4 c = d % 16
+        const int d = j * 64 + lane, e = d >> 4, c = d & 15;
+        const int re = __shfl(rowl, e);
+        if (e < cnt && 4 * c < rw)
+          *reinterpret_cast<f32x4*>(sgr + e * P + 4 * c) =
+              *reinterpret_cast<const f32x4*>(F + (int64_t)re * R + rb + 4 * c);
+      }
+    } else {
+      for (int j = 0; j < cnt; ++j) {
+        const int64_t re = __builtin_amdgcn_readlane(rowl, j);
+        if (lane < rw) sgr[j * P + lane] = F[re * R + rb + lane];
+      }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < cnt; ++j) add(j, lane < rw ? sgr[j * P + lane] : 0.f);
   }
   const int64_t stride = nseg * R;
 #pragma unroll
@@ -283,15 +322,16 @@ static hipError_t grad_launch(const SpV& v, const float* F, const float* q, cons
                               int64_t N, int64_t T, int64_t R, float* gp, double* vseg, float* pu, float* puc,
                               float* py, double* vpart, hipStream_t s) {
   const int64_t nseg = SIDE == 0 ? v.nseg_c : v.nseg_r;
-  const dim3 grid((unsigned)std::max<int64_t>(1, cdiv(nseg, 4)));
+  const dim3 grid((unsigned)std::max<int64_t>(1, nseg));      // a workgroup (one wave) per segment
+  const size_t lds = (size_t)64 * (R <= 64 ? ((R + 3) & ~int64_t(3)) : 64) * sizeof(float);
   const char* gname = SIDE == 0 ? (MU ? "sp_grad_mu_H" : "sp_grad_H") : (MU ? "sp_grad_mu_W" : "sp_grad_W");
   prof_begin(gname, s);
   if (R <= 64)
-    hipLaunchKernelGGL((k_sp_grad<SIDE, 1, MU>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 1, MU>), grid, dim3(64), lds, s, v, F, q, qb, N, T, R, gp, vseg);
   else if (R <= 128)
-    hipLaunchKernelGGL((k_sp_grad<SIDE, 2, MU>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 2, MU>), grid, dim3(64), lds, s, v, F, q, qb, N, T, R, gp, vseg);
   else
-    hipLaunchKernelGGL((k_sp_grad<SIDE, 4, MU>), grid, dim3(256), 0, s, v, F, q, qb, N, T, R, gp, vseg);
+    hipLaunchKernelGGL((k_sp_grad<SIDE, 4, MU>), grid, dim3(64), lds, s, v, F, q, qb, N, T, R, gp, vseg);
   prof_end(gname, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
