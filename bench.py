@@ -73,6 +73,9 @@ def kernel_key(rocprof_name):
                 return "qmax16"
         if base == "k_ratio":
             return {"0": "ratio_H", "1": "ratio_W"}.get(parts[0], "ratio_" + parts[0])
+        if base in ("k_sp_grad", "k_sp_cost", "k_sp_comb", "k_sp_cost_comb"):
+            mu = "_mu" if base == "k_sp_grad" and parts[-1] == "true" else ""
+            return base[2:] + mu + ("_H" if parts[0] == "0" else "_W")
     if side is not None:
         return base[2:] + ("_H" if side == "0" else "_W")
     return base[2:] if base.startswith("k_") else base
@@ -293,7 +296,8 @@ def sparse_main(args):
     nbytes = sparse_kernel_bytes(dom, N, T, R, sv.nnz, nseg_r, nseg_c)
     achieved = nbytes / (cands[dom]["avg_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "avg_ms": cands[dom]["avg_ms"], "achieved": achieved,
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                "traffic": traffic_of(dom, "sparse_" + args.sparse)}
     target = None
     if not args.no_target:
         Wm, Hm = W0.clone(), H0.clone()

@@ -1,0 +1,40 @@
+"""Host logic of bench.py (no GPU): the mapping from rocprofv3 kernel names to
+the kernel names the library's profiler uses, which the traffic and roofline
+figures are keyed by, and the multi-GPU refusal."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("rocprof, key", [
+    ("void dna::k_rgh_H<false, 0>(float const*, float const*)", "rgh_H"),
+    ("dna::k_rgh_W<true, 2>(float const*)", "rgh_W"),
+    ("dna::k_costf_H(float const*)", "costf_H"),
+    ("dna::k_cand_H<2, 32>(float const*)", "cand_H"),
+    ("dna::k_ratio<1, 0>(float const*)", "ratio_W"),
+    ("dna::k_sp_grad<0, 1, false>(dna::SpV, float const*)", "sp_grad_H"),
+    ("dna::k_sp_grad<1, 2, true>(dna::SpV, float const*)", "sp_grad_mu_W"),
+    ("dna::k_sp_cost<0>(dna::SpV, float const*)", "sp_cost_H"),
+    ("dna::k_sp_cost_comb<1>(dna::SpV, double const*)", "sp_cost_comb_W"),
+    ("dna::k_sp_comb<1, true>(dna::SpV, float const*)", "sp_comb_W"),
+    ("dna::k_sp_qz(dna::SpV, float const*)", "sp_qz"),
+])
+def test_kernel_key(rocprof, key):
+    assert bench.kernel_key(rocprof) == key
+
+
+def test_traffic_missing_tag_is_none():
+    assert bench.traffic_of("rgh_H", "no_such_workload") is None
+
+
+def test_more_than_one_gpu_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
