@@ -298,6 +298,8 @@ def sparse_main(args):
     roofline = {"bound": "hbm", "kernel": dom, "avg_ms": cands[dom]["avg_ms"], "achieved": achieved,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                 "traffic": traffic_of(dom, "sparse_" + args.sparse)}
+    if roofline["traffic"] is not None:
+        roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     target = None
     if not args.no_target:
         Wm, Hm = W0.clone(), H0.clone()
