@@ -24,7 +24,6 @@ CFLAGS = [
     "-Wno-unused-function", "-Wno-unused-variable",
     # no packed-FP32 instructions in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics",
 ]
 SOURCES = ["api.hip", "kernels_fwd.hip", "kernels_adj.hip", "kernels_16.hip", "kernels_fused.hip",
            "kernels_sparse.hip"]

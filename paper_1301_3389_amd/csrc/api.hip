@@ -143,7 +143,11 @@ struct Layout {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
+// Q and Q-bar (N x T fp32 each) are carved only where a kernel reads them: Q
+// for the tiled fp32 products (DNA and MU) when R > FUSED_MAX_R, Q-bar for the
+// tiled fp32 DNA products, and both for the unrolled adjoint (`adj`).  The
+// 16-bit forms keep their 16-bit Q, Q - 1 and Q-bar in their own scratch.
+static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16, bool adj = false) {
   Layout L;
   L.sh = choose_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM));
   L.sw = choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM));
@@ -165,8 +169,9 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16) {
   const size_t klt = (size_t)L.rt_m * L.rt_n;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-  L.q = take(nt * 4);
-  L.qb = take(nt * 4);
+  const bool tiled = R > FUSED_MAX_R;
+  L.q = take((adj || tiled) ? nt * 4 : 0);
+  L.qb = take((adj || (tiled && !with16)) ? nt * 4 : 0);
   L.pu = take(psplit * 4);
   L.puc = take(psplit * 4);
   L.py = take(psplit * 4);
@@ -197,7 +202,7 @@ struct AdjLayout {
 
 static AdjLayout make_adj_layout(int64_t N, int64_t T, int64_t R) {
   AdjLayout A;
-  A.base = make_layout(N, T, R, false);
+  A.base = make_layout(N, T, R, false, true);
   A.swb = choose_split(T, cdiv(R, WB_BN) * cdiv(N, WB_BM));
   size_t off = A.base.total;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -285,8 +290,7 @@ static dna_status checked_end(int* chk, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Shared stages.
-// The 16-bit path reuses the Q / Q-bar buffers (16-bit Q and Q - 1 fit in the
-// fp32 Q buffer, 16-bit Q-bar in the fp32 one) and carves its scale buffers.
+// The 16-bit path's operands, 16-bit Q, Q - 1, Q-bar and scale buffers.
 static Scratch16 scratch16(void* ws, const Layout& L, int64_t N, int64_t T, int64_t R) {
   return scratch16_carve(at<char>(ws, L.s16), N, T, R);
 }
@@ -779,8 +783,23 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
     float* Gout = (k == 0) ? dH_init : G[k & 1];
     RatioArgs ra{V, W, Hk, N, T, R, Q, Qb, vpart, nullptr, nullptr, Z};
     DNA_HIP(launch_ratio(RM_ADJ, ra, s), "ratio_adj");
-    DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
-    DNA_HIP(launch_cand_bwd_H(Hk, pu, puc, py, L.sh.splits, c32, vpart, L.rt_m, T, R, o->eps, o->alpha,
+    // u, u_c, y and the V sums from the product path and split the forward's
+    // run_candidates took, so that every branch of the candidate arithmetic
+    // (gain form, floor, cap, value floor) repeats bit for bit
+    int sp = L.sh.splits, vtiles = L.rt_m;
+    if (R <= FUSED_MAX_R) {
+      DNA_HIP(launch_rgh(0, V, W, Hk, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, SumJob{}, nullptr, s),
+              "rgh_H");
+      sp = L.shf.splits;
+      vtiles = L.shf.splits;
+    } else {
+      DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
+    }
+    if (sp > 8 && T < 256 * 32) {
+      DNA_HIP(launch_fold_splits(pu, puc, py, sp, R * T, s), "fold_splits");
+      sp = 1;
+    }
+    DNA_HIP(launch_cand_bwd_H(Hk, pu, puc, py, sp, c32, vpart, vtiles, T, R, o->eps, o->alpha,
                               sel_ckpt + (int64_t)k * T, Gin, Ub, Yb, Hd, Cb, sbar, s), "cand_bwd_H");
     DNA_HIP(launch_zbar(V, Z, W, Ub, Yb, sbar, N, T, R, Zbar, dV, acc, s), "zbar");
     {

@@ -101,6 +101,16 @@ __device__ __forceinline__ float log2_1p(float u) {
   return (d == 0.f) ? series : general;
 }
 
+// log2(z_MU / z_DNA) for z_DNA, z_MU > 0 given u = dZ / z_DNA: the log1p form
+// while the ratio is near 1; below 1/2 the ratio itself, formed as z_MU / z_DNA
+// (1 + u would lose its relative precision, or fall to or below zero through
+// rounding, when z_MU is far smaller than z_DNA).
+__device__ __forceinline__ float log2_ratio(float u, float zM, float izN) {
+  const float direct = log2_hw(zM * izN);
+  const float near1 = log2_1p(fmaxf(u, -0.5f));
+  return (u < -0.5f) ? direct : near1;
+}
+
 __device__ __forceinline__ double xlog2x_over(float v, float z) {
   // v log2(v/z) for v > 0, z > 0 (the summand of eq. 1 and steps 9/14, base 2)
   return (double)(v * log2_hw(v * __builtin_amdgcn_rcpf(z)));
@@ -121,7 +131,8 @@ __device__ __forceinline__ int cost_acc(float x, float zN, float dz, double& s0,
   const bool okN = zN > 0.f, okM = zM > 0.f;
   const float izN = __builtin_amdgcn_rcpf(zN);
   const float l0 = log2_hw((pos && okN) ? x * izN : 1.f);
-  const float l1 = log2_1p((pos && okN && okM) ? dz * izN : 0.f);
+  const bool both = pos && okN && okM;
+  const float l1 = log2_ratio(both ? dz * izN : 0.f, both ? zM : 1.f, both ? izN : 1.f);
   s0 += (double)(x * l0);
   s1 -= (double)(x * l1);
   int fl = 0;
@@ -140,7 +151,8 @@ __device__ __forceinline__ int cost_acc_f(float x, float zN, float dz, float& a0
   const bool okN = zN > 0.f, okM = zM > 0.f;
   const float izN = __builtin_amdgcn_rcpf(zN);
   const float l0 = log2_hw((pos && okN) ? x * izN : 1.f);
-  const float l1 = log2_1p((pos && okN && okM) ? dz * izN : 0.f);
+  const bool both = pos && okN && okM;
+  const float l1 = log2_ratio(both ? dz * izN : 0.f, both ? zM : 1.f, both ? izN : 1.f);
   a0 += x * l0;
   a1 -= x * l1;
   int fl = 0;

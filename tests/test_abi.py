@@ -54,8 +54,12 @@ def test_workspace_bytes(lib):
     small = ws(8, 8, 2, ctypes.byref(o))
     big = ws(1024, 8192, 64, ctypes.byref(o))
     assert 0 < small < big
-    # Q and Q-bar alone need 2 * N * T floats
-    assert big >= 2 * 1024 * 8192 * 4
+    # the fused path (R <= 64) keeps Q and Q-bar on chip: no pair of N x T buffers
+    assert big < 2 * 1024 * 8192 * 4
+    # the tiled fp32 path (R > 64) hands Q and Q-bar over in 2 * N * T floats
+    assert ws(1024, 8192, 65, ctypes.byref(o)) >= 2 * 1024 * 8192 * 4
+    # the unrolled adjoint reads both at any rank
+    assert dna._lib_uws(1024, 8192, 64, ctypes.byref(o)) >= 2 * 1024 * 8192 * 4
 
 
 def test_invalid_arguments_rejected_before_launch():
