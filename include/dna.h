@@ -155,6 +155,24 @@ dna_status dna_iterate(const float* V, float* W, float* H,
                        int64_t N, int64_t T, int64_t R, int iters,
                        const dna_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): dna_iterate on a scratch
+ * array of DNA_NOALLOC_SCRATCH_BYTES that the library itself holds, one per GPU,
+ * from the library's load until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); the caller passes only
+ * the inputs and outputs, which are those of dna_iterate, and the current
+ * device's array is used (`stream` must belong to the current device).
+ * Problems whose dna_workspace_bytes() exceeds DNA_NOALLOC_SCRATCH_BYTES return
+ * DNA_EUNSUPPORTED before anything is enqueued (dna_last_error() gives both
+ * sizes).  Every call on one GPU shares that GPU's array and leaves its contents
+ * behind; calls that overlap on one GPU (concurrent streams or host threads)
+ * race on it and must be serialised by the caller.  Results equal dna_iterate's
+ * on the same inputs. */
+#define DNA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dna_status dna_iterate_noalloc(const float* V, float* W, float* H,
+                               int64_t N, int64_t T, int64_t R, int iters,
+                               const dna_opts* opts, void* stream);
+
 /* ---- Sparse V (Sec. 4.2: term-document matrices with 0.2-0.35% nonzeros) ---
  * Only the nonzeros of V enter Q, Q-bar and the costs (end of Sec. 3), so the
  * O(NRT) products become O(nnz R) gathers.  V is described by its nonzeros (all

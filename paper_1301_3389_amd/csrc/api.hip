@@ -567,6 +567,37 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
   return epilogue(c);
 }
 
+// ---------------------------------------------------------------------------
+// dna_iterate_noalloc: dna_iterate on a scratch array the library owns, for
+// callers that cannot allocate device memory.  The array is a file-scope
+// device variable: every GPU the library runs on holds its own copy, at its own
+// address, from code-object load until the process ends.  In host code its name
+// is a host-side stand-in, not a device address; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and is
+// the only form of the array host code passes anywhere.  No kernel needs the
+// workspace to start at any particular content, so nothing is cleared.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[DNA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+static dna_status scratch_address(void** out) {
+  int dev = -1;
+  DNA_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(DNA_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    DNA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(DNA_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return DNA_OK;
+}
+
 // One MU half-step (eq. 11) on the prologue's state; with_cost writes the input
 // state's per-column (row) cost to d_out.
 static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R,
@@ -610,6 +641,24 @@ static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N
     DNA_HIP(launch_mu_W(W, pu, L.sw.splits, c32, N, R, cpart, L.rt_n, with_cost ? d_out : nullptr, c.s), "mu_W");
   }
   return DNA_OK;
+}
+
+dna_status dna_iterate_noalloc(const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R, int iters,
+                               const dna_opts* o, void* stream) {
+  if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
+  if (iters < 0) return fail(DNA_EINVAL, "iters must be >= 0");
+  DNA_TRY(check_dims(N, T, R));
+  DNA_TRY(check_opts(o));
+  const size_t need = make_layout(N, T, R, o->gemm != DNA_GEMM_FP32).total;
+  if (need > DNA_NOALLOC_SCRATCH_BYTES) {
+    std::snprintf(g_err, sizeof(g_err),
+                  "dna_iterate_noalloc: this problem needs %zu bytes of workspace, more than the %zu-byte scratch "
+                  "array; call dna_iterate with a workspace instead", need, (size_t)DNA_NOALLOC_SCRATCH_BYTES);
+    return DNA_EUNSUPPORTED;
+  }
+  void* ws = nullptr;
+  DNA_TRY(scratch_address(&ws));
+  return dna_iterate(V, W, H, N, T, R, iters, o, ws, DNA_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 dna_status mu_update(int side, const float* V, float* W, float* H, int64_t N, int64_t T, int64_t R,

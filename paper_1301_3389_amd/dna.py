@@ -57,6 +57,7 @@ _lib_normalize = _decl("dna_normalize", _int, _int, _p, _p, _i64, _i64, _i64, _O
 _lib_update_H = _decl("dna_update_H", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_update_W = _decl("dna_update_W", _int, _p, _p, _p, _i64, _i64, _i64, _OP, _p, _sz, _p, _p, _p, _p)
 _lib_iterate = _decl("dna_iterate", _int, _p, _p, _p, _i64, _i64, _i64, _int, _OP, _p, _sz, _p)
+_lib_iterate_noalloc = _decl("dna_iterate_noalloc", _int, _p, _p, _p, _i64, _i64, _i64, _int, _OP, _p)
 class SparseVStruct(ctypes.Structure):
     _fields_ = [("nnz", ctypes.c_int64), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("row_of", ctypes.c_void_p), ("csc_row", ctypes.c_void_p), ("csc_col", ctypes.c_void_p),
@@ -92,7 +93,7 @@ _lib_build_info = _decl("dna_build_info", ctypes.c_char_p)
 
 EXPORTED = [
     "dna_default_opts", "dna_workspace_bytes", "dna_normalize", "dna_update_H", "dna_update_W",
-    "dna_iterate", "dna_sparse_workspace_bytes", "dna_sparse_update_H", "dna_sparse_update_W",
+    "dna_iterate", "dna_iterate_noalloc", "dna_sparse_workspace_bytes", "dna_sparse_update_H", "dna_sparse_update_W",
     "dna_sparse_kl_cost", "dna_sparse_mu_update", "dna_sparse_mu_iterate", "dna_sparse_iterate", "mu_update", "mu_iterate", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
     "dna_unrolled_workspace_bytes", "dna_unrolled_H_fwd", "dna_unrolled_H_bwd",
     "dna_status_string", "dna_last_error", "dna_profile_enable", "dna_profile_reset",
@@ -243,6 +244,14 @@ def iterate(V, W, H, iters, **kw):
     ws, nb = workspace(N, T, R, o)
     _check(_lib_iterate(_ptr(V), _ptr(W), _ptr(H), N, T, R, int(iters), ctypes.byref(o), _ptr(ws), ws.numel(),
                         _stream()))
+
+
+def iterate_noalloc(V, W, H, iters, **kw):
+    """``iterate`` on the library's own scratch array (dna_iterate_noalloc):
+    no workspace is allocated, by torch or by the library."""
+    N, T, R = _dims(V, W, H)
+    o = make_opts(**kw)
+    _check(_lib_iterate_noalloc(_ptr(V), _ptr(W), _ptr(H), N, T, R, int(iters), ctypes.byref(o), _stream()))
 
 
 def mu_update(side, V, W, H, with_cost=False, **kw):

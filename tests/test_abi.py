@@ -62,6 +62,22 @@ def test_workspace_bytes(lib):
     assert dna._lib_uws(1024, 8192, 64, ctypes.byref(o)) >= 2 * 1024 * 8192 * 4
 
 
+def test_noalloc_rejects_oversized_problems_before_any_launch(lib):
+    """dna_iterate_noalloc refuses a problem whose workspace exceeds its
+    scratch array on the host, naming both sizes (no HIP call is made)."""
+    from paper_1301_3389_amd import dna
+    o = dna.make_opts()
+    fake = ctypes.c_void_p(256)            # never dereferenced: the call returns first
+    N, T, R = 4096, 32768, 512
+    st = dna._lib_iterate_noalloc(fake, fake, fake, N, T, R, 1, ctypes.byref(o), None)
+    assert st == 6, st                     # DNA_EUNSUPPORTED
+    msg = dna._lib_last_error().decode()
+    need = dna._lib_ws(N, T, R, ctypes.byref(o))
+    assert str(need) in msg and str(64 << 20) in msg, msg
+    assert dna._lib_iterate_noalloc(fake, fake, fake, 8, 8, 2, -1, ctypes.byref(o), None) == 1
+    assert dna._lib_iterate_noalloc(None, fake, fake, 8, 8, 2, 1, ctypes.byref(o), None) == 1
+
+
 def test_invalid_arguments_rejected_before_launch():
     from paper_1301_3389_amd import dna
     o = dna.make_opts()
