@@ -11,7 +11,7 @@ import oracle
 from oracle import dna_oracle as O
 from paper_1301_3389_amd import synth
 from parity_util import (FLOOR32, SELECT_TIE, STATE_TIE, STEP_TOL, TRAJ_TOL, cost_err, gpu, host, log_result,
-                         recon_gap, rel_cols, selection_report)
+                         recon_gap, rel_cols, rescore, selection_report)
 
 pytestmark = pytest.mark.gpu
 
@@ -118,6 +118,8 @@ def test_select_from_identical_candidates(dna, shape, side):
 
 def _check_update(dna, V, W, H, side, name):
     Vg, Wg, Hg = gpu(V), gpu(W), gpu(H)
+    # the GPU's own candidates from the same state (the kernels the update runs)
+    Xmu, Xn = dna.candidates(side, Vg, Wg, Hg)
     if side == 0:
         m, d, g = dna.update_H(Vg, Wg, Hg, mask=True, d_sel=True, margin=True)
         got = host(Hg)
@@ -131,6 +133,8 @@ def _check_update(dna, V, W, H, side, name):
     Wd, Hd = W.astype(float), H.astype(float)
     zgap = recon_gap(Wd @ r.X_mu, Wd @ r.X_newton, 0) if side == 0 else recon_gap(r.X_mu @ Hd, r.X_newton @ Hd, 1)
     rep = selection_report(mask, r.chose_newton, r.margin, r.d_mu, STATE_TIE, zgap)
+    ch, mg, dm, zg = rescore(V, W if side == 0 else H, host(Xmu), host(Xn), side)
+    rep_own = selection_report(mask, ch, mg, dm, SELECT_TIE, zg)
     same = mask == r.chose_newton
     err = rel_cols(got, r.X, ax)[same]
     vsum = V.astype(float).sum(axis=0 if side == 0 else 1)
@@ -140,7 +144,8 @@ def _check_update(dna, V, W, H, side, name):
     err_other = rel_cols(got, other, ax)[~same]
     err_d = cost_err(host(d)[same], r.d_sel[same], vsum[same])
     log_result(name, {"side": side, **rep, "max_err": float(err.max()) if err.size else 0.0,
-                      "err_dsel": err_d})
+                      "err_dsel": err_d, "own": rep_own})
+    assert rep_own["n_flips_above_tie"] == 0, rep_own
     assert rep["n_flips_above_tie"] == 0, rep
     assert err.size == 0 or err.max() <= STEP_TOL
     assert err_other.size == 0 or err_other.max() <= STEP_TOL
@@ -328,6 +333,50 @@ def test_trajectory_config2_long(dna):
     assert rel.max() <= TRAJ_TOL
 
 
+def _golden_config2():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_trajectory.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_trajectory_config2_full(dna):
+    """The full N=1024 T=8192 R=64 workload, 200 DNA iterations in the launch
+    configuration the benchmark times (one dna_iterate call per iteration),
+    against the FP64 oracle's trajectory with the float32 value floor
+    (tests/golden/config2_trajectory.json, written by the committed script that
+    calls only the oracle): relative KL within 1e-4 after every iteration."""
+    w = synth.config2()
+    ref = np.array(_golden_config2()["dna_floor"])
+    Vg, Wg, Hg = gpu(w.V), gpu(w.W), gpu(w.H)
+    kls = host(dna.fit(Vg, Wg, Hg, 200, method="dna", record_kl=True))
+    rel = np.abs(kls - ref) / np.abs(ref)
+    log_result("trajectory_config2_full", {"max_rel": float(rel.max()), "kl_last": float(kls[-1]),
+                                           "kl_ref_last": float(ref[-1])})
+    assert rel.max() <= TRAJ_TOL
+
+
+def test_mu_target_kl_config2_full(dna):
+    """The benchmark's target KL (float32 GPU MU, 1000 iterations from the same
+    start on the full N=1024 T=8192 R=64 workload) against the FP64 oracle's
+    1000-iteration MU trajectory: within 1e-4 at every 50th iteration and at the
+    end."""
+    ref = np.array(_golden_config2()["mu_floor"])
+    w = synth.config2()
+    Vg, Wg, Hg = gpu(w.V), gpu(w.W), gpu(w.H)
+    dna.normalize(0, Wg, Hg)
+    got = [dna.kl_cost(Vg, Wg, Hg).item()]
+    for k in range(20):
+        dna.mu_iterate(Vg, Wg, Hg, 50)
+        got.append(dna.kl_cost(Vg, Wg, Hg).item())
+    got = np.array(got)
+    rel = np.abs(got - ref[::50]) / ref[::50]
+    log_result("mu_target_kl_config2_full", {"max_rel": float(rel.max()), "kl_gpu": float(got[-1]),
+                                             "kl_oracle": float(ref[-1])})
+    assert rel.max() <= TRAJ_TOL
+
+
 # --------------------------------------------------------------------------- full sizes, sampled
 
 def _sampled_step(dna, V, W, H, n_cols=24, n_rows=24, seed=0):
@@ -339,23 +388,31 @@ def _sampled_step(dna, V, W, H, n_cols=24, n_rows=24, seed=0):
     cols = np.sort(rng.choice(T, size=min(n_cols, T), replace=False))
     rows = np.sort(rng.choice(N, size=min(n_rows, N), replace=False))
     H1 = Hg.clone()
+    Xmu, Xn = dna.candidates(0, Vg, Wg, Hg)
     m, d, g = dna.update_H(Vg, Wg, H1, mask=True, d_sel=True, margin=True)
     r = oracle.h_step(V[:, cols], W, H[:, cols], value_floor=FLOOR32)
+    ch, mg, dm, zo = rescore(V[:, cols], W, host(Xmu)[:, cols], host(Xn)[:, cols], 0)
+    del Xmu, Xn
     got = host(H1)[:, cols]
     mask = host(m)[cols].astype(bool)
     Wd = W.astype(float)
     zg = recon_gap(Wd @ r.X_mu, Wd @ r.X_newton, 0)
     rep_h = selection_report(mask, r.chose_newton, r.margin, r.d_mu, STATE_TIE, zg)
+    rep_h["own"] = selection_report(mask, ch, mg, dm, SELECT_TIE, zo)
     same = mask == r.chose_newton
     err_h = rel_cols(got, r.X, 0)[same]
     W1 = Wg.clone()
+    Xmu, Xn = dna.candidates(1, Vg, Wg, Hg)
     m2, d2, g2 = dna.update_W(Vg, W1, Hg, mask=True, d_sel=True, margin=True)
     rw = oracle.w_step(V[rows], W[rows], H, value_floor=FLOOR32)
+    ch, mg, dm, zo = rescore(V[rows], H, host(Xmu)[rows], host(Xn)[rows], 1)
+    del Xmu, Xn
     gotw = host(W1)[rows]
     maskw = host(m2)[rows].astype(bool)
     Hd = H.astype(float)
     zgw = recon_gap(rw.X_mu @ Hd, rw.X_newton @ Hd, 1)
     rep_w = selection_report(maskw, rw.chose_newton, rw.margin, rw.d_mu, STATE_TIE, zgw)
+    rep_w["own"] = selection_report(maskw, ch, mg, dm, SELECT_TIE, zo)
     samew = maskw == rw.chose_newton
     err_w = rel_cols(gotw, rw.X, 1)[samew]
     return rep_h, err_h, rep_w, err_w
@@ -370,6 +427,7 @@ def test_full_size_sampled(dna, k):
                                      "err_w": float(err_w.max()) if err_w.size else 0.0,
                                      "meta": {kk: v for kk, v in w.meta.items() if isinstance(v, (int, float))}})
     assert rep_h["n_flips_above_tie"] == 0 and rep_w["n_flips_above_tie"] == 0
+    assert rep_h["own"]["n_flips_above_tie"] == 0 and rep_w["own"]["n_flips_above_tie"] == 0
     assert err_h.size == 0 or err_h.max() <= STEP_TOL
     assert err_w.size == 0 or err_w.max() <= STEP_TOL
     del w

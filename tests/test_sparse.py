@@ -226,3 +226,58 @@ def test_sparse_unsupported(dna):
     with pytest.raises(dna.DNAError) as e:
         dna.sparse_iterate(sv, gpu(W), gpu(H), -1)
     assert e.value.status == 1
+
+
+@pytest.mark.gpu
+def test_sparse_tdt2_shape_sampled(dna):
+    """One sparse H step and one W step at the TDT2-shaped workload the
+    benchmark times (36771 x 10212, 0.35% nonzeros, Zipf row lengths, R = 40),
+    checked against the FP64 oracle on 24 sampled columns (H step: columns are
+    independent given W) and 24 sampled rows (W step: rows independent given H),
+    each formed densely from the nonzeros."""
+    rows, cols, vals, N, T, W, H = synth.sparse_workload("tdt2", R=40)
+    print(f"sparse tdt2 shape N={N} T={T} nnz={rows.size}", flush=True)
+    sv = dna.SparseV(rows, cols, vals, N, T, device=torch.device("cuda:0"))
+    rng = np.random.default_rng(40)
+    cs = np.sort(rng.choice(T, 24, replace=False))
+    # a few of the longest rows (the Zipf head) and random ones
+    counts = np.bincount(rows, minlength=N)
+    rs = np.sort(np.unique(np.concatenate([np.argsort(counts)[-4:], rng.choice(N, 20, replace=False)])))
+    Vc = np.zeros((N, cs.size), np.float32)
+    sel = np.isin(cols, cs)
+    Vc[rows[sel], np.searchsorted(cs, cols[sel])] = vals[sel]
+    Vr = np.zeros((rs.size, T), np.float32)
+    sel = np.isin(rows, rs)
+    Vr[np.searchsorted(rs, rows[sel]), cols[sel]] = vals[sel]
+    Wg, Hg = gpu(W), gpu(H)
+    H1 = Hg.clone()
+    m, d, g = dna.sparse_update_H(sv, Wg, H1, mask=True, d_sel=True, margin=True)
+    r = oracle.h_step(Vc, W, H[:, cs], value_floor=FLOOR32)
+    mask = host(m)[cs].astype(bool)
+    Wd = W.astype(float)
+    rep_h = selection_report(mask, r.chose_newton, r.margin, r.d_mu, STATE_TIE,
+                             recon_gap(Wd @ r.X_mu, Wd @ r.X_newton, 0))
+    got = host(H1)[:, cs]
+    same = mask == r.chose_newton
+    err_h = rel_cols(got, r.X, 0)[same]
+    err_h_other = rel_cols(got, np.where(r.chose_newton[None, :], r.X_mu, r.X_newton), 0)[~same]
+    err_dh = cost_err(host(d)[cs][same], r.d_sel[same], Vc.astype(float).sum(0)[same])
+    W1 = Wg.clone()
+    m2, d2, g2 = dna.sparse_update_W(sv, W1, Hg, mask=True, d_sel=True, margin=True)
+    rw = oracle.w_step(Vr, W[rs], H, value_floor=FLOOR32)
+    maskw = host(m2)[rs].astype(bool)
+    Hd = H.astype(float)
+    rep_w = selection_report(maskw, rw.chose_newton, rw.margin, rw.d_mu, STATE_TIE,
+                             recon_gap(rw.X_mu @ Hd, rw.X_newton @ Hd, 1))
+    gotw = host(W1)[rs]
+    samew = maskw == rw.chose_newton
+    err_w = rel_cols(gotw, rw.X, 1)[samew]
+    err_w_other = rel_cols(gotw, np.where(rw.chose_newton[:, None], rw.X_mu, rw.X_newton), 1)[~samew]
+    err_dw = cost_err(host(d2)[rs][samew], rw.d_sel[samew], Vr.astype(float).sum(1)[samew])
+    log_result("sparse_tdt2_sampled", {"h": rep_h, "w": rep_w, "err_h": float(err_h.max()) if err_h.size else 0.0,
+                                       "err_w": float(err_w.max()) if err_w.size else 0.0,
+                                       "err_dsel_h": err_dh, "err_dsel_w": err_dw})
+    assert rep_h["n_flips_above_tie"] == 0 and rep_w["n_flips_above_tie"] == 0, (rep_h, rep_w)
+    for e in (err_h, err_h_other, err_w, err_w_other):
+        assert e.size == 0 or e.max() <= STEP_TOL
+    assert err_dh <= 1.0 and err_dw <= 1.0
