@@ -169,6 +169,8 @@ def parse():
     ap.add_argument("--lam", type=float, default=0.0, help="eq. 2 weight of sum H")
     ap.add_argument("--streams", type=int, default=4,
                     help="--paper-sweep: also time this many independent problems on as many streams")
+    ap.add_argument("--no-r512", action="store_true",
+                    help="skip the R = 512 records (N=4096 T=32768, FP32 and BF16) of the default run")
     return ap.parse_args()
 
 
@@ -197,10 +199,11 @@ def timed_steps(dna, V, W, H, steps, gemm):
     return 1e3 * (time.perf_counter() - t0) / steps
 
 
-def iters_to_target(dna, V, W0, H0, kl_target, budget, gemm, chunk=10):
-    """DNA iterations (from the same start) until the KL is at or below the target;
-    the KL after every iteration is recorded on the device and checked every
-    `chunk` iterations.  Returns (iterations or None, last KL)."""
+def iters_to_targets(dna, V, W0, H0, targets, budget, gemm, chunk=10):
+    """DNA iterations (from the same start, step 1 first) until the KL is at or
+    below each of `targets`; the KL after every iteration is recorded on the
+    device and checked every `chunk` iterations.  Returns ({target: first
+    iteration or None}, last KL)."""
     import numpy as np
     import torch
     W, H = W0.clone(), H0.clone()
@@ -208,16 +211,40 @@ def iters_to_target(dna, V, W0, H0, kl_target, budget, gemm, chunk=10):
     kls = torch.empty(budget + 1, dtype=torch.float64, device=V.device)
     dna.kl_cost(V, W, H, out=kls[0:1])
     done = 0
+    hits = {t: None for t in targets}
     while done < budget:
         m = min(chunk, budget - done)
         for k in range(m):
             dna.iterate(V, W, H, 1, gemm=gemm)
             dna.kl_cost(V, W, H, out=kls[done + k + 1:done + k + 2])
         done += m
-        hit = np.nonzero(kls[:done + 1].cpu().numpy() <= kl_target)[0]
-        if hit.size:
-            return int(hit[0]), float(kls[hit[0]].item())
-    return None, float(kls[done].item())
+        host = kls[:done + 1].cpu().numpy()
+        for t in targets:
+            if hits[t] is None:
+                h = np.nonzero(host <= t)[0]
+                if h.size:
+                    hits[t] = int(h[0])
+        if all(v is not None for v in hits.values()):
+            break
+    return hits, float(kls[done].item())
+
+
+def mu_reference(dna, V, W0, H0, marks):
+    """MU (no cost) from the same start, step 1 first: the KL after each of the
+    iteration counts in `marks` (ascending) and the ms per MU iteration."""
+    import torch
+    W, H = W0.clone(), H0.clone()
+    dna.normalize(0, W, H)
+    kl, done, wall = {}, 0, 0.0
+    for m in marks:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dna.mu_iterate(V, W, H, m - done, with_cost=False)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        done = m
+        kl[m] = dna.kl_cost(V, W, H).item()
+    return kl, 1e3 * wall / marks[-1]
 
 
 def cpu_baseline(w, seconds):
@@ -243,8 +270,39 @@ def cpu_baseline(w, seconds):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "DNA iterations/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} full DNA iterations (FP64 NumPy) of the same workload from the same initial state"}
+    out = {"value": n / dt, "unit": "DNA iterations/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{n} full DNA iterations (FP64 NumPy) of the same workload from the same initial state",
+           "cpu_model": cpu_model()}
+    try:                                   # the same oracle on one thread
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            W1, H1 = oracle.normalize_w_columns(w.W, w.H)
+            t1 = time.perf_counter()
+            n1 = 0
+            while True:
+                H1 = oracle.h_step(V, W1, H1).X
+                W1, H1 = oracle.normalize_h_rows(W1, H1)
+                W1 = oracle.w_step(V, W1, H1).X
+                W1, H1 = oracle.normalize_w_columns(W1, H1)
+                n1 += 1
+                if time.perf_counter() - t1 >= seconds:
+                    break
+            out["single_thread"] = {"value": n1 / (time.perf_counter() - t1), "cores": 1,
+                                    "sample": f"{n1} full DNA iterations on one thread"}
+    except ImportError:  # pragma: no cover
+        pass
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return None
 
 
 def sparse_kernel_bytes(name, N, T, R, nnz, nseg_r, nseg_c):
@@ -435,7 +493,6 @@ def main():
               "needs one all-reduce of its N x R gradient sums and per-row costs)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1301_3389_amd import dna, synth
 
@@ -453,62 +510,13 @@ def main():
     regularised = args.rho > 0 or args.lam > 0
     if regularised:
         args.no_target = args.no_cpu_baseline = True
-    W, H = W0.clone(), H0.clone()
-    dna.normalize(0, W, H, **reg)                            # Algorithm 1 step 1
-    dna.iterate(V, W, H, args.warmup, gemm=gemm, **reg)
-    torch.cuda.synchronize()
-
-    # ---- timed region -----------------------------------------------------
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    dna.iterate(V, W, H, args.steps, gemm=gemm, **reg)   # args.steps full iterations, one call
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
-    ms_per_step = 1e3 * wall / args.steps
-    value = args.steps / wall
-
-    # ---- per-kernel HIP-event timing over a repeat of the timed region ---
-    dna.profile_reset()
-    dna.profile_enable(True)
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    dna.iterate(V, W, H, args.steps, gemm=gemm, **reg)
-    torch.cuda.synchronize()
-    prof_wall = time.perf_counter() - tp
-    stats = dna.profile_read()
-    dna.profile_enable(False)
-    kernels = {k: {"launches": n, "avg_ms": ms / max(n, 1), "total_ms": ms} for k, (n, ms) in stats.items()}
-    ranked = sorted(((k, v) for k, v in kernels.items() if kernel_work(k, N, T, R)
-                     and kernel_work(k, N, T, R)[0] == "flops"), key=lambda kv: -kv[1]["total_ms"])
-    dom, rec = ranked[0]
-    flops = kernel_work(dom, N, T, R)[1]
-    achieved = flops / (rec["avg_ms"] * 1e-3) / 1e12
-    peak = PEAK_FP32_TFLOPS if gemm == "fp32" else PEAK_16_TFLOPS
-    roofline = {"bound": "mfma", "kernel": dom, "avg_ms": rec["avg_ms"], "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": traffic_of(dom, args.traffic_tag)}
-    if roofline["traffic"] is not None:
-        roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-
-    alg_flops_iter = 16.0 * N * R * T
-    gflops = alg_flops_iter * value / 1e9
+    rec = dense_record(dna, V, W0, H0, gemm, args.steps, args.warmup, args.traffic_tag, reg)
 
     # ---- time to target KL (MU's KL after --mu-iters iterations) ----------
     target = None
     if not args.no_target:
-        Wm, Hm = W0.clone(), H0.clone()
-        dna.normalize(0, Wm, Hm)
-        torch.cuda.synchronize()
-        tm = time.perf_counter()
-        dna.mu_iterate(V, Wm, Hm, args.mu_iters, with_cost=False)
-        torch.cuda.synchronize()
-        mu_wall = time.perf_counter() - tm
-        kl_target = dna.kl_cost(V, Wm, Hm).item()
+        kl_mu, mu_ms = mu_reference(dna, V, W0, H0, [args.mu_iters])
+        kl_target = kl_mu[args.mu_iters]
         Wc, Hc = W0.clone(), H0.clone()
         dna.normalize(0, Wc, Hc)
         nc = min(100, args.mu_iters)
@@ -517,41 +525,135 @@ def main():
         dna.mu_iterate(V, Wc, Hc, nc, with_cost=True)
         torch.cuda.synchronize()
         mu_cost_ms = 1e3 * (time.perf_counter() - tc) / nc
+        mu_wall = mu_ms * args.mu_iters / 1e3
         target = {"target_kl": kl_target, "mu_iters": args.mu_iters,
-                  "mu_ms_per_iter_no_cost": 1e3 * mu_wall / args.mu_iters,
+                  "mu_ms_per_iter_no_cost": mu_ms,
                   "mu_ms_per_iter_with_cost": mu_cost_ms, "mu_time_to_target_s": mu_wall,
                   "dna_iter_budget": args.dna_iters}
         forms = [gemm] + (["fp32"] if gemm != "fp32" else [])
         for g in forms:
-            ms = ms_per_step if g == gemm else timed_steps(dna, V, W.clone(), H.clone(), 20, g)
-            k_hit, kl_last = iters_to_target(dna, V, W0, H0, kl_target, args.dna_iters, g)
-            rec = {"ms_per_iter": ms, "iters_to_target": k_hit,
-                   "time_to_target_s": (k_hit * ms / 1e3) if k_hit is not None else None,
-                   "kl_at_stop": kl_last}
+            ms = rec["ms_per_step"] if g == gemm else timed_steps(dna, V, W0.clone(), H0.clone(), 20, g)
+            hits, kl_last = iters_to_targets(dna, V, W0, H0, [kl_target], args.dna_iters, g)
+            k_hit = hits[kl_target]
+            r = {"ms_per_iter": ms, "iters_to_target": k_hit,
+                 "time_to_target_s": (k_hit * ms / 1e3) if k_hit is not None else None,
+                 "kl_at_stop": kl_last}
             if k_hit:
-                rec["speedup_vs_mu_no_cost"] = mu_wall / (k_hit * ms / 1e3)
-            target[f"dna_{g}"] = rec
+                r["speedup_vs_mu_no_cost"] = mu_wall / (k_hit * ms / 1e3)
+            target[f"dna_{g}"] = r
 
     out = {
-        "metric": METRIC, "value": value, "unit": "DNA iterations/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": rec["value"], "unit": "DNA iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[gemm],
         "accumulate": "f32 products, f64 cost and selection sums",
         "data": "synthetic",
         "config": {"workload": f"DNA KL-NMF, N={N} T={T} R={R}, {WORKLOADS[args.config]}",
                    "N": N, "T": T, "R": R, "iteration": "H step, step 16, W step, step 29",
                    "parallelism": "single GPU", **({"rho": args.rho, "lambda": args.lam} if regularised else {})},
-        "gpu_ms_per_step": gpu_ms / args.steps,
-        "algorithmic_gflops": gflops,
-        "mfma_frac_algorithmic": gflops / 1e3 / peak,
-        "roofline": roofline,
-        "kernels": kernels,
-        "profiled_ms_per_step": 1e3 * prof_wall / args.steps,
+        **{k: rec[k] for k in ("gpu_ms_per_step", "algorithmic_gflops", "mfma_frac_algorithmic", "roofline",
+                               "kernels", "profiled_ms_per_step")},
         "time_to_target": target,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    del V, W0, H0
+    if args.config == 2 and not args.no_r512 and not regularised:
+        torch.cuda.empty_cache()
+        out["r512"] = r512_records(dna, synth, dev, args)
     print(json.dumps(out))
+
+
+def dense_record(dna, V, W0, H0, gemm, steps, warmup, traffic_tag, reg=None):
+    """Timed DNA iterations (one dna_iterate call of `steps` iterations after
+    `warmup` untimed ones, step 1 first) and the per-kernel HIP-event times of
+    a repeat of the same call; the roofline record of the dominant flops kernel."""
+    import torch
+    reg = reg or {}
+    N, T = V.shape
+    R = W0.shape[1]
+    W, H = W0.clone(), H0.clone()
+    dna.normalize(0, W, H, **reg)                            # Algorithm 1 step 1
+    dna.iterate(V, W, H, warmup, gemm=gemm, **reg)
+    torch.cuda.synchronize()
+    # ---- timed region -----------------------------------------------------
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    dna.iterate(V, W, H, steps, gemm=gemm, **reg)            # `steps` full iterations, one call
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    # ---- per-kernel HIP-event timing over a repeat of the timed region ---
+    dna.profile_reset()
+    dna.profile_enable(True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    dna.iterate(V, W, H, steps, gemm=gemm, **reg)
+    torch.cuda.synchronize()
+    prof_wall = time.perf_counter() - tp
+    stats = dna.profile_read()
+    dna.profile_enable(False)
+    kernels = {k: {"launches": n, "avg_ms": ms / max(n, 1), "total_ms": ms} for k, (n, ms) in stats.items()}
+    ranked = sorted(((k, v) for k, v in kernels.items() if kernel_work(k, N, T, R)
+                     and kernel_work(k, N, T, R)[0] == "flops"), key=lambda kv: -kv[1]["total_ms"])
+    dom, krec = ranked[0]
+    flops = kernel_work(dom, N, T, R)[1]
+    achieved = flops / (krec["avg_ms"] * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if gemm == "fp32" else PEAK_16_TFLOPS
+    roofline = {"bound": "mfma", "kernel": dom, "avg_ms": krec["avg_ms"], "achieved": achieved,
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic_of(dom, traffic_tag)}
+    if roofline["traffic"] is not None:
+        roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    value = steps / wall
+    gflops = 16.0 * N * R * T * value / 1e9
+    return {"value": value, "ms_per_step": 1e3 * wall / steps, "gpu_ms_per_step": gpu_ms / steps,
+            "algorithmic_gflops": gflops, "mfma_frac_algorithmic": gflops / 1e3 / peak,
+            "roofline": roofline, "kernels": kernels, "profiled_ms_per_step": 1e3 * prof_wall / steps}
+
+
+def r512_records(dna, synth, dev, args):
+    """The high-rank workload (N=4096 T=32768 R=512, spectrogram-like) in the
+    plain FP32 form and the BF16 precision form: iterations/s, the dominant
+    kernel's roofline record, and the time to MU's KL after 200 and after 1000
+    iterations from the same start."""
+    import torch
+    w = synth.config3()
+    N, T = w.V.shape
+    R = w.W.shape[1]
+    V = torch.from_numpy(w.V).to(dev)
+    W0 = torch.from_numpy(w.W).to(dev)
+    H0 = torch.from_numpy(w.H).to(dev)
+    del w
+    out = {"config": {"workload": f"DNA KL-NMF, N={N} T={T} R={R}, {WORKLOADS[3]}", "N": N, "T": T, "R": R},
+           "steps": args.steps, "warmup": args.warmup}
+    for g in ("fp32", "bf16"):
+        rec = dense_record(dna, V, W0, H0, g, args.steps, args.warmup, workload_tag(3, g))
+        rec["kernels"] = {k: v for k, v in sorted(rec["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])[:8]}
+        rec["dtype"] = DTYPE[g]
+        out[g] = rec
+    if not args.no_target:
+        marks = [200, 1000]
+        kl_mu, mu_ms = mu_reference(dna, V, W0, H0, marks)
+        tt = {"mu_ms_per_iter": mu_ms, "target_kl": {str(m): kl_mu[m] for m in marks},
+              "mu_time_to_target_s": {str(m): m * mu_ms / 1e3 for m in marks}}
+        for g in ("fp32", "bf16"):
+            hits, kl_last = iters_to_targets(dna, V, W0, H0, [kl_mu[m] for m in marks], args.dna_iters, g)
+            ms = out[g]["ms_per_step"]
+            r = {"ms_per_iter": ms, "kl_at_stop": kl_last}
+            for m in marks:
+                k = hits[kl_mu[m]]
+                r[f"iters_to_mu{m}"] = k
+                r[f"time_to_mu{m}_s"] = k * ms / 1e3 if k is not None else None
+                if k:
+                    r[f"speedup_vs_mu{m}"] = (m * mu_ms) / (k * ms)
+            tt[f"dna_{g}"] = r
+        out["time_to_target"] = tt
+    return out
 
 
 if __name__ == "__main__":
