@@ -72,7 +72,7 @@ def kernel_key(rocprof_name):
             if maxonly == "true":
                 return "qmax16"
         if base == "k_ratio":
-            return {"0": "ratio_H", "1": "ratio_W"}.get(parts[0], "ratio_" + parts[0])
+            return {"0": "ratio_H", "1": "ratio_W", "8": "ratio_H", "9": "ratio_W"}.get(parts[0], "ratio_" + parts[0])
         if base in ("k_sp_grad", "k_sp_cost", "k_sp_comb", "k_sp_cost_comb"):
             mu = "_mu" if base == "k_sp_grad" and parts[-1] == "true" else ""
             return base[2:] + mu + ("_H" if parts[0] == "0" else "_W")
@@ -169,6 +169,8 @@ def parse():
     ap.add_argument("--lam", type=float, default=0.0, help="eq. 2 weight of sum H")
     ap.add_argument("--streams", type=int, default=4,
                     help="--paper-sweep: also time this many independent problems on as many streams")
+    ap.add_argument("--unrolled", action="store_true",
+                    help="time the differentiable unrolled H-solve (N=513 R=1024 T=4096, K=20): forward + backward")
     ap.add_argument("--no-r512", action="store_true",
                     help="skip the R = 512 records (N=4096 T=32768, FP32 and BF16) of the default run")
     return ap.parse_args()
@@ -393,6 +395,89 @@ def sparse_main(args):
     print(json.dumps(out))
 
 
+def unrolled_main(args):
+    """The differentiable unrolled H-solve at its workload (W fixed 513 x 1024,
+    V = Poisson(W H0) with T = 4096 columns, K = 20 DNA H-updates, loss
+    ||H_K - H0||^2): ms per forward (K updates with checkpoints) and per
+    backward (the hand-written adjoint), per-kernel HIP-event times of each,
+    and the roofline record of the dominant algorithmic kernel of each.
+    Algorithmic work: forward 8NRT per update (the paper's four products);
+    backward 12NRT per update (qbar, qbbar: 4NRT in zbar; the three W-gradient
+    products: 6NRT in wbar; W^t zbar: 2NRT); the recomputed Z, Q and gradient
+    sums of the backward are not counted."""
+    import torch
+    from paper_1301_3389_amd import dna, synth
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    K = 20
+    w = synth.config5()
+    N, T = w.V.shape
+    R = w.W.shape[1]
+    V = torch.from_numpy(w.V).to(dev)
+    W = torch.from_numpy(w.W).to(dev)
+    H = torch.from_numpy(w.H).to(dev)
+    H0 = torch.from_numpy(w.H0).to(dev)
+    nrt = float(N) * R * T
+
+    def fwd():
+        return dna.unrolled_forward(V, W, H, K)
+
+    def bwd(Hc, sel):
+        return dna.unrolled_backward(V, W, Hc, sel, K, 2.0 * (Hc[K] - H0).contiguous())
+
+    for _ in range(max(1, args.warmup)):
+        Hc, sel = fwd()
+        bwd(Hc, sel)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Hc, sel = fwd()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        bwd(Hc, sel)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd_ms, bwd_ms = 1e3 * (t1 - t0) / reps, 1e3 * (t2 - t1) / reps
+
+    def kernel_profile(fn):
+        dna.profile_reset()
+        dna.profile_enable(True)
+        fn()
+        torch.cuda.synchronize()
+        st = dna.profile_read()
+        dna.profile_enable(False)
+        return {k: {"launches": n, "avg_ms": ms / max(n, 1), "total_ms": ms} for k, (n, ms) in st.items()}
+
+    kf = kernel_profile(fwd)
+    kb = kernel_profile(lambda: bwd(Hc, sel))
+    peak = PEAK_FP32_TFLOPS
+
+    def roof(kernels, work):
+        cand = {k: v for k, v in kernels.items() if k in work}
+        dom = max(cand, key=lambda k: cand[k]["total_ms"])
+        ach = work[dom] / (cand[dom]["avg_ms"] * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": dom, "avg_ms": cand[dom]["avg_ms"], "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None}
+    fwd_work = {"gh_H": 4 * nrt, "cost_H": 4 * nrt}
+    bwd_work = {"zbar": 4 * nrt, "wbar": 6 * nrt, "gh_mu_H": 2 * nrt}
+    alg_f, alg_b = K * 8 * nrt, K * 12 * nrt
+    out = {"metric": "unrolled DNA H-solve, forward + backward per second", "value": 1e3 / (fwd_ms + bwd_ms),
+           "unit": "forward+backward/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+           "ms_per_step": fwd_ms + bwd_ms, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"unrolled H-solve, W fixed Gamma(0.5) {N} x {R}, V = Poisson(W H0) with "
+                                  f"T={T}, K={K} DNA H-updates, loss ||H_K - H0||^2", "N": N, "T": T, "R": R, "K": K,
+                      "parallelism": "single GPU"},
+           "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+           "forward_tflops_algorithmic": alg_f / (fwd_ms * 1e-3) / 1e12,
+           "backward_tflops_algorithmic": alg_b / (bwd_ms * 1e-3) / 1e12,
+           "roofline": roof(kb, bwd_work), "roofline_forward": roof(kf, fwd_work),
+           "kernels_forward": kf, "kernels_backward": kb}
+    print(json.dumps(out))
+
+
 def paper_sweep(args):
     """Table 1 of the paper at its dense shapes (ORL 4096 x 165, PIE 1024 x 11554;
     R = 10, 20, 40, 80) with synthetic data of those shapes: ms per iteration of
@@ -471,6 +556,9 @@ def main():
     args = parse()
     if args.paper_sweep:
         paper_sweep(args)
+        return
+    if args.unrolled:
+        unrolled_main(args)
         return
     if args.sparse:
         if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -138,8 +138,17 @@ struct Layout {
   Split chf;                 // row chunks of the fused H-orientation cost pass (three workgroups per CU fit)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
-  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, sume, vpart, cpart, fpart, s16, check, total;
+  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, sume, vpart, cpart, fpart, s16, cs, zd, dz, selm, check,
+      total;
 };
+
+// Split of an fp32 tiled gradient product whose chunks are whole multiples of
+// GH_CHUNK (the chunked gradient sums of launch_gh_H / launch_gh_W).
+static Split chunk_aligned(Split s, int64_t K) {
+  s.kchunk = cdiv(s.kchunk, GH_CHUNK) * GH_CHUNK;
+  s.splits = (int)cdiv(K, s.kchunk);
+  return s;
+}
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -149,8 +158,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // 16-bit forms keep their 16-bit Q, Q - 1 and Q-bar in their own scratch.
 static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16, bool adj = false) {
   Layout L;
-  L.sh = choose_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM));
-  L.sw = choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM));
+  L.sh = chunk_aligned(choose_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM)), N);
+  L.sw = chunk_aligned(choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM)), T);
   L.sh16 = choose_split(N, cdiv(T, 128) * cdiv(R, 128));
   L.sw16 = choose_split(T, cdiv(R, 128) * cdiv(N, 128));
   L.shf = fused_split(N, cdiv(T, 64));
@@ -187,6 +196,14 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16, bool adj
   L.cpart = take(std::max(3 * red, klt) * 8);
   L.fpart = take(red * 4);
   L.s16 = take(with16 ? scratch16_bytes(N, T, R) : 0);
+  // chunk sums of the fixed factor for the tiled fp32 gradient products
+  L.cs = take((adj || (tiled && !with16)) ? (size_t)std::max(cdiv(N, GH_CHUNK), cdiv(T, GH_CHUNK)) * cdiv(R, 64) * 64 * 4
+                                           : 0);
+  // Z_DNA, dZ and the selection a cost pass leaves for the next ratio pass (dna_iterate, tiled fp32)
+  const bool carry = tiled && !with16 && !adj;
+  L.zd = take(carry ? nt * 4 : 0);
+  L.dz = take(carry ? nt * 4 : 0);
+  L.selm = take(carry ? (size_t)std::max(N, T) : 0);
   L.check = take(16);
   L.total = off;
   return L;
@@ -299,10 +316,13 @@ static Scratch16 scratch16(void* ws, const Layout& L, int64_t N, int64_t T, int6
 // side 0: candidates for H (R x T) given W;  side 1: candidates for W (N x R) given H.
 // `pre`, if given, holds the first level of c (side 0) / g (side 1) already
 // written by the preceding normalisation; otherwise a sum kernel writes it.
+// `carry`: inside dna_iterate on the tiled fp32 path, Z of the current state is
+// taken from the preceding half-step's cost pass (Algorithm 1 steps 15, 28)
+// instead of being formed again from W H.
 static dna_status run_candidates(int side, const float* V, const float* W, const float* H, int64_t N,
                                  int64_t T, int64_t R, const dna_opts* o, const Layout& L, void* ws,
                                  float* Xmu, float* Xn, float* Aout, float* Bout, int* chk, hipStream_t s,
-                                 const SumJob* pre = nullptr) {
+                                 const SumJob* pre = nullptr, bool carry = false) {
   float* Q = at<float>(ws, L.q);
   float* Qb = at<float>(ws, L.qb);
   float* pu = at<float>(ws, L.pu);
@@ -312,6 +332,11 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
   double* c64 = at<double>(ws, L.c64);
   double* vpart = at<double>(ws, L.vpart);
   RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk, nullptr};
+  if (carry) {
+    ra.carry.zd = at<float>(ws, L.zd);
+    ra.carry.dz = at<float>(ws, L.dz);
+    ra.carry.sel = at<uint8_t>(ws, L.selm);
+  }
   const bool p16 = o->gemm != DNA_GEMM_FP32;
   const Scratch16 S = scratch16(ws, L, N, T, R);
   SumJob job;
@@ -328,8 +353,11 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
       DNA_HIP(launch_rgh(0, V, W, H, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, job, chk, s),
               "rgh_H");
     } else {
-      DNA_HIP(launch_ratio(RM_H, ra, s), "ratio_H");
-      DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
+      float* cs = at<float>(ws, L.cs);
+      DNA_HIP(launch_ratio(carry ? RM_H_CARRY : RM_H, ra, s), "ratio_H");
+      if (N >= GH_CHUNK_MIN_K) DNA_HIP(launch_chunk_sums(0, W, N, T, R, cs, s), "chunk_sums_W");
+      DNA_HIP(launch_gh_H(W, Q, Qb, N >= GH_CHUNK_MIN_K ? cs : nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc,
+                          py, s), "gh_H");
     }
     // the 16-bit Z pass tiles N by 128 like the fp32 one (RT_BM)
     int sp = p16 ? L.sh16.splits : (fused ? L.shf.splits : L.sh.splits);
@@ -352,8 +380,11 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
       DNA_HIP(launch_rgh(1, V, W, H, N, T, R, L.swf.splits, L.swf.kchunk, pu, puc, py, vpart, job, chk, s),
               "rgh_W");
     } else {
-      DNA_HIP(launch_ratio(RM_W, ra, s), "ratio_W");
-      DNA_HIP(launch_gh_W(Q, Qb, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc, py, s), "gh_W");
+      float* cs = at<float>(ws, L.cs);
+      DNA_HIP(launch_ratio(carry ? RM_W_CARRY : RM_W, ra, s), "ratio_W");
+      if (T >= GH_CHUNK_MIN_K) DNA_HIP(launch_chunk_sums(1, H, N, T, R, cs, s), "chunk_sums_H");
+      DNA_HIP(launch_gh_W(Q, Qb, H, T >= GH_CHUNK_MIN_K ? cs : nullptr, N, T, R, L.sw.splits, L.sw.kchunk, pu, puc,
+                          py, s), "gh_W");
     }
     // the 16-bit Z pass tiles T by 128, the fp32 one by RT_BN
     const int sp = p16 ? L.sw16.splits : (fused ? L.swf.splits : L.sw.splits);
@@ -364,9 +395,16 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
   return DNA_OK;
 }
 
+// `keep`: the cost pass also stores Z_DNA and dZ, and the selection is written to
+// the workspace mask when the caller wants none, for the next half-step's
+// carried Z (tiled fp32 path only).
 static dna_status run_select(int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                              float* Xout, int64_t N, int64_t T, int64_t R, const dna_opts* o, const Layout& L,
-                             void* ws, uint8_t* mask, double* dsel, double* margin, hipStream_t s) {
+                             void* ws, uint8_t* mask, double* dsel, double* margin, hipStream_t s,
+                             bool keep = false) {
+  float* zd = keep ? at<float>(ws, L.zd) : nullptr;
+  float* dz = keep ? at<float>(ws, L.dz) : nullptr;
+  if (keep) mask = at<uint8_t>(ws, L.selm);
   double* cpart = at<double>(ws, L.cpart);
   int* fpart = at<int>(ws, L.fpart);
   if (o->gemm != DNA_GEMM_FP32) {
@@ -383,14 +421,14 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
     if (fused)
       DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.chf.splits, L.chf.kchunk, cpart, fpart, s), "costf_H");
     else
-      DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_H");
+      DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz), "cost_H");
     DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, fused ? L.chf.splits : L.ch_m, T, R, mask, dsel, margin,
                             s), "select_H");
   } else {
     if (fused)
       DNA_HIP(launch_costf(1, V, F, Xmu, Xn, N, T, R, L.swf.splits, L.swf.kchunk, cpart, fpart, s), "costf_W");
     else
-      DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s), "cost_W");
+      DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz), "cost_W");
     DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, fused ? L.swf.splits : L.cw_n, N, R, mask, dsel, margin,
                             s), "select_W");
   }
@@ -554,15 +592,20 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
   float* Xn = at<float>(ws, c.L.xn);
   SumJob next;
   bool have = false;                                // `next` holds c for the coming H step
+  // tiled fp32 path: each cost pass leaves Z of both candidates and the choice
+  // for the next half-step's ratio pass (Algorithm 1 steps 15, 28)
+  const bool keep = o->gemm == DNA_GEMM_FP32 && R > FUSED_MAX_R;
+  bool zin = false;                                 // Z of the current state is in the workspace
   for (int it = 0; it < iters; ++it) {
     DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
-                           have ? &next : nullptr));
-    DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s));
+                           have ? &next : nullptr, zin));
+    DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep));
     DNA_TRY(iterate_normalize(1, W, H, N, T, R, o, c, ws, next, have));  // step 16; next = g
     DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
-                           have ? &next : nullptr));
-    DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s));
+                           have ? &next : nullptr, keep));
+    DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep));
     DNA_TRY(iterate_normalize(0, W, H, N, T, R, o, c, ws, next, have));  // step 29; next = c
+    zin = keep;
   }
   return epilogue(c);
 }
@@ -623,7 +666,8 @@ static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N
     }
     ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_H_COST : RM_MU_H, ra, c.s), "ratio_mu_H");
-    DNA_HIP(launch_gh_H(W, Q, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_H");
+    DNA_HIP(launch_gh_H(W, Q, nullptr, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, c.s),
+            "gh_mu_H");
     DNA_HIP(launch_mu_H(H, pu, L.sh.splits, c32, T, R, cpart, L.rt_m, with_cost ? d_out : nullptr, c.s), "mu_H");
   } else {
     DNA_HIP(launch_rowsum_part(H, T, R, at<double>(ws, L.sump), job, c.s), "rowsum_H");
@@ -637,7 +681,8 @@ static dna_status run_mu(int side, const float* V, float* W, float* H, int64_t N
     }
     ra.fin = job;
     DNA_HIP(launch_ratio(with_cost ? RM_MU_W_COST : RM_MU_W, ra, c.s), "ratio_mu_W");
-    DNA_HIP(launch_gh_W(Q, nullptr, H, N, T, R, L.sw.splits, L.sw.kchunk, pu, nullptr, nullptr, c.s), "gh_mu_W");
+    DNA_HIP(launch_gh_W(Q, nullptr, H, nullptr, N, T, R, L.sw.splits, L.sw.kchunk, pu, nullptr, nullptr, c.s),
+            "gh_mu_W");
     DNA_HIP(launch_mu_W(W, pu, L.sw.splits, c32, N, R, cpart, L.rt_n, with_cost ? d_out : nullptr, c.s), "mu_W");
   }
   return DNA_OK;
@@ -819,11 +864,13 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
   double* cbar64 = at<double>(ws, A.cbar64);
   float* p0 = at<float>(ws, A.wp0);
   float* p1 = at<float>(ws, A.wp1);
+  float* cs = at<float>(ws, L.cs);
   {
     SumJob job;
     DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
     job.s32 = c32;
     DNA_HIP(launch_sum_final(job, s), "sum_final");
+    if (R > FUSED_MAX_R && N >= GH_CHUNK_MIN_K) DNA_HIP(launch_chunk_sums(0, W, N, T, R, cs, s), "chunk_sums_W");
   }
   const float* Gin = dH_K;
   for (int k = K - 1; k >= 0; --k) {
@@ -842,7 +889,8 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
       sp = L.shf.splits;
       vtiles = L.shf.splits;
     } else {
-      DNA_HIP(launch_gh_H(W, Q, Qb, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc, py, s), "gh_H");
+      DNA_HIP(launch_gh_H(W, Q, Qb, N >= GH_CHUNK_MIN_K ? cs : nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc,
+                          py, s), "gh_H");
     }
     if (sp > 8 && T < 256 * 32) {
       DNA_HIP(launch_fold_splits(pu, puc, py, sp, R * T, s), "fold_splits");
@@ -860,7 +908,8 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
     DNA_HIP(launch_wbar(Q, Zbar, Qb, Ub, Hk, Yb, N, T, R, A.swb.splits, A.swb.kchunk, p0, p1, s), "wbar");
     DNA_HIP(launch_dw_final(W, p0, p1, A.swb.splits, cbar64, N, R, dW, acc, s), "dw_final");
     if (Gout) {
-      DNA_HIP(launch_gh_H(W, Zbar, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, s), "gh_zbar");
+      DNA_HIP(launch_gh_H(W, Zbar, nullptr, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, s),
+              "gh_zbar");
       DNA_HIP(launch_dh_final(Hd, pu, L.sh.splits, R, T, Gout, s), "dh_final");
     }
     Gin = Gout;

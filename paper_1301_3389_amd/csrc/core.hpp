@@ -216,6 +216,54 @@ struct Tile {
     }
   }
 
+  // run() with a hook: after every `tiles_per_chunk` K-tiles of this range (and
+  // after the last one) flush(c) is called with the chunk's index c = 0, 1, ...
+  // counted from k_begin, while the next K-tile's loads are in flight.
+  template <class FL>
+  __device__ __forceinline__ void run_flush(const Opnd (&A)[NA], const Opnd (&B)[NB], int64_t m0, int64_t n0,
+                                            int64_t k_begin, int64_t k_end, float* lds, int tiles_per_chunk,
+                                            FL&& flush) {
+    const int tid = threadIdx.x;
+    const int64_t nk = (k_end - k_begin + G::BK - 1) / G::BK;
+    if (nk <= 0) return;
+    Stage<G::BM, G::BK, G::NT, AK> sa[NA];
+    Stage<G::BN, G::BK, G::NT, BKM> sb[NB];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) sa[a].load(A[a], m0, k_begin, k_end, tid);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) sb[b].load(B[b], n0, k_begin, k_end, tid);
+#pragma unroll
+    for (int a = 0; a < NA; ++a) sa[a].store(lds + a * G::LDA * G::BK, tid);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) sb[b].store(lds + NA * G::LDA * G::BK + b * G::LDB * G::BK, tid);
+    __syncthreads();
+    int in_chunk = 0, chunk = 0;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const bool more = kt + 1 < nk;
+      const int64_t kn = k_begin + (kt + 1) * G::BK;
+      if (more) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) sa[a].load(A[a], m0, kn, k_end, tid);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) sb[b].load(B[b], n0, kn, k_end, tid);
+      }
+      compute(lds + (kt & 1) * BUF);
+      if (++in_chunk == tiles_per_chunk || !more) {
+        flush(chunk);
+        ++chunk;
+        in_chunk = 0;
+      }
+      if (more) {
+        float* nb = lds + ((kt + 1) & 1) * BUF;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) sa[a].store(nb + a * G::LDA * G::BK, tid);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) sb[b].store(nb + NA * G::LDA * G::BK + b * G::LDB * G::BK, tid);
+      }
+      __syncthreads();
+    }
+  }
+
   // Load X[row][col] (row-major, leading dimension ld) at this lane's accumulator
   // positions.  Indices are clamped into the matrix so that every load is issued
   // unconditionally (and early, before the K loop); callers ignore the clamped

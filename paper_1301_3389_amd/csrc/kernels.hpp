@@ -46,7 +46,19 @@ enum RatioMode {
   RM_MU_W = 4,     // Q only                              (MU W step)
   RM_MU_W_COST = 5,// Q, per-row cost of the input
   RM_KL = 6,       // per-tile sums of the eq. (1) terms only
-  RM_ADJ = 7       // Q, Q-bar, Z and column sums of V      (adjoint recompute)
+  RM_ADJ = 7,      // Q, Q-bar, Z and column sums of V      (adjoint recompute)
+  RM_H_CARRY = 8,  // RM_H with Z read from the preceding W step's cost pass
+  RM_W_CARRY = 9   // RM_W with Z read from the preceding H step's cost pass
+};
+
+// Z of the candidate each row (RM_H_CARRY: the preceding W step chose per row
+// n) or column (RM_W_CARRY: per column t) kept, from that step's cost pass:
+// z = zd + (sel == 0 ? dz : 0), zd = Z_DNA, dz = Z_MU - Z_DNA (Algorithm 1
+// steps 15 and 28 carry Z; the normalisations between leave W H unchanged).
+struct ZCarry {
+  const float* zd = nullptr;
+  const float* dz = nullptr;
+  const uint8_t* sel = nullptr;
 };
 
 // Second level of a column / row sum of a factor (see launch_colsum_part): the
@@ -74,18 +86,30 @@ struct RatioArgs {
   int* check;         // nullptr unless checked
   float* Z;           // RM_ADJ only: Z = W H
   SumJob fin;         // folded second level of the preceding factor sum (part = nullptr: none)
+  ZCarry carry;       // RM_H_CARRY / RM_W_CARRY only
 };
 hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s);
 
 // Gradient / Hessian numerators, split over the contraction index.
 //   H orientation: pu[sp][r][t] = sum_{n in split} w_nr q_nt, py with w^2, q-bar
 //   W orientation: pu[sp][n][r] = sum_{t in split} q_nt h_rt, py with q-bar, h^2
-// With Qb == nullptr only pu is written (MU).  u_c = u - c is accumulated from
-// (q - 1) directly; see the candidate kernels for which form is used where.
-hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t N, int64_t T,
+// With Qb == nullptr only pu is written (MU).  Otherwise, with cs == nullptr,
+// u_c = sum w (q - 1) is a third product over q - 1; with cs (the fixed
+// factor's chunk sums, launch_chunk_sums: cdiv(K, GH_CHUNK) x (R rounded up to
+// 64) floats) it is formed from the chunk sums of
+// w q (GH_CHUNK contraction indices each) less cs, two products instead of
+// three, and kchunk must be a multiple of GH_CHUNK.  The chunk form carries
+// about 2^-24 u sqrt(GH_CHUNK / K) of rounding in u_c, the direct one
+// 2^-24 times the partial sums of w (q - 1), which stay small near a fixed
+// point; the chunk form is used for contractions of at least GH_CHUNK_MIN_K
+// indices.  See the candidate kernels for which form of the gain is used where.
+constexpr int64_t GH_CHUNK = 32;
+constexpr int64_t GH_CHUNK_MIN_K = 2048;
+hipError_t launch_chunk_sums(int side, const float* F, int64_t N, int64_t T, int64_t R, float* cs, hipStream_t s);
+hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, const float* cs, int64_t N, int64_t T,
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s);
-hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t N, int64_t T,
+hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, const float* cs, int64_t N, int64_t T,
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s);
 
@@ -105,10 +129,13 @@ hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, cons
 
 // Fused candidate reconstruction + log + reduction (costs of both candidates).
 //   part: [3][tiles][L] float64 (sum_N, margin, MU-only rows), fpart: [tiles][L] int
+// With zd / dz (N x T, row-major) the kernels also store z_DNA and dZ there.
 hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn,
-                         int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s);
+                         int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s,
+                         float* zd = nullptr, float* dz = nullptr);
 hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const float* Xn,
-                         int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s);
+                         int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s,
+                         float* zd = nullptr, float* dz = nullptr);
 
 // Selection and write-back.
 hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,

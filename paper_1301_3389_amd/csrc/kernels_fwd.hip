@@ -45,6 +45,7 @@ struct RatioKArgs {
   int* check;
   float* Z;
   SumJob fin;
+  ZCarry carry;
 };
 
 template <int MODE>
@@ -53,21 +54,40 @@ __global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
   using TL = Tile<GZ, ProdSingle, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
+  constexpr bool CARRY = MODE == RM_H_CARRY || MODE == RM_W_CARRY;
   sum_job(a.fin);
   float vf[GZ::FM][GZ::FN][16];
   TL::load_frag(vf, a.V, a.T, m0, n0, a.N, a.T);     // in flight during the K loop
   TL t;
   t.zero();
-  {
+  if constexpr (CARRY) {
+    // Z of the kept candidates: z_DNA, plus dZ where MU was kept (per row n
+    // after a W step, per column t after an H step)
+    float zf[GZ::FM][GZ::FN][16], df[GZ::FM][GZ::FN][16];
+    TL::load_frag(zf, a.carry.zd, a.T, m0, n0, a.N, a.T);
+    TL::load_frag(df, a.carry.dz, a.T, m0, n0, a.N, a.T);
+#pragma unroll
+    for (int i = 0; i < GZ::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < GZ::FN; ++j) {
+        const int64_t col = min(TL::col_of(n0, j), a.T - 1);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = min(TL::row_of(m0, i, v), a.N - 1);
+          const bool mu = (MODE == RM_H_CARRY ? a.carry.sel[row] : a.carry.sel[col]) == 0;
+          t.acc[i][j][0][v] = mu ? zf[i][j][v] + df[i][j][v] : zf[i][j][v];
+        }
+      }
+  } else {
     const Opnd A[1] = {a.W};
     const Opnd B[1] = {a.H};
     t.run(A, B, m0, n0, 0, a.R, lds);
   }
   constexpr bool WANT_Q = MODE != RM_KL;
-  constexpr bool WANT_QB = MODE == RM_H || MODE == RM_W || MODE == RM_ADJ;
+  constexpr bool WANT_QB = MODE == RM_H || MODE == RM_W || MODE == RM_ADJ || CARRY;
   constexpr bool WANT_Z = MODE == RM_ADJ;
-  constexpr bool COLS = MODE == RM_H || MODE == RM_MU_H_COST || MODE == RM_ADJ;  // column partials
-  constexpr bool ROWS = MODE == RM_W || MODE == RM_MU_W_COST;     // row partials
+  constexpr bool COLS = MODE == RM_H || MODE == RM_MU_H_COST || MODE == RM_ADJ || MODE == RM_H_CARRY;
+  constexpr bool ROWS = MODE == RM_W || MODE == RM_MU_W_COST || MODE == RM_W_CARRY;
   constexpr bool COST = MODE == RM_MU_H_COST || MODE == RM_MU_W_COST;
   const int64_t N = a.N, T = a.T;
   double cp[1][GZ::FN];
@@ -143,6 +163,9 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
   k.N = a.N; k.T = a.T; k.R = a.R;
   k.Q = a.Q; k.Qb = a.Qb; k.vpart = a.vpart; k.cpart = a.cpart; k.check = a.check; k.Z = a.Z;
   k.fin = a.fin;
+  k.carry = a.carry;
+  if ((mode == RM_H_CARRY || mode == RM_W_CARRY) && (!a.carry.zd || !a.carry.dz || !a.carry.sel))
+    return hipErrorInvalidValue;
   dim3 grid((unsigned)cdiv(a.T, GR::BN), (unsigned)cdiv(a.N, GR::BM));
   const char* nm = "ratio";
 #define DNA_RATIO_CASE(M, NAME)                                         \
@@ -160,6 +183,8 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
     DNA_RATIO_CASE(RM_MU_W_COST, "ratio_mu_W_cost")
     DNA_RATIO_CASE(RM_KL, "kl_terms")
     DNA_RATIO_CASE(RM_ADJ, "ratio_adj")
+    DNA_RATIO_CASE(RM_H_CARRY, "ratio_H")
+    DNA_RATIO_CASE(RM_W_CARRY, "ratio_W")
     default: return hipErrorInvalidValue;
   }
 #undef DNA_RATIO_CASE
@@ -208,7 +233,190 @@ __global__ __launch_bounds__(G::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64_
     }
 }
 
-hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t N, int64_t T,
+// The DNA gradient products with two MFMA chains instead of three: the
+// contraction runs in chunks of GH_CHUNK indices; each chunk's sum of w q is
+// added to the plain sum u and, less the chunk's sum of the fixed factor
+// (cs[chunk][r]), to the centred sum u_c = sum w (q - 1).  Each chunk sum
+// carries float32 rounding of its own size only, so u keeps the MU gain's
+// relative accuracy and u_c the absolute accuracy of A near 0, as a separate
+// product over q - 1 would.
+template <class G>
+__global__ __launch_bounds__(G::NT, 2) void k_gh2_H(Opnd Wt, Opnd Q, Opnd Qb, const float* __restrict__ cs, int64_t N,
+                                                  int64_t T, int64_t R, int64_t kchunk, GHOut out) {
+  using TL = Tile<G, ProdDualB_SqA, false, false>;     // acc 0: w q, acc 1: w^2 q-bar
+  __shared__ __align__(16) float lds[TL::LDS_FLOATS];
+  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
+  const int64_t sp = blockIdx.z;
+  const int64_t k0 = sp * kchunk, k1 = min(N, k0 + kchunk);
+  const int64_t c0 = k0 / GH_CHUNK;
+  TL t;
+  t.zero();
+  float ur[G::FM][G::FN][16], ucr[G::FM][G::FN][16];
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) ur[i][j][v] = ucr[i][j][v] = 0.f;
+  {
+    const Opnd A[1] = {Wt};
+    const Opnd B[2] = {Q, Qb};
+    // this lane's chunk sums (table rows padded to a multiple of 64 ranks with
+    // zeros), four rows per 16-byte load, one chunk ahead of their use
+    const int64_t Rp = (R + 63) / 64 * 64;
+    const int64_t nchunks = (k1 - k0 + GH_CHUNK - 1) / GH_CHUNK;
+    const int lane = threadIdx.x & 63, wm = (threadIdx.x >> 6) % G::WGM;
+    const float* csb = cs + c0 * Rp + m0 + wm * G::WM + (lane >> 5) * 4;
+    f32x4 cc[G::FM][4];
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) cc[i][g] = *reinterpret_cast<const f32x4*>(csb + i * 32 + g * 8);
+    t.run_flush(A, B, m0, n0, k0, k1, lds, GH_CHUNK / G::BK, [&](int c) {
+      const float* nx = csb + min<int64_t>(c + 1, nchunks - 1) * Rp;
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+#pragma unroll
+          for (int j = 0; j < G::FN; ++j) {
+            const float x = t.acc[i][j][0][v];
+            ur[i][j][v] += x;
+            ucr[i][j][v] += x - cc[i][v >> 2][v & 3];
+            t.acc[i][j][0][v] = 0.f;
+          }
+        }
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) cc[i][g] = *reinterpret_cast<const f32x4*>(nx + i * 32 + g * 8);
+    });
+  }
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int64_t col = TL::col_of(n0, j);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = TL::row_of(m0, i, v);
+        if (row < R && col < T) {
+          const int64_t e = (sp * R + row) * T + col;
+          out.p[0][e] = ur[i][j][v];
+          out.p[1][e] = ucr[i][j][v];
+          out.p[2][e] = t.acc[i][j][1][v];
+        }
+      }
+    }
+}
+
+template <class G>
+__global__ __launch_bounds__(G::NT, 2) void k_gh2_W(Opnd Q, Opnd Qb, Opnd Ht, const float* __restrict__ cs, int64_t N,
+                                                  int64_t T, int64_t R, int64_t kchunk, GHOut out) {
+  using TL = Tile<G, ProdDualA_SqB, true, true>;       // acc 0: q h, acc 1: q-bar h^2
+  __shared__ __align__(16) float lds[TL::LDS_FLOATS];
+  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
+  const int64_t sp = blockIdx.z;
+  const int64_t k0 = sp * kchunk, k1 = min(T, k0 + kchunk);
+  const int64_t c0 = k0 / GH_CHUNK;
+  TL t;
+  t.zero();
+  float ur[G::FM][G::FN][16], ucr[G::FM][G::FN][16];
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) ur[i][j][v] = ucr[i][j][v] = 0.f;
+  {
+    const Opnd A[2] = {Q, Qb};
+    const Opnd B[1] = {Ht};
+    const int64_t Rp = (R + 63) / 64 * 64;
+    const int64_t nchunks = (k1 - k0 + GH_CHUNK - 1) / GH_CHUNK;
+    const float* csb = cs + c0 * Rp + TL::col_of(n0, 0);
+    float cc[G::FN];
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) cc[j] = csb[j * 32];
+    t.run_flush(A, B, m0, n0, k0, k1, lds, GH_CHUNK / G::BK, [&](int c) {
+      const float* nx = csb + min<int64_t>(c + 1, nchunks - 1) * Rp;
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+#pragma unroll
+        for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const float x = t.acc[i][j][0][v];
+            ur[i][j][v] += x;
+            ucr[i][j][v] += x - cc[j];
+            t.acc[i][j][0][v] = 0.f;
+          }
+        cc[j] = nx[j * 32];
+      }
+    });
+  }
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int64_t col = TL::col_of(n0, j);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = TL::row_of(m0, i, v);
+        if (row < N && col < R) {
+          const int64_t e = (sp * N + row) * R + col;
+          out.p[0][e] = ur[i][j][v];
+          out.p[1][e] = ucr[i][j][v];
+          out.p[2][e] = t.acc[i][j][1][v];
+        }
+      }
+    }
+}
+
+// cs[c][r] = float32 of the float64 sum of W[n][r] over the rows n of chunk c
+// (GH_CHUNK rows; side 0), or of H[r][t] over the columns t of chunk c (side 1);
+// rows r of the table padded to Rp = R rounded up to 64 with zeros.
+__global__ __launch_bounds__(256) void k_chunk_sums_W(const float* __restrict__ W, int64_t N, int64_t R, int64_t Rp,
+                                                      float* __restrict__ cs) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (r >= Rp) return;
+  double s = 0.0;
+  if (r < R) {
+    const int64_t n1 = min(N, (c + 1) * GH_CHUNK);
+    for (int64_t n = c * GH_CHUNK; n < n1; ++n) s += (double)W[n * R + r];
+  }
+  cs[c * Rp + r] = (float)s;
+}
+
+__global__ __launch_bounds__(256) void k_chunk_sums_H(const float* __restrict__ H, int64_t T, int64_t R, int64_t Rp,
+                                                      int64_t nchunks, float* __restrict__ cs) {
+  // one half-wave per (chunk, r): a value per lane, then a fixed-order sum
+  static_assert(GH_CHUNK == 32, "a chunk is one half-wave");
+  const int lane = threadIdx.x & 31;
+  const int64_t item = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
+  const bool ok = item < nchunks * Rp;
+  const int64_t r = ok ? item / nchunks : 0, c = ok ? item % nchunks : 0;
+  const int64_t t = c * GH_CHUNK + lane;
+  double s = (ok && r < R && t < T) ? (double)H[r * T + t] : 0.0;
+#pragma unroll
+  for (int m = 16; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+  if (ok && lane == 0) cs[c * Rp + r] = (float)s;
+}
+
+hipError_t launch_chunk_sums(int side, const float* F, int64_t N, int64_t T, int64_t R, float* cs, hipStream_t s) {
+  const int64_t Rp = cdiv(R, 64) * 64;
+  prof_begin("chunk_sums", s);
+  if (side == 0) {
+    hipLaunchKernelGGL(k_chunk_sums_W, dim3((unsigned)cdiv(Rp, 256), (unsigned)cdiv(N, GH_CHUNK)), dim3(256), 0, s,
+                       F, N, R, Rp, cs);
+  } else {
+    const int64_t nc = cdiv(T, GH_CHUNK);
+    hipLaunchKernelGGL(k_chunk_sums_H, dim3((unsigned)cdiv(nc * Rp, 8)), dim3(256), 0, s, F, T, R, Rp, nc, cs);
+  }
+  prof_end("chunk_sums", s);
+  return hipGetLastError();
+}
+
+hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, const float* cs, int64_t N, int64_t T,
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s) {
   const bool small = cdiv(T, GH::BN) * cdiv(R, GH::BM) * splits < GH_SMALL_GRID;
@@ -217,7 +425,14 @@ hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, int64_t 
   const Opnd wt = make_opnd(W, R, R);     // element (r, n) at W[n*R + r]: MN-contiguous
   const Opnd q = make_opnd(Q, T, T);      // element (t, n) at Q[n*T + t]: MN-contiguous
   GHOut out = {{pu, puc, py}};
-  if (Qb) {
+  if (Qb && cs) {
+    if (kchunk % GH_CHUNK != 0) return hipErrorInvalidValue;
+    const Opnd qb = make_opnd(Qb, T, T);
+    prof_begin("gh_H", s);
+    if (small) hipLaunchKernelGGL((k_gh2_H<GS>), grid, dim3(GS::NT), 0, s, wt, q, qb, cs, N, T, R, kchunk, out);
+    else hipLaunchKernelGGL((k_gh2_H<GH>), grid, dim3(GH::NT), 0, s, wt, q, qb, cs, N, T, R, kchunk, out);
+    prof_end("gh_H", s);
+  } else if (Qb) {
     const Opnd qb = make_opnd(Qb, T, T);
     prof_begin("gh_H", s);
     if (small) hipLaunchKernelGGL((k_gh_H<GS, ProdGH3_H>), grid, dim3(GS::NT), 0, s, wt, q, qb, N, T, R, kchunk, out);
@@ -265,7 +480,7 @@ __global__ __launch_bounds__(G::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64_
     }
 }
 
-hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t N, int64_t T,
+hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, const float* cs, int64_t N, int64_t T,
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s) {
   const bool small = cdiv(R, GW::BN) * cdiv(N, GW::BM) * splits < GH_SMALL_GRID;
@@ -274,7 +489,14 @@ hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, int64_t 
   const Opnd q = make_opnd(Q, T, N);      // element (n, t) at Q[n*T + t]: K-contiguous
   const Opnd ht = make_opnd(H, T, R);     // element (r, t) at H[r*T + t]: K-contiguous
   GHOut out = {{pu, puc, py}};
-  if (Qb) {
+  if (Qb && cs) {
+    if (kchunk % GH_CHUNK != 0) return hipErrorInvalidValue;
+    const Opnd qb = make_opnd(Qb, T, N);
+    prof_begin("gh_W", s);
+    if (small) hipLaunchKernelGGL((k_gh2_W<GS>), grid, dim3(GS::NT), 0, s, q, qb, ht, cs, N, T, R, kchunk, out);
+    else hipLaunchKernelGGL((k_gh2_W<GW>), grid, dim3(GW::NT), 0, s, q, qb, ht, cs, N, T, R, kchunk, out);
+    prof_end("gh_W", s);
+  } else if (Qb) {
     const Opnd qb = make_opnd(Qb, T, N);
     prof_begin("gh_W", s);
     if (small) hipLaunchKernelGGL((k_gh_W<GS, ProdGH3_W>), grid, dim3(GS::NT), 0, s, q, qb, ht, N, T, R, kchunk, out);
@@ -666,8 +888,29 @@ hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, cons
   return hipGetLastError();
 }
 
+// z_DNA and dZ of a finished cost tile to zd / dz (both N x T, row-major).
+template <class TL, class G>
+__device__ __forceinline__ void store_recon(const TL& t, int64_t m0, int64_t n0, int64_t N, int64_t T, float* zd,
+                                            float* dz) {
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int64_t col = TL::col_of(n0, j);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = TL::row_of(m0, i, v);
+        if (row < N && col < T) {
+          zd[row * T + col] = t.acc[i][j][0][v];
+          dz[row * T + col] = t.acc[i][j][1][v];
+        }
+      }
+    }
+}
+
 __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,
-                                                     int64_t T, int64_t R, double* part, int* fpart) {
+                                                     int64_t T, int64_t R, double* part, int* fpart, float* zd,
+                                                     float* dz) {
   using GZ = GCH;
   using TL = Tile<GZ, ProdDualB, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
@@ -684,24 +927,26 @@ __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd
     const Opnd B[2] = {Hn, Hd};
     t.run(A, B, m0, n0, 0, R, lds);
   }
+  if (zd) store_recon<TL, GZ>(t, m0, n0, N, T, zd, dz);
   const int64_t base = (int64_t)blockIdx.y * T, stride = (int64_t)gridDim.y * T;
   cost_cols<GZ>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn, int64_t N,
-                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s) {
+                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s, float* zd, float* dz) {
   dim3 grid((unsigned)cdiv(T, GCH::BN), (unsigned)cdiv(N, GCH::BM));
   const Opnd w = make_opnd(W, R, N);
   const Opnd hn = make_opnd(Xn, T, T);
   const Opnd hd = make_opnd(Xmu, T, T, Xn);
   prof_begin("cost_H", s);
-  hipLaunchKernelGGL(k_cost_H, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart);
+  hipLaunchKernelGGL(k_cost_H, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart, zd, dz);
   prof_end("cost_H", s);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(GCW::NT) void k_cost_W(const float* V, Opnd Wn, Opnd Wd, Opnd H, int64_t N,
-                                                     int64_t T, int64_t R, double* part, int* fpart) {
+__global__ __launch_bounds__(GCW::NT, 2) void k_cost_W(const float* V, Opnd Wn, Opnd Wd, Opnd H, int64_t N,
+                                                     int64_t T, int64_t R, double* part, int* fpart, float* zd,
+                                                     float* dz) {
   using TL = Tile<GCW, ProdDualA, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   __shared__ int fl_s[GCW::BM];
@@ -717,18 +962,19 @@ __global__ __launch_bounds__(GCW::NT) void k_cost_W(const float* V, Opnd Wn, Opn
     const Opnd B[1] = {H};
     t.run(A, B, m0, n0, 0, R, lds);
   }
+  if (zd) store_recon<TL, GCW>(t, m0, n0, N, T, zd, dz);
   const int64_t base = (int64_t)blockIdx.x * N, stride = (int64_t)gridDim.x * N;
   cost_rows<GCW>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const float* Xn, int64_t N,
-                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s) {
+                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s, float* zd, float* dz) {
   dim3 grid((unsigned)cdiv(T, GCW::BN), (unsigned)cdiv(N, GCW::BM));
   const Opnd wn = make_opnd(Xn, R, N);
   const Opnd wd = make_opnd(Xmu, R, N, Xn);
   const Opnd h = make_opnd(H, T, T);
   prof_begin("cost_W", s);
-  hipLaunchKernelGGL(k_cost_W, grid, dim3(GCW::NT), 0, s, V, wn, wd, h, N, T, R, part, fpart);
+  hipLaunchKernelGGL(k_cost_W, grid, dim3(GCW::NT), 0, s, V, wn, wd, h, N, T, R, part, fpart, zd, dz);
   prof_end("cost_W", s);
   return hipGetLastError();
 }

@@ -29,6 +29,7 @@ SHAPES = [
     (150, 170, 100, 0.1, 10),    # 64 < R <= 128: the register-resident candidate forms
     (2600, 150, 80, 0.1, 13),    # many contraction splits over few columns: folded before the candidates
     (2600, 150, 40, 0.1, 14),    # the same through the fused kernels: 41 cost partials per column
+    (2100, 2300, 96, 0.1, 15),   # contractions of >= 2048 indices both ways: chunked gradient sums
 ]
 
 
