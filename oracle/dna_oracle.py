@@ -195,7 +195,33 @@ def _select(d_mu, d_nr, X_mu, X_nr, axis):
     return choose, X, d_sel, margin
 
 
-def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, lam=0.0):
+def _select_newton_first(d_cur, d_nr, X, X_mu, X_nr, c, s, axis):
+    """The damped selection (reading of Sec. 5's "more refined step damping"):
+    evaluate the Newton candidate only and keep it iff it does not raise the
+    column's (axis 0) or row's (axis 1) objective of eq. (5),
+        d + sum_r c_r x_r - sum v       (c including lambda, resp. rho),
+    above the current state's; else take the MU candidate, which never raises
+    it (Sec. 2.1), without evaluating its cost.  Returns choose, X, d_sel (NaN
+    where MU is kept: its cost is not formed), margin = objective(current) -
+    objective(Newton)."""
+    if axis == 0:
+        obj_cur = d_cur + c @ X - s
+        obj_nr = d_nr + c @ X_nr - s
+    else:
+        obj_cur = d_cur + X @ c - s
+        obj_nr = d_nr + X_nr @ c - s
+    with np.errstate(invalid="ignore"):
+        margin = obj_cur - obj_nr
+    choose = np.isfinite(d_nr) & (obj_nr <= obj_cur)
+    if axis == 0:
+        Xo = np.where(choose[None, :], X_nr, X_mu)
+    else:
+        Xo = np.where(choose[:, None], X_nr, X_mu)
+    d_sel = np.where(choose, d_nr, np.nan)
+    return choose, Xo, d_sel, margin
+
+
+def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, lam=0.0, select="both"):
     """One DNA update of H with W fixed: Algorithm 1 steps 4-15 (Sec. 2-3).
 
     c = W^t 1 + lambda; Z = W H; Q, Q-bar (steps 2-3, 10); A = W^t Q / c - 1
@@ -203,6 +229,10 @@ def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, lam=0.0):
     H(1+A) (eq. 11, step 6); Newton candidate (eq. 15/17, step 11)
     renormalised by eq. (10) with s = 1^t V; per-column costs (steps 7-9,
     12-14); selection (step 15).  ``lam`` is the H weight of eq. (2).
+
+    ``select="newton_first"``: the damped selection of _select_newton_first in
+    place of steps 7-9 and 15 (the MU candidate's cost is not evaluated;
+    ``d_mu`` is then NaN).
     """
     V, W, H = _f64(V), _f64(W), _f64(H)
     c = W.sum(axis=0)
@@ -215,13 +245,17 @@ def h_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, lam=0.0):
     H_mu = np.maximum(H * (1.0 + A), value_floor)
     H_nr = np.maximum(renormalize(newton_candidate(H, A, B, eps, alpha), c, V.sum(axis=0), axis=0),
                       value_floor)
-    d_mu = partial_cost(V, W @ H_mu, axis=0)
     d_nr = partial_cost(V, W @ H_nr, axis=0)
+    if select == "newton_first":
+        d_cur = partial_cost(V, W @ H, axis=0)
+        choose, X, d_sel, margin = _select_newton_first(d_cur, d_nr, H, H_mu, H_nr, c, V.sum(axis=0), 0)
+        return StepResult(X, choose, d_sel, np.full_like(d_nr, np.nan), d_nr, margin, A, B, H_mu, H_nr)
+    d_mu = partial_cost(V, W @ H_mu, axis=0)
     choose, X, d_sel, margin = _select(d_mu, d_nr, H_mu, H_nr, axis=0)
     return StepResult(X, choose, d_sel, d_mu, d_nr, margin, A, B, H_mu, H_nr)
 
 
-def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0):
+def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0, select="both"):
     """One DNA update of W with H fixed: Algorithm 1 steps 17-28.
 
     The mirror of ``h_step`` written out directly: g = H 1 + rho;
@@ -229,7 +263,7 @@ def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0):
     W(1+A) (step 19); Newton candidate (step 24 read as eq. 15/17) with each
     row renormalised so that sum_r g_r w_nr = (V 1)_n; per-row costs
     (steps 20-22, 25-27); selection per row (step 28).  ``rho`` is the W weight
-    of eq. (2).
+    of eq. (2).  ``select`` as in ``h_step``, per row.
     """
     V, W, H = _f64(V), _f64(W), _f64(H)
     g = H.sum(axis=1)
@@ -242,8 +276,12 @@ def w_step(V, W, H, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0):
     W_mu = np.maximum(W * (1.0 + A), value_floor)
     W_nr = np.maximum(renormalize(newton_candidate(W, A, B, eps, alpha), g, V.sum(axis=1), axis=1),
                       value_floor)
-    d_mu = partial_cost(V, W_mu @ H, axis=1)
     d_nr = partial_cost(V, W_nr @ H, axis=1)
+    if select == "newton_first":
+        d_cur = partial_cost(V, W @ H, axis=1)
+        choose, X, d_sel, margin = _select_newton_first(d_cur, d_nr, W, W_mu, W_nr, g, V.sum(axis=1), 1)
+        return StepResult(X, choose, d_sel, np.full_like(d_nr, np.nan), d_nr, margin, A, B, W_mu, W_nr)
+    d_mu = partial_cost(V, W_mu @ H, axis=1)
     choose, X, d_sel, margin = _select(d_mu, d_nr, W_mu, W_nr, axis=1)
     return StepResult(X, choose, d_sel, d_mu, d_nr, margin, A, B, W_mu, W_nr)
 
@@ -340,22 +378,22 @@ class FitResult:
     obj: list = dataclasses.field(default_factory=list)   # eq. (2), same points as kl
 
 
-def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0, lam=0.0):
+def fit_dna(V, W, H, iters, eps=EPS, alpha=ALPHA, value_floor=0.0, rho=0.0, lam=0.0, select="both"):
     """Algorithm 1: step 1, then per iteration H half-step (4-15), step 16,
     W half-step (17-28), step 29.  Z and Q are recomputed from W H at the start
     of each half-step, which equals carrying them because the normalisations
-    leave W H unchanged."""
+    leave W H unchanged.  ``select`` as in ``h_step``."""
     V = _f64(V)
     W, H = normalize(W, H, 0, rho, lam)
     kl = [kl_cost(V, W, H)]
     obj = [objective(V, W, H, rho, lam)]
     fh, fw = [], []
     for _ in range(iters):
-        r = h_step(V, W, H, eps, alpha, value_floor, lam=lam)
+        r = h_step(V, W, H, eps, alpha, value_floor, lam=lam, select=select)
         H = r.X
         fh.append(float(r.chose_newton.mean()))
         W, H = normalize(W, H, 1, rho, lam)
-        r = w_step(V, W, H, eps, alpha, value_floor, rho=rho)
+        r = w_step(V, W, H, eps, alpha, value_floor, rho=rho, select=select)
         W = r.X
         fw.append(float(r.chose_newton.mean()))
         W, H = normalize(W, H, 0, rho, lam)
