@@ -192,16 +192,17 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
 
 
-def timed_steps(dna, V, W, H, steps, gemm):
+def timed_steps(dna, V, W, H, steps, gemm, **kw):
     import torch
+    dna.iterate(V, W, H, 2, gemm=gemm, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    dna.iterate(V, W, H, steps, gemm=gemm)
+    dna.iterate(V, W, H, steps, gemm=gemm, **kw)
     torch.cuda.synchronize()
     return 1e3 * (time.perf_counter() - t0) / steps
 
 
-def iters_to_targets(dna, V, W0, H0, targets, budget, gemm, chunk=10):
+def iters_to_targets(dna, V, W0, H0, targets, budget, gemm, chunk=10, **kw):
     """DNA iterations (from the same start, step 1 first) until the KL is at or
     below each of `targets`; the KL after every iteration is recorded on the
     device and checked every `chunk` iterations.  Returns ({target: first
@@ -217,7 +218,7 @@ def iters_to_targets(dna, V, W0, H0, targets, budget, gemm, chunk=10):
     while done < budget:
         m = min(chunk, budget - done)
         for k in range(m):
-            dna.iterate(V, W, H, 1, gemm=gemm)
+            dna.iterate(V, W, H, 1, gemm=gemm, **kw)
             dna.kl_cost(V, W, H, out=kls[done + k + 1:done + k + 2])
         done += m
         host = kls[:done + 1].cpu().numpy()
@@ -629,6 +630,17 @@ def main():
             if k_hit:
                 r["speedup_vs_mu_no_cost"] = mu_wall / (k_hit * ms / 1e3)
             target[f"dna_{g}"] = r
+        if R <= 64 and gemm == "fp32":
+            # the damped selection (Newton costed alone, kept iff it does not raise the cost)
+            ms = timed_steps(dna, V, W0.clone(), H0.clone(), args.steps, "fp32", select="newton_first")
+            hits, kl_last = iters_to_targets(dna, V, W0, H0, [kl_target], args.dna_iters, "fp32",
+                                             select="newton_first")
+            k_hit = hits[kl_target]
+            r = {"ms_per_iter": ms, "iters_to_target": k_hit,
+                 "time_to_target_s": (k_hit * ms / 1e3) if k_hit is not None else None, "kl_at_stop": kl_last}
+            if k_hit:
+                r["speedup_vs_mu_no_cost"] = mu_wall / (k_hit * ms / 1e3)
+            target["dna_fp32_newton_first"] = r
 
     out = {
         "metric": METRIC, "value": rec["value"], "unit": "DNA iterations/s", "n_gpus": 1,

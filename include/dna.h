@@ -79,9 +79,31 @@ typedef struct {
                     read-back of the check flags (tests and debugging only)        */
   float rho;     /* eq. (2) weight of sum w (W half-steps, normalisations); >= 0   */
   float lambda;  /* eq. (2) weight of sum h (H half-steps, normalisations); >= 0   */
+  int select;    /* dna_select_rule: how each half-step picks its candidate         */
 } dna_opts;
 
-/* eps = 0.01, alpha = 4 (Sec. 4), FP32 products, unchecked, rho = lambda = 0. */
+/* The selection of steps 7-9, 12-15 (H step; 20-22, 25-28 W step).
+ * DNA_SELECT_BOTH (Algorithm 1): cost both candidates, keep Newton iff
+ *   d_DNA < d_MU.
+ * DNA_SELECT_NEWTON_FIRST (Sec. 5's "more refined step damping", which the
+ *   paper names as its next step without a method; this is the reading built
+ *   here): cost the Newton candidate only and keep it iff its column's (row's)
+ *   eq. (5) objective d_DNA is not above the current state's,
+ *   d_cur + sum_r c_r x_r - sum v (c including lambda, or g including rho),
+ *   with d_cur formed in the ratio pass; else keep the MU candidate, which
+ *   never raises it (Sec. 2.1), uncosted.  One reconstruction product per
+ *   half-step instead of two.  The cost never rises.  Outputs: d_sel is NaN
+ *   where MU is kept; margin = current objective - Newton objective.
+ *   Supported by dna_update_H/W and dna_iterate with FP32 products and
+ *   R <= 64 (DNA_EUNSUPPORTED otherwise, and from dna_select, the sparse calls
+ *   and the unrolled adjoint). */
+typedef enum {
+  DNA_SELECT_BOTH = 0,
+  DNA_SELECT_NEWTON_FIRST = 1
+} dna_select_rule;
+
+/* eps = 0.01, alpha = 4 (Sec. 4), FP32 products, unchecked, rho = lambda = 0,
+ * DNA_SELECT_BOTH. */
 void dna_default_opts(dna_opts* opts);
 
 /* Bytes of workspace any call below needs for an N x T x R problem with these

@@ -138,8 +138,8 @@ struct Layout {
   Split chf;                 // row chunks of the fused H-orientation cost pass (three workgroups per CU fit)
   int rt_m, rt_n;            // ratio-pass tiles along N and along T
   int ch_m, cw_n;            // cost-pass tiles along N (H orientation) / T (W orientation)
-  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, sume, vpart, cpart, fpart, s16, cs, zd, dz, selm, check,
-      total;
+  size_t q, qb, pu, puc, py, xmu, xn, c32, c64, sump, sump2, sume, vpart, dpart, cpart, fpart, s16, cs, zd, dz, selm,
+      check, total;
 };
 
 // Split of an fp32 tiled gradient product whose chunks are whole multiples of
@@ -193,6 +193,7 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16, bool adj
   // sums emitted by the normalisation for the next half-step (dna_iterate)
   L.sume = take((size_t)std::max(scale_emit_parts(0, N, T), scale_emit_parts(1, N, T)) * R * 8);
   L.vpart = take(red * 8);
+  L.dpart = take(R <= FUSED_MAX_R ? red * 8 : 0);     // input-state costs of the damped selection
   L.cpart = take(std::max(3 * red, klt) * 8);
   L.fpart = take(red * 4);
   L.s16 = take(with16 ? scratch16_bytes(N, T, R) : 0);
@@ -255,6 +256,19 @@ static dna_status check_opts(const dna_opts* o) {
   if (o->gemm < DNA_GEMM_FP32 || o->gemm > DNA_GEMM_FP16) return fail(DNA_EINVAL, "unknown gemm type");
   if (!(o->rho >= 0.f) || !std::isfinite(o->rho) || !(o->lambda >= 0.f) || !std::isfinite(o->lambda))
     return fail(DNA_EINVAL, "rho and lambda must be finite and >= 0");
+  if (o->select != DNA_SELECT_BOTH && o->select != DNA_SELECT_NEWTON_FIRST)
+    return fail(DNA_EINVAL, "unknown selection rule");
+  return DNA_OK;
+}
+
+// The damped selection runs on the fused fp32 path (R <= FUSED_MAX_R).
+static dna_status check_select(const dna_opts* o, int64_t R) {
+  if (o->select == DNA_SELECT_NEWTON_FIRST && (o->gemm != DNA_GEMM_FP32 || R > FUSED_MAX_R))
+    return fail(DNA_EUNSUPPORTED, "DNA_SELECT_NEWTON_FIRST runs with FP32 products and R <= 64 only");
+  return DNA_OK;
+}
+static dna_status check_select_both(const dna_opts* o) {
+  if (o->select != DNA_SELECT_BOTH) return fail(DNA_EUNSUPPORTED, "this call supports DNA_SELECT_BOTH only");
   return DNA_OK;
 }
 
@@ -350,8 +364,9 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
       DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh16.splits, L.sh16.kchunk, pu, puc, py,
                                 vpart, chk, job, s), "ratio_gh16_H");
     } else if (fused) {
-      DNA_HIP(launch_rgh(0, V, W, H, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, job, chk, s),
-              "rgh_H");
+      const bool damp = o->select == DNA_SELECT_NEWTON_FIRST;
+      DNA_HIP(launch_rgh(0, V, W, H, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, job, chk, s,
+                         damp ? RGH_DNA_COST : RGH_DNA, damp ? at<double>(ws, L.dpart) : nullptr), "rgh_H");
     } else {
       float* cs = at<float>(ws, L.cs);
       DNA_HIP(launch_ratio(carry ? RM_H_CARRY : RM_H, ra, s), "ratio_H");
@@ -377,8 +392,9 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
       DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw16.splits, L.sw16.kchunk, pu, puc, py,
                                 vpart, chk, job, s), "ratio_gh16_W");
     } else if (fused) {
-      DNA_HIP(launch_rgh(1, V, W, H, N, T, R, L.swf.splits, L.swf.kchunk, pu, puc, py, vpart, job, chk, s),
-              "rgh_W");
+      const bool damp = o->select == DNA_SELECT_NEWTON_FIRST;
+      DNA_HIP(launch_rgh(1, V, W, H, N, T, R, L.swf.splits, L.swf.kchunk, pu, puc, py, vpart, job, chk, s,
+                         damp ? RGH_DNA_COST : RGH_DNA, damp ? at<double>(ws, L.dpart) : nullptr), "rgh_W");
     } else {
       float* cs = at<float>(ws, L.cs);
       DNA_HIP(launch_ratio(carry ? RM_W_CARRY : RM_W, ra, s), "ratio_W");
@@ -417,20 +433,33 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
     return DNA_OK;
   }
   const bool fused = R <= FUSED_MAX_R;   // candidates' block resident in LDS
+  // the damped selection: the Newton candidate's cost against the input
+  // state's (its cost parts from the fused ratio pass; Xout holds that state)
+  const bool damp = o->select == DNA_SELECT_NEWTON_FIRST;
+  Damp dp;
+  if (damp) {
+    dp.dpart = at<double>(ws, L.dpart);
+    dp.vpart = at<double>(ws, L.vpart);
+    dp.dtiles = dp.vtiles = side == 0 ? L.shf.splits : L.swf.splits;
+    dp.c64 = at<double>(ws, L.c64);
+    dp.reg = side == 0 ? o->lambda : o->rho;
+  }
   if (side == 0) {
     if (fused)
-      DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.chf.splits, L.chf.kchunk, cpart, fpart, s), "costf_H");
+      DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.chf.splits, L.chf.kchunk, cpart, fpart, s, damp),
+              "costf_H");
     else
       DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz), "cost_H");
     DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, fused ? L.chf.splits : L.ch_m, T, R, mask, dsel, margin,
-                            s), "select_H");
+                            s, dp), "select_H");
   } else {
     if (fused)
-      DNA_HIP(launch_costf(1, V, F, Xmu, Xn, N, T, R, L.swf.splits, L.swf.kchunk, cpart, fpart, s), "costf_W");
+      DNA_HIP(launch_costf(1, V, F, Xmu, Xn, N, T, R, L.swf.splits, L.swf.kchunk, cpart, fpart, s, damp),
+              "costf_W");
     else
       DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz), "cost_W");
     DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, fused ? L.swf.splits : L.cw_n, N, R, mask, dsel, margin,
-                            s), "select_W");
+                            s, dp), "select_W");
   }
   return DNA_OK;
 }
@@ -526,6 +555,7 @@ void dna_default_opts(dna_opts* o) {
   o->checked = 0;
   o->rho = 0.f;
   o->lambda = 0.f;
+  o->select = DNA_SELECT_BOTH;
 }
 
 size_t dna_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_opts* o) {
@@ -549,6 +579,8 @@ dna_status dna_update_H(const float* V, const float* W, float* H, int64_t N, int
                         double* margin, void* stream) {
   if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
   Common c;
+  DNA_TRY(check_opts(o));
+  DNA_TRY(check_select(o, R));   // before anything is enqueued
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   float* Xmu = at<float>(ws, c.L.xmu);
   float* Xn = at<float>(ws, c.L.xn);
@@ -562,6 +594,8 @@ dna_status dna_update_W(const float* V, float* W, const float* H, int64_t N, int
                         double* margin, void* stream) {
   if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
   Common c;
+  DNA_TRY(check_opts(o));
+  DNA_TRY(check_select(o, R));   // before anything is enqueued
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   float* Xmu = at<float>(ws, c.L.xmu);
   float* Xn = at<float>(ws, c.L.xn);
@@ -587,6 +621,8 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
   if (!V || !W || !H) return fail(DNA_EINVAL, "V, W or H is NULL");
   if (iters < 0) return fail(DNA_EINVAL, "iters must be >= 0");
   Common c;
+  DNA_TRY(check_opts(o));
+  DNA_TRY(check_select(o, R));   // before anything is enqueued
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
   float* Xmu = at<float>(ws, c.L.xmu);
   float* Xn = at<float>(ws, c.L.xn);
@@ -780,6 +816,7 @@ dna_status dna_select(int side, const float* V, const float* F, const float* X_m
   Common c;
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
+  DNA_TRY(check_select_both(o));
   c.L = make_layout(N, T, R, o->gemm != DNA_GEMM_FP32);
   DNA_TRY(check_ws(ws, ws_bytes, c.L.total));
   c.s = static_cast<hipStream_t>(stream);
@@ -801,6 +838,7 @@ dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_ini
   if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
+  DNA_TRY(check_select_both(o));
   if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint runs in fp32 only");
   if (o->lambda != 0.f) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint has no lambda terms");
   const AdjLayout A = make_adj_layout(N, T, R);
@@ -833,6 +871,7 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
   if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
+  DNA_TRY(check_select_both(o));
   if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint runs in fp32 only");
   if (o->lambda != 0.f) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint has no lambda terms");
   const AdjLayout A = make_adj_layout(N, T, R);
@@ -969,6 +1008,7 @@ static dna_status check_sparse(const dna_sparse_v* V, int64_t N, int64_t T, int6
   if (!V) return fail(DNA_EINVAL, "sparse V is NULL");
   DNA_TRY(check_dims(N, T, R));
   DNA_TRY(check_opts(o));
+  DNA_TRY(check_select_both(o));
   if (o->gemm != DNA_GEMM_FP32) return fail(DNA_EUNSUPPORTED, "sparse V supports FP32 products only");
   if (R > SP_MAX_R) return fail(DNA_EUNSUPPORTED, "sparse V supports R <= 256");
   if (V->nnz < 0 || V->nnz >= ((int64_t)1 << 31)) return fail(DNA_EINVAL, "nnz must lie in [0, 2^31)");

@@ -164,6 +164,19 @@ __device__ __forceinline__ int cost_acc_f(float x, float zN, float dz, float& a0
 }
 
 // ---------------------------------------------------------------------------
+// The Newton candidate's term alone (damped selection): s0 += v log2(v/z_DNA);
+// returns flag bit 1 where z_DNA <= 0 at v > 0.
+__device__ __forceinline__ int cost_acc_newton(float x, float zN, double& s0) {
+  const bool pos = x > 0.f, okN = zN > 0.f;
+  s0 += (double)(x * log2_hw((pos && okN) ? x * __builtin_amdgcn_rcpf(zN) : 1.f));
+  return (pos && !okN) ? 1 : 0;
+}
+__device__ __forceinline__ int cost_acc_newton_f(float x, float zN, float& a0) {
+  const bool pos = x > 0.f, okN = zN > 0.f;
+  a0 += x * log2_hw((pos && okN) ? x * __builtin_amdgcn_rcpf(zN) : 1.f);
+  return (pos && !okN) ? 1 : 0;
+}
+
 // Epilogues of the candidate-cost passes (steps 7-9, 12-14), shared by the fp32
 // and 16-bit kernels.  acc[..][0] holds z_DNA, acc[..][1] holds dZ = z_MU - z_DNA
 // at this lane's accumulator positions; vf holds v there.  Partials (natural

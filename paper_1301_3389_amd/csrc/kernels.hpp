@@ -138,12 +138,23 @@ hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const
                          float* zd = nullptr, float* dz = nullptr);
 
 // Selection and write-back.
+// The damped selection's inputs (dpart == nullptr: Algorithm 1's rule).  With
+// them the selection reads the current factor from the output buffer before
+// overwriting it (Xout must hold the input state).
+struct Damp {
+  const double* dpart = nullptr;   // input-state cost parts, dtiles x L
+  int dtiles = 0;
+  const double* vpart = nullptr;   // data sum parts, vtiles x L
+  int vtiles = 0;
+  const double* c64 = nullptr;     // c = W^t 1 (H step) / g = H 1 (W step), float64
+  double reg = 0.0;                // lambda (H step) / rho (W step)
+};
 hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,
                            const int* fpart, int tiles_m, int64_t T, int64_t R, uint8_t* mask,
-                           double* dsel, double* margin, hipStream_t s);
+                           double* dsel, double* margin, hipStream_t s, const Damp& dp = Damp{});
 hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const double* part,
                            const int* fpart, int tiles_n, int64_t N, int64_t R, uint8_t* mask,
-                           double* dsel, double* margin, hipStream_t s);
+                           double* dsel, double* margin, hipStream_t s, const Damp& dp = Damp{});
 
 // MU update from split partials (+ optional cost finalisation).
 hipError_t launch_mu_H(float* H, const float* pu, int splits, const float* c, int64_t T, int64_t R,
@@ -185,16 +196,21 @@ hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int6
 // u and, in vpart, the per-column (side 0) / per-row (side 1) cost
 // sum_{v>0} v log(v/z) of the input state, natural log.
 constexpr int64_t FUSED_MAX_R = 64;
-constexpr int RGH_DNA = 0, RGH_MU = 1, RGH_MU_COST = 2;
+// RGH_DNA_COST: RGH_DNA and, in dpart (same layout as vpart), the input
+// state's per-column (row) cost, natural log (the damped selection).
+constexpr int RGH_DNA = 0, RGH_MU = 1, RGH_MU_COST = 2, RGH_DNA_COST = 3;
 hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
                       int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart, const SumJob& fin,
-                      int* check, hipStream_t s, int mode = RGH_DNA);
+                      int* check, hipStream_t s, int mode = RGH_DNA, double* dpart = nullptr);
 
 // Steps 7-9, 12-14 for R <= 64 with the candidates' block resident in LDS:
 // cost partials over `splits` chunks of rows n (side 0) or columns t (side 1),
 // in the layout of launch_cost_H / launch_cost_W with tiles = splits.
+// newton_only: the damped selection's pass, the Newton candidate's cost alone
+// (one product; the margin and MU slots of the partials are zero).
 hipError_t launch_costf(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
-                        int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s);
+                        int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s,
+                        bool newton_only = false);
 
 hipError_t launch_kl_final(const double* cpart, int ntiles, double* out, hipStream_t s);
 

@@ -135,14 +135,18 @@ __device__ __forceinline__ void fetch_v_in(const float* V, int64_t T, int64_t n0
 // MU numerator u alone (no Q-bar tile); RGH_MU_COST also the input state's
 // cost sum_{v>0} v log(v/z) per column (row) in place of the V sums, with the
 // ratio pass's per-entry arithmetic.
+// RGH_DNA_COST: RGH_DNA plus the input state's per-column (row) cost in dpart
+// (the damped selection compares the Newton candidate with it).
 template <bool CHK, int MODE>
 __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W, const float* H, int64_t N,
                                                   int64_t T, int64_t R, int64_t nchunk, float* pu, float* puc,
-                                                  float* py, double* vpart, SumJob fin, int* check) {
-  constexpr int NA = MODE == RGH_DNA ? 3 : 1;     // accumulated products
+                                                  float* py, double* vpart, double* dpart, SumJob fin, int* check) {
+  constexpr bool DNA = MODE == RGH_DNA || MODE == RGH_DNA_COST;
+  constexpr int NA = DNA ? 3 : 1;                 // accumulated products
+  constexpr int NQ = MODE == RGH_DNA_COST ? 2 : 1;   // column sums: V (DNA) or cost (MU), and the cost
   __shared__ __align__(16) float lh[FT];
   __shared__ __align__(16) float lw[FT];
-  __shared__ __align__(16) float lq[MODE == RGH_DNA ? 2 : 1][FT];
+  __shared__ __align__(16) float lq[DNA ? 2 : 1][FT];
   sum_job(fin);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave: scalar loop bounds
@@ -160,8 +164,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
   for (int c = 0; c < NA; ++c)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
-  double cp[1][GF::FN];
-  cp[0][0] = 0.0;
+  double cp[NQ][GF::FN];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) cp[q][0] = 0.0;
   int bad = 0;
   {
     f32x4 hx[4];
@@ -206,9 +211,10 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       const float q = x > 0.f ? x * iz : 0.f;
       if (CHK) bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
       lq[0][rl * FP + cl] = q;
-      if constexpr (MODE == RGH_DNA) {
+      if constexpr (DNA) {
         lq[1][rl * FP + cl] = x > 0.f ? q * iz : 0.f;   // padding has z = 0: no 0 * inf
         cp[0][0] += (double)x;
+        if constexpr (MODE == RGH_DNA_COST) cp[1][0] += (double)(x * log2_hw(x > 0.f ? q : 1.f));
       } else if constexpr (MODE == RGH_MU_COST) {
         cp[0][0] += (double)(x * log2_hw(x > 0.f ? q : 1.f)) * LN2;
       }
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
         const float a = lw[kr * FP + rb + (lane & 31)];
         const float b0 = lq[0][kr * FP + cl];
         acc[0] = mfma32(a, b0, acc[0]);
-        if constexpr (MODE == RGH_DNA) {
+        if constexpr (DNA) {
           const float b1 = lq[NA - 2][kr * FP + cl];
           acc[NA - 2] = mfma32(a, b0 - 1.f, acc[NA - 2]);
           acc[NA - 1] = mfma32(a * a, b1, acc[NA - 1]);
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
       for (int v = 0; v < 16; ++v) vf[v] = vn[v];
     __syncthreads();                              // lw and lq free for the next sub-tile
   }
-  static_assert(NA * 2048 <= (MODE == RGH_DNA ? 2 : 1) * FT, "fold buffer");
+  static_assert(NA * 2048 <= (DNA ? 2 : 1) * FT, "fold buffer");
   if (half) fold_halves<NA>(acc, &lq[0][0], wm == 1, wn, lane);   // the wm = 1 pair holds no rank >= R
   float* out[3] = {pu, puc, py};
 #pragma unroll
@@ -245,8 +251,11 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
     }
   }
   if constexpr (MODE != RGH_MU)                   // V sums (DNA) or input-state costs (MU with cost)
-    reduce_cols<GF, 1>(cp, reinterpret_cast<double*>(lw), [&](int c, const double (&s)[1]) {
-      if (t0 + c < T) vpart[sp * T + t0 + c] = s[0];
+    reduce_cols<GF, NQ>(cp, reinterpret_cast<double*>(lw), [&](int c, const double (&s)[NQ]) {
+      if (t0 + c < T) {
+        vpart[sp * T + t0 + c] = s[0];
+        if constexpr (NQ == 2) dpart[sp * T + t0 + c] = s[NQ - 1] * LN2;
+      }
     });
   if (CHK && bad) atomicOr(check, CHK_DOMAIN);
 }
@@ -260,11 +269,13 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
 template <bool CHK, int MODE>
 __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W, const float* H, int64_t N,
                                                   int64_t T, int64_t R, int64_t tchunk, float* pu, float* puc,
-                                                  float* py, double* vpart, SumJob fin, int* check) {
-  constexpr int NA = MODE == RGH_DNA ? 3 : 1;
+                                                  float* py, double* vpart, double* dpart, SumJob fin, int* check) {
+  constexpr bool DNA = MODE == RGH_DNA || MODE == RGH_DNA_COST;
+  constexpr int NA = DNA ? 3 : 1;
+  constexpr int NQ = MODE == RGH_DNA_COST ? 2 : 1;
   __shared__ __align__(16) float lw[FT];
   __shared__ __align__(16) float lh[FT];
-  __shared__ __align__(16) float lq[MODE == RGH_DNA ? 2 : 1][FT];
+  __shared__ __align__(16) float lq[DNA ? 2 : 1][FT];
   sum_job(fin);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave: scalar loop bounds
@@ -281,9 +292,11 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   for (int c = 0; c < NA; ++c)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
-  double rp[1][GF::FM][16];
+  double rp[NQ][GF::FM][16];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) rp[0][0][v] = 0.0;
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) rp[q][0][v] = 0.0;
   int bad = 0;
   {
     f32x4 wx[4];
@@ -330,9 +343,10 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       const float q = x > 0.f ? x * iz : 0.f;
       if (CHK) bad |= (x > 0.f && !(z[v] > 0.f)) ? 1 : 0;
       lq[0][rl * FP + tl] = q;
-      if constexpr (MODE == RGH_DNA) {
+      if constexpr (DNA) {
         lq[1][rl * FP + tl] = x > 0.f ? q * iz : 0.f;
         rp[0][0][v] += (double)x;
+        if constexpr (MODE == RGH_DNA_COST) rp[1][0][v] += (double)(x * log2_hw(x > 0.f ? q : 1.f));
       } else if constexpr (MODE == RGH_MU_COST) {
         rp[0][0][v] += (double)(x * log2_hw(x > 0.f ? q : 1.f)) * LN2;
       }
@@ -345,7 +359,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       for (int g = g0; g < g0 + ng; ++g) {
         const f32x4 a0 = ld4(lq[0] + o + 8 * g);
         const f32x4 b = ld4(pb + 8 * g);
-        if constexpr (MODE == RGH_DNA) {
+        if constexpr (DNA) {
           const f32x4 a1 = ld4(lq[NA - 2] + o + 8 * g);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
@@ -364,7 +378,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
       for (int v = 0; v < 16; ++v) vf[v] = vn[v];
     __syncthreads();
   }
-  static_assert(NA * 2048 <= (MODE == RGH_DNA ? 2 : 1) * FT, "fold buffer");
+  static_assert(NA * 2048 <= (DNA ? 2 : 1) * FT, "fold buffer");
   if (half) fold_halves<NA>(acc, &lq[0][0], wn == 1, wm, lane);   // the wn = 1 pair holds no rank >= R
   float* out[3] = {pu, puc, py};
 #pragma unroll
@@ -376,8 +390,11 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
     }
   }
   if constexpr (MODE != RGH_MU)
-    reduce_rows<GF, 1>(rp, reinterpret_cast<double*>(lw), [&](int r, const double (&s)[1]) {
-      if (n0 + r < N) vpart[sp * N + n0 + r] = s[0];
+    reduce_rows<GF, NQ>(rp, reinterpret_cast<double*>(lw), [&](int r, const double (&s)[NQ]) {
+      if (n0 + r < N) {
+        vpart[sp * N + n0 + r] = s[0];
+        if constexpr (NQ == 2) dpart[sp * N + n0 + r] = s[NQ - 1] * LN2;
+      }
     });
   if (CHK && bad) atomicOr(check, CHK_DOMAIN);
 }
@@ -391,6 +408,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
 // [r][t]) and a range of rows n (W rows streamed, [n][r]); each lane keeps
 // float64 column partials over the whole range.  Partials: part[q][sp][t].
 // ---------------------------------------------------------------------------
+// NO (newton only, the damped selection): z_DNA alone, the cost terms of
+// d_DNA only (the margin and MU slots of the partials are written as zero).
+template <bool NO>
 __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float* W, const float* Xmu,
                                                     const float* Xn, int64_t N, int64_t T, int64_t R,
                                                     int64_t nchunk, double* part, int* fpart) {
@@ -410,11 +430,13 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
   {
     f32x4 a[4], b[4];
     fetch_block(Xn, T, 0, t0, R, T, a, tid);
-    fetch_block(Xmu, T, 0, t0, R, T, b, tid);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) b[i] -= a[i];
     store_block(ln, a, tid);
-    store_block(ld, b, tid);
+    if (!NO) {
+      fetch_block(Xmu, T, 0, t0, R, T, b, tid);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b[i] -= a[i];
+      store_block(ld, b, tid);
+    }
   }
   double cp[3][GF::FN];
   cp[0][0] = cp[1][0] = cp[2][0] = 0.0;
@@ -451,14 +473,15 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
         for (int m = 0; m < 4; ++m) {
           const int kk = kq(g, lane, m) * FP + cl;
           zn = mfma32(a4[m], ln[kk], zn);
-          dz = mfma32(a4[m], ld[kk], dz);
+          if (!NO) dz = mfma32(a4[m], ld[kk], dz);
         }
       }
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float x = vf[v];                      // 0 outside the matrix
-      fl |= cost_acc(x, zn[v], dz[v], cp[0][0], cp[1][0], cp[2][0]);
+      if (NO) fl |= cost_acc_newton(x, zn[v], cp[0][0]);
+      else fl |= cost_acc(x, zn[v], dz[v], cp[0][0], cp[1][0], cp[2][0]);
     }
     if (more)
 #pragma unroll
@@ -481,6 +504,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
 // [n][r]) and a range of columns t (H streamed, [r][t]).  Row partials of each
 // sub-tile are reduced across the half-wave at once (halfwave_slot_sum) and
 // kept per lane in float64.  Partials: part[q][sp][n].
+template <bool NO>
 __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float* H, const float* Xmu,
                                                     const float* Xn, int64_t N, int64_t T, int64_t R,
                                                     int64_t tchunk, double* part, int* fpart) {
@@ -499,11 +523,13 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
   {
     f32x4 a[4], b[4];
     fetch_block(Xn, R, n0, 0, N, R, a, tid);
-    fetch_block(Xmu, R, n0, 0, N, R, b, tid);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) b[i] -= a[i];
     store_block(ln, a, tid);
-    store_block(ld, b, tid);
+    if (!NO) {
+      fetch_block(Xmu, R, n0, 0, N, R, b, tid);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b[i] -= a[i];
+      store_block(ld, b, tid);
+    }
   }
   double rs[3] = {0.0, 0.0, 0.0};                 // this lane's slot of the row partials
   int flr[16];
@@ -544,12 +570,12 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
 #pragma unroll 2
       for (int g = 0; g < gz; ++g) {
         const f32x4 an = ld4(ln + o + 8 * g);
-        const f32x4 ad = ld4(ld + o + 8 * g);
+        const f32x4 ad = NO ? an : ld4(ld + o + 8 * g);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const float b = lh[kq(g, lane, m) * FP + tl];
           zn = mfma32(an[m], b, zn);
-          dz = mfma32(ad[m], b, dz);
+          if (!NO) dz = mfma32(ad[m], b, dz);
         }
       }
     }
@@ -559,7 +585,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
     for (int v = 0; v < 16; ++v) {
       s2[v] = 0.0;
       const float x = vf[v];                      // 0 outside the matrix
-      const int f = cost_acc_f(x, zn[v], dz[v], a0[v], a1[v], s2[v]);
+      const int f = NO ? cost_acc_newton_f(x, zn[v], a0[v]) : cost_acc_f(x, zn[v], dz[v], a0[v], a1[v], s2[v]);
       flr[v] |= f;
       fsub |= f;
     }
@@ -602,17 +628,24 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
 }
 
 hipError_t launch_costf(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
-                        int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s) {
+                        int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s,
+                        bool newton_only) {
   if (R > FUSED_MAX_R) return hipErrorInvalidValue;
   if (side == 0) {
     prof_begin("costf_H", s);
-    hipLaunchKernelGGL(k_costf_H, dim3((unsigned)cdiv(T, 64), (unsigned)splits), dim3(256), 0, s, V, F, Xmu, Xn, N,
-                       T, R, chunk, part, fpart);
+    const dim3 grid((unsigned)cdiv(T, 64), (unsigned)splits);
+    if (newton_only)
+      hipLaunchKernelGGL(k_costf_H<true>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
+    else
+      hipLaunchKernelGGL(k_costf_H<false>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
     prof_end("costf_H", s);
   } else {
     prof_begin("costf_W", s);
-    hipLaunchKernelGGL(k_costf_W, dim3((unsigned)cdiv(N, 64), (unsigned)splits), dim3(256), 0, s, V, F, Xmu, Xn, N,
-                       T, R, chunk, part, fpart);
+    const dim3 grid((unsigned)cdiv(N, 64), (unsigned)splits);
+    if (newton_only)
+      hipLaunchKernelGGL(k_costf_W<true>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
+    else
+      hipLaunchKernelGGL(k_costf_W<false>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
     prof_end("costf_W", s);
   }
   return hipGetLastError();
@@ -621,38 +654,42 @@ hipError_t launch_costf(int side, const float* V, const float* F, const float* X
 template <int MODE>
 static void launch_rgh_mode(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T,
                             int64_t R, int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart,
-                            const SumJob& fin, int* check, hipStream_t s) {
+                            double* dpart, const SumJob& fin, int* check, hipStream_t s) {
   if (side == 0) {
     const dim3 grid((unsigned)cdiv(T, 64), (unsigned)splits);
     if (check)
       hipLaunchKernelGGL((k_rgh_H<true, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
-                         fin, check);
+                         dpart, fin, check);
     else
       hipLaunchKernelGGL((k_rgh_H<false, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
-                         fin, check);
+                         dpart, fin, check);
   } else {
     const dim3 grid((unsigned)cdiv(N, 64), (unsigned)splits);
     if (check)
       hipLaunchKernelGGL((k_rgh_W<true, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
-                         fin, check);
+                         dpart, fin, check);
     else
       hipLaunchKernelGGL((k_rgh_W<false, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
-                         fin, check);
+                         dpart, fin, check);
   }
 }
 
 hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T, int64_t R,
                       int splits, int64_t chunk, float* pu, float* puc, float* py, double* vpart, const SumJob& fin,
-                      int* check, hipStream_t s, int mode) {
+                      int* check, hipStream_t s, int mode, double* dpart) {
   if (R > FUSED_MAX_R) return hipErrorInvalidValue;
-  const char* name = mode == RGH_DNA ? (side == 0 ? "rgh_H" : "rgh_W") : (side == 0 ? "rgh_mu_H" : "rgh_mu_W");
+  if (mode == RGH_DNA_COST && !dpart) return hipErrorInvalidValue;
+  const bool dna = mode == RGH_DNA || mode == RGH_DNA_COST;
+  const char* name = dna ? (side == 0 ? "rgh_H" : "rgh_W") : (side == 0 ? "rgh_mu_H" : "rgh_mu_W");
   prof_begin(name, s);
   if (mode == RGH_DNA)
-    launch_rgh_mode<RGH_DNA>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, fin, check, s);
+    launch_rgh_mode<RGH_DNA>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, dpart, fin, check, s);
+  else if (mode == RGH_DNA_COST)
+    launch_rgh_mode<RGH_DNA_COST>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, dpart, fin, check, s);
   else if (mode == RGH_MU)
-    launch_rgh_mode<RGH_MU>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, fin, check, s);
+    launch_rgh_mode<RGH_MU>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, dpart, fin, check, s);
   else
-    launch_rgh_mode<RGH_MU_COST>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, fin, check, s);
+    launch_rgh_mode<RGH_MU_COST>(side, V, W, H, N, T, R, splits, chunk, pu, puc, py, vpart, dpart, fin, check, s);
   prof_end(name, s);
   return hipGetLastError();
 }

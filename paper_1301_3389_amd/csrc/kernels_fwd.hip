@@ -982,6 +982,29 @@ hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const
 // ---------------------------------------------------------------------------
 // Selection (steps 15 and 28).
 // ---------------------------------------------------------------------------
+// The damped selection (dp.dpart != nullptr): the Newton candidate is kept iff
+// its column (row) objective of eq. (5), d_DNA (Sigma c x = Sigma v by eq. 10),
+// is not above the current state's, d_cur + Sigma_r c_r x_r - Sigma v; the
+// margin is their difference and d_sel is NaN where MU is kept uncosted.
+__device__ __forceinline__ bool decide_damped(double dN, int fl, double dcur, double cx, double sv, double& dsel,
+                                              double& margin) {
+  const bool finite = (fl & 1) == 0;
+  margin = finite ? (dcur + cx - sv) - dN : -INFINITY;
+  const bool newton = finite && margin >= 0.0;
+  dsel = newton ? dN : NAN;
+  return newton;
+}
+
+// Per-column (row) inputs of the damped rule, each summed in a fixed order:
+// the input state's cost parts (dtiles of them), the data sum parts (vtiles)
+// and Sigma_r (c_r + reg) x_r of the current factor entries.
+__device__ __forceinline__ void damp_sums(const Damp& dp, int64_t L, int64_t idx, double& dcur, double& sv) {
+  dcur = 0.0;
+  sv = 0.0;
+  for (int m = 0; m < dp.dtiles; ++m) dcur += dp.dpart[(int64_t)m * L + idx];
+  for (int m = 0; m < dp.vtiles; ++m) sv += dp.vpart[(int64_t)m * L + idx];
+}
+
 __device__ __forceinline__ bool decide(double q0, double q1, double q2, int fl, double& dsel, double& margin) {
   const double dN = (fl & 1) ? INFINITY : q0;
   const double dM = (fl & 2) ? INFINITY : q0 + q1 + q2;
@@ -1001,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_select_H(const float* __restrict__ Xmu,
                                                   float* __restrict__ Hout,
                                                   const double* part, const int* fpart, int tiles,
                                                   int64_t T, int64_t R, uint8_t* mask, double* dsel,
-                                                  double* margin) {
+                                                  double* margin, Damp dp) {
   // CAND_COLS columns per block: row group 0 decides, every row group copies.
   __shared__ int pick[CAND_COLS];
   const int tid = threadIdx.x, cl = tid % CAND_COLS, rg = tid / CAND_COLS;
@@ -1020,7 +1043,15 @@ __global__ __launch_bounds__(256) void k_select_H(const float* __restrict__ Xmu,
       fl |= fpart[o];
     }
     double ds, mg;
-    const bool nw = decide(q0, q1, q2, fl, ds, mg);
+    bool nw;
+    if (dp.dpart) {                      // Hout still holds the current H
+      double dcur, sv, cx = 0.0;
+      damp_sums(dp, T, t, dcur, sv);
+      for (int64_t r = 0; r < R; ++r) cx += (dp.c64[r] + dp.reg) * (double)Hout[r * T + t];
+      nw = decide_damped(q0, fl, dcur, cx, sv, ds, mg);
+    } else {
+      nw = decide(q0, q1, q2, fl, ds, mg);
+    }
     if (mask) mask[t] = nw ? 1 : 0;
     if (dsel) dsel[t] = ds;
     if (margin) margin[t] = mg;
@@ -1042,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_select_H_cols(const float* __restrict__
                                                        float* __restrict__ Hout,
                                                        const double* part, const int* fpart, int tiles,
                                                        int64_t T, int64_t R, uint8_t* mask, double* dsel,
-                                                       double* margin) {
+                                                       double* margin, Damp dp) {
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= T) return;
@@ -1061,7 +1092,17 @@ __global__ __launch_bounds__(256) void k_select_H_cols(const float* __restrict__
   q2 = __shfl(wave_sum(q2), 0);
   fl = wave_or(fl);
   double ds, mg;
-  const bool nw = decide(q0, q1, q2, fl, ds, mg);
+  bool nw;
+  if (dp.dpart) {                        // Hout still holds the current H
+    double cx = 0.0;
+    for (int64_t r = lane; r < R; r += 64) cx += (dp.c64[r] + dp.reg) * (double)Hout[r * T + t];
+    cx = __shfl(wave_sum(cx), 0);
+    double dcur, sv;
+    damp_sums(dp, T, t, dcur, sv);
+    nw = decide_damped(q0, fl, dcur, cx, sv, ds, mg);
+  } else {
+    nw = decide(q0, q1, q2, fl, ds, mg);
+  }
   if (lane == 0) {
     if (mask) mask[t] = nw ? 1 : 0;
     if (dsel) dsel[t] = ds;
@@ -1073,14 +1114,14 @@ __global__ __launch_bounds__(256) void k_select_H_cols(const float* __restrict__
 
 hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,
                            const int* fpart, int tiles_m, int64_t T, int64_t R, uint8_t* mask,
-                           double* dsel, double* margin, hipStream_t s) {
+                           double* dsel, double* margin, hipStream_t s, const Damp& dp) {
   prof_begin("select_H", s);
   if (tiles_m > SEL_MANY && T <= SEL_MANY_COLS)
     hipLaunchKernelGGL(k_select_H_cols, dim3((unsigned)cdiv(T, 4)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
-                       tiles_m, T, R, mask, dsel, margin);
+                       tiles_m, T, R, mask, dsel, margin, dp);
   else
     hipLaunchKernelGGL(k_select_H, dim3((unsigned)cdiv(T, CAND_COLS)), dim3(256), 0, s, Xmu, Xn, Hout, part, fpart,
-                       tiles_m, T, R, mask, dsel, margin);
+                       tiles_m, T, R, mask, dsel, margin, dp);
   prof_end("select_H", s);
   return hipGetLastError();
 }
@@ -1090,7 +1131,7 @@ __global__ __launch_bounds__(256) void k_select_W(const float* __restrict__ Xmu,
                                                   float* __restrict__ Wout,
                                                   const double* part, const int* fpart, int tiles,
                                                   int64_t N, int64_t R, uint8_t* mask, double* dsel,
-                                                  double* margin) {
+                                                  double* margin, Damp dp) {
   const int lane = threadIdx.x & 63;
   const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= N) return;
@@ -1109,7 +1150,17 @@ __global__ __launch_bounds__(256) void k_select_W(const float* __restrict__ Xmu,
   q2 = __shfl(wave_sum(q2), 0);
   fl = wave_or(fl);
   double ds, mg;
-  const bool nw = decide(q0, q1, q2, fl, ds, mg);
+  bool nw;
+  if (dp.dpart) {                        // Wout still holds the current W
+    double cx = 0.0;
+    for (int64_t r = lane; r < R; r += 64) cx += (dp.c64[r] + dp.reg) * (double)Wout[n * R + r];
+    cx = __shfl(wave_sum(cx), 0);
+    double dcur, sv;
+    damp_sums(dp, N, n, dcur, sv);
+    nw = decide_damped(q0, fl, dcur, cx, sv, ds, mg);
+  } else {
+    nw = decide(q0, q1, q2, fl, ds, mg);
+  }
   if (lane == 0) {
     if (mask) mask[n] = nw ? 1 : 0;
     if (dsel) dsel[n] = ds;
@@ -1127,7 +1178,7 @@ __global__ __launch_bounds__(256) void k_select_W_rows(const float* __restrict__
                                                        float* __restrict__ Wout,
                                                        const double* part, const int* fpart, int tiles,
                                                        int64_t N, int64_t R, uint8_t* mask, double* dsel,
-                                                       double* margin) {
+                                                       double* margin, Damp dp) {
   __shared__ int pick[SEL_ROWS];
   const int tid = threadIdx.x;
   const int64_t n0 = (int64_t)blockIdx.x * SEL_ROWS;
@@ -1145,7 +1196,15 @@ __global__ __launch_bounds__(256) void k_select_W_rows(const float* __restrict__
       fl |= fpart[o];
     }
     double ds, mg;
-    const bool nw = decide(q0, q1, q2, fl, ds, mg);
+    bool nw;
+    if (dp.dpart) {                      // Wout still holds the current W
+      double dcur, sv, cx = 0.0;
+      damp_sums(dp, N, n, dcur, sv);
+      for (int64_t r = 0; r < R; ++r) cx += (dp.c64[r] + dp.reg) * (double)Wout[n * R + r];
+      nw = decide_damped(q0, fl, dcur, cx, sv, ds, mg);
+    } else {
+      nw = decide(q0, q1, q2, fl, ds, mg);
+    }
     if (mask) mask[n] = nw ? 1 : 0;
     if (dsel) dsel[n] = ds;
     if (margin) margin[n] = mg;
@@ -1163,14 +1222,14 @@ __global__ __launch_bounds__(256) void k_select_W_rows(const float* __restrict__
 
 hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const double* part,
                            const int* fpart, int tiles_n, int64_t N, int64_t R, uint8_t* mask,
-                           double* dsel, double* margin, hipStream_t s) {
+                           double* dsel, double* margin, hipStream_t s, const Damp& dp) {
   prof_begin("select_W", s);
   if (tiles_n <= SEL_FEW)
     hipLaunchKernelGGL(k_select_W_rows, dim3((unsigned)cdiv(N, SEL_ROWS)), dim3(256), 0, s, Xmu, Xn, Wout, part,
-                       fpart, tiles_n, N, R, mask, dsel, margin);
+                       fpart, tiles_n, N, R, mask, dsel, margin, dp);
   else
     hipLaunchKernelGGL(k_select_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, Xmu, Xn, Wout, part, fpart,
-                       tiles_n, N, R, mask, dsel, margin);
+                       tiles_n, N, R, mask, dsel, margin, dp);
   prof_end("select_W", s);
   return hipGetLastError();
 }

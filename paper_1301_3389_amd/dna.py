@@ -34,7 +34,10 @@ STATUS = {0: "DNA_OK", 1: "DNA_EINVAL", 2: "DNA_EWORKSPACE", 3: "DNA_EDOMAIN",
 class Opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("alpha", ctypes.c_float),
                 ("gemm", ctypes.c_int), ("checked", ctypes.c_int),
-                ("rho", ctypes.c_float), ("lam", ctypes.c_float)]   # dna_opts.rho, dna_opts.lambda
+                ("rho", ctypes.c_float), ("lam", ctypes.c_float),   # dna_opts.rho, dna_opts.lambda
+                ("select", ctypes.c_int)]
+
+SELECT_RULES = {"both": 0, "newton_first": 1}
 
 
 class KernelStat(ctypes.Structure):
@@ -112,9 +115,10 @@ def _check(status):
         raise DNAError(status, _lib_last_error().decode())
 
 
-def make_opts(eps=0.01, alpha=4.0, gemm="fp32", checked=False, rho=0.0, lam=0.0):
-    """dna_opts: eps, alpha (Sec. 2.3), product type, checked mode, and the
-    eq. (2) weights rho (sum of W) and lam (lambda, sum of H)."""
+def make_opts(eps=0.01, alpha=4.0, gemm="fp32", checked=False, rho=0.0, lam=0.0, select="both"):
+    """dna_opts: eps, alpha (Sec. 2.3), product type, checked mode, the eq. (2)
+    weights rho (sum of W) and lam (lambda, sum of H), and the selection rule
+    ("both": Algorithm 1; "newton_first": the damped rule)."""
     o = Opts()
     _lib_default_opts(ctypes.byref(o))
     o.eps = float(eps)
@@ -123,6 +127,7 @@ def make_opts(eps=0.01, alpha=4.0, gemm="fp32", checked=False, rho=0.0, lam=0.0)
     o.checked = 1 if checked else 0
     o.rho = float(rho)
     o.lam = float(lam)
+    o.select = SELECT_RULES[select] if isinstance(select, str) else int(select)
     return o
 
 
