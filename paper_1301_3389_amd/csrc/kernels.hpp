@@ -113,6 +113,17 @@ hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, const fl
                        int64_t R, int splits, int64_t kchunk, float* pu, float* puc, float* py,
                        hipStream_t s);
 
+// Block layout of the H-orientation candidate kernel (columns per block, row
+// groups), which its adjoint repeats so that every sum over r rounds alike.
+struct CandLayout {
+  int cols, rg;
+};
+inline CandLayout cand_layout(int64_t T, int64_t R) {
+  if (R <= 128) return {32, 32};
+  if (cdiv(T, 32) >= 512) return {32, 8};
+  return {8, 32};
+}
+
 // Adds the `splits` partials of u, u_c, y (each splits x n floats) into split 0,
 // in split order.
 hipError_t launch_fold_splits(float* pu, float* puc, float* py, int splits, int64_t n, hipStream_t s);

@@ -169,6 +169,12 @@ constexpr int OUT_PITCH = 128 + 8;   // LDS pitch of the 128 x 128 output stagin
 constexpr int RATIO_OUT_BYTES = 3 * 128 * OUT_PITCH * 2;
 
 constexpr int RATIO_STAGES = 4, GH_STAGES = 3, COST_STAGES = 4;
+// The H-orientation cost pass (column partials, a light epilogue) fits two waves
+// per SIMD with a 2-stage ring: one workgroup's epilogue then overlaps another's
+// products.  The W orientation keeps 192 float64 row partials and one wave.
+template <int SIDE> struct CostCfg;
+template <> struct CostCfg<0> { static constexpr int STAGES = 2, WAVES_PER_EU = 2; };
+template <> struct CostCfg<1> { static constexpr int STAGES = COST_STAGES, WAVES_PER_EU = 1; };
 
 template <typename TE, int SPLIT>
 using ZEng = Gemm16<G128, TE, typename ZProds<SPLIT>::P, RATIO_STAGES>;
@@ -455,11 +461,12 @@ typedef Prods<1, 2, 2, 2, 0, 0, 0, 0, 1, 1> CH_P;
 typedef Prods<2, 1, 2, 2, 0, 0, 0, 1, 0, 1> CW_P;
 
 template <typename TE, int SIDE>
-__global__ __launch_bounds__(256) void k_cost16(const float* V, Ops16 ops, int64_t N, int64_t T,
-                                                int64_t Rk, double* part, int* fpart) {
+__global__ __launch_bounds__(256, CostCfg<SIDE>::WAVES_PER_EU) void k_cost16(const float* V, Ops16 ops, int64_t N,
+                                                                            int64_t T, int64_t Rk, double* part,
+                                                                            int* fpart) {
   using G = G128;
   typedef typename std::conditional<SIDE == 0, CH_P, CW_P>::type PR;
-  typedef Gemm16<G, TE, PR, COST_STAGES> E;
+  typedef Gemm16<G, TE, PR, CostCfg<SIDE>::STAGES> E;
   extern __shared__ __align__(16) char lds_dyn[];
   __shared__ int fl_s[128];
   const Tile3 tl = xcd_tile();
@@ -710,12 +717,13 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
   }
   prof_end(side == 0 ? "conv16c_H" : "conv16c_W", s);
   const dim3 grid((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128));
-  const size_t lb = (size_t)Gemm16<G128, TE, CH_P, COST_STAGES>::LDS_BYTES;
   prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
   if (side == 0) {
+    const size_t lb = (size_t)Gemm16<G128, TE, CH_P, CostCfg<0>::STAGES>::LDS_BYTES;
     lds_attr(k_cost16<TE, 0>, lb);
     hipLaunchKernelGGL((k_cost16<TE, 0>), grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
   } else {
+    const size_t lb = (size_t)Gemm16<G128, TE, CW_P, CostCfg<1>::STAGES>::LDS_BYTES;
     lds_attr(k_cost16<TE, 1>, lb);
     hipLaunchKernelGGL((k_cost16<TE, 1>), grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
   }

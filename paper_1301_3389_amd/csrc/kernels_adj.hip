@@ -77,12 +77,12 @@ __device__ __forceinline__ void gain_bwd(float u, float uc, float c, float& g, f
   }
 }
 
-// Per-column adjoint of one H-update.  Block: BW_COLS columns x BW_RG row groups
-// (the forward candidate kernel's layout, so every sum rounds identically).
+// Per-column adjoint of one H-update.  Block: COLS columns x RG row groups, the
+// forward candidate kernel's layout for the same T and R (cand_layout), so
+// every sum over r rounds identically.
 // Newton columns take three passes over r: D = sum c p (-> kappa), then the
 // clamp-aware sum of G p (-> beta), then the per-entry adjoints.  An entry held
 // at the value floor in the forward pass is a constant and carries no gradient.
-constexpr int BW_COLS = 32, BW_RG = 256 / BW_COLS;
 
 struct Sums {
   float u, uc, y;
@@ -99,7 +99,8 @@ __device__ __forceinline__ Sums split_sums(const float* pu, const float* puc, co
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_cand_bwd_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
+template <int BW_COLS, int BW_RG>
+__global__ __launch_bounds__(BW_COLS * BW_RG) void k_cand_bwd_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
                                                     const float* c, const double* vpart, int tiles_m, int64_t T,
                                                     int64_t R, float eps, float alpha, const uint8_t* sel,
                                                     const float* G, float* Ubar, float* Ybar, float* Hd,
@@ -203,8 +204,16 @@ hipError_t launch_cand_bwd_H(const float* H, const float* pu, const float* puc, 
                              const uint8_t* sel, const float* G, float* Ubar, float* Ybar, float* Hd,
                              float* Cbar, float* sbar, hipStream_t s) {
   prof_begin("cand_bwd_H", s);
-  hipLaunchKernelGGL(k_cand_bwd_H, dim3((unsigned)cdiv(T, BW_COLS)), dim3(256), 0, s, H, pu, puc, py, splits, c, vpart,
-                     tiles_m, T, R, eps, alpha, sel, G, Ubar, Ybar, Hd, Cbar, sbar);
+  const CandLayout lay = cand_layout(T, R);
+  if (lay.cols == 32 && lay.rg == 32)
+    hipLaunchKernelGGL((k_cand_bwd_H<32, 32>), dim3((unsigned)cdiv(T, 32)), dim3(1024), 0, s, H, pu, puc, py, splits,
+                       c, vpart, tiles_m, T, R, eps, alpha, sel, G, Ubar, Ybar, Hd, Cbar, sbar);
+  else if (lay.cols == 32)
+    hipLaunchKernelGGL((k_cand_bwd_H<32, 8>), dim3((unsigned)cdiv(T, 32)), dim3(256), 0, s, H, pu, puc, py, splits,
+                       c, vpart, tiles_m, T, R, eps, alpha, sel, G, Ubar, Ybar, Hd, Cbar, sbar);
+  else
+    hipLaunchKernelGGL((k_cand_bwd_H<8, 32>), dim3((unsigned)cdiv(T, 8)), dim3(256), 0, s, H, pu, puc, py, splits,
+                       c, vpart, tiles_m, T, R, eps, alpha, sel, G, Ubar, Ybar, Hd, Cbar, sbar);
   prof_end("cand_bwd_H", s);
   return hipGetLastError();
 }

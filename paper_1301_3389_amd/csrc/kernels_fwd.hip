@@ -561,17 +561,17 @@ __device__ __forceinline__ Cand candidate(float x, float u, float uc, float y, f
 // general form for any R.
 constexpr int CAND_COLS = 32, CAND_RG = 256 / CAND_COLS;
 
-template <int RPT, int RG>
-__global__ __launch_bounds__(CAND_COLS * RG) void k_cand_H(
+template <int RPT, int RG, int COLS = CAND_COLS>
+__global__ __launch_bounds__(COLS * RG) void k_cand_H(
     const float* __restrict__ H, const float* __restrict__ pu, const float* __restrict__ puc,
     const float* __restrict__ py, int splits, const float* __restrict__ c, const double* __restrict__ vpart,
     int tiles_m, int64_t T, int64_t R, float eps, float alpha, float reg, float* __restrict__ Xmu,
     float* __restrict__ Xn,
     float* __restrict__ Aout, float* __restrict__ Bout) {
-  __shared__ double red[RG][CAND_COLS];
-  __shared__ double fac[CAND_COLS];
-  const int tid = threadIdx.x, cl = tid % CAND_COLS, rg = tid / CAND_COLS;
-  const int64_t t = (int64_t)blockIdx.x * CAND_COLS + cl;
+  __shared__ double red[RG][COLS];
+  __shared__ double fac[COLS];
+  const int tid = threadIdx.x, cl = tid % COLS, rg = tid / COLS;
+  const int64_t t = (int64_t)blockIdx.x * COLS + cl;
   const bool ok = t < T;
   double den = 0.0;
   constexpr int KEEP = RPT > 0 ? RPT : 1;
@@ -687,8 +687,10 @@ hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, cons
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_H", s);
   // for R <= 128, 32 row groups (1024 threads) give every CU 16 waves of
-  // independent loads; larger R takes the general loop with 8 row groups
-  const dim3 grid((unsigned)cdiv(T, CAND_COLS));
+  // independent loads; larger R takes the general loop, with 32 columns x 8 row
+  // groups per block, or 8 x 32 where that would leave fewer than 512 blocks
+  const CandLayout lay = cand_layout(T, R);
+  const dim3 grid((unsigned)cdiv(T, lay.cols));
   constexpr int RG = 32;
   if (R <= 2 * RG)
     hipLaunchKernelGGL((k_cand_H<2, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
@@ -696,9 +698,12 @@ hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, cons
   else if (R <= 4 * RG)
     hipLaunchKernelGGL((k_cand_H<4, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
                        tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
-  else
+  else if (lay.cols == CAND_COLS)
     hipLaunchKernelGGL((k_cand_H<0, CAND_RG>), grid, dim3(CAND_COLS * CAND_RG), 0, s, H, pu, puc, py, splits, c,
                        vpart, tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
+  else
+    hipLaunchKernelGGL((k_cand_H<0, 32, 8>), grid, dim3(8 * 32), 0, s, H, pu, puc, py, splits, c, vpart, tiles_m, T,
+                       R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
   prof_end("cand_H", s);
   return hipGetLastError();
 }
