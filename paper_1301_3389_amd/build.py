@@ -26,7 +26,7 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 SOURCES = ["api.hip", "kernels_fwd.hip", "kernels_adj.hip", "kernels_16.hip", "kernels_fused.hip",
-           "kernels_sparse.hip"]
+           "kernels_sparse.hip", "kernels_cols.hip"]
 
 
 def _compile(src: str) -> str:

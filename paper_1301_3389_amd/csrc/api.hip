@@ -507,12 +507,17 @@ static int norm_side(const dna_opts* o, int side) {
 // sums for 1).
 static dna_status run_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const dna_opts* o,
                                 double* sump, double* sump2, int* chk, hipStream_t s, double* emit,
-                                SumJob* emitted) {
+                                SumJob* emitted, const SumJob* fresh = nullptr) {
   const int es = norm_side(o, side);
   SumJob cj, gj;
+  // `fresh`: first-level sums of the factor the half-step just wrote (H row
+  // sums after an H step, side 1), left by that step's kernel
+  const bool fh = fresh && side == 1, fw = fresh && side == 0;
   if (o->rho > 0.f && o->lambda > 0.f) {          // balanced: the scale kernel takes both factors' sums
-    DNA_HIP(launch_colsum_part(W, N, R, sump, cj, s), "colsum_W");
-    DNA_HIP(launch_rowsum_part(H, T, R, sump2, gj, s), "rowsum_H");
+    if (fw) cj = *fresh;
+    else DNA_HIP(launch_colsum_part(W, N, R, sump, cj, s), "colsum_W");
+    if (fh) gj = *fresh;
+    else DNA_HIP(launch_rowsum_part(H, T, R, sump2, gj, s), "rowsum_H");
     SumJob& mine = es == 0 ? cj : gj;
     mine.check = chk;
     DNA_HIP(launch_scale(es, W, H, N, T, R, mine, emit, emitted, s, es == 0 ? gj : cj,
@@ -520,7 +525,9 @@ static dna_status run_normalize(int side, float* W, float* H, int64_t N, int64_t
     return DNA_OK;
   }
   SumJob& job = es == 0 ? cj : gj;
-  if (es == 0) DNA_HIP(launch_colsum_part(W, N, R, sump, job, s), "colsum_W");
+  if (es == 0 && fw) job = *fresh;
+  else if (es == 1 && fh) job = *fresh;
+  else if (es == 0) DNA_HIP(launch_colsum_part(W, N, R, sump, job, s), "colsum_W");
   else DNA_HIP(launch_rowsum_part(H, T, R, sump, job, s), "rowsum_H");
   job.check = chk;
   DNA_HIP(launch_scale(es, W, H, N, T, R, job, emit, emitted, s), "scale");
@@ -574,6 +581,29 @@ dna_status dna_normalize(int side, float* W, float* H, int64_t N, int64_t T, int
   return epilogue(c);
 }
 
+// The H half-step as one kernel (R <= 64, float32 products, the selection of
+// Algorithm 1, T >= HCOLS_MIN_T): candidates, costs and choice per block of
+// columns, no split partials.  `fresh` receives the partial row sums of the new
+// H (in the pu buffer, which the next W step overwrites only after the
+// normalisation has read them).
+static bool hcols_path(const dna_opts* o, int64_t T, int64_t R) {
+  return o->gemm == DNA_GEMM_FP32 && R <= FUSED_MAX_R && o->select == DNA_SELECT_BOTH && T >= HCOLS_MIN_T &&
+         T <= HCOLS_MAX_T;
+}
+
+static dna_status run_hstep_cols(const float* V, const float* W, float* H, int64_t N, int64_t T, int64_t R,
+                                 const dna_opts* o, const Common& c, void* ws, const SumJob* pre, uint8_t* mask,
+                                 double* dsel, double* margin, SumJob* fresh) {
+  SumJob job;
+  if (pre) job = *pre;
+  else DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, c.L.sump), job, c.s), "colsum_W");
+  job.reg = o->lambda;
+  const HColsArgs a{V, W, H, N, T, R, job, o->eps, o->alpha, mask, dsel, margin, at<double>(ws, c.L.pu), c.chk};
+  DNA_HIP(launch_hstep_cols(a, c.s), "hstep_cols");
+  if (fresh) *fresh = SumJob{a.emit, (int)hcols_blocks(T), R};
+  return DNA_OK;
+}
+
 dna_status dna_update_H(const float* V, const float* W, float* H, int64_t N, int64_t T, int64_t R,
                         const dna_opts* o, void* ws, size_t ws_bytes, uint8_t* chose_newton, double* d_sel,
                         double* margin, void* stream) {
@@ -582,6 +612,10 @@ dna_status dna_update_H(const float* V, const float* W, float* H, int64_t N, int
   DNA_TRY(check_opts(o));
   DNA_TRY(check_select(o, R));   // before anything is enqueued
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  if (hcols_path(o, T, R)) {
+    DNA_TRY(run_hstep_cols(V, W, H, N, T, R, o, c, ws, nullptr, chose_newton, d_sel, margin, nullptr));
+    return epilogue(c);
+  }
   float* Xmu = at<float>(ws, c.L.xmu);
   float* Xn = at<float>(ws, c.L.xn);
   DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s));
@@ -609,9 +643,10 @@ dna_status dna_update_W(const float* V, float* W, const float* H, int64_t N, int
 // when that factor is W (H), i.e. unless one eq. 2 weight alone is positive
 // and fixes the other factor's scale.
 static dna_status iterate_normalize(int side, float* W, float* H, int64_t N, int64_t T, int64_t R,
-                                    const dna_opts* o, const Common& c, void* ws, SumJob& next, bool& valid) {
+                                    const dna_opts* o, const Common& c, void* ws, SumJob& next, bool& valid,
+                                    const SumJob* fresh = nullptr) {
   DNA_TRY(run_normalize(side, W, H, N, T, R, o, at<double>(ws, c.L.sump), at<double>(ws, c.L.sump2), c.chk, c.s,
-                        at<double>(ws, c.L.sume), &next));
+                        at<double>(ws, c.L.sume), &next, fresh));
   valid = norm_side(o, side) == side;
   return DNA_OK;
 }
@@ -632,11 +667,18 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
   // for the next half-step's ratio pass (Algorithm 1 steps 15, 28)
   const bool keep = o->gemm == DNA_GEMM_FP32 && R > FUSED_MAX_R;
   bool zin = false;                                 // Z of the current state is in the workspace
+  const bool cols = hcols_path(o, T, R);
   for (int it = 0; it < iters; ++it) {
-    DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
-                           have ? &next : nullptr, zin));
-    DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep));
-    DNA_TRY(iterate_normalize(1, W, H, N, T, R, o, c, ws, next, have));  // step 16; next = g
+    if (cols) {
+      SumJob fresh;
+      DNA_TRY(run_hstep_cols(V, W, H, N, T, R, o, c, ws, have ? &next : nullptr, nullptr, nullptr, nullptr, &fresh));
+      DNA_TRY(iterate_normalize(1, W, H, N, T, R, o, c, ws, next, have, &fresh));  // step 16; next = g
+    } else {
+      DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
+                             have ? &next : nullptr, zin));
+      DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep));
+      DNA_TRY(iterate_normalize(1, W, H, N, T, R, o, c, ws, next, have));  // step 16; next = g
+    }
     DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
                            have ? &next : nullptr, keep));
     DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep));
@@ -804,6 +846,17 @@ dna_status dna_candidates(int side, const float* V, const float* W, const float*
   if (side != 0 && side != 1) return fail(DNA_EINVAL, "side must be 0 or 1");
   Common c;
   DNA_TRY(prologue(V, W, H, N, T, R, o, ws, ws_bytes, stream, c));
+  if (side == 0 && hcols_path(o, T, R)) {          // the candidates the one-kernel H step forms
+    SumJob job;
+    DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, c.L.sump), job, c.s), "colsum_W");
+    job.reg = o->lambda;
+    HColsArgs a{V, W, const_cast<float*>(H), N, T, R, job, o->eps, o->alpha, nullptr, nullptr, nullptr,
+                at<double>(ws, c.L.pu), c.chk};
+    a.xmu_out = X_mu;
+    a.xn_out = X_newton;
+    DNA_HIP(launch_hstep_cols(a, c.s), "hstep_cols");
+    return epilogue(c);
+  }
   DNA_TRY(run_candidates(side, V, W, H, N, T, R, o, c.L, ws, X_mu, X_newton, nullptr, nullptr, c.chk, c.s));
   return epilogue(c);
 }

@@ -274,4 +274,66 @@ __device__ __forceinline__ void cost_rows(const float (&vf)[G::FM][G::FN][16],
   });
 }
 
+// ---------------------------------------------------------------------------
+// Candidates (eq. 7, 11, 14, 15, 17) of one coordinate.
+// ---------------------------------------------------------------------------
+struct Cand {
+  float mu, newton, A, B;
+};
+
+// MU gain g = u/c and A = g - 1 (eq. 7) from the two forms of the gradient sum,
+// c = (F^t 1)_r + reg (reg: the eq. 2 weight, lambda or rho): where g < 1/2 the
+// plain sum u = (F^t q)_r carries g to float32 relative accuracy; elsewhere the
+// centred sum u_c = (F^t (q - 1))_r = u - (c - reg) carries A = (u_c - reg)/c to
+// float32 accuracy near its zero (near-stationary coordinates, where the Newton
+// step divides by b).
+__device__ __forceinline__ void gain(float u, float uc, float c, float reg, float& g, float& A) {
+  const float gp = u / c;
+  if (gp < 0.5f) {
+    g = gp;
+    A = gp - 1.f;
+  } else {
+    A = (uc - reg) / c;
+    g = 1.f + A;
+  }
+}
+
+// One coordinate: numerators u, u_c, y = ((F*F)^t q-bar)_r, scale c_r (which
+// includes reg).
+__device__ __forceinline__ Cand candidate(float x, float u, float uc, float y, float c, float eps, float alpha,
+                                          float reg) {
+  Cand o;
+  float g;
+  gain(u, uc, c, reg, g, o.A);      // eq. (7)
+  o.B = y / c;                      // eq. (14)
+  o.mu = fmaxf(x * g, VALUE_FLOOR); // eq. (11), kept a positive normal float
+  if (o.A < 0.f) {                  // eq. (15), gain floored at eps
+    const float xb = x * o.B;
+    o.newton = x * fmaxf(xb / (xb - o.A), eps);
+  } else {                          // eq. (17), step capped at alpha x
+    const float step = (o.B > 0.f) ? o.A / o.B : (o.A > 0.f ? INFINITY : 0.f);
+    o.newton = x + fminf(step, alpha * x);
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// The choice of step 15 (28) from a column's (row's) cost sums: q0 = d_DNA,
+// q1 = d_MU - d_DNA, q2 = the terms where only z_MU is positive, fl the flags.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool decide(double q0, double q1, double q2, int fl, double& dsel, double& margin) {
+  const double dN = (fl & 1) ? INFINITY : q0;
+  const double dM = (fl & 2) ? INFINITY : q0 + q1 + q2;
+  bool newton;
+  if (fl == 0) {
+    newton = q1 > 0.0;        // d_DNA < d_MU, decided on the directly computed difference
+    margin = q1;
+  } else {
+    newton = dN < dM;
+    margin = dM - dN;
+  }
+  dsel = newton ? dN : dM;
+  return newton;
+}
+
 }  // namespace dna

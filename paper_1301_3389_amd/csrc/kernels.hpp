@@ -223,6 +223,32 @@ hipError_t launch_costf(int side, const float* V, const float* F, const float* X
                         int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s,
                         bool newton_only = false);
 
+// The whole H half-step (steps 2-15) for R <= 64 in one kernel, a workgroup per
+// block of HCOLS_TB columns running over all N rows (kernels_cols.hip): H is
+// overwritten with the chosen columns; emit[block][r] (cdiv(T, HCOLS_TB) x R
+// doubles) receives the partial row sums of the new H; mask / dsel / margin as
+// launch_select_H (nullptr: not written).  cj: first-level parts of W^t 1,
+// cj.reg = lambda.  With xmu_out (and xn_out) set, the kernel stops after the
+// candidates and writes them there (R x T each) instead: H, emit and the
+// selection outputs are left alone.  Used where T gives every compute unit
+// column blocks of its own (T >= HCOLS_MIN_T).
+constexpr int64_t HCOLS_TB = 16;
+constexpr int64_t HCOLS_MIN_T = 4096;
+constexpr int64_t HCOLS_MAX_T = int64_t(1) << 23;   // 32-bit byte offsets within a 64-row sub-tile
+struct HColsArgs {
+  const float* V; const float* W; float* H;
+  int64_t N, T, R;
+  SumJob cj;
+  float eps, alpha;
+  uint8_t* mask; double* dsel; double* margin;
+  double* emit;
+  int* check;
+  float* xmu_out = nullptr;
+  float* xn_out = nullptr;
+};
+inline int64_t hcols_blocks(int64_t T) { return cdiv(T, HCOLS_TB); }
+hipError_t launch_hstep_cols(const HColsArgs& a, hipStream_t s);
+
 hipError_t launch_kl_final(const double* cpart, int ntiles, double* out, hipStream_t s);
 
 // Checked mode: negative or non-finite entries in a buffer.

@@ -514,46 +514,6 @@ hipError_t launch_gh_W(const float* Q, const float* Qb, const float* H, const fl
 // ---------------------------------------------------------------------------
 // Candidates.
 // ---------------------------------------------------------------------------
-struct Cand {
-  float mu, newton, A, B;
-};
-
-// MU gain g = u/c and A = g - 1 (eq. 7) from the two forms of the gradient sum,
-// c = (F^t 1)_r + reg (reg: the eq. 2 weight, lambda or rho): where g < 1/2 the
-// plain sum u = (F^t q)_r carries g to float32 relative accuracy; elsewhere the
-// centred sum u_c = (F^t (q - 1))_r = u - (c - reg) carries A = (u_c - reg)/c to
-// float32 accuracy near its zero (near-stationary coordinates, where the Newton
-// step divides by b).
-__device__ __forceinline__ void gain(float u, float uc, float c, float reg, float& g, float& A) {
-  const float gp = u / c;
-  if (gp < 0.5f) {
-    g = gp;
-    A = gp - 1.f;
-  } else {
-    A = (uc - reg) / c;
-    g = 1.f + A;
-  }
-}
-
-// One coordinate: numerators u, u_c, y = ((F*F)^t q-bar)_r, scale c_r (which
-// includes reg).
-__device__ __forceinline__ Cand candidate(float x, float u, float uc, float y, float c, float eps, float alpha,
-                                          float reg) {
-  Cand o;
-  float g;
-  gain(u, uc, c, reg, g, o.A);      // eq. (7)
-  o.B = y / c;                      // eq. (14)
-  o.mu = fmaxf(x * g, VALUE_FLOOR); // eq. (11), kept a positive normal float
-  if (o.A < 0.f) {                  // eq. (15), gain floored at eps
-    const float xb = x * o.B;
-    o.newton = x * fmaxf(xb / (xb - o.A), eps);
-  } else {                          // eq. (17), step capped at alpha x
-    const float step = (o.B > 0.f) ? o.A / o.B : (o.A > 0.f ? INFINITY : 0.f);
-    o.newton = x + fminf(step, alpha * x);
-  }
-  return o;
-}
-
 // CAND_COLS columns per block, RG row groups; renormalisation eq. (10) per
 // column through a fixed-order LDS reduction.  With RPT > 0 (R <= RPT * RG)
 // each thread keeps its RPT Newton values in registers between the two passes
@@ -1010,20 +970,6 @@ __device__ __forceinline__ void damp_sums(const Damp& dp, int64_t L, int64_t idx
   for (int m = 0; m < dp.vtiles; ++m) sv += dp.vpart[(int64_t)m * L + idx];
 }
 
-__device__ __forceinline__ bool decide(double q0, double q1, double q2, int fl, double& dsel, double& margin) {
-  const double dN = (fl & 1) ? INFINITY : q0;
-  const double dM = (fl & 2) ? INFINITY : q0 + q1 + q2;
-  bool newton;
-  if (fl == 0) {
-    newton = q1 > 0.0;        // d_DNA < d_MU, decided on the directly computed difference
-    margin = q1;
-  } else {
-    newton = dN < dM;
-    margin = dM - dN;
-  }
-  dsel = newton ? dN : dM;
-  return newton;
-}
 
 __global__ __launch_bounds__(256) void k_select_H(const float* __restrict__ Xmu, const float* __restrict__ Xn,
                                                   float* __restrict__ Hout,
@@ -1425,8 +1371,10 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
       const int g = tid >> 6;
       double f = 0.0, f2 = 0.0;
       if (r < R) {
+#pragma unroll 8
         for (int p = g; p < j.nparts; p += 4) f += j.part[(int64_t)p * R + r];
         if (o.part)
+#pragma unroll 8
           for (int p = g; p < o.nparts; p += 4) f2 += o.part[(int64_t)p * R + r];
       }
       red[g][tid & 63] = f;
@@ -1473,6 +1421,7 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
     }
     if (tid < 64) {  // one wave: a lane per part, fixed-order butterfly
       double f = tid < j.nparts ? j.part[(int64_t)tid * R + r] : 0.0;
+#pragma unroll 8
       for (int p = tid + 64; p < j.nparts; p += 64) f += j.part[(int64_t)p * R + r];
       f = wave_sum(f);
       if (o.part) {
