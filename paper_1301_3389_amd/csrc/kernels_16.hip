@@ -166,9 +166,13 @@ template <> struct ZProds<2> { typedef Prods<2, 1, 2, 1, 1, 0, 0, 0, 0, 0> P; };
 template <> struct ZProds<3> { typedef Prods<2, 2, 3, 1, 1, 0, 0, 0, 1, 0, 0, 0, 0> P; }; // both
 
 constexpr int OUT_PITCH = 128 + 8;   // LDS pitch of the 128 x 128 output staging tiles
-constexpr int RATIO_OUT_BYTES = 3 * 128 * OUT_PITCH * 2;
+constexpr int OUT_TILE = 128 * OUT_PITCH;                  // elements of one staging tile
+constexpr int RATIO_OUT_BYTES = 2 * OUT_TILE * 2;          // Q and Q - 1 staged together, Q-bar after
 
-constexpr int RATIO_STAGES = 4, GH_STAGES = 3, COST_STAGES = 4;
+// The Z pass runs two workgroups per CU (a 2-stage ring, 64 KiB of LDS, at most
+// 256 registers per lane): one workgroup's epilogue and V loads overlap the
+// other's products.
+constexpr int RATIO_STAGES = 2, GH_STAGES = 3, COST_STAGES = 4;
 // The H-orientation cost pass (column partials, a light epilogue) fits two waves
 // per SIMD with a 2-stage ring: one workgroup's epilogue then overlaps another's
 // products.  The W orientation keeps 192 float64 row partials and one wave.
@@ -179,8 +183,32 @@ template <> struct CostCfg<1> { static constexpr int STAGES = COST_STAGES, WAVES
 template <typename TE, int SPLIT>
 using ZEng = Gemm16<G128, TE, typename ZProds<SPLIT>::P, RATIO_STAGES>;
 
+// V of this lane's accumulator positions of the tile at (m0, n0), after the
+// products: a buffer descriptor from the tile's first entry to the end of V
+// (rows past N read as zero; columns past T, masked by the callers, read the
+// next row), a per-lane offset and a uniform one per (i, j, v).
+template <class G>
+__device__ __forceinline__ void load_v16(const float* V, int64_t N, int64_t T, int64_t m0, int64_t n0,
+                                         float (&vf)[G::FM][G::FN][16]) {
+  const int tid = threadIdx.x, lane = tid & 63, wm = (tid >> 6) % G::WGM, wn = (tid >> 6) / G::WGM;
+  const float* base = V + m0 * T + n0;
+  const int64_t bytes = (N * T - (m0 * T + n0)) * 4;
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)std::min<int64_t>(bytes, 0x7fffffff), 0x00020000);
+  const int voff = (int)(((lane >> 5) * 4 * T + (lane & 31)) * 4);
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t ru = wm * G::WM + i * 32 + (v >> 2) * 8 + (v & 3), cu = wn * G::WN + j * 32;
+        vf[i][j][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)((ru * T + cu) * 4), 0));
+      }
+}
+
 template <typename TE, int SIDE, bool MAXONLY, int SPLIT>
-__global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
+__global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
   using G = G128;
   typedef typename ZProds<SPLIT>::P PR;
   typedef ZEng<TE, SPLIT> E;
@@ -191,15 +219,6 @@ __global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
   const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
   const int64_t N = a.N, T = a.T;
   if (!MAXONLY) sum_job(a.fin);
-  float vf[G::FM][G::FN][16];
-#pragma unroll
-  for (int j = 0; j < G::FN; ++j) {
-    const int64_t col = std::min<int64_t>(col16<G>(n0, j), T - 1);
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) vf[i][j][v] = a.V[std::min<int64_t>(row16<G>(m0, i, v), N - 1) * T + col];
-  }
   f32x16 acc[G::FM][G::FN][1];
   zero16<G, 1>(acc);
   {
@@ -210,6 +229,8 @@ __global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
     for (int y = 0; y < PR::NB; ++y) B[y] = a.B[y];
     E::run(A, B, m0, n0, 0, a.Rk, lds, acc);
   }
+  float vf[G::FM][G::FN][16];
+  load_v16<G>(a.V, N, T, m0, n0, vf);
   const int lane = threadIdx.x & 63;
   if (MAXONLY) {
     float mx[3][G::FN] = {};
@@ -307,81 +328,93 @@ __global__ __launch_bounds__(256) void k_ratio16(Ratio16Args a) {
       });
     }
   }
-  // The three outputs in one pass through three LDS staging tiles.  In the H
-  // step (transposed tiles, [t][n]) the four consecutive rows a lane holds per
+  // The outputs through LDS staging tiles: Q and Q - 1 in a first round, Q-bar
+  // (recomputed from the same z and v) in a second.  In the H step
+  // (transposed tiles, [t][n]) the four consecutive rows a lane holds per
   // group of four accumulator slots are adjacent: one 8-byte store.
   TE* st = reinterpret_cast<TE*>(lds);
   int bad = 0;
-  __syncthreads();
+  const int64_t ld = SIDE == 0 ? a.Np : a.Tp;
+  const int64_t r0 = SIDE == 0 ? n0 : m0, c0 = SIDE == 0 ? m0 : n0;
 #pragma unroll
-  for (int i = 0; i < G::FM; ++i)
+  for (int round = 0; round < 2; ++round) {
+    const int nout = round == 0 ? 2 : 1;
+    __syncthreads();                              // the staging tiles are free
 #pragma unroll
-    for (int j = 0; j < G::FN; ++j) {
-      const int64_t col = col16<G>(n0, j);
-      const int cl = (int)(col - n0);
-      const float s0 = (SIDE == 0 && a.qs[0] && col < T) ? a.qs[0][col] : 1.f;
-      const float s1 = (SIDE == 0 && a.qs[1] && col < T) ? a.qs[1][col] : 1.f;
-      const float s2 = (SIDE == 0 && a.qs[2] && col < T) ? a.qs[2][col] : 1.f;
+    for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        TE out[3][4];
+      for (int j = 0; j < G::FN; ++j) {
+        const int64_t col = col16<G>(n0, j);
+        const int cl = (int)(col - n0);
+        float sc[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int v = 4 * g + u;
-          const int64_t row = row16<G>(m0, i, v);
-          float q = 0.f, qc = 0.f, qb = 0.f;
-          if (row < N && col < T) {
-            const float x = vf[i][j][v], z = acc[i][j][0][v];
-            const bool pos = x > 0.f;
-            const float iz = __builtin_amdgcn_rcpf(z);
-            q = pos ? x * iz : 0.f;
-            qc = pos ? (x - z) * iz : -1.f;
-            qb = pos ? q * iz : 0.f;
-            bad |= (pos && !(z > 0.f)) ? 1 : 0;
-            if (SIDE == 0) {
-              q *= s0; qc *= s1; qb *= s2;
-            } else {
-              if (a.qs[0]) q *= a.qs[0][row];
-              if (a.qs[1]) qc *= a.qs[1][row];
-              if (a.qs[2]) qb *= a.qs[2][row];
-            }
-          }
-          out[0][u] = (TE)q;
-          out[1][u] = (TE)qc;
-          out[2][u] = (TE)qb;
+        for (int o = 0; o < 2; ++o) {
+          const int k = round == 0 ? o : 2;
+          sc[o] = (SIDE == 0 && a.qs[k] && col < T) ? a.qs[k][col] : 1.f;
         }
-        const int rl0 = (int)(row16<G>(m0, i, 4 * g) - m0);    // rows rl0 .. rl0 + 3
 #pragma unroll
-        for (int o = 0; o < 3; ++o) {
-          TE* t = st + o * 128 * OUT_PITCH;
-          if (SIDE == 0) {
-            typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-            u32x2 w;
-            w[0] = (unsigned)__builtin_bit_cast(uint16_t, out[o][0]) |
-                   ((unsigned)__builtin_bit_cast(uint16_t, out[o][1]) << 16);
-            w[1] = (unsigned)__builtin_bit_cast(uint16_t, out[o][2]) |
-                   ((unsigned)__builtin_bit_cast(uint16_t, out[o][3]) << 16);
-            *reinterpret_cast<u32x2*>(t + cl * OUT_PITCH + rl0) = w;
-          } else {
+        for (int gq = 0; gq < 4; ++gq) {
+          TE out[2][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) t[(rl0 + u) * OUT_PITCH + cl] = out[o][u];
+          for (int u = 0; u < 4; ++u) {
+            const int v = 4 * gq + u;
+            const int64_t row = row16<G>(m0, i, v);
+            float o0 = 0.f, o1 = 0.f;
+            if (row < N && col < T) {
+              const float x = vf[i][j][v], z = acc[i][j][0][v];
+              const bool pos = x > 0.f;
+              const float iz = __builtin_amdgcn_rcpf(z);
+              const float q = pos ? x * iz : 0.f;
+              if (round == 0) {
+                o0 = q;
+                o1 = pos ? (x - z) * iz : -1.f;
+                bad |= (pos && !(z > 0.f)) ? 1 : 0;
+              } else {
+                o0 = pos ? q * iz : 0.f;
+              }
+#pragma unroll
+              for (int o = 0; o < 2; ++o) {
+                float& y = o == 0 ? o0 : o1;
+                const int k = round == 0 ? o : 2;
+                if (SIDE == 0) y *= sc[o];
+                else if (a.qs[k]) y *= a.qs[k][row];
+              }
+            }
+            out[0][u] = (TE)o0;
+            out[1][u] = (TE)o1;
+          }
+          const int rl0 = (int)(row16<G>(m0, i, 4 * gq) - m0);    // rows rl0 .. rl0 + 3
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            if (o >= nout) continue;
+            TE* t = st + o * OUT_TILE;
+            if (SIDE == 0) {
+              typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+              u32x2 w;
+              w[0] = (unsigned)__builtin_bit_cast(uint16_t, out[o][0]) |
+                     ((unsigned)__builtin_bit_cast(uint16_t, out[o][1]) << 16);
+              w[1] = (unsigned)__builtin_bit_cast(uint16_t, out[o][2]) |
+                     ((unsigned)__builtin_bit_cast(uint16_t, out[o][3]) << 16);
+              *reinterpret_cast<u32x2*>(t + cl * OUT_PITCH + rl0) = w;
+            } else {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) t[(rl0 + u) * OUT_PITCH + cl] = out[o][u];
+            }
           }
         }
       }
-    }
-  __syncthreads();
-  // copy out: three tiles of 128 rows of 128 elements, 16-byte chunks
-  {
-    const int64_t ld = SIDE == 0 ? a.Np : a.Tp;
-    const int64_t r0 = SIDE == 0 ? n0 : m0, c0 = SIDE == 0 ? m0 : n0;
+    __syncthreads();
+    // copy out: nout tiles of 128 rows of 128 elements, 16-byte chunks
     const uint16_t* src = reinterpret_cast<const uint16_t*>(st);
 #pragma unroll
-    for (int k = 0; k < 24; ++k) {
+    for (int k = 0; k < 16; ++k) {
       const int f = threadIdx.x + k * 256;
       const int o = f / 2048, rr = (f % 2048) / 16, ch = (f % 16) * 8;
-      uint16_t* dst = reinterpret_cast<uint16_t*>(a.q3) + (int64_t)o * a.Np * a.Tp;
+      if (o >= nout) continue;
+      const int ko = round == 0 ? o : 2;
+      uint16_t* dst = reinterpret_cast<uint16_t*>(a.q3) + (int64_t)ko * a.Np * a.Tp;
       *reinterpret_cast<u32x4*>(dst + (r0 + rr) * ld + c0 + ch) =
-          *reinterpret_cast<const u32x4*>(src + o * 128 * OUT_PITCH + rr * OUT_PITCH + ch);
+          *reinterpret_cast<const u32x4*>(src + o * OUT_TILE + rr * OUT_PITCH + ch);
     }
   }
   if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
@@ -735,6 +768,8 @@ hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W,
                              int64_t T, int64_t R, const Scratch16& S, int splits, int64_t kchunk, float* pu,
                              float* puc, float* py, double* vpart, int* check, const SumJob& fin,
                              hipStream_t s) {
+  // the Z pass addresses V with 32-bit byte offsets of up to 128 rows
+  if (T >= (int64_t(1) << 22)) return hipErrorInvalidValue;
   if (gemm == 1)
     return ratio_gh16<__bf16>(side, V, W, H, N, T, R, S, false, splits, kchunk, pu, puc, py, vpart, check, fin, s);
   return ratio_gh16<_Float16>(side, V, W, H, N, T, R, S, true, splits, kchunk, pu, puc, py, vpart, check, fin, s);
