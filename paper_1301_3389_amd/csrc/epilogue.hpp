@@ -253,25 +253,52 @@ __device__ __forceinline__ void cost_rows_acc(const float (&vf)[G::FM][G::FN][16
     }
 }
 
+// The partials of one row block i at a time (the sums, their order and the
+// LDS layout of reduce_rows, with a third of the float64 registers live).
 template <class G, int NC>
 __device__ __forceinline__ void cost_rows(const float (&vf)[G::FM][G::FN][16],
                                           const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
                                           int64_t N, int64_t T, double* red, int* fl_s, double* part, int* fpart,
                                           int64_t base, int64_t stride) {
-  double rp[3][G::FM][16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % G::WGM, wn = wave / G::WGM;
 #pragma unroll
-  for (int i = 0; i < G::FM; ++i)
+  for (int i = 0; i < G::FM; ++i) {
+    double rp[3][16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) rp[0][i][v] = rp[1][i][v] = rp[2][i][v] = 0.0;
-  cost_rows_acc<G>(vf, acc, m0, n0, N, T, rp, fl_s);
-  reduce_rows<G, 3>(rp, red, [&](int r, const double (&s)[3]) {
+    for (int v = 0; v < 16; ++v) {
+      rp[0][v] = rp[1][v] = rp[2][v] = 0.0;
+      const int64_t row = epi_row<G>(m0, i, v);
+      int fl = 0;
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+        const float x = (row < N && epi_col<G>(n0, j) < T) ? vf[i][j][v] : 0.f;
+        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], rp[0][v], rp[1][v], rp[2][v]);
+      }
+      if (fl) atomicOr(&fl_s[row - m0], fl);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double y = halfwave_slot_sum(rp[q], lane);
+      if ((lane & 1) == 0) red[(q * G::WGN + wn) * G::BM + wm * G::WM + i * 32 + slot_row(lane)] = y;
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < G::BM; r += G::NT) {
+    double s[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      s[q] = 0.0;
+      for (int w = 0; w < G::WGN; ++w) s[q] += red[(q * G::WGN + w) * G::BM + r];
+    }
     if (m0 + r < N) {
       part[base + m0 + r] = s[0] * LN2;
       part[stride + base + m0 + r] = s[1] * LN2;
       part[2 * stride + base + m0 + r] = s[2] * LN2;
       fpart[base + m0 + r] = fl_s[r];
     }
-  });
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------

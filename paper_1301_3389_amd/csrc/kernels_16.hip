@@ -33,6 +33,7 @@
 namespace dna {
 
 using G128 = G16<128, 128>;
+using GGH = G128;   // tiles of the gradient products
 
 // ---------------------------------------------------------------------------
 // Workspace.
@@ -175,7 +176,8 @@ constexpr int RATIO_OUT_BYTES = 2 * OUT_TILE * 2;          // Q and Q - 1 staged
 constexpr int RATIO_STAGES = 2, GH_STAGES = 3, COST_STAGES = 4;
 // The H-orientation cost pass (column partials, a light epilogue) fits two waves
 // per SIMD with a 2-stage ring: one workgroup's epilogue then overlaps another's
-// products.  The W orientation keeps 192 float64 row partials and one wave.
+// products.  The W orientation (row partials in float64) keeps one wave and a
+// 4-stage ring.  Both read V after the products.
 template <int SIDE> struct CostCfg;
 template <> struct CostCfg<0> { static constexpr int STAGES = 2, WAVES_PER_EU = 2; };
 template <> struct CostCfg<1> { static constexpr int STAGES = COST_STAGES, WAVES_PER_EU = 1; };
@@ -446,7 +448,7 @@ template <typename TE, int SIDE>
 __global__ __launch_bounds__(256) void k_gh16(Ops16 ops, int64_t M, int64_t Ncol,
                                               int64_t K32, int64_t kchunk, float* pu, float* puc, float* py,
                                               Fold f) {
-  using G = G128;
+  using G = GGH;
   typedef typename std::conditional<SIDE == 0, GHH_P, GHW_P>::type PR;
   typedef Gemm16<G, TE, PR, GH_STAGES> E;
   extern __shared__ __align__(16) char lds_dyn[];
@@ -506,15 +508,6 @@ __global__ __launch_bounds__(256, CostCfg<SIDE>::WAVES_PER_EU) void k_cost16(con
   const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
   const int tid = threadIdx.x;
   if (tid < 128) fl_s[tid] = 0;
-  float vf[G::FM][G::FN][16];
-#pragma unroll
-  for (int j = 0; j < G::FN; ++j) {
-    const int64_t col = std::min<int64_t>(col16<G>(n0, j), T - 1);
-#pragma unroll
-    for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) vf[i][j][v] = V[std::min<int64_t>(row16<G>(m0, i, v), N - 1) * T + col];
-  }
   f32x16 acc[G::FM][G::FN][2];
   zero16<G, 2>(acc);
   {
@@ -525,6 +518,8 @@ __global__ __launch_bounds__(256, CostCfg<SIDE>::WAVES_PER_EU) void k_cost16(con
     for (int y = 0; y < PR::NB; ++y) B[y] = ops.m[PR::NA + y];
     E::run(A, B, m0, n0, 0, Rk, lds_dyn, acc);
   }
+  float vf[G::FM][G::FN][16];
+  load_v16<G>(V, N, T, m0, n0, vf);
   double* red = reinterpret_cast<double*>(lds_dyn);
   if (SIDE == 0) {
     const int64_t base = tl.y * T, stride = (int64_t)gridDim.y * T;
@@ -700,16 +695,17 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
     ops.m[0] = Mat16{S.g0, d.Np}; ops.m[1] = Mat16{S.g1, d.Np};
     for (int k = 0; k < 3; ++k) ops.m[2 + k] = Mat16{q + k * npt, d.Np};
     M = R; Ncol = T; K32 = cdiv(N, 32) * 32;
-    grid = dim3((unsigned)(d.Rm / 128), (unsigned)(d.Tp / 128), (unsigned)splits);
+    grid = dim3((unsigned)(d.Rm / GGH::BM), (unsigned)(d.Tp / GGH::BN), (unsigned)splits);
   } else {           // rows n carry the Q scales, columns r the H scale
     const float* cc[3] = {irs, irs, irs2};
     for (int k = 0; k < 3; ++k) { f.r[k] = iqs[k]; f.c[k] = cc[k]; }
     for (int k = 0; k < 3; ++k) ops.m[k] = Mat16{q + k * npt, d.Tp};
     ops.m[3] = Mat16{S.g0, d.Tp}; ops.m[4] = Mat16{S.g1, d.Tp};
     M = N; Ncol = R; K32 = cdiv(T, 32) * 32;
-    grid = dim3((unsigned)(d.Rm / 128), (unsigned)(d.Np / 128), (unsigned)splits);
+    grid = dim3((unsigned)(d.Rm / GGH::BN), (unsigned)(d.Np / GGH::BM), (unsigned)splits);
   }
-  const size_t lb = (size_t)Gemm16<G128, TE, GHH_P, GH_STAGES>::LDS_BYTES;
+  const size_t lb = (size_t)std::max(Gemm16<GGH, TE, GHH_P, GH_STAGES>::LDS_BYTES,
+                                     Gemm16<GGH, TE, GHW_P, GH_STAGES>::LDS_BYTES);
   prof_begin(side == 0 ? "gh16_H" : "gh16_W", s);
   if (side == 0) {
     lds_attr(k_gh16<TE, 0>, lb);
@@ -778,6 +774,7 @@ hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W,
 hipError_t launch_cost16(int gemm, int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                          int64_t N, int64_t T, int64_t R, const Scratch16& S, double* part, int* fpart,
                          hipStream_t s) {
+  if (T >= (int64_t(1) << 22)) return hipErrorInvalidValue;   // 32-bit offsets into V, as the Z pass
   if (gemm == 1) return cost16<__bf16>(side, V, F, Xmu, Xn, N, T, R, S, false, part, fpart, s);
   return cost16<_Float16>(side, V, F, Xmu, Xn, N, T, R, S, true, part, fpart, s);
 }
