@@ -53,6 +53,8 @@ def kernel_work(name, N, T, R):
     # fused kernels (R <= 64): Z recompute + gradient products / the two reconstructions
     table["rgh_H"] = table["rgh_W"] = ("flops", 4 * nrt)
     table["costf_H"] = table["costf_W"] = ("flops", 4 * nrt)
+    # the one-kernel H half-step: gradient products and the two reconstructions
+    table["hstep_cols"] = ("flops", 8 * nrt)
     return table.get(name)
 
 

@@ -24,9 +24,19 @@ import bench  # noqa: E402
     ("dna::k_sp_cost_comb<1>(dna::SpV, double const*)", "sp_cost_comb_W"),
     ("dna::k_sp_comb<1, true>(dna::SpV, float const*)", "sp_comb_W"),
     ("dna::k_sp_qz(dna::SpV, float const*)", "sp_qz"),
+    ("void dna::k_hstep_cols<4, false, true>(dna::HColsArgs)", "hstep_cols"),
+    ("dna::k_ratio<8>(dna::RatioArgs)", "ratio_H"),
 ])
 def test_kernel_key(rocprof, key):
     assert bench.kernel_key(rocprof) == key
+
+
+def test_hstep_cols_counts_both_passes():
+    """The one-kernel H step does the gradient products and the two candidate
+    reconstructions of a half-step: 8NRT algorithmic flops per launch."""
+    assert bench.kernel_work("hstep_cols", 1024, 8192, 64) == ("flops", 8.0 * 1024 * 8192 * 64)
+    assert bench.kernel_work("rgh_W", 1024, 8192, 64)[1] + bench.kernel_work("costf_W", 1024, 8192, 64)[1] == \
+        bench.kernel_work("hstep_cols", 1024, 8192, 64)[1]
 
 
 def test_traffic_missing_tag_is_none():
