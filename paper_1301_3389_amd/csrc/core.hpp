@@ -83,13 +83,24 @@ __device__ __forceinline__ f32x4 fetch4(const Opnd& o, int64_t mn, int64_t k, in
   return r;
 }
 
-// Register stage of one MN x BK operand tile (MN = BM or BN).
-template <int MN, int BK, int NT, bool KMAJ>
+// Register stage of one MN x BK operand tile (MN = BM or BN).  A DIFF stage
+// may hold a difference operand (Opnd::p2 set): its unchecked loads keep both
+// terms in registers and subtract them when the stage is stored, so that no
+// load result is consumed before the stage's LDS store.
+template <int MN, int BK, int NT, bool KMAJ, bool DIFF = false>
 struct Stage {
   static constexpr int NV = MN * BK / 4;
   static constexpr int PT = (NV + NT - 1) / NT;
   f32x4 r[PT];
+  f32x4 r2[DIFF ? PT : 1];
 
+  // Element offset of this thread's i-th vector from the tile origin (mn0, k0).
+  __device__ __forceinline__ static int64_t offset(int f, int64_t ld) {
+    if (KMAJ) return (int64_t)(f / (BK / 4)) * ld + (f % (BK / 4)) * 4;
+    return (int64_t)(f / (MN / 4)) * ld + (f % (MN / 4)) * 4;
+  }
+
+  // Bounds-checked loads (any tile, any alignment).
   __device__ __forceinline__ void load(const Opnd& o, int64_t mn0, int64_t k0, int64_t k_end, int tid) {
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
@@ -102,24 +113,71 @@ struct Stage {
         const int kr = f / (MN / 4), mq = (f % (MN / 4)) * 4;
         r[i] = fetch4<false>(o, mn0 + mq, k0 + kr, k_end);
       }
+      if (DIFF) r2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
   }
+
+  // Unchecked 16-byte loads: the caller has established that the whole tile
+  // lies inside the operand and that o.vec holds.
+  __device__ __forceinline__ void load_fast(const Opnd& o, int64_t mn0, int64_t k0, int tid) {
+    const int64_t origin = KMAJ ? mn0 * o.ld + k0 : k0 * o.ld + mn0;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int f = tid + i * NT;
+      if (NV % NT != 0 && f >= NV) break;
+      r[i] = *reinterpret_cast<const f32x4*>(o.p + origin + offset(f, o.ld));
+    }
+    if (DIFF) {
+      if (o.p2) {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+          const int f = tid + i * NT;
+          if (NV % NT != 0 && f >= NV) break;
+          r2[i] = *reinterpret_cast<const f32x4*>(o.p2 + origin + offset(f, o.ld));
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) r2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+
   __device__ __forceinline__ void store(float* lds, int tid) const {
     constexpr int LD = MN + 4;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
       const int f = tid + i * NT;
       if (NV % NT != 0 && f >= NV) break;
+      const f32x4 x = DIFF ? r[i] - r2[i] : r[i];
       if (KMAJ) {
         const int row = f / (BK / 4), kq = (f % (BK / 4)) * 4;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) lds[(kq + j) * LD + row] = r[i][j];
+        for (int j = 0; j < 4; ++j) lds[(kq + j) * LD + row] = x[j];
       } else {
         const int kr = f / (MN / 4), mq = (f % (MN / 4)) * 4;
-        *reinterpret_cast<f32x4*>(lds + kr * LD + mq) = r[i];
+        *reinterpret_cast<f32x4*>(lds + kr * LD + mq) = x;
       }
     }
   }
+};
+
+// Product lists may mark their A (B) operands as possible difference operands
+// with a static member DIFF_A (DIFF_B) = true.
+template <class PR, class = void>
+struct DiffA {
+  static constexpr bool v = false;
+};
+template <class PR>
+struct DiffA<PR, decltype(void(PR::DIFF_A))> {
+  static constexpr bool v = PR::DIFF_A;
+};
+template <class PR, class = void>
+struct DiffB {
+  static constexpr bool v = false;
+};
+template <class PR>
+struct DiffB<PR, decltype(void(PR::DIFF_B))> {
+  static constexpr bool v = PR::DIFF_B;
 };
 
 __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
@@ -152,68 +210,78 @@ struct Tile {
           for (int v = 0; v < 16; ++v) acc[i][j][c][v] = 0.f;
   }
 
+  // One K tile: every fragment of the tile is read from LDS first (all reads in
+  // flight together, one wait), then the MFMA chains run back to back.
   __device__ __forceinline__ void compute(const float* lds) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % G::WGM, wn = wave / G::WGM;
     const float* la = lds;
     const float* lb = lds + NA * G::LDA * G::BK;
+    constexpr int KP = G::BK / 2;
+    float af[KP][G::FM][NA], bf[KP][G::FN][NB];
 #pragma unroll
-    for (int kk = 0; kk < G::BK; kk += 2) {
-      const int kr = kk + (lane >> 5);
-      float af[G::FM][NA], bf[G::FN][NB];
+    for (int kp = 0; kp < KP; ++kp) {
+      const int kr = 2 * kp + (lane >> 5);
 #pragma unroll
       for (int i = 0; i < G::FM; ++i)
 #pragma unroll
         for (int a = 0; a < NA; ++a)
-          af[i][a] = la[a * G::LDA * G::BK + kr * G::LDA + wm * G::WM + i * 32 + (lane & 31)];
+          af[kp][i][a] = la[a * G::LDA * G::BK + kr * G::LDA + wm * G::WM + i * 32 + (lane & 31)];
 #pragma unroll
       for (int j = 0; j < G::FN; ++j)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          bf[j][b] = lb[b * G::LDB * G::BK + kr * G::LDB + wn * G::WN + j * 32 + (lane & 31)];
+          bf[kp][j][b] = lb[b * G::LDB * G::BK + kr * G::LDB + wn * G::WN + j * 32 + (lane & 31)];
+    }
+#pragma unroll
+    for (int kp = 0; kp < KP; ++kp)
 #pragma unroll
       for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < G::FN; ++j) PR::mma(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < G::FN; ++j) PR::mma(af[kp][i], bf[kp][j], acc[i][j]);
+  }
+
+  typedef Stage<G::BM, G::BK, G::NT, AK, DiffA<PR>::v> SA;
+  typedef Stage<G::BN, G::BK, G::NT, BKM, DiffB<PR>::v> SB;
+
+  // Whether the tile's MN ranges lie inside every operand and all of them take
+  // 16-byte loads: then every K tile but a ragged last one loads unchecked.
+  __device__ __forceinline__ static bool interior(const Opnd (&A)[NA], const Opnd (&B)[NB], int64_t m0, int64_t n0) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) ok = ok && A[a].vec && m0 + G::BM <= A[a].mn_end && (DiffA<PR>::v || !A[a].p2);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) ok = ok && B[b].vec && n0 + G::BN <= B[b].mn_end && (DiffB<PR>::v || !B[b].p2);
+    return ok;
+  }
+
+  __device__ __forceinline__ static void load_stage(SA (&sa)[NA], SB (&sb)[NB], const Opnd (&A)[NA],
+                                                    const Opnd (&B)[NB], int64_t m0, int64_t n0, int64_t k,
+                                                    int64_t k_end, bool inner, int tid) {
+    if (inner && k + G::BK <= k_end) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sa[a].load_fast(A[a], m0, k, tid);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) sb[b].load_fast(B[b], n0, k, tid);
+    } else {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sa[a].load(A[a], m0, k, k_end, tid);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) sb[b].load(B[b], n0, k, k_end, tid);
     }
+  }
+
+  __device__ __forceinline__ static void store_stage(const SA (&sa)[NA], const SB (&sb)[NB], float* buf, int tid) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) sa[a].store(buf + a * G::LDA * G::BK, tid);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) sb[b].store(buf + NA * G::LDA * G::BK + b * G::LDB * G::BK, tid);
   }
 
   // Accumulate over k in [k_begin, k_end).  lds must hold LDS_FLOATS floats.
   __device__ __forceinline__ void run(const Opnd (&A)[NA], const Opnd (&B)[NB], int64_t m0, int64_t n0,
                                       int64_t k_begin, int64_t k_end, float* lds) {
-    const int tid = threadIdx.x;
-    const int64_t nk = (k_end - k_begin + G::BK - 1) / G::BK;
-    if (nk <= 0) return;
-    Stage<G::BM, G::BK, G::NT, AK> sa[NA];
-    Stage<G::BN, G::BK, G::NT, BKM> sb[NB];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) sa[a].load(A[a], m0, k_begin, k_end, tid);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) sb[b].load(B[b], n0, k_begin, k_end, tid);
-#pragma unroll
-    for (int a = 0; a < NA; ++a) sa[a].store(lds + a * G::LDA * G::BK, tid);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) sb[b].store(lds + NA * G::LDA * G::BK + b * G::LDB * G::BK, tid);
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-      const bool more = kt + 1 < nk;
-      const int64_t kn = k_begin + (kt + 1) * G::BK;
-      if (more) {
-#pragma unroll
-        for (int a = 0; a < NA; ++a) sa[a].load(A[a], m0, kn, k_end, tid);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) sb[b].load(B[b], n0, kn, k_end, tid);
-      }
-      compute(lds + (kt & 1) * BUF);
-      if (more) {
-        float* nb = lds + ((kt + 1) & 1) * BUF;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) sa[a].store(nb + a * G::LDA * G::BK, tid);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) sb[b].store(nb + NA * G::LDA * G::BK + b * G::LDB * G::BK, tid);
-      }
-      __syncthreads();
-    }
+    run_flush(A, B, m0, n0, k_begin, k_end, lds, 1 << 30, [](int) {});
   }
 
   // run() with a hook: after every `tiles_per_chunk` K-tiles of this range (and
@@ -226,40 +294,23 @@ struct Tile {
     const int tid = threadIdx.x;
     const int64_t nk = (k_end - k_begin + G::BK - 1) / G::BK;
     if (nk <= 0) return;
-    Stage<G::BM, G::BK, G::NT, AK> sa[NA];
-    Stage<G::BN, G::BK, G::NT, BKM> sb[NB];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) sa[a].load(A[a], m0, k_begin, k_end, tid);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) sb[b].load(B[b], n0, k_begin, k_end, tid);
-#pragma unroll
-    for (int a = 0; a < NA; ++a) sa[a].store(lds + a * G::LDA * G::BK, tid);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) sb[b].store(lds + NA * G::LDA * G::BK + b * G::LDB * G::BK, tid);
+    const bool inner = interior(A, B, m0, n0);
+    SA sa[NA];
+    SB sb[NB];
+    load_stage(sa, sb, A, B, m0, n0, k_begin, k_end, inner, tid);
+    store_stage(sa, sb, lds, tid);
     __syncthreads();
     int in_chunk = 0, chunk = 0;
     for (int64_t kt = 0; kt < nk; ++kt) {
       const bool more = kt + 1 < nk;
-      const int64_t kn = k_begin + (kt + 1) * G::BK;
-      if (more) {
-#pragma unroll
-        for (int a = 0; a < NA; ++a) sa[a].load(A[a], m0, kn, k_end, tid);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) sb[b].load(B[b], n0, kn, k_end, tid);
-      }
+      if (more) load_stage(sa, sb, A, B, m0, n0, k_begin + (kt + 1) * G::BK, k_end, inner, tid);
       compute(lds + (kt & 1) * BUF);
       if (++in_chunk == tiles_per_chunk || !more) {
         flush(chunk);
         ++chunk;
         in_chunk = 0;
       }
-      if (more) {
-        float* nb = lds + ((kt + 1) & 1) * BUF;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) sa[a].store(nb + a * G::LDA * G::BK, tid);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) sb[b].store(nb + NA * G::LDA * G::BK + b * G::LDB * G::BK, tid);
-      }
+      if (more) store_stage(sa, sb, lds + ((kt + 1) & 1) * BUF, tid);
       __syncthreads();
     }
   }
@@ -338,15 +389,17 @@ struct ProdGH3_W {  // A0 = Q, A1 = Q-bar, B = H^t (shared)
   }
 };
 
-struct ProdDualB {  // C0 += A B0, C1 += A B1
+struct ProdDualB {  // C0 += A B0, C1 += A B1   (B1 may be a difference operand)
   static constexpr int NA = 1, NB = 2, NC = 2;
+  static constexpr bool DIFF_B = true;
   __device__ __forceinline__ static void mma(const float (&a)[1], const float (&b)[2], f32x16 (&c)[2]) {
     c[0] = mfma32(a[0], b[0], c[0]);
     c[1] = mfma32(a[0], b[1], c[1]);
   }
 };
-struct ProdDualA {  // C0 += A0 B, C1 += A1 B
+struct ProdDualA {  // C0 += A0 B, C1 += A1 B   (A1 may be a difference operand)
   static constexpr int NA = 2, NB = 1, NC = 2;
+  static constexpr bool DIFF_A = true;
   __device__ __forceinline__ static void mma(const float (&a)[2], const float (&b)[1], f32x16 (&c)[2]) {
     c[0] = mfma32(a[0], b[0], c[0]);
     c[1] = mfma32(a[1], b[0], c[1]);
@@ -410,6 +463,50 @@ __device__ __forceinline__ int wave_or(int x) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) x |= __shfl_xor(x, m);
   return x;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap the dispatch order so that every XCD receives one contiguous range of
+// the logical tile order (x fastest): tiles that are neighbours along x -- and
+// share an operand block -- then run on the same XCD at the same time.
+struct Tile3 {
+  int64_t x, y, z;
+};
+__device__ __forceinline__ Tile3 xcd_tile() {
+  const int64_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int64_t total = gx * gy * gz;
+  const int64_t b = (int64_t)blockIdx.x + gx * ((int64_t)blockIdx.y + gy * (int64_t)blockIdx.z);
+  const int64_t q = total / 8, rem = total % 8, x = b % 8, s = b / 8;
+  const int64_t L = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + s;
+  Tile3 t;
+  t.x = L % gx;
+  t.y = (L / gx) % gy;
+  t.z = L / (gx * gy);
+  return t;
+}
+
+// The same XCD ranges over a grouped logical order: the x-y plane of tiles is cut
+// into bands of GY rows (y) and inside a band y runs fastest.  A window of
+// consecutive tiles then covers about as many x as y blocks, so the operand
+// blocks of both sides are each read once by the tiles that share them on an
+// XCD, whichever side is the larger one.  A grid of fewer than two workgroups
+// per CU keeps the dispatch order: its operands stay in the caches anyway, and
+// there the remap measured slower.
+template <int GY>
+__device__ __forceinline__ Tile3 xcd_tile_grouped() {
+  const int64_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int64_t plane = gx * gy, total = plane * gz;
+  if (total < 512) return Tile3{(int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)blockIdx.z};
+  const int64_t b = (int64_t)blockIdx.x + gx * ((int64_t)blockIdx.y + gy * (int64_t)blockIdx.z);
+  const int64_t q = total / 8, rem = total % 8, x = b % 8, s = b / 8;
+  const int64_t L = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + s;
+  const int64_t l = L % plane, band = l / (GY * gx), y0 = band * GY;
+  const int64_t h = gy - y0 < GY ? gy - y0 : GY, o = l - band * GY * gx;
+  Tile3 t;
+  t.y = y0 + o % h;
+  t.x = o / h;
+  t.z = L / plane;
+  return t;
 }
 
 }  // namespace dna

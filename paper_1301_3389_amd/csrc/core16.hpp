@@ -178,25 +178,6 @@ struct Gemm16 {
   }
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Remap the dispatch order so that every XCD receives one contiguous range of
-// the logical tile order (x fastest): tiles that are neighbours along x -- and
-// share an operand block -- then run on the same XCD at the same time.
-struct Tile3 {
-  int64_t x, y, z;
-};
-__device__ __forceinline__ Tile3 xcd_tile() {
-  const int64_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
-  const int64_t total = gx * gy * gz;
-  const int64_t b = (int64_t)blockIdx.x + gx * ((int64_t)blockIdx.y + gy * (int64_t)blockIdx.z);
-  const int64_t q = total / 8, rem = total % 8, x = b % 8, s = b / 8;
-  const int64_t L = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + s;
-  Tile3 t;
-  t.x = L % gx;
-  t.y = (L / gx) % gy;
-  t.z = L / (gx * gy);
-  return t;
-}
 
 template <class G>
 __device__ __forceinline__ int64_t row16(int64_t m0, int i, int v) {

@@ -225,7 +225,8 @@ __global__ __launch_bounds__(GZB::NT) void k_zbar(const float* V, const float* Z
                                                   float* Zbar, float* dV, int accumulate) {
   using TL = Tile<GZB, ProdDualB_SqA, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * GZB::BM, n0 = (int64_t)blockIdx.x * GZB::BN;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * GZB::BM, n0 = tl.x * GZB::BN;
   TL t;
   t.zero();
   {
@@ -303,8 +304,9 @@ __global__ __launch_bounds__(GWB::NT) void k_wbar(Opnd Q, Opnd Zb, Opnd Qb, Opnd
                                                   int64_t T, int64_t R, int64_t kchunk, float* p0, float* p1) {
   using TL = Tile<GWB, ProdWbar, true, true>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * GWB::BM, n0 = (int64_t)blockIdx.x * GWB::BN;
-  const int64_t sp = blockIdx.z;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * GWB::BM, n0 = tl.x * GWB::BN;
+  const int64_t sp = tl.z;
   const int64_t k0 = sp * kchunk, k1 = std::min<int64_t>(T, k0 + kchunk);
   TL t;
   t.zero();

@@ -53,7 +53,10 @@ __global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
   using GZ = GR;
   using TL = Tile<GZ, ProdSingle, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
+  // dispatch order: the Q, Q-bar (and Z) writes of the resident tiles then
+  // cover whole rows; the XCD remaps measured slower here
+  const Tile3 tl{(int64_t)blockIdx.x, (int64_t)blockIdx.y, 0};
+  const int64_t m0 = tl.y * GZ::BM, n0 = tl.x * GZ::BN;
   constexpr bool CARRY = MODE == RM_H_CARRY || MODE == RM_W_CARRY;
   sum_job(a.fin);
   float vf[GZ::FM][GZ::FN][16];
@@ -133,13 +136,13 @@ __global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
   if (COLS) {
     double* dst = COST ? a.cpart : a.vpart;
     reduce_cols<GZ, 1>(cp, red, [&](int c, const double (&s)[1]) {
-      if (n0 + c < T) dst[(int64_t)blockIdx.y * T + n0 + c] = s[0];
+      if (n0 + c < T) dst[tl.y * T + n0 + c] = s[0];
     });
   }
   if (ROWS) {
     double* dst = COST ? a.cpart : a.vpart;
     reduce_rows<GZ, 1>(rp, red, [&](int r, const double (&s)[1]) {
-      if (m0 + r < N) dst[(int64_t)blockIdx.x * N + m0 + r] = s[0];
+      if (m0 + r < N) dst[tl.x * N + m0 + r] = s[0];
     });
   }
   if (MODE == RM_KL) {
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
     if (tid == 0) {
       double s = 0.0;
       for (int k = 0; k < GZ::WAVES; ++k) s += red[k];
-      a.cpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+      a.cpart[tl.y * gridDim.x + tl.x] = s;
     }
   }
 }
@@ -205,8 +208,9 @@ __global__ __launch_bounds__(G::NT) void k_gh_H(Opnd Wt, Opnd Q, Opnd Qb, int64_
                                                  int64_t R, int64_t kchunk, GHOut out) {
   using TL = Tile<G, PR, false, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
-  const int64_t sp = blockIdx.z;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
+  const int64_t sp = tl.z;
   const int64_t k0 = sp * kchunk, k1 = min(N, k0 + kchunk);
   TL t;
   t.zero();
@@ -245,8 +249,9 @@ __global__ __launch_bounds__(G::NT, 2) void k_gh2_H(Opnd Wt, Opnd Q, Opnd Qb, co
                                                   int64_t T, int64_t R, int64_t kchunk, GHOut out) {
   using TL = Tile<G, ProdDualB_SqA, false, false>;     // acc 0: w q, acc 1: w^2 q-bar
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
-  const int64_t sp = blockIdx.z;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
+  const int64_t sp = tl.z;
   const int64_t k0 = sp * kchunk, k1 = min(N, k0 + kchunk);
   const int64_t c0 = k0 / GH_CHUNK;
   TL t;
@@ -315,8 +320,9 @@ __global__ __launch_bounds__(G::NT, 2) void k_gh2_W(Opnd Q, Opnd Qb, Opnd Ht, co
                                                   int64_t T, int64_t R, int64_t kchunk, GHOut out) {
   using TL = Tile<G, ProdDualA_SqB, true, true>;       // acc 0: q h, acc 1: q-bar h^2
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
-  const int64_t sp = blockIdx.z;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
+  const int64_t sp = tl.z;
   const int64_t k0 = sp * kchunk, k1 = min(T, k0 + kchunk);
   const int64_t c0 = k0 / GH_CHUNK;
   TL t;
@@ -452,8 +458,9 @@ __global__ __launch_bounds__(G::NT) void k_gh_W(Opnd Q, Opnd Qb, Opnd Ht, int64_
                                                  int64_t R, int64_t kchunk, GHOut out) {
   using TL = Tile<G, PR, true, true>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
-  const int64_t m0 = (int64_t)blockIdx.y * G::BM, n0 = (int64_t)blockIdx.x * G::BN;
-  const int64_t sp = blockIdx.z;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
+  const int64_t sp = tl.z;
   const int64_t k0 = sp * kchunk, k1 = min(T, k0 + kchunk);
   TL t;
   t.zero();
@@ -880,7 +887,8 @@ __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd
   using TL = Tile<GZ, ProdDualB, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   __shared__ int fl_s[GZ::BN];
-  const int64_t m0 = (int64_t)blockIdx.y * GZ::BM, n0 = (int64_t)blockIdx.x * GZ::BN;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * GZ::BM, n0 = tl.x * GZ::BN;
   const int tid = threadIdx.x;
   for (int c = tid; c < GZ::BN; c += GZ::NT) fl_s[c] = 0;
   float vf[GZ::FM][GZ::FN][16];
@@ -893,7 +901,7 @@ __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd
     t.run(A, B, m0, n0, 0, R, lds);
   }
   if (zd) store_recon<TL, GZ>(t, m0, n0, N, T, zd, dz);
-  const int64_t base = (int64_t)blockIdx.y * T, stride = (int64_t)gridDim.y * T;
+  const int64_t base = tl.y * T, stride = (int64_t)gridDim.y * T;
   cost_cols<GZ>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
@@ -915,7 +923,8 @@ __global__ __launch_bounds__(GCW::NT, 2) void k_cost_W(const float* V, Opnd Wn, 
   using TL = Tile<GCW, ProdDualA, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   __shared__ int fl_s[GCW::BM];
-  const int64_t m0 = (int64_t)blockIdx.y * GCW::BM, n0 = (int64_t)blockIdx.x * GCW::BN;
+  const Tile3 tl = xcd_tile_grouped<8>();
+  const int64_t m0 = tl.y * GCW::BM, n0 = tl.x * GCW::BN;
   const int tid = threadIdx.x;
   for (int r = tid; r < GCW::BM; r += GCW::NT) fl_s[r] = 0;
   float vf[GCW::FM][GCW::FN][16];
@@ -928,7 +937,7 @@ __global__ __launch_bounds__(GCW::NT, 2) void k_cost_W(const float* V, Opnd Wn, 
     t.run(A, B, m0, n0, 0, R, lds);
   }
   if (zd) store_recon<TL, GCW>(t, m0, n0, N, T, zd, dz);
-  const int64_t base = (int64_t)blockIdx.x * N, stride = (int64_t)gridDim.x * N;
+  const int64_t base = tl.x * N, stride = (int64_t)gridDim.x * N;
   cost_rows<GCW>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
