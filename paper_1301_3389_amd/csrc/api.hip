@@ -97,6 +97,33 @@ static Split choose_split(int64_t K, int64_t base_tiles) {
   return s;
 }
 
+// Split-K for a product of base_tiles output tiles of which `slots` workgroups
+// run at once (CUs x workgroups per CU): the split whose rounds of resident
+// workgroups, each worth one chunk (plus a fixed epilogue of about 64
+// contraction indices), take the least time; ties go to fewer splits (less
+// partial traffic).  Chunks are multiples of `align` and at least MIN_KCHUNK
+// long.  A tile count just above a multiple of `slots` would otherwise run a
+// nearly empty last round.
+static Split wave_split(int64_t K, int64_t base_tiles, int64_t slots, int64_t align) {
+  const int64_t base = std::max<int64_t>(1, base_tiles);
+  const int64_t max_sp = std::min<int64_t>(1024, std::max<int64_t>(1, K / MIN_KCHUNK));
+  Split best{1, std::max<int64_t>(1, cdiv(K, align)) * align};
+  if (K <= 0) return best;
+  int64_t best_cost = INT64_MAX;
+  for (int64_t sp = 1; sp <= max_sp; ++sp) {
+    const int64_t kchunk = cdiv(cdiv(K, sp), align) * align;
+    const int64_t real = cdiv(K, kchunk);
+    if (real != sp) continue;
+    const int64_t cost = cdiv(base * real, slots) * (kchunk + 64);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best.splits = (int)real;
+      best.kchunk = kchunk;
+    }
+  }
+  return best;
+}
+
 // Chunks of the fused kernels along the contraction (multiples of 64), aiming
 // at two workgroups per CU.
 static Split fused_split(int64_t K, int64_t base_tiles) {
@@ -142,14 +169,6 @@ struct Layout {
       check, total;
 };
 
-// Split of an fp32 tiled gradient product whose chunks are whole multiples of
-// GH_CHUNK (the chunked gradient sums of launch_gh_H / launch_gh_W).
-static Split chunk_aligned(Split s, int64_t K) {
-  s.kchunk = cdiv(s.kchunk, GH_CHUNK) * GH_CHUNK;
-  s.splits = (int)cdiv(K, s.kchunk);
-  return s;
-}
-
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Q and Q-bar (N x T fp32 each) are carved only where a kernel reads them: Q
@@ -158,10 +177,11 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // 16-bit forms keep their 16-bit Q, Q - 1 and Q-bar in their own scratch.
 static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16, bool adj = false) {
   Layout L;
-  L.sh = chunk_aligned(choose_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM)), N);
-  L.sw = chunk_aligned(choose_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM)), T);
-  L.sh16 = choose_split(N, cdiv(T, 128) * cdiv(R, 128));
-  L.sw16 = choose_split(T, cdiv(R, 128) * cdiv(N, 128));
+  // the fp32 gradient products run two workgroups per CU
+  L.sh = wave_split(N, cdiv(T, GH_BN) * cdiv(R, GH_BM), 2 * 256, GH_CHUNK);
+  L.sw = wave_split(T, cdiv(R, GW_BN) * cdiv(N, GW_BM), 2 * 256, GH_CHUNK);
+  L.sh16 = wave_split(N, cdiv(T, 128) * cdiv(R, 128), GH16_WG_PER_CU * 256, 32);
+  L.sw16 = wave_split(T, cdiv(R, 128) * cdiv(N, 128), GH16_WG_PER_CU * 256, 32);
   L.shf = fused_split(N, cdiv(T, 64));
   L.swf = fused_split(T, cdiv(N, 64));
   L.chf = balanced_split(N, cdiv(T, 64), 3);

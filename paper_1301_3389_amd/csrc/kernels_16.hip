@@ -173,7 +173,9 @@ constexpr int RATIO_OUT_BYTES = 2 * OUT_TILE * 2;          // Q and Q - 1 staged
 // The Z pass runs two workgroups per CU (a 2-stage ring, 64 KiB of LDS, at most
 // 256 registers per lane): one workgroup's epilogue and V loads overlap the
 // other's products.
-constexpr int RATIO_STAGES = 2, GH_STAGES = 3, COST_STAGES = 4;
+// The gradient products likewise: a 2-stage ring (80 KiB) and two workgroups
+// per CU (GH16_WG_PER_CU), all accumulators in registers.
+constexpr int RATIO_STAGES = 2, GH_STAGES = 2, COST_STAGES = 4;
 // The H-orientation cost pass (column partials, a light epilogue) fits two waves
 // per SIMD with a 2-stage ring: one workgroup's epilogue then overlaps another's
 // products.  The W orientation (row partials in float64) keeps one wave and a
@@ -445,7 +447,7 @@ typedef Prods<2, 3, 3, 3, 0, 0, 0, 0, 1, 1, 1, 2, 2> GHH_P;
 typedef Prods<3, 2, 3, 3, 0, 0, 0, 1, 0, 1, 2, 1, 2> GHW_P;
 
 template <typename TE, int SIDE>
-__global__ __launch_bounds__(256) void k_gh16(Ops16 ops, int64_t M, int64_t Ncol,
+__global__ __launch_bounds__(256, GH16_WG_PER_CU) void k_gh16(Ops16 ops, int64_t M, int64_t Ncol,
                                               int64_t K32, int64_t kchunk, float* pu, float* puc, float* py,
                                               Fold f) {
   using G = GGH;

@@ -4,6 +4,9 @@
 
 namespace dna {
 
+// Workgroups of the 16-bit gradient products resident per CU (sizes their split-K).
+constexpr int GH16_WG_PER_CU = 2;
+
 // Padded extents of the 16-bit operands: N and T to the 128-wide tiles, R to
 // the 32-deep K tile where it is contracted and to 128 where it is a tile
 // dimension.
