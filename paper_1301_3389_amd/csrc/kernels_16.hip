@@ -269,18 +269,29 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
         }
       }
       if (SIDE == 1) {
-        // the 32 lanes of a half-wave hold the same rows: reduce across them,
-        // then one atomic per row from lanes 0 and 32
+        // The 32 lanes of a half-wave hold the same 16 rows.  A halving
+        // exchange: at the step over lane bit b each lane keeps half of its
+        // rows and takes the partner's maxima of them, so after four steps lane
+        // c holds row slot c >> 1 (lanes c and c ^ 1 agree after the fifth);
+        // then one atomic per row and quantity from the even lanes.
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k) {
+          float* x = rmx[k];
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            float m = rmx[k][v];
+          for (int h = 8; h >= 1; h >>= 1) {
+            const bool up = (lane & (2 * h)) != 0;     // lane bit log2(2h): keep the upper half
 #pragma unroll
-            for (int sh = 1; sh < 32; sh <<= 1) m = fmaxf(m, __shfl_xor(m, sh));
-            const int64_t row = row16<G>(m0, i, v);
-            if ((lane & 31) == 0 && row < N && m > 0.f) atomicMax(a.qmax[k] + row, __float_as_uint(m));
+            for (int e = 0; e < h; ++e) {
+              const float send = up ? x[e] : x[e + h];
+              const float keep = up ? x[e + h] : x[e];
+              x[e] = fmaxf(keep, __shfl_xor(send, 2 * h));
+            }
           }
+          const float m = fmaxf(x[0], __shfl_xor(x[0], 1));
+          const int v = (lane & 31) >> 1;
+          const int64_t row = row16<G>(m0, i, v);
+          if ((lane & 1) == 0 && row < N && m > 0.f) atomicMax(a.qmax[k] + row, __float_as_uint(m));
+        }
       }
     }
     if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
