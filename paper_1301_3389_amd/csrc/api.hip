@@ -440,11 +440,14 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
                              bool keep = false) {
   float* zd = keep ? at<float>(ws, L.zd) : nullptr;
   float* dz = keep ? at<float>(ws, L.dz) : nullptr;
+  // the choice reads the margin and the flags only; the kept candidate's cost
+  // (the sum_N partials) is formed only when the caller asks for d_sel
+  const bool s0 = dsel != nullptr;
   if (keep) mask = at<uint8_t>(ws, L.selm);
   double* cpart = at<double>(ws, L.cpart);
   int* fpart = at<int>(ws, L.fpart);
   if (o->gemm != DNA_GEMM_FP32) {
-    DNA_HIP(launch_cost16(o->gemm, side, V, F, Xmu, Xn, N, T, R, scratch16(ws, L, N, T, R), cpart, fpart, s),
+    DNA_HIP(launch_cost16(o->gemm, side, V, F, Xmu, Xn, N, T, R, scratch16(ws, L, N, T, R), cpart, fpart, s, s0),
             "cost16");
     if (side == 0)
       DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.ch_m, T, R, mask, dsel, margin, s), "select_H");
@@ -466,18 +469,18 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
   }
   if (side == 0) {
     if (fused)
-      DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.chf.splits, L.chf.kchunk, cpart, fpart, s, damp),
+      DNA_HIP(launch_costf(0, V, F, Xmu, Xn, N, T, R, L.chf.splits, L.chf.kchunk, cpart, fpart, s, damp, s0),
               "costf_H");
     else
-      DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz), "cost_H");
+      DNA_HIP(launch_cost_H(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz, s0), "cost_H");
     DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, fused ? L.chf.splits : L.ch_m, T, R, mask, dsel, margin,
                             s, dp), "select_H");
   } else {
     if (fused)
-      DNA_HIP(launch_costf(1, V, F, Xmu, Xn, N, T, R, L.swf.splits, L.swf.kchunk, cpart, fpart, s, damp),
+      DNA_HIP(launch_costf(1, V, F, Xmu, Xn, N, T, R, L.swf.splits, L.swf.kchunk, cpart, fpart, s, damp, s0),
               "costf_W");
     else
-      DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz), "cost_W");
+      DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz, s0), "cost_W");
     DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, fused ? L.swf.splits : L.cw_n, N, R, mask, dsel, margin,
                             s, dp), "select_W");
   }

@@ -125,15 +125,17 @@ __device__ __forceinline__ double xlog2x_over(float v, float z) {
 // Branch-free for the common case (both reconstructions positive or v = 0): the
 // logarithms take neutral arguments where a term must vanish.  Returns the flag
 // bits of this element.
+// The choice (decide) reads s1 and the flags only; s0 is the kept candidate's
+// cost, so callers that want no cost pass S0 = false and s0 stays untouched.
+template <bool S0 = true>
 __device__ __forceinline__ int cost_acc(float x, float zN, float dz, double& s0, double& s1, double& s2) {
   const float zM = zN + dz;
   const bool pos = x > 0.f;
   const bool okN = zN > 0.f, okM = zM > 0.f;
   const float izN = __builtin_amdgcn_rcpf(zN);
-  const float l0 = log2_hw((pos && okN) ? x * izN : 1.f);
+  if (S0) s0 += (double)(x * log2_hw((pos && okN) ? x * izN : 1.f));
   const bool both = pos && okN && okM;
   const float l1 = log2_ratio(both ? dz * izN : 0.f, both ? zM : 1.f, both ? izN : 1.f);
-  s0 += (double)(x * l0);
   s1 -= (double)(x * l1);
   int fl = 0;
   if (pos && !(okN && okM)) {            // a reconstruction vanished where v > 0
@@ -145,15 +147,15 @@ __device__ __forceinline__ int cost_acc(float x, float zN, float dz, double& s0,
 
 // cost_acc with the first two terms added to float32 accumulators (a caller
 // that flushes them to float64 every few elements).
+template <bool S0 = true>
 __device__ __forceinline__ int cost_acc_f(float x, float zN, float dz, float& a0, float& a1, double& s2) {
   const float zM = zN + dz;
   const bool pos = x > 0.f;
   const bool okN = zN > 0.f, okM = zM > 0.f;
   const float izN = __builtin_amdgcn_rcpf(zN);
-  const float l0 = log2_hw((pos && okN) ? x * izN : 1.f);
+  if (S0) a0 += x * log2_hw((pos && okN) ? x * izN : 1.f);
   const bool both = pos && okN && okM;
   const float l1 = log2_ratio(both ? dz * izN : 0.f, both ? zM : 1.f, both ? izN : 1.f);
-  a0 += x * l0;
   a1 -= x * l1;
   int fl = 0;
   if (pos && !(okN && okM)) {
@@ -195,7 +197,7 @@ __device__ __forceinline__ int64_t epi_col(int64_t n0, int j) {
 }
 
 // Column form (H orientation: one partial per column t of the tile).
-template <class G, int NC>
+template <class G, bool S0, int NC>
 __device__ __forceinline__ void cost_cols_acc(const float (&vf)[G::FM][G::FN][16],
                                               const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
                                               int64_t N, int64_t T, double (&cp)[3][G::FN], int* fl_s) {
@@ -208,13 +210,14 @@ __device__ __forceinline__ void cost_cols_acc(const float (&vf)[G::FM][G::FN][16
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const float x = (epi_row<G>(m0, i, v) < N && col < T) ? vf[i][j][v] : 0.f;
-        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], cp[0][j], cp[1][j], cp[2][j]);
+        fl |= cost_acc<S0>(x, acc[i][j][0][v], acc[i][j][1][v], cp[0][j], cp[1][j], cp[2][j]);
       }
     if (fl) atomicOr(&fl_s[col - n0], fl);
   }
 }
 
-template <class G, int NC>
+// With S0 = false the s0 partials are written as 0 (no cost wanted).
+template <class G, bool S0 = true, int NC>
 __device__ __forceinline__ void cost_cols(const float (&vf)[G::FM][G::FN][16],
                                           const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
                                           int64_t N, int64_t T, double* red, int* fl_s, double* part, int* fpart,
@@ -222,19 +225,36 @@ __device__ __forceinline__ void cost_cols(const float (&vf)[G::FM][G::FN][16],
   double cp[3][G::FN];
 #pragma unroll
   for (int j = 0; j < G::FN; ++j) cp[0][j] = cp[1][j] = cp[2][j] = 0.0;
-  cost_cols_acc<G>(vf, acc, m0, n0, N, T, cp, fl_s);
-  reduce_cols<G, 3>(cp, red, [&](int c, const double (&s)[3]) {
-    if (n0 + c < T) {
-      part[base + n0 + c] = s[0] * LN2;
-      part[stride + base + n0 + c] = s[1] * LN2;
-      part[2 * stride + base + n0 + c] = s[2] * LN2;
-      fpart[base + n0 + c] = fl_s[c];
+  cost_cols_acc<G, S0>(vf, acc, m0, n0, N, T, cp, fl_s);
+  if (S0) {
+    reduce_cols<G, 3>(cp, red, [&](int c, const double (&s)[3]) {
+      if (n0 + c < T) {
+        part[base + n0 + c] = s[0] * LN2;
+        part[stride + base + n0 + c] = s[1] * LN2;
+        part[2 * stride + base + n0 + c] = s[2] * LN2;
+        fpart[base + n0 + c] = fl_s[c];
+      }
+    });
+  } else {
+    double c2[2][G::FN];
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      c2[0][j] = cp[1][j];
+      c2[1][j] = cp[2][j];
     }
-  });
+    reduce_cols<G, 2>(c2, red, [&](int c, const double (&s)[2]) {
+      if (n0 + c < T) {
+        part[base + n0 + c] = 0.0;
+        part[stride + base + n0 + c] = s[0] * LN2;
+        part[2 * stride + base + n0 + c] = s[1] * LN2;
+        fpart[base + n0 + c] = fl_s[c];
+      }
+    });
+  }
 }
 
 // Row form (W orientation: one partial per row n of the tile).
-template <class G, int NC>
+template <class G, bool S0, int NC>
 __device__ __forceinline__ void cost_rows_acc(const float (&vf)[G::FM][G::FN][16],
                                               const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
                                               int64_t N, int64_t T, double (&rp)[3][G::FM][16], int* fl_s) {
@@ -247,7 +267,7 @@ __device__ __forceinline__ void cost_rows_acc(const float (&vf)[G::FM][G::FN][16
 #pragma unroll
       for (int j = 0; j < G::FN; ++j) {
         const float x = (row < N && epi_col<G>(n0, j) < T) ? vf[i][j][v] : 0.f;
-        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], rp[0][i][v], rp[1][i][v], rp[2][i][v]);
+        fl |= cost_acc<S0>(x, acc[i][j][0][v], acc[i][j][1][v], rp[0][i][v], rp[1][i][v], rp[2][i][v]);
       }
       if (fl) atomicOr(&fl_s[row - m0], fl);
     }
@@ -255,7 +275,8 @@ __device__ __forceinline__ void cost_rows_acc(const float (&vf)[G::FM][G::FN][16
 
 // The partials of one row block i at a time (the sums, their order and the
 // LDS layout of reduce_rows, with a third of the float64 registers live).
-template <class G, int NC>
+// With S0 = false the s0 partials are written as 0 (no cost wanted).
+template <class G, bool S0 = true, int NC>
 __device__ __forceinline__ void cost_rows(const float (&vf)[G::FM][G::FN][16],
                                           const f32x16 (&acc)[G::FM][G::FN][NC], int64_t m0, int64_t n0,
                                           int64_t N, int64_t T, double* red, int* fl_s, double* part, int* fpart,
@@ -273,12 +294,12 @@ __device__ __forceinline__ void cost_rows(const float (&vf)[G::FM][G::FN][16],
 #pragma unroll
       for (int j = 0; j < G::FN; ++j) {
         const float x = (row < N && epi_col<G>(n0, j) < T) ? vf[i][j][v] : 0.f;
-        fl |= cost_acc(x, acc[i][j][0][v], acc[i][j][1][v], rp[0][v], rp[1][v], rp[2][v]);
+        fl |= cost_acc<S0>(x, acc[i][j][0][v], acc[i][j][1][v], rp[0][v], rp[1][v], rp[2][v]);
       }
       if (fl) atomicOr(&fl_s[row - m0], fl);
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = S0 ? 0 : 1; q < 3; ++q) {
       const double y = halfwave_slot_sum(rp[q], lane);
       if ((lane & 1) == 0) red[(q * G::WGN + wn) * G::BM + wm * G::WM + i * 32 + slot_row(lane)] = y;
     }
@@ -289,7 +310,8 @@ __device__ __forceinline__ void cost_rows(const float (&vf)[G::FM][G::FN][16],
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       s[q] = 0.0;
-      for (int w = 0; w < G::WGN; ++w) s[q] += red[(q * G::WGN + w) * G::BM + r];
+      if (q > 0 || S0)
+        for (int w = 0; w < G::WGN; ++w) s[q] += red[(q * G::WGN + w) * G::BM + r];
     }
     if (m0 + r < N) {
       part[base + m0 + r] = s[0] * LN2;

@@ -141,12 +141,14 @@ hipError_t launch_cand_W(const float* W, const float* pu, const float* puc, cons
 // Fused candidate reconstruction + log + reduction (costs of both candidates).
 //   part: [3][tiles][L] float64 (sum_N, margin, MU-only rows), fpart: [tiles][L] int
 // With zd / dz (N x T, row-major) the kernels also store z_DNA and dZ there.
+// s0 = false: the sum_N partials are written as 0 (the choice needs only the
+// margin and the flags; the kept candidate's cost is then not available).
 hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn,
                          int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s,
-                         float* zd = nullptr, float* dz = nullptr);
+                         float* zd = nullptr, float* dz = nullptr, bool s0 = true);
 hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const float* Xn,
                          int64_t N, int64_t T, int64_t R, double* part, int* fpart, hipStream_t s,
-                         float* zd = nullptr, float* dz = nullptr);
+                         float* zd = nullptr, float* dz = nullptr, bool s0 = true);
 
 // Selection and write-back.
 // The damped selection's inputs (dpart == nullptr: Algorithm 1's rule).  With
@@ -218,10 +220,11 @@ hipError_t launch_rgh(int side, const float* V, const float* W, const float* H, 
 // cost partials over `splits` chunks of rows n (side 0) or columns t (side 1),
 // in the layout of launch_cost_H / launch_cost_W with tiles = splits.
 // newton_only: the damped selection's pass, the Newton candidate's cost alone
-// (one product; the margin and MU slots of the partials are zero).
+// (one product; the margin and MU slots of the partials are zero).  s0 = false
+// (both candidates): the sum_N partials are written as 0, as in launch_cost_H.
 hipError_t launch_costf(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
                         int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s,
-                        bool newton_only = false);
+                        bool newton_only = false, bool s0 = true);
 
 // The whole H half-step (steps 2-15) for R <= 64 in one kernel, a workgroup per
 // block of HCOLS_TB columns running over all N rows (kernels_cols.hip): H is

@@ -508,7 +508,7 @@ __global__ __launch_bounds__(256, GH16_WG_PER_CU) void k_gh16(Ops16 ops, int64_t
 typedef Prods<1, 2, 2, 2, 0, 0, 0, 0, 1, 1> CH_P;
 typedef Prods<2, 1, 2, 2, 0, 0, 0, 1, 0, 1> CW_P;
 
-template <typename TE, int SIDE>
+template <typename TE, int SIDE, bool S0>
 __global__ __launch_bounds__(256, CostCfg<SIDE>::WAVES_PER_EU) void k_cost16(const float* V, Ops16 ops, int64_t N,
                                                                             int64_t T, int64_t Rk, double* part,
                                                                             int* fpart) {
@@ -536,10 +536,10 @@ __global__ __launch_bounds__(256, CostCfg<SIDE>::WAVES_PER_EU) void k_cost16(con
   double* red = reinterpret_cast<double*>(lds_dyn);
   if (SIDE == 0) {
     const int64_t base = tl.y * T, stride = (int64_t)gridDim.y * T;
-    cost_cols<G>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
+    cost_cols<G, S0>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
   } else {
     const int64_t base = tl.x * N, stride = (int64_t)gridDim.x * N;
-    cost_rows<G>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
+    cost_rows<G, S0>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
   }
 }
 
@@ -734,7 +734,7 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
 template <typename TE>
 static hipError_t cost16(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
                          int64_t T, int64_t R, const Scratch16& S, bool scaled, double* part, int* fpart,
-                         hipStream_t s) {
+                         hipStream_t s, bool s0) {
   const Dims16 d = dims16(N, T, R);
   const float* rs = nullptr;
   const float* irs = nullptr;
@@ -762,12 +762,14 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
   prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
   if (side == 0) {
     const size_t lb = (size_t)Gemm16<G128, TE, CH_P, CostCfg<0>::STAGES>::LDS_BYTES;
-    lds_attr(k_cost16<TE, 0>, lb);
-    hipLaunchKernelGGL((k_cost16<TE, 0>), grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
+    auto k = s0 ? k_cost16<TE, 0, true> : k_cost16<TE, 0, false>;
+    lds_attr(k, lb);
+    hipLaunchKernelGGL(k, grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
   } else {
     const size_t lb = (size_t)Gemm16<G128, TE, CW_P, CostCfg<1>::STAGES>::LDS_BYTES;
-    lds_attr(k_cost16<TE, 1>, lb);
-    hipLaunchKernelGGL((k_cost16<TE, 1>), grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
+    auto k = s0 ? k_cost16<TE, 1, true> : k_cost16<TE, 1, false>;
+    lds_attr(k, lb);
+    hipLaunchKernelGGL(k, grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
   }
   prof_end(side == 0 ? "cost16_H" : "cost16_W", s);
   return hipGetLastError();
@@ -786,10 +788,10 @@ hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W,
 
 hipError_t launch_cost16(int gemm, int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                          int64_t N, int64_t T, int64_t R, const Scratch16& S, double* part, int* fpart,
-                         hipStream_t s) {
+                         hipStream_t s, bool s0) {
   if (T >= (int64_t(1) << 22)) return hipErrorInvalidValue;   // 32-bit offsets into V, as the Z pass
-  if (gemm == 1) return cost16<__bf16>(side, V, F, Xmu, Xn, N, T, R, S, false, part, fpart, s);
-  return cost16<_Float16>(side, V, F, Xmu, Xn, N, T, R, S, true, part, fpart, s);
+  if (gemm == 1) return cost16<__bf16>(side, V, F, Xmu, Xn, N, T, R, S, false, part, fpart, s, s0);
+  return cost16<_Float16>(side, V, F, Xmu, Xn, N, T, R, S, true, part, fpart, s, s0);
 }
 
 }  // namespace dna

@@ -48,6 +48,6 @@ hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W,
 // partials over cdiv(N, 128) (H step) or cdiv(T, 128) (W step) tiles.
 hipError_t launch_cost16(int gemm, int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                          int64_t N, int64_t T, int64_t R, const Scratch16& S, double* part, int* fpart,
-                         hipStream_t s);
+                         hipStream_t s, bool s0 = true);
 
 }  // namespace dna

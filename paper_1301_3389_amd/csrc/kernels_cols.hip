@@ -92,7 +92,7 @@ __device__ __forceinline__ int wsw(int n, int c) { return n * 64 + (((c >> 2) ^ 
 // read as zero (the descriptor range); rank columns past R hold the next row's
 // finite entries, which meet zero operands (H and the candidates past R); V of
 // padding columns is a valid column's, masked where used.
-template <int RB, bool CHK, bool W16>
+template <int RB, bool CHK, bool W16, bool DS>
 __global__ __launch_bounds__(256, 2) void k_hstep_cols(HColsArgs a) {
   constexpr int WLOADS = W16 ? 4 : 16, LOADS = WLOADS + 4;   // DMA instructions per thread and stage
   static_assert(2 * LOADS <= 63, "vmcnt holds at most 63 outstanding operations");
@@ -395,8 +395,8 @@ __global__ __launch_bounds__(256, 2) void k_hstep_cols(HColsArgs a) {
   auto costs = [&]() {
     float a0 = 0.f, a1 = 0.f;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) fl |= cost_acc_f(vp[v], zp[v], dp[v], a0, a1, s2);
-    s0 += (double)a0;
+    for (int v = 0; v < 4; ++v) fl |= cost_acc_f<DS>(vp[v], zp[v], dp[v], a0, a1, s2);
+    if (DS) s0 += (double)a0;
     s1 += (double)a1;
   };
   run([&](const float* L, int64_t nb, const float (&vf)[4]) {
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256, 2) void k_hstep_cols(HColsArgs a) {
 
   // ---------------- choice (step 15), H, row sums ----------------
   {
-    const double a0 = group4_sum(s0), a1 = group4_sum(s1), a2 = group4_sum(s2);
+    const double a0 = DS ? group4_sum(s0) : 0.0, a1 = group4_sum(s1), a2 = group4_sum(s2);
     if (g == 0) {
       col3[0][w][j] = a0;
       col3[1][w][j] = a1;
@@ -472,17 +472,24 @@ hipError_t launch_hstep_cols(const HColsArgs& a, hipStream_t s) {
   const int rb = (int)((a.R + 15) / 16);
   prof_begin("hstep_cols", s);
   const bool w16 = a.R % 4 == 0 && (reinterpret_cast<uintptr_t>(a.W) & 15) == 0;
+  // modes: no check and no cost wanted (the choice reads the margin and the
+  // flags only), the kept cost wanted, checked (with the cost)
   typedef void (*Kern)(HColsArgs);
-  static const Kern table[2][4][2] = {
-      {{&k_hstep_cols<1, false, false>, &k_hstep_cols<1, false, true>},
-       {&k_hstep_cols<2, false, false>, &k_hstep_cols<2, false, true>},
-       {&k_hstep_cols<3, false, false>, &k_hstep_cols<3, false, true>},
-       {&k_hstep_cols<4, false, false>, &k_hstep_cols<4, false, true>}},
-      {{&k_hstep_cols<1, true, false>, &k_hstep_cols<1, true, true>},
-       {&k_hstep_cols<2, true, false>, &k_hstep_cols<2, true, true>},
-       {&k_hstep_cols<3, true, false>, &k_hstep_cols<3, true, true>},
-       {&k_hstep_cols<4, true, false>, &k_hstep_cols<4, true, true>}}};
-  const Kern k = table[a.check ? 1 : 0][rb - 1][w16 ? 1 : 0];
+  static const Kern table[3][4][2] = {
+      {{&k_hstep_cols<1, false, false, false>, &k_hstep_cols<1, false, true, false>},
+       {&k_hstep_cols<2, false, false, false>, &k_hstep_cols<2, false, true, false>},
+       {&k_hstep_cols<3, false, false, false>, &k_hstep_cols<3, false, true, false>},
+       {&k_hstep_cols<4, false, false, false>, &k_hstep_cols<4, false, true, false>}},
+      {{&k_hstep_cols<1, false, false, true>, &k_hstep_cols<1, false, true, true>},
+       {&k_hstep_cols<2, false, false, true>, &k_hstep_cols<2, false, true, true>},
+       {&k_hstep_cols<3, false, false, true>, &k_hstep_cols<3, false, true, true>},
+       {&k_hstep_cols<4, false, false, true>, &k_hstep_cols<4, false, true, true>}},
+      {{&k_hstep_cols<1, true, false, true>, &k_hstep_cols<1, true, true, true>},
+       {&k_hstep_cols<2, true, false, true>, &k_hstep_cols<2, true, true, true>},
+       {&k_hstep_cols<3, true, false, true>, &k_hstep_cols<3, true, true, true>},
+       {&k_hstep_cols<4, true, false, true>, &k_hstep_cols<4, true, true, true>}}};
+  const int mode = a.check ? 2 : (a.dsel ? 1 : 0);
+  const Kern k = table[mode][rb - 1][w16 ? 1 : 0];
   hipLaunchKernelGGL(k, grid, dim3(256), 0, s, a);
   prof_end("hstep_cols", s);
   return hipGetLastError();

@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
 // ---------------------------------------------------------------------------
 // NO (newton only, the damped selection): z_DNA alone, the cost terms of
 // d_DNA only (the margin and MU slots of the partials are written as zero).
-template <bool NO>
+template <bool NO, bool S0>
 __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float* W, const float* Xmu,
                                                     const float* Xn, int64_t N, int64_t T, int64_t R,
                                                     int64_t nchunk, double* part, int* fpart) {
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
     for (int v = 0; v < 16; ++v) {
       const float x = vf[v];                      // 0 outside the matrix
       if (NO) fl |= cost_acc_newton(x, zn[v], cp[0][0]);
-      else fl |= cost_acc(x, zn[v], dz[v], cp[0][0], cp[1][0], cp[2][0]);
+      else fl |= cost_acc<S0>(x, zn[v], dz[v], cp[0][0], cp[1][0], cp[2][0]);
     }
     if (more)
 #pragma unroll
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_H(const float* V, const float*
 // [n][r]) and a range of columns t (H streamed, [r][t]).  Row partials of each
 // sub-tile are reduced across the half-wave at once (halfwave_slot_sum) and
 // kept per lane in float64.  Partials: part[q][sp][n].
-template <bool NO>
+template <bool NO, bool S0>
 __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float* H, const float* Xmu,
                                                     const float* Xn, int64_t N, int64_t T, int64_t R,
                                                     int64_t tchunk, double* part, int* fpart) {
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
     for (int v = 0; v < 16; ++v) {
       s2[v] = 0.0;
       const float x = vf[v];                      // 0 outside the matrix
-      const int f = NO ? cost_acc_newton_f(x, zn[v], a0[v]) : cost_acc_f(x, zn[v], dz[v], a0[v], a1[v], s2[v]);
+      const int f = NO ? cost_acc_newton_f(x, zn[v], a0[v]) : cost_acc_f<S0>(x, zn[v], dz[v], a0[v], a1[v], s2[v]);
       flr[v] |= f;
       fsub |= f;
     }
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
         s1[v] = (double)a1[v];
         a0[v] = a1[v] = 0.f;
       }
-      rs[0] += halfwave_slot_sum(s0, lane);
+      if (NO || S0) rs[0] += halfwave_slot_sum(s0, lane);
       rs[1] += halfwave_slot_sum(s1, lane);
       ng = 0;
     }
@@ -629,23 +629,19 @@ __global__ __launch_bounds__(256, 2) void k_costf_W(const float* V, const float*
 
 hipError_t launch_costf(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
                         int64_t T, int64_t R, int splits, int64_t chunk, double* part, int* fpart, hipStream_t s,
-                        bool newton_only) {
+                        bool newton_only, bool s0) {
   if (R > FUSED_MAX_R) return hipErrorInvalidValue;
   if (side == 0) {
     prof_begin("costf_H", s);
     const dim3 grid((unsigned)cdiv(T, 64), (unsigned)splits);
-    if (newton_only)
-      hipLaunchKernelGGL(k_costf_H<true>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
-    else
-      hipLaunchKernelGGL(k_costf_H<false>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
+    auto k = newton_only ? k_costf_H<true, true> : (s0 ? k_costf_H<false, true> : k_costf_H<false, false>);
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
     prof_end("costf_H", s);
   } else {
     prof_begin("costf_W", s);
     const dim3 grid((unsigned)cdiv(N, 64), (unsigned)splits);
-    if (newton_only)
-      hipLaunchKernelGGL(k_costf_W<true>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
-    else
-      hipLaunchKernelGGL(k_costf_W<false>, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
+    auto k = newton_only ? k_costf_W<true, true> : (s0 ? k_costf_W<false, true> : k_costf_W<false, false>);
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, V, F, Xmu, Xn, N, T, R, chunk, part, fpart);
     prof_end("costf_W", s);
   }
   return hipGetLastError();

@@ -880,6 +880,7 @@ __device__ __forceinline__ void store_recon(const TL& t, int64_t m0, int64_t n0,
     }
 }
 
+template <bool S0>
 __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,
                                                      int64_t T, int64_t R, double* part, int* fpart, float* zd,
                                                      float* dz) {
@@ -902,21 +903,24 @@ __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd
   }
   if (zd) store_recon<TL, GZ>(t, m0, n0, N, T, zd, dz);
   const int64_t base = tl.y * T, stride = (int64_t)gridDim.y * T;
-  cost_cols<GZ>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
+  cost_cols<GZ, S0>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn, int64_t N,
-                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s, float* zd, float* dz) {
+                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s, float* zd, float* dz,
+                         bool s0) {
   dim3 grid((unsigned)cdiv(T, GCH::BN), (unsigned)cdiv(N, GCH::BM));
   const Opnd w = make_opnd(W, R, N);
   const Opnd hn = make_opnd(Xn, T, T);
   const Opnd hd = make_opnd(Xmu, T, T, Xn);
   prof_begin("cost_H", s);
-  hipLaunchKernelGGL(k_cost_H, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart, zd, dz);
+  if (s0) hipLaunchKernelGGL(k_cost_H<true>, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart, zd, dz);
+  else hipLaunchKernelGGL(k_cost_H<false>, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart, zd, dz);
   prof_end("cost_H", s);
   return hipGetLastError();
 }
 
+template <bool S0>
 __global__ __launch_bounds__(GCW::NT, 2) void k_cost_W(const float* V, Opnd Wn, Opnd Wd, Opnd H, int64_t N,
                                                      int64_t T, int64_t R, double* part, int* fpart, float* zd,
                                                      float* dz) {
@@ -938,17 +942,19 @@ __global__ __launch_bounds__(GCW::NT, 2) void k_cost_W(const float* V, Opnd Wn, 
   }
   if (zd) store_recon<TL, GCW>(t, m0, n0, N, T, zd, dz);
   const int64_t base = tl.x * N, stride = (int64_t)gridDim.x * N;
-  cost_rows<GCW>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
+  cost_rows<GCW, S0>(vf, t.acc, m0, n0, N, T, reinterpret_cast<double*>(lds), fl_s, part, fpart, base, stride);
 }
 
 hipError_t launch_cost_W(const float* V, const float* H, const float* Xmu, const float* Xn, int64_t N,
-                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s, float* zd, float* dz) {
+                         int64_t T, int64_t R, double* part, int* fpart, hipStream_t s, float* zd, float* dz,
+                         bool s0) {
   dim3 grid((unsigned)cdiv(T, GCW::BN), (unsigned)cdiv(N, GCW::BM));
   const Opnd wn = make_opnd(Xn, R, N);
   const Opnd wd = make_opnd(Xmu, R, N, Xn);
   const Opnd h = make_opnd(H, T, T);
   prof_begin("cost_W", s);
-  hipLaunchKernelGGL(k_cost_W, grid, dim3(GCW::NT), 0, s, V, wn, wd, h, N, T, R, part, fpart, zd, dz);
+  if (s0) hipLaunchKernelGGL(k_cost_W<true>, grid, dim3(GCW::NT), 0, s, V, wn, wd, h, N, T, R, part, fpart, zd, dz);
+  else hipLaunchKernelGGL(k_cost_W<false>, grid, dim3(GCW::NT), 0, s, V, wn, wd, h, N, T, R, part, fpart, zd, dz);
   prof_end("cost_W", s);
   return hipGetLastError();
 }
