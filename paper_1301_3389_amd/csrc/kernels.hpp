@@ -120,6 +120,10 @@ struct CandLayout {
 };
 inline CandLayout cand_layout(int64_t T, int64_t R) {
   if (R <= 128) return {32, 32};
+  // 1024-thread blocks run two per CU: only where the blocks fill those rounds
+  // to at least 85%
+  const int64_t b = cdiv(T, 32);
+  if (R <= 512 && b >= 256 && b * 100 >= cdiv(b, 512) * 512 * 85) return {32, 32};
   if (cdiv(T, 32) >= 512) return {32, 8};
   return {8, 32};
 }

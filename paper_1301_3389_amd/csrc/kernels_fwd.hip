@@ -545,34 +545,40 @@ __global__ __launch_bounds__(COLS * RG) void k_cand_H(
   float keep[KEEP];
   if (ok) {
     if constexpr (RPT > 0) {
-      float u[RPT], uc[RPT], y[RPT];
+      // rows in groups of CH (the sums of a group in flight together); the
+      // Newton values stay in registers until the renormalisation
+      constexpr int CH = RPT < 4 ? RPT : 4;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) u[i] = uc[i] = y[i] = 0.f;
-      constexpr int SPU = RPT <= 2 ? 8 : (RPT <= 8 ? 2 : 1);   // loads in flight: 3 x RPT x SPU
+      for (int i0 = 0; i0 < RPT; i0 += CH) {
+        float u[CH], uc[CH], y[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) u[i] = uc[i] = y[i] = 0.f;
+        constexpr int SPU = CH <= 2 ? 8 : (CH <= 8 ? 2 : 1);   // loads in flight: 3 x CH x SPU
 #pragma unroll SPU
-      for (int sp = 0; sp < splits; ++sp) {
-        const int64_t o = (int64_t)sp * R * T + t;
+        for (int sp = 0; sp < splits; ++sp) {
+          const int64_t o = (int64_t)sp * R * T + t;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const int64_t r = rg + i * RG;
-          if (r < R) {
-            u[i] += pu[o + r * T];
-            uc[i] += puc[o + r * T];
-            y[i] += py[o + r * T];
+          for (int i = 0; i < CH; ++i) {
+            const int64_t r = rg + (i0 + i) * RG;
+            if (r < R) {
+              u[i] += pu[o + r * T];
+              uc[i] += puc[o + r * T];
+              y[i] += py[o + r * T];
+            }
           }
         }
-      }
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int64_t r = rg + i * RG;
-        keep[i] = 0.f;
-        if (r < R) {
-          const Cand k = candidate(H[r * T + t], u[i], uc[i], y[i], c[r], eps, alpha, reg);
-          Xmu[r * T + t] = k.mu;
-          keep[i] = k.newton;
-          if (Aout) Aout[r * T + t] = k.A;
-          if (Bout) Bout[r * T + t] = k.B;
-          den += (double)c[r] * (double)k.newton;
+        for (int i = 0; i < CH; ++i) {
+          const int64_t r = rg + (i0 + i) * RG;
+          keep[i0 + i] = 0.f;
+          if (r < R) {
+            const Cand k = candidate(H[r * T + t], u[i], uc[i], y[i], c[r], eps, alpha, reg);
+            Xmu[r * T + t] = k.mu;
+            keep[i0 + i] = k.newton;
+            if (Aout) Aout[r * T + t] = k.A;
+            if (Bout) Bout[r * T + t] = k.B;
+            den += (double)c[r] * (double)k.newton;
+          }
         }
       }
     } else {
@@ -653,9 +659,11 @@ hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, cons
                          const double* vpart, int tiles_m, int64_t T, int64_t R, float eps, float alpha, float reg,
                          float* Xmu, float* Xn, float* Aout, float* Bout, hipStream_t s) {
   prof_begin("cand_H", s);
-  // for R <= 128, 32 row groups (1024 threads) give every CU 16 waves of
-  // independent loads; larger R takes the general loop, with 32 columns x 8 row
-  // groups per block, or 8 x 32 where that would leave fewer than 512 blocks
+  // for R <= 128 (and R <= 512 where T gives at least 256 blocks), 32 row
+  // groups (1024 threads) give every CU 16 waves of independent loads and keep
+  // each thread's Newton values in registers until the renormalisation; larger
+  // R takes the general loop, with 32 columns x 8 row groups per block, or
+  // 8 x 32 where that would leave fewer than 512 blocks
   const CandLayout lay = cand_layout(T, R);
   const dim3 grid((unsigned)cdiv(T, lay.cols));
   constexpr int RG = 32;
@@ -664,6 +672,9 @@ hipError_t launch_cand_H(const float* H, const float* pu, const float* puc, cons
                        tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
   else if (R <= 4 * RG)
     hipLaunchKernelGGL((k_cand_H<4, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
+                       tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
+  else if (lay.rg == RG && R <= 16 * RG)
+    hipLaunchKernelGGL((k_cand_H<16, RG>), grid, dim3(CAND_COLS * RG), 0, s, H, pu, puc, py, splits, c, vpart,
                        tiles_m, T, R, eps, alpha, reg, Xmu, Xn, Aout, Bout);
   else if (lay.cols == CAND_COLS)
     hipLaunchKernelGGL((k_cand_H<0, CAND_RG>), grid, dim3(CAND_COLS * CAND_RG), 0, s, H, pu, puc, py, splits, c,
