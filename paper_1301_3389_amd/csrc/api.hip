@@ -185,9 +185,9 @@ static Layout make_layout(int64_t N, int64_t T, int64_t R, bool with16, bool adj
   L.shf = fused_split(N, cdiv(T, 64));
   L.swf = fused_split(T, cdiv(N, 64));
   L.chf = balanced_split(N, cdiv(T, 64), 3);
-  L.rt_m = (int)cdiv(N, RT_BM);
+  L.rt_m = (int)cdiv(N, ratio_tile_rows(N, T));
   L.rt_n = (int)cdiv(T, RT_BN);
-  L.ch_m = (int)cdiv(N, CH_BM);
+  L.ch_m = (int)cdiv(N, cost_h_tile_rows(N, T));
   L.cw_n = (int)cdiv(T, CW_BN);
   const size_t nt = (size_t)N * T, fac = (size_t)std::max(R * T, N * R);
   const int64_t sph = std::max({L.sh.splits, L.sh16.splits, L.shf.splits});
@@ -394,13 +394,14 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
       DNA_HIP(launch_gh_H(W, Q, Qb, N >= GH_CHUNK_MIN_K ? cs : nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc,
                           py, s), "gh_H");
     }
-    // the 16-bit Z pass tiles N by 128 like the fp32 one (RT_BM)
+    // the 16-bit Z pass tiles N by 128
     int sp = p16 ? L.sh16.splits : (fused ? L.shf.splits : L.sh.splits);
+    const int tiles = p16 ? (int)cdiv(N, 128) : (fused ? L.shf.splits : L.rt_m);
     if (sp > 8 && T < 256 * 32) {                   // few column blocks, many splits: fold them first
       DNA_HIP(launch_fold_splits(pu, puc, py, sp, R * T, s), "fold_splits");
       sp = 1;
     }
-    DNA_HIP(launch_cand_H(H, pu, puc, py, sp, c32, vpart, fused ? L.shf.splits : L.rt_m, T, R, o->eps, o->alpha,
+    DNA_HIP(launch_cand_H(H, pu, puc, py, sp, c32, vpart, tiles, T, R, o->eps, o->alpha,
                           o->lambda, Xmu, Xn, Aout, Bout, s), "cand_H");
   } else {
     if (pre) job = *pre;
@@ -450,9 +451,11 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
     DNA_HIP(launch_cost16(o->gemm, side, V, F, Xmu, Xn, N, T, R, scratch16(ws, L, N, T, R), cpart, fpart, s, s0),
             "cost16");
     if (side == 0)
-      DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, L.ch_m, T, R, mask, dsel, margin, s), "select_H");
+      DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, (int)cdiv(N, 128), T, R, mask, dsel, margin, s),
+              "select_H");   // the 16-bit cost pass tiles N by 128
     else
-      DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, L.cw_n, N, R, mask, dsel, margin, s), "select_W");
+      DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, (int)cdiv(T, 128), N, R, mask, dsel, margin, s),
+              "select_W");
     return DNA_OK;
   }
   const bool fused = R <= FUSED_MAX_R;   // candidates' block resident in LDS

@@ -30,6 +30,12 @@ constexpr int GEMM_BK = 16;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Rows per tile of the fp32 ratio pass and of the H-orientation cost pass:
+// 128, or 64 where 128-row tiles would give fewer than two workgroups per CU
+// (the partial sums of both passes then come in cdiv(N, 64) row tiles).
+inline int ratio_tile_rows(int64_t N, int64_t T) { return cdiv(N, RT_BM) * cdiv(T, RT_BN) < 512 ? 64 : RT_BM; }
+inline int cost_h_tile_rows(int64_t N, int64_t T) { return cdiv(N, CH_BM) * cdiv(T, CH_BN) < 512 ? 64 : CH_BM; }
+
 // Every updated factor entry is kept at or above the smallest positive normal
 // float32 (2^-126).  In exact arithmetic no update sends a positive entry to 0
 // (the eps floor bounds the shrink per step), but float32 underflows an entry

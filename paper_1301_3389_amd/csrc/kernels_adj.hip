@@ -220,6 +220,7 @@ hipError_t launch_cand_bwd_H(const float* H, const float* pu, const float* puc, 
 
 // qbar = W ubar, qbbar = (W*W) ybar (MFMA, K = R) and the pointwise chain rule
 // through q = v/z, qb = v/z^2.
+template <class GZB>
 __global__ __launch_bounds__(GZB::NT) void k_zbar(const float* V, const float* Z, Opnd W, Opnd Ub, Opnd Yb,
                                                   const float* sbar, int64_t N, int64_t T, int64_t R,
                                                   float* Zbar, float* dV, int accumulate) {
@@ -261,12 +262,20 @@ __global__ __launch_bounds__(GZB::NT) void k_zbar(const float* V, const float* Z
 hipError_t launch_zbar(const float* V, const float* Z, const float* W, const float* Ubar, const float* Ybar,
                        const float* sbar, int64_t N, int64_t T, int64_t R, float* Zbar, float* dV, int accumulate,
                        hipStream_t s) {
-  dim3 grid((unsigned)cdiv(T, GZB::BN), (unsigned)cdiv(N, GZB::BM));
   const Opnd w = make_opnd(W, R, N);
   const Opnd ub = make_opnd(Ubar, T, T);
   const Opnd yb = make_opnd(Ybar, T, T);
   prof_begin("zbar", s);
-  hipLaunchKernelGGL(k_zbar, grid, dim3(GZB::NT), 0, s, V, Z, w, ub, yb, sbar, N, T, R, Zbar, dV, accumulate);
+  // fewer 128 x 128 tiles than two per CU: 64 x 64 tiles (elementwise outputs,
+  // the same sums per entry)
+  if (cdiv(T, GZB::BN) * cdiv(N, GZB::BM) < 512) {
+    using GS = Geo<64, 64, GEMM_BK, 2, 2>;
+    dim3 grid((unsigned)cdiv(T, GS::BN), (unsigned)cdiv(N, GS::BM));
+    hipLaunchKernelGGL(k_zbar<GS>, grid, dim3(GS::NT), 0, s, V, Z, w, ub, yb, sbar, N, T, R, Zbar, dV, accumulate);
+  } else {
+    dim3 grid((unsigned)cdiv(T, GZB::BN), (unsigned)cdiv(N, GZB::BM));
+    hipLaunchKernelGGL(k_zbar<GZB>, grid, dim3(GZB::NT), 0, s, V, Z, w, ub, yb, sbar, N, T, R, Zbar, dV, accumulate);
+  }
   prof_end("zbar", s);
   return hipGetLastError();
 }

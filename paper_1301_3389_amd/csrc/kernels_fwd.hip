@@ -48,9 +48,8 @@ struct RatioKArgs {
   ZCarry carry;
 };
 
-template <int MODE>
-__global__ __launch_bounds__(GR::NT) void k_ratio(RatioKArgs a) {
-  using GZ = GR;
+template <int MODE, class GZ>
+__global__ __launch_bounds__(GZ::NT) void k_ratio(RatioKArgs a) {
   using TL = Tile<GZ, ProdSingle, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   // dispatch order: the Q, Q-bar (and Z) writes of the resident tiles then
@@ -169,13 +168,16 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s) {
   k.carry = a.carry;
   if ((mode == RM_H_CARRY || mode == RM_W_CARRY) && (!a.carry.zd || !a.carry.dz || !a.carry.sel))
     return hipErrorInvalidValue;
-  dim3 grid((unsigned)cdiv(a.T, GR::BN), (unsigned)cdiv(a.N, GR::BM));
+  const bool small = ratio_tile_rows(a.N, a.T) == GS::BM;
+  static_assert(GS::BN == GR::BN, "both ratio geometries tile T alike");
+  dim3 grid((unsigned)cdiv(a.T, GR::BN), (unsigned)cdiv(a.N, small ? GS::BM : GR::BM));
   const char* nm = "ratio";
-#define DNA_RATIO_CASE(M, NAME)                                         \
-  case M:                                                                \
-    nm = NAME;                                                           \
-    prof_begin(nm, s);                                                   \
-    hipLaunchKernelGGL(k_ratio<M>, grid, dim3(GR::NT), 0, s, k);         \
+#define DNA_RATIO_CASE(M, NAME)                                                           \
+  case M:                                                                                  \
+    nm = NAME;                                                                             \
+    prof_begin(nm, s);                                                                     \
+    if (small) hipLaunchKernelGGL((k_ratio<M, GS>), grid, dim3(GS::NT), 0, s, k);         \
+    else hipLaunchKernelGGL((k_ratio<M, GR>), grid, dim3(GR::NT), 0, s, k);               \
     break;
   switch (mode) {
     DNA_RATIO_CASE(RM_H, "ratio_H")
@@ -891,11 +893,10 @@ __device__ __forceinline__ void store_recon(const TL& t, int64_t m0, int64_t n0,
     }
 }
 
-template <bool S0>
-__global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,
+template <bool S0, class GZ>
+__global__ __launch_bounds__(GZ::NT) void k_cost_H(const float* V, Opnd W, Opnd Hn, Opnd Hd, int64_t N,
                                                      int64_t T, int64_t R, double* part, int* fpart, float* zd,
                                                      float* dz) {
-  using GZ = GCH;
   using TL = Tile<GZ, ProdDualB, true, false>;
   __shared__ __align__(16) float lds[TL::LDS_FLOATS];
   __shared__ int fl_s[GZ::BN];
@@ -920,13 +921,15 @@ __global__ __launch_bounds__(GCH::NT) void k_cost_H(const float* V, Opnd W, Opnd
 hipError_t launch_cost_H(const float* V, const float* W, const float* Xmu, const float* Xn, int64_t N,
                          int64_t T, int64_t R, double* part, int* fpart, hipStream_t s, float* zd, float* dz,
                          bool s0) {
-  dim3 grid((unsigned)cdiv(T, GCH::BN), (unsigned)cdiv(N, GCH::BM));
+  const bool small = cost_h_tile_rows(N, T) == GS::BM;
+  static_assert(GS::BN == GCH::BN, "both cost geometries tile T alike");
+  dim3 grid((unsigned)cdiv(T, GCH::BN), (unsigned)cdiv(N, small ? GS::BM : GCH::BM));
   const Opnd w = make_opnd(W, R, N);
   const Opnd hn = make_opnd(Xn, T, T);
   const Opnd hd = make_opnd(Xmu, T, T, Xn);
   prof_begin("cost_H", s);
-  if (s0) hipLaunchKernelGGL(k_cost_H<true>, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart, zd, dz);
-  else hipLaunchKernelGGL(k_cost_H<false>, grid, dim3(GCH::NT), 0, s, V, w, hn, hd, N, T, R, part, fpart, zd, dz);
+  auto k = small ? (s0 ? k_cost_H<true, GS> : k_cost_H<false, GS>) : (s0 ? k_cost_H<true, GCH> : k_cost_H<false, GCH>);
+  hipLaunchKernelGGL(k, grid, dim3(256), 0, s, V, w, hn, hd, N, T, R, part, fpart, zd, dz);
   prof_end("cost_H", s);
   return hipGetLastError();
 }
