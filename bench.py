@@ -58,10 +58,39 @@ def kernel_work(name, N, T, R):
     return table.get(name)
 
 
+def _unmangle(name):
+    """(base, template arguments) of a mangled dna:: kernel name, which rocprofv3
+    leaves mangled when a template argument is a 16-bit float type; None if the
+    name is not of that form."""
+    import re
+    m = re.match(r"_ZN3dna(\d+)", name)
+    if not m:
+        return None
+    n = int(m.group(1))
+    rest = name[m.end():]
+    base, rest = rest[:n], rest[n:]
+    if not rest.startswith("I"):
+        return base, []
+    parts = []
+    for tok in re.findall(r"L[ib]\d+E|DF16[b_]", rest[1:rest.find("EEv") + 1]):
+        if tok.startswith("DF16"):
+            parts.append("bf16" if tok == "DF16b" else "fp16")
+        elif tok.startswith("Lb"):
+            parts.append("true" if tok[2:-1] == "1" else "false")
+        else:
+            parts.append(tok[2:-1])
+    return base, parts
+
+
 def kernel_key(rocprof_name):
     """Bench kernel key of a rocprofv3 kernel name (the names prof_begin uses)."""
     import re
-    nm = rocprof_name.split("(")[0].replace("void ", "").replace("dna::", "")
+    um = _unmangle(rocprof_name.strip())
+    if um is not None:
+        base, parts = um
+        nm = base + ("<" + ", ".join(parts) + ">" if parts else "")
+    else:
+        nm = rocprof_name.split("(")[0].replace("void ", "").replace("dna::", "")
     base = re.sub(r"<.*>", "", nm)
     targs = re.search(r"<(.*)>", nm)
     side = None

@@ -26,6 +26,12 @@ import bench  # noqa: E402
     ("dna::k_sp_qz(dna::SpV, float const*)", "sp_qz"),
     ("void dna::k_hstep_cols<4, false, true>(dna::HColsArgs)", "hstep_cols"),
     ("dna::k_ratio<8>(dna::RatioArgs)", "ratio_H"),
+    ("void dna::k_ratio<9, dna::Geo<64, 64, 16, 2, 2> >(dna::RatioKArgs)", "ratio_W"),
+    ("_ZN3dna9k_ratio16IDF16bLi0ELb0ELi3EEEvNS_11Ratio16ArgsE", "ratio16_H"),
+    ("_ZN3dna9k_ratio16IDF16_Li1ELb1ELi0EEEvNS_11Ratio16ArgsE", "qmax16"),
+    ("_ZN3dna6k_gh16IDF16bLi0EEEvNS_5Ops16EllllPfS2_S2_NS_4FoldE", "gh16_H"),
+    ("_ZN3dna8k_cost16IDF16_Li1ELb0EEEvPKfNS_5Ops16ElllPdPi", "cost16_W"),
+    ("_ZN3dna8k_conv16IDF16bLb0EEEvNS_8ConvArgsE", "conv16"),
 ])
 def test_kernel_key(rocprof, key):
     assert bench.kernel_key(rocprof) == key
