@@ -92,6 +92,7 @@ def kernel_key(rocprof_name):
     else:
         nm = rocprof_name.split("(")[0].replace("void ", "").replace("dna::", "")
     base = re.sub(r"<.*>", "", nm)
+    base = {"k_gh2_H": "k_gh_H", "k_gh2_W": "k_gh_W"}.get(base, base)   # both gradient forms profile as gh_H/W
     targs = re.search(r"<(.*)>", nm)
     side = None
     if targs:

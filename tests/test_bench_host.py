@@ -32,6 +32,8 @@ import bench  # noqa: E402
     ("_ZN3dna6k_gh16IDF16bLi0EEEvNS_5Ops16EllllPfS2_S2_NS_4FoldE", "gh16_H"),
     ("_ZN3dna8k_cost16IDF16_Li1ELb0EEEvPKfNS_5Ops16ElllPdPi", "cost16_W"),
     ("_ZN3dna8k_conv16IDF16bLb0EEEvNS_8ConvArgsE", "conv16"),
+    ("void dna::k_gh2_W<dna::Geo<128, 64, 16, 2, 2> >(dna::Opnd, dna::Opnd)", "gh_W"),
+    ("void dna::k_gh_H<dna::Geo<64, 128, 16, 2, 2>, dna::ProdGH3_H>(dna::Opnd)", "gh_H"),
 ])
 def test_kernel_key(rocprof, key):
     assert bench.kernel_key(rocprof) == key
