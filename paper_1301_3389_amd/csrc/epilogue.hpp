@@ -105,10 +105,14 @@ __device__ __forceinline__ float log2_1p(float u) {
 // while the ratio is near 1; below 1/2 the ratio itself, formed as z_MU / z_DNA
 // (1 + u would lose its relative precision, or fall to or below zero through
 // rounding, when z_MU is far smaller than z_DNA).
+// The direct form is evaluated only when some lane of the wave needs it (a
+// wave-uniform branch): z_MU below half of z_DNA is rare, and the logarithm
+// costs a quarter-rate instruction per element.
 __device__ __forceinline__ float log2_ratio(float u, float zM, float izN) {
-  const float direct = log2_hw(zM * izN);
   const float near1 = log2_1p(fmaxf(u, -0.5f));
-  return (u < -0.5f) ? direct : near1;
+  const bool low = u < -0.5f;
+  if (__any(low)) return low ? log2_hw(zM * izN) : near1;
+  return near1;
 }
 
 __device__ __forceinline__ double xlog2x_over(float v, float z) {
