@@ -435,10 +435,14 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
 // `keep`: the cost pass also stores Z_DNA and dZ, and the selection is written to
 // the workspace mask when the caller wants none, for the next half-step's
 // carried Z (tiled fp32 path only).
+// `fresh` (W step): the selection also leaves the first level of the column
+// sums of the new W (in the pu buffer, whose split partials the candidates have
+// consumed) for the normalisation that follows.
 static dna_status run_select(int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                              float* Xout, int64_t N, int64_t T, int64_t R, const dna_opts* o, const Layout& L,
                              void* ws, uint8_t* mask, double* dsel, double* margin, hipStream_t s,
-                             bool keep = false) {
+                             bool keep = false, SumJob* fresh = nullptr) {
+  double* emit = fresh ? at<double>(ws, L.pu) : nullptr;
   float* zd = keep ? at<float>(ws, L.zd) : nullptr;
   float* dz = keep ? at<float>(ws, L.dz) : nullptr;
   // the choice reads the margin and the flags only; the kept candidate's cost
@@ -453,9 +457,11 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
     if (side == 0)
       DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, (int)cdiv(N, 128), T, R, mask, dsel, margin, s),
               "select_H");   // the 16-bit cost pass tiles N by 128
-    else
-      DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, (int)cdiv(T, 128), N, R, mask, dsel, margin, s),
-              "select_W");
+    else {
+      DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, (int)cdiv(T, 128), N, R, mask, dsel, margin, s, Damp{},
+                              emit), "select_W");
+      if (fresh) *fresh = SumJob{emit, select_w_parts((int)cdiv(T, 128), N), R};
+    }
     return DNA_OK;
   }
   const bool fused = R <= FUSED_MAX_R;   // candidates' block resident in LDS
@@ -484,8 +490,10 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
               "costf_W");
     else
       DNA_HIP(launch_cost_W(V, F, Xmu, Xn, N, T, R, cpart, fpart, s, zd, dz, s0), "cost_W");
-    DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, fused ? L.swf.splits : L.cw_n, N, R, mask, dsel, margin,
-                            s, dp), "select_W");
+    const int tiles = fused ? L.swf.splits : L.cw_n;
+    DNA_HIP(launch_select_W(Xmu, Xn, Xout, cpart, fpart, tiles, N, R, mask, dsel, margin, s, dp, emit),
+            "select_W");
+    if (fresh) *fresh = SumJob{emit, select_w_parts(tiles, N), R};
   }
   return DNA_OK;
 }
@@ -707,8 +715,9 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
     }
     DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
                            have ? &next : nullptr, keep));
-    DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep));
-    DNA_TRY(iterate_normalize(0, W, H, N, T, R, o, c, ws, next, have));  // step 29; next = c
+    SumJob freshW;
+    DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep, &freshW));
+    DNA_TRY(iterate_normalize(0, W, H, N, T, R, o, c, ws, next, have, &freshW));  // step 29; next = c
     zin = keep;
   }
   return epilogue(c);

@@ -175,9 +175,13 @@ struct Damp {
 hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const double* part,
                            const int* fpart, int tiles_m, int64_t T, int64_t R, uint8_t* mask,
                            double* dsel, double* margin, hipStream_t s, const Damp& dp = Damp{});
+// With `emit`, also the float64 column sums of the new W over each block's
+// rows: emit[p * R + r] for the select_w_parts(tiles_n, N) blocks p.
 hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const double* part,
                            const int* fpart, int tiles_n, int64_t N, int64_t R, uint8_t* mask,
-                           double* dsel, double* margin, hipStream_t s, const Damp& dp = Damp{});
+                           double* dsel, double* margin, hipStream_t s, const Damp& dp = Damp{},
+                           double* emit = nullptr);
+int select_w_parts(int tiles_n, int64_t N);
 
 // MU update from split partials (+ optional cost finalisation).
 hipError_t launch_mu_H(float* H, const float* pu, int splits, const float* c, int64_t T, int64_t R,

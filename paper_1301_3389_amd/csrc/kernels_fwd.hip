@@ -1106,15 +1106,35 @@ hipError_t launch_select_H(const float* Xmu, const float* Xn, float* Hout, const
   return hipGetLastError();
 }
 
+// The column sums over a block's four rows of the new W: wave w holds row
+// w's entries (`row`, nullptr for a row past N), lane r of every 64-column
+// chunk; the four rows are added in order through LDS.  Every wave of the block
+// calls this (it has barriers).
+__device__ __forceinline__ void select_w_emit(const float* row, int64_t R, int wave, int lane, double* emit) {
+  __shared__ double cs[4][64];
+  for (int64_t r0 = 0; r0 < R; r0 += 64) {
+    const int64_t r = r0 + lane;
+    cs[wave][lane] = (row && r < R) ? (double)row[r] : 0.0;
+    __syncthreads();
+    if (wave == 0 && r < R) emit[(int64_t)blockIdx.x * R + r] = ((cs[0][lane] + cs[1][lane]) + cs[2][lane]) + cs[3][lane];
+    __syncthreads();
+  }
+}
+
 // A wave per row (four rows per block): the lanes add the tile partials.
+// With `emit`, the block also writes the float64 sums over its rows of each
+// column r of the new W (emit[block * R + r]; parts for the normalisation).
 __global__ __launch_bounds__(256) void k_select_W(const float* __restrict__ Xmu, const float* __restrict__ Xn,
                                                   float* __restrict__ Wout,
                                                   const double* part, const int* fpart, int tiles,
                                                   int64_t N, int64_t R, uint8_t* mask, double* dsel,
-                                                  double* margin, Damp dp) {
-  const int lane = threadIdx.x & 63;
-  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (n >= N) return;
+                                                  double* margin, Damp dp, double* emit) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * 4 + wave;
+  if (n >= N) {
+    if (emit) select_w_emit(nullptr, R, wave, lane, emit);
+    return;
+  }
   const int64_t stride = (int64_t)tiles * N;
   double q0 = 0.0, q1 = 0.0, q2 = 0.0;
   int fl = 0;
@@ -1148,6 +1168,7 @@ __global__ __launch_bounds__(256) void k_select_W(const float* __restrict__ Xmu,
   }
   const float* src = nw ? Xn : Xmu;
   for (int64_t r = lane; r < R; r += 64) Wout[n * R + r] = src[n * R + r];
+  if (emit) select_w_emit(src + n * R, R, wave, lane, emit);
 }
 
 // Few tile partials (at most SEL_FEW, e.g. the sparse path's one): SEL_ROWS
@@ -1158,8 +1179,9 @@ __global__ __launch_bounds__(256) void k_select_W_rows(const float* __restrict__
                                                        float* __restrict__ Wout,
                                                        const double* part, const int* fpart, int tiles,
                                                        int64_t N, int64_t R, uint8_t* mask, double* dsel,
-                                                       double* margin, Damp dp) {
+                                                       double* margin, Damp dp, double* emit) {
   __shared__ int pick[SEL_ROWS];
+  __shared__ double cs[4][64];
   const int tid = threadIdx.x;
   const int64_t n0 = (int64_t)blockIdx.x * SEL_ROWS;
   if (tid < SEL_ROWS && n0 + tid < N) {
@@ -1192,24 +1214,38 @@ __global__ __launch_bounds__(256) void k_select_W_rows(const float* __restrict__
   }
   __syncthreads();
   const int64_t rows = std::min<int64_t>(SEL_ROWS, N - n0);
-  const int lane = tid & 63;
-  for (int64_t nl = tid >> 6; nl < rows; nl += 4) {
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int64_t nl = wave; nl < rows; nl += 4) {
     const int64_t o = (n0 + nl) * R;
     const float* src = pick[nl] ? Xn : Xmu;
     for (int64_t r = lane; r < R; r += 64) Wout[o + r] = src[o + r];
   }
+  if (emit) {   // column sums over the block's rows: each wave every fourth row, then the four waves in order
+    for (int64_t r0 = 0; r0 < R; r0 += 64) {
+      const int64_t r = r0 + lane;
+      double a = 0.0;
+      if (r < R)
+        for (int64_t nl = wave; nl < rows; nl += 4) a += (double)(pick[nl] ? Xn : Xmu)[(n0 + nl) * R + r];
+      cs[wave][lane] = a;
+      __syncthreads();
+      if (wave == 0 && r < R) emit[(int64_t)blockIdx.x * R + r] = ((cs[0][lane] + cs[1][lane]) + cs[2][lane]) + cs[3][lane];
+      __syncthreads();
+    }
+  }
 }
+
+int select_w_parts(int tiles_n, int64_t N) { return (int)(tiles_n <= SEL_FEW ? cdiv(N, SEL_ROWS) : cdiv(N, 4)); }
 
 hipError_t launch_select_W(const float* Xmu, const float* Xn, float* Wout, const double* part,
                            const int* fpart, int tiles_n, int64_t N, int64_t R, uint8_t* mask,
-                           double* dsel, double* margin, hipStream_t s, const Damp& dp) {
+                           double* dsel, double* margin, hipStream_t s, const Damp& dp, double* emit) {
   prof_begin("select_W", s);
   if (tiles_n <= SEL_FEW)
     hipLaunchKernelGGL(k_select_W_rows, dim3((unsigned)cdiv(N, SEL_ROWS)), dim3(256), 0, s, Xmu, Xn, Wout, part,
-                       fpart, tiles_n, N, R, mask, dsel, margin, dp);
+                       fpart, tiles_n, N, R, mask, dsel, margin, dp, emit);
   else
     hipLaunchKernelGGL(k_select_W, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, Xmu, Xn, Wout, part, fpart,
-                       tiles_n, N, R, mask, dsel, margin, dp);
+                       tiles_n, N, R, mask, dsel, margin, dp, emit);
   prof_end("select_W", s);
   return hipGetLastError();
 }
