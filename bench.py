@@ -436,8 +436,9 @@ def unrolled_main(args):
     and the roofline record of the dominant algorithmic kernel of each.
     Algorithmic work: forward 8NRT per update (the paper's four products);
     backward 12NRT per update (qbar, qbbar: 4NRT in zbar; the three W-gradient
-    products: 6NRT in wbar; W^t zbar: 2NRT); the recomputed Z, Q and gradient
-    sums of the backward are not counted."""
+    products: 6NRT in wbar; W^t zbar: 2NRT).  The forward keeps Z, Q, Q-bar and
+    the gradient sums of every update for the backward (the autograd path's
+    calls), so the backward recomputes no product."""
     import torch
     from paper_1301_3389_amd import dna, synth
     torch.cuda.set_device(0)
@@ -452,24 +453,26 @@ def unrolled_main(args):
     H0 = torch.from_numpy(w.H0).to(dev)
     nrt = float(N) * R * T
 
+    # the autograd path's calls: the forward keeps Z, Q, Q-bar and the gradient
+    # sums of every update, which the backward reads instead of recomputing
     def fwd():
-        return dna.unrolled_forward(V, W, H, K)
+        return dna.unrolled_forward(V, W, H, K, keep_sums=True)
 
-    def bwd(Hc, sel):
-        return dna.unrolled_backward(V, W, Hc, sel, K, 2.0 * (Hc[K] - H0).contiguous())
+    def bwd(Hc, sel, aux):
+        return dna.unrolled_backward(V, W, Hc, sel, K, 2.0 * (Hc[K] - H0).contiguous(), aux=aux)
 
     for _ in range(max(1, args.warmup)):
-        Hc, sel = fwd()
-        bwd(Hc, sel)
+        Hc, sel, aux = fwd()
+        bwd(Hc, sel, aux)
     torch.cuda.synchronize()
     reps = max(1, args.steps)
     t0 = time.perf_counter()
     for _ in range(reps):
-        Hc, sel = fwd()
+        Hc, sel, aux = fwd()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(reps):
-        bwd(Hc, sel)
+        bwd(Hc, sel, aux)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     fwd_ms, bwd_ms = 1e3 * (t1 - t0) / reps, 1e3 * (t2 - t1) / reps
@@ -484,7 +487,7 @@ def unrolled_main(args):
         return {k: {"launches": n, "avg_ms": ms / max(n, 1), "total_ms": ms} for k, (n, ms) in st.items()}
 
     kf = kernel_profile(fwd)
-    kb = kernel_profile(lambda: bwd(Hc, sel))
+    kb = kernel_profile(lambda: bwd(Hc, sel, aux))
     peak = PEAK_FP32_TFLOPS
 
     def roof(kernels, work):
@@ -502,7 +505,7 @@ def unrolled_main(args):
            "data": "synthetic",
            "config": {"workload": f"unrolled H-solve, W fixed Gamma(0.5) {N} x {R}, V = Poisson(W H0) with "
                                   f"T={T}, K={K} DNA H-updates, loss ||H_K - H0||^2", "N": N, "T": T, "R": R, "K": K,
-                      "parallelism": "single GPU"},
+                      "kept_sums": aux is not None, "parallelism": "single GPU"},
            "forward_ms": fwd_ms, "backward_ms": bwd_ms,
            "forward_tflops_algorithmic": alg_f / (fwd_ms * 1e-3) / 1e12,
            "backward_tflops_algorithmic": alg_b / (bwd_ms * 1e-3) / 1e12,

@@ -360,6 +360,33 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
                               float* dW, float* dV, float* dH_init, const dna_opts* opts,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* Kept sums (for callers with memory to spare; the gradients are the same).
+ * The backward above recomputes, for every update k, Z = W H_k, Q, Q-bar and
+ * the sums u, u_c, y of eq. 7 and 14 (two products per update).  The _aux
+ * variants instead have the forward keep them in a caller-owned device
+ * buffer `aux` of dna_unrolled_aux_bytes(N, T, R, K, opts) bytes (256-byte
+ * aligned; per update 3 N T + 3 s R T floats, s the split count of the
+ * product), which the backward reads: the backward then skips both products.
+ * The bytes are 0 for R <= 64 (there the recompute is one fused pass) and the
+ * _aux calls then behave as the plain ones, `aux` unused (it may be NULL).
+ * The buffer must hold, unmodified, what the _aux forward of the same V, W,
+ * H_init, K and opts wrote when the _aux backward reads it; it is the
+ * caller's.  Errors: DNA_EWORKSPACE if aux_bytes is too small, DNA_EINVAL if
+ * aux is misaligned, otherwise as the plain calls. */
+size_t dna_unrolled_aux_bytes(int64_t N, int64_t T, int64_t R, int K, const dna_opts* opts);
+
+dna_status dna_unrolled_H_fwd_aux(const float* V, const float* W, const float* H_init, int K,
+                                  int64_t N, int64_t T, int64_t R, const dna_opts* opts,
+                                  float* H_ckpt, uint8_t* sel_ckpt,
+                                  void* ws, size_t ws_bytes, void* aux, size_t aux_bytes, void* stream);
+
+dna_status dna_unrolled_H_bwd_aux(const float* V, const float* W, const float* H_ckpt,
+                                  const uint8_t* sel_ckpt, int K,
+                                  int64_t N, int64_t T, int64_t R, const float* dH_K,
+                                  float* dW, float* dV, float* dH_init, const dna_opts* opts,
+                                  void* ws, size_t ws_bytes, const void* aux, size_t aux_bytes,
+                                  void* stream);
+
 /* ---- Diagnostics ---------------------------------------------------------- */
 
 const char* dna_status_string(dna_status s);

@@ -301,6 +301,12 @@ static dna_status check_dims(int64_t N, int64_t T, int64_t R) {
   return DNA_OK;
 }
 
+static dna_status check_aux(const void* aux, size_t aux_bytes, size_t need) {
+  if (aux_bytes < need) return fail(DNA_EWORKSPACE, "kept-sums buffer smaller than dna_unrolled_aux_bytes()");
+  if ((reinterpret_cast<uintptr_t>(aux) & 255) != 0) return fail(DNA_EINVAL, "kept-sums buffer must be 256-byte aligned");
+  return DNA_OK;
+}
+
 static dna_status check_ws(void* ws, size_t ws_bytes, size_t need) {
   if (!ws) return fail(DNA_EINVAL, "workspace is NULL");
   if (ws_bytes < need) return fail(DNA_EWORKSPACE, "workspace smaller than dna_workspace_bytes()");
@@ -353,19 +359,33 @@ static Scratch16 scratch16(void* ws, const Layout& L, int64_t N, int64_t T, int6
 // `carry`: inside dna_iterate on the tiled fp32 path, Z of the current state is
 // taken from the preceding half-step's cost pass (Algorithm 1 steps 15, 28)
 // instead of being formed again from W H.
+// Where the H step of the tiled fp32 path (R > 64) leaves Z, Q, Q-bar, the
+// split partials of u, u_c, y and the V column sums, for an adjoint that reads
+// them instead of recomputing them (the unrolled forward's kept sums).
+struct AuxOut {
+  float* Z;
+  float* Q;
+  float* Qb;
+  float* pu;
+  float* puc;
+  float* py;
+  double* vpart;
+};
+
 static dna_status run_candidates(int side, const float* V, const float* W, const float* H, int64_t N,
                                  int64_t T, int64_t R, const dna_opts* o, const Layout& L, void* ws,
                                  float* Xmu, float* Xn, float* Aout, float* Bout, int* chk, hipStream_t s,
-                                 const SumJob* pre = nullptr, bool carry = false) {
-  float* Q = at<float>(ws, L.q);
-  float* Qb = at<float>(ws, L.qb);
-  float* pu = at<float>(ws, L.pu);
-  float* puc = at<float>(ws, L.puc);
-  float* py = at<float>(ws, L.py);
+                                 const SumJob* pre = nullptr, bool carry = false, const AuxOut* aux = nullptr) {
+  const bool keep_sums = aux && side == 0 && o->gemm == DNA_GEMM_FP32 && R > FUSED_MAX_R && !carry;
+  float* Q = keep_sums ? aux->Q : at<float>(ws, L.q);
+  float* Qb = keep_sums ? aux->Qb : at<float>(ws, L.qb);
+  float* pu = keep_sums ? aux->pu : at<float>(ws, L.pu);
+  float* puc = keep_sums ? aux->puc : at<float>(ws, L.puc);
+  float* py = keep_sums ? aux->py : at<float>(ws, L.py);
   float* c32 = at<float>(ws, L.c32);
   double* c64 = at<double>(ws, L.c64);
-  double* vpart = at<double>(ws, L.vpart);
-  RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk, nullptr};
+  double* vpart = keep_sums ? aux->vpart : at<double>(ws, L.vpart);
+  RatioArgs ra{V, W, H, N, T, R, Q, Qb, vpart, nullptr, chk, keep_sums ? aux->Z : nullptr};
   if (carry) {
     ra.carry.zd = at<float>(ws, L.zd);
     ra.carry.dz = at<float>(ws, L.dz);
@@ -389,7 +409,7 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
                          damp ? RGH_DNA_COST : RGH_DNA, damp ? at<double>(ws, L.dpart) : nullptr), "rgh_H");
     } else {
       float* cs = at<float>(ws, L.cs);
-      DNA_HIP(launch_ratio(carry ? RM_H_CARRY : RM_H, ra, s), "ratio_H");
+      DNA_HIP(launch_ratio(carry ? RM_H_CARRY : (keep_sums ? RM_ADJ : RM_H), ra, s), "ratio_H");
       if (N >= GH_CHUNK_MIN_K) DNA_HIP(launch_chunk_sums(0, W, N, T, R, cs, s), "chunk_sums_W");
       DNA_HIP(launch_gh_H(W, Q, Qb, N >= GH_CHUNK_MIN_K ? cs : nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc,
                           py, s), "gh_H");
@@ -919,9 +939,48 @@ size_t dna_unrolled_workspace_bytes(int64_t N, int64_t T, int64_t R, const dna_o
   return make_adj_layout(N, T, R).total;
 }
 
-dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_init, int K, int64_t N, int64_t T,
-                              int64_t R, const dna_opts* o, float* H_ckpt, uint8_t* sel_ckpt, void* ws,
-                              size_t ws_bytes, void* stream) {
+// The kept sums of the unrolled forward: per update k, Z, Q, Q-bar (N x T
+// each) and the split partials of u, u_c, y (splits x R x T each), then the V
+// column sums of the ratio pass (the same for every k).  Only the tiled fp32
+// path (R > 64) keeps them; with R <= 64 the adjoint recomputes (fused, cheap).
+struct AuxLayout {
+  size_t z, q, qb, pu, puc, py, step, vpart, total;
+};
+
+static AuxLayout make_aux_layout(int64_t N, int64_t T, int64_t R, int K) {
+  AuxLayout X{};
+  if (R <= FUSED_MAX_R || K <= 0) return X;
+  const Layout L = make_adj_layout(N, T, R).base;
+  const size_t nt = align_up((size_t)N * T * 4), part = align_up((size_t)L.sh.splits * R * T * 4);
+  X.z = 0;
+  X.q = nt;
+  X.qb = 2 * nt;
+  X.pu = 3 * nt;
+  X.puc = 3 * nt + part;
+  X.py = 3 * nt + 2 * part;
+  X.step = 3 * nt + 3 * part;
+  X.vpart = X.step * (size_t)K;
+  X.total = X.vpart + align_up((size_t)L.rt_m * T * 8);
+  return X;
+}
+
+static AuxOut aux_at(void* aux, const AuxLayout& X, int k) {
+  char* b = static_cast<char*>(aux) + X.step * (size_t)k;
+  return AuxOut{reinterpret_cast<float*>(b + X.z), reinterpret_cast<float*>(b + X.q),
+                reinterpret_cast<float*>(b + X.qb), reinterpret_cast<float*>(b + X.pu),
+                reinterpret_cast<float*>(b + X.puc), reinterpret_cast<float*>(b + X.py),
+                reinterpret_cast<double*>(static_cast<char*>(aux) + X.vpart)};
+}
+
+size_t dna_unrolled_aux_bytes(int64_t N, int64_t T, int64_t R, int K, const dna_opts* o) {
+  (void)o;
+  if (N <= 0 || T <= 0 || R <= 0 || K <= 0) return 0;
+  return make_aux_layout(N, T, R, K).total;
+}
+
+static dna_status unrolled_fwd(const float* V, const float* W, const float* H_init, int K, int64_t N, int64_t T,
+                               int64_t R, const dna_opts* o, float* H_ckpt, uint8_t* sel_ckpt, void* ws,
+                               size_t ws_bytes, void* aux, size_t aux_bytes, void* stream) {
   if (!V || !W || !H_init || !H_ckpt || (K > 0 && !sel_ckpt)) return fail(DNA_EINVAL, "NULL argument");
   if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
   DNA_TRY(check_dims(N, T, R));
@@ -931,6 +990,9 @@ dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_ini
   if (o->lambda != 0.f) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint has no lambda terms");
   const AdjLayout A = make_adj_layout(N, T, R);
   DNA_TRY(check_ws(ws, ws_bytes, A.total));
+  const AuxLayout X = make_aux_layout(N, T, R, K);
+  const bool keep = aux != nullptr && X.total > 0;
+  if (keep) DNA_TRY(check_aux(aux, aux_bytes, X.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
   int* chk = o->checked ? at<int>(ws, A.base.check) : nullptr;
   if (chk) {
@@ -945,16 +1007,31 @@ dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_ini
   for (int k = 0; k < K; ++k) {
     const float* Hk = H_ckpt + (int64_t)k * RT;
     float* Hk1 = H_ckpt + (int64_t)(k + 1) * RT;
-    DNA_TRY(run_candidates(0, V, W, Hk, N, T, R, o, A.base, ws, Xmu, Xn, nullptr, nullptr, chk, s));
+    const AuxOut ax = keep ? aux_at(aux, X, k) : AuxOut{};
+    DNA_TRY(run_candidates(0, V, W, Hk, N, T, R, o, A.base, ws, Xmu, Xn, nullptr, nullptr, chk, s, nullptr, false,
+                           keep ? &ax : nullptr));
     DNA_TRY(run_select(0, V, W, Xmu, Xn, Hk1, N, T, R, o, A.base, ws, sel_ckpt + (int64_t)k * T, nullptr, nullptr, s));
   }
   if (chk) return checked_end(chk, s);
   return DNA_OK;
 }
 
-dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckpt, const uint8_t* sel_ckpt, int K,
-                              int64_t N, int64_t T, int64_t R, const float* dH_K, float* dW, float* dV,
-                              float* dH_init, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+dna_status dna_unrolled_H_fwd(const float* V, const float* W, const float* H_init, int K, int64_t N, int64_t T,
+                              int64_t R, const dna_opts* o, float* H_ckpt, uint8_t* sel_ckpt, void* ws,
+                              size_t ws_bytes, void* stream) {
+  return unrolled_fwd(V, W, H_init, K, N, T, R, o, H_ckpt, sel_ckpt, ws, ws_bytes, nullptr, 0, stream);
+}
+
+dna_status dna_unrolled_H_fwd_aux(const float* V, const float* W, const float* H_init, int K, int64_t N, int64_t T,
+                                  int64_t R, const dna_opts* o, float* H_ckpt, uint8_t* sel_ckpt, void* ws,
+                                  size_t ws_bytes, void* aux, size_t aux_bytes, void* stream) {
+  return unrolled_fwd(V, W, H_init, K, N, T, R, o, H_ckpt, sel_ckpt, ws, ws_bytes, aux, aux_bytes, stream);
+}
+
+static dna_status unrolled_bwd(const float* V, const float* W, const float* H_ckpt, const uint8_t* sel_ckpt, int K,
+                               int64_t N, int64_t T, int64_t R, const float* dH_K, float* dW, float* dV,
+                               float* dH_init, const dna_opts* o, void* ws, size_t ws_bytes, const void* aux,
+                               size_t aux_bytes, void* stream) {
   if (!V || !W || !H_ckpt || !dH_K || !dW || !dV || (K > 0 && !sel_ckpt)) return fail(DNA_EINVAL, "NULL argument");
   if (K < 0) return fail(DNA_EINVAL, "K must be >= 0");
   DNA_TRY(check_dims(N, T, R));
@@ -964,6 +1041,9 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
   if (o->lambda != 0.f) return fail(DNA_EUNSUPPORTED, "the unrolled adjoint has no lambda terms");
   const AdjLayout A = make_adj_layout(N, T, R);
   DNA_TRY(check_ws(ws, ws_bytes, A.total));
+  const AuxLayout X = make_aux_layout(N, T, R, K);
+  const bool kept = aux != nullptr && X.total > 0;
+  if (kept) DNA_TRY(check_aux(aux, aux_bytes, X.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Layout& L = A.base;
   const int64_t RT = R * T;
@@ -973,14 +1053,8 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
     if (dH_init) DNA_HIP(launch_copy(dH_K, dH_init, RT, s), "copy");
     return DNA_OK;
   }
-  float* Q = at<float>(ws, L.q);
-  float* Qb = at<float>(ws, L.qb);
-  float* pu = at<float>(ws, L.pu);
-  float* puc = at<float>(ws, L.puc);
-  float* py = at<float>(ws, L.py);
+  float* wpu = at<float>(ws, L.pu);
   float* c32 = at<float>(ws, L.c32);
-  double* vpart = at<double>(ws, L.vpart);
-  float* Z = at<float>(ws, A.z);
   float* Zbar = at<float>(ws, A.zbar);
   float* Ub = at<float>(ws, A.ubar);
   float* Yb = at<float>(ws, A.ybar);
@@ -997,31 +1071,42 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
     DNA_HIP(launch_colsum_part(W, N, R, at<double>(ws, L.sump), job, s), "colsum_W");
     job.s32 = c32;
     DNA_HIP(launch_sum_final(job, s), "sum_final");
-    if (R > FUSED_MAX_R && N >= GH_CHUNK_MIN_K) DNA_HIP(launch_chunk_sums(0, W, N, T, R, cs, s), "chunk_sums_W");
+    if (!kept && R > FUSED_MAX_R && N >= GH_CHUNK_MIN_K) DNA_HIP(launch_chunk_sums(0, W, N, T, R, cs, s), "chunk_sums_W");
   }
   const float* Gin = dH_K;
   for (int k = K - 1; k >= 0; --k) {
     const float* Hk = H_ckpt + (int64_t)k * RT;
     const int acc = k != K - 1;
     float* Gout = (k == 0) ? dH_init : G[k & 1];
-    RatioArgs ra{V, W, Hk, N, T, R, Q, Qb, vpart, nullptr, nullptr, Z};
-    DNA_HIP(launch_ratio(RM_ADJ, ra, s), "ratio_adj");
-    // u, u_c, y and the V sums from the product path and split the forward's
-    // run_candidates took, so that every branch of the candidate arithmetic
-    // (gain form, floor, cap, value floor) repeats bit for bit
+    // Z, Q, Q-bar, u, u_c, y and the V sums of the forward's update k: kept
+    // by the forward, or recomputed on the product path and split the
+    // forward's run_candidates took, so that every branch of the candidate
+    // arithmetic (gain form, floor, cap, value floor) repeats bit for bit
+    float *Z, *Q, *Qb, *pu, *puc, *py;
+    double* vpart;
     int sp = L.sh.splits, vtiles = L.rt_m;
-    if (R <= FUSED_MAX_R) {
-      DNA_HIP(launch_rgh(0, V, W, Hk, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, SumJob{}, nullptr, s),
-              "rgh_H");
-      sp = L.shf.splits;
-      vtiles = L.shf.splits;
+    if (kept) {
+      const AuxOut ax = aux_at(const_cast<void*>(aux), X, k);
+      Z = ax.Z; Q = ax.Q; Qb = ax.Qb; pu = ax.pu; puc = ax.puc; py = ax.py; vpart = ax.vpart;
+      if (sp > 8 && T < 256 * 32) sp = 1;              // the forward folded them into split 0
     } else {
-      DNA_HIP(launch_gh_H(W, Q, Qb, N >= GH_CHUNK_MIN_K ? cs : nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, puc,
-                          py, s), "gh_H");
-    }
-    if (sp > 8 && T < 256 * 32) {
-      DNA_HIP(launch_fold_splits(pu, puc, py, sp, R * T, s), "fold_splits");
-      sp = 1;
+      Z = at<float>(ws, A.z); Q = at<float>(ws, L.q); Qb = at<float>(ws, L.qb);
+      pu = wpu; puc = at<float>(ws, L.puc); py = at<float>(ws, L.py); vpart = at<double>(ws, L.vpart);
+      RatioArgs ra{V, W, Hk, N, T, R, Q, Qb, vpart, nullptr, nullptr, Z};
+      DNA_HIP(launch_ratio(RM_ADJ, ra, s), "ratio_adj");
+      if (R <= FUSED_MAX_R) {
+        DNA_HIP(launch_rgh(0, V, W, Hk, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, SumJob{}, nullptr,
+                           s), "rgh_H");
+        sp = L.shf.splits;
+        vtiles = L.shf.splits;
+      } else {
+        DNA_HIP(launch_gh_H(W, Q, Qb, N >= GH_CHUNK_MIN_K ? cs : nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu,
+                            puc, py, s), "gh_H");
+      }
+      if (sp > 8 && T < 256 * 32) {
+        DNA_HIP(launch_fold_splits(pu, puc, py, sp, R * T, s), "fold_splits");
+        sp = 1;
+      }
     }
     DNA_HIP(launch_cand_bwd_H(Hk, pu, puc, py, sp, c32, vpart, vtiles, T, R, o->eps, o->alpha,
                               sel_ckpt + (int64_t)k * T, Gin, Ub, Yb, Hd, Cb, sbar, s), "cand_bwd_H");
@@ -1035,13 +1120,28 @@ dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckp
     DNA_HIP(launch_wbar(Q, Zbar, Qb, Ub, Hk, Yb, N, T, R, A.swb.splits, A.swb.kchunk, p0, p1, s), "wbar");
     DNA_HIP(launch_dw_final(W, p0, p1, A.swb.splits, cbar64, N, R, dW, acc, s), "dw_final");
     if (Gout) {
-      DNA_HIP(launch_gh_H(W, Zbar, nullptr, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, pu, nullptr, nullptr, s),
+      DNA_HIP(launch_gh_H(W, Zbar, nullptr, nullptr, N, T, R, L.sh.splits, L.sh.kchunk, wpu, nullptr, nullptr, s),
               "gh_zbar");
-      DNA_HIP(launch_dh_final(Hd, pu, L.sh.splits, R, T, Gout, s), "dh_final");
+      DNA_HIP(launch_dh_final(Hd, wpu, L.sh.splits, R, T, Gout, s), "dh_final");
     }
     Gin = Gout;
   }
   return DNA_OK;
+}
+
+dna_status dna_unrolled_H_bwd(const float* V, const float* W, const float* H_ckpt, const uint8_t* sel_ckpt, int K,
+                              int64_t N, int64_t T, int64_t R, const float* dH_K, float* dW, float* dV,
+                              float* dH_init, const dna_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  return unrolled_bwd(V, W, H_ckpt, sel_ckpt, K, N, T, R, dH_K, dW, dV, dH_init, o, ws, ws_bytes, nullptr, 0,
+                      stream);
+}
+
+dna_status dna_unrolled_H_bwd_aux(const float* V, const float* W, const float* H_ckpt, const uint8_t* sel_ckpt,
+                                  int K, int64_t N, int64_t T, int64_t R, const float* dH_K, float* dW, float* dV,
+                                  float* dH_init, const dna_opts* o, void* ws, size_t ws_bytes, const void* aux,
+                                  size_t aux_bytes, void* stream) {
+  return unrolled_bwd(V, W, H_ckpt, sel_ckpt, K, N, T, R, dH_K, dW, dV, dH_init, o, ws, ws_bytes, aux, aux_bytes,
+                      stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -87,6 +87,11 @@ _lib_select = _decl("dna_select", _int, _int, _p, _p, _p, _p, _p, _i64, _i64, _i
 _lib_ufwd = _decl("dna_unrolled_H_fwd", _int, _p, _p, _p, _int, _i64, _i64, _i64, _OP, _p, _p, _p, _sz, _p)
 _lib_ubwd = _decl("dna_unrolled_H_bwd", _int, _p, _p, _p, _p, _int, _i64, _i64, _i64, _p, _p, _p, _p,
                   _OP, _p, _sz, _p)
+_lib_uaux = _decl("dna_unrolled_aux_bytes", _sz, _i64, _i64, _i64, _int, _OP)
+_lib_ufwd_aux = _decl("dna_unrolled_H_fwd_aux", _int, _p, _p, _p, _int, _i64, _i64, _i64, _OP, _p, _p, _p, _sz,
+                      _p, _sz, _p)
+_lib_ubwd_aux = _decl("dna_unrolled_H_bwd_aux", _int, _p, _p, _p, _p, _int, _i64, _i64, _i64, _p, _p, _p, _p,
+                      _OP, _p, _sz, _p, _sz, _p)
 _lib_status_string = _decl("dna_status_string", ctypes.c_char_p, _int)
 _lib_last_error = _decl("dna_last_error", ctypes.c_char_p)
 _lib_prof_enable = _decl("dna_profile_enable", None, _int)
@@ -99,6 +104,7 @@ EXPORTED = [
     "dna_iterate", "dna_iterate_noalloc", "dna_sparse_workspace_bytes", "dna_sparse_update_H", "dna_sparse_update_W",
     "dna_sparse_kl_cost", "dna_sparse_mu_update", "dna_sparse_mu_iterate", "dna_sparse_iterate", "mu_update", "mu_iterate", "kl_cost", "dna_gradient_hessian", "dna_candidates", "dna_select",
     "dna_unrolled_workspace_bytes", "dna_unrolled_H_fwd", "dna_unrolled_H_bwd",
+    "dna_unrolled_aux_bytes", "dna_unrolled_H_fwd_aux", "dna_unrolled_H_bwd_aux",
     "dna_status_string", "dna_last_error", "dna_profile_enable", "dna_profile_reset",
     "dna_profile_read", "dna_build_info",
 ]
@@ -336,20 +342,35 @@ def select(side, V, F, X_mu, X_newton, **kw):
 
 # --------------------------------------------------------------------------- unrolled H-solve
 
-def unrolled_forward(V, W, H_init, K, **kw):
-    """K DNA H-updates with W fixed.  Returns (H_ckpt [K+1,R,T], sel [K,T])."""
+def unrolled_forward(V, W, H_init, K, keep_sums=False, **kw):
+    """K DNA H-updates with W fixed.  Returns (H_ckpt [K+1,R,T], sel [K,T]), and
+    with keep_sums=True also the kept-sums buffer (a uint8 tensor, or None where
+    the library keeps none) for unrolled_backward(..., aux=...)."""
     N, T, R = _dims(V, W, H_init)
     o = make_opts(**kw)
     ws, nb = workspace(N, T, R, o, unrolled=True)
     H_ckpt = torch.empty((K + 1, R, T), dtype=torch.float32, device=V.device)
     sel = torch.empty((max(K, 1), T), dtype=torch.uint8, device=V.device)
-    _check(_lib_ufwd(_ptr(V), _ptr(W), _ptr(H_init), int(K), N, T, R, ctypes.byref(o), _ptr(H_ckpt),
-                     _ptr(sel), _ptr(ws), ws.numel(), _stream()))
+    aux = None
+    if keep_sums:
+        ab = int(_lib_uaux(N, T, R, int(K), ctypes.byref(o)))
+        if ab > 0:
+            aux = torch.empty(ab, dtype=torch.uint8, device=V.device)
+    if aux is None:
+        _check(_lib_ufwd(_ptr(V), _ptr(W), _ptr(H_init), int(K), N, T, R, ctypes.byref(o), _ptr(H_ckpt),
+                         _ptr(sel), _ptr(ws), ws.numel(), _stream()))
+    else:
+        _check(_lib_ufwd_aux(_ptr(V), _ptr(W), _ptr(H_init), int(K), N, T, R, ctypes.byref(o), _ptr(H_ckpt),
+                             _ptr(sel), _ptr(ws), ws.numel(), _ptr(aux), aux.numel(), _stream()))
+    if keep_sums:
+        return H_ckpt, sel[:K], aux
     return H_ckpt, sel[:K]
 
 
-def unrolled_backward(V, W, H_ckpt, sel, K, dH_K, want_dH_init=True, **kw):
-    """Vector-Jacobian product of the K updates: returns (dW, dV, dH_init)."""
+def unrolled_backward(V, W, H_ckpt, sel, K, dH_K, want_dH_init=True, aux=None, **kw):
+    """Vector-Jacobian product of the K updates: returns (dW, dV, dH_init).
+    `aux`: the kept sums of unrolled_forward(..., keep_sums=True) for the same
+    inputs (the backward then reads them instead of recomputing them)."""
     N, T = V.shape
     R = W.shape[1]
     _mat(V, "V")
@@ -363,8 +384,13 @@ def unrolled_backward(V, W, H_ckpt, sel, K, dH_K, want_dH_init=True, **kw):
     dV = torch.empty((N, T), dtype=torch.float32, device=V.device)
     dH0 = torch.empty((R, T), dtype=torch.float32, device=V.device) if want_dH_init else None
     sel = sel.contiguous()
-    _check(_lib_ubwd(_ptr(V), _ptr(W), _ptr(H_ckpt), _ptr(sel), int(K), N, T, R, _ptr(dH_K), _ptr(dW), _ptr(dV),
-                     _ptr(dH0), ctypes.byref(o), _ptr(ws), ws.numel(), _stream()))
+    if aux is None:
+        _check(_lib_ubwd(_ptr(V), _ptr(W), _ptr(H_ckpt), _ptr(sel), int(K), N, T, R, _ptr(dH_K), _ptr(dW),
+                         _ptr(dV), _ptr(dH0), ctypes.byref(o), _ptr(ws), ws.numel(), _stream()))
+    else:
+        _check(_lib_ubwd_aux(_ptr(V), _ptr(W), _ptr(H_ckpt), _ptr(sel), int(K), N, T, R, _ptr(dH_K), _ptr(dW),
+                             _ptr(dV), _ptr(dH0), ctypes.byref(o), _ptr(ws), ws.numel(), _ptr(aux), aux.numel(),
+                             _stream()))
     return dW, dV, dH0
 
 
@@ -376,8 +402,9 @@ class DNAUnrolledH(torch.autograd.Function):
     @staticmethod
     def forward(ctx, W, V, H_init, K, eps=0.01, alpha=4.0):
         W, V, H_init = W.detach().contiguous(), V.detach().contiguous(), H_init.detach().contiguous()
-        H_ckpt, sel = unrolled_forward(V, W, H_init, K, eps=eps, alpha=alpha)
+        H_ckpt, sel, aux = unrolled_forward(V, W, H_init, K, keep_sums=True, eps=eps, alpha=alpha)
         ctx.save_for_backward(W, V, H_ckpt, sel)
+        ctx.aux = aux                     # the forward's kept sums (None where none are kept)
         ctx.K, ctx.eps, ctx.alpha = K, eps, alpha
         return H_ckpt[K].clone()
 
@@ -385,7 +412,9 @@ class DNAUnrolledH(torch.autograd.Function):
     def backward(ctx, gH):
         W, V, H_ckpt, sel = ctx.saved_tensors
         dW, dV, dH0 = unrolled_backward(V, W, H_ckpt, sel, ctx.K, gH.contiguous().float(),
-                                        want_dH_init=ctx.needs_input_grad[2], eps=ctx.eps, alpha=ctx.alpha)
+                                        want_dH_init=ctx.needs_input_grad[2], aux=ctx.aux, eps=ctx.eps,
+                                        alpha=ctx.alpha)
+        ctx.aux = None
         return (dW if ctx.needs_input_grad[0] else None, dV if ctx.needs_input_grad[1] else None,
                 dH0, None, None, None)
 

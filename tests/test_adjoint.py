@@ -194,6 +194,35 @@ def test_gpu_adjoint_k0(dna):
     assert torch.equal(dH, g)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(300, 512, 96), (2600, 150, 80), (200, 300, 20)])
+def test_gpu_adjoint_kept_sums(dna, shape):
+    """The forward that keeps Z, Q, Q-bar and the gradient sums of every update
+    (dna_unrolled_H_fwd_aux) gives the same checkpoints as the plain forward, and
+    the backward that reads them (dna_unrolled_H_bwd_aux) the same gradients,
+    bit for bit, as the backward that recomputes them on the forward's product
+    path.  Shapes: one split, ten splits folded into one (T < 8192), and R <= 64
+    (no sums kept: the calls behave as the plain ones)."""
+    N, T, R = shape
+    K = 3
+    print(f"kept sums N={N} T={T} R={R} K={K}", flush=True)
+    rng = np.random.default_rng(N + T + R)
+    W = rng.gamma(0.5, 1.0, (N, R)) + 0.05
+    H0 = rng.gamma(0.5, 1.0, (R, T))
+    V = rng.poisson(W @ H0 * 3.0).astype(float) + 0.5
+    cuda = lambda x: torch.tensor(np.asarray(x, dtype=np.float32), device="cuda")
+    Vg, Wg, Hg = cuda(V), cuda(W), cuda(rng.uniform(0.1, 1.0, (R, T)))
+    Hc, sel, aux = dna.unrolled_forward(Vg, Wg, Hg, K, keep_sums=True)
+    Hc2, sel2 = dna.unrolled_forward(Vg, Wg, Hg, K)
+    assert (aux is not None) == (R > 64)
+    assert torch.equal(Hc, Hc2) and torch.equal(sel, sel2)
+    G = cuda(rng.standard_normal((R, T)))
+    a = dna.unrolled_backward(Vg, Wg, Hc, sel, K, G, aux=aux)
+    b = dna.unrolled_backward(Vg, Wg, Hc, sel, K, G)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
 def _near_kink_columns(V, W, Hk, sel, eps=oracle.EPS, alpha=oracle.ALPHA, delta=3e-5):
     """Newton columns of one H-update (FP64, from Hk) with an entry near a point
     where the update's derivative jumps: the eps floor of the gain (eq. 15:
