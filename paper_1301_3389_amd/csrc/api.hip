@@ -77,25 +77,12 @@ void prof_end(const char* name, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Workspace layout (one layout serves every forward entry point).
 // ---------------------------------------------------------------------------
-constexpr int64_t TARGET_WG = 512;     // aim for this many workgroups in split GEMMs
 constexpr int64_t MIN_KCHUNK = 256;    // never split the contraction finer than this
 
 struct Split {
   int splits;
   int64_t kchunk;
 };
-
-static Split choose_split(int64_t K, int64_t base_tiles) {
-  int64_t sp = std::max<int64_t>(1, cdiv(TARGET_WG, std::max<int64_t>(1, base_tiles)));
-  sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / MIN_KCHUNK));
-  sp = std::min<int64_t>(sp, 1024);
-  // multiple of 32: the K-tile of the 16-bit kernels (and two of the fp32 ones)
-  int64_t kchunk = cdiv(cdiv(K, sp), 32) * 32;
-  Split s;
-  s.kchunk = kchunk;
-  s.splits = (int)cdiv(K, kchunk);
-  return s;
-}
 
 // Split-K for a product of base_tiles output tiles of which `slots` workgroups
 // run at once (CUs x workgroups per CU): the split whose rounds of resident
@@ -241,7 +228,7 @@ struct AdjLayout {
 static AdjLayout make_adj_layout(int64_t N, int64_t T, int64_t R) {
   AdjLayout A;
   A.base = make_layout(N, T, R, false, true);
-  A.swb = choose_split(T, cdiv(R, WB_BN) * cdiv(N, WB_BM));
+  A.swb = wave_split(T, cdiv(R, WB_BN) * cdiv(N, WB_BM), 3 * 256, 32);   // three k_wbar workgroups fit a CU
   size_t off = A.base.total;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   const size_t nt = (size_t)N * T, rt = (size_t)R * T, nr = (size_t)N * R;

@@ -99,78 +99,16 @@ __device__ __forceinline__ Sums split_sums(const float* pu, const float* puc, co
   return s;
 }
 
-template <int BW_COLS, int BW_RG>
-__global__ __launch_bounds__(BW_COLS * BW_RG) void k_cand_bwd_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
-                                                    const float* c, const double* vpart, int tiles_m, int64_t T,
-                                                    int64_t R, float eps, float alpha, const uint8_t* sel,
-                                                    const float* G, float* Ubar, float* Ybar, float* Hd,
-                                                    float* Cbar, float* sbar) {
-  __shared__ double red[BW_RG][BW_COLS];
-  __shared__ double kap[BW_COLS], bet[BW_COLS];
-  const int tid = threadIdx.x, cl = tid % BW_COLS, rg = tid / BW_COLS;
-  const int64_t t = (int64_t)blockIdx.x * BW_COLS + cl;
-  const bool ok = t < T;
-  const bool newton = ok && sel[t] != 0;
-  // pass 1: D = sum_r c_r p_r (the renormalisation denominator of eq. 10)
-  double D = 0.0;
-  if (newton) {
-    for (int64_t r = rg; r < R; r += BW_RG) {
-      const Sums q = split_sums(pu, puc, py, splits, R, T, r, t);
-      const float cr = c[r];
-      float g, A;
-      gain_bwd(q.u, q.uc, cr, g, A);
-      D += (double)cr * (double)newton_deriv(H[r * T + t], A, q.y / cr, eps, alpha).p;
-    }
-  }
-  red[rg][cl] = D;
-  __syncthreads();
-  if (rg == 0) {
-    double d = 0.0, kappa = 1.0;
-    if (newton) {
-      for (int k = 0; k < BW_RG; ++k) d += red[k][cl];
-      if (d > 0.0) {
-        double s = 0.0;
-        for (int m = 0; m < tiles_m; ++m) s += vpart[(int64_t)m * T + t];
-        kappa = s / d;
-      }
-    }
-    kap[cl] = kappa;
-    bet[cl] = d;          // keeps D for pass 2
-  }
-  __syncthreads();
-  const double kappa = kap[cl], Dsum = bet[cl];
-  // pass 2: beta = sum over unclamped r of G_r p_r / D
-  double GP = 0.0;
-  if (newton && Dsum > 0.0) {
-    for (int64_t r = rg; r < R; r += BW_RG) {
-      const Sums q = split_sums(pu, puc, py, splits, R, T, r, t);
-      const float cr = c[r];
-      float g, A;
-      gain_bwd(q.u, q.uc, cr, g, A);
-      const float p = newton_deriv(H[r * T + t], A, q.y / cr, eps, alpha).p;
-      if (!((float)((double)p * kappa) < VALUE_FLOOR)) GP += (double)G[r * T + t] * (double)p;
-    }
-  }
-  __syncthreads();
-  red[rg][cl] = GP;
-  __syncthreads();
-  if (rg == 0) {
-    double b = 0.0;
-    if (newton && Dsum > 0.0) {
-      for (int k = 0; k < BW_RG; ++k) b += red[k][cl];
-      b /= Dsum;
-    }
-    bet[cl] = b;
-  }
-  __syncthreads();
-  if (!ok) return;
-  const double beta = bet[cl];
-  const bool renorm = newton && Dsum > 0.0;
-  if (rg == 0) sbar[t] = renorm ? (float)beta : 0.f;
-  // pass 3: per-entry adjoints
-  for (int64_t r = rg; r < R; r += BW_RG) {
+// One entry (r, t) of the per-column adjoint (pass 3 of k_cand_bwd_H), with G
+// at (r, t) given.
+__device__ __forceinline__ void cand_bwd_entry(const float* pu, const float* puc, const float* py, int splits,
+                                               int64_t R, int64_t T, int64_t r, int64_t t, const float* c,
+                                               const float* H, float gr, float eps, float alpha, bool newton,
+                                               bool renorm, double kappa, double beta, float* Ubar, float* Ybar,
+                                               float* Hd, float* Cbar) {
+  {
     const Sums q = split_sums(pu, puc, py, splits, R, T, r, t);
-    const float cr = c[r], x = H[r * T + t], gr = G[r * T + t];
+    const float cr = c[r], x = H[r * T + t];
     float g, A;
     gain_bwd(q.u, q.uc, cr, g, A);
     float ub, yb, hd, cb;
@@ -197,6 +135,120 @@ __global__ __launch_bounds__(BW_COLS * BW_RG) void k_cand_bwd_H(const float* H, 
     Hd[r * T + t] = hd;
     Cbar[r * T + t] = cb;
   }
+}
+
+template <int BW_COLS, int BW_RG>
+__global__ __launch_bounds__(BW_COLS * BW_RG) void k_cand_bwd_H(const float* H, const float* pu, const float* puc, const float* py, int splits,
+                                                    const float* c, const double* vpart, int tiles_m, int64_t T,
+                                                    int64_t R, float eps, float alpha, const uint8_t* sel,
+                                                    const float* G, float* Ubar, float* Ybar, float* Hd,
+                                                    float* Cbar, float* sbar) {
+  __shared__ double red[BW_RG][BW_COLS];
+  __shared__ double kap[BW_COLS], bet[BW_COLS];
+  const int tid = threadIdx.x, cl = tid % BW_COLS, rg = tid / BW_COLS;
+  const int64_t t = (int64_t)blockIdx.x * BW_COLS + cl;
+  const bool ok = t < T;
+  const bool newton = ok && sel[t] != 0;
+  // pass 1: D = sum_r c_r p_r (the renormalisation denominator of eq. 10).
+  // With at most CI rows per thread, p and G stay in registers from pass to
+  // pass (pass 2 then reads only G, pass 3 not G); the sums are the same.
+  constexpr int CI = 32;
+  const bool cache = (R + BW_RG - 1) / BW_RG <= CI;
+  float pc[CI], gc[CI];
+  double D = 0.0;
+  if (newton) {
+    if (cache) {
+#pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        const int64_t r = rg + (int64_t)i * BW_RG;
+        pc[i] = 0.f;
+        if (r < R) {
+          const Sums q = split_sums(pu, puc, py, splits, R, T, r, t);
+          const float cr = c[r];
+          float g, A;
+          gain_bwd(q.u, q.uc, cr, g, A);
+          pc[i] = newton_deriv(H[r * T + t], A, q.y / cr, eps, alpha).p;
+          D += (double)cr * (double)pc[i];
+        }
+      }
+    } else {
+      for (int64_t r = rg; r < R; r += BW_RG) {
+        const Sums q = split_sums(pu, puc, py, splits, R, T, r, t);
+        const float cr = c[r];
+        float g, A;
+        gain_bwd(q.u, q.uc, cr, g, A);
+        D += (double)cr * (double)newton_deriv(H[r * T + t], A, q.y / cr, eps, alpha).p;
+      }
+    }
+  }
+  red[rg][cl] = D;
+  __syncthreads();
+  if (rg == 0) {
+    double d = 0.0, kappa = 1.0;
+    if (newton) {
+      for (int k = 0; k < BW_RG; ++k) d += red[k][cl];
+      if (d > 0.0) {
+        double s = 0.0;
+        for (int m = 0; m < tiles_m; ++m) s += vpart[(int64_t)m * T + t];
+        kappa = s / d;
+      }
+    }
+    kap[cl] = kappa;
+    bet[cl] = d;          // keeps D for pass 2
+  }
+  __syncthreads();
+  const double kappa = kap[cl], Dsum = bet[cl];
+  // pass 2: beta = sum over unclamped r of G_r p_r / D
+  double GP = 0.0;
+  if (newton && Dsum > 0.0) {
+    if (cache) {
+#pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        const int64_t r = rg + (int64_t)i * BW_RG;
+        if (r < R) {
+          gc[i] = G[r * T + t];
+          if (!((float)((double)pc[i] * kappa) < VALUE_FLOOR)) GP += (double)gc[i] * (double)pc[i];
+        }
+      }
+    } else {
+      for (int64_t r = rg; r < R; r += BW_RG) {
+        const Sums q = split_sums(pu, puc, py, splits, R, T, r, t);
+        const float cr = c[r];
+        float g, A;
+        gain_bwd(q.u, q.uc, cr, g, A);
+        const float p = newton_deriv(H[r * T + t], A, q.y / cr, eps, alpha).p;
+        if (!((float)((double)p * kappa) < VALUE_FLOOR)) GP += (double)G[r * T + t] * (double)p;
+      }
+    }
+  }
+  __syncthreads();
+  red[rg][cl] = GP;
+  __syncthreads();
+  if (rg == 0) {
+    double b = 0.0;
+    if (newton && Dsum > 0.0) {
+      for (int k = 0; k < BW_RG; ++k) b += red[k][cl];
+      b /= Dsum;
+    }
+    bet[cl] = b;
+  }
+  __syncthreads();
+  if (!ok) return;
+  const double beta = bet[cl];
+  const bool renorm = newton && Dsum > 0.0;
+  if (rg == 0) sbar[t] = renorm ? (float)beta : 0.f;
+  // pass 3: per-entry adjoints
+  const bool gcached = cache && newton && Dsum > 0.0;
+#pragma unroll
+  for (int i = 0; i < CI; ++i) {
+    const int64_t r = rg + (int64_t)i * BW_RG;
+    if (cache && r < R) cand_bwd_entry(pu, puc, py, splits, R, T, r, t, c, H, gcached ? gc[i] : G[r * T + t], eps,
+                                       alpha, newton, renorm, kappa, beta, Ubar, Ybar, Hd, Cbar);
+  }
+  if (!cache)
+    for (int64_t r = rg; r < R; r += BW_RG)
+      cand_bwd_entry(pu, puc, py, splits, R, T, r, t, c, H, G[r * T + t], eps, alpha, newton, renorm, kappa, beta,
+                     Ubar, Ybar, Hd, Cbar);
 }
 
 hipError_t launch_cand_bwd_H(const float* H, const float* pu, const float* puc, const float* py, int splits, const float* c,
