@@ -30,6 +30,8 @@ SHAPES = [
     (2600, 150, 80, 0.1, 13),    # many contraction splits over few columns: folded before the candidates
     (2600, 150, 40, 0.1, 14),    # the same through the fused kernels: 41 cost partials per column
     (2100, 2300, 96, 0.1, 15),   # contractions of >= 2048 indices both ways: chunked gradient sums
+    (64, 16384, 200, 0.1, 16),   # 128 < R <= 512 over whole rounds of 1024-thread blocks: the H-side
+                                 # candidates keep 16 rows per thread in registers (R ragged)
 ]
 
 
