@@ -397,16 +397,17 @@ __global__ __launch_bounds__(256) void k_chunk_sums_W(const float* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_chunk_sums_H(const float* __restrict__ H, int64_t T, int64_t R, int64_t Rp,
                                                       int64_t nchunks, float* __restrict__ cs) {
-  // one half-wave per (chunk, r): a value per lane, then a fixed-order sum
-  static_assert(GH_CHUNK == 32, "a chunk is one half-wave");
-  const int lane = threadIdx.x & 31;
-  const int64_t item = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
+  // GH_CHUNK lanes (a half-wave or a wave) per (chunk, r): a value per lane,
+  // then a fixed-order sum
+  static_assert(GH_CHUNK == 32 || GH_CHUNK == 64, "a chunk is a half-wave or a wave");
+  const int lane = threadIdx.x & (GH_CHUNK - 1);
+  const int64_t item = (int64_t)blockIdx.x * (256 / GH_CHUNK) + threadIdx.x / GH_CHUNK;
   const bool ok = item < nchunks * Rp;
   const int64_t r = ok ? item / nchunks : 0, c = ok ? item % nchunks : 0;
   const int64_t t = c * GH_CHUNK + lane;
   double s = (ok && r < R && t < T) ? (double)H[r * T + t] : 0.0;
 #pragma unroll
-  for (int m = 16; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+  for (int m = GH_CHUNK / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m);
   if (ok && lane == 0) cs[c * Rp + r] = (float)s;
 }
 
@@ -418,7 +419,8 @@ hipError_t launch_chunk_sums(int side, const float* F, int64_t N, int64_t T, int
                        F, N, R, Rp, cs);
   } else {
     const int64_t nc = cdiv(T, GH_CHUNK);
-    hipLaunchKernelGGL(k_chunk_sums_H, dim3((unsigned)cdiv(nc * Rp, 8)), dim3(256), 0, s, F, T, R, Rp, nc, cs);
+    hipLaunchKernelGGL(k_chunk_sums_H, dim3((unsigned)cdiv(nc * Rp, 256 / GH_CHUNK)), dim3(256), 0, s, F, T, R, Rp,
+                       nc, cs);
   }
   prof_end("chunk_sums", s);
   return hipGetLastError();
