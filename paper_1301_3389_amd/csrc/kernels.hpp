@@ -109,7 +109,7 @@ hipError_t launch_ratio(RatioMode mode, const RatioArgs& a, hipStream_t s);
 // 2^-24 times the partial sums of w (q - 1), which stay small near a fixed
 // point; the chunk form is used for contractions of at least GH_CHUNK_MIN_K
 // indices.  See the candidate kernels for which form of the gain is used where.
-constexpr int64_t GH_CHUNK = 32;
+constexpr int64_t GH_CHUNK = 64;
 constexpr int64_t GH_CHUNK_MIN_K = 2048;
 hipError_t launch_chunk_sums(int side, const float* F, int64_t N, int64_t T, int64_t R, float* cs, hipStream_t s);
 hipError_t launch_gh_H(const float* W, const float* Q, const float* Qb, const float* cs, int64_t N, int64_t T,
