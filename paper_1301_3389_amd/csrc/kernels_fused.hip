@@ -266,16 +266,22 @@ __global__ __launch_bounds__(256, 2) void k_rgh_H(const float* V, const float* W
 //   phase 1: Z[n][t] = sum_r lw[n][r] lh[r][t]      (wave block n = wm, t = wn)
 //   phase 2: acc[n][r] += sum_t {Q, Q - 1, Q-bar lh[r][t]}[n][t] lh[r][t]  (n = wm, r = wn)
 // ---------------------------------------------------------------------------
-template <bool CHK, int MODE>
+// CH (DNA modes, R > 32, T >= GH_CHUNK_MIN_K): u_c = sum over the 64-column
+// sub-tiles of (sum of q h) - (sum of h), the sub-tile sums of the rows of H
+// formed in float64 from the LDS tile; two product chains instead of three
+// (the chunked gradient sums of the tiled kernels, chunks of one sub-tile).
+template <bool CHK, int MODE, bool CH>
 __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W, const float* H, int64_t N,
                                                   int64_t T, int64_t R, int64_t tchunk, float* pu, float* puc,
                                                   float* py, double* vpart, double* dpart, SumJob fin, int* check) {
   constexpr bool DNA = MODE == RGH_DNA || MODE == RGH_DNA_COST;
-  constexpr int NA = DNA ? 3 : 1;
+  static_assert(!CH || DNA, "the chunked sums are a DNA form");
+  constexpr int NA = DNA ? (CH ? 2 : 3) : 1;
   constexpr int NQ = MODE == RGH_DNA_COST ? 2 : 1;
   __shared__ __align__(16) float lw[FT];
   __shared__ __align__(16) float lh[FT];
   __shared__ __align__(16) float lq[DNA ? 2 : 1][FT];
+  __shared__ float csk[CH ? 64 : 1];
   sum_job(fin);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave: scalar loop bounds
@@ -292,6 +298,9 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   for (int c = 0; c < NA; ++c)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
+  float ur[CH ? 16 : 1], ucr[CH ? 16 : 1];
+#pragma unroll
+  for (int v = 0; v < (CH ? 16 : 1); ++v) ur[v] = ucr[v] = 0.f;
   double rp[NQ][GF::FM][16];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -351,6 +360,18 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
         rp[0][0][v] += (double)(x * log2_hw(x > 0.f ? q : 1.f)) * LN2;
       }
     }
+    if constexpr (CH) {   // sum over this sub-tile's 64 columns of each row r of H (zeros past T and R)
+      const int r = tid >> 2, qd = tid & 3;
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f32x4 h4 = ld4(lh + r * FP + 16 * qd + 4 * j);
+        a += ((double)h4[0] + (double)h4[1]) + ((double)h4[2] + (double)h4[3]);
+      }
+      a += __shfl_xor(a, 1);
+      a += __shfl_xor(a, 2);
+      if (qd == 0) csk[r] = (float)a;
+    }
     __syncthreads();
     {
       const int o = (wm * 32 + (lane & 31)) * FP + 4 * (lane >> 5);
@@ -360,17 +381,27 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
         const f32x4 a0 = ld4(lq[0] + o + 8 * g);
         const f32x4 b = ld4(pb + 8 * g);
         if constexpr (DNA) {
-          const f32x4 a1 = ld4(lq[NA - 2] + o + 8 * g);
+          const f32x4 a1 = ld4(lq[1] + o + 8 * g);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             acc[0] = mfma32(a0[m], b[m], acc[0]);
-            acc[NA - 2] = mfma32(a0[m] - 1.f, b[m], acc[NA - 2]);
+            if constexpr (!CH) acc[1] = mfma32(a0[m] - 1.f, b[m], acc[1]);
             acc[NA - 1] = mfma32(a1[m], b[m] * b[m], acc[NA - 1]);
           }
         } else {
 #pragma unroll
           for (int m = 0; m < 4; ++m) acc[0] = mfma32(a0[m], b[m], acc[0]);
         }
+      }
+    }
+    if constexpr (CH) {   // this sub-tile's sum of q h, into u and (less the H sums) into u_c
+      const float cr = csk[tl];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float x = acc[0][v];
+        ur[v] += x;
+        ucr[v] += x - cr;
+        acc[0][v] = 0.f;
       }
     }
     if (more)
@@ -385,8 +416,14 @@ __global__ __launch_bounds__(256, 2) void k_rgh_W(const float* V, const float* W
   for (int v = 0; v < 16; ++v) {
     const int64_t n = n0 + wm * 32 + blk_row(v, lane);
     if (n < N && tl < R) {
+      if constexpr (CH) {
+        out[0][(sp * N + n) * R + tl] = ur[v];
+        out[1][(sp * N + n) * R + tl] = ucr[v];
+        out[2][(sp * N + n) * R + tl] = acc[1][v];
+      } else {
 #pragma unroll
-      for (int c = 0; c < NA; ++c) out[c][(sp * N + n) * R + tl] = acc[c][v];
+        for (int c = 0; c < NA; ++c) out[c][(sp * N + n) * R + tl] = acc[c][v];
+      }
     }
   }
   if constexpr (MODE != RGH_MU)
@@ -661,12 +698,14 @@ static void launch_rgh_mode(int side, const float* V, const float* W, const floa
                          dpart, fin, check);
   } else {
     const dim3 grid((unsigned)cdiv(N, 64), (unsigned)splits);
-    if (check)
-      hipLaunchKernelGGL((k_rgh_W<true, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
-                         dpart, fin, check);
-    else
-      hipLaunchKernelGGL((k_rgh_W<false, MODE>), grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart,
-                         dpart, fin, check);
+    // the chunked u_c for the plain DNA mode (the cost-carrying mode of the damped
+    // selection has no registers to spare for it)
+    constexpr bool PLAIN = MODE == RGH_DNA;
+    const bool ch = PLAIN && R > 32 && T >= GH_CHUNK_MIN_K;   // chunk = one 64-column sub-tile
+    static_assert(GH_CHUNK == 64, "the chunks of k_rgh_W are its sub-tiles");
+    auto k = check ? (ch ? k_rgh_W<true, MODE, PLAIN> : k_rgh_W<true, MODE, false>)
+                   : (ch ? k_rgh_W<false, MODE, PLAIN> : k_rgh_W<false, MODE, false>);
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, V, W, H, N, T, R, chunk, pu, puc, py, vpart, dpart, fin, check);
   }
 }
 

@@ -32,6 +32,7 @@ SHAPES = [
     (2100, 2300, 96, 0.1, 15),   # contractions of >= 2048 indices both ways: chunked gradient sums
     (64, 16384, 200, 0.1, 16),   # 128 < R <= 512 over whole rounds of 1024-thread blocks: the H-side
                                  # candidates keep 16 rows per thread in registers (R ragged)
+    (300, 4100, 48, 0.1, 17),    # 32 < R <= 64 with T >= 2048: the fused W step's chunked u_c
 ]
 
 
