@@ -175,14 +175,10 @@ constexpr int RATIO_OUT_BYTES = 2 * OUT_TILE * 2;          // Q and Q - 1 staged
 // other's products.
 // The gradient products likewise: a 2-stage ring (80 KiB) and two workgroups
 // per CU (GH16_WG_PER_CU), all accumulators in registers.
-constexpr int RATIO_STAGES = 2, GH_STAGES = 2, COST_STAGES = 4;
-// The H-orientation cost pass (column partials, a light epilogue) fits two waves
-// per SIMD with a 2-stage ring: one workgroup's epilogue then overlaps another's
-// products.  The W orientation (row partials in float64) keeps one wave and a
-// 4-stage ring.  Both read V after the products.
-template <int SIDE> struct CostCfg;
-template <> struct CostCfg<0> { static constexpr int STAGES = 2, WAVES_PER_EU = 2; };
-template <> struct CostCfg<1> { static constexpr int STAGES = COST_STAGES, WAVES_PER_EU = 1; };
+// The cost passes keep per-column partials of their tiles (a light epilogue)
+// and fit two waves per SIMD with a 2-stage ring: one workgroup's epilogue then
+// overlaps another's products.  Both read V after the products.
+constexpr int RATIO_STAGES = 2, GH_STAGES = 2, COST_STAGES = 2;
 
 template <typename TE, int SPLIT>
 using ZEng = Gemm16<G128, TE, typename ZProds<SPLIT>::P, RATIO_STAGES>;
@@ -208,6 +204,29 @@ __device__ __forceinline__ void load_v16(const float* V, int64_t N, int64_t T, i
       for (int v = 0; v < 16; ++v) {
         const int64_t ru = wm * G::WM + i * 32 + (v >> 2) * 8 + (v & 3), cu = wn * G::WN + j * 32;
         vf[i][j][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)((ru * T + cu) * 4), 0));
+      }
+}
+
+// The same for a transposed tile: tile rows are columns t of V (from m0), tile
+// columns are rows n (from n0), v(n, t) = V[n * T + t].  Rows n past N read as
+// zero; entries past T read the next row n and are masked by the callers.
+template <class G>
+__device__ __forceinline__ void load_v16t(const float* V, int64_t N, int64_t T, int64_t m0, int64_t n0,
+                                          float (&vf)[G::FM][G::FN][16]) {
+  const int tid = threadIdx.x, lane = tid & 63, wm = (tid >> 6) % G::WGM, wn = (tid >> 6) / G::WGM;
+  const float* base = V + n0 * T + m0;
+  const int64_t bytes = (N * T - (n0 * T + m0)) * 4;
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)std::min<int64_t>(bytes, 0x7fffffff), 0x00020000);
+  const int voff = (int)(((lane & 31) * T + (lane >> 5) * 4) * 4);
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t ru = wm * G::WM + i * 32 + (v >> 2) * 8 + (v & 3), cu = wn * G::WN + j * 32;
+        vf[i][j][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)((cu * T + ru) * 4), 0));
       }
 }
 
@@ -501,20 +520,21 @@ __global__ __launch_bounds__(256, GH16_WG_PER_CU) void k_gh16(Ops16 ops, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Candidate costs (epilogues shared with the fp32 kernels), 16-bit products:
-// H orientation A = {W}, B = {X_DNA^t, (X_MU - X_DNA)^t}; W orientation
-// A = {X_DNA, X_MU - X_DNA}, B = {H^t}.  acc 0 = z_DNA, acc 1 = dZ.
+// Candidate costs (epilogues shared with the fp32 kernels), 16-bit products,
+// A = the fixed factor, B = {X_DNA, X_MU - X_DNA}; acc 0 = z_DNA, acc 1 = dZ.
+// H orientation: A = W, B = the candidates' transposes, tile (n, t), one
+// partial per column t.  W orientation: the tile transposed, A = H^t, B = the
+// candidates, tile (t, n), so that its partials (one per row n of W) are again
+// per tile column and both orientations share the column epilogue.
 // ---------------------------------------------------------------------------
 typedef Prods<1, 2, 2, 2, 0, 0, 0, 0, 1, 1> CH_P;
-typedef Prods<2, 1, 2, 2, 0, 0, 0, 1, 0, 1> CW_P;
 
 template <typename TE, int SIDE, bool S0>
-__global__ __launch_bounds__(256, CostCfg<SIDE>::WAVES_PER_EU) void k_cost16(const float* V, Ops16 ops, int64_t N,
-                                                                            int64_t T, int64_t Rk, double* part,
-                                                                            int* fpart) {
+__global__ __launch_bounds__(256, 2) void k_cost16(const float* V, Ops16 ops, int64_t N, int64_t T, int64_t Rk,
+                                                   double* part, int* fpart) {
   using G = G128;
-  typedef typename std::conditional<SIDE == 0, CH_P, CW_P>::type PR;
-  typedef Gemm16<G, TE, PR, CostCfg<SIDE>::STAGES> E;
+  typedef CH_P PR;
+  typedef Gemm16<G, TE, PR, COST_STAGES> E;
   extern __shared__ __align__(16) char lds_dyn[];
   __shared__ int fl_s[128];
   const Tile3 tl = xcd_tile();
@@ -532,15 +552,13 @@ __global__ __launch_bounds__(256, CostCfg<SIDE>::WAVES_PER_EU) void k_cost16(con
     E::run(A, B, m0, n0, 0, Rk, lds_dyn, acc);
   }
   float vf[G::FM][G::FN][16];
-  load_v16<G>(V, N, T, m0, n0, vf);
+  if (SIDE == 0) load_v16<G>(V, N, T, m0, n0, vf);
+  else load_v16t<G>(V, N, T, m0, n0, vf);
   double* red = reinterpret_cast<double*>(lds_dyn);
-  if (SIDE == 0) {
-    const int64_t base = tl.y * T, stride = (int64_t)gridDim.y * T;
-    cost_cols<G, S0>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
-  } else {
-    const int64_t base = tl.x * N, stride = (int64_t)gridDim.x * N;
-    cost_rows<G, S0>(vf, acc, m0, n0, N, T, red, fl_s, part, fpart, base, stride);
-  }
+  // extents of the tile rows and columns; partials part[q * stride + base + column]
+  const int64_t M = SIDE == 0 ? N : T, C = SIDE == 0 ? T : N;
+  const int64_t base = tl.y * C, stride = (int64_t)gridDim.y * C;
+  cost_cols<G, S0>(vf, acc, m0, n0, M, C, red, fl_s, part, fpart, base, stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,22 +769,23 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
     conv16<TE>(ConvArgs{Xn, nullptr, R, T, T, irs, nullptr, S.x0, nullptr, 0, d.Tp, d.Rk, d.Rk}, true, s);
     conv16<TE>(ConvArgs{Xmu, Xn, R, T, T, irs, nullptr, S.x1, nullptr, 0, d.Tp, d.Rk, d.Rk}, true, s);
     ops.m[0] = Mat16{S.fa_hi, d.Rk}; ops.m[1] = Mat16{S.x0, d.Rk}; ops.m[2] = Mat16{S.x1, d.Rk};
-  } else {           // A = X (scaled irs), B = H^t (scaled rs)
+  } else {           // A = H^t (scaled rs), B = X (scaled irs): the transposed tile
     conv16<TE>(ConvArgs{Xn, nullptr, N, R, R, nullptr, irs, S.x0, nullptr, 0, d.Np, d.Rk, d.Rk}, false, s);
     conv16<TE>(ConvArgs{Xmu, Xn, N, R, R, nullptr, irs, S.x1, nullptr, 0, d.Np, d.Rk, d.Rk}, false, s);
     conv16<TE>(ConvArgs{F, nullptr, R, T, T, rs, nullptr, S.fb_hi, nullptr, 0, d.Tp, d.Rk, d.Rk}, true, s);
-    ops.m[0] = Mat16{S.x0, d.Rk}; ops.m[1] = Mat16{S.x1, d.Rk}; ops.m[2] = Mat16{S.fb_hi, d.Rk};
+    ops.m[0] = Mat16{S.fb_hi, d.Rk}; ops.m[1] = Mat16{S.x0, d.Rk}; ops.m[2] = Mat16{S.x1, d.Rk};
   }
   prof_end(side == 0 ? "conv16c_H" : "conv16c_W", s);
-  const dim3 grid((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128));
+  // grid x: tiles along the partial index (t for H, n for W); y: along the other
+  const dim3 grid = side == 0 ? dim3((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128))
+                              : dim3((unsigned)(d.Np / 128), (unsigned)(d.Tp / 128));
+  const size_t lb = (size_t)Gemm16<G128, TE, CH_P, COST_STAGES>::LDS_BYTES;
   prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
   if (side == 0) {
-    const size_t lb = (size_t)Gemm16<G128, TE, CH_P, CostCfg<0>::STAGES>::LDS_BYTES;
     auto k = s0 ? k_cost16<TE, 0, true> : k_cost16<TE, 0, false>;
     lds_attr(k, lb);
     hipLaunchKernelGGL(k, grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
   } else {
-    const size_t lb = (size_t)Gemm16<G128, TE, CW_P, CostCfg<1>::STAGES>::LDS_BYTES;
     auto k = s0 ? k_cost16<TE, 1, true> : k_cost16<TE, 1, false>;
     lds_attr(k, lb);
     hipLaunchKernelGGL(k, grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
