@@ -5,8 +5,10 @@
 //
 // Each half-step first converts its fp32 factors into zero-padded, K-contiguous
 // 16-bit operands (k_conv16), so that every product runs the bounds-free engine
-// of core16.hpp.  The Z pass writes Q, Q - 1 and Q-bar in 16 bits, transposed
-// in the H step (the gradient products there contract over n).
+// of core16.hpp.  The Z pass writes Q, Q - 1 and Q-bar in 16 bits, laid out for
+// the gradient products (contraction index contiguous); it and the cost pass
+// compute the W step's tiles transposed, (t, n), so that both orientations
+// keep per-column partials.
 //
 // The factor being updated (H in the H step, W in the W step) enters Z as a
 // two-term split hi + lo (BF16: both factors): with a single rounding the
@@ -163,7 +165,6 @@ struct Ratio16Args {
 template <int SPLIT> struct ZProds;
 template <> struct ZProds<0> { typedef Prods<1, 1, 1, 1, 0, 0, 0> P; };
 template <> struct ZProds<1> { typedef Prods<1, 2, 2, 1, 0, 1, 0, 0, 0, 0> P; };          // B split
-template <> struct ZProds<2> { typedef Prods<2, 1, 2, 1, 1, 0, 0, 0, 0, 0> P; };          // A split
 template <> struct ZProds<3> { typedef Prods<2, 2, 3, 1, 1, 0, 0, 0, 1, 0, 0, 0, 0> P; }; // both
 
 constexpr int OUT_PITCH = 128 + 8;   // LDS pitch of the 128 x 128 output staging tiles
@@ -190,7 +191,9 @@ using ZEng = Gemm16<G128, TE, typename ZProds<SPLIT>::P, RATIO_STAGES>;
 template <class G>
 __device__ __forceinline__ void load_v16(const float* V, int64_t N, int64_t T, int64_t m0, int64_t n0,
                                          float (&vf)[G::FM][G::FN][16]) {
-  const int tid = threadIdx.x, lane = tid & 63, wm = (tid >> 6) % G::WGM, wn = (tid >> 6) / G::WGM;
+  // the wave index made uniform, so that the per-slot offsets are scalars
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % G::WGM, wn = wave / G::WGM;
   const float* base = V + m0 * T + n0;
   const int64_t bytes = (N * T - (m0 * T + n0)) * 4;
   const __amdgpu_buffer_rsrc_t r =
@@ -209,27 +212,56 @@ __device__ __forceinline__ void load_v16(const float* V, int64_t N, int64_t T, i
 
 // The same for a transposed tile: tile rows are columns t of V (from m0), tile
 // columns are rows n (from n0), v(n, t) = V[n * T + t].  Rows n past N read as
-// zero; entries past T read the next row n and are masked by the callers.
+// zero; entries past T read the next row n and are masked by the callers.  The
+// four accumulator slots 4g .. 4g + 3 of a lane are four consecutive t of one
+// row n: one 16-byte load where the rows of V are 16-byte aligned (T % 4 == 0).
 template <class G>
 __device__ __forceinline__ void load_v16t(const float* V, int64_t N, int64_t T, int64_t m0, int64_t n0,
                                           float (&vf)[G::FM][G::FN][16]) {
-  const int tid = threadIdx.x, lane = tid & 63, wm = (tid >> 6) % G::WGM, wn = (tid >> 6) / G::WGM;
+  // the wave index made uniform, so that the per-slot offsets are scalars
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % G::WGM, wn = wave / G::WGM;
   const float* base = V + n0 * T + m0;
   const int64_t bytes = (N * T - (n0 * T + m0)) * 4;
   const __amdgpu_buffer_rsrc_t r =
       __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)std::min<int64_t>(bytes, 0x7fffffff), 0x00020000);
   const int voff = (int)(((lane & 31) * T + (lane >> 5) * 4) * 4);
+  if ((T & 3) == 0) {
 #pragma unroll
-  for (int i = 0; i < G::FM; ++i)
+    for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < G::FN; ++j)
+      for (int j = 0; j < G::FN; ++j)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t ru = wm * G::WM + i * 32 + (v >> 2) * 8 + (v & 3), cu = wn * G::WN + j * 32;
-        vf[i][j][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)((cu * T + ru) * 4), 0));
-      }
+        for (int gq = 0; gq < 4; ++gq) {
+          const int64_t ru = wm * G::WM + i * 32 + gq * 8, cu = wn * G::WN + j * 32;
+          const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, (int)((cu * T + ru) * 4), 0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {   // element to a scalar first: a bit cast of x[u] itself reads x[0]
+            const unsigned e = x[u];
+            vf[i][j][4 * gq + u] = __uint_as_float(e);
+          }
+        }
+  } else {
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t ru = wm * G::WM + i * 32 + (v >> 2) * 8 + (v & 3), cu = wn * G::WN + j * 32;
+          vf[i][j][v] =
+              __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)((cu * T + ru) * 4), 0));
+        }
+  }
 }
 
+// The Z pass.  H step (SIDE 0): tile (n, t) = W H, A = W, B = H^t.  W step
+// (SIDE 1): the transposed tile (t, n) = H^t W^t, A = H^t, B = W, so that in
+// both the per-column quantities (V sums, Q scales and maxima) belong to the
+// index the gradient products do not contract over, and the outputs (Q^t,
+// (Q - 1)^t, Q-bar^t for the H step; Q, Q - 1, Q-bar for the W step) are the
+// tile transposed.  Grid x walks t in both (consecutive tiles read adjacent
+// blocks of the same rows of V).
 template <typename TE, int SIDE, bool MAXONLY, int SPLIT>
 __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
   using G = G128;
@@ -239,8 +271,11 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
   extern __shared__ __align__(16) char lds_dyn[];
   char* lds = lds_dyn;
   const Tile3 tl = xcd_tile();
-  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
+  // tile row block rt (rows from m0), column block (columns from n0)
+  const int64_t rt = SIDE == 0 ? tl.y : tl.x, ct = SIDE == 0 ? tl.x : tl.y;
+  const int64_t m0 = rt * G::BM, n0 = ct * G::BN;
   const int64_t N = a.N, T = a.T;
+  const int64_t ME = SIDE == 0 ? N : T, CE = SIDE == 0 ? T : N;   // extents of tile rows / columns
   if (!MAXONLY) sum_job(a.fin);
   f32x16 acc[G::FM][G::FN][1];
   zero16<G, 1>(acc);
@@ -253,21 +288,21 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
     E::run(A, B, m0, n0, 0, a.Rk, lds, acc);
   }
   float vf[G::FM][G::FN][16];
-  load_v16<G>(a.V, N, T, m0, n0, vf);
+  if (SIDE == 0) load_v16<G>(a.V, N, T, m0, n0, vf);
+  else load_v16t<G>(a.V, N, T, m0, n0, vf);
   const int lane = threadIdx.x & 63;
-  if (MAXONLY) {
+  if (MAXONLY) {   // per-column maxima of Q, |Q - 1|, Q-bar
     float mx[3][G::FN] = {};
     int bad = 0;
 #pragma unroll
-    for (int i = 0; i < G::FM; ++i) {
-      float rmx[3][16] = {};        // SIDE 1: per-row maxima of this lane's columns
+    for (int i = 0; i < G::FM; ++i)
 #pragma unroll
       for (int j = 0; j < G::FN; ++j) {
         const int64_t col = col16<G>(n0, j);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int64_t row = row16<G>(m0, i, v);
-          if (row < N && col < T) {
+          if (row < ME && col < CE) {
             const float x = vf[i][j][v], z = acc[i][j][0][v];
             const bool pos = x > 0.f;
             const float iz = __builtin_amdgcn_rcpf(z);
@@ -275,101 +310,50 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
             const float qc = pos ? (x - z) * iz : -1.f;
             const float qb = pos ? q * iz : 0.f;
             bad |= (pos && !(z > 0.f)) ? 1 : 0;
-            if (SIDE == 0) {
-              mx[0][j] = fmaxf(mx[0][j], q);
-              mx[1][j] = fmaxf(mx[1][j], fabsf(qc));
-              mx[2][j] = fmaxf(mx[2][j], qb);
-            } else {
-              rmx[0][v] = fmaxf(rmx[0][v], q);
-              rmx[1][v] = fmaxf(rmx[1][v], fabsf(qc));
-              rmx[2][v] = fmaxf(rmx[2][v], qb);
-            }
+            mx[0][j] = fmaxf(mx[0][j], q);
+            mx[1][j] = fmaxf(mx[1][j], fabsf(qc));
+            mx[2][j] = fmaxf(mx[2][j], qb);
           }
         }
       }
-      if (SIDE == 1) {
-        // The 32 lanes of a half-wave hold the same 16 rows.  A halving
-        // exchange: at the step over lane bit b each lane keeps half of its
-        // rows and takes the partner's maxima of them, so after four steps lane
-        // c holds row slot c >> 1 (lanes c and c ^ 1 agree after the fifth);
-        // then one atomic per row and quantity from the even lanes.
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          float* x = rmx[k];
-#pragma unroll
-          for (int h = 8; h >= 1; h >>= 1) {
-            const bool up = (lane & (2 * h)) != 0;     // lane bit log2(2h): keep the upper half
-#pragma unroll
-            for (int e = 0; e < h; ++e) {
-              const float send = up ? x[e] : x[e + h];
-              const float keep = up ? x[e + h] : x[e];
-              x[e] = fmaxf(keep, __shfl_xor(send, 2 * h));
-            }
-          }
-          const float m = fmaxf(x[0], __shfl_xor(x[0], 1));
-          const int v = (lane & 31) >> 1;
-          const int64_t row = row16<G>(m0, i, v);
-          if ((lane & 1) == 0 && row < N && m > 0.f) atomicMax(a.qmax[k] + row, __float_as_uint(m));
-        }
-      }
-    }
     if (a.check && bad) atomicOr(a.check, CHK_DOMAIN);
-    if (SIDE == 0) {
 #pragma unroll
-      for (int j = 0; j < G::FN; ++j) {
-        const int64_t col = col16<G>(n0, j);
+    for (int j = 0; j < G::FN; ++j) {
+      const int64_t col = col16<G>(n0, j);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const float m = fmaxf(mx[k][j], __shfl_xor(mx[k][j], 32));
-          if (lane < 32 && col < T) atomicMax(a.qmax[k] + col, __float_as_uint(m));
-        }
+      for (int k = 0; k < 3; ++k) {
+        const float m = fmaxf(mx[k][j], __shfl_xor(mx[k][j], 32));
+        if (lane < 32 && col < CE) atomicMax(a.qmax[k] + col, __float_as_uint(m));
       }
     }
     return;
   }
-  // V sums of this tile (column sums in the H step, row sums in the W step)
+  // V sums of this tile's columns (column sums of V in the H step, row sums in
+  // the W step): vpart[rt * CE + column]
   {
     double* red = reinterpret_cast<double*>(lds);
-    if (SIDE == 0) {
-      double cp[1][G::FN];
+    double cp[1][G::FN];
 #pragma unroll
-      for (int j = 0; j < G::FN; ++j) {
-        cp[0][j] = 0.0;
-        const int64_t col = col16<G>(n0, j);
-#pragma unroll
-        for (int i = 0; i < G::FM; ++i)
-#pragma unroll
-          for (int v = 0; v < 16; ++v)
-            if (row16<G>(m0, i, v) < N && col < T) cp[0][j] += (double)vf[i][j][v];
-      }
-      reduce_cols<G, 1>(cp, red, [&](int c, const double (&s)[1]) {
-        if (n0 + c < T) a.vpart[tl.y * T + n0 + c] = s[0];
-      });
-    } else {
-      double rp[1][G::FM][16];
+    for (int j = 0; j < G::FN; ++j) {
+      cp[0][j] = 0.0;
+      const int64_t col = col16<G>(n0, j);
 #pragma unroll
       for (int i = 0; i < G::FM; ++i)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          rp[0][i][v] = 0.0;
-          const int64_t row = row16<G>(m0, i, v);
-#pragma unroll
-          for (int j = 0; j < G::FN; ++j)
-            if (row < N && col16<G>(n0, j) < T) rp[0][i][v] += (double)vf[i][j][v];
-        }
-      reduce_rows<G, 1>(rp, red, [&](int r, const double (&s)[1]) {
-        if (m0 + r < N) a.vpart[tl.x * N + m0 + r] = s[0];
-      });
+        for (int v = 0; v < 16; ++v)
+          if (row16<G>(m0, i, v) < ME && col < CE) cp[0][j] += (double)vf[i][j][v];
     }
+    reduce_cols<G, 1>(cp, red, [&](int c, const double (&s)[1]) {
+      if (n0 + c < CE) a.vpart[rt * CE + n0 + c] = s[0];
+    });
   }
   // The outputs through LDS staging tiles: Q and Q - 1 in a first round, Q-bar
-  // (recomputed from the same z and v) in a second.  In the H step
-  // (transposed tiles, [t][n]) the four consecutive rows a lane holds per
+  // (recomputed from the same z and v) in a second.  The staging tiles are the
+  // tile transposed ([column][row]); the four consecutive rows a lane holds per
   // group of four accumulator slots are adjacent: one 8-byte store.
   TE* st = reinterpret_cast<TE*>(lds);
   int bad = 0;
   const int64_t ld = SIDE == 0 ? a.Np : a.Tp;
-  const int64_t r0 = SIDE == 0 ? n0 : m0, c0 = SIDE == 0 ? m0 : n0;
 #pragma unroll
   for (int round = 0; round < 2; ++round) {
     const int nout = round == 0 ? 2 : 1;
@@ -384,7 +368,7 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
           const int k = round == 0 ? o : 2;
-          sc[o] = (SIDE == 0 && a.qs[k] && col < T) ? a.qs[k][col] : 1.f;
+          sc[o] = (a.qs[k] && col < CE) ? a.qs[k][col] : 1.f;
         }
 #pragma unroll
         for (int gq = 0; gq < 4; ++gq) {
@@ -394,24 +378,17 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
             const int v = 4 * gq + u;
             const int64_t row = row16<G>(m0, i, v);
             float o0 = 0.f, o1 = 0.f;
-            if (row < N && col < T) {
+            if (row < ME && col < CE) {
               const float x = vf[i][j][v], z = acc[i][j][0][v];
               const bool pos = x > 0.f;
               const float iz = __builtin_amdgcn_rcpf(z);
               const float q = pos ? x * iz : 0.f;
               if (round == 0) {
-                o0 = q;
-                o1 = pos ? (x - z) * iz : -1.f;
+                o0 = q * sc[0];
+                o1 = (pos ? (x - z) * iz : -1.f) * sc[1];
                 bad |= (pos && !(z > 0.f)) ? 1 : 0;
               } else {
-                o0 = pos ? q * iz : 0.f;
-              }
-#pragma unroll
-              for (int o = 0; o < 2; ++o) {
-                float& y = o == 0 ? o0 : o1;
-                const int k = round == 0 ? o : 2;
-                if (SIDE == 0) y *= sc[o];
-                else if (a.qs[k]) y *= a.qs[k][row];
+                o0 = (pos ? q * iz : 0.f) * sc[0];
               }
             }
             out[0][u] = (TE)o0;
@@ -422,23 +399,19 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
           for (int o = 0; o < 2; ++o) {
             if (o >= nout) continue;
             TE* t = st + o * OUT_TILE;
-            if (SIDE == 0) {
-              typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-              u32x2 w;
-              w[0] = (unsigned)__builtin_bit_cast(uint16_t, out[o][0]) |
-                     ((unsigned)__builtin_bit_cast(uint16_t, out[o][1]) << 16);
-              w[1] = (unsigned)__builtin_bit_cast(uint16_t, out[o][2]) |
-                     ((unsigned)__builtin_bit_cast(uint16_t, out[o][3]) << 16);
-              *reinterpret_cast<u32x2*>(t + cl * OUT_PITCH + rl0) = w;
-            } else {
-#pragma unroll
-              for (int u = 0; u < 4; ++u) t[(rl0 + u) * OUT_PITCH + cl] = out[o][u];
-            }
+            typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+            u32x2 w;
+            w[0] = (unsigned)__builtin_bit_cast(uint16_t, out[o][0]) |
+                   ((unsigned)__builtin_bit_cast(uint16_t, out[o][1]) << 16);
+            w[1] = (unsigned)__builtin_bit_cast(uint16_t, out[o][2]) |
+                   ((unsigned)__builtin_bit_cast(uint16_t, out[o][3]) << 16);
+            *reinterpret_cast<u32x2*>(t + cl * OUT_PITCH + rl0) = w;
           }
         }
       }
     __syncthreads();
-    // copy out: nout tiles of 128 rows of 128 elements, 16-byte chunks
+    // copy out: nout tiles of 128 output rows (tile columns) of 128 elements,
+    // 16-byte chunks
     const uint16_t* src = reinterpret_cast<const uint16_t*>(st);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -447,7 +420,7 @@ __global__ __launch_bounds__(256, 2) void k_ratio16(Ratio16Args a) {
       if (o >= nout) continue;
       const int ko = round == 0 ? o : 2;
       uint16_t* dst = reinterpret_cast<uint16_t*>(a.q3) + (int64_t)ko * a.Np * a.Tp;
-      *reinterpret_cast<u32x4*>(dst + (r0 + rr) * ld + c0 + ch) =
+      *reinterpret_cast<u32x4*>(dst + (n0 + rr) * ld + m0 + ch) =
           *reinterpret_cast<const u32x4*>(src + o * OUT_TILE + rr * OUT_PITCH + ch);
     }
   }
@@ -538,7 +511,9 @@ __global__ __launch_bounds__(256, 2) void k_cost16(const float* V, Ops16 ops, in
   extern __shared__ __align__(16) char lds_dyn[];
   __shared__ int fl_s[128];
   const Tile3 tl = xcd_tile();
-  const int64_t m0 = tl.y * G::BM, n0 = tl.x * G::BN;
+  // tile row block rt, column block ct; grid x walks t in both orientations
+  const int64_t rt = SIDE == 0 ? tl.y : tl.x, ct = SIDE == 0 ? tl.x : tl.y;
+  const int64_t m0 = rt * G::BM, n0 = ct * G::BN;
   const int tid = threadIdx.x;
   if (tid < 128) fl_s[tid] = 0;
   f32x16 acc[G::FM][G::FN][2];
@@ -557,7 +532,7 @@ __global__ __launch_bounds__(256, 2) void k_cost16(const float* V, Ops16 ops, in
   double* red = reinterpret_cast<double*>(lds_dyn);
   // extents of the tile rows and columns; partials part[q * stride + base + column]
   const int64_t M = SIDE == 0 ? N : T, C = SIDE == 0 ? T : N;
-  const int64_t base = tl.y * C, stride = (int64_t)gridDim.y * C;
+  const int64_t base = rt * C, stride = (int64_t)(SIDE == 0 ? gridDim.y : gridDim.x) * C;
   cost_cols<G, S0>(vf, acc, m0, n0, M, C, red, fl_s, part, fpart, base, stride);
 }
 
@@ -675,12 +650,15 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
     conv16<TE>(ConvArgs{H, nullptr, R, T, T, rs, nullptr, S.g0, S.g1, 2, d.Rm, d.Tp, d.Tp}, false, s);
   prof_end(side == 0 ? "conv16_H" : "conv16_W", s);
 
+  // H step: tile (n, t), A = W, B = H^t; W step: tile (t, n), A = H^t, B = W
+  const Mat16 wm[2] = {Mat16{S.fa_hi, d.Rk}, Mat16{split_a ? S.fa_lo : S.fa_hi, d.Rk}};
+  const Mat16 hm[2] = {Mat16{S.fb_hi, d.Rk}, Mat16{split_b ? S.fb_lo : S.fb_hi, d.Rk}};
   Ratio16Args ra;
   ra.V = V;
-  ra.A[0] = Mat16{S.fa_hi, d.Rk};
-  ra.A[1] = Mat16{split_a ? S.fa_lo : S.fa_hi, d.Rk};
-  ra.B[0] = Mat16{S.fb_hi, d.Rk};
-  ra.B[1] = Mat16{split_b ? S.fb_lo : S.fb_hi, d.Rk};
+  for (int k = 0; k < 2; ++k) {
+    ra.A[k] = side == 0 ? wm[k] : hm[k];
+    ra.B[k] = side == 0 ? hm[k] : wm[k];
+  }
   ra.N = N; ra.T = T; ra.Rk = d.Rk; ra.Np = d.Np; ra.Tp = d.Tp;
   ra.q3 = S.q3; ra.vpart = vpart; ra.check = check; ra.fin = fin;
   for (int k = 0; k < 3; ++k) { ra.qs[k] = nullptr; ra.qmax[k] = nullptr; }
@@ -707,8 +685,8 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
   if (side == 0) {
     if (split == 1) launch_ratio_k(k_ratio16<TE, 0, false, 1>, ZEng<TE, 1>::LDS_BYTES, rgrid, ra, s);
     else launch_ratio_k(k_ratio16<TE, 0, false, 3>, ZEng<TE, 3>::LDS_BYTES, rgrid, ra, s);
-  } else {
-    if (split == 2) launch_ratio_k(k_ratio16<TE, 1, false, 2>, ZEng<TE, 2>::LDS_BYTES, rgrid, ra, s);
+  } else {           // the operands swapped: W (split in FP16) is now the B operand
+    if (split == 2) launch_ratio_k(k_ratio16<TE, 1, false, 1>, ZEng<TE, 1>::LDS_BYTES, rgrid, ra, s);
     else launch_ratio_k(k_ratio16<TE, 1, false, 3>, ZEng<TE, 3>::LDS_BYTES, rgrid, ra, s);
   }
   prof_end(side == 0 ? "ratio16_H" : "ratio16_W", s);
@@ -776,9 +754,7 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
     ops.m[0] = Mat16{S.fb_hi, d.Rk}; ops.m[1] = Mat16{S.x0, d.Rk}; ops.m[2] = Mat16{S.x1, d.Rk};
   }
   prof_end(side == 0 ? "conv16c_H" : "conv16c_W", s);
-  // grid x: tiles along the partial index (t for H, n for W); y: along the other
-  const dim3 grid = side == 0 ? dim3((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128))
-                              : dim3((unsigned)(d.Np / 128), (unsigned)(d.Tp / 128));
+  const dim3 grid((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128));
   const size_t lb = (size_t)Gemm16<G128, TE, CH_P, COST_STAGES>::LDS_BYTES;
   prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
   if (side == 0) {
