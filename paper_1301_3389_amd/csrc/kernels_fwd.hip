@@ -1393,14 +1393,17 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 }
 
 // Normalisation with the second level of the sums done per tile: blocks
-// [0, wtiles) scale 64 x 64 tiles of W (64 columns r, each block summing the
-// parts of its 64 factors into LDS); the remaining blocks scale SC_TCHUNK
-// entries of one row r of H.  Every block loads its factor entries before it
-// adds the parts, so the two latencies overlap.  Multiplying by the float64
-// reciprocal of f rounds like dividing except in double-rounding ties.  With
-// `emit`, the blocks of the normalised factor (W tiles for side 0, H chunks for
-// side 1) also write the float64 sum of the values they stored (an unchanged
-// column / row where f is not positive): emit[tile * R + r].
+// [0, wtiles) scale (4096 / WR) x WR tiles of W (WR columns r, each block
+// summing the parts of its WR factors, 256 / WR lanes per column); the
+// remaining blocks scale SC_TCHUNK entries of one row r of H.  WR = 64 serves
+// few parts; with many (the W selection leaves one per four rows of W) the
+// part sums of 64-column tiles become long dependent chains, and WR = 16 cuts
+// them to a quarter.  Every block loads its factor entries before it adds the
+// parts, so the two latencies overlap.  Multiplying by the float64 reciprocal
+// of f rounds like dividing except in double-rounding ties.  With `emit`, the
+// blocks of the normalised factor (W tiles for side 0, H chunks for side 1)
+// also write the float64 sum of the values they stored (an unchanged column /
+// row where f is not positive): emit[tile * R + r].
 //
 // With `o.part` (the balanced normalisation of eq. 2, both weights positive)
 // the other factor's sums come in `o` and f becomes sqrt(w_j * S_j / (w_o * S_o))
@@ -1408,49 +1411,66 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 // with lambda; side 1 the reverse), so W column r is multiplied by
 // sqrt(lambda G_r / (rho C_r)) either way; a sum that is not positive leaves
 // the column / row unscaled and sets CHK_DOMAIN.
-constexpr int SC_W_PER = 64 * 64 / 256, SC_H_PER = SC_TCHUNK / 256;
+constexpr int SC_H_PER = SC_TCHUNK / 256;
+constexpr int SC_MANY_PARTS = 256;   // above this many parts the 16-column W tiles
 __device__ __forceinline__ double balance_factor(double sj, double so, double wj, double wo, int* check) {
   if (sj > 0.0 && so > 0.0) return sqrt((wj * sj) / (wo * so));
   if (check) atomicOr(check, CHK_DOMAIN);
   return 0.0;
 }
 
+// Sum of x over the lanes of a wave with equal lane % WR, in a fixed order
+// (every such lane ends with the same value: the pairings are symmetric).
+template <int WR>
+__device__ __forceinline__ double lane_group_sum(double x) {
+  if constexpr (WR <= 16) x += __shfl_xor(x, 16);
+  if constexpr (WR <= 32) x += __shfl_xor(x, 32);
+  return x;
+}
+
+template <int WR>
 __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, float* __restrict__ H, int64_t N,
                                                int64_t T, int64_t R, SumJob j, SumJob o, double wj, double wo,
                                                int64_t rtiles, int64_t wtiles, int64_t tchunks,
                                                double* __restrict__ emit) {
-  __shared__ double fs[64];
-  __shared__ double red[4][64];
-  __shared__ double red2[4][64];
-  const int tid = threadIdx.x;
+  constexpr int WG = 256 / WR, WN = 4096 / WR, WPER = WN / WG;   // lane groups, tile rows, rows per lane
+  static_assert(WR == 16 || WR == 32 || WR == 64, "16, 32 or 64 columns per W tile");
+  __shared__ double fs[WR];
+  __shared__ double red[4][WR];
+  __shared__ double red2[4][WR];
+  const int tid = threadIdx.x, wave = tid >> 6;
   const int64_t b = blockIdx.x;
   if (b < wtiles) {
     const int64_t rt = b % rtiles, nt = b / rtiles;
-    const int64_t r = rt * 64 + (tid & 63);
-    const int64_t nb = nt * 64 + (tid >> 6);
-    float w[SC_W_PER];
+    const int rr = tid % WR, g = tid / WR;
+    const int64_t r = rt * WR + rr;
+    const int64_t nb = nt * WN + g;
+    float w[WPER];
 #pragma unroll
-    for (int k = 0; k < SC_W_PER; ++k) {
-      const int64_t n = nb + 4 * k;
+    for (int k = 0; k < WPER; ++k) {
+      const int64_t n = nb + WG * k;
       w[k] = (n < N && r < R) ? W[n * R + r] : 0.f;
     }
-    {  // four groups of 64 threads add every fourth part, then one thread per r adds the groups
-      const int g = tid >> 6;
+    {  // WG groups of WR lanes add every WG-th part, then the groups are added
       double f = 0.0, f2 = 0.0;
       if (r < R) {
 #pragma unroll 8
-        for (int p = g; p < j.nparts; p += 4) f += j.part[(int64_t)p * R + r];
+        for (int p = g; p < j.nparts; p += WG) f += j.part[(int64_t)p * R + r];
         if (o.part)
 #pragma unroll 8
-          for (int p = g; p < o.nparts; p += 4) f2 += o.part[(int64_t)p * R + r];
+          for (int p = g; p < o.nparts; p += WG) f2 += o.part[(int64_t)p * R + r];
       }
-      red[g][tid & 63] = f;
-      red2[g][tid & 63] = f2;
+      f = lane_group_sum<WR>(f);
+      f2 = lane_group_sum<WR>(f2);
+      if ((tid & 63) < WR) {
+        red[wave][rr] = f;
+        red2[wave][rr] = f2;
+      }
     }
     __syncthreads();
-    if (tid < 64) {
+    if (tid < WR) {
       double f = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-      const bool in = rt * 64 + tid < R;
+      const bool in = rt * WR + tid < R;
       if (o.part) {
         const double f2 = (red2[0][tid] + red2[1][tid]) + (red2[2][tid] + red2[3][tid]);
         f = in ? balance_factor(f, f2, wj, wo, j.check) : 0.0;
@@ -1460,22 +1480,23 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
       fs[tid] = f;
     }
     __syncthreads();
-    const double f = fs[tid & 63];
+    const double f = fs[rr];
     const bool sc = r < R && f > 0.0;
     const double m = side == 0 ? 1.0 / f : f;
     double cs = 0.0;
 #pragma unroll
-    for (int k = 0; k < SC_W_PER; ++k) {
-      const int64_t n = nb + 4 * k;
+    for (int k = 0; k < WPER; ++k) {
+      const int64_t n = nb + WG * k;
       const float x = sc ? (float)((double)w[k] * m) : w[k];
       if (sc && n < N) W[n * R + r] = x;
       cs += (double)x;                            // 0 outside the matrix
     }
     if (emit && side == 0) {                      // column sums of this tile of the new W
-      red[tid >> 6][tid & 63] = cs;
+      cs = lane_group_sum<WR>(cs);
+      if ((tid & 63) < WR) red[wave][rr] = cs;
       __syncthreads();
-      if (tid < 64 && rt * 64 + tid < R)
-        emit[nt * R + rt * 64 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+      if (tid < WR && rt * WR + tid < R)
+        emit[nt * R + rt * WR + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
     }
   } else {
     const int64_t hb = b - wtiles;
@@ -1545,19 +1566,27 @@ hipError_t launch_penalty(const SumJob& cj, const SumJob& gj, double rho, double
   return hipGetLastError();
 }
 
+// The most parts any normalisation emits (the 64-column W tiles emit the most).
 int64_t scale_emit_parts(int side, int64_t N, int64_t T) {
   return side == 0 ? cdiv(N, 64) : cdiv(T, SC_TCHUNK);
 }
 
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
                         double* emit, SumJob* emitted, hipStream_t s, const SumJob& other, double wj, double wo) {
-  const int64_t rtiles = cdiv(R, 64), wtiles = rtiles * cdiv(N, 64), tchunks = cdiv(T, SC_TCHUNK);
+  const bool many = std::max(job.nparts, other.part ? other.nparts : 0) > SC_MANY_PARTS;
+  const int wr = many ? 16 : 64, wn = 4096 / wr;
+  const int64_t rtiles = cdiv(R, wr), wtiles = rtiles * cdiv(N, wn), tchunks = cdiv(T, SC_TCHUNK);
   const int64_t blocks = wtiles + R * tchunks;
   prof_begin("scale", s);
-  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, other, wj, wo,
-                     rtiles, wtiles, tchunks, emit);
+  if (many)
+    hipLaunchKernelGGL(k_scale<16>, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, other, wj, wo,
+                       rtiles, wtiles, tchunks, emit);
+  else
+    hipLaunchKernelGGL(k_scale<64>, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, other, wj, wo,
+                       rtiles, wtiles, tchunks, emit);
   prof_end("scale", s);
-  if (emit && emitted) *emitted = SumJob{emit, (int)scale_emit_parts(side, N, T), R, nullptr, nullptr, nullptr};
+  if (emit && emitted)
+    *emitted = SumJob{emit, (int)(side == 0 ? cdiv(N, wn) : cdiv(T, SC_TCHUNK)), R, nullptr, nullptr, nullptr};
   return hipGetLastError();
 }
 

@@ -52,6 +52,9 @@ SHAPES = [
     (1000, 515, 64, 0.1, 4),
     (130, 200, 1, 0.0, 5),
     (200, 300, 129, 0.05, 9),
+    # T % 4 == 0 with ragged N and several K tiles: the W step's transposed
+    # tiles read V in 16-byte pieces
+    (300, 516, 40, 0.1, 11),
 ]
 
 
