@@ -1412,7 +1412,7 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 // sqrt(lambda G_r / (rho C_r)) either way; a sum that is not positive leaves
 // the column / row unscaled and sets CHK_DOMAIN.
 constexpr int SC_H_PER = SC_TCHUNK / 256;
-constexpr int SC_MANY_PARTS = 256;   // above this many parts the 16-column W tiles
+constexpr int SC_MANY_PARTS = 128;   // above this many parts the 16-column W tiles
 __device__ __forceinline__ double balance_factor(double sj, double so, double wj, double wo, int* check) {
   if (sj > 0.0 && so > 0.0) return sqrt((wj * sj) / (wo * so));
   if (check) atomicOr(check, CHK_DOMAIN);
