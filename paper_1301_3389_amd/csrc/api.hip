@@ -362,7 +362,8 @@ struct AuxOut {
 static dna_status run_candidates(int side, const float* V, const float* W, const float* H, int64_t N,
                                  int64_t T, int64_t R, const dna_opts* o, const Layout& L, void* ws,
                                  float* Xmu, float* Xn, float* Aout, float* Bout, int* chk, hipStream_t s,
-                                 const SumJob* pre = nullptr, bool carry = false, const AuxOut* aux = nullptr) {
+                                 const SumJob* pre = nullptr, bool carry = false, const AuxOut* aux = nullptr,
+                                 bool qmax16 = false) {
   const bool keep_sums = aux && side == 0 && o->gemm == DNA_GEMM_FP32 && R > FUSED_MAX_R && !carry;
   float* Q = keep_sums ? aux->Q : at<float>(ws, L.q);
   float* Qb = keep_sums ? aux->Qb : at<float>(ws, L.qb);
@@ -389,7 +390,7 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     const bool fused = !p16 && R <= FUSED_MAX_R;
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 0, V, W, H, N, T, R, S, L.sh16.splits, L.sh16.kchunk, pu, puc, py,
-                                vpart, chk, job, s), "ratio_gh16_H");
+                                vpart, chk, job, s, qmax16), "ratio_gh16_H");
     } else if (fused) {
       const bool damp = o->select == DNA_SELECT_NEWTON_FIRST;
       DNA_HIP(launch_rgh(0, V, W, H, N, T, R, L.shf.splits, L.shf.kchunk, pu, puc, py, vpart, job, chk, s,
@@ -418,7 +419,7 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
     const bool fused = !p16 && R <= FUSED_MAX_R;
     if (p16) {
       DNA_HIP(launch_ratio_gh16(o->gemm, 1, V, W, H, N, T, R, S, L.sw16.splits, L.sw16.kchunk, pu, puc, py,
-                                vpart, chk, job, s), "ratio_gh16_W");
+                                vpart, chk, job, s, qmax16), "ratio_gh16_W");
     } else if (fused) {
       const bool damp = o->select == DNA_SELECT_NEWTON_FIRST;
       DNA_HIP(launch_rgh(1, V, W, H, N, T, R, L.swf.splits, L.swf.kchunk, pu, puc, py, vpart, job, chk, s,
@@ -445,10 +446,12 @@ static dna_status run_candidates(int side, const float* V, const float* W, const
 // `fresh` (W step): the selection also leaves the first level of the column
 // sums of the new W (in the pu buffer, whose split partials the candidates have
 // consumed) for the normalisation that follows.
+// `qmax16` (FP16): the cost pass also leaves bounds of the next half-step's Q
+// maxima, which that half-step's Z pass then takes instead of a maxima pass.
 static dna_status run_select(int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                              float* Xout, int64_t N, int64_t T, int64_t R, const dna_opts* o, const Layout& L,
                              void* ws, uint8_t* mask, double* dsel, double* margin, hipStream_t s,
-                             bool keep = false, SumJob* fresh = nullptr) {
+                             bool keep = false, SumJob* fresh = nullptr, bool qmax16 = false) {
   double* emit = fresh ? at<double>(ws, L.pu) : nullptr;
   float* zd = keep ? at<float>(ws, L.zd) : nullptr;
   float* dz = keep ? at<float>(ws, L.dz) : nullptr;
@@ -459,8 +462,8 @@ static dna_status run_select(int side, const float* V, const float* F, const flo
   double* cpart = at<double>(ws, L.cpart);
   int* fpart = at<int>(ws, L.fpart);
   if (o->gemm != DNA_GEMM_FP32) {
-    DNA_HIP(launch_cost16(o->gemm, side, V, F, Xmu, Xn, N, T, R, scratch16(ws, L, N, T, R), cpart, fpart, s, s0),
-            "cost16");
+    DNA_HIP(launch_cost16(o->gemm, side, V, F, Xmu, Xn, N, T, R, scratch16(ws, L, N, T, R), cpart, fpart, s, s0,
+                          qmax16), "cost16");
     if (side == 0)
       DNA_HIP(launch_select_H(Xmu, Xn, Xout, cpart, fpart, (int)cdiv(N, 128), T, R, mask, dsel, margin, s),
               "select_H");   // the 16-bit cost pass tiles N by 128
@@ -709,6 +712,8 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
   const bool keep = o->gemm == DNA_GEMM_FP32 && R > FUSED_MAX_R;
   bool zin = false;                                 // Z of the current state is in the workspace
   const bool cols = hcols_path(o, T, R);
+  // FP16: each cost pass bounds the next Z pass's Q maxima (the first has none)
+  const bool qm = o->gemm == DNA_GEMM_FP16;
   for (int it = 0; it < iters; ++it) {
     if (cols) {
       SumJob fresh;
@@ -716,14 +721,16 @@ dna_status dna_iterate(const float* V, float* W, float* H, int64_t N, int64_t T,
       DNA_TRY(iterate_normalize(1, W, H, N, T, R, o, c, ws, next, have, &fresh));  // step 16; next = g
     } else {
       DNA_TRY(run_candidates(0, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
-                             have ? &next : nullptr, zin));
-      DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep));
+                             have ? &next : nullptr, zin, nullptr, qm && it > 0));
+      DNA_TRY(run_select(0, V, W, Xmu, Xn, H, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep, nullptr,
+                         qm));
       DNA_TRY(iterate_normalize(1, W, H, N, T, R, o, c, ws, next, have));  // step 16; next = g
     }
     DNA_TRY(run_candidates(1, V, W, H, N, T, R, o, c.L, ws, Xmu, Xn, nullptr, nullptr, c.chk, c.s,
-                           have ? &next : nullptr, keep));
+                           have ? &next : nullptr, keep, nullptr, qm));
     SumJob freshW;
-    DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep, &freshW));
+    DNA_TRY(run_select(1, V, H, Xmu, Xn, W, N, T, R, o, c.L, ws, nullptr, nullptr, nullptr, c.s, keep, &freshW,
+                       qm && it + 1 < iters));
     DNA_TRY(iterate_normalize(0, W, H, N, T, R, o, c, ws, next, have, &freshW));  // step 29; next = c
     zin = keep;
   }

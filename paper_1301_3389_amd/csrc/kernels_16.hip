@@ -502,9 +502,78 @@ __global__ __launch_bounds__(256, GH16_WG_PER_CU) void k_gh16(Ops16 ops, int64_t
 // ---------------------------------------------------------------------------
 typedef Prods<1, 2, 2, 2, 0, 0, 0, 0, 1, 1> CH_P;
 
-template <typename TE, int SIDE, bool S0>
+// FP16 inside dna_iterate: bounds of the next half-step's Q, |Q - 1| and Q-bar
+// maxima per tile row (H step: rows n, for the W step's Q scales; W step: rows
+// t, for the H step's), taken over both candidates' reconstructions z_DNA and
+// z_DNA + dZ, between which the selection picks row by row (the normalisation
+// after it changes Z only by rounding; the scales are powers of two).  They
+// replace the next Z pass's maxima pass.  The 32 lanes of a half-wave hold the
+// same 16 rows: a halving exchange leaves one lane per row, which adds it to
+// the row's maximum with an atomic.  (Per-tile stores reduced by the next Z
+// pass instead of the atomics measured slower.)
+template <class G>
+__device__ __forceinline__ void row_qmax(const float (&vf)[G::FM][G::FN][16], const f32x16 (&acc)[G::FM][G::FN][2],
+                                         int64_t m0, int64_t n0, int64_t ME, int64_t CE, unsigned* qmax,
+                                         int64_t L) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+    for (int hv = 0; hv < 2; ++hv) {   // row slots 8 hv .. 8 hv + 7 (eight at a time: registers)
+      float x[3][8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[0][e] = x[1][e] = x[2][e] = 0.f;
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) {
+        const int64_t col = col16<G>(n0, j);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int v = 8 * hv + e;
+          if (row16<G>(m0, i, v) < ME && col < CE) {
+            // q = v/z is largest at the smaller positive z, and so is v/z^2;
+            // |q - 1| is largest at one of the two (a candidate whose z is not
+            // positive is left out: its z reads as infinity, q as 0)
+            const float xv = vf[i][j][v];
+            float z1 = acc[i][j][0][v], z2 = acc[i][j][0][v] + acc[i][j][1][v];
+            // opaque copies: the cost epilogue's reciprocals of the same z are
+            // not kept live until here (they would not fit the registers)
+            asm volatile("" : "+v"(z1), "+v"(z2));
+            const float inf = __builtin_inff();
+            const float za = z1 > 0.f ? z1 : inf, zb = z2 > 0.f ? z2 : inf;
+            const float zlo = fminf(za, zb), zhi = fmaxf(za, zb) < inf ? fmaxf(za, zb) : zlo;
+            const float rlo = __builtin_amdgcn_rcpf(zlo), rhi = __builtin_amdgcn_rcpf(zhi);
+            const float qlo = xv * rlo, qhi = xv * rhi;
+            x[0][e] = fmaxf(x[0][e], qlo);
+            x[1][e] = fmaxf(x[1][e], fmaxf(fabsf(qlo - 1.f), fabsf(qhi - 1.f)));
+            x[2][e] = fmaxf(x[2][e], qlo * rlo);
+          }
+        }
+      }
+      // halving exchange over lane bits 3, 2, 1: lane c keeps slot (c >> 1) & 7;
+      // then lane bits 0 and 4 (the same slots) are folded in
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int h = 4; h >= 1; h >>= 1) {
+          const bool up = (lane & (2 * h)) != 0;
+#pragma unroll
+          for (int e = 0; e < h; ++e) {
+            const float send = up ? x[k][e] : x[k][e + h];
+            const float keep = up ? x[k][e + h] : x[k][e];
+            x[k][e] = fmaxf(keep, __shfl_xor(send, 2 * h));
+          }
+        }
+        float m = fmaxf(x[k][0], __shfl_xor(x[k][0], 1));
+        m = fmaxf(m, __shfl_xor(m, 16));
+        const int64_t row = row16<G>(m0, i, 8 * hv + ((lane >> 1) & 7));
+        if ((lane & 17) == 0 && row < ME && m > 0.f) atomicMax(qmax + k * L + row, __float_as_uint(m));
+      }
+    }
+}
+
+template <typename TE, int SIDE, bool S0, bool QM>
 __global__ __launch_bounds__(256, 2) void k_cost16(const float* V, Ops16 ops, int64_t N, int64_t T, int64_t Rk,
-                                                   double* part, int* fpart) {
+                                                   double* part, int* fpart, unsigned* qmax) {
   using G = G128;
   typedef CH_P PR;
   typedef Gemm16<G, TE, PR, COST_STAGES> E;
@@ -534,6 +603,7 @@ __global__ __launch_bounds__(256, 2) void k_cost16(const float* V, Ops16 ops, in
   const int64_t M = SIDE == 0 ? N : T, C = SIDE == 0 ? T : N;
   const int64_t base = rt * C, stride = (int64_t)(SIDE == 0 ? gridDim.y : gridDim.x) * C;
   cost_cols<G, S0>(vf, acc, m0, n0, M, C, red, fl_s, part, fpart, base, stride);
+  if (QM) row_qmax<G>(vf, acc, m0, n0, M, C, qmax, M);
 }
 
 // ---------------------------------------------------------------------------
@@ -625,7 +695,7 @@ template <typename TE>
 static hipError_t ratio_gh16(int side, const float* V, const float* W, const float* H, int64_t N, int64_t T,
                              int64_t R, const Scratch16& S, bool scaled, int splits, int64_t kchunk, float* pu,
                              float* puc, float* py, double* vpart, int* check, const SumJob& fin,
-                             hipStream_t s) {
+                             hipStream_t s, bool qmax_given) {
   const Dims16 d = dims16(N, T, R);
   const float* rs = nullptr;
   const float* irs = nullptr;
@@ -667,13 +737,16 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
   const float* iqs[3] = {nullptr, nullptr, nullptr};
   if (scaled) {
     unsigned* qbits = S.bits + d.Rm;
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid1(3 * L)), dim3(256), 0, s, qbits, 3 * L);
-    for (int k = 0; k < 3; ++k) ra.qmax[k] = qbits + k * L;
-    // the scales only need the maxima to a few bits: unsplit product
-    prof_begin("qmax16", s);
-    if (side == 0) launch_ratio_k(k_ratio16<TE, 0, true, 0>, ZEng<TE, 0>::LDS_BYTES, rgrid, ra, s);
-    else launch_ratio_k(k_ratio16<TE, 1, true, 0>, ZEng<TE, 0>::LDS_BYTES, rgrid, ra, s);
-    prof_end("qmax16", s);
+    if (!qmax_given) {   // else the preceding cost pass left bounds of them there
+      hipLaunchKernelGGL(k_zero_u32, dim3(grid1(3 * L)), dim3(256), 0, s, qbits, 3 * L);
+      for (int k = 0; k < 3; ++k) ra.qmax[k] = qbits + k * L;
+      // the scales only need the maxima to a few bits: unsplit product
+      prof_begin("qmax16", s);
+      if (side == 0) launch_ratio_k(k_ratio16<TE, 0, true, 0>, ZEng<TE, 0>::LDS_BYTES, rgrid, ra, s);
+      else launch_ratio_k(k_ratio16<TE, 1, true, 0>, ZEng<TE, 0>::LDS_BYTES, rgrid, ra, s);
+      prof_end("qmax16", s);
+      for (int k = 0; k < 3; ++k) ra.qmax[k] = nullptr;
+    }
     for (int k = 0; k < 3; ++k) {
       hipLaunchKernelGGL(k_scales, dim3(grid1(L)), dim3(256), 0, s, qbits + k * L, L, 13, S.qs + k * L,
                          S.iqs + k * L, (float*)nullptr);
@@ -730,7 +803,7 @@ static hipError_t ratio_gh16(int side, const float* V, const float* W, const flo
 template <typename TE>
 static hipError_t cost16(int side, const float* V, const float* F, const float* Xmu, const float* Xn, int64_t N,
                          int64_t T, int64_t R, const Scratch16& S, bool scaled, double* part, int* fpart,
-                         hipStream_t s, bool s0) {
+                         hipStream_t s, bool s0, bool qmax_next) {
   const Dims16 d = dims16(N, T, R);
   const float* rs = nullptr;
   const float* irs = nullptr;
@@ -756,16 +829,24 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
   prof_end(side == 0 ? "conv16c_H" : "conv16c_W", s);
   const dim3 grid((unsigned)(d.Tp / 128), (unsigned)(d.Np / 128));
   const size_t lb = (size_t)Gemm16<G128, TE, CH_P, COST_STAGES>::LDS_BYTES;
-  prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
-  if (side == 0) {
-    auto k = s0 ? k_cost16<TE, 0, true> : k_cost16<TE, 0, false>;
-    lds_attr(k, lb);
-    hipLaunchKernelGGL(k, grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
-  } else {
-    auto k = s0 ? k_cost16<TE, 1, true> : k_cost16<TE, 1, false>;
-    lds_attr(k, lb);
-    hipLaunchKernelGGL(k, grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart);
+  // maxima for the next half-step's Q scales: per n after the H step, per t after the W step
+  unsigned* qmax = nullptr;
+  if (scaled && qmax_next) {
+    const int64_t L = side == 0 ? N : T;
+    qmax = S.bits + d.Rm;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid1(3 * L)), dim3(256), 0, s, qmax, 3 * L);
   }
+  prof_begin(side == 0 ? "cost16_H" : "cost16_W", s);
+  typedef void (*Kern)(const float*, Ops16, int64_t, int64_t, int64_t, double*, int*, unsigned*);
+  Kern k;
+  if (side == 0)
+    k = qmax ? (s0 ? k_cost16<TE, 0, true, true> : k_cost16<TE, 0, false, true>)
+             : (s0 ? k_cost16<TE, 0, true, false> : k_cost16<TE, 0, false, false>);
+  else
+    k = qmax ? (s0 ? k_cost16<TE, 1, true, true> : k_cost16<TE, 1, false, true>)
+             : (s0 ? k_cost16<TE, 1, true, false> : k_cost16<TE, 1, false, false>);
+  lds_attr(k, lb);
+  hipLaunchKernelGGL(k, grid, dim3(256), lb, s, V, ops, N, T, d.Rk, part, fpart, qmax);
   prof_end(side == 0 ? "cost16_H" : "cost16_W", s);
   return hipGetLastError();
 }
@@ -773,20 +854,22 @@ static hipError_t cost16(int side, const float* V, const float* F, const float* 
 hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W, const float* H, int64_t N,
                              int64_t T, int64_t R, const Scratch16& S, int splits, int64_t kchunk, float* pu,
                              float* puc, float* py, double* vpart, int* check, const SumJob& fin,
-                             hipStream_t s) {
+                             hipStream_t s, bool qmax_given) {
   // the Z pass addresses V with 32-bit byte offsets of up to 128 rows
   if (T >= (int64_t(1) << 22)) return hipErrorInvalidValue;
   if (gemm == 1)
-    return ratio_gh16<__bf16>(side, V, W, H, N, T, R, S, false, splits, kchunk, pu, puc, py, vpart, check, fin, s);
-  return ratio_gh16<_Float16>(side, V, W, H, N, T, R, S, true, splits, kchunk, pu, puc, py, vpart, check, fin, s);
+    return ratio_gh16<__bf16>(side, V, W, H, N, T, R, S, false, splits, kchunk, pu, puc, py, vpart, check, fin, s,
+                              false);
+  return ratio_gh16<_Float16>(side, V, W, H, N, T, R, S, true, splits, kchunk, pu, puc, py, vpart, check, fin, s,
+                              qmax_given);
 }
 
 hipError_t launch_cost16(int gemm, int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                          int64_t N, int64_t T, int64_t R, const Scratch16& S, double* part, int* fpart,
-                         hipStream_t s, bool s0) {
+                         hipStream_t s, bool s0, bool qmax_next) {
   if (T >= (int64_t(1) << 22)) return hipErrorInvalidValue;   // 32-bit offsets into V, as the Z pass
-  if (gemm == 1) return cost16<__bf16>(side, V, F, Xmu, Xn, N, T, R, S, false, part, fpart, s, s0);
-  return cost16<_Float16>(side, V, F, Xmu, Xn, N, T, R, S, true, part, fpart, s, s0);
+  if (gemm == 1) return cost16<__bf16>(side, V, F, Xmu, Xn, N, T, R, S, false, part, fpart, s, s0, false);
+  return cost16<_Float16>(side, V, F, Xmu, Xn, N, T, R, S, true, part, fpart, s, s0, qmax_next);
 }
 
 }  // namespace dna

@@ -42,12 +42,12 @@ Scratch16 scratch16_carve(void* base, int64_t N, int64_t T, int64_t R);
 hipError_t launch_ratio_gh16(int gemm, int side, const float* V, const float* W, const float* H, int64_t N,
                              int64_t T, int64_t R, const Scratch16& S, int splits, int64_t kchunk, float* pu,
                              float* puc, float* py, double* vpart, int* check, const SumJob& fin,
-                             hipStream_t s);
+                             hipStream_t s, bool qmax_given = false);
 
 // Steps 7-9, 12-14 with 16-bit reconstruction products (float64 cost sums);
 // partials over cdiv(N, 128) (H step) or cdiv(T, 128) (W step) tiles.
 hipError_t launch_cost16(int gemm, int side, const float* V, const float* F, const float* Xmu, const float* Xn,
                          int64_t N, int64_t T, int64_t R, const Scratch16& S, double* part, int* fpart,
-                         hipStream_t s, bool s0 = true);
+                         hipStream_t s, bool s0 = true, bool qmax_next = false);
 
 }  // namespace dna

@@ -144,6 +144,26 @@ def test_trajectory_16_config1(dna, gemm):
     assert rel.max() <= traj_tol(gemm)
 
 
+def test_trajectory_fp16_one_call(dna):
+    """20 DNA iterations in FP16 as one native call, in which each cost pass
+    bounds the next Z pass's Q maxima (no maxima pass after the first half
+    step): the final KL follows the FP64 oracle's to the form's accuracy, and
+    matches the iteration-by-iteration run (a maxima pass every half step) to
+    within the same bound."""
+    w = synth.config(1)
+    kl_ref = oracle.fit_dna(w.V, w.W, w.H, iters=20, value_floor=FLOOR32).kl[-1]
+    Vg, Wg, Hg = gpu(w.V), gpu(w.W), gpu(w.H)
+    dna.fit(Vg, Wg, Hg, 20, method="dna", gemm="fp16")
+    kl_one = float(host(dna.kl_cost(Vg, Wg, Hg))[0])
+    Vg, Wg, Hg = gpu(w.V), gpu(w.W), gpu(w.H)
+    for _ in range(20):
+        dna.fit(Vg, Wg, Hg, 1, method="dna", gemm="fp16")
+    kl_each = float(host(dna.kl_cost(Vg, Wg, Hg))[0])
+    log_result("precision_trajectory_fp16_one_call", {"kl_one": kl_one, "kl_each": kl_each, "kl_ref": kl_ref})
+    assert abs(kl_one - kl_ref) / abs(kl_ref) <= traj_tol("fp16")
+    assert abs(kl_one - kl_each) / abs(kl_each) <= traj_tol("fp16")
+
+
 _WORKLOADS = {}
 
 
