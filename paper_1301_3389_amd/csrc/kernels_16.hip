@@ -214,7 +214,8 @@ __device__ __forceinline__ void load_v16(const float* V, int64_t N, int64_t T, i
 // columns are rows n (from n0), v(n, t) = V[n * T + t].  Rows n past N read as
 // zero; entries past T read the next row n and are masked by the callers.  The
 // four accumulator slots 4g .. 4g + 3 of a lane are four consecutive t of one
-// row n: one 16-byte load where the rows of V are 16-byte aligned (T % 4 == 0).
+// row n: one 16-byte load where the rows of V are 16-byte aligned (V itself
+// and T % 4 == 0).
 template <class G>
 __device__ __forceinline__ void load_v16t(const float* V, int64_t N, int64_t T, int64_t m0, int64_t n0,
                                           float (&vf)[G::FM][G::FN][16]) {
@@ -226,7 +227,7 @@ __device__ __forceinline__ void load_v16t(const float* V, int64_t N, int64_t T, 
   const __amdgpu_buffer_rsrc_t r =
       __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)std::min<int64_t>(bytes, 0x7fffffff), 0x00020000);
   const int voff = (int)(((lane & 31) * T + (lane >> 5) * 4) * 4);
-  if ((T & 3) == 0) {
+  if ((T & 3) == 0 && (reinterpret_cast<uintptr_t>(V) & 15) == 0) {
 #pragma unroll
     for (int i = 0; i < G::FM; ++i)
 #pragma unroll
@@ -549,8 +550,10 @@ __device__ __forceinline__ void row_qmax(const float (&vf)[G::FM][G::FN][16], co
           }
         }
       }
-      // halving exchange over lane bits 3, 2, 1: lane c keeps slot (c >> 1) & 7;
-      // then lane bits 0 and 4 (the same slots) are folded in
+      // halving exchange deciding on lane bits 3, 2, 1 (lane c keeps slot
+      // (c >> 1) & 7), with partners that flip the deciding bit and keep the
+      // higher ones: the row mirror (c ^ 15), the half-row mirror (c ^ 7), then
+      // c ^ 2; c ^ 1 and c ^ 16 complete the half-wave (DPP moves, one shuffle)
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
 #pragma unroll
@@ -560,10 +563,15 @@ __device__ __forceinline__ void row_qmax(const float (&vf)[G::FM][G::FN][16], co
           for (int e = 0; e < h; ++e) {
             const float send = up ? x[k][e] : x[k][e + h];
             const float keep = up ? x[k][e + h] : x[k][e];
-            x[k][e] = fmaxf(keep, __shfl_xor(send, 2 * h));
+            const int si = __float_as_int(send);
+            const int got = h == 4 ? __builtin_amdgcn_mov_dpp(si, 0x140, 0xF, 0xF, false)    // row mirror
+                          : h == 2 ? __builtin_amdgcn_mov_dpp(si, 0x141, 0xF, 0xF, false)    // half-row mirror
+                                   : __builtin_amdgcn_mov_dpp(si, 0x4E, 0xF, 0xF, false);    // quad [2,3,0,1]
+            x[k][e] = fmaxf(keep, __int_as_float(got));
           }
         }
-        float m = fmaxf(x[k][0], __shfl_xor(x[k][0], 1));
+        float m = fmaxf(x[k][0], __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x[k][0]), 0xB1, 0xF, 0xF,
+                                                                           false)));   // quad [1,0,3,2]
         m = fmaxf(m, __shfl_xor(m, 16));
         const int64_t row = row16<G>(m0, i, 8 * hv + ((lane >> 1) & 7));
         if ((lane & 17) == 0 && row < ME && m > 0.f) atomicMax(qmax + k * L + row, __float_as_uint(m));
