@@ -113,16 +113,42 @@ def kernel_key(rocprof_name):
     return base[2:] if base.startswith("k_") else base
 
 
+def strip_comments(src):
+    """C/C++ source text without its comments and blank runs (string and character
+    literals kept as they are), so that editing a comment changes no hash."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(" ".join(l.split()) for l in "".join(out).splitlines() if l.strip())
+
+
 def source_hash():
-    """Hash of the HIP sources: traffic counters are only valid for the build they were taken on."""
+    """Hash of the HIP sources' code (comments left out): traffic counters are only valid for the
+    build they were taken on."""
     import hashlib
     d = os.path.join(ROOT, "paper_1301_3389_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(d, f), encoding="utf-8") as fh:
+                h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

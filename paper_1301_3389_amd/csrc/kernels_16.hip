@@ -505,9 +505,11 @@ typedef Prods<1, 2, 2, 2, 0, 0, 0, 0, 1, 1> CH_P;
 
 // FP16 inside dna_iterate: bounds of the next half-step's Q, |Q - 1| and Q-bar
 // maxima per tile row (H step: rows n, for the W step's Q scales; W step: rows
-// t, for the H step's), taken over both candidates' reconstructions z_DNA and
-// z_DNA + dZ, between which the selection picks row by row (the normalisation
-// after it changes Z only by rounding; the scales are powers of two).  They
+// t, for the H step's), taken element by element over both candidates'
+// reconstructions z_DNA and z_DNA + dZ, one of which the selection keeps for
+// each column of H (H step) or row of W (W step), so that the bound holds
+// whatever it picks (the normalisation after it changes Z only by rounding;
+// the scales are powers of two).  They
 // replace the next Z pass's maxima pass.  The 32 lanes of a half-wave hold the
 // same 16 rows: a halving exchange leaves one lane per row, which adds it to
 // the row's maximum with an atomic.  (Per-tile stores reduced by the next Z

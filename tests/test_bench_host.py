@@ -56,3 +56,18 @@ def test_more_than_one_gpu_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_strip_comments_keeps_code_and_literals():
+    """The traffic files' source hash covers code only: comments and blank runs
+    drop out, string and character literals (which may hold comment markers)
+    stay."""
+    src = ('int a = 1; // note "x"\n'
+           '/* block\n comment */ int b = 2;\n\n'
+           'const char* s = "not // a comment /* either */";\n'
+           "char c = '\"'; char d = '\\\\';\n")
+    out = bench.strip_comments(src)
+    assert "note" not in out and "block" not in out
+    assert '"not // a comment /* either */"' in out
+    assert "int a = 1;" in out and "int b = 2;" in out and "char d = '\\\\';" in out
+    assert bench.strip_comments(src.replace("note", "other note")) == out
