@@ -60,8 +60,9 @@ typedef enum {
  * float32 in HBM; operands are rounded to 16 bits when staged.  BF16 rounds
  * directly; FP16 first applies power-of-two scales (per rank component from the
  * W column / H row maxima, per column or row of Q, Q - 1 and Q-bar from a max
- * pass) that are undone in float32, so FP16 neither overflows nor flushes to
- * zero where the fp32 values are normal.  The candidates, the selection sums
+ * pass, or inside dna_iterate after its first half step from bounds that the
+ * preceding cost pass leaves) that are undone in float32, so FP16 neither
+ * overflows nor flushes to zero where the fp32 values are normal.  The candidates, the selection sums
  * and the update itself stay in float32 / float64.  dna_mu_update and
  * dna_kl_cost ignore the field (float32 products); the unrolled adjoint returns
  * DNA_EUNSUPPORTED for 16-bit types. */
