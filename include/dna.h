@@ -49,7 +49,7 @@ typedef enum {
                            column sums)                                         */
   DNA_ENONFINITE = 4,   /* checked mode: NaN or Inf in an input                */
   DNA_EHIP = 5,         /* HIP runtime or launch error                         */
-  DNA_EUNSUPPORTED = 6  /* valid request this build does not implement         */
+  DNA_EUNSUPPORTED = 6  /* valid request this library does not implement       */
 } dna_status;
 
 /* Operand type of the matrix products (the accumulation is always float32 and

@@ -1433,7 +1433,7 @@ const char* dna_status_string(dna_status s) {
     case DNA_EDOMAIN: return "DNA_EDOMAIN: input outside the domain of the method";
     case DNA_ENONFINITE: return "DNA_ENONFINITE: non-finite input";
     case DNA_EHIP: return "DNA_EHIP: HIP runtime error";
-    case DNA_EUNSUPPORTED: return "DNA_EUNSUPPORTED: not supported by this build";
+    case DNA_EUNSUPPORTED: return "DNA_EUNSUPPORTED: not supported by this library";
   }
   return "unknown dna_status";
 }

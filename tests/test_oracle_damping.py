@@ -1,4 +1,4 @@
-"""Pins of the damped selection (select="newton_first", the reading this build
+"""Pins of the damped selection (select="newton_first", the reading this library
 gives Sec. 5's "more refined step damping"): the Newton candidate alone is
 costed and kept iff it does not raise the column's (row's) eq. (5) objective,
 else the MU candidate is kept uncosted.  CPU only."""
