@@ -1395,7 +1395,10 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 // Normalisation with the second level of the sums done per tile: blocks
 // [0, wtiles) scale (4096 / WR) x WR tiles of W (WR columns r, each block
 // summing the parts of its WR factors, 256 / WR lanes per column); the
-// remaining blocks scale SC_TCHUNK entries of one row r of H.  WR = 64 serves
+// remaining blocks scale a chunk of one row r of H (SC_TCHUNK entries, or the
+// whole row where the parts are so many that every chunk re-reading all of
+// them would cost more than the row: then HP = 32 entries per lane and
+// piece).  WR = 64 serves
 // few parts; with many (the W selection leaves one per four rows of W) the
 // part sums of 64-column tiles become long dependent chains, and WR = 16 cuts
 // them to a quarter.  Every block loads its factor entries before it adds the
@@ -1411,7 +1414,6 @@ hipError_t launch_sum_final(const SumJob& job, hipStream_t s) {
 // with lambda; side 1 the reverse), so W column r is multiplied by
 // sqrt(lambda G_r / (rho C_r)) either way; a sum that is not positive leaves
 // the column / row unscaled and sets CHK_DOMAIN.
-constexpr int SC_H_PER = SC_TCHUNK / 256;
 constexpr int SC_MANY_PARTS = 128;   // above this many parts the 16-column W tiles
 __device__ __forceinline__ double balance_factor(double sj, double so, double wj, double wo, int* check) {
   if (sj > 0.0 && so > 0.0) return sqrt((wj * sj) / (wo * so));
@@ -1428,10 +1430,10 @@ __device__ __forceinline__ double lane_group_sum(double x) {
   return x;
 }
 
-template <int WR>
+template <int WR, int HP>
 __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, float* __restrict__ H, int64_t N,
                                                int64_t T, int64_t R, SumJob j, SumJob o, double wj, double wo,
-                                               int64_t rtiles, int64_t wtiles, int64_t tchunks,
+                                               int64_t rtiles, int64_t wtiles, int64_t tchunks, int64_t tspan,
                                                double* __restrict__ emit) {
   constexpr int WG = 256 / WR, WN = 4096 / WR, WPER = WN / WG;   // lane groups, tile rows, rows per lane
   static_assert(WR == 16 || WR == 32 || WR == 64, "16, 32 or 64 columns per W tile");
@@ -1500,12 +1502,13 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
     }
   } else {
     const int64_t hb = b - wtiles;
-    const int64_t r = hb / tchunks, ch = hb % tchunks, t0 = ch * SC_TCHUNK + tid;
-    float h[SC_H_PER];
+    const int64_t r = hb / tchunks, ch = hb % tchunks;
+    const int64_t tb = ch * tspan, te = std::min<int64_t>(T, tb + tspan);   // pieces of 256 HP entries
+    float h[HP];
 #pragma unroll
-    for (int k = 0; k < SC_H_PER; ++k) {
-      const int64_t t = t0 + 256 * k;
-      h[k] = t < T ? H[r * T + t] : 0.f;
+    for (int k = 0; k < HP; ++k) {
+      const int64_t t = tb + tid + 256 * k;
+      h[k] = t < te ? H[r * T + t] : 0.f;
     }
     if (tid < 64) {  // one wave: a lane per part, fixed-order butterfly
       double f = tid < j.nparts ? j.part[(int64_t)tid * R + r] : 0.0;
@@ -1525,12 +1528,20 @@ __global__ __launch_bounds__(256) void k_scale(int side, float* __restrict__ W, 
     const bool sc = f > 0.0;
     const double m = side == 0 ? f : 1.0 / f;
     double rs = 0.0;
+    for (int64_t t0 = tb; t0 < te; t0 += 256 * HP) {
+      if (t0 != tb)
 #pragma unroll
-    for (int k = 0; k < SC_H_PER; ++k) {
-      const int64_t t = t0 + 256 * k;
-      const float x = sc ? (float)((double)h[k] * m) : h[k];
-      if (sc && t < T) H[r * T + t] = x;
-      rs += (double)x;                            // 0 outside the matrix
+        for (int k = 0; k < HP; ++k) {
+          const int64_t t = t0 + tid + 256 * k;
+          h[k] = t < te ? H[r * T + t] : 0.f;
+        }
+#pragma unroll
+      for (int k = 0; k < HP; ++k) {
+        const int64_t t = t0 + tid + 256 * k;
+        const float x = sc ? (float)((double)h[k] * m) : h[k];
+        if (sc && t < te) H[r * T + t] = x;
+        rs += (double)x;                          // 0 outside the matrix
+      }
     }
     if (emit && side == 1) {                      // row sum of this chunk of the new H
       rs = wave_sum(rs);
@@ -1573,20 +1584,27 @@ int64_t scale_emit_parts(int side, int64_t N, int64_t T) {
 
 hipError_t launch_scale(int side, float* W, float* H, int64_t N, int64_t T, int64_t R, const SumJob& job,
                         double* emit, SumJob* emitted, hipStream_t s, const SumJob& other, double wj, double wo) {
-  const bool many = std::max(job.nparts, other.part ? other.nparts : 0) > SC_MANY_PARTS;
+  const int64_t np = std::max(job.nparts, other.part ? other.nparts : 0);
+  const bool many = np > SC_MANY_PARTS;
   const int wr = many ? 16 : 64, wn = 4096 / wr;
-  const int64_t rtiles = cdiv(R, wr), wtiles = rtiles * cdiv(N, wn), tchunks = cdiv(T, SC_TCHUNK);
+  const int64_t rtiles = cdiv(R, wr), wtiles = rtiles * cdiv(N, wn);
+  // every chunk of an H row reads all of the row's parts (8 bytes each, a
+  // sector apart): fewer chunks where those reads would pass about 32 MiB
+  const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 25) / std::max<int64_t>(1, R * np * 64));
+  const int64_t want = std::min(cdiv(T, SC_TCHUNK), cap);
+  const int64_t tspan = cdiv(cdiv(T, want), SC_TCHUNK) * SC_TCHUNK, tchunks = cdiv(T, tspan);
+  const bool longrow = tspan > SC_TCHUNK;
   const int64_t blocks = wtiles + R * tchunks;
+  typedef void (*Kern)(int, float*, float*, int64_t, int64_t, int64_t, SumJob, SumJob, double, double, int64_t,
+                       int64_t, int64_t, int64_t, double*);
+  const Kern k = many ? (longrow ? k_scale<16, 32> : k_scale<16, SC_TCHUNK / 256>)
+                      : (longrow ? k_scale<64, 32> : k_scale<64, SC_TCHUNK / 256>);
   prof_begin("scale", s);
-  if (many)
-    hipLaunchKernelGGL(k_scale<16>, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, other, wj, wo,
-                       rtiles, wtiles, tchunks, emit);
-  else
-    hipLaunchKernelGGL(k_scale<64>, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, other, wj, wo,
-                       rtiles, wtiles, tchunks, emit);
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, s, side, W, H, N, T, R, job, other, wj, wo, rtiles,
+                     wtiles, tchunks, tspan, emit);
   prof_end("scale", s);
   if (emit && emitted)
-    *emitted = SumJob{emit, (int)(side == 0 ? cdiv(N, wn) : cdiv(T, SC_TCHUNK)), R, nullptr, nullptr, nullptr};
+    *emitted = SumJob{emit, (int)(side == 0 ? cdiv(N, wn) : tchunks), R, nullptr, nullptr, nullptr};
   return hipGetLastError();
 }
 
