@@ -252,9 +252,12 @@ def test_deterministic(dna):
 
 
 # (1000, 4100, 37): the one-kernel H step and normalisations over more than 128
-# parts with R not a multiple of the 16-column W tiles
+# parts with R not a multiple of the 16-column W tiles; (1024, 10240, 512): the
+# W-step normalisation over 256 parts at R = 512 takes longer H chunks (two of
+# 4096 entries and a last one of 2048)
 @pytest.mark.parametrize("shape", [SHAPES[0], SHAPES[3], SHAPES[6], SHAPES[7], (1024, 2300, 64, 0.1, 11),
-                                   (200, 2100, 100, 0.0, 12), (1000, 4100, 37, 0.1, 18)])
+                                   (200, 2100, 100, 0.0, 12), (1000, 4100, 37, 0.1, 18),
+                                   (1024, 10240, 512, 0.1, 19)])
 def test_iterate_matches_separate_calls(dna, shape):
     """dna_iterate (sums handed from each normalisation to the next half-step)
     against the four separate entry points, from the same state: the state after
